@@ -1,0 +1,130 @@
+"""Sim3 reprojection residual, its gradient and Gauss-Newton, in float64
+(test infrastructure only).
+
+After matching, the loop Sim3 is refined from the matched pairs (the Sim(3)
+optimisation between the two projection searches of Sec. IV-C).  For a
+matched pair (map point X, observation uv, keyframe pose T_k = (R_k, t_k)):
+
+    p = s R X + t             (the loop Sim3 S applied to the point)
+    q = R_k p + t_k           (into keyframe k)
+    r = pi(q) - uv,  pi(q) = (fx q0/q2 + cx, fy q1/q2 + cy)
+    e = |r|,  rho(e) = e^2/2 if e <= delta else delta e - delta^2/2
+    L = sum rho(e)            (pairs with q2 <= 0 contribute nothing)
+
+The gradient is taken with respect to a left perturbation S <- exp(xi) S at
+xi = 0, xi = (omega, upsilon, sigma).  With w = min(1, delta/e) the Huber
+weight, g = sum w J^T r and the Gauss-Newton matrix H = sum w J^T J where
+J = d r / d xi.  Here J is obtained by the chain rule written out term by
+term; the tests pin it against central finite differences of L.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import sim3
+
+
+def _kf_RT(kf_idx, kf_T, n):
+    if kf_T is None:
+        R = np.broadcast_to(np.eye(3), (n, 3, 3))
+        t = np.zeros((n, 3))
+    else:
+        T = np.asarray(kf_T, np.float64)[np.asarray(kf_idx)]
+        R = T[:, :9].reshape(-1, 3, 3)
+        t = T[:, 9:12]
+    return R, t
+
+
+def project(S, xyz, kf_idx, kf_T, cam):
+    X = np.asarray(xyz, np.float64)
+    p = sim3.act(S, X)
+    R, t = _kf_RT(kf_idx, kf_T, len(X))
+    q = np.einsum("nij,nj->ni", R, p) + t
+    fx, fy, cx, cy = (float(c) for c in cam[:4])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        uv = np.stack([fx * q[:, 0] / q[:, 2] + cx, fy * q[:, 1] / q[:, 2] + cy], axis=1)
+    return p, q, uv, R
+
+
+def huber(e, delta):
+    e = np.asarray(e, np.float64)
+    rho = np.where(e <= delta, 0.5 * e * e, delta * e - 0.5 * delta * delta)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(e <= delta, 1.0, delta / e)
+    return rho, w
+
+
+def forward(S, xyz, uv, kf_idx, kf_T, cam, delta):
+    """Per-pair residual r [n,2], Huber weight w [n] (0 for pairs behind the
+    camera), and the loss L."""
+    _, q, uvp, _ = project(S, xyz, kf_idx, kf_T, cam)
+    valid = q[:, 2] > 0
+    r = np.where(valid[:, None], uvp - np.asarray(uv, np.float64), 0.0)
+    e = np.linalg.norm(r, axis=1)
+    rho, w = huber(e, delta)
+    rho = np.where(valid, rho, 0.0)
+    w = np.where(valid, w, 0.0)
+    return r, w, float(rho.sum())
+
+
+def jacobian(S, xyz, kf_idx, kf_T, cam):
+    """J [n, 2, 7] = d pi(q) / d q  .  R_k  .  [ -[p]x | I | p ]."""
+    p, q, _, R = project(S, xyz, kf_idx, kf_T, cam)
+    fx, fy = float(cam[0]), float(cam[1])
+    n = len(p)
+    dpi = np.zeros((n, 2, 3))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        iz = 1.0 / q[:, 2]
+        dpi[:, 0, 0] = fx * iz
+        dpi[:, 0, 2] = -fx * q[:, 0] * iz * iz
+        dpi[:, 1, 1] = fy * iz
+        dpi[:, 1, 2] = -fy * q[:, 1] * iz * iz
+    dp = np.zeros((n, 3, 7))
+    # d(exp(xi) p)/d xi at 0: omega x p = -[p]x omega, upsilon, sigma p
+    dp[:, 0, 1], dp[:, 0, 2] = p[:, 2], -p[:, 1]
+    dp[:, 1, 0], dp[:, 1, 2] = -p[:, 2], p[:, 0]
+    dp[:, 2, 0], dp[:, 2, 1] = p[:, 1], -p[:, 0]
+    dp[:, 0, 3] = dp[:, 1, 4] = dp[:, 2, 5] = 1.0
+    dp[:, :, 6] = p
+    J = np.einsum("nab,nbc,ncd->nad", dpi, R, dp)
+    J[q[:, 2] <= 0] = 0.0
+    return J
+
+
+def grad_hess(S, xyz, uv, kf_idx, kf_T, cam, delta):
+    """g [7] = sum w J^T r, H [7,7] = sum w J^T J, and L."""
+    r, w, L = forward(S, xyz, uv, kf_idx, kf_T, cam, delta)
+    J = jacobian(S, xyz, kf_idx, kf_T, cam)
+    g = np.einsum("n,nai,na->i", w, J, r)
+    H = np.einsum("n,nai,naj->ij", w, J, J)
+    return g, H, L
+
+
+def loss_at(xi, S0, xyz, uv, kf_idx, kf_T, cam, delta):
+    return forward(sim3.compose(sim3.exp(xi), S0), xyz, uv, kf_idx, kf_T, cam, delta)[2]
+
+
+def fd_grad(S0, xyz, uv, kf_idx, kf_T, cam, delta, h=1e-4):
+    """Central differences of L(exp(xi) S0) at xi = 0."""
+    g = np.zeros(7)
+    for i in range(7):
+        e = np.zeros(7)
+        e[i] = h
+        g[i] = (loss_at(e, S0, xyz, uv, kf_idx, kf_T, cam, delta)
+                - loss_at(-e, S0, xyz, uv, kf_idx, kf_T, cam, delta)) / (2 * h)
+    return g
+
+
+def H_upper(H) -> np.ndarray:
+    """The 28 entries of the upper triangle of a symmetric 7x7, row by row."""
+    return np.asarray(H)[np.triu_indices(7)]
+
+
+def gauss_newton(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=10):
+    """Undamped IRLS Gauss-Newton: solve H dxi = -g, S <- exp(dxi) S."""
+    S = np.asarray(S0, np.float64).copy()
+    for _ in range(iters):
+        g, H, _ = grad_hess(S, xyz, uv, kf_idx, kf_T, cam, delta)
+        dxi = np.linalg.solve(H, -g)
+        S = sim3.compose(sim3.exp(dxi), S)
+    return S

@@ -1,0 +1,77 @@
+"""Hand-built test cases shared by the oracle pins and the GPU parity tests."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from synth import Event, LoopParams
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _bits(a, b):
+    bits = np.zeros(256, bool)
+    bits[a:b] = True
+    return np.packbits(bits, bitorder="little")
+
+
+def single_kf_event(xyz, desc, dmax, ids, kp_xy, kp_oct, kp_desc, kp_owner, sim3_16, cam8,
+                    params: LoopParams, name="case") -> Event:
+    n_mp = len(xyz)
+    n_kp = len(kp_xy)
+    return Event(
+        cams=np.asarray(cam8, np.float32).reshape(1, 8), kf_T=np.zeros((1, 12)),
+        S_true=np.zeros(13), S_init=np.zeros(13),
+        kf_sim3=np.asarray(sim3_16, np.float32).reshape(1, 16),
+        mp_xyz=np.asarray(xyz, np.float32).reshape(-1, 3),
+        mp_desc=np.asarray(desc, np.uint8).reshape(-1, 32),
+        mp_dmax=np.asarray(dmax, np.float32), mp_id=np.asarray(ids, np.int32),
+        kp_offset=np.array([0, n_kp], np.int32),
+        kp_xy=np.asarray(kp_xy, np.float32).reshape(-1, 2), kp_oct=np.asarray(kp_oct, np.int8),
+        kp_desc=np.asarray(kp_desc, np.uint8).reshape(-1, 32),
+        kp_owner=np.asarray(kp_owner, np.int32),
+        pair_offset=np.array([0, n_mp], np.int64), pair_mp=None,
+        planted_kf=np.zeros(0, np.int32), planted_kp=np.zeros(0, np.int32),
+        planted_mp=np.zeros(0, np.int32), planted_kind=np.zeros(0, np.int8),
+        params=params, name=name)
+
+
+def hand_case():
+    """The hand-worked fixture: (event, expected outputs dict)."""
+    with open(os.path.join(GOLDEN, "fusion_hand_case.json")) as f:
+        g = json.load(f)
+    pts = g["points"]
+    kps = g["keypoints"]
+    params = LoopParams(**g["params"])
+    ev = single_kf_event(
+        xyz=[p["xyz"] for p in pts], desc=np.zeros((len(pts), 32), np.uint8),
+        dmax=[p["dmax"] for p in pts], ids=[p["id"] for p in pts],
+        kp_xy=[k["xy"] for k in kps], kp_oct=[k["octave"] for k in kps],
+        kp_desc=np.stack([_bits(*k["bits"]) for k in kps]), kp_owner=[k["owner"] for k in kps],
+        sim3_16=g["sim3"], cam8=g["camera"], params=params, name="hand")
+    exp = {k: np.asarray(v) for k, v in g["expected"].items()}
+    return ev, exp
+
+
+def conflict_case(order):
+    """Five points with identical descriptors within 0.1 px of each other
+    (plus one far away), all matching the same free keypoint; `order`
+    permutes the points.  Returns (event, index of the original point 0 in
+    the permuted order)."""
+    rng = np.random.default_rng(7)
+    desc = rng.integers(0, 256, 32, dtype=np.uint8)
+    base = np.array([[0.25, -0.5, 2.0]] * 5 + [[-0.5, 0.5, 2.0]])
+    base[:5, 0] += np.arange(5) * 0.0004    # 0.02 px apart in u
+    order = np.asarray(order)
+    xyz = base[order]
+    ids = (500 + order).astype(np.int32)
+    kp_desc = np.stack([desc, rng.integers(0, 256, 32, dtype=np.uint8)])
+    ev = single_kf_event(
+        xyz=xyz, desc=np.tile(desc, (6, 1)), dmax=np.ones(6), ids=ids,
+        kp_xy=[[62.6, 25.1], [25.0, 75.0]], kp_oct=[0, 0], kp_desc=kp_desc, kp_owner=[-1, -1],
+        sim3_16=[1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0],
+        cam8=[100, 100, 50, 50, 100, 100, 0, 0],
+        params=LoopParams(win_px=3.0, n_octaves=4, grid_cols=8, grid_rows=8), name="conflict")
+    return ev
