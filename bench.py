@@ -1,0 +1,250 @@
+"""Benchmark: point-keyframe match candidates/s and ms per loop event, batched
+vs plain, on one MI355X.
+
+One step is one loop event through the whole hot path: keypoint grids of all
+keyframes, Sim3 search-and-fuse over every (point, keyframe) pair, ADD
+conflict resolution, then 10 Gauss-Newton refinement steps of the loop Sim3
+on the accepted pairs.  Inputs are resident in HBM before timing starts.
+
+  batched : one upload of the event tables + one HIP-graph launch per event
+  plain   : the per-call pattern (one fl_search_fuse per keyframe, each
+            followed by a copy of its results to the host and a stream sync;
+            then each refinement step as its own call, copy and sync)
+
+Prints one JSON line.  Workload (default): a loop event of 20 keyframes
+(752x480, 1,200 keypoints each) and 15,000 map points, 300,000 dense pairs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+GN_ITERS = 10
+HUBER = 2.45
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def search_bytes(ev, params, n_pairs):
+    """Algorithmic bytes of one search-kernel launch: every point's xyz,
+    descriptor, distance invariance and id once (52 B), every keypoint's
+    cell-ordered record and descriptor and owner once (52 B), every grid
+    and owner-table entry once, every pair's 13 bytes of outputs once."""
+    cells = params.grid_cols * params.grid_rows
+    n_kp = np.diff(ev.kp_offset)
+    hash_bytes = 4 * sum(max(16, 1 << int(np.ceil(np.log2(max(2 * int(k), 1))))) for k in n_kp)
+    return (52 * ev.n_mp + 52 * int(ev.kp_offset[-1]) + 4 * (cells + 1) * ev.n_kf + hash_bytes
+            + 13 * n_pairs)
+
+
+def search_ops(st, n_pairs):
+    """Algorithmic VALU lane-ops of one search launch from its exact counters:
+    25 per pair (tile bookkeeping, owner probe, decision, stores), 40 per
+    visible pair (transform, projection, octave, window), 6 per grid cell
+    scanned, 8 per keypoint scanned (record load and box / octave test) and
+    20 per descriptor comparison (8 xor + 8 popcount-accumulate + key/min)."""
+    return (25 * n_pairs + 40 * st["n_visible"] + 6 * st["n_cells"] + 8 * st["n_kp_scanned"]
+            + 20 * st["n_cand"])
+
+
+def cpu_baseline(ev, budget_s=12.0):
+    """The oracle as it stands on this host's cores: brute-force search-and-
+    fuse of the event, then 10 float64 Gauss-Newton steps on its accepted
+    pairs; repeated until about budget_s."""
+    import oracle
+    from oracle import residual as R
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        out = oracle.search_fuse(ev, use_grid=False)
+        acc = np.nonzero((out["decision"] == oracle.ADD) | (out["decision"] == oracle.FUSE))[0]
+        kf = np.searchsorted(ev.pair_offset, acc, side="right") - 1
+        mp = acc - ev.pair_offset[kf]
+        kp = ev.kp_offset[kf] + out["best_idx"][acc]
+        R.gauss_newton(ev.S_init, ev.mp_xyz[mp], ev.kp_xy[kp], kf, ev.kf_T, ev.cams[0], HUBER, iters=GN_ITERS)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 20:
+            break
+    return n, el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(events and keyframes shard across GPUs without exchange, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_17201_amd as fl
+    import synth
+
+    dev = torch.device("cuda:0")
+    log("generating the loop event (20 keyframes x 1,200 keypoints, 15,000 points)")
+    ev = synth.gen_c2()
+    P = ev.params
+    ctx = fl.Context(0)
+    b = fl.DeviceBatch(ev, device=dev)
+    n_pairs = b.n_pairs
+    out = fl.FuseOutputs.empty(n_pairs, dev)
+    stream = torch.cuda.current_stream(dev)
+
+    tuning = None
+    if not args.no_autotune:
+        t, ms = ctx.autotune(b, P, out, reps=3)
+        tuning = dict(pairs_per_lane=t[0], block=t[1], waves_per_cu=t[2], xcd_queues=t[3])
+        log(f"autotune: {tuning} ({ms * 1e3:.1f} us per eager batched search)")
+
+    # exact per-class counters of this workload (one untimed counting launch)
+    ctx.set_stats(True)
+    ctx.search_fuse_batched(b, P, out)
+    torch.cuda.synchronize()
+    st = ctx.get_stats()
+    ctx.set_stats(False)
+
+    S_init = torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(dev)
+    S = S_init.clone()
+    n_matched = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def step():
+        S.copy_(S_init)
+        ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched))
+
+    log(f"batched: warmup {args.warmup}, timing {args.steps} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    log(f"batched: {ms_step * 1e3:.1f} us per event (device-resident)")
+
+    # batched, results copied to the host and synchronised per event
+    host = {k: torch.empty(getattr(out, k).shape, dtype=getattr(out, k).dtype, pin_memory=True)
+            for k in ("best_idx", "best_dist", "second_dist", "decision", "target")}
+    host_S = torch.empty((1, 13), dtype=torch.float64, pin_memory=True)
+    e2e = []
+    for i in range(args.warmup + args.steps):
+        t0 = time.perf_counter()
+        step()
+        for k, h in host.items():
+            h.copy_(getattr(out, k), non_blocking=True)
+        host_S.copy_(S, non_blocking=True)
+        stream.synchronize()
+        if i >= args.warmup:
+            e2e.append((time.perf_counter() - t0) * 1e3)
+    ms_e2e = statistics.median(e2e)
+
+    # dominant kernel: search, timed with HIP events around each launch
+    ctx.set_profiling(True)
+    for _ in range(args.steps):
+        ctx.search_fuse_batched(b, P, out)
+    k_ms, k_n = ctx.get_profile()
+    ctx.set_profiling(False)
+    k_ms /= max(k_n, 1)
+    nbytes = search_bytes(ev, P, n_pairs)
+    nops = search_ops(st, n_pairs)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = nops / (ALU_PEAK_TOPS * 1e12)
+    if t_alu > t_hbm:
+        roof = dict(bound="alu", achieved=nops / (k_ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
+    else:
+        roof = dict(bound="hbm", achieved=nbytes / (k_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "search_batched_kernel"
+    roof["kernel_us"] = k_ms * 1e3
+    roof["alg_bytes"] = nbytes
+    roof["alg_ops"] = nops
+    log(f"search kernel: {k_ms * 1e3:.2f} us, {nbytes / 1e6:.2f} MB, {nops / 1e6:.1f} M ops")
+
+    plain = None
+    if not args.no_plain:
+        log(f"plain: {args.plain_steps} events, per-keyframe calls with copy + sync")
+        X, D, M, I = b.mp_xyz, b.mp_desc, b.mp_dmax, b.mp_id
+        kfs = []
+        for k in range(ev.n_kf):
+            a, c = int(ev.kp_offset[k]), int(ev.kp_offset[k + 1])
+            p0, p1 = int(ev.pair_offset[k]), int(ev.pair_offset[k + 1])
+            o = fl.FuseOutputs(out.best_idx[p0:p1], out.best_dist[p0:p1], out.second_dist[p0:p1],
+                               out.decision[p0:p1], out.target[p0:p1])
+            kfs.append((b.kp_xy[a:c], b.kp_oct[a:c], b.kp_desc[a:c], b.kp_owner[a:c], o, p0, p1))
+        times = []
+        for i in range(2 + args.plain_steps):
+            t0 = time.perf_counter()
+            for k, (kx, ko, kd, kw, o, p0, p1) in enumerate(kfs):
+                ctx.search_fuse(X, D, M, I, kx, ko, kd, kw, ev.kf_sim3[k], ev.cams[k], P, out=o)
+                for name, h in host.items():
+                    h[p0:p1].copy_(getattr(o, name), non_blocking=True)
+                stream.synchronize()
+            S.copy_(S_init)
+            for _ in range(GN_ITERS):
+                ctx.refine_events(b, out, (1, HUBER, S, None, None))
+                host_S.copy_(S, non_blocking=True)
+                stream.synchronize()
+            if i >= 2:
+                times.append((time.perf_counter() - t0) * 1e3)
+        ms_plain = statistics.median(times)
+        plain = dict(ms_per_event=ms_plain, pairs_per_s=n_pairs / (ms_plain * 1e-3),
+                     p99_ms=float(np.percentile(times, 99)))
+        log(f"plain: {ms_plain:.3f} ms per event")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle (brute-force search + float64 GN) on the same event")
+        n, el = cpu_baseline(ev)
+        cpu = dict(value=n * n_pairs / el, unit="pairs/s", cores=1, kind="oracle",
+                   sample=f"{n} full loop events of this workload ({n * n_pairs} pairs), "
+                          f"single-threaded C oracle + NumPy float64 Gauss-Newton, {el:.1f} s",
+                   ms_per_event=el / n * 1e3)
+
+    res = dict(
+        metric="point-keyframe match candidates/s (batched loop event incl. 10 GN steps)",
+        value=n_pairs / (ms_step * 1e-3), unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload="loop event: 20 keyframes 752x480 x 1,200 keypoints, 15,000 points, "
+                             "300,000 dense pairs; search-and-fuse + 10 Gauss-Newton Sim3 steps",
+                    n_pairs=n_pairs, n_kf=ev.n_kf, n_mp=ev.n_mp, gn_iters=GN_ITERS, tuning=tuning),
+        ms_per_event_batched=ms_step, ms_per_event_batched_with_d2h=ms_e2e,
+        plain=plain,
+        batched_vs_plain=(plain["ms_per_event"] / ms_e2e) if plain else None,
+        batched_vs_plain_device_resident=(plain["ms_per_event"] / ms_step) if plain else None,
+        matched_pairs=int(n_matched.item()),
+        roofline=roof,
+        cpu_baseline=cpu,
+    )
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,289 @@
+/*
+ * fastloop.h - C ABI of an MI355X (gfx950) library for the data-parallel core
+ * of loop closing in visual SLAM: Sim3-corrected search-and-fuse and the
+ * Sim3 reprojection residual with its hand-written backward.
+ *
+ * Paper: "FastLoop: Parallel Loop Closing with GPU-Acceleration in Visual
+ * SLAM" (arXiv 2603.17201).  Loop fusion (Sec. III-B, Sec. IV-D3) projects the
+ * map points of the loop region through the loop-corrected Sim3 into every
+ * connected keyframe and merges points with keypoints that are close in the
+ * image and similar in descriptor.  Keyframes are mutually independent
+ * (Sec. IV-D3), data stays resident on the GPU and is transferred once, in
+ * compact wrapper structures, into memory allocated once (Sec. IV-E).
+ *
+ * Conventions for every entry point
+ *  - Pointers named in the argument comments as "host" point to host memory;
+ *    all others are device pointers into HBM owned by the caller.  The
+ *    library never frees caller memory.
+ *  - All work is enqueued on the given stream; no call synchronises the
+ *    stream unless it says so.  Host arrays are copied before the call
+ *    returns, so the caller may reuse them immediately.
+ *  - Every function returns FL_OK (0) or a negative FL_E* code; the message
+ *    of the last failure on the calling thread is in fl_last_error().  All
+ *    checks that can run on the host run before anything is enqueued.
+ *  - Descriptor rows (32 bytes each) must start at a 16-byte aligned address.
+ *  - A Sim3 acts as X -> s R X + t (world to camera).  The search form
+ *    fl_sim3 stores sR row-major, t and 1/s in float32.  The float64 form
+ *    used by refinement is 13 doubles [R row-major (9), t (3), s].  Tangent
+ *    vectors are xi = (omega, upsilon, sigma) with left perturbation
+ *    S <- exp(xi) S.
+ */
+#ifndef FASTLOOP_H
+#define FASTLOOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FL_OK 0
+#define FL_EINVAL (-1)   /* an argument is invalid (NULL, negative, misaligned, inconsistent) */
+#define FL_ENOMEM (-2)   /* device or pinned host allocation failed */
+#define FL_EHIP (-3)     /* a HIP runtime call failed */
+#define FL_ERANGE (-4)   /* a size exceeds a documented limit */
+#define FL_ENOTSUP (-5)  /* the device is not supported */
+
+/* decision per (map point, keyframe) pair */
+#define FL_NOT_VISIBLE 0 /* behind the camera or projects outside the image */
+#define FL_NO_MATCH 1    /* visible, no candidate accepted */
+#define FL_ADD 2         /* accepted; the keypoint was free and this point takes it */
+#define FL_FUSE 3        /* accepted; merge into target (owner id) */
+#define FL_SKIP 4        /* the point already owns a keypoint of this keyframe */
+#define FL_INVALID 5     /* a sparse pair names a point outside its event */
+
+#define FL_NO_DIST 0x7FFF
+#define FL_MAX_KP 65535      /* keypoints per keyframe (16-bit index in the packed key) */
+#define FL_MAX_OCTAVES 32
+#define FL_MAX_CELLS 8192    /* grid_cols * grid_rows */
+#define FL_MAX_PAIRS 2147483647LL
+
+typedef struct fl_ctx fl_ctx;
+
+/* Search form of a (keyframe-composed) Sim3: q = sR X + t, metric distance
+ * |q| * inv_s.  64 bytes. */
+typedef struct {
+    float sR[9];
+    float t[3];
+    float inv_s;
+    float pad[3];
+} fl_sim3;
+
+/* Pinhole camera: u = fx x/z + cx, v = fy y/z + cy, image [0,width) x [0,height). */
+typedef struct {
+    float fx, fy, cx, cy, width, height;
+    float pad[2];
+} fl_pinhole;
+
+/* Search thresholds.  Window half-width win_px * scale_factor^pred where
+ * pred is the point's predicted octave; keypoint octave gate {pred-1, pred};
+ * accept iff Hamming distance <= hamming_th (and, when 0 < nn_ratio < 1,
+ * best < nn_ratio * second).  Typical: 3.0, 1.2, 8, 64, 48, 50, 0. */
+typedef struct {
+    float win_px;
+    float scale_factor;
+    int32_t n_octaves;   /* 1..32 */
+    int32_t grid_cols;   /* grid_cols * grid_rows <= FL_MAX_CELLS */
+    int32_t grid_rows;
+    int32_t hamming_th;
+    float nn_ratio;      /* <= 0 or >= 1: ratio test off */
+    int32_t flags;       /* must be 0 */
+} fl_params;
+
+/* Per-pair outputs (device arrays, one entry per pair).  best_idx is the
+ * keypoint index within its keyframe (-1: no candidate); best_dist and
+ * second_dist are Hamming distances (FL_NO_DIST when absent); target is the
+ * owner id merged into for FL_FUSE, else -1. */
+typedef struct {
+    int32_t* best_idx;
+    int16_t* best_dist;
+    int16_t* second_dist;
+    uint8_t* decision;
+    int32_t* target;
+} fl_fuse_out;
+
+/* One keyframe's keypoints (device arrays of n_kp entries).  kp_owner < 0
+ * marks a free keypoint, otherwise the id of the map point observed there.
+ * cell_start [grid_cols*grid_rows + 1] / cell_kp [n_kp] is the keypoint grid
+ * produced by fl_build_grid; both NULL: the library builds it. */
+typedef struct {
+    int32_t n_kp;
+    const float* kp_xy;        /* [n_kp][2] */
+    const int8_t* kp_octave;   /* [n_kp] */
+    const uint8_t* kp_desc;    /* [n_kp][32] */
+    const int32_t* kp_owner;   /* [n_kp] */
+    const int32_t* cell_start;
+    const int32_t* cell_kp;
+} fl_keyframe;
+
+/* A batch of loop events.  Keyframes, keypoints and points of all events are
+ * concatenated; pairs are grouped by keyframe.  Small tables are host arrays
+ * (validated and uploaded by the library), bulk data are device arrays. */
+typedef struct {
+    int32_t n_events;
+    int32_t n_kf;
+    int32_t n_mp;                     /* total points */
+    int32_t n_kp_total;               /* total keypoints */
+    int64_t n_pairs;                  /* total pairs (< 2^31) */
+    const int32_t* event_kf_offset;   /* host [n_events+1] keyframe range of each event */
+    const int32_t* event_mp_offset;   /* host [n_events+1] point range of each event */
+    const int32_t* kp_offset;         /* host [n_kf+1] keypoint range of each keyframe */
+    const int64_t* pair_offset;       /* host [n_kf+1] pair range of each keyframe */
+    const fl_sim3* kf_sim3;           /* host [n_kf] search transform of each keyframe */
+    const fl_pinhole* kf_K;           /* host [n_kf] camera of each keyframe */
+    const float* kf_T;                /* host [n_kf][12] world->camera SE3 (R row-major, t); refinement only, may be NULL */
+    const int32_t* pair_mp;           /* device [n_pairs] point index within the event; NULL = dense
+                                         (pair j of keyframe k is point j of its event) */
+    const float* kp_xy;               /* device [n_kp_total][2] */
+    const int8_t* kp_octave;          /* device [n_kp_total] */
+    const uint8_t* kp_desc;           /* device [n_kp_total][32] */
+    const int32_t* kp_owner;          /* device [n_kp_total] */
+    const float* mp_xyz;              /* device [n_mp][3] */
+    const uint8_t* mp_desc;           /* device [n_mp][32] */
+    const float* mp_dmax;             /* device [n_mp] distance invariance; NULL: pred = n_octaves-1, no octave gate */
+    const int32_t* mp_id;             /* device [n_mp]; NULL: id = index in the batch */
+} fl_batch;
+
+/* Refinement of each event's loop Sim3 after matching (Gauss-Newton on the
+ * Huber reprojection residual of the accepted pairs). */
+typedef struct {
+    int32_t n_iters;        /* 0 = no refinement */
+    float huber_delta;      /* pixels */
+    double* event_S;        /* device [n_events][13] in: start, out: refined (float64 Sim3) */
+    fl_sim3* event_S32;     /* device [n_events] out: float32 form of the refined Sim3 (may be NULL) */
+    int32_t* event_n_matched; /* device [n_events] out: pairs used (may be NULL) */
+} fl_refine;
+
+/* ------------------------------------------------------------------ */
+/* Context: workspace memory, pinned staging and captured graphs, allocated
+ * once and reused (Sec. IV-E).  One context per device and host thread. */
+int fl_create(fl_ctx** out, int device);
+void fl_destroy(fl_ctx* ctx);
+const char* fl_last_error(void);
+int fl_version(void);
+
+/* Keypoint cell grid of one keyframe (the "grid" input of the search).
+ * Cell of a keypoint = (clamp(floor(y*R/H)), clamp(floor(x*C/W))) in float32;
+ * cell_start [C*R+1] is the exclusive prefix sum of the per-cell counts and
+ * cell_kp [n_kp] lists keypoint indices cell by cell, increasing within a
+ * cell.  Errors: FL_EINVAL (NULL with n_kp > 0, bad params), FL_ERANGE
+ * (n_kp > FL_MAX_KP, cells > FL_MAX_CELLS). */
+int fl_build_grid(fl_ctx* ctx, int32_t n_kp, const float* kp_xy, const fl_pinhole* K /* host */,
+                  const fl_params* P /* host */, int32_t* cell_start, int32_t* cell_kp, hipStream_t stream);
+
+/* Plain search-and-fuse: every one of n_mp points against ONE keyframe, one
+ * lane per point, the per-call form of the paper's projection-search kernel
+ * (Sec. IV-D1, loop fusion Sec. IV-D3).  Pair index = point index; ids are
+ * mp_id[i] (or i when mp_id is NULL).  Outputs: see fl_fuse_out.  Errors:
+ * FL_EINVAL, FL_ERANGE as for fl_build_grid; misaligned descriptors. */
+int fl_search_fuse(fl_ctx* ctx, int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc,
+                   const float* mp_dmax, const int32_t* mp_id, const fl_keyframe* kf /* host */,
+                   const fl_sim3* S /* host */, const fl_pinhole* K /* host */,
+                   const fl_params* P /* host */, const fl_fuse_out* out /* host */, hipStream_t stream);
+
+/* Batched search-and-fuse over whole loop events (Sec. IV-D3: connected
+ * keyframes evaluated concurrently on resident data): one upload of the
+ * batch tables, a grid-build kernel over all keyframes, one persistent
+ * search kernel over all pairs of all events, and a conflict-resolution
+ * kernel.  Results are identical to fl_search_fuse applied per keyframe.
+ * Errors: FL_EINVAL (inconsistent offsets or NULL arrays), FL_ERANGE. */
+/* Host-only check of a batch (every test fl_search_fuse_batched makes before
+ * enqueuing anything; no device memory is touched, no context needed).
+ * Returns FL_OK or the error code the batched call would return. */
+int fl_validate_batch(const fl_batch* B /* host */, const fl_params* P /* host */, const fl_fuse_out* out /* host */);
+
+int fl_search_fuse_batched(fl_ctx* ctx, const fl_batch* B /* host */, const fl_params* P /* host */,
+                           const fl_fuse_out* out /* host */, hipStream_t stream);
+
+/* The same work as fl_search_fuse_batched, optionally followed by per-event
+ * Sim3 refinement, replayed from a HIP graph captured on first use: one
+ * upload and one graph launch per call.  The graph is independent of the
+ * batch sizes and re-captured only when the workspace grows or the tuning
+ * changes.  refine may be NULL. */
+int fl_search_fuse_graph_launch(fl_ctx* ctx, const fl_batch* B /* host */, const fl_params* P /* host */,
+                                const fl_fuse_out* out /* host */, const fl_refine* refine /* host */,
+                                hipStream_t stream);
+
+/* Per-event Sim3 refinement on the pairs a previous search accepted (ADD or
+ * FUSE; observation = matched keypoint position), eagerly launched.
+ * B must describe the same batch and out hold that search's results. */
+int fl_refine_events(fl_ctx* ctx, const fl_batch* B /* host */, const fl_fuse_out* out /* host */,
+                     const fl_refine* refine /* host */, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Sim3 reprojection residual over n matched pairs (the refinement that
+ * follows matching, Sec. IV-C): p = sR X + t, q = R_k p + t_k,
+ * r = pi(q) - uv, e = |r|, Huber rho(e) with threshold huber_delta,
+ * w = min(1, delta/e); pairs with q_z <= 0 give r = 0, w = 0.
+ * xyz [n][3], uv [n][2], kf_idx [n] (NULL: all 0), kf_T [n_kf][12] device
+ * (NULL: identity), S device pointer to one fl_sim3.  Outputs r [n][2],
+ * w [n] (either may be NULL) and loss [1] (float64, sum of rho). */
+int fl_reproj_residual_fwd(fl_ctx* ctx, int32_t n, const float* xyz, const float* uv,
+                           const int32_t* kf_idx, int32_t n_kf, const float* kf_T, const fl_sim3* S,
+                           const fl_pinhole* K /* host */, float huber_delta, float* r, float* w,
+                           double* loss, hipStream_t stream);
+
+/* Hand-written backward of the residual: with J = d r / d xi (2x7, left
+ * perturbation at xi = 0), g = grad_scale * sum w J^T r (7 doubles) and,
+ * if H is not NULL, the Gauss-Newton matrix sum w J^T J as its 28 upper-
+ * triangle entries row by row.  Per-pair terms in float32, sums in float64. */
+int fl_reproj_residual_bwd(fl_ctx* ctx, int32_t n, const float* xyz, const float* uv,
+                           const int32_t* kf_idx, int32_t n_kf, const float* kf_T, const fl_sim3* S,
+                           const fl_pinhole* K /* host */, float huber_delta, double grad_scale,
+                           double* g, double* H, hipStream_t stream);
+
+/* S_out = exp(xi) S_in (float64, device [7], [13], [13]); S32_out (device,
+ * may be NULL) receives the float32 search form. */
+int fl_sim3_exp_mul(fl_ctx* ctx, const double* xi, const double* S_in, double* S_out, fl_sim3* S32_out,
+                    hipStream_t stream);
+
+/* One Gauss-Newton / Levenberg-Marquardt step: solve (H + lambda diag(H)) d = -g
+ * by float64 Cholesky (g [7], H [28] upper as above, device), then
+ * S <- exp(d) S in place (device [13]) and S32 (device, may be NULL) <- its
+ * float32 form.  A non-positive pivot leaves S unchanged. */
+int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, double* S, fl_sim3* S32,
+               hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Tuning of the persistent search kernel.  Any tuning gives identical
+ * results; fl_autotune times the candidates on the given batch (the stream
+ * is synchronised) and keeps the fastest in the context. */
+typedef struct {
+    int32_t pairs_per_lane;  /* 1, 2 or 4 */
+    int32_t block;           /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t waves_per_cu;    /* persistent grid = CUs * waves_per_cu / (block / 64) workgroups */
+    int32_t xcd_queues;      /* 1: one work queue per XCD with stealing, 0: one global queue */
+} fl_tuning;
+
+int fl_get_tuning(fl_ctx* ctx, fl_tuning* out /* host */);
+int fl_set_tuning(fl_ctx* ctx, const fl_tuning* t /* host */);
+int fl_autotune(fl_ctx* ctx, const fl_batch* B /* host */, const fl_params* P /* host */,
+                const fl_fuse_out* out /* host */, int32_t reps, fl_tuning* best /* host, may be NULL */,
+                float* best_ms /* host, may be NULL */, hipStream_t stream);
+
+/* Optional per-call counters of the last batched search on this context
+ * (pairs visible, grid cells scanned, keypoints scanned, descriptor
+ * comparisons), enabled by fl_set_stats(ctx, 1); read after the stream
+ * completes.  Counting costs time and is off by default. */
+int fl_set_stats(fl_ctx* ctx, int enable);
+int fl_get_stats(fl_ctx* ctx, int64_t* out4 /* host [4] */);
+
+/* Kernel timing: when enabled, eager batched searches on this context record
+ * a pair of HIP events around the search kernel on the launch stream;
+ * fl_get_profile waits for the last of them and returns the summed kernel
+ * time in milliseconds and the number of launches since profiling was
+ * enabled (then clears them).  Graph launches are not timed. */
+int fl_set_profiling(fl_ctx* ctx, int enable);
+int fl_get_profile(fl_ctx* ctx, double* total_ms /* host */, int64_t* launches /* host */);
+
+/* Test hook: cap the provisional-ADD and matched-pair lists at `cap`
+ * entries (0 restores the default) so that their overflow paths, full scans
+ * of the pair outputs, run.  Results are unchanged. */
+int fl_debug_set_list_cap(fl_ctx* ctx, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTLOOP_H */

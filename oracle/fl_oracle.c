@@ -13,7 +13,8 @@
  *   sf[n]   = (float) pow(scale_factor, n), n < n_octaves (computed in double)
  *   r0      = win_px,  invw = (float)grid_cols / W,  invh = (float)grid_rows / H
  *   id(p)   = mp_id[p] if given, else the global index of p
- *   SKIP    (4) if id(p) equals kp_owner[i] for some keypoint i of k
+ *   SKIP    (4) if id(p) equals kp_owner[i] >= 0 for some keypoint i of k
+ *           (kp_owner < 0 marks a free keypoint)
  *   q_j     = fmaf(A[j][2], z, fmaf(A[j][1], y, fmaf(A[j][0], x, t[j])))
  *   NOT_VISIBLE (0) unless q_2 > 0
  *   iz = 1/q_2,  u = fmaf(fx, q_0*iz, cx),  v = fmaf(fy, q_1*iz, cy)
@@ -201,7 +202,7 @@ int orc_search_fuse(int n_kf, const int32_t* kp_offset, const float* kp_xy, cons
 
             int observed = 0;
             for (int i = 0; i < nkp; ++i)
-                if (ow[i] == id) { observed = 1; break; }
+                if (ow[i] >= 0 && ow[i] == id) { observed = 1; break; }
             if (observed) { decision[o] = D_SKIP; continue; }
 
             float u, v, d;
@@ -330,7 +331,7 @@ int orc_census_fp64(int n_kf, const int32_t* kp_offset, const float* kp_xy, cons
             const int32_t id = mp_id ? mp_id[gp] : (int32_t)gp;
             int observed = 0;
             for (int i = 0; i < nkp; ++i)
-                if (ow[i] == id) { observed = 1; break; }
+                if (ow[i] >= 0 && ow[i] == id) { observed = 1; break; }
             if (observed) continue;
             ++n_exam;
             const float x = mp_xyz[3 * gp], y = mp_xyz[3 * gp + 1], z = mp_xyz[3 * gp + 2];
@@ -421,5 +422,13 @@ int orc_project(int n, const float* X, const float* S, const float* K, const flo
         d[i] = dd;
         pred[i] = vis[i] ? pr : -1;
     }
+    return 0;
+}
+
+/* Keypoint cell grid of one keyframe (the CSR the search scans). */
+int orc_build_grid(int n, const float* xy, int C, int R, float W, float H, int32_t* cell_start,
+                   int32_t* cell_kp) {
+    if (n < 0 || C < 1 || R < 1) return -1;
+    build_grid(n, xy, C, R, (float)C / W, (float)R / H, cell_start, cell_kp);
     return 0;
 }

@@ -165,3 +165,18 @@ def project(X, S16, cam8, dmax=None, params=None):
     if rc != 0:
         raise ValueError("oracle rejected the parameters")
     return u, v, d, pred, vis.astype(bool)
+
+
+def build_grid(xy, cam8, params):
+    """(cell_start [C*R+1], cell_kp [n]) of one keyframe's keypoints."""
+    lib = _load()
+    xy = np.ascontiguousarray(xy, np.float32).reshape(-1, 2)
+    C, R = int(params.grid_cols), int(params.grid_rows)
+    cs = np.empty(C * R + 1, np.int32)
+    ck = np.empty(max(len(xy), 1), np.int32)
+    lib.orc_build_grid.restype = ctypes.c_int
+    rc = lib.orc_build_grid(ctypes.c_int(len(xy)), _ptr(xy), ctypes.c_int(C), ctypes.c_int(R),
+                            ctypes.c_float(float(cam8[4])), ctypes.c_float(float(cam8[5])), _ptr(cs), _ptr(ck))
+    if rc != 0:
+        raise ValueError("oracle rejected the grid")
+    return cs, ck[: len(xy)]

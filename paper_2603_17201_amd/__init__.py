@@ -1,0 +1,20 @@
+"""MI355X (gfx950) library for Sim3-corrected search-and-fuse (loop fusion)
+and the Sim3 reprojection residual, after FastLoop (arXiv 2603.17201).
+
+The compute lives in ``libfastloop.so`` (HIP, built by ``build.py``) behind
+the C ABI of ``include/fastloop.h``; this package only marshals arguments.
+"""
+from ._abi import (ADD, FUSE, INVALID, MAX_KP, NO_DIST, NO_MATCH, NOT_VISIBLE, SKIP,  # noqa: F401
+                   LIB_PATH, SIGNATURES, load, last_error)
+
+__all__ = ["load", "last_error", "LIB_PATH", "SIGNATURES", "Context", "DeviceBatch", "FuseOutputs",
+           "Sim3Residual", "FlError"]
+
+
+def __getattr__(name):
+    # the torch-facing binding is imported lazily so that the ABI can be
+    # inspected without importing torch
+    if name in ("Context", "DeviceBatch", "FuseOutputs", "Sim3Residual", "FlError", "params_struct"):
+        from . import binding
+        return getattr(binding, name)
+    raise AttributeError(name)

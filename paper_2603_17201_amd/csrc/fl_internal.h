@@ -1,0 +1,226 @@
+// Internal layouts and device helpers of the fastloop library (gfx950).
+//
+// The batch descriptor lives in device memory (uploaded once per call from a
+// pinned staging buffer); every kernel takes only a pointer to it, so one
+// captured HIP graph serves batches of any size up to the workspace capacity.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fastloop.h"
+
+namespace fl {
+
+constexpr int kWave = 64;
+constexpr int kMaxQueues = 8;        // one work queue per XCD
+constexpr int kCounterWords = 64;    // uint32 counters at the head of the counter block
+
+// counter block layout (uint32 words, then uint64 stats)
+enum : int {
+    kCtrQueue = 0,          // [0, 8) per-queue tile counters
+    kCtrAdd = 8,            // provisional-ADD list length
+    kCtrRefineDone = 16,    // [16, 16+?) unused; per-event done counters live in their own array
+};
+
+// One keyframe of a batch: search transform, camera, grid and ranges.
+struct alignas(16) KfDesc {
+    float A[9];          // sR, row-major
+    float t[3];
+    float inv_s;
+    float fx, fy, cx, cy, W, H;
+    float invw, invh;    // grid_cols / W, grid_rows / H (float32, rounded once)
+    float T[12];         // world->camera SE3 for refinement (R row-major, t)
+    int32_t kp_off;      // first keypoint (global index)
+    int32_t n_kp;
+    int32_t grid_off;    // first cell_start entry
+    int32_t event;
+    int32_t mp_off;      // first point of the event (global index)
+    int32_t n_mp;        // points in the event
+    int32_t hash_off;    // owner hash table of this keyframe
+    int32_t hash_mask;
+    int32_t tile_off;    // first tile of this keyframe in the tile table
+    int32_t n_tiles;
+    int64_t pair_off;
+    int64_t n_pairs;
+};
+
+struct alignas(16) EventDesc {
+    int32_t kf_begin, kf_end;
+    int32_t mp_off, n_mp;
+    int32_t list_off, list_cap;    // region of the matched-pair list
+    int64_t pair_begin, pair_end;  // pair range (pairs of the event are contiguous)
+};
+
+// Entry of the provisional-ADD and matched-pair lists.
+struct alignas(16) PairRef {
+    int32_t pair;     // global pair index
+    int32_t kp;       // global keypoint index of the best candidate
+    int32_t gp;       // global point index
+    int32_t kf;       // keyframe index
+};
+
+// Cell-ordered keypoint record used by the batched search: 16 bytes, one
+// dwordx4 load.  idx is the keypoint index within its keyframe.
+struct alignas(16) KpRec {
+    float x, y;
+    int32_t idx;
+    int32_t oct;
+};
+
+struct alignas(16) BatchHdr {
+    int32_t n_events, n_kf, n_mp, n_kp_total;
+    int64_t n_pairs;
+    int32_t n_tiles, tile_pairs;
+    int32_t cells, grid_cols, grid_rows, n_octaves;
+    int32_t hamming_th;
+    float nn_ratio;
+    float r0;
+    int32_t gate;               // 1: point distance invariance given (octave gate on)
+    int32_t dense;
+    int32_t n_queues;
+    int32_t queue_begin[kMaxQueues + 1];
+    int32_t add_cap;            // capacity of the provisional-ADD list
+    int32_t stats;              // 1: count visible / cells / keypoints / candidates
+    float sf[32];               // scale_factor^n rounded to float32
+    // tables in the uploaded blob
+    const KfDesc* kf;
+    const EventDesc* ev;
+    int2* tile;                 // [n_tiles] (keyframe, tile index within keyframe)
+    // inputs (caller-owned)
+    const float* kp_xy;
+    const int8_t* kp_oct;
+    const uint8_t* kp_desc;
+    const int32_t* kp_owner;
+    const float* mp_xyz;
+    const uint8_t* mp_desc;
+    const float* mp_dmax;
+    const int32_t* mp_id;
+    const int32_t* pair_mp;
+    // outputs (caller-owned)
+    int32_t* best_idx;
+    int16_t* best_dist;
+    int16_t* second_dist;
+    uint8_t* decision;
+    int32_t* target;
+    // workspace (library-owned)
+    int32_t* cell_start;        // [n_kf * (cells + 1)]
+    KpRec* recs;                // [n_kp_total]
+    uint4* desc_sorted;         // [n_kp_total * 2]
+    int32_t* cell_kp;           // [n_kp_total] (original keypoint index per slot)
+    int32_t* hash;              // owner hash tables
+    int32_t* claim;             // [n_kp_total]
+    PairRef* add_list;          // [add_cap]
+    PairRef* match_list;        // [sum of event list caps]
+    uint32_t* counters;         // [kCounterWords]
+    unsigned long long* stats_out;  // [4]
+    uint32_t* ev_match_count;   // [n_events]
+    // refinement
+    int32_t refine_iters;
+    float huber_delta;
+    int32_t refine_blocks;      // blocks per event
+    int32_t refine_scan;        // 1: take accepted pairs from the decisions, not the list
+    double* event_S;            // [n_events][13]
+    fl_sim3* event_S32;         // [n_events] (workspace copy used by the kernels)
+    fl_sim3* event_S32_out;     // caller's copy (may be null)
+    int32_t* event_n_matched;   // caller's (may be null)
+    double* refine_partial;     // [n_events * refine_blocks * 36]
+    uint32_t* refine_done;      // [n_events]
+};
+
+// ---------------------------------------------------------------------------
+// float32 helpers whose rounding is fixed: every multiply-add written as
+// fmaf is one fused operation, every other operation rounds on its own (the
+// library is compiled with -ffp-contract=off).
+
+__device__ __forceinline__ int cell_of(float x, float inv, int n) {
+    const float f = floorf(x * inv);
+    if (!(f >= 0.0f)) return 0;   // negative or NaN
+    if (f >= (float)n) return n - 1;
+    return (int)f;
+}
+
+struct Proj {
+    float u, v, d;
+    int pred;
+};
+
+// Transform by the keyframe's Sim3, pinhole projection, image test and
+// predicted octave.  Returns false when the point is not visible.
+__device__ __forceinline__ bool project(const KfDesc& k, float x, float y, float z, float dmax, int gate,
+                                        const float* sf, int N, Proj& p) {
+    const float q0 = fmaf(k.A[2], z, fmaf(k.A[1], y, fmaf(k.A[0], x, k.t[0])));
+    const float q1 = fmaf(k.A[5], z, fmaf(k.A[4], y, fmaf(k.A[3], x, k.t[1])));
+    const float q2 = fmaf(k.A[8], z, fmaf(k.A[7], y, fmaf(k.A[6], x, k.t[2])));
+    if (!(q2 > 0.0f)) return false;
+    const float iz = 1.0f / q2;
+    const float u = fmaf(k.fx, q0 * iz, k.cx);
+    const float v = fmaf(k.fy, q1 * iz, k.cy);
+    if (!(u >= 0.0f && u < k.W && v >= 0.0f && v < k.H)) return false;
+    const float d = sqrtf(fmaf(q0, q0, fmaf(q1, q1, q2 * q2))) * k.inv_s;
+    int pred = N - 1;
+    if (gate) {
+        for (int n = 0; n < N; ++n) {
+            if (d * sf[n] >= dmax) { pred = n; break; }
+        }
+    }
+    p.u = u;
+    p.v = v;
+    p.d = d;
+    p.pred = pred;
+    return true;
+}
+
+__device__ __forceinline__ int hamming(const uint4& a0, const uint4& a1, const uint4& b0, const uint4& b1) {
+    int h = __popc(a0.x ^ b0.x);
+    h += __popc(a0.y ^ b0.y);
+    h += __popc(a0.z ^ b0.z);
+    h += __popc(a0.w ^ b0.w);
+    h += __popc(a1.x ^ b1.x);
+    h += __popc(a1.y ^ b1.y);
+    h += __popc(a1.z ^ b1.z);
+    h += __popc(a1.w ^ b1.w);
+    return h;
+}
+
+// Running best / second best over packed keys (h << 16 | idx): the minimum
+// key is the lexicographic minimum of (distance, keypoint index), so the
+// result does not depend on the order candidates are visited in.
+struct Best {
+    uint32_t key;   // 0xFFFFFFFF: none
+    int second;     // FL_NO_DIST: none
+    __device__ __forceinline__ void init() {
+        key = 0xFFFFFFFFu;
+        second = FL_NO_DIST;
+    }
+    __device__ __forceinline__ void offer(int h, int idx) {
+        const uint32_t k = ((uint32_t)h << 16) | (uint32_t)idx;
+        if (k < key) {
+            if (key != 0xFFFFFFFFu) second = min(second, (int)(key >> 16));
+            key = k;
+        } else {
+            second = min(second, h);
+        }
+    }
+};
+
+__device__ __forceinline__ uint32_t hash_id(int32_t id) {
+    return (uint32_t)id * 0x9E3779B1u;
+}
+
+// Is `id` among the owners stored in a keyframe's open-addressing table?
+__device__ __forceinline__ bool owner_lookup(const int32_t* __restrict__ table, int32_t mask, int32_t id) {
+    if (id < 0) return false;
+    uint32_t h = (hash_id(id) >> 7) & (uint32_t)mask;
+    for (int probe = 0; probe <= mask; ++probe) {
+        const int32_t v = table[h];
+        if (v == id) return true;
+        if (v < 0) return false;
+        h = (h + 1) & (uint32_t)mask;
+    }
+    return false;
+}
+
+__device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
+
+}  // namespace fl

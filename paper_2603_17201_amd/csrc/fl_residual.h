@@ -1,0 +1,504 @@
+// Sim3 reprojection residual, its hand-written backward, the float64 Sim3
+// exponential and the Gauss-Newton step, plus per-event refinement of the
+// loop Sim3 on the pairs a search accepted.
+//
+// The paper refines the loop Sim3 between its two projection searches
+// (Sec. IV-C) and optimises poses with Jacobians it obtains by automatic
+// differentiation (Sec. IV-F).  Here the residual of a matched pair is
+//   p = sR X + t,  q = R_k p + t_k,  r = pi(q) - uv,
+// its Jacobian with respect to a left perturbation xi = (omega, upsilon,
+// sigma) of the Sim3 is written out by hand,
+//   J = dpi/dq R_k [ -[p]x | I | p ],
+// per-pair arithmetic is float32 and every sum is float64 with a fixed
+// reduction order (thread, wave, block, then blocks in index order).
+#pragma once
+
+#include "fl_internal.h"
+
+namespace fl {
+
+constexpr int kResBlock = 256;
+constexpr int kNAcc = 36;   // 7 gradient + 28 upper-triangle H + 1 loss
+
+// ---------------------------------------------------------------------------
+// float64 Sim3 algebra
+
+struct Sim3d {
+    double R[9];
+    double t[3];
+    double s;
+};
+
+__device__ inline double exp_moment(int n, double s) {
+    // I_n(s) = integral_0^1 e^{s tau} tau^n d tau
+    if (fabs(s) < 2.0) {
+        double term = 1.0, sum = 0.0;
+        for (int k = 0; k < 60; ++k) {
+            const double c = term / (double)(n + k + 1);
+            sum += c;
+            if (fabs(c) < 1e-18 * fabs(sum)) break;
+            term *= s / (double)(k + 1);
+        }
+        return sum;
+    }
+    const double es = exp(s);
+    double I = expm1(s) / s;
+    for (int m = 1; m <= n; ++m) I = (es - (double)m * I) / s;
+    return I;
+}
+
+// exp of a tangent xi = (omega, upsilon, sigma):  R = exp([omega]x),
+// s = e^sigma, t = V upsilon with V = integral_0^1 e^{sigma tau} exp(tau [omega]x) d tau
+// = c0 I + c1 W + c2 W^2 (closed form; series for small rotation angles).
+__device__ inline Sim3d sim3_exp(const double* xi) {
+    const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
+    const double sig = xi[6];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    const double th = sqrt(th2);
+    double a, b;
+    if (th < 1e-4) {
+        a = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        b = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    } else {
+        a = sin(th) / th;
+        b = (1.0 - cos(th)) / th2;
+    }
+    const double c0 = exp_moment(0, sig);
+    double c1, c2;
+    if (th < 1e-2) {
+        c1 = exp_moment(1, sig) - th2 / 6.0 * exp_moment(3, sig) + th2 * th2 / 120.0 * exp_moment(5, sig);
+        c2 = 0.5 * exp_moment(2, sig) - th2 / 24.0 * exp_moment(4, sig) + th2 * th2 / 720.0 * exp_moment(6, sig);
+    } else {
+        const double es = exp(sig);
+        const double den = sig * sig + th2;
+        c1 = (es * (sig * sin(th) - th * cos(th)) + th) / (th * den);
+        c2 = (c0 - (es * (sig * cos(th) + th * sin(th)) - sig) / den) / th2;
+    }
+    const double W[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+    double W2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            W2[3 * i + j] = W[3 * i] * W[j] + W[3 * i + 1] * W[3 + j] + W[3 * i + 2] * W[6 + j];
+    Sim3d S;
+    double V[9];
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        S.R[i] = I + a * W[i] + b * W2[i];
+        V[i] = c0 * I + c1 * W[i] + c2 * W2[i];
+    }
+    for (int i = 0; i < 3; ++i) S.t[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
+    S.s = exp(sig);
+    return S;
+}
+
+// A o B  (X -> A(B(X)))
+__device__ inline Sim3d sim3_mul(const Sim3d& A, const Sim3d& B) {
+    Sim3d C;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            C.R[3 * i + j] = A.R[3 * i] * B.R[j] + A.R[3 * i + 1] * B.R[3 + j] + A.R[3 * i + 2] * B.R[6 + j];
+        C.t[i] = A.s * (A.R[3 * i] * B.t[0] + A.R[3 * i + 1] * B.t[1] + A.R[3 * i + 2] * B.t[2]) + A.t[i];
+    }
+    C.s = A.s * B.s;
+    return C;
+}
+
+__device__ inline Sim3d sim3_load(const double* p) {
+    Sim3d S;
+    for (int i = 0; i < 9; ++i) S.R[i] = p[i];
+    for (int i = 0; i < 3; ++i) S.t[i] = p[9 + i];
+    S.s = p[12];
+    return S;
+}
+
+__device__ inline void sim3_store(const Sim3d& S, double* p) {
+    for (int i = 0; i < 9; ++i) p[i] = S.R[i];
+    for (int i = 0; i < 3; ++i) p[9 + i] = S.t[i];
+    p[12] = S.s;
+}
+
+__device__ inline void sim3_to_f32(const Sim3d& S, fl_sim3* o) {
+    for (int i = 0; i < 9; ++i) o->sR[i] = (float)(S.s * S.R[i]);
+    for (int i = 0; i < 3; ++i) o->t[i] = (float)S.t[i];
+    o->inv_s = (float)(1.0 / S.s);
+    o->pad[0] = o->pad[1] = o->pad[2] = 0.0f;
+}
+
+// Solve (H + lambda diag H) d = -g by Cholesky; H given as its 28 upper
+// entries row by row.  Returns false (d = 0) for a non-positive pivot.
+__device__ inline bool solve7(const double* g, const double* Hu, double lambda, double* d) {
+    double L[49];
+    int k = 0;
+    double dmax = 0.0;
+    for (int i = 0; i < 7; ++i)
+        for (int j = i; j < 7; ++j) {
+            L[7 * i + j] = Hu[k];
+            L[7 * j + i] = Hu[k];
+            ++k;
+        }
+    for (int i = 0; i < 7; ++i) {
+        L[8 * i] *= (1.0 + lambda);
+        dmax = fmax(dmax, fabs(L[8 * i]));
+    }
+    for (int j = 0; j < 7; ++j) {
+        double s = L[8 * j];
+        for (int m = 0; m < j; ++m) s -= L[7 * j + m] * L[7 * j + m];
+        if (!(s > 1e-14 * dmax)) {
+            for (int i = 0; i < 7; ++i) d[i] = 0.0;
+            return false;
+        }
+        const double ljj = sqrt(s);
+        L[8 * j] = ljj;
+        for (int i = j + 1; i < 7; ++i) {
+            double v = L[7 * i + j];
+            for (int m = 0; m < j; ++m) v -= L[7 * i + m] * L[7 * j + m];
+            L[7 * i + j] = v / ljj;
+        }
+    }
+    double y[7];
+    for (int i = 0; i < 7; ++i) {
+        double v = -g[i];
+        for (int m = 0; m < i; ++m) v -= L[7 * i + m] * y[m];
+        y[i] = v / L[8 * i];
+    }
+    for (int i = 6; i >= 0; --i) {
+        double v = y[i];
+        for (int m = i + 1; m < 7; ++m) v -= L[7 * m + i] * d[m];
+        d[i] = v / L[8 * i];
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// per-pair residual and Jacobian (float32)
+
+struct PairTerm {
+    float r0, r1, w, rho;
+    float J[2][7];
+    bool valid;
+};
+
+__device__ __forceinline__ void pair_term(const float* A, const float* tS, const float* T, float fx, float fy,
+                                          float cx, float cy, float x, float y, float z, float uo, float vo,
+                                          float delta, bool need_J, PairTerm& o) {
+    const float p0 = A[0] * x + A[1] * y + A[2] * z + tS[0];
+    const float p1 = A[3] * x + A[4] * y + A[5] * z + tS[1];
+    const float p2 = A[6] * x + A[7] * y + A[8] * z + tS[2];
+    float q0 = p0, q1 = p1, q2 = p2;
+    if (T) {
+        q0 = T[0] * p0 + T[1] * p1 + T[2] * p2 + T[9];
+        q1 = T[3] * p0 + T[4] * p1 + T[5] * p2 + T[10];
+        q2 = T[6] * p0 + T[7] * p1 + T[8] * p2 + T[11];
+    }
+    o.valid = q2 > 0.0f;
+    if (!o.valid) {
+        o.r0 = o.r1 = o.w = o.rho = 0.0f;
+        return;
+    }
+    const float iz = 1.0f / q2;
+    o.r0 = fx * q0 * iz + cx - uo;
+    o.r1 = fy * q1 * iz + cy - vo;
+    const float e = sqrtf(o.r0 * o.r0 + o.r1 * o.r1);
+    if (e <= delta) {
+        o.w = 1.0f;
+        o.rho = 0.5f * e * e;
+    } else {
+        o.w = delta / e;
+        o.rho = delta * e - 0.5f * delta * delta;
+    }
+    if (!need_J) return;
+    // M = dpi/dq R_k (2 x 3)
+    const float a0 = fx * iz, a2 = -fx * q0 * iz * iz;
+    const float b1 = fy * iz, b2 = -fy * q1 * iz * iz;
+    float M[2][3];
+    if (T) {
+        for (int c = 0; c < 3; ++c) {
+            M[0][c] = a0 * T[c] + a2 * T[6 + c];
+            M[1][c] = b1 * T[3 + c] + b2 * T[6 + c];
+        }
+    } else {
+        M[0][0] = a0; M[0][1] = 0.0f; M[0][2] = a2;
+        M[1][0] = 0.0f; M[1][1] = b1; M[1][2] = b2;
+    }
+    for (int r = 0; r < 2; ++r) {
+        const float m0 = M[r][0], m1 = M[r][1], m2 = M[r][2];
+        o.J[r][0] = p1 * m2 - p2 * m1;   // p x m: derivative along omega
+        o.J[r][1] = p2 * m0 - p0 * m2;
+        o.J[r][2] = p0 * m1 - p1 * m0;
+        o.J[r][3] = m0;                  // upsilon
+        o.J[r][4] = m1;
+        o.J[r][5] = m2;
+        o.J[r][6] = m0 * p0 + m1 * p1 + m2 * p2;   // sigma
+    }
+}
+
+// acc[0..6] += w J^T r, acc[7..34] += w J^T J (upper, row by row), in float64
+__device__ __forceinline__ void accumulate(const PairTerm& t, double* acc) {
+    const double w = t.w, r0 = t.r0, r1 = t.r1;
+    double J0[7], J1[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        J0[i] = t.J[0][i];
+        J1[i] = t.J[1][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] += w * (J0[i] * r0 + J1[i] * r1);
+    int k = 7;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = i; j < 7; ++j) acc[k++] += w * (J0[i] * J0[j] + J1[i] * J1[j]);
+}
+
+// Block reduction of NV doubles per thread (fixed order).  Result valid in
+// s_out[0..NV) after the call.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double* v, double* s_red, double* s_out) {
+    const int lane = wave_lane();
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        v[i] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s_red[wid * NV + i] = v[i];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += s_red[w * NV + threadIdx.x];
+        s_out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+struct ResArgs {
+    int32_t n;
+    int32_t n_kf;
+    const float* xyz;
+    const float* uv;
+    const int32_t* kf_idx;
+    const float* kf_T;
+    const fl_sim3* S;
+    float fx, fy, cx, cy;
+    float delta;
+    double grad_scale;
+    float* r;
+    float* w;
+    double* loss;
+    double* g;
+    double* H;
+    double* partial;      // [gridDim.x][kNAcc]
+    uint32_t* done;       // one counter, zero on entry and on exit
+};
+
+__device__ __forceinline__ bool load_pair(const ResArgs& a, int i, float& x, float& y, float& z, float& uo,
+                                          float& vo, const float*& T) {
+    x = a.xyz[3 * (int64_t)i];
+    y = a.xyz[3 * (int64_t)i + 1];
+    z = a.xyz[3 * (int64_t)i + 2];
+    uo = a.uv[2 * (int64_t)i];
+    vo = a.uv[2 * (int64_t)i + 1];
+    T = nullptr;
+    if (a.kf_idx) {
+        const int k = a.kf_idx[i];
+        if (k < 0 || k >= a.n_kf) return false;
+        if (a.kf_T) T = a.kf_T + 12 * (int64_t)k;
+    } else if (a.kf_T) {
+        T = a.kf_T;
+    }
+    return true;
+}
+
+// Sum the per-block partials (in block order) in the last block to finish.
+__device__ __forceinline__ bool last_block(uint32_t* done) {
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (s_last) __threadfence();   // acquire: see every block's partial (L2s of other XCDs)
+    return s_last != 0;
+}
+
+__global__ __launch_bounds__(kResBlock) void residual_fwd_kernel(ResArgs a) {
+    __shared__ double s_red[(kResBlock / kWave) * 1];
+    __shared__ double s_out[1];
+    const fl_sim3 S = *a.S;
+    double acc[1] = {0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+        float x, y, z, uo, vo;
+        const float* T;
+        PairTerm t;
+        if (load_pair(a, i, x, y, z, uo, vo, T)) {
+            pair_term(S.sR, S.t, T, a.fx, a.fy, a.cx, a.cy, x, y, z, uo, vo, a.delta, false, t);
+        } else {
+            t.valid = false;
+            t.r0 = t.r1 = t.w = t.rho = 0.0f;
+        }
+        if (a.r) {
+            a.r[2 * (int64_t)i] = t.r0;
+            a.r[2 * (int64_t)i + 1] = t.r1;
+        }
+        if (a.w) a.w[i] = t.w;
+        acc[0] += (double)t.rho;
+    }
+    block_reduce<1>(acc, s_red, s_out);
+    if (threadIdx.x == 0) a.partial[blockIdx.x * kNAcc] = s_out[0];
+    if (last_block(a.done)) {
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += a.partial[b * kNAcc];
+            *a.loss = s;
+            *a.done = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kResBlock) void residual_bwd_kernel(ResArgs a) {
+    __shared__ double s_red[(kResBlock / kWave) * 35];
+    __shared__ double s_out[35];
+    const fl_sim3 S = *a.S;
+    double acc[35];
+#pragma unroll
+    for (int i = 0; i < 35; ++i) acc[i] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+        float x, y, z, uo, vo;
+        const float* T;
+        if (!load_pair(a, i, x, y, z, uo, vo, T)) continue;
+        PairTerm t;
+        pair_term(S.sR, S.t, T, a.fx, a.fy, a.cx, a.cy, x, y, z, uo, vo, a.delta, true, t);
+        if (t.valid) accumulate(t, acc);
+    }
+    block_reduce<35>(acc, s_red, s_out);
+    if ((int)threadIdx.x < 35) a.partial[blockIdx.x * kNAcc + threadIdx.x] = s_out[threadIdx.x];
+    if (last_block(a.done)) {
+        if ((int)threadIdx.x < 35) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += a.partial[b * kNAcc + threadIdx.x];
+            if (threadIdx.x < 7) a.g[threadIdx.x] = a.grad_scale * s;
+            else if (a.H) a.H[threadIdx.x - 7] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *a.done = 0;
+    }
+}
+
+__global__ void sim3_exp_mul_kernel(const double* __restrict__ xi, const double* __restrict__ S_in,
+                                    double* __restrict__ S_out, fl_sim3* __restrict__ S32) {
+    if (threadIdx.x != 0) return;
+    const Sim3d E = sim3_exp(xi);
+    const Sim3d S = sim3_mul(E, sim3_load(S_in));
+    sim3_store(S, S_out);
+    if (S32) sim3_to_f32(S, S32);
+}
+
+__global__ void gn_step_kernel(const double* __restrict__ g, const double* __restrict__ H, double lambda,
+                               double* __restrict__ S_io, fl_sim3* __restrict__ S32) {
+    if (threadIdx.x != 0) return;
+    double d[7];
+    Sim3d S = sim3_load(S_io);
+    if (solve7(g, H, lambda, d)) {
+        S = sim3_mul(sim3_exp(d), S);
+        sim3_store(S, S_io);
+    }
+    if (S32) sim3_to_f32(S, S32);
+}
+
+// ---------------------------------------------------------------------------
+// Per-event refinement inside a batch: refine_blocks workgroups per event
+// accumulate g and H over the event's accepted pairs; the last of them
+// solves the 7x7 system and updates the event's Sim3.
+
+__global__ void refine_init_kernel(const BatchHdr* __restrict__ hp) {
+    const BatchHdr& h = *hp;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < h.n_events; e += gridDim.x * blockDim.x) {
+        sim3_to_f32(sim3_load(h.event_S + 13 * (int64_t)e), &h.event_S32[e]);
+        h.refine_done[e] = 0;
+    }
+}
+
+__device__ __forceinline__ void refine_accumulate(const BatchHdr& h, const PairRef& e, const fl_sim3& S, float delta,
+                                                  double* acc) {
+    const KfDesc& kd = h.kf[e.kf];
+    const float x = h.mp_xyz[3 * (int64_t)e.gp], y = h.mp_xyz[3 * (int64_t)e.gp + 1],
+                z = h.mp_xyz[3 * (int64_t)e.gp + 2];
+    const float uo = h.kp_xy[2 * (int64_t)e.kp], vo = h.kp_xy[2 * (int64_t)e.kp + 1];
+    PairTerm t;
+    pair_term(S.sR, S.t, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, x, y, z, uo, vo, delta, true, t);
+    if (t.valid) {
+        accumulate(t, acc);
+        acc[35] += 1.0;
+    }
+}
+
+__global__ __launch_bounds__(kResBlock) void refine_iter_kernel(const BatchHdr* __restrict__ hp) {
+    __shared__ double s_red[(kResBlock / kWave) * kNAcc];
+    __shared__ double s_out[kNAcc];
+    __shared__ int s_last;
+    const BatchHdr& h = *hp;
+    const int B = h.refine_blocks;
+    for (int eb = blockIdx.x; eb < h.n_events * B; eb += gridDim.x) {
+        const int ev = eb / B, b = eb % B;
+        const EventDesc& ed = h.ev[ev];
+        const fl_sim3 S = h.event_S32[ev];
+        double acc[kNAcc];
+#pragma unroll
+        for (int i = 0; i < kNAcc; ++i) acc[i] = 0.0;
+        const uint32_t cnt = h.ev_match_count[ev];
+        const int stride = B * blockDim.x;
+        if (!h.refine_scan && cnt <= (uint32_t)ed.list_cap) {
+            for (int i = b * blockDim.x + threadIdx.x; i < (int)cnt; i += stride)
+                refine_accumulate(h, h.match_list[ed.list_off + i], S, h.huber_delta, acc);
+        } else {
+            // the list overflowed: scan the event's pairs keyframe by keyframe
+            for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
+                const KfDesc& kd = h.kf[k];
+                for (int64_t j = b * blockDim.x + threadIdx.x; j < kd.n_pairs; j += stride) {
+                    const int64_t o = kd.pair_off + j;
+                    const uint8_t dec = h.decision[o];
+                    if (dec != FL_ADD && dec != FL_FUSE) continue;
+                    PairRef e;
+                    e.pair = (int32_t)o;
+                    e.kp = kd.kp_off + h.best_idx[o];
+                    e.gp = kd.mp_off + (h.dense ? (int32_t)j : h.pair_mp[o]);
+                    e.kf = k;
+                    refine_accumulate(h, e, S, h.huber_delta, acc);
+                }
+            }
+        }
+        block_reduce<kNAcc>(acc, s_red, s_out);
+        double* part = h.refine_partial + ((int64_t)ev * B + b) * kNAcc;
+        if ((int)threadIdx.x < kNAcc) part[threadIdx.x] = s_out[threadIdx.x];
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(&h.refine_done[ev], 1u) == (uint32_t)(B - 1);
+        __syncthreads();
+        if (s_last) __threadfence();   // acquire before reading the other blocks' partials
+        if (s_last && threadIdx.x == 0) {
+            double gh[kNAcc];
+            for (int i = 0; i < kNAcc; ++i) {
+                double s = 0.0;
+                for (int bb = 0; bb < B; ++bb) s += h.refine_partial[((int64_t)ev * B + bb) * kNAcc + i];
+                gh[i] = s;
+            }
+            double d[7];
+            Sim3d Sd = sim3_load(h.event_S + 13 * (int64_t)ev);
+            if (solve7(gh, gh + 7, 0.0, d)) {
+                Sd = sim3_mul(sim3_exp(d), Sd);
+                sim3_store(Sd, h.event_S + 13 * (int64_t)ev);
+            }
+            sim3_to_f32(Sd, &h.event_S32[ev]);
+            if (h.event_S32_out) h.event_S32_out[ev] = h.event_S32[ev];
+            if (h.event_n_matched) h.event_n_matched[ev] = (int32_t)gh[35];
+            h.refine_done[ev] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace fl

@@ -1,0 +1,140 @@
+"""The C ABI library loads, exports every function include/fastloop.h
+declares, and rejects invalid arguments on the host before any device work
+(no GPU needed: fl_validate_batch is host-only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2603_17201_amd as fl
+from paper_2603_17201_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastloop.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fl_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fl.LIB_PATH):
+        from paper_2603_17201_amd import build
+        build.build()
+    return fl.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares exactly the header's functions
+    assert sorted(s[0] for s in _abi.SIGNATURES) == names
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(_abi.Sim3) == 64
+    assert ctypes.sizeof(_abi.Pinhole) == 32
+    assert ctypes.sizeof(_abi.Params) == 32
+    assert ctypes.sizeof(_abi.FuseOut) == 40
+    assert ctypes.sizeof(_abi.Refine) == 32
+
+
+def _batch(n_kf=2, n_mp=10, n_kp=(5, 7), dense=True):
+    kp_off = np.concatenate([[0], np.cumsum(n_kp)]).astype(np.int32)
+    pair_off = (np.arange(n_kf + 1) * n_mp).astype(np.int64)
+    tables = dict(
+        ekf=np.array([0, n_kf], np.int32), emp=np.array([0, n_mp], np.int32), kp_off=kp_off,
+        pair_off=pair_off, sim3=np.zeros((n_kf, 16), np.float32),
+        K=np.tile(np.array([458, 458, 367, 248, 752, 480, 0, 0], np.float32), (n_kf, 1)))
+    b = _abi.Batch()
+    b.n_events, b.n_kf, b.n_mp, b.n_kp_total, b.n_pairs = 1, n_kf, n_mp, int(kp_off[-1]), int(pair_off[-1])
+    b.event_kf_offset = tables["ekf"].ctypes.data_as(ctypes.c_void_p)
+    b.event_mp_offset = tables["emp"].ctypes.data_as(ctypes.c_void_p)
+    b.kp_offset = tables["kp_off"].ctypes.data_as(ctypes.c_void_p)
+    b.pair_offset = tables["pair_off"].ctypes.data_as(ctypes.c_void_p)
+    b.kf_sim3 = tables["sim3"].ctypes.data_as(ctypes.c_void_p)
+    b.kf_K = tables["K"].ctypes.data_as(ctypes.c_void_p)
+    fake = 0x10000   # never dereferenced: validation is host-only
+    for f in ("kp_xy", "kp_octave", "kp_desc", "kp_owner", "mp_xyz", "mp_desc"):
+        setattr(b, f, fake)
+    o = _abi.FuseOut(fake, fake, fake, fake, fake)
+    P = _abi.Params(3.0, 1.2, 8, 64, 48, 50, 0.0, 0)
+    return b, P, o, tables
+
+
+def test_validate_accepts_a_consistent_batch(lib):
+    b, P, o, t = _batch()
+    assert lib.fl_validate_batch(ctypes.byref(b), ctypes.byref(P), ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("case,code", [
+    ("null_kp_xy", _abi.FL_EINVAL), ("negative_n_mp", _abi.FL_EINVAL), ("misaligned_desc", _abi.FL_EINVAL),
+    ("grid_overflow", _abi.FL_ERANGE), ("octaves_33", _abi.FL_ERANGE), ("octaves_0", _abi.FL_ERANGE),
+    ("too_many_kp", _abi.FL_ERANGE), ("nonfinite_K", _abi.FL_EINVAL), ("zero_width", _abi.FL_EINVAL),
+    ("kp_offset_total", _abi.FL_EINVAL), ("pair_offset_dense", _abi.FL_EINVAL), ("flags", _abi.FL_EINVAL),
+    ("win_nan", _abi.FL_EINVAL), ("event_offset_start", _abi.FL_EINVAL), ("null_output", _abi.FL_EINVAL),
+    ("pairs_2_31", _abi.FL_ERANGE),
+])
+def test_validate_rejects(lib, case, code):
+    b, P, o, t = _batch()
+    if case == "null_kp_xy":
+        b.kp_xy = None
+    elif case == "negative_n_mp":
+        b.n_mp = -1
+    elif case == "misaligned_desc":
+        b.mp_desc = 0x10004
+    elif case == "grid_overflow":
+        P.grid_cols, P.grid_rows = 100, 100
+    elif case == "octaves_33":
+        P.n_octaves = 33
+    elif case == "octaves_0":
+        P.n_octaves = 0
+    elif case == "too_many_kp":
+        t["kp_off"][1:] = [70000, 70007]
+        b.n_kp_total = 70007
+    elif case == "nonfinite_K":
+        t["K"][1, 0] = np.inf
+    elif case == "zero_width":
+        t["K"][0, 4] = 0.0
+    elif case == "kp_offset_total":
+        b.n_kp_total = 99
+    elif case == "pair_offset_dense":
+        t["pair_off"][1] = 9
+    elif case == "flags":
+        P.flags = 1
+    elif case == "win_nan":
+        P.win_px = float("nan")
+    elif case == "event_offset_start":
+        t["ekf"][0] = 1
+    elif case == "null_output":
+        o.decision = None
+    elif case == "pairs_2_31":
+        b.n_pairs = 2 ** 31
+    rc = lib.fl_validate_batch(ctypes.byref(b), ctypes.byref(P), ctypes.byref(o))
+    assert rc == code, (case, rc, fl.last_error())
+    assert fl.last_error()
+
+
+def test_null_context_is_rejected(lib):
+    P = _abi.Params(3.0, 1.2, 8, 64, 48, 50, 0.0, 0)
+    K = _abi.Pinhole(458, 458, 367, 248, 752, 480)
+    rc = lib.fl_build_grid(None, 0, None, ctypes.byref(K), ctypes.byref(P), None, None, None)
+    assert rc == _abi.FL_EINVAL
+    rc = lib.fl_set_stats(None, 1)
+    assert rc == _abi.FL_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError):
+        _abi._lib, saved = None, _abi._lib
+        try:
+            _abi.load(str(tmp_path / "nope.so"))
+        finally:
+            _abi._lib = saved

@@ -1,0 +1,176 @@
+"""GPU parity of the Sim3 residual, its hand-written backward, the Sim3
+exponential, the Gauss-Newton step, the autograd Function and per-event
+refinement against the float64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import residual as R
+from oracle import sim3
+from gpu_util import dev, t
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4   # relative error bound (infinity norm) of float32 per-pair terms vs float64
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2603_17201_amd as fl
+    c = fl.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def s32(S):
+    return t(sim3.to_f32_rows(S))
+
+
+def multi_view(n, seed):
+    rng = np.random.default_rng(seed)
+    d = synth.gen_c4(n=n, seed=seed, pix_sigma=0.0, outlier_frac=0.0)
+    T = np.array([sim3.exp(np.concatenate([rng.normal(size=3) * 0.1, rng.normal(size=3) * 0.5, [0.0]]))[:12]
+                  for _ in range(5)])
+    kf = rng.integers(0, 5, n).astype(np.int32)
+    _, q, uv, _ = R.project(d["S_true"], d["xyz"], kf, T, d["cam"])
+    uv = uv + rng.normal(0, 1.0, uv.shape)
+    out = rng.random(n) < 0.1
+    th = rng.uniform(0, 2 * np.pi, n)
+    uv[out] += 20 * np.stack([np.cos(th[out]), np.sin(th[out])], 1)
+    keep = q[:, 2] > 0.1
+    return d, d["xyz"][keep], uv[keep].astype(np.float32), kf[keep], T
+
+
+@pytest.fixture(scope="module")
+def c4():
+    d = synth.gen_c4()
+    d["S0"] = sim3.compose(sim3.exp(d["xi0"]), d["S_true"])
+    return d
+
+
+def test_forward_matches_fp64(ctx, c4):
+    S0 = c4["S0"]
+    r, w, loss = ctx.residual_fwd(t(c4["xyz"]), t(c4["uv"]), None, None, s32(S0), c4["cam"], c4["huber_delta"])
+    r64, w64, L64 = R.forward(sim3.from_matrix(sim3.to_matrix(S0)), c4["xyz"], c4["uv"], None, None, c4["cam"],
+                              c4["huber_delta"])
+    assert rel(r.cpu().numpy(), r64) < REL
+    assert rel(w.cpu().numpy(), w64) < REL
+    assert abs(loss.item() - L64) / L64 < REL
+
+
+def test_backward_matches_fp64_and_fd(ctx, c4):
+    S0 = c4["S0"]
+    g, H = ctx.residual_bwd(t(c4["xyz"]), t(c4["uv"]), None, None, s32(S0), c4["cam"], c4["huber_delta"])
+    g64, H64, _ = R.grad_hess(S0, c4["xyz"], c4["uv"], None, None, c4["cam"], c4["huber_delta"])
+    assert rel(g.cpu().numpy(), g64) < REL
+    assert rel(H.cpu().numpy(), R.H_upper(H64)) < REL
+    fd = R.fd_grad(S0, c4["xyz"], c4["uv"], None, None, c4["cam"], c4["huber_delta"], h=1e-4)
+    assert rel(g.cpu().numpy(), fd) < 2 * REL
+    # deterministic: same bits on a second call
+    g2, H2 = ctx.residual_bwd(t(c4["xyz"]), t(c4["uv"]), None, None, s32(S0), c4["cam"], c4["huber_delta"])
+    assert torch.equal(g, g2) and torch.equal(H, H2)
+
+
+def test_backward_with_keyframe_poses(ctx):
+    d, xyz, uv, kf, T = multi_view(30000, 5)
+    S0 = sim3.compose(sim3.exp(d["xi0"]), d["S_true"])
+    g, H = ctx.residual_bwd(t(xyz), t(uv), t(kf), t(T.astype(np.float32)), s32(S0), d["cam"], 2.45)
+    g64, H64, _ = R.grad_hess(S0, xyz, uv, kf, T, d["cam"], 2.45)
+    assert rel(g.cpu().numpy(), g64) < REL
+    assert rel(H.cpu().numpy(), R.H_upper(H64)) < REL
+
+
+def test_sim3_exp_mul_matches_expm(ctx):
+    rng = np.random.default_rng(2)
+    for scale in (1e-7, 1e-3, 0.05, 0.5, 2.0):
+        xi = rng.normal(size=7) * scale
+        S_in = sim3.exp(rng.normal(size=7) * 0.3)
+        S_out, S32 = ctx.sim3_exp_mul(t(xi), t(S_in))
+        exp = sim3.compose(sim3.exp(xi), S_in)
+        assert np.max(np.abs(S_out.cpu().numpy() - exp)) < 1e-12 * max(1.0, np.max(np.abs(exp))), scale
+        assert np.max(np.abs(S32.cpu().numpy() - sim3.to_f32_rows(exp))) < 1e-6
+
+
+def test_gn_step_matches_oracle(ctx, c4):
+    d, xyz, uv, kf, T = multi_view(20000, 8)
+    S0 = sim3.compose(sim3.exp(d["xi0"]), d["S_true"])
+    g64, H64, _ = R.grad_hess(S0, xyz, uv, kf, T, d["cam"], 2.45)
+    S = t(S0.copy())
+    S32 = torch.empty(16, dtype=torch.float32, device=dev())
+    ctx.gn_step(t(g64), t(R.H_upper(H64)), S, S32)
+    exp = sim3.compose(sim3.exp(np.linalg.solve(H64, -g64)), S0)
+    assert np.max(np.abs(S.cpu().numpy() - exp)) < 1e-9
+
+
+def test_autograd_function(ctx, c4):
+    import paper_2603_17201_amd as fl
+    S0 = t(c4["S0"])
+    xi = torch.zeros(7, dtype=torch.float64, device=dev(), requires_grad=True)
+    loss = fl.Sim3Residual.apply(xi, S0, t(c4["xyz"]), t(c4["uv"]), None, None, c4["cam"], c4["huber_delta"], ctx)
+    (2.0 * loss).backward()
+    g64, _, L64 = R.grad_hess(c4["S0"], c4["xyz"], c4["uv"], None, None, c4["cam"], c4["huber_delta"])
+    assert abs(loss.item() - L64) / L64 < REL
+    assert rel(xi.grad.cpu().numpy(), 2.0 * g64) < REL
+    # central differences of the Function itself around xi = 0
+    h = 1e-4
+    fd = np.zeros(7)
+    for i in range(7):
+        e = torch.zeros(7, dtype=torch.float64, device=dev())
+        e[i] = h
+        lp = fl.Sim3Residual.apply(e, S0, t(c4["xyz"]), t(c4["uv"]), None, None, c4["cam"], c4["huber_delta"], ctx)
+        lm = fl.Sim3Residual.apply(-e, S0, t(c4["xyz"]), t(c4["uv"]), None, None, c4["cam"], c4["huber_delta"], ctx)
+        fd[i] = (lp.item() - lm.item()) / (2 * h)
+    # float32 losses limit the difference quotient: compare on the dominant components
+    big = np.abs(g64) > 1e-3 * np.max(np.abs(g64))
+    assert np.max(np.abs(fd[big] - g64[big])) / np.max(np.abs(g64)) < 1e-3
+
+
+def test_refine_events_matches_oracle_gn(ctx):
+    import paper_2603_17201_amd as fl
+    ev = synth.gen_c2()
+    out = oracle.search_fuse(ev, use_grid=True)
+    b = fl.DeviceBatch(ev, device=dev())
+    res = ctx.search_fuse_graph(b, ev.params)
+    got = res.numpy()
+    for k in got:
+        assert np.array_equal(got[k], out[k]), k
+    # oracle GN on the accepted pairs
+    acc = np.nonzero((out["decision"] == oracle.ADD) | (out["decision"] == oracle.FUSE))[0]
+    kf = (np.searchsorted(ev.pair_offset, acc, side="right") - 1).astype(np.int32)
+    mp = acc - ev.pair_offset[kf]
+    kp = ev.kp_offset[kf] + out["best_idx"][acc]
+    xyz, uv = ev.mp_xyz[mp], ev.kp_xy[kp]
+    T32 = ev.kf_T.astype(np.float32).astype(np.float64)   # the keyframe poses the GPU sees
+    S_ref = R.gauss_newton(ev.S_init, xyz, uv, kf, T32, ev.cams[0], 2.45, iters=10)
+    for graph in (False, True):
+        event_S = t(ev.S_init.reshape(1, 13).copy())
+        nm = torch.zeros(1, dtype=torch.int32, device=dev())
+        ref = (10, 2.45, event_S, None, nm)
+        if graph:
+            ctx.search_fuse_graph(b, ev.params, refine=ref)
+        else:
+            ctx.refine_events(b, res, ref)
+        S_gpu = event_S.cpu().numpy()[0]
+        assert nm.item() == len(acc)
+        err = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(S_ref))))
+        assert err < 1e-6, (graph, err)
+        # and the refinement moved toward the truth
+        e_true = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(ev.S_true))))
+        e_init = np.linalg.norm(sim3.log(sim3.compose(ev.S_init, sim3.inverse(ev.S_true))))
+        assert e_true < e_init
+
+
+def test_zero_pairs(ctx):
+    z3 = torch.zeros((0, 3), dtype=torch.float32, device=dev())
+    z2 = torch.zeros((0, 2), dtype=torch.float32, device=dev())
+    S = s32(sim3.identity())
+    _, _, loss = ctx.residual_fwd(z3, z2, None, None, S, synth.scenes._cam_row(synth.CAM_752), 2.45)
+    g, H = ctx.residual_bwd(z3, z2, None, None, S, synth.scenes._cam_row(synth.CAM_752), 2.45)
+    assert loss.item() == 0.0 and torch.all(g == 0) and torch.all(H == 0)

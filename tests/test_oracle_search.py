@@ -257,3 +257,25 @@ def test_octave_extremes_and_threshold():
     pr = synth.LoopParams(**{**ev.params.__dict__, "nn_ratio": 0.8})
     r = oracle.search_fuse(ev, params=pr)
     assert r["decision"][0] == oracle.ADD and r["decision"][9] == oracle.NO_MATCH
+
+
+def test_grid_is_a_stable_counting_sort_by_cell():
+    ev = synth.gen_c3(n_kf=3, n_mp=1000)
+    p = ev.params
+    for k in range(ev.n_kf):
+        a, b = int(ev.kp_offset[k]), int(ev.kp_offset[k + 1])
+        xy = ev.kp_xy[a:b]
+        cs, ck = oracle.build_grid(xy, ev.cams[k], p)
+        # every keypoint lies in the cell it is listed under, in float64
+        cw = ev.cams[k][4] / p.grid_cols
+        ch = ev.cams[k][5] / p.grid_rows
+        cells = np.repeat(np.arange(p.grid_cols * p.grid_rows), np.diff(cs))
+        cx, cy = cells % p.grid_cols, cells // p.grid_cols
+        x, y = xy[ck, 0].astype(np.float64), xy[ck, 1].astype(np.float64)
+        inner = (x > 0) & (x < ev.cams[k][4]) & (y > 0) & (y < ev.cams[k][5])
+        assert np.all((x[inner] >= cx[inner] * cw - 1e-3) & (x[inner] <= (cx[inner] + 1) * cw + 1e-3))
+        assert np.all((y[inner] >= cy[inner] * ch - 1e-3) & (y[inner] <= (cy[inner] + 1) * ch + 1e-3))
+        assert sorted(ck.tolist()) == list(range(b - a))
+        for c in range(len(cs) - 1):
+            seg = ck[cs[c]:cs[c + 1]]
+            assert np.all(np.diff(seg) > 0)
