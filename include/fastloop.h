@@ -247,14 +247,16 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
                hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
-/* Tuning of the persistent search kernel.  Any tuning gives identical
+/* Tuning of the batched search kernel.  Any tuning gives identical
  * results; fl_autotune times the candidates on the given batch (the stream
  * is synchronised) and keeps the fastest in the context. */
 typedef struct {
-    int32_t pairs_per_lane;  /* 1, 2 or 4 */
-    int32_t block;           /* threads per workgroup: 64, 128, 256 or 512 */
-    int32_t waves_per_cu;    /* persistent grid = CUs * waves_per_cu / (block / 64) workgroups */
-    int32_t xcd_queues;      /* 1: one work queue per XCD with stealing, 0: one global queue */
+    int32_t pairs_per_lane;  /* 1, 2 or 4: a tile is 1024 * pairs_per_lane pairs of one keyframe */
+    int32_t lds_mode;        /* 2: keyframe grid, records and descriptors in LDS; 1: grid and
+                                records in LDS, descriptors from HBM; 0: grids prebuilt in HBM.
+                                A mode whose LDS footprint does not fit falls back to the next. */
+    int32_t wg_per_cu;       /* 1 or 2 workgroups of 1024 threads per compute unit */
+    int32_t xcd_aware;       /* 1: the tiles of a keyframe stay on one XCD (shared L2) */
 } fl_tuning;
 
 int fl_get_tuning(fl_ctx* ctx, fl_tuning* out /* host */);

@@ -61,8 +61,8 @@ class Refine(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("pairs_per_lane", c_int32), ("block", c_int32), ("waves_per_cu", c_int32),
-                ("xcd_queues", c_int32)]
+    _fields_ = [("pairs_per_lane", c_int32), ("lds_mode", c_int32), ("wg_per_cu", c_int32),
+                ("xcd_aware", c_int32)]
 
 
 # (name, restype, argtypes) of every exported function

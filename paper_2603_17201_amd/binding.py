@@ -335,8 +335,8 @@ class Context:
         _check(self._lib.fl_get_tuning(self._h, ctypes.byref(t)), "fl_get_tuning")
         return t
 
-    def set_tuning(self, pairs_per_lane=2, block=256, waves_per_cu=16, xcd_queues=1):
-        t = Tuning(pairs_per_lane, block, waves_per_cu, xcd_queues)
+    def set_tuning(self, pairs_per_lane=1, lds_mode=2, wg_per_cu=1, xcd_aware=1):
+        t = Tuning(pairs_per_lane, lds_mode, wg_per_cu, xcd_aware)
         _check(self._lib.fl_set_tuning(self._h, ctypes.byref(t)), "fl_set_tuning")
 
     def autotune(self, batch: DeviceBatch, params, out: FuseOutputs, reps: int = 3, stream=None):
@@ -347,7 +347,7 @@ class Context:
         ms = ctypes.c_float()
         _check(self._lib.fl_autotune(self._h, ctypes.byref(b), ctypes.byref(P), ctypes.byref(o), int(reps),
                                      ctypes.byref(t), ctypes.byref(ms), self._stream(stream)), "fl_autotune")
-        return (t.pairs_per_lane, t.block, t.waves_per_cu, t.xcd_queues), ms.value
+        return (t.pairs_per_lane, t.lds_mode, t.wg_per_cu, t.xcd_aware), ms.value
 
     def set_stats(self, on: bool):
         _check(self._lib.fl_set_stats(self._h, int(bool(on))), "fl_set_stats")

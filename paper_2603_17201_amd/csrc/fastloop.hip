@@ -48,7 +48,9 @@ int next_pow2(int x) {
 struct DevBuf {
     void* p = nullptr;
     size_t size = 0;
-    int ensure(size_t need) {
+    // Grow to at least `need` bytes; a new allocation is filled with `fill`
+    // (-1: left uninitialised).
+    int ensure(size_t need, int fill = -1) {
         if (need <= size) return FL_OK;
         if (p) {
             hipDeviceSynchronize();   // work queued on any stream may still use the old buffer
@@ -63,6 +65,7 @@ struct DevBuf {
             return fail(FL_ENOMEM, "hipMalloc of %zu bytes failed", n);
         }
         size = n;
+        if (fill >= 0 && hipMemset(p, fill, n) != hipSuccess) return fail(FL_EHIP, "hipMemset failed");
         return FL_OK;
     }
     void release() {
@@ -73,6 +76,8 @@ struct DevBuf {
 };
 
 // Pinned staging buffer with an event marking when its last upload finished.
+constexpr int kPinRing = 16;   // staging buffers in flight
+
 struct Pinned {
     void* p = nullptr;
     size_t size = 0;
@@ -80,35 +85,35 @@ struct Pinned {
     bool pending = false;
 };
 
-// Offsets of the workspace regions of one batch.
-struct Layout {
-    size_t hdr, kf, ev, cell_start, recs, desc_sorted, cell_kp, hash, claim, tile, add_list, match_list,
-        counters, stats, ev_match, refine_done, event_S32, refine_partial, total;
-    size_t blob_bytes;   // hdr + kf + ev (uploaded per call)
-};
 
 }  // namespace
 
 struct fl_ctx {
     int device = 0;
     int n_cu = 256;
-    DevBuf ws;           // batched workspace (header, tables, grids, lists)
-    DevBuf plain;        // plain-path workspace
-    DevBuf res;          // residual partials and done counter
-    Pinned pin[2];
+    size_t lds_max = 65536;     // dynamic LDS per workgroup the device allows
+    DevBuf ws;                  // batched workspace (tables, global grids, lists, partials)
+    DevBuf claims;              // ADD claims, 0xFF.. between epochs
+    DevBuf ctrs;                // stats + per-keyframe + per-event counters, zero at rest
+    DevBuf plain;               // plain-path workspace
+    DevBuf res;                 // residual partials and done counter
+    Pinned pin[kPinRing];
     int pin_next = 0;
     hipStream_t cap_stream = nullptr;
-    fl_tuning tune{2, 256, 16, 1};
+    fl_tuning tune{1, kModeLdsDesc, 1, 1};
+    uint32_t epoch = 0xFFFFFFFEu;
     int stats = 0;
-    int add_cap_override = 0;   // test hook: >0 forces a small ADD / match list capacity
+    int add_cap_override = 0;   // test hook: >0 forces small ADD / match list capacities
     int prof = 0;               // record events around eager search kernels
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     // captured graph and its key
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // replayed alternately
+    int g_next = 0;
     void* g_ws = nullptr;
-    fl_tuning g_tune{};
-    int g_stats = -1;
-    int g_refine = -1;
+    void* g_claims = nullptr;
+    void* g_ctrs = nullptr;
+    int g_mode = -1, g_ppl = -1, g_grid = -1, g_refine = -1;
+    size_t g_lds = 0;
 };
 
 namespace {
@@ -169,9 +174,14 @@ void fill_kf_geometry(KfDesc& k, const fl_sim3& S, const fl_pinhole& K, const fl
 
 int get_pinned(fl_ctx* c, size_t need, Pinned** out) {
     Pinned& p = c->pin[c->pin_next];
-    c->pin_next ^= 1;
+    c->pin_next = (c->pin_next + 1) % kPinRing;
     if (p.pending) {
-        FL_HIP(hipEventSynchronize(p.done));
+        // the upload from this buffer kPinRing calls ago must have run; poll
+        // rather than block so a short wait does not cost a scheduler tick
+        hipError_t q;
+        while ((q = hipEventQuery(p.done)) == hipErrorNotReady) {
+        }
+        if (q != hipSuccess) return fail(FL_EHIP, "hipEventQuery: %s", hipGetErrorString(q));
         p.pending = false;
     }
     if (p.size < need) {
@@ -189,17 +199,6 @@ int get_pinned(fl_ctx* c, size_t need, Pinned** out) {
     return FL_OK;
 }
 
-// ---------------------------------------------------------------------------
-// batch preparation
-
-struct Prepared {
-    Layout L;
-    std::vector<KfDesc> kf;
-    std::vector<EventDesc> ev;
-    BatchHdr hdr;
-    int n_tiles = 0;
-    int refine_blocks = 1;
-};
 
 int validate_batch(const fl_batch* B, const fl_params* P, const fl_fuse_out* out) {
     if (!B) return fail(FL_EINVAL, "batch is NULL");
@@ -250,34 +249,82 @@ int validate_batch(const fl_batch* B, const fl_params* P, const fl_fuse_out* out
     return FL_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// batch preparation
+
+constexpr int kPrepGrid = 512;     // workgroups of the global-grid build
+constexpr int kRefineGrid = 256;   // workgroups of a refinement step
+
+struct Prepared {
+    std::vector<char> blob;     // header + tables, uploaded per call
+    BatchHdr* hdr = nullptr;
+    int mode = kModeGlobal;
+    int ppl = 1;
+    int grid = 1;
+    size_t lds = 16;
+    int refine_iters = 0;
+};
+
+template <typename T>
+size_t blob_take(std::vector<char>& blob, size_t n) {
+    size_t off = align_up(blob.size(), 256);
+    blob.resize(off + sizeof(T) * std::max<size_t>(n, 1), 0);
+    return off;
+}
+
+// Choose the staging mode: the tuned one if its LDS footprint fits.
+int pick_mode(const fl_ctx* c, int want, int kp_cap, int cells, int hash_cap) {
+    for (int m = want; m > kModeGlobal; --m)
+        if (search_lds_bytes(m, kp_cap, cells, hash_cap) <= c->lds_max) return m;
+    return kModeGlobal;
+}
+
 int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_out* out, const fl_refine* R,
-                  int ppl, Prepared& pr) {
+                  bool refine_scan, Prepared& pr) {
     const int cells = P->grid_cols * P->grid_rows;
     const int n_kf = B->n_kf, n_ev = B->n_events;
-    const int tile_pairs = kWave * ppl;
+    const int ppl = c->tune.pairs_per_lane;
+    const int64_t tile_pairs = (int64_t)kSearchBlock * ppl;
     const bool refine = R && R->n_iters > 0;
-    pr.kf.assign(n_kf, KfDesc{});
-    pr.ev.assign(n_ev, EventDesc{});
-    // per-keyframe geometry, ranges and tables
-    int64_t hash_total = 0;
-    int64_t list_total = 0;
-    std::vector<double> cost(n_kf);
+    pr.ppl = ppl;
+    pr.refine_iters = refine ? R->n_iters : 0;
+    int kp_cap = 1;
+    for (int k = 0; k < n_kf; ++k) kp_cap = std::max(kp_cap, B->kp_offset[k + 1] - B->kp_offset[k]);
+    const int lds_hash_cap = std::max(64, next_pow2(kp_cap + 1));
+    pr.mode = pick_mode(c, c->tune.lds_mode, kp_cap, cells, lds_hash_cap);
+    pr.lds = search_lds_bytes(pr.mode, kp_cap, cells, lds_hash_cap);
+
+    std::vector<char>& blob = pr.blob;
+    blob.clear();
+    const size_t o_hdr = blob_take<BatchHdr>(blob, 1);
+    const size_t o_kf = blob_take<KfDesc>(blob, n_kf);
+    const size_t o_ev = blob_take<EventDesc>(blob, n_ev);
+    const size_t o_order = blob_take<int32_t>(blob, n_kf);
+    const size_t o_prefix = blob_take<int32_t>(blob, n_kf + 1);
+    KfDesc* kfd = (KfDesc*)(blob.data() + o_kf);
+    EventDesc* evd = (EventDesc*)(blob.data() + o_ev);
+
+    // keyframes, events, list regions, tiles
+    int64_t hash_total = 0, add_total = 0, list_total = 0;
+    std::vector<double> tile_cost;    // cost of each keyframe's tiles (per tile)
+    tile_cost.resize(n_kf);
     for (int e = 0; e < n_ev; ++e) {
-        EventDesc& ed = pr.ev[e];
+        EventDesc& ed = evd[e];
         ed.kf_begin = B->event_kf_offset[e];
         ed.kf_end = B->event_kf_offset[e + 1];
         ed.mp_off = B->event_mp_offset[e];
         ed.n_mp = B->event_mp_offset[e + 1] - ed.mp_off;
         ed.pair_begin = B->pair_offset[ed.kf_begin];
         ed.pair_end = B->pair_offset[ed.kf_end];
-        int64_t kp_ev = B->kp_offset[ed.kf_end] - B->kp_offset[ed.kf_begin];
+        const int64_t kp_ev = B->kp_offset[ed.kf_end] - B->kp_offset[ed.kf_begin];
         int64_t cap = std::min<int64_t>(ed.pair_end - ed.pair_begin, std::max<int64_t>(2 * kp_ev, 4096));
         if (c->add_cap_override > 0) cap = std::min<int64_t>(cap, c->add_cap_override);
         ed.list_off = refine ? (int32_t)list_total : 0;
         ed.list_cap = refine ? (int32_t)cap : 0;
         if (refine) list_total += cap;
         for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
-            KfDesc& kd = pr.kf[k];
+            KfDesc& kd = kfd[k];
             fill_kf_geometry(kd, B->kf_sim3[k], B->kf_K[k], P);
             if (B->kf_T)
                 for (int i = 0; i < 12; ++i) kd.T[i] = B->kf_T[12 * (int64_t)k + i];
@@ -294,87 +341,107 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             kd.pair_off = B->pair_offset[k];
             kd.n_pairs = B->pair_offset[k + 1] - B->pair_offset[k];
             kd.n_tiles = (int32_t)((kd.n_pairs + tile_pairs - 1) / tile_pairs);
-            // cost per pair grows with keypoint density (candidates scanned)
-            cost[k] = (double)kd.n_pairs * (1.0 + 4.0 * kd.n_kp / std::max(1, cells));
+            int64_t acap = std::min<int64_t>(kd.n_pairs, (int64_t)kd.n_kp + 256);
+            if (c->add_cap_override > 0) acap = std::min<int64_t>(acap, c->add_cap_override);
+            kd.add_off = (int32_t)add_total;
+            kd.add_cap = (int32_t)acap;
+            add_total += acap;
+            // a pair costs more where keypoints are dense (more candidates scanned)
+            tile_cost[k] = (double)tile_pairs * (1.0 + 2.0 * kd.n_kp / std::max(1, cells));
         }
     }
-    // tile order: keyframes by decreasing cost, tiles of a keyframe consecutive
-    std::vector<int> order(n_kf);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    int64_t tiles = 0;
-    std::vector<double> tile_cost_prefix(1, 0.0);
-    for (int k : order) {
-        pr.kf[k].tile_off = (int32_t)tiles;
-        tiles += pr.kf[k].n_tiles;
+    if (add_total > INT32_MAX || list_total > INT32_MAX || hash_total > INT32_MAX)
+        return fail(FL_ERANGE, "batch too large for the workspace indexing");
+    // tile order: keyframes in batch order
+    int32_t* order = (int32_t*)(blob.data() + o_order);
+    int32_t* prefix = (int32_t*)(blob.data() + o_prefix);
+    int64_t n_tiles = 0;
+    for (int k = 0; k < n_kf; ++k) {
+        order[k] = k;
+        prefix[k] = (int32_t)n_tiles;
+        n_tiles += kfd[k].n_tiles;
+        if (n_tiles > INT32_MAX / 2) return fail(FL_ERANGE, "too many tiles");
     }
-    if (tiles > INT32_MAX / 2) return fail(FL_ERANGE, "too many tiles");
-    pr.n_tiles = (int)tiles;
-    // split the tile sequence into per-XCD queues of about equal estimated cost
-    BatchHdr& h = pr.hdr;
-    memset(&h, 0, sizeof(h));
-    const int nq = c->tune.xcd_queues ? kMaxQueues : 1;
-    h.n_queues = nq;
+    prefix[n_kf] = (int32_t)n_tiles;
+    // workgroups and their contiguous, cost-balanced tile ranges
+    int grid = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles));
+    pr.grid = grid;
+    const size_t o_range = blob_take<int2>(blob, grid);
+    kfd = (KfDesc*)(blob.data() + o_kf);
+    evd = (EventDesc*)(blob.data() + o_ev);
+    order = (int32_t*)(blob.data() + o_order);
+    prefix = (int32_t*)(blob.data() + o_prefix);
+    int2* wr = (int2*)(blob.data() + o_range);
     {
-        double total = 0.0;
-        for (int k = 0; k < n_kf; ++k) total += cost[k];
-        int q = 1;
-        double acc = 0.0;
-        h.queue_begin[0] = 0;
-        for (int k : order) {
-            const KfDesc& kd = pr.kf[k];
-            const double per_tile = kd.n_tiles ? cost[k] / kd.n_tiles : 0.0;
-            for (int j = 0; j < kd.n_tiles && q < nq; ++j) {
-                acc += per_tile;
-                while (q < nq && acc >= total * q / nq) h.queue_begin[q++] = kd.tile_off + j + 1;
-            }
+        // cumulative cost at each tile boundary, by keyframe
+        std::vector<double> kcum(n_kf + 1, 0.0);
+        for (int k = 0; k < n_kf; ++k) kcum[k + 1] = kcum[k] + tile_cost[k] * kfd[k].n_tiles;
+        auto tile_at_cost = [&](double target) -> int64_t {   // first tile whose end cost >= target
+            if (target <= 0.0) return 0;
+            int k = (int)(std::upper_bound(kcum.begin(), kcum.end(), target) - kcum.begin()) - 1;
+            k = std::min(std::max(k, 0), n_kf - 1);
+            const double per = tile_cost[k] > 0 ? tile_cost[k] : 1.0;
+            int64_t j = (int64_t)std::ceil((target - kcum[k]) / per);
+            j = std::min<int64_t>(std::max<int64_t>(j, 0), kfd[k].n_tiles);
+            return prefix[k] + j;
+        };
+        const double total = kcum[n_kf];
+        std::vector<int64_t> bound(grid + 1);
+        bound[0] = 0;
+        bound[grid] = n_tiles;
+        for (int i = 1; i < grid; ++i) bound[i] = tile_at_cost(total * i / grid);
+        for (int i = 1; i <= grid; ++i) bound[i] = std::max(bound[i], bound[i - 1]);
+        for (int i = grid - 1; i >= 0; --i) bound[i] = std::min(bound[i], bound[i + 1]);
+        // chunk i of the sequence goes to workgroup w(i); with xcd_aware the
+        // chunks of one XCD's share are consecutive in the sequence
+        std::vector<int> wg_of(grid);
+        if (c->tune.xcd_aware && grid >= 2 * kMaxQueues) {
+            int i = 0;
+            for (int x = 0; x < kMaxQueues; ++x)
+                for (int b = x; b < grid; b += kMaxQueues) wg_of[i++] = b;
+        } else {
+            for (int i = 0; i < grid; ++i) wg_of[i] = i;
         }
-        while (q <= nq) h.queue_begin[q++] = pr.n_tiles;
-        h.queue_begin[nq] = pr.n_tiles;
-        for (int i = 1; i <= nq; ++i) h.queue_begin[i] = std::max(h.queue_begin[i], h.queue_begin[i - 1]);
+        for (int i = 0; i < grid; ++i) wr[wg_of[i]] = make_int2((int)bound[i], (int)bound[i + 1]);
     }
+
     // workspace layout
-    Layout& L = pr.L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
-        off = align_up(off + bytes, 256);
+        off = align_up(off + std::max<size_t>(bytes, 16), 256);
         return o;
     };
-    L.hdr = take(sizeof(BatchHdr));
-    L.kf = take(sizeof(KfDesc) * (size_t)n_kf);
-    L.ev = take(sizeof(EventDesc) * (size_t)n_ev);
-    L.blob_bytes = off;
-    L.cell_start = take(sizeof(int32_t) * (size_t)n_kf * (cells + 1));
-    L.recs = take(sizeof(KpRec) * (size_t)B->n_kp_total);
-    L.desc_sorted = take(32 * (size_t)B->n_kp_total);
-    L.cell_kp = take(sizeof(int32_t) * (size_t)B->n_kp_total);
-    L.hash = take(sizeof(int32_t) * (size_t)hash_total);
-    L.claim = take(sizeof(int32_t) * (size_t)B->n_kp_total);
-    L.tile = take(sizeof(int2) * (size_t)pr.n_tiles);
-    int64_t add_cap = std::min<int64_t>(B->n_pairs, std::max<int64_t>(2 * (int64_t)B->n_kp_total, 4096));
-    if (c->add_cap_override > 0) add_cap = std::min<int64_t>(add_cap, c->add_cap_override);
-    L.add_list = take(sizeof(PairRef) * (size_t)add_cap);
-    L.match_list = take(sizeof(PairRef) * (size_t)list_total);
-    L.counters = take(sizeof(uint32_t) * kCounterWords);
-    L.stats = take(sizeof(unsigned long long) * 4);
-    L.ev_match = take(sizeof(uint32_t) * (size_t)n_ev);
-    L.refine_done = take(sizeof(uint32_t) * (size_t)n_ev);
-    L.event_S32 = take(sizeof(fl_sim3) * (size_t)n_ev);
-    pr.refine_blocks = std::max(1, std::min(64, 1024 / std::max(1, n_ev)));
-    L.refine_partial = take(sizeof(double) * kNAcc * (size_t)n_ev * pr.refine_blocks);
-    L.total = off;
-    int rc = c->ws.ensure(L.total);
+    const size_t L_blob = take(blob.size());
+    const bool global_grid = pr.mode == kModeGlobal;
+    const size_t L_cs = take(global_grid ? sizeof(int32_t) * (size_t)n_kf * (cells + 1) : 0);
+    const size_t L_recs = take(global_grid ? sizeof(KpRec) * (size_t)B->n_kp_total : 0);
+    const size_t L_desc = take(global_grid ? 32 * (size_t)B->n_kp_total : 0);
+    const size_t L_ck = take(global_grid ? sizeof(int32_t) * (size_t)B->n_kp_total : 0);
+    const size_t L_hash = take(global_grid ? sizeof(int32_t) * (size_t)hash_total : 0);
+    const size_t L_add = take(sizeof(AddRef) * (size_t)add_total);
+    const size_t L_match = take(sizeof(MatchRec) * (size_t)list_total);
+    const int refine_blocks = std::max(1, std::min(64, kRefineGrid / std::max(1, n_ev)));
+    const size_t L_part = take(2 * sizeof(double) * kNAcc * (size_t)n_ev * refine_blocks);
+    int rc = c->ws.ensure(off);
+    if (rc) return rc;
+    rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(B->n_kp_total, 1), 0xFF);
+    if (rc) return rc;
+    rc = c->ctrs.ensure(32 + sizeof(uint32_t) * ((size_t)kKfCtrs * n_kf + (size_t)kEvCtrs * n_ev), 0x00);
     if (rc) return rc;
     char* base = (char*)c->ws.p;
-    // header
+    char* cb = (char*)c->ctrs.p;
+
+    BatchHdr& h = *(BatchHdr*)(blob.data() + o_hdr);
+    pr.hdr = &h;
     h.n_events = n_ev;
     h.n_kf = n_kf;
     h.n_mp = B->n_mp;
     h.n_kp_total = B->n_kp_total;
     h.n_pairs = B->n_pairs;
-    h.n_tiles = pr.n_tiles;
-    h.tile_pairs = tile_pairs;
+    h.n_tiles = (int32_t)n_tiles;
+    h.tile_pairs = (int32_t)tile_pairs;
     h.cells = cells;
     h.grid_cols = P->grid_cols;
     h.grid_rows = P->grid_rows;
@@ -384,13 +451,18 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.r0 = P->win_px;
     h.gate = B->mp_dmax != nullptr;
     h.dense = B->pair_mp == nullptr;
-    h.add_cap = (int32_t)add_cap;
     h.stats = c->stats;
+    h.epoch = c->epoch;
+    h.lds_hash_mask = lds_hash_cap - 1;
+    h.lds_kp_cap = kp_cap;   // the record capacity search_lds_bytes sized
+    h.n_wg = grid;
     SearchConst sc;
     fill_search_const(P, sc, h.sf);
-    h.kf = (const KfDesc*)(base + L.kf);
-    h.ev = (const EventDesc*)(base + L.ev);
-    h.tile = (int2*)(base + L.tile);
+    h.kf = (const KfDesc*)(base + L_blob + o_kf);
+    h.ev = (const EventDesc*)(base + L_blob + o_ev);
+    h.kf_order = (const int32_t*)(base + L_blob + o_order);
+    h.tile_prefix = (const int32_t*)(base + L_blob + o_prefix);
+    h.wg_range = (const int2*)(base + L_blob + o_range);
     h.kp_xy = B->kp_xy;
     h.kp_oct = B->kp_octave;
     h.kp_desc = B->kp_desc;
@@ -405,21 +477,20 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.second_dist = out->second_dist;
     h.decision = out->decision;
     h.target = out->target;
-    h.cell_start = (int32_t*)(base + L.cell_start);
-    h.recs = (KpRec*)(base + L.recs);
-    h.desc_sorted = (uint4*)(base + L.desc_sorted);
-    h.cell_kp = (int32_t*)(base + L.cell_kp);
-    h.hash = (int32_t*)(base + L.hash);
-    h.claim = (int32_t*)(base + L.claim);
-    h.add_list = (PairRef*)(base + L.add_list);
-    h.match_list = (PairRef*)(base + L.match_list);
-    h.counters = (uint32_t*)(base + L.counters);
-    h.stats_out = (unsigned long long*)(base + L.stats);
-    h.ev_match_count = (uint32_t*)(base + L.ev_match);
-    h.refine_done = (uint32_t*)(base + L.refine_done);
-    h.event_S32 = (fl_sim3*)(base + L.event_S32);
-    h.refine_partial = (double*)(base + L.refine_partial);
-    h.refine_blocks = pr.refine_blocks;
+    h.cell_start = (int32_t*)(base + L_cs);
+    h.recs = (KpRec*)(base + L_recs);
+    h.desc_sorted = (uint4*)(base + L_desc);
+    h.cell_kp = (int32_t*)(base + L_ck);
+    h.hash = (int32_t*)(base + L_hash);
+    h.claim = (unsigned long long*)c->claims.p;
+    h.stats_out = (unsigned long long*)cb;
+    h.kf_ctr = (uint32_t*)(cb + 32);
+    h.ev_ctr = (uint32_t*)(cb + 32 + sizeof(uint32_t) * (size_t)kKfCtrs * n_kf);
+    h.add_list = (AddRef*)(base + L_add);
+    h.match_list = (MatchRec*)(base + L_match);
+    h.refine_blocks = refine_blocks;
+    h.refine_scan = refine_scan ? 1 : 0;
+    h.refine_partial = (double*)(base + L_part);
     if (refine) {
         h.refine_iters = R->n_iters;
         h.huber_delta = R->huber_delta;
@@ -430,64 +501,70 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     return FL_OK;
 }
 
+// Copy the header and tables to the workspace through pinned memory, on the
+// stream that will run the kernels.  Advances the claim epoch.
 int upload_batch(fl_ctx* c, Prepared& pr, hipStream_t stream) {
+    if (c->epoch <= 1) {   // epochs exhausted: reset every claim and start again
+        FL_HIP(hipMemsetAsync(c->claims.p, 0xFF, c->claims.size, stream));
+        c->epoch = 0xFFFFFFFEu;
+        pr.hdr->epoch = c->epoch;
+    }
+    --c->epoch;
     Pinned* pin = nullptr;
-    int rc = get_pinned(c, pr.L.blob_bytes, &pin);
+    int rc = get_pinned(c, pr.blob.size(), &pin);
     if (rc) return rc;
-    char* hb = (char*)pin->p;
-    memcpy(hb + pr.L.hdr, &pr.hdr, sizeof(BatchHdr));
-    if (!pr.kf.empty()) memcpy(hb + pr.L.kf, pr.kf.data(), sizeof(KfDesc) * pr.kf.size());
-    if (!pr.ev.empty()) memcpy(hb + pr.L.ev, pr.ev.data(), sizeof(EventDesc) * pr.ev.size());
-    FL_HIP(hipMemcpyAsync(c->ws.p, hb, pr.L.blob_bytes, hipMemcpyHostToDevice, stream));
+    memcpy(pin->p, pr.blob.data(), pr.blob.size());
+    FL_HIP(hipMemcpyAsync(c->ws.p, pin->p, pr.blob.size(), hipMemcpyHostToDevice, stream));
     FL_HIP(hipEventRecord(pin->done, stream));
     pin->pending = true;
     return FL_OK;
 }
 
-int search_grid_size(const fl_ctx* c) {
-    const int waves_per_block = std::max(1, c->tune.block / kWave);
-    return std::max(1, c->n_cu * c->tune.waves_per_cu / waves_per_block);
+template <int PPL, int MODE, bool STATS>
+void launch_fused(const BatchHdr* dh, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((search_fused_kernel<PPL, MODE, STATS>), dim3(grid), dim3(kSearchBlock), lds, s, dh);
 }
 
-constexpr int kPrepGrid = 512;
-constexpr int kResolveGrid = 256;
-constexpr int kRefineGrid = 1024;
+template <int PPL, int MODE>
+void launch_fused_s(bool stats, const BatchHdr* dh, int grid, size_t lds, hipStream_t s) {
+    if (stats) launch_fused<PPL, MODE, true>(dh, grid, lds, s);
+    else launch_fused<PPL, MODE, false>(dh, grid, lds, s);
+}
 
-int launch_search(fl_ctx* c, const BatchHdr* dh, hipStream_t s, bool eager_sizes, int n_kf) {
-    const int pg = eager_sizes ? std::max(1, std::min(n_kf, kPrepGrid)) : kPrepGrid;
-    hipLaunchKernelGGL(prep_batched_kernel, dim3(pg), dim3(kPrepBlock), 0, s, dh);
-    const int g = search_grid_size(c);
-    const int b = c->tune.block;
-    const int ppl = c->tune.pairs_per_lane;
-    const bool timed = eager_sizes && c->prof;
+template <int PPL>
+void launch_fused_m(int mode, bool stats, const BatchHdr* dh, int grid, size_t lds, hipStream_t s) {
+    if (mode == kModeLdsDesc) launch_fused_s<PPL, kModeLdsDesc>(stats, dh, grid, lds, s);
+    else if (mode == kModeLdsRec) launch_fused_s<PPL, kModeLdsRec>(stats, dh, grid, lds, s);
+    else launch_fused_s<PPL, kModeGlobal>(stats, dh, grid, lds, s);
+}
+
+
+int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t s, bool eager, bool stats) {
+    if (pr.mode == kModeGlobal) {
+        const int pg = eager ? std::max(1, std::min(pr.hdr->n_kf, kPrepGrid)) : kPrepGrid;
+        hipLaunchKernelGGL(prep_global_kernel, dim3(pg), dim3(kPrepBlock), 0, s, dh);
+    }
+    const bool timed = eager && c->prof;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (timed) {
         FL_HIP(hipEventCreate(&t0));
         FL_HIP(hipEventCreate(&t1));
         FL_HIP(hipEventRecord(t0, s));
     }
-    if (c->stats) {
-        if (ppl == 1) hipLaunchKernelGGL((search_batched_kernel<1, true>), dim3(g), dim3(b), 0, s, dh);
-        else if (ppl == 2) hipLaunchKernelGGL((search_batched_kernel<2, true>), dim3(g), dim3(b), 0, s, dh);
-        else hipLaunchKernelGGL((search_batched_kernel<4, true>), dim3(g), dim3(b), 0, s, dh);
-    } else {
-        if (ppl == 1) hipLaunchKernelGGL((search_batched_kernel<1, false>), dim3(g), dim3(b), 0, s, dh);
-        else if (ppl == 2) hipLaunchKernelGGL((search_batched_kernel<2, false>), dim3(g), dim3(b), 0, s, dh);
-        else hipLaunchKernelGGL((search_batched_kernel<4, false>), dim3(g), dim3(b), 0, s, dh);
-    }
+    if (pr.ppl == 1) launch_fused_m<1>(pr.mode, stats, dh, pr.grid, pr.lds, s);
+    else if (pr.ppl == 2) launch_fused_m<2>(pr.mode, stats, dh, pr.grid, pr.lds, s);
+    else launch_fused_m<4>(pr.mode, stats, dh, pr.grid, pr.lds, s);
     if (timed) {
         FL_HIP(hipEventRecord(t1, s));
         c->prof_ev.emplace_back(t0, t1);
     }
-    hipLaunchKernelGGL(resolve_batched_kernel, dim3(kResolveGrid), dim3(256), 0, s, dh);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
 
 int launch_refine(const BatchHdr* dh, int n_iters, hipStream_t s) {
-    hipLaunchKernelGGL(refine_init_kernel, dim3(1), dim3(256), 0, s, dh);
-    for (int it = 0; it < n_iters; ++it)
-        hipLaunchKernelGGL(refine_iter_kernel, dim3(kRefineGrid), dim3(kResBlock), 0, s, dh);
+    if (n_iters <= 0) return FL_OK;
+    hipLaunchKernelGGL(refine_kernel, dim3(kRefineGrid), dim3(kResBlock), 0, s, dh);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
@@ -498,6 +575,21 @@ int check_refine(const fl_batch* B, const fl_refine* R) {
     if (!finite_pos(R->huber_delta)) return fail(FL_EINVAL, "refine.huber_delta must be finite and > 0");
     if (B->n_events > 0 && !R->event_S) return fail(FL_EINVAL, "refine.event_S must not be NULL");
     return FL_OK;
+}
+
+// Every instantiation of the fused kernel may use up to lds_max bytes of LDS.
+template <int PPL, int MODE, bool STATS>
+void allow_lds(size_t bytes) {
+    (void)hipFuncSetAttribute((const void*)search_fused_kernel<PPL, MODE, STATS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int PPL>
+void allow_lds_all(size_t bytes) {
+    allow_lds<PPL, kModeLdsDesc, false>(bytes);
+    allow_lds<PPL, kModeLdsDesc, true>(bytes);
+    allow_lds<PPL, kModeLdsRec, false>(bytes);
+    allow_lds<PPL, kModeLdsRec, true>(bytes);
 }
 
 }  // namespace
@@ -511,7 +603,7 @@ extern "C" {
 
 const char* fl_last_error(void) { return g_err; }
 
-int fl_version(void) { return 10000; }
+int fl_version(void) { return 10100; }
 
 int fl_create(fl_ctx** out, int device) {
     if (!out) return fail(FL_EINVAL, "out is NULL");
@@ -527,6 +619,10 @@ int fl_create(fl_ctx** out, int device) {
     fl_ctx* c = new fl_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->lds_max = std::max<size_t>(prop.sharedMemPerBlock, 65536) - 1024;   // room for static LDS
+    allow_lds_all<1>(c->lds_max);
+    allow_lds_all<2>(c->lds_max);
+    allow_lds_all<4>(c->lds_max);
     for (auto& p : c->pin) {
         if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) {
             fl_destroy(c);
@@ -538,8 +634,7 @@ int fl_create(fl_ctx** out, int device) {
         return fail(FL_EHIP, "hipStreamCreate failed");
     }
     // residual partials: 1024 blocks x kNAcc doubles + a done counter
-    if (c->res.ensure(sizeof(double) * 1024 * kNAcc + 256) != FL_OK ||
-        hipMemset(c->res.p, 0, c->res.size) != hipSuccess) {
+    if (c->res.ensure(sizeof(double) * 1024 * kNAcc + 256, 0x00) != FL_OK) {
         fl_destroy(c);
         return fail(FL_ENOMEM, "residual workspace allocation failed");
     }
@@ -551,7 +646,8 @@ void fl_destroy(fl_ctx* c) {
     if (!c) return;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    for (auto& g : c->gexec)
+        if (g) hipGraphExecDestroy(g);
     clear_profile(c);
     for (auto& p : c->pin) {
         if (p.p) hipHostFree(p.p);
@@ -559,6 +655,8 @@ void fl_destroy(fl_ctx* c) {
     }
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     c->ws.release();
+    c->claims.release();
+    c->ctrs.release();
     c->plain.release();
     c->res.release();
     delete c;
@@ -583,6 +681,7 @@ int fl_build_grid(fl_ctx* c, int32_t n_kp, const float* kp_xy, const fl_pinhole*
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
+
 
 int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc, const float* mp_dmax,
                    const int32_t* mp_id, const fl_keyframe* kf, const fl_sim3* S, const fl_pinhole* K,
@@ -620,8 +719,8 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
     const size_t o_ck = take(sizeof(int32_t) * (size_t)std::max(n_kp, 1));
     const size_t o_hash = take(sizeof(int32_t) * (size_t)hsize);
     const size_t o_claim = take(sizeof(int32_t) * (size_t)std::max(n_kp, 1));
-    const size_t o_ctr = take(sizeof(uint32_t) * kCounterWords);
-    const size_t o_list = take(sizeof(PairRef) * (size_t)cap);
+    const size_t o_ctr = take(sizeof(uint32_t) * 4);
+    const size_t o_list = take(sizeof(AddRef) * (size_t)cap);
     rc = c->plain.ensure(off);
     if (rc) return rc;
     char* base = (char*)c->plain.p;
@@ -644,8 +743,8 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
     a.kp_owner = kf->kp_owner;
     a.hash = (const int32_t*)(base + o_hash);
     a.claim = (int32_t*)(base + o_claim);
-    a.counters = (uint32_t*)(base + o_ctr);
-    a.add_list = (PairRef*)(base + o_list);
+    a.counter = (uint32_t*)(base + o_ctr);
+    a.add_list = (AddRef*)(base + o_list);
     a.best_idx = out->best_idx;
     a.best_dist = out->best_dist;
     a.second_dist = out->second_dist;
@@ -663,15 +762,16 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
         a.cell_kp = ck;
     }
     hipLaunchKernelGGL(plain_prep_kernel, dim3(1), dim3(kPrepBlock), 0, stream, n_kp, kf->kp_owner,
-                       (int32_t*)(base + o_hash), hsize - 1, a.claim, a.counters);
+                       (int32_t*)(base + o_hash), hsize - 1, a.claim, a.counter);
     const int grid = (n_mp + 255) / 256;
     hipLaunchKernelGGL(search_plain_kernel, dim3(grid), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(resolve_plain_kernel, dim3(std::min(grid, 256)), dim3(256), 0, stream, n_mp,
-                       (const uint32_t*)a.counters, (const PairRef*)a.add_list, (int32_t)cap,
+                       (const uint32_t*)a.counter, (const AddRef*)a.add_list, (int32_t)cap,
                        (const int32_t*)a.claim, mp_id, (const int32_t*)out->best_idx, out->decision, out->target);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
+
 
 int fl_validate_batch(const fl_batch* B, const fl_params* P, const fl_fuse_out* out) {
     return validate_batch(B, P, out);
@@ -682,13 +782,14 @@ int fl_search_fuse_batched(fl_ctx* c, const fl_batch* B, const fl_params* P, con
     if (!c) return fail(FL_EINVAL, "ctx is NULL");
     int rc = validate_batch(B, P, out);
     if (rc) return rc;
-    if (B->n_pairs == 0 && B->n_kf == 0) return FL_OK;
+    if (B->n_pairs == 0) return FL_OK;
     Prepared pr;
-    rc = prepare_batch(c, B, P, out, nullptr, c->tune.pairs_per_lane, pr);
+    rc = prepare_batch(c, B, P, out, nullptr, false, pr);
     if (rc) return rc;
     rc = upload_batch(c, pr, stream);
     if (rc) return rc;
-    return launch_search(c, (const BatchHdr*)c->ws.p, stream, true, B->n_kf);
+    if (c->stats) FL_HIP(hipMemsetAsync(c->ctrs.p, 0, 32, stream));
+    return launch_search(c, pr, (const BatchHdr*)c->ws.p, stream, true, c->stats != 0);
 }
 
 int fl_refine_events(fl_ctx* c, const fl_batch* B, const fl_fuse_out* out, const fl_refine* R, hipStream_t stream) {
@@ -700,9 +801,8 @@ int fl_refine_events(fl_ctx* c, const fl_batch* B, const fl_fuse_out* out, const
     if (rc) return rc;
     if (!R || R->n_iters == 0 || B->n_events == 0) return FL_OK;
     Prepared pr;
-    rc = prepare_batch(c, B, &P, out, R, c->tune.pairs_per_lane, pr);
+    rc = prepare_batch(c, B, &P, out, R, true, pr);
     if (rc) return rc;
-    pr.hdr.refine_scan = 1;
     rc = upload_batch(c, pr, stream);
     if (rc) return rc;
     return launch_refine((const BatchHdr*)c->ws.p, R->n_iters, stream);
@@ -715,49 +815,59 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
     if (rc) return rc;
     rc = check_refine(B, R);
     if (rc) return rc;
-    if (B->n_pairs == 0 && B->n_kf == 0) return FL_OK;
-    const int n_iters = (R && R->n_iters > 0) ? R->n_iters : 0;
+    if (B->n_pairs == 0) return FL_OK;
     Prepared pr;
-    rc = prepare_batch(c, B, P, out, R, c->tune.pairs_per_lane, pr);
+    rc = prepare_batch(c, B, P, out, R, false, pr);
     if (rc) return rc;
-    const bool stale = !c->gexec || c->g_ws != c->ws.p || memcmp(&c->g_tune, &c->tune, sizeof(fl_tuning)) != 0 ||
-                       c->g_stats != c->stats || c->g_refine != n_iters;
+    pr.hdr->stats = 0;   // counters are an eager-path feature
+    const int refine_on = pr.refine_iters > 0 ? 1 : 0;
+    const bool stale = !c->gexec[0] || c->g_ws != c->ws.p || c->g_claims != c->claims.p || c->g_ctrs != c->ctrs.p ||
+                       c->g_mode != pr.mode || c->g_ppl != pr.ppl || c->g_grid != pr.grid ||
+                       c->g_refine != refine_on || c->g_lds != pr.lds;
     if (stale) {
-        if (c->gexec) {
-            FL_HIP(hipStreamSynchronize(stream));
-            hipGraphExecDestroy(c->gexec);
-            c->gexec = nullptr;
+        FL_HIP(hipStreamSynchronize(stream));
+        for (auto& g : c->gexec) {
+            if (g) hipGraphExecDestroy(g);
+            g = nullptr;
         }
         const BatchHdr* dh = (const BatchHdr*)c->ws.p;
-        hipGraph_t graph = nullptr;
-        FL_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        int lrc = launch_search(c, dh, c->cap_stream, false, B->n_kf);
-        if (lrc == FL_OK && n_iters > 0) lrc = launch_refine(dh, n_iters, c->cap_stream);
-        hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
-        if (lrc) {
-            if (graph) hipGraphDestroy(graph);
-            return lrc;
-        }
-        if (ce != hipSuccess) return fail(FL_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
-        hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (ie != hipSuccess) {
-            c->gexec = nullptr;
-            return fail(FL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        for (int gi = 0; gi < 2; ++gi) {
+            hipGraph_t graph = nullptr;
+            FL_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            const int saved_prof = c->prof;
+            c->prof = 0;
+            int lrc = launch_search(c, pr, dh, c->cap_stream, false, false);
+            c->prof = saved_prof;
+            if (lrc == FL_OK && refine_on) lrc = launch_refine(dh, pr.refine_iters, c->cap_stream);
+            hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
+            if (lrc) {
+                if (graph) hipGraphDestroy(graph);
+                return lrc;
+            }
+            if (ce != hipSuccess) return fail(FL_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+            hipError_t ie = hipGraphInstantiate(&c->gexec[gi], graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                c->gexec[gi] = nullptr;
+                return fail(FL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+            }
         }
         c->g_ws = c->ws.p;
-        c->g_tune = c->tune;
-        c->g_stats = c->stats;
-        c->g_refine = n_iters;
+        c->g_claims = c->claims.p;
+        c->g_ctrs = c->ctrs.p;
+        c->g_mode = pr.mode;
+        c->g_ppl = pr.ppl;
+        c->g_grid = pr.grid;
+        c->g_refine = refine_on;
+        c->g_lds = pr.lds;
     }
     rc = upload_batch(c, pr, stream);
     if (rc) return rc;
-    FL_HIP(hipGraphLaunch(c->gexec, stream));
+    FL_HIP(hipGraphLaunch(c->gexec[c->g_next], stream));
+    c->g_next ^= 1;
     return FL_OK;
 }
 
-// ---------------------------------------------------------------------------
-// residual
 
 static int residual_args(fl_ctx* c, int32_t n, const float* xyz, const float* uv, const int32_t* kf_idx,
                          int32_t n_kf, const float* kf_T, const fl_sim3* S, const fl_pinhole* K, float delta,
@@ -841,8 +951,10 @@ int fl_gn_step(fl_ctx* c, const double* g, const double* H, double lambda, doubl
     return FL_OK;
 }
 
+
+
 // ---------------------------------------------------------------------------
-// tuning and statistics
+// tuning, statistics, profiling
 
 int fl_get_tuning(fl_ctx* c, fl_tuning* out) {
     if (!c || !out) return fail(FL_EINVAL, "NULL argument");
@@ -854,9 +966,9 @@ int fl_set_tuning(fl_ctx* c, const fl_tuning* t) {
     if (!c || !t) return fail(FL_EINVAL, "NULL argument");
     if (t->pairs_per_lane != 1 && t->pairs_per_lane != 2 && t->pairs_per_lane != 4)
         return fail(FL_EINVAL, "pairs_per_lane must be 1, 2 or 4");
-    if (t->block != 64 && t->block != 128 && t->block != 256) return fail(FL_EINVAL, "block must be 64, 128 or 256");
-    if (t->waves_per_cu < 1 || t->waves_per_cu > 32) return fail(FL_EINVAL, "waves_per_cu must be in [1, 32]");
-    if (t->xcd_queues != 0 && t->xcd_queues != 1) return fail(FL_EINVAL, "xcd_queues must be 0 or 1");
+    if (t->lds_mode < kModeGlobal || t->lds_mode > kModeLdsDesc) return fail(FL_EINVAL, "lds_mode must be 0, 1 or 2");
+    if (t->wg_per_cu != 1 && t->wg_per_cu != 2) return fail(FL_EINVAL, "wg_per_cu must be 1 or 2");
+    if (t->xcd_aware != 0 && t->xcd_aware != 1) return fail(FL_EINVAL, "xcd_aware must be 0 or 1");
     c->tune = *t;
     return FL_OK;
 }
@@ -871,36 +983,40 @@ int fl_autotune(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_
     FL_HIP(hipEventCreate(&e0));
     FL_HIP(hipEventCreate(&e1));
     const fl_tuning saved = c->tune;
+    const int saved_stats = c->stats, saved_prof = c->prof;
+    c->stats = 0;
+    c->prof = 0;
     fl_tuning top = saved;
     float top_ms = 1e30f;
     const int ppls[] = {1, 2, 4};
-    const int blocks[] = {128, 256};
-    const int wpcs[] = {8, 16, 32};
+    const int modes[] = {kModeLdsDesc, kModeLdsRec, kModeGlobal};
     for (int ppl : ppls)
-        for (int blk : blocks)
-            for (int wpc : wpcs)
-                for (int xq = 0; xq <= 1; ++xq) {
-                    c->tune = fl_tuning{ppl, blk, wpc, xq};
+        for (int mode : modes)
+            for (int wpc = 1; wpc <= 2; ++wpc)
+                for (int xa = 0; xa <= 1 && rc == FL_OK; ++xa) {
+                    c->tune = fl_tuning{ppl, mode, wpc, xa};
                     rc = fl_search_fuse_batched(c, B, P, out, stream);   // warm-up
                     if (rc) break;
-                    hipEventRecord(e0, stream);
+                    (void)hipEventRecord(e0, stream);
                     for (int r = 0; r < reps && rc == FL_OK; ++r) rc = fl_search_fuse_batched(c, B, P, out, stream);
-                    hipEventRecord(e1, stream);
+                    (void)hipEventRecord(e1, stream);
                     if (rc) break;
                     if (hipEventSynchronize(e1) != hipSuccess) {
                         rc = fail(FL_EHIP, "hipEventSynchronize failed");
                         break;
                     }
                     float ms = 0.0f;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    (void)hipEventElapsedTime(&ms, e0, e1);
                     ms /= (float)reps;
                     if (ms < top_ms) {
                         top_ms = ms;
                         top = c->tune;
                     }
                 }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->stats = saved_stats;
+    c->prof = saved_prof;
     c->tune = rc == FL_OK ? top : saved;
     if (rc) return rc;
     if (best) *best = top;
@@ -916,23 +1032,24 @@ int fl_set_stats(fl_ctx* c, int enable) {
 
 int fl_get_stats(fl_ctx* c, int64_t* out4) {
     if (!c || !out4) return fail(FL_EINVAL, "NULL argument");
-    if (!c->ws.p) return fail(FL_EINVAL, "no batched search has run on this context");
-    // the stats block follows the fixed-size regions; its device address is in the header
-    BatchHdr h;
-    FL_HIP(hipMemcpy(&h, c->ws.p, sizeof(h), hipMemcpyDeviceToHost));
+    if (!c->ctrs.p) return fail(FL_EINVAL, "no batched search has run on this context");
     unsigned long long v[4];
-    FL_HIP(hipMemcpy(v, h.stats_out, sizeof(v), hipMemcpyDeviceToHost));
+    FL_HIP(hipMemcpy(v, c->ctrs.p, sizeof(v), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; ++i) out4[i] = (int64_t)v[i];
     return FL_OK;
 }
 
+}  // extern "C"
+
 static void clear_profile(fl_ctx* c) {
     for (auto& pr : c->prof_ev) {
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
     }
     c->prof_ev.clear();
 }
+
+extern "C" {
 
 int fl_set_profiling(fl_ctx* c, int enable) {
     if (!c) return fail(FL_EINVAL, "ctx is NULL");
@@ -956,8 +1073,6 @@ int fl_get_profile(fl_ctx* c, double* total_ms, int64_t* launches) {
     return FL_OK;
 }
 
-// Test hook: cap the provisional-ADD and matched-pair lists at `cap` entries
-// (0 restores the default) so the overflow paths can be exercised.
 int fl_debug_set_list_cap(fl_ctx* c, int32_t cap) {
     if (!c || cap < 0) return fail(FL_EINVAL, "bad argument");
     c->add_cap_override = cap;

@@ -14,14 +14,7 @@ namespace fl {
 
 constexpr int kWave = 64;
 constexpr int kMaxQueues = 8;        // one work queue per XCD
-constexpr int kCounterWords = 64;    // uint32 counters at the head of the counter block
-
-// counter block layout (uint32 words, then uint64 stats)
-enum : int {
-    kCtrQueue = 0,          // [0, 8) per-queue tile counters
-    kCtrAdd = 8,            // provisional-ADD list length
-    kCtrRefineDone = 16,    // [16, 16+?) unused; per-event done counters live in their own array
-};
+constexpr int kNAccPad = 36;        // doubles per partial of a float64 reduction
 
 // One keyframe of a batch: search transform, camera, grid and ranges.
 struct alignas(16) KfDesc {
@@ -33,14 +26,16 @@ struct alignas(16) KfDesc {
     float T[12];         // world->camera SE3 for refinement (R row-major, t)
     int32_t kp_off;      // first keypoint (global index)
     int32_t n_kp;
-    int32_t grid_off;    // first cell_start entry
+    int32_t grid_off;    // first cell_start entry (global-grid mode)
     int32_t event;
     int32_t mp_off;      // first point of the event (global index)
     int32_t n_mp;        // points in the event
-    int32_t hash_off;    // owner hash table of this keyframe
+    int32_t hash_off;    // owner hash table of this keyframe (global-grid mode)
     int32_t hash_mask;
-    int32_t tile_off;    // first tile of this keyframe in the tile table
     int32_t n_tiles;
+    int32_t add_off;     // region of the provisional-ADD list
+    int32_t add_cap;
+    int32_t pad0;
     int64_t pair_off;
     int64_t n_pairs;
 };
@@ -52,21 +47,37 @@ struct alignas(16) EventDesc {
     int64_t pair_begin, pair_end;  // pair range (pairs of the event are contiguous)
 };
 
-// Entry of the provisional-ADD and matched-pair lists.
-struct alignas(16) PairRef {
+// Provisional ADD: a pair whose point claimed a free keypoint.
+struct alignas(16) AddRef {
     int32_t pair;     // global pair index
-    int32_t kp;       // global keypoint index of the best candidate
+    int32_t kp;       // global keypoint index
     int32_t gp;       // global point index
-    int32_t kf;       // keyframe index
+    int32_t pad;
 };
 
-// Cell-ordered keypoint record used by the batched search: 16 bytes, one
-// dwordx4 load.  idx is the keypoint index within its keyframe.
+// Accepted pair kept for refinement: point, observation, keyframe.
+struct alignas(16) MatchRec {
+    float x, y, z;
+    float u, v;
+    int32_t kf;
+    int32_t pad0, pad1;
+};
+
+// Cell-ordered keypoint record: 16 bytes, one dwordx4 load.  idx is the
+// keypoint index within its keyframe.
 struct alignas(16) KpRec {
     float x, y;
     int32_t idx;
     int32_t oct;
 };
+
+// Per-keyframe counters (zero between launches: the kernel that uses them
+// last resets them).
+enum : int { kKfDone = 0, kKfAdd = 1, kKfCtrs = 2 };
+// Per-event counters.
+enum : int { kEvMatch = 0, kEvBarrier = 1, kEvLeave = 2, kEvCtrs = 4 };
+
+enum : int { kModeGlobal = 0, kModeLdsRec = 1, kModeLdsDesc = 2 };
 
 struct alignas(16) BatchHdr {
     int32_t n_events, n_kf, n_mp, n_kp_total;
@@ -78,15 +89,22 @@ struct alignas(16) BatchHdr {
     float r0;
     int32_t gate;               // 1: point distance invariance given (octave gate on)
     int32_t dense;
-    int32_t n_queues;
-    int32_t queue_begin[kMaxQueues + 1];
-    int32_t add_cap;            // capacity of the provisional-ADD list
     int32_t stats;              // 1: count visible / cells / keypoints / candidates
+    uint32_t epoch;             // tag of this launch's ADD claims (decreases per launch)
+    int32_t lds_hash_mask;      // owner hash capacity - 1 in the LDS modes
+    int32_t n_wg;               // workgroups of the search launch
+    int32_t refine_iters;
+    float huber_delta;
+    int32_t refine_blocks;      // blocks per event
+    int32_t refine_scan;        // 1: take accepted pairs from the decisions, not the list
+    int32_t lds_kp_cap;         // keypoint capacity of the LDS records in the LDS modes
     float sf[32];               // scale_factor^n rounded to float32
     // tables in the uploaded blob
     const KfDesc* kf;
     const EventDesc* ev;
-    int2* tile;                 // [n_tiles] (keyframe, tile index within keyframe)
+    const int32_t* kf_order;    // keyframes in tile order
+    const int32_t* tile_prefix; // [n_kf+1] first tile of each keyframe in tile order
+    const int2* wg_range;       // [n_wg] tile range of each workgroup
     // inputs (caller-owned)
     const float* kp_xy;
     const int8_t* kp_oct;
@@ -104,28 +122,22 @@ struct alignas(16) BatchHdr {
     uint8_t* decision;
     int32_t* target;
     // workspace (library-owned)
-    int32_t* cell_start;        // [n_kf * (cells + 1)]
-    KpRec* recs;                // [n_kp_total]
-    uint4* desc_sorted;         // [n_kp_total * 2]
-    int32_t* cell_kp;           // [n_kp_total] (original keypoint index per slot)
-    int32_t* hash;              // owner hash tables
-    int32_t* claim;             // [n_kp_total]
-    PairRef* add_list;          // [add_cap]
-    PairRef* match_list;        // [sum of event list caps]
-    uint32_t* counters;         // [kCounterWords]
+    int32_t* cell_start;        // global-grid mode: [n_kf * (cells + 1)]
+    KpRec* recs;                // global-grid mode: [n_kp_total]
+    uint4* desc_sorted;         // global-grid mode: [n_kp_total * 2]
+    int32_t* cell_kp;           // global-grid mode: [n_kp_total]
+    int32_t* hash;              // global-grid mode: owner hash tables
+    unsigned long long* claim;  // [n_kp_total] (epoch << 32 | lowest claiming point)
+    uint32_t* kf_ctr;           // [n_kf * kKfCtrs]
+    uint32_t* ev_ctr;           // [n_events * kEvCtrs]
+    AddRef* add_list;           // per-keyframe regions
+    MatchRec* match_list;       // per-event regions
     unsigned long long* stats_out;  // [4]
-    uint32_t* ev_match_count;   // [n_events]
     // refinement
-    int32_t refine_iters;
-    float huber_delta;
-    int32_t refine_blocks;      // blocks per event
-    int32_t refine_scan;        // 1: take accepted pairs from the decisions, not the list
-    double* event_S;            // [n_events][13]
-    fl_sim3* event_S32;         // [n_events] (workspace copy used by the kernels)
-    fl_sim3* event_S32_out;     // caller's copy (may be null)
+    double* event_S;            // [n_events][13] caller's, in/out
+    fl_sim3* event_S32_out;     // caller's (may be null)
     int32_t* event_n_matched;   // caller's (may be null)
-    double* refine_partial;     // [n_events * refine_blocks * 36]
-    uint32_t* refine_done;      // [n_events]
+    double* refine_partial;     // [2][n_events * refine_blocks * kNAccPad] (ping-pong by step)
 };
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@
 namespace fl {
 
 constexpr int kResBlock = 256;
-constexpr int kNAcc = 36;   // 7 gradient + 28 upper-triangle H + 1 loss
+constexpr int kNAcc = kNAccPad;   // 7 gradient + 28 upper-triangle H + 1 count / loss
 
 // ---------------------------------------------------------------------------
 // float64 Sim3 algebra
@@ -314,20 +314,46 @@ __device__ __forceinline__ bool load_pair(const ResArgs& a, int i, float& x, flo
     return true;
 }
 
-// Sum the per-block partials (in block order) in the last block to finish.
-__device__ __forceinline__ bool last_block(uint32_t* done) {
+// Last-block-done: true in the one block that finishes last (all blocks'
+// partials are then visible to it).
+__device__ __forceinline__ bool last_block(uint32_t* done, unsigned n_blocks) {
     __shared__ int s_last;
-    __threadfence();
+    __syncthreads();   // every wave's partial is written before thread 0 releases
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(done, 1u) == n_blocks - 1;
+        if (s_last) __threadfence();   // acquire: see every block's partial (L2s of other XCDs)
+    }
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (s_last) __threadfence();   // acquire: see every block's partial (L2s of other XCDs)
     return s_last != 0;
+}
+
+// Sum `rows` partials of NV doubles (row stride kNAcc) in row order into
+// s_out[0..NV): rows are staged through LDS in chunks by the whole block so
+// the loads are issued in parallel, then column i is summed by thread i.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* part, int rows, double* s_chunk, double* s_out) {
+    constexpr int kRows = 32;
+    double acc = 0.0;
+    for (int r0 = 0; r0 < rows; r0 += kRows) {
+        const int nr = min(kRows, rows - r0);
+        for (int i = threadIdx.x; i < nr * NV; i += blockDim.x) {
+            const int r = i / NV, c = i % NV;
+            s_chunk[r * NV + c] = part[(int64_t)(r0 + r) * kNAcc + c];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < NV)
+            for (int r = 0; r < nr; ++r) acc += s_chunk[r * NV + threadIdx.x];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < NV) s_out[threadIdx.x] = acc;
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kResBlock) void residual_fwd_kernel(ResArgs a) {
     __shared__ double s_red[(kResBlock / kWave) * 1];
     __shared__ double s_out[1];
+    __shared__ double s_chunk[32 * 1];
     const fl_sim3 S = *a.S;
     double acc[1] = {0.0};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
@@ -349,11 +375,10 @@ __global__ __launch_bounds__(kResBlock) void residual_fwd_kernel(ResArgs a) {
     }
     block_reduce<1>(acc, s_red, s_out);
     if (threadIdx.x == 0) a.partial[blockIdx.x * kNAcc] = s_out[0];
-    if (last_block(a.done)) {
+    if (last_block(a.done, gridDim.x)) {
+        sum_partials<1>(a.partial, gridDim.x, s_chunk, s_out);
         if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += a.partial[b * kNAcc];
-            *a.loss = s;
+            *a.loss = s_out[0];
             *a.done = 0;
         }
     }
@@ -362,6 +387,7 @@ __global__ __launch_bounds__(kResBlock) void residual_fwd_kernel(ResArgs a) {
 __global__ __launch_bounds__(kResBlock) void residual_bwd_kernel(ResArgs a) {
     __shared__ double s_red[(kResBlock / kWave) * 35];
     __shared__ double s_out[35];
+    __shared__ double s_chunk[32 * 35];
     const fl_sim3 S = *a.S;
     double acc[35];
 #pragma unroll
@@ -376,14 +402,10 @@ __global__ __launch_bounds__(kResBlock) void residual_bwd_kernel(ResArgs a) {
     }
     block_reduce<35>(acc, s_red, s_out);
     if ((int)threadIdx.x < 35) a.partial[blockIdx.x * kNAcc + threadIdx.x] = s_out[threadIdx.x];
-    if (last_block(a.done)) {
-        if ((int)threadIdx.x < 35) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += a.partial[b * kNAcc + threadIdx.x];
-            if (threadIdx.x < 7) a.g[threadIdx.x] = a.grad_scale * s;
-            else if (a.H) a.H[threadIdx.x - 7] = s;
-        }
-        __syncthreads();
+    if (last_block(a.done, gridDim.x)) {
+        sum_partials<35>(a.partial, gridDim.x, s_chunk, s_out);
+        if (threadIdx.x < 7) a.g[threadIdx.x] = a.grad_scale * s_out[threadIdx.x];
+        else if ((int)threadIdx.x < 35 && a.H) a.H[threadIdx.x - 7] = s_out[threadIdx.x];
         if (threadIdx.x == 0) *a.done = 0;
     }
 }
@@ -410,24 +432,20 @@ __global__ void gn_step_kernel(const double* __restrict__ g, const double* __res
 }
 
 // ---------------------------------------------------------------------------
-// Per-event refinement inside a batch: refine_blocks workgroups per event
-// accumulate g and H over the event's accepted pairs; the last of them
-// solves the 7x7 system and updates the event's Sim3.
+// Per-event refinement inside a batch, all Gauss-Newton steps in one launch.
+// refine_blocks workgroups per event accumulate g and H over the event's
+// accepted pairs (recorded by the search as point + observation + keyframe),
+// publish their partials and meet at a barrier; every workgroup then sums the
+// partials in the same order and solves the same 7x7 system, so all of them
+// hold the bitwise-identical next Sim3 without a second barrier.  The
+// barrier only waits for workgroups of the same event, which are co-resident
+// (at most one workgroup per CU is launched when an event has more than
+// one); its spin is bounded and a timeout is reported as n_matched = -1.
 
-__global__ void refine_init_kernel(const BatchHdr* __restrict__ hp) {
-    const BatchHdr& h = *hp;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < h.n_events; e += gridDim.x * blockDim.x) {
-        sim3_to_f32(sim3_load(h.event_S + 13 * (int64_t)e), &h.event_S32[e]);
-        h.refine_done[e] = 0;
-    }
-}
+constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ void refine_accumulate(const BatchHdr& h, const PairRef& e, const fl_sim3& S, float delta,
-                                                  double* acc) {
-    const KfDesc& kd = h.kf[e.kf];
-    const float x = h.mp_xyz[3 * (int64_t)e.gp], y = h.mp_xyz[3 * (int64_t)e.gp + 1],
-                z = h.mp_xyz[3 * (int64_t)e.gp + 2];
-    const float uo = h.kp_xy[2 * (int64_t)e.kp], vo = h.kp_xy[2 * (int64_t)e.kp + 1];
+__device__ __forceinline__ void refine_accumulate(const KfDesc& kd, float x, float y, float z, float uo, float vo,
+                                                  const fl_sim3& S, float delta, double* acc) {
     PairTerm t;
     pair_term(S.sR, S.t, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, x, y, z, uo, vo, delta, true, t);
     if (t.valid) {
@@ -436,66 +454,105 @@ __device__ __forceinline__ void refine_accumulate(const BatchHdr& h, const PairR
     }
 }
 
-__global__ __launch_bounds__(kResBlock) void refine_iter_kernel(const BatchHdr* __restrict__ hp) {
+__global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
     __shared__ double s_red[(kResBlock / kWave) * kNAcc];
     __shared__ double s_out[kNAcc];
-    __shared__ int s_last;
+    __shared__ double s_chunk[32 * kNAcc];
+    __shared__ double s_S64[13];
+    __shared__ fl_sim3 s_S;
+    __shared__ int s_fail;
     const BatchHdr& h = *hp;
     const int B = h.refine_blocks;
-    for (int eb = blockIdx.x; eb < h.n_events * B; eb += gridDim.x) {
-        const int ev = eb / B, b = eb % B;
-        const EventDesc& ed = h.ev[ev];
-        const fl_sim3 S = h.event_S32[ev];
-        double acc[kNAcc];
-#pragma unroll
-        for (int i = 0; i < kNAcc; ++i) acc[i] = 0.0;
-        const uint32_t cnt = h.ev_match_count[ev];
+    const int n_units = h.n_events * B;
+    const int iters = h.refine_iters;
+    const float delta = h.huber_delta;
+    for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+        const int ev = unit / B, b = unit % B;
+        const EventDesc ed = h.ev[ev];
+        if (threadIdx.x < 13) s_S64[threadIdx.x] = h.event_S[13 * (int64_t)ev + threadIdx.x];
+        if (threadIdx.x == 0) s_fail = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) sim3_to_f32(sim3_load(s_S64), &s_S);
+        __syncthreads();
+        const uint32_t cnt = h.ev_ctr[ev * kEvCtrs + kEvMatch];
+        const bool use_list = !h.refine_scan && cnt <= (uint32_t)ed.list_cap;
         const int stride = B * blockDim.x;
-        if (!h.refine_scan && cnt <= (uint32_t)ed.list_cap) {
-            for (int i = b * blockDim.x + threadIdx.x; i < (int)cnt; i += stride)
-                refine_accumulate(h, h.match_list[ed.list_off + i], S, h.huber_delta, acc);
-        } else {
-            // the list overflowed: scan the event's pairs keyframe by keyframe
-            for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
-                const KfDesc& kd = h.kf[k];
-                for (int64_t j = b * blockDim.x + threadIdx.x; j < kd.n_pairs; j += stride) {
-                    const int64_t o = kd.pair_off + j;
-                    const uint8_t dec = h.decision[o];
-                    if (dec != FL_ADD && dec != FL_FUSE) continue;
-                    PairRef e;
-                    e.pair = (int32_t)o;
-                    e.kp = kd.kp_off + h.best_idx[o];
-                    e.gp = kd.mp_off + (h.dense ? (int32_t)j : h.pair_mp[o]);
-                    e.kf = k;
-                    refine_accumulate(h, e, S, h.huber_delta, acc);
+        for (int it = 0; it < iters; ++it) {
+            const fl_sim3 S = s_S;
+            double acc[kNAcc];
+#pragma unroll
+            for (int i = 0; i < kNAcc; ++i) acc[i] = 0.0;
+            if (use_list) {
+                for (int i = b * blockDim.x + threadIdx.x; i < (int)cnt; i += stride) {
+                    const MatchRec m = h.match_list[ed.list_off + i];
+                    refine_accumulate(h.kf[m.kf], m.x, m.y, m.z, m.u, m.v, S, delta, acc);
+                }
+            } else {
+                // no list (or it overflowed): scan the event's pairs keyframe by keyframe
+                for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
+                    const KfDesc& kd = h.kf[k];
+                    for (int64_t j = b * blockDim.x + threadIdx.x; j < kd.n_pairs; j += stride) {
+                        const int64_t o = kd.pair_off + j;
+                        const uint8_t dec = h.decision[o];
+                        if (dec != FL_ADD && dec != FL_FUSE) continue;
+                        const int32_t lp = h.dense ? (int32_t)j : h.pair_mp[o];
+                        const int32_t bi = h.best_idx[o];
+                        if (lp < 0 || lp >= kd.n_mp || bi < 0 || bi >= kd.n_kp) continue;
+                        const int64_t gp = kd.mp_off + lp, kp = kd.kp_off + bi;
+                        refine_accumulate(kd, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1], h.mp_xyz[3 * gp + 2],
+                                          h.kp_xy[2 * kp], h.kp_xy[2 * kp + 1], S, delta, acc);
+                    }
+                }
+            }
+            block_reduce<kNAcc>(acc, s_red, s_out);
+            double* part = h.refine_partial + ((int64_t)(it & 1) * n_units + (int64_t)ev * B) * kNAcc;
+            if (B > 1) {
+                if ((int)threadIdx.x < kNAcc) part[(int64_t)b * kNAcc + threadIdx.x] = s_out[threadIdx.x];
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    __threadfence();   // release this workgroup's partial
+                    uint32_t* bar = &h.ev_ctr[ev * kEvCtrs + kEvBarrier];
+                    atomicAdd(bar, 1u);
+                    const uint32_t goal = (uint32_t)(it + 1) * (uint32_t)B;
+                    unsigned spins = 0;
+                    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < goal) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kSpinLimit) {
+                            s_fail = 1;
+                            break;
+                        }
+                    }
+                    __threadfence();   // acquire the other workgroups' partials
+                }
+                __syncthreads();
+                if (s_fail) break;
+                sum_partials<kNAcc>(part, B, s_chunk, s_out);
+            }
+            if (threadIdx.x == 0) {
+                double d[7];
+                if (solve7(s_out, s_out + 7, 0.0, d)) {
+                    const Sim3d Sd = sim3_mul(sim3_exp(d), sim3_load(s_S64));
+                    sim3_store(Sd, s_S64);
+                    sim3_to_f32(Sd, &s_S);
+                }
+            }
+            __syncthreads();
+        }
+        if (B > 1) {   // the last workgroup to leave resets the event's barrier
+            if (threadIdx.x == 0) {
+                if (atomicAdd(&h.ev_ctr[ev * kEvCtrs + kEvLeave], 1u) == (uint32_t)(B - 1)) {
+                    h.ev_ctr[ev * kEvCtrs + kEvBarrier] = 0;
+                    h.ev_ctr[ev * kEvCtrs + kEvLeave] = 0;
                 }
             }
         }
-        block_reduce<kNAcc>(acc, s_red, s_out);
-        double* part = h.refine_partial + ((int64_t)ev * B + b) * kNAcc;
-        if ((int)threadIdx.x < kNAcc) part[threadIdx.x] = s_out[threadIdx.x];
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = atomicAdd(&h.refine_done[ev], 1u) == (uint32_t)(B - 1);
-        __syncthreads();
-        if (s_last) __threadfence();   // acquire before reading the other blocks' partials
-        if (s_last && threadIdx.x == 0) {
-            double gh[kNAcc];
-            for (int i = 0; i < kNAcc; ++i) {
-                double s = 0.0;
-                for (int bb = 0; bb < B; ++bb) s += h.refine_partial[((int64_t)ev * B + bb) * kNAcc + i];
-                gh[i] = s;
+        if (b == 0 && threadIdx.x == 0) {
+            if (!s_fail) {
+                for (int i = 0; i < 13; ++i) h.event_S[13 * (int64_t)ev + i] = s_S64[i];
+                if (h.event_S32_out) h.event_S32_out[ev] = s_S;
             }
-            double d[7];
-            Sim3d Sd = sim3_load(h.event_S + 13 * (int64_t)ev);
-            if (solve7(gh, gh + 7, 0.0, d)) {
-                Sd = sim3_mul(sim3_exp(d), Sd);
-                sim3_store(Sd, h.event_S + 13 * (int64_t)ev);
-            }
-            sim3_to_f32(Sd, &h.event_S32[ev]);
-            if (h.event_S32_out) h.event_S32_out[ev] = h.event_S32[ev];
-            if (h.event_n_matched) h.event_n_matched[ev] = (int32_t)gh[35];
-            h.refine_done[ev] = 0;
+            if (h.event_n_matched) h.event_n_matched[ev] = s_fail ? -1 : (int32_t)s_out[35];
+            h.ev_ctr[ev * kEvCtrs + kEvMatch] = 0;   // the event's list is spent
         }
         __syncthreads();
     }

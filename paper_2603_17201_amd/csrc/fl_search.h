@@ -1,5 +1,5 @@
-// Search-and-fuse kernels: keypoint grid build, the persistent batched
-// search, the plain per-keyframe search and ADD-conflict resolution.
+// Search-and-fuse kernels: the fused batched search, its global-grid
+// fallback, the plain per-keyframe search and ADD-conflict resolution.
 //
 // Loop fusion (paper Sec. III-B, Sec. IV-D3): every map point of the loop
 // region is projected through the corrected Sim3 into each connected
@@ -15,6 +15,7 @@
 namespace fl {
 
 constexpr uint8_t kDecUndecided = 0xFF;
+constexpr int kSearchBlock = 1024;   // threads of a batched-search workgroup (16 waves)
 
 struct SearchConst {
     float sf[32];
@@ -67,65 +68,129 @@ __device__ __forceinline__ bool in_window(const Window& w, float x, float y, int
     return true;
 }
 
+__device__ __forceinline__ uint32_t owner_slot(int32_t id, int32_t mask) {
+    return (hash_id(id) >> 7) & (uint32_t)mask;
+}
+
+// Insert an owner id into an open-addressing set with at least one free slot.
+__device__ __forceinline__ void owner_insert(int32_t* tab, int32_t mask, int32_t o) {
+    uint32_t hh = owner_slot(o, mask);
+    for (int probe = 0; probe <= mask; ++probe) {
+        const int32_t prev = atomicCAS(&tab[hh], -1, o);
+        if (prev == -1 || prev == o) return;
+        hh = (hh + 1) & (uint32_t)mask;
+    }
+}
+
+// Workgroup exclusive scan of a[0..n) in place (n may exceed blockDim).
+// s_tmp needs blockDim / 64 + 1 ints.
+__device__ void block_exclusive_scan(int32_t* a, int n, int32_t* s_tmp) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = wave_lane(), wid = tid / kWave, nw = nt / kWave;
+    const int chunk = (n + nt - 1) / nt;
+    const int b = min(tid * chunk, n), e = min(b + chunk, n);
+    int sum = 0;
+    for (int i = b; i < e; ++i) sum += a[i];
+    int incl = sum;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    if (lane == kWave - 1) s_tmp[wid] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int v = s_tmp[w];
+            s_tmp[w] = run;
+            run += v;
+        }
+        s_tmp[nw] = run;
+    }
+    __syncthreads();
+    int run = s_tmp[wid] + incl - sum;
+    for (int i = b; i < e; ++i) {
+        const int v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// Grid build: one workgroup per keyframe (strided).  LDS histogram of cells,
-// exclusive prefix scan into cell_start, scatter of keypoint indices into
-// cell_kp, then per-cell sort so the layout is deterministic.  Optionally
-// also writes the cell-ordered records / descriptors, the owner hash set,
-// resets the ADD claims and fills the tile table.
+// Keyframe grid in LDS: histogram of cells, exclusive scan, scatter of
+// cell-ordered records (and descriptors), owner hash set.  On return s_cs[c]
+// is the first slot of cell c and s_cs[cells] = n_kp.  The order of the
+// keypoints inside a cell is arbitrary: the packed (distance, index) key
+// makes every output independent of it.
+
+template <bool STAGE_DESC>
+__device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_cs, KpRec* s_rec, uint4* s_desc,
+                               int32_t* s_hash, int32_t* s_tmp) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n = kd.n_kp;
+    const int cells = h.cells, C = h.grid_cols, R = h.grid_rows;
+    const int hmask = h.lds_hash_mask;
+    const float* xy = h.kp_xy + 2 * (int64_t)kd.kp_off;
+    for (int c = tid; c <= cells; c += nt) s_cs[c] = 0;
+    for (int s = tid; s <= hmask; s += nt) s_hash[s] = -1;
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) {
+        const int c = cell_of(xy[2 * i + 1], kd.invh, R) * C + cell_of(xy[2 * i], kd.invw, C);
+        atomicAdd(&s_cs[c + 1], 1);
+        const int32_t o = h.kp_owner[kd.kp_off + i];
+        if (o >= 0) owner_insert(s_hash, hmask, o);
+    }
+    __syncthreads();
+    block_exclusive_scan(s_cs + 1, cells, s_tmp);   // s_cs[1 + c] = first slot of c
+    for (int i = tid; i < n; i += nt) {
+        const float x = xy[2 * i], y = xy[2 * i + 1];
+        const int c = cell_of(y, kd.invh, R) * C + cell_of(x, kd.invw, C);
+        const int slot = atomicAdd(&s_cs[c + 1], 1);   // ends as the first slot of c + 1
+        KpRec r;
+        r.x = x;
+        r.y = y;
+        r.idx = i;
+        r.oct = (int)h.kp_oct[kd.kp_off + i];
+        s_rec[slot] = r;
+        if (STAGE_DESC) {
+            const uint4* src = reinterpret_cast<const uint4*>(h.kp_desc + 32 * ((int64_t)kd.kp_off + i));
+            s_desc[2 * slot] = src[0];
+            s_desc[2 * slot + 1] = src[1];
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Global keyframe grids (fallback for keyframes too large for LDS, and
+// fl_build_grid): one workgroup per keyframe.
 
 constexpr int kPrepBlock = 256;
 
-template <bool FULL>
-__device__ void prep_keyframe(const KfDesc& kd, int k, int cells, int C, int R, const float* __restrict__ kp_xy,
-                              const int8_t* __restrict__ kp_oct, const uint8_t* __restrict__ kp_desc,
-                              const int32_t* __restrict__ kp_owner, int32_t* __restrict__ cell_start,
-                              int32_t* __restrict__ cell_kp, KpRec* __restrict__ recs,
-                              uint4* __restrict__ desc_sorted, int32_t* __restrict__ hash,
-                              int32_t* __restrict__ claim, int2* __restrict__ tiles, int32_t* s_cnt,
-                              int32_t* s_part) {
-    const int tid = threadIdx.x;
-    const int nb = blockDim.x;
+__device__ void build_grid_global(const KfDesc& kd, int cells, int C, int R, const float* __restrict__ kp_xy,
+                                  int32_t* __restrict__ cs, int32_t* __restrict__ ck, int32_t* s_cnt,
+                                  int32_t* s_tmp) {
+    const int tid = threadIdx.x, nb = blockDim.x;
     const int n = kd.n_kp;
     const float* xy = kp_xy + 2 * (int64_t)kd.kp_off;
-    for (int c = tid; c < cells; c += nb) s_cnt[c] = 0;
+    for (int c = tid; c <= cells; c += nb) s_cnt[c] = 0;
     __syncthreads();
     for (int i = tid; i < n; i += nb) {
         const int c = cell_of(xy[2 * i + 1], kd.invh, R) * C + cell_of(xy[2 * i], kd.invw, C);
         atomicAdd(&s_cnt[c], 1);
     }
     __syncthreads();
-    // exclusive scan: each thread owns a contiguous chunk of cells
-    const int chunk = (cells + nb - 1) / nb;
-    const int cb = min(tid * chunk, cells), ce = min(cb + chunk, cells);
-    int sum = 0;
-    for (int c = cb; c < ce; ++c) sum += s_cnt[c];
-    s_part[tid] = sum;
+    block_exclusive_scan(s_cnt, cells, s_tmp);
+    for (int c = tid; c < cells; c += nb) cs[c] = s_cnt[c];
+    if (tid == 0) cs[cells] = n;
     __syncthreads();
-    for (int off = 1; off < nb; off <<= 1) {
-        const int v = tid >= off ? s_part[tid - off] : 0;
-        __syncthreads();
-        s_part[tid] += v;
-        __syncthreads();
-    }
-    int run = s_part[tid] - sum;   // exclusive prefix of this chunk
-    int32_t* cs = cell_start + kd.grid_off;
-    for (int c = cb; c < ce; ++c) {
-        const int v = s_cnt[c];
-        cs[c] = run;
-        s_cnt[c] = run;
-        run += v;
-    }
-    if (tid == nb - 1) cs[cells] = s_part[nb - 1];
-    __syncthreads();
-    int32_t* ck = cell_kp + kd.kp_off;
     for (int i = tid; i < n; i += nb) {
         const int c = cell_of(xy[2 * i + 1], kd.invh, R) * C + cell_of(xy[2 * i], kd.invw, C);
-        const int slot = atomicAdd(&s_cnt[c], 1);
-        ck[slot] = i;
+        ck[atomicAdd(&s_cnt[c], 1)] = i;
     }
     __syncthreads();
-    // keypoints of a cell in increasing index order
+    // keypoints of a cell in increasing index order (deterministic layout)
     for (int c = tid; c < cells; c += nb) {
         const int b = cs[c], e = cs[c + 1];
         for (int a = b + 1; a < e; ++a) {
@@ -138,55 +203,37 @@ __device__ void prep_keyframe(const KfDesc& kd, int k, int cells, int C, int R, 
             ck[j + 1] = v;
         }
     }
-    if (!FULL) return;
     __syncthreads();
-    for (int s = tid; s < n; s += nb) {
-        const int i = ck[s];
-        KpRec r;
-        r.x = xy[2 * i];
-        r.y = xy[2 * i + 1];
-        r.idx = i;
-        r.oct = (int)kp_oct[kd.kp_off + i];
-        recs[kd.kp_off + s] = r;
-        const uint4* src = reinterpret_cast<const uint4*>(kp_desc + 32 * ((int64_t)kd.kp_off + i));
-        uint4* dst = desc_sorted + 2 * ((int64_t)kd.kp_off + s);
-        dst[0] = src[0];
-        dst[1] = src[1];
-    }
-    int32_t* tab = hash + kd.hash_off;
-    for (int s = tid; s <= kd.hash_mask; s += nb) tab[s] = -1;
-    for (int i = tid; i < n; i += nb) claim[kd.kp_off + i] = 0x7FFFFFFF;
-    for (int j = tid; j < kd.n_tiles; j += nb) tiles[kd.tile_off + j] = make_int2(k, j);
-    __syncthreads();
-    for (int i = tid; i < n; i += nb) {
-        const int32_t o = kp_owner[kd.kp_off + i];
-        if (o < 0) continue;
-        uint32_t hh = (hash_id(o) >> 7) & (uint32_t)kd.hash_mask;
-        for (;;) {
-            const int32_t prev = atomicCAS(&tab[hh], -1, o);
-            if (prev == -1 || prev == o) break;
-            hh = (hh + 1) & (uint32_t)kd.hash_mask;
-        }
-    }
 }
 
-__global__ __launch_bounds__(kPrepBlock) void prep_batched_kernel(const BatchHdr* __restrict__ hp) {
-    __shared__ int32_t s_cnt[FL_MAX_CELLS];
-    __shared__ int32_t s_part[kPrepBlock];
+__global__ __launch_bounds__(kPrepBlock) void prep_global_kernel(const BatchHdr* __restrict__ hp) {
+    __shared__ int32_t s_cnt[FL_MAX_CELLS + 1];
+    __shared__ int32_t s_tmp[kPrepBlock / kWave + 1];
     const BatchHdr& h = *hp;
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) h.counters[i] = 0;
-        for (int i = threadIdx.x; i < 4; i += blockDim.x) h.stats_out[i] = 0ull;
-        for (int i = threadIdx.x; i < h.n_events; i += blockDim.x) {
-            h.ev_match_count[i] = 0;
-            h.refine_done[i] = 0;
-        }
-    }
     for (int k = blockIdx.x; k < h.n_kf; k += gridDim.x) {
         const KfDesc& kd = h.kf[k];
-        prep_keyframe<true>(kd, k, h.cells, h.grid_cols, h.grid_rows, h.kp_xy, h.kp_oct, h.kp_desc, h.kp_owner,
-                            h.cell_start, h.cell_kp, h.recs, h.desc_sorted, h.hash, h.claim,
-                            h.tile, s_cnt, s_part);
+        int32_t* cs = h.cell_start + kd.grid_off;
+        int32_t* ck = h.cell_kp + kd.kp_off;
+        build_grid_global(kd, h.cells, h.grid_cols, h.grid_rows, h.kp_xy, cs, ck, s_cnt, s_tmp);
+        for (int s = threadIdx.x; s < kd.n_kp; s += blockDim.x) {
+            const int i = ck[s];
+            KpRec r;
+            r.x = h.kp_xy[2 * ((int64_t)kd.kp_off + i)];
+            r.y = h.kp_xy[2 * ((int64_t)kd.kp_off + i) + 1];
+            r.idx = i;
+            r.oct = (int)h.kp_oct[kd.kp_off + i];
+            h.recs[kd.kp_off + s] = r;
+            const uint4* src = reinterpret_cast<const uint4*>(h.kp_desc + 32 * ((int64_t)kd.kp_off + i));
+            h.desc_sorted[2 * ((int64_t)kd.kp_off + s)] = src[0];
+            h.desc_sorted[2 * ((int64_t)kd.kp_off + s) + 1] = src[1];
+        }
+        int32_t* tab = h.hash + kd.hash_off;
+        for (int s = threadIdx.x; s <= kd.hash_mask; s += blockDim.x) tab[s] = -1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kd.n_kp; i += blockDim.x) {
+            const int32_t o = h.kp_owner[kd.kp_off + i];
+            if (o >= 0) owner_insert(tab, kd.hash_mask, o);
+        }
         __syncthreads();
     }
 }
@@ -196,39 +243,16 @@ __global__ __launch_bounds__(kPrepBlock) void grid_single_kernel(KfDesc kd, int 
                                                                const float* __restrict__ kp_xy,
                                                                int32_t* __restrict__ cell_start,
                                                                int32_t* __restrict__ cell_kp) {
-    __shared__ int32_t s_cnt[FL_MAX_CELLS];
-    __shared__ int32_t s_part[kPrepBlock];
-    prep_keyframe<false>(kd, 0, cells, C, R, kp_xy, nullptr, nullptr, nullptr, cell_start, cell_kp, nullptr,
-                         nullptr, nullptr, nullptr, nullptr, s_cnt, s_part);
-}
-
-// Owner hash set and claim reset of a single keyframe (plain path).
-__global__ __launch_bounds__(kPrepBlock) void plain_prep_kernel(int n, const int32_t* __restrict__ kp_owner,
-                                                              int32_t* __restrict__ tab, int32_t mask,
-                                                              int32_t* __restrict__ claim,
-                                                              uint32_t* __restrict__ counters) {
-    const int tid = threadIdx.x;
-    for (int s = tid; s <= mask; s += blockDim.x) tab[s] = -1;
-    for (int i = tid; i < n; i += blockDim.x) claim[i] = 0x7FFFFFFF;
-    for (int i = tid; i < kCounterWords; i += blockDim.x) counters[i] = 0;
-    __syncthreads();
-    for (int i = tid; i < n; i += blockDim.x) {
-        const int32_t o = kp_owner[i];
-        if (o < 0) continue;
-        uint32_t hh = (hash_id(o) >> 7) & (uint32_t)mask;
-        for (;;) {
-            const int32_t prev = atomicCAS(&tab[hh], -1, o);
-            if (prev == -1 || prev == o) break;
-            hh = (hh + 1) & (uint32_t)mask;
-        }
-    }
+    __shared__ int32_t s_cnt[FL_MAX_CELLS + 1];
+    __shared__ int32_t s_tmp[kPrepBlock / kWave + 1];
+    build_grid_global(kd, cells, C, R, kp_xy, cell_start, cell_kp, s_cnt, s_tmp);
 }
 
 // ---------------------------------------------------------------------------
-// Wave-aggregated append to a list: one atomic per wave.
+// Wave-aggregated append to a bounded list: one atomic per wave.
 
-__device__ __forceinline__ void wave_append(bool want, uint32_t* counter, PairRef* list, int32_t cap,
-                                            const PairRef& e) {
+template <typename T>
+__device__ __forceinline__ void wave_append(bool want, uint32_t* counter, T* list, int32_t cap, const T& e) {
     const unsigned long long m = __ballot(want);
     if (m == 0ull) return;
     const int lane = wave_lane();
@@ -243,59 +267,118 @@ __device__ __forceinline__ void wave_append(bool want, uint32_t* counter, PairRe
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batched search.  Each wave takes tiles of 64 * PPL consecutive
-// pairs of one keyframe from an atomic work queue; with one queue per XCD,
-// a workgroup serves the queue of the XCD it was dispatched to (workgroups
-// are dispatched to the 8 XCDs round-robin) and steals from the next queues
-// once its own is empty, so the keyframes of a queue stay in one L2.
+// Fused batched search.  Each workgroup owns a contiguous, cost-balanced run
+// of tiles (1024 * PPL consecutive pairs of one keyframe) inside the range of
+// its XCD (workgroups are dispatched to the 8 XCDs round-robin), so the
+// keyframes of an XCD stay in its L2 and no atomic is spent on scheduling.
+// When its tile moves to a new keyframe the workgroup builds that keyframe's
+// grid, records (and descriptors) and owner hash set in LDS.  The workgroup
+// finishing the last tile of a keyframe resolves that keyframe's ADD
+// conflicts, so no second kernel is needed.
 
-template <int PPL, bool STATS>
-__global__ __launch_bounds__(256) void search_batched_kernel(const BatchHdr* __restrict__ hp) {
+struct KfView {
+    const int32_t* cs;
+    const KpRec* rec;
+    const uint4* desc;          // cell-ordered descriptors (LDS or workspace), or null
+    const uint8_t* desc_orig;   // keypoint descriptors by original index (when desc is null)
+    const int32_t* hash;
+    int32_t hash_mask;
+};
+
+// LDS bytes of the search kernel (shared with the host).
+__host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cells, int hash_cap) {
+    if (mode == kModeGlobal) return 16;
+    size_t b = 16 * (size_t)kp_cap;
+    if (mode == kModeLdsDesc) b += 32 * (size_t)kp_cap;
+    b += 4 * (size_t)((cells + 4 + 3) & ~3);
+    b += 4 * (size_t)hash_cap;
+    b += 4 * (size_t)(kSearchBlock / kWave + 4);
+    b += 16;
+    return b;
+}
+
+template <int PPL, int MODE, bool STATS>
+__global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchHdr* __restrict__ hp) {
+    extern __shared__ __align__(16) unsigned char s_mem[];
     const BatchHdr& h = *hp;
+    const int tid = threadIdx.x;
     const int lane = wave_lane();
-    const int nq = h.n_queues;
-    int q = (int)(blockIdx.x % (unsigned)nq);
-    int exhausted = 0;
-    SearchConst sc;   // scalars only; the octave table is read from the header
+    KpRec* s_rec = reinterpret_cast<KpRec*>(s_mem);
+    uint4* s_desc = nullptr;
+    int32_t* s_cs = nullptr;
+    int32_t* s_hash = nullptr;
+    int32_t* s_tmp = nullptr;
+    int32_t* s_flag = reinterpret_cast<int32_t*>(s_mem);
+    if (MODE != kModeGlobal) {
+        unsigned char* p = s_mem + 16 * (size_t)h.lds_kp_cap;
+        if (MODE == kModeLdsDesc) {
+            s_desc = reinterpret_cast<uint4*>(p);
+            p += 32 * (size_t)h.lds_kp_cap;
+        }
+        s_cs = reinterpret_cast<int32_t*>(p);
+        p += 4 * (size_t)((h.cells + 4 + 3) & ~3);
+        s_hash = reinterpret_cast<int32_t*>(p);
+        p += 4 * (size_t)(h.lds_hash_mask + 1);
+        s_tmp = reinterpret_cast<int32_t*>(p);
+        p += 4 * (size_t)(kSearchBlock / kWave + 4);
+        s_flag = reinterpret_cast<int32_t*>(p);
+    }
+
     const float* sf = h.sf;
-    sc.N = h.n_octaves;
-    sc.gate = h.gate;
-    sc.C = h.grid_cols;
-    sc.R = h.grid_rows;
-    sc.th = h.hamming_th;
-    sc.ratio = h.nn_ratio;
-    sc.r0 = h.r0;
+    const int N = h.n_octaves, gate = h.gate, C = h.grid_cols, R = h.grid_rows, th = h.hamming_th;
+    const float ratio = h.nn_ratio, r0w = h.r0;
     const bool dense = h.dense != 0;
     const bool want_matches = h.refine_iters > 0;
+    const unsigned long long tag = (unsigned long long)h.epoch << 32;
     unsigned long long st_vis = 0, st_cells = 0, st_kp = 0, st_cand = 0;
 
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = (int)atomicAdd(&h.counters[kCtrQueue + q], 1u);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0)) + h.queue_begin[q];
-        if (t >= h.queue_begin[q + 1]) {
-            if (++exhausted >= nq) break;
-            q = (q + 1 == nq) ? 0 : q + 1;
-            continue;
+    const int2 range = h.wg_range[blockIdx.x];
+    int slot = 0;
+    {   // keyframe (in tile order) of the first tile: tile_prefix[slot] <= t < tile_prefix[slot + 1]
+        int lo = 0, hi = h.n_kf;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (h.tile_prefix[mid] <= range.x) lo = mid; else hi = mid;
         }
-        const int2 te = h.tile[t];
-        const int k = __builtin_amdgcn_readfirstlane(te.x);
-        const int tk = __builtin_amdgcn_readfirstlane(te.y);
-        const KfDesc& kd = h.kf[k];
-        const EventDesc& ed = h.ev[kd.event];
-        const int64_t pb = kd.pair_off + (int64_t)tk * h.tile_pairs;
+        slot = lo;
+    }
+    int staged = -1;
+    for (int t = range.x; t < range.y; ++t) {
+        while (t >= h.tile_prefix[slot + 1]) ++slot;
+        const int k = h.kf_order[slot];
+        const KfDesc kd = h.kf[k];            // by value: kept in registers across the stores below
+        const EventDesc ed = h.ev[kd.event];
+        KfView v;
+        if (MODE == kModeGlobal) {
+            v.cs = h.cell_start + kd.grid_off;
+            v.rec = h.recs + kd.kp_off;
+            v.desc = h.desc_sorted + 2 * (int64_t)kd.kp_off;
+            v.desc_orig = nullptr;
+            v.hash = h.hash + kd.hash_off;
+            v.hash_mask = kd.hash_mask;
+        } else {
+            if (staged != k) {
+                __syncthreads();   // every reader of the previous keyframe is done
+                stage_keyframe<MODE == kModeLdsDesc>(h, kd, s_cs, s_rec, s_desc, s_hash, s_tmp);
+                staged = k;
+            }
+            v.cs = s_cs;
+            v.rec = s_rec;
+            v.desc = MODE == kModeLdsDesc ? s_desc : nullptr;
+            v.desc_orig = h.kp_desc + 32 * (int64_t)kd.kp_off;
+            v.hash = s_hash;
+            v.hash_mask = h.lds_hash_mask;
+        }
+        const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
         const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
-        const int32_t* cs = h.cell_start + kd.grid_off;
-        const KpRec* recs = h.recs + kd.kp_off;
-        const uint4* kdesc = h.desc_sorted + 2 * (int64_t)kd.kp_off;
-        const int32_t* tab = h.hash + kd.hash_off;
 
 #pragma unroll
         for (int r = 0; r < PPL; ++r) {
-            const int64_t o = pb + (int64_t)r * kWave + lane;
+            const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
             const bool active = o < pe;
             uint8_t dec = active ? kDecUndecided : (uint8_t)0;
-            int32_t gp = 0, id = 0;
+            int32_t gp = 0, id = -1;
+            float x = 0.0f, y = 0.0f, z = 0.0f, dmax = 0.0f;
             if (active) {
                 const int64_t j = o - kd.pair_off;
                 const int32_t lp = dense ? (int32_t)j : h.pair_mp[o];
@@ -304,42 +387,65 @@ __global__ __launch_bounds__(256) void search_batched_kernel(const BatchHdr* __r
                 } else {
                     gp = kd.mp_off + lp;
                     id = h.mp_id ? h.mp_id[gp] : gp;
-                    if (owner_lookup(tab, kd.hash_mask, id)) dec = FL_SKIP;
+                    x = h.mp_xyz[3 * (int64_t)gp];
+                    y = h.mp_xyz[3 * (int64_t)gp + 1];
+                    z = h.mp_xyz[3 * (int64_t)gp + 2];
+                    if (gate) dmax = h.mp_dmax[gp];
+                }
+            }
+            // owner probe: a point already observed in this keyframe is skipped
+            if (dec == kDecUndecided && id >= 0) {
+                uint32_t hh = owner_slot(id, v.hash_mask);
+                for (int probe = 0; probe <= v.hash_mask; ++probe) {
+                    const int32_t hv = v.hash[hh];
+                    if (hv == id) {
+                        dec = FL_SKIP;
+                        break;
+                    }
+                    if (hv < 0) break;
+                    hh = (hh + 1) & (uint32_t)v.hash_mask;
                 }
             }
             Best best;
             best.init();
             int32_t target = -1;
+            float ku = 0.0f, kv = 0.0f;
             if (dec == kDecUndecided) {
-                const float x = h.mp_xyz[3 * (int64_t)gp];
-                const float y = h.mp_xyz[3 * (int64_t)gp + 1];
-                const float z = h.mp_xyz[3 * (int64_t)gp + 2];
-                const float dmax = sc.gate ? h.mp_dmax[gp] : 0.0f;
                 Proj p;
-                if (!project(kd, x, y, z, dmax, sc.gate, sf, sc.N, p)) {
+                if (!project(kd, x, y, z, dmax, gate, sf, N, p)) {
                     dec = FL_NOT_VISIBLE;
                 } else {
                     if (STATS) ++st_vis;
                     uint4 a0, a1;
                     load_desc(h.mp_desc, gp, a0, a1);
-                    const Window w = make_window(p, kd, sf, sc.r0, sc.C, sc.R);
+                    const Window w = make_window(p, kd, sf, r0w, C, R);
                     for (int row = w.r0; row <= w.r1; ++row) {
-                        const int s = cs[row * sc.C + w.c0];
-                        const int e = cs[row * sc.C + w.c1 + 1];
+                        const int s = v.cs[row * C + w.c0];
+                        const int e = v.cs[row * C + w.c1 + 1];
                         if (STATS) {
                             st_cells += (unsigned long long)(w.c1 - w.c0 + 1);
                             st_kp += (unsigned long long)(e - s);
                         }
                         for (int i = s; i < e; ++i) {
-                            const KpRec rc = recs[i];
-                            if (!in_window(w, rc.x, rc.y, rc.oct, p.pred, sc.gate)) continue;
+                            const KpRec rc = v.rec[i];
+                            if (!in_window(w, rc.x, rc.y, rc.oct, p.pred, gate)) continue;
                             if (STATS) ++st_cand;
-                            const uint4 b0 = kdesc[2 * i];
-                            const uint4 b1 = kdesc[2 * i + 1];
+                            uint4 b0, b1;
+                            if (MODE == kModeLdsRec) {
+                                load_desc(v.desc_orig, rc.idx, b0, b1);
+                            } else {
+                                b0 = v.desc[2 * i];
+                                b1 = v.desc[2 * i + 1];
+                            }
+                            const uint32_t before = best.key;
                             best.offer(hamming(a0, a1, b0, b1), rc.idx);
+                            if (best.key != before) {
+                                ku = rc.x;
+                                kv = rc.y;
+                            }
                         }
                     }
-                    if (!accept_match(best, sc.th, sc.ratio)) {
+                    if (!accept_match(best, th, ratio)) {
                         dec = FL_NO_MATCH;
                     } else {
                         const int32_t ow = h.kp_owner[kd.kp_off + (int32_t)(best.key & 0xFFFFu)];
@@ -347,7 +453,7 @@ __global__ __launch_bounds__(256) void search_batched_kernel(const BatchHdr* __r
                             dec = FL_FUSE;
                             target = ow;
                         } else {
-                            dec = FL_ADD;   // provisional; losers are relabelled by the resolve kernel
+                            dec = FL_ADD;   // provisional; losers are relabelled by the resolver
                         }
                     }
                 }
@@ -362,58 +468,76 @@ __global__ __launch_bounds__(256) void search_batched_kernel(const BatchHdr* __r
                 h.target[o] = target;
             }
             const bool is_add = active && dec == FL_ADD;
-            if (is_add) atomicMin(&h.claim[kpg], gp);
-            PairRef e;
-            e.pair = (int32_t)o;
-            e.kp = kpg;
-            e.gp = gp;
-            e.kf = k;
-            wave_append(is_add, &h.counters[kCtrAdd], h.add_list, h.add_cap, e);
+            if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp);
+            AddRef ae;
+            ae.pair = (int32_t)o;
+            ae.kp = kpg;
+            ae.gp = gp;
+            ae.pad = 0;
+            wave_append(is_add, &h.kf_ctr[k * kKfCtrs + kKfAdd], h.add_list + kd.add_off, kd.add_cap, ae);
             if (want_matches) {
                 const bool acc = active && (dec == FL_ADD || dec == FL_FUSE);
-                wave_append(acc, &h.ev_match_count[kd.event], h.match_list + ed.list_off, ed.list_cap, e);
+                MatchRec me;
+                me.x = x;
+                me.y = y;
+                me.z = z;
+                me.u = ku;
+                me.v = kv;
+                me.kf = k;
+                me.pad0 = me.pad1 = 0;
+                wave_append(acc, &h.ev_ctr[kd.event * kEvCtrs + kEvMatch], h.match_list + ed.list_off,
+                            ed.list_cap, me);
+            }
+        }
+
+        // Tile done; the workgroup completing a keyframe resolves its ADD
+        // conflicts.  The barrier orders every wave's stores before thread 0's
+        // device-scope release (an L2 write-back, so one per tile, not one per
+        // wave); the resolver's acquire invalidates this CU's caches.
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            s_flag[0] = atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfDone], 1u) == (uint32_t)(kd.n_tiles - 1);
+            if (s_flag[0]) __threadfence();
+        }
+        __syncthreads();
+        if (s_flag[0]) {
+            const uint32_t n_add = h.kf_ctr[k * kKfCtrs + kKfAdd];
+            if (n_add <= (uint32_t)kd.add_cap) {
+                for (uint32_t i = tid; i < n_add; i += kSearchBlock) {
+                    const AddRef e = h.add_list[kd.add_off + i];
+                    const int32_t w = (int32_t)(h.claim[e.kp] - tag);
+                    if (w != e.gp) {
+                        h.decision[e.pair] = FL_FUSE;
+                        h.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
+                    }
+                }
+            } else {   // the list overflowed: scan the keyframe's pairs
+                for (int64_t j = tid; j < kd.n_pairs; j += kSearchBlock) {
+                    const int64_t o = kd.pair_off + j;
+                    if (h.decision[o] != FL_ADD) continue;
+                    const int32_t gp = kd.mp_off + (dense ? (int32_t)j : h.pair_mp[o]);
+                    const int32_t w = (int32_t)(h.claim[kd.kp_off + h.best_idx[o]] - tag);
+                    if (w != gp) {
+                        h.decision[o] = FL_FUSE;
+                        h.target[o] = h.mp_id ? h.mp_id[w] : w;
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                h.kf_ctr[k * kKfCtrs + kKfDone] = 0;
+                h.kf_ctr[k * kKfCtrs + kKfAdd] = 0;
             }
         }
     }
     if (STATS) {
-        unsigned long long v[4] = {st_vis, st_cells, st_kp, st_cand};
+        unsigned long long vals[4] = {st_vis, st_cells, st_kp, st_cand};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            unsigned long long x = v[i];
-            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-            if (lane == 0 && x) atomicAdd(&h.stats_out[i], x);
-        }
-    }
-}
-
-// Conflict resolution: every provisional ADD whose point is not the lowest
-// claimant of its keypoint becomes a FUSE into that claimant.  Uses the ADD
-// list, or, when it overflowed, a scan of all pairs.
-__global__ __launch_bounds__(256) void resolve_batched_kernel(const BatchHdr* __restrict__ hp) {
-    const BatchHdr& h = *hp;
-    const uint32_t n = h.counters[kCtrAdd];
-    if (n <= (uint32_t)h.add_cap) {
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-            const PairRef e = h.add_list[i];
-            const int32_t w = h.claim[e.kp];
-            if (w != e.gp) {
-                h.decision[e.pair] = FL_FUSE;
-                h.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
-            }
-        }
-        return;
-    }
-    for (int k = blockIdx.x; k < h.n_kf; k += gridDim.x) {
-        const KfDesc& kd = h.kf[k];
-        for (int64_t j = threadIdx.x; j < kd.n_pairs; j += blockDim.x) {
-            const int64_t o = kd.pair_off + j;
-            if (h.decision[o] != FL_ADD) continue;
-            const int32_t gp = kd.mp_off + (h.dense ? (int32_t)j : h.pair_mp[o]);
-            const int32_t w = h.claim[kd.kp_off + h.best_idx[o]];
-            if (w != gp) {
-                h.decision[o] = FL_FUSE;
-                h.target[o] = h.mp_id ? h.mp_id[w] : w;
-            }
+            unsigned long long xv = vals[i];
+            for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+            if (lane == 0 && xv) atomicAdd(&h.stats_out[i], xv);
         }
     }
 }
@@ -422,6 +546,22 @@ __global__ __launch_bounds__(256) void resolve_batched_kernel(const BatchHdr* __
 // Plain search: one lane per map point against one keyframe, candidates
 // gathered through the caller's (or a freshly built) cell_start / cell_kp
 // grid from the keyframe's own arrays.
+
+// Owner hash set and claim reset of a single keyframe (plain path).
+__global__ __launch_bounds__(kPrepBlock) void plain_prep_kernel(int n, const int32_t* __restrict__ kp_owner,
+                                                              int32_t* __restrict__ tab, int32_t mask,
+                                                              int32_t* __restrict__ claim,
+                                                              uint32_t* __restrict__ counter) {
+    const int tid = threadIdx.x;
+    for (int s = tid; s <= mask; s += blockDim.x) tab[s] = -1;
+    for (int i = tid; i < n; i += blockDim.x) claim[i] = 0x7FFFFFFF;
+    if (tid == 0) *counter = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+        const int32_t o = kp_owner[i];
+        if (o >= 0) owner_insert(tab, mask, o);
+    }
+}
 
 struct PlainArgs {
     KfDesc kd;
@@ -440,8 +580,8 @@ struct PlainArgs {
     const int32_t* cell_kp;
     const int32_t* hash;
     int32_t* claim;
-    uint32_t* counters;
-    PairRef* add_list;
+    uint32_t* counter;
+    AddRef* add_list;
     int32_t* best_idx;
     int16_t* best_dist;
     int16_t* second_dist;
@@ -508,26 +648,26 @@ __global__ __launch_bounds__(256) void search_plain_kernel(PlainArgs a) {
     }
     const bool is_add = active && dec == FL_ADD;
     if (is_add) atomicMin(&a.claim[bidx], gp);
-    PairRef e;
+    AddRef e;
     e.pair = (int32_t)o;
     e.kp = bidx < 0 ? 0 : bidx;
     e.gp = gp;
-    e.kf = 0;
-    wave_append(is_add, &a.counters[kCtrAdd], a.add_list, a.add_cap, e);
+    e.pad = 0;
+    wave_append(is_add, a.counter, a.add_list, a.add_cap, e);
 }
 
-__global__ __launch_bounds__(256) void resolve_plain_kernel(int32_t n_mp, const uint32_t* __restrict__ counters,
-                                                          const PairRef* __restrict__ list, int32_t cap,
+__global__ __launch_bounds__(256) void resolve_plain_kernel(int32_t n_mp, const uint32_t* __restrict__ counter,
+                                                          const AddRef* __restrict__ list, int32_t cap,
                                                           const int32_t* __restrict__ claim,
                                                           const int32_t* __restrict__ mp_id,
                                                           const int32_t* __restrict__ best_idx,
                                                           uint8_t* __restrict__ decision,
                                                           int32_t* __restrict__ target) {
-    const uint32_t n = counters[kCtrAdd];
+    const uint32_t n = *counter;
     const int stride = gridDim.x * blockDim.x;
     if (n <= (uint32_t)cap) {
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-            const PairRef e = list[i];
+            const AddRef e = list[i];
             const int32_t w = claim[e.kp];
             if (w != e.gp) {
                 decision[e.pair] = FL_FUSE;

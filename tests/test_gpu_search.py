@@ -90,10 +90,10 @@ def test_c2_every_tuning_and_repeat(ctx, c2):
     ev, exp = c2
     b = fl.DeviceBatch(ev, device=dev())
     try:
-        for ppl, blk, wpc, xq in itertools.product((1, 2, 4), (64, 128, 256), (4, 16), (0, 1)):
-            ctx.set_tuning(ppl, blk, wpc, xq)
+        for ppl, mode, wpc, xa in itertools.product((1, 2, 4), (0, 1, 2), (1, 2), (0, 1)):
+            ctx.set_tuning(ppl, mode, wpc, xa)
             got = ctx.search_fuse_batched(b, ev.params).numpy()
-            assert_same(got, exp, f"tuning {ppl} {blk} {wpc} {xq}")
+            assert_same(got, exp, f"tuning {ppl} {mode} {wpc} {xa}")
     finally:
         ctx.set_tuning()
     first = ctx.search_fuse_batched(b, ev.params).numpy()
