@@ -81,6 +81,7 @@ constexpr int kPinRing = 16;   // staging buffers in flight
 struct Pinned {
     void* p = nullptr;
     size_t size = 0;
+    size_t used = 0;            // bytes of tables staged in it
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -101,13 +102,15 @@ struct fl_ctx {
     int pin_next = 0;
     hipStream_t cap_stream = nullptr;
     fl_tuning tune{1, kModeLdsDesc, 1, 1};
-    uint32_t epoch = 0xFFFFFFFEu;
+    uint32_t launches = 0;      // table fetches since the claims were last reset
+    Pinned* pin_last = nullptr; // ring buffer of the last eager upload
     int stats = 0;
     int add_cap_override = 0;   // test hook: >0 forces small ADD / match list capacities
     int prof = 0;               // record events around eager search kernels
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
     // captured graph and its key
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // replayed alternately
+    Pinned gpin[2];             // the pinned tables each graph fetches from
     int g_next = 0;
     void* g_ws = nullptr;
     void* g_claims = nullptr;
@@ -176,12 +179,8 @@ int get_pinned(fl_ctx* c, size_t need, Pinned** out) {
     Pinned& p = c->pin[c->pin_next];
     c->pin_next = (c->pin_next + 1) % kPinRing;
     if (p.pending) {
-        // the upload from this buffer kPinRing calls ago must have run; poll
-        // rather than block so a short wait does not cost a scheduler tick
-        hipError_t q;
-        while ((q = hipEventQuery(p.done)) == hipErrorNotReady) {
-        }
-        if (q != hipSuccess) return fail(FL_EHIP, "hipEventQuery: %s", hipGetErrorString(q));
+        // the fetch from this buffer kPinRing uploads ago must have run
+        FL_HIP(hipEventSynchronize(p.done));
         p.pending = false;
     }
     if (p.size < need) {
@@ -263,6 +262,7 @@ struct Prepared {
     int ppl = 1;
     int grid = 1;
     size_t lds = 16;
+    size_t blob_cap = 0;
     int refine_iters = 0;
 };
 
@@ -413,7 +413,11 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         off = align_up(off + std::max<size_t>(bytes, 16), 256);
         return o;
     };
-    const size_t L_blob = take(blob.size());
+    // the tables region has a power-of-two capacity: a captured graph fetches
+    // the whole capacity from its pinned buffer
+    pr.blob_cap = std::max<size_t>(65536, 1);
+    while (pr.blob_cap < blob.size()) pr.blob_cap <<= 1;
+    const size_t L_blob = take(pr.blob_cap);
     const bool global_grid = pr.mode == kModeGlobal;
     const size_t L_cs = take(global_grid ? sizeof(int32_t) * (size_t)n_kf * (cells + 1) : 0);
     const size_t L_recs = take(global_grid ? sizeof(KpRec) * (size_t)B->n_kp_total : 0);
@@ -428,8 +432,14 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     if (rc) return rc;
     rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(B->n_kp_total, 1), 0xFF);
     if (rc) return rc;
-    rc = c->ctrs.ensure(32 + sizeof(uint32_t) * ((size_t)kKfCtrs * n_kf + (size_t)kEvCtrs * n_ev), 0x00);
+    const void* old_ctrs = c->ctrs.p;
+    rc = c->ctrs.ensure(64 + sizeof(uint32_t) * ((size_t)kKfCtrs * n_kf + (size_t)kEvCtrs * n_ev), 0x00);
     if (rc) return rc;
+    if (c->ctrs.p != old_ctrs && old_ctrs != nullptr) {
+        // a fresh counter block restarts the epoch: every stored claim must be reset too
+        if (hipMemset(c->claims.p, 0xFF, c->claims.size) != hipSuccess) return fail(FL_EHIP, "hipMemset failed");
+        c->launches = 0;
+    }
     char* base = (char*)c->ws.p;
     char* cb = (char*)c->ctrs.p;
 
@@ -452,7 +462,6 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.gate = B->mp_dmax != nullptr;
     h.dense = B->pair_mp == nullptr;
     h.stats = c->stats;
-    h.epoch = c->epoch;
     h.lds_hash_mask = lds_hash_cap - 1;
     h.lds_kp_cap = kp_cap;   // the record capacity search_lds_bytes sized
     h.n_wg = grid;
@@ -484,8 +493,9 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.hash = (int32_t*)(base + L_hash);
     h.claim = (unsigned long long*)c->claims.p;
     h.stats_out = (unsigned long long*)cb;
-    h.kf_ctr = (uint32_t*)(cb + 32);
-    h.ev_ctr = (uint32_t*)(cb + 32 + sizeof(uint32_t) * (size_t)kKfCtrs * n_kf);
+    h.epoch = (const uint32_t*)(cb + 32);
+    h.kf_ctr = (uint32_t*)(cb + 64);
+    h.ev_ctr = (uint32_t*)(cb + 64 + sizeof(uint32_t) * (size_t)kKfCtrs * n_kf);
     h.add_list = (AddRef*)(base + L_add);
     h.match_list = (MatchRec*)(base + L_match);
     h.refine_blocks = refine_blocks;
@@ -501,22 +511,44 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     return FL_OK;
 }
 
-// Copy the header and tables to the workspace through pinned memory, on the
-// stream that will run the kernels.  Advances the claim epoch.
-int upload_batch(fl_ctx* c, Prepared& pr, hipStream_t stream) {
-    if (c->epoch <= 1) {   // epochs exhausted: reset every claim and start again
+// Count launches; when the device epoch (decremented by every table fetch)
+// is about to run out, reset every claim and the epoch.
+int next_epoch(fl_ctx* c, hipStream_t stream) {
+    if (++c->launches >= 0xFFFFFFF0u) {
         FL_HIP(hipMemsetAsync(c->claims.p, 0xFF, c->claims.size, stream));
-        c->epoch = 0xFFFFFFFEu;
-        pr.hdr->epoch = c->epoch;
+        FL_HIP(hipMemsetAsync((char*)c->ctrs.p + 32, 0, 4, stream));
+        c->launches = 1;
     }
-    --c->epoch;
-    Pinned* pin = nullptr;
-    int rc = get_pinned(c, pr.blob.size(), &pin);
+    return FL_OK;
+}
+
+void launch_fetch(fl_ctx* c, const void* src, size_t bytes, hipStream_t stream) {
+    const int n16 = (int)((bytes + 15) / 16);
+    const int grid = std::max(1, std::min((n16 + 255) / 256, 64));
+    hipLaunchKernelGGL(fetch_blob_kernel, dim3(grid), dim3(256), 0, stream, (const uint4*)src, (uint4*)c->ws.p, n16,
+                       (uint32_t*)((char*)c->ctrs.p + 32));
+}
+
+// Eager calls: stage the header and tables in a pinned ring buffer and fetch
+// them into the workspace with a copy kernel on the launch stream.
+int upload_batch(fl_ctx* c, Prepared& pr, hipStream_t stream) {
+    int rc = next_epoch(c, stream);
     if (rc) return rc;
-    memcpy(pin->p, pr.blob.data(), pr.blob.size());
-    FL_HIP(hipMemcpyAsync(c->ws.p, pin->p, pr.blob.size(), hipMemcpyHostToDevice, stream));
+    Pinned* last = c->pin_last;
+    Pinned* pin = nullptr;
+    if (last && last->used == pr.blob.size() && memcmp(last->p, pr.blob.data(), pr.blob.size()) == 0) {
+        pin = last;   // unchanged tables: fetch again from the same buffer, nothing is overwritten
+    } else {
+        rc = get_pinned(c, pr.blob.size(), &pin);
+        if (rc) return rc;
+        memcpy(pin->p, pr.blob.data(), pr.blob.size());
+        pin->used = pr.blob.size();
+    }
+    launch_fetch(c, pin->p, pr.blob.size(), stream);
+    FL_HIP(hipGetLastError());
     FL_HIP(hipEventRecord(pin->done, stream));
     pin->pending = true;
+    c->pin_last = pin;
     return FL_OK;
 }
 
@@ -623,6 +655,12 @@ int fl_create(fl_ctx** out, int device) {
     allow_lds_all<1>(c->lds_max);
     allow_lds_all<2>(c->lds_max);
     allow_lds_all<4>(c->lds_max);
+    for (auto& p : c->gpin) {
+        if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) {
+            fl_destroy(c);
+            return fail(FL_EHIP, "hipEventCreate failed");
+        }
+    }
     for (auto& p : c->pin) {
         if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) {
             fl_destroy(c);
@@ -650,6 +688,10 @@ void fl_destroy(fl_ctx* c) {
         if (g) hipGraphExecDestroy(g);
     clear_profile(c);
     for (auto& p : c->pin) {
+        if (p.p) hipHostFree(p.p);
+        if (p.done) hipEventDestroy(p.done);
+    }
+    for (auto& p : c->gpin) {
         if (p.p) hipHostFree(p.p);
         if (p.done) hipEventDestroy(p.done);
     }
@@ -823,12 +865,26 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
     const int refine_on = pr.refine_iters > 0 ? 1 : 0;
     const bool stale = !c->gexec[0] || c->g_ws != c->ws.p || c->g_claims != c->claims.p || c->g_ctrs != c->ctrs.p ||
                        c->g_mode != pr.mode || c->g_ppl != pr.ppl || c->g_grid != pr.grid ||
-                       c->g_refine != refine_on || c->g_lds != pr.lds;
+                       c->g_refine != refine_on || c->g_lds != pr.lds || c->gpin[0].size != pr.blob_cap;
     if (stale) {
         FL_HIP(hipStreamSynchronize(stream));
-        for (auto& g : c->gexec) {
-            if (g) hipGraphExecDestroy(g);
-            g = nullptr;
+        for (int gi = 0; gi < 2; ++gi) {
+            if (c->gexec[gi]) hipGraphExecDestroy(c->gexec[gi]);
+            c->gexec[gi] = nullptr;
+            Pinned& gp = c->gpin[gi];
+            gp.pending = false;
+            gp.used = 0;
+            if (gp.size != pr.blob_cap) {
+                if (gp.p) hipHostFree(gp.p);
+                gp.p = nullptr;
+                gp.size = 0;
+                const size_t n = pr.blob_cap;
+                if (hipHostMalloc(&gp.p, n, hipHostMallocDefault) != hipSuccess) {
+                    gp.p = nullptr;
+                    return fail(FL_ENOMEM, "hipHostMalloc of %zu bytes failed", n);
+                }
+                gp.size = n;
+            }
         }
         const BatchHdr* dh = (const BatchHdr*)c->ws.p;
         for (int gi = 0; gi < 2; ++gi) {
@@ -836,6 +892,7 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
             FL_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             const int saved_prof = c->prof;
             c->prof = 0;
+            launch_fetch(c, c->gpin[gi].p, c->gpin[gi].size, c->cap_stream);
             int lrc = launch_search(c, pr, dh, c->cap_stream, false, false);
             c->prof = saved_prof;
             if (lrc == FL_OK && refine_on) lrc = launch_refine(dh, pr.refine_iters, c->cap_stream);
@@ -861,9 +918,21 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
         c->g_refine = refine_on;
         c->g_lds = pr.lds;
     }
-    rc = upload_batch(c, pr, stream);
+    // The graph fetches its tables from its own pinned buffer.  Unchanged
+    // tables are left in place; otherwise wait until the previous replay of
+    // this graph has fetched them before overwriting.
+    Pinned& gp = c->gpin[c->g_next];
+    if (!(gp.used == pr.blob.size() && memcmp(gp.p, pr.blob.data(), pr.blob.size()) == 0)) {
+        if (gp.pending) FL_HIP(hipEventSynchronize(gp.done));
+        gp.pending = false;
+        memcpy(gp.p, pr.blob.data(), pr.blob.size());
+        gp.used = pr.blob.size();
+    }
+    rc = next_epoch(c, stream);
     if (rc) return rc;
     FL_HIP(hipGraphLaunch(c->gexec[c->g_next], stream));
+    FL_HIP(hipEventRecord(gp.done, stream));
+    gp.pending = true;
     c->g_next ^= 1;
     return FL_OK;
 }

@@ -90,7 +90,7 @@ struct alignas(16) BatchHdr {
     int32_t gate;               // 1: point distance invariance given (octave gate on)
     int32_t dense;
     int32_t stats;              // 1: count visible / cells / keypoints / candidates
-    uint32_t epoch;             // tag of this launch's ADD claims (decreases per launch)
+    uint32_t pad_epoch;
     int32_t lds_hash_mask;      // owner hash capacity - 1 in the LDS modes
     int32_t n_wg;               // workgroups of the search launch
     int32_t refine_iters;
@@ -128,6 +128,7 @@ struct alignas(16) BatchHdr {
     int32_t* cell_kp;           // global-grid mode: [n_kp_total]
     int32_t* hash;              // global-grid mode: owner hash tables
     unsigned long long* claim;  // [n_kp_total] (epoch << 32 | lowest claiming point)
+    const uint32_t* epoch;      // tag of this launch's claims, decremented by the table fetch
     uint32_t* kf_ctr;           // [n_kf * kKfCtrs]
     uint32_t* ev_ctr;           // [n_events * kEvCtrs]
     AddRef* add_list;           // per-keyframe regions

@@ -29,15 +29,24 @@ struct Sim3d {
     double s;
 };
 
+// 1 / (i + 1), i < 72
+struct RecipTable {
+    double v[72];
+    constexpr RecipTable() : v() {
+        for (int i = 0; i < 72; ++i) v[i] = 1.0 / (double)(i + 1);
+    }
+};
+__device__ constexpr RecipTable kRecip{};
+
 __device__ inline double exp_moment(int n, double s) {
-    // I_n(s) = integral_0^1 e^{s tau} tau^n d tau
+    // I_n(s) = integral_0^1 e^{s tau} tau^n d tau = sum_k s^k / (k! (n + k + 1))
     if (fabs(s) < 2.0) {
         double term = 1.0, sum = 0.0;
         for (int k = 0; k < 60; ++k) {
-            const double c = term / (double)(n + k + 1);
+            const double c = term * kRecip.v[n + k];
             sum += c;
             if (fabs(c) < 1e-18 * fabs(sum)) break;
-            term *= s / (double)(k + 1);
+            term *= s * kRecip.v[k];
         }
         return sum;
     }
@@ -57,8 +66,8 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     const double th = sqrt(th2);
     double a, b;
     if (th < 1e-4) {
-        a = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-        b = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        a = 1.0 - th2 * (1.0 / 6.0) + th2 * th2 * (1.0 / 120.0);
+        b = 0.5 - th2 * (1.0 / 24.0) + th2 * th2 * (1.0 / 720.0);
     } else {
         a = sin(th) / th;
         b = (1.0 - cos(th)) / th2;
@@ -66,8 +75,10 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     const double c0 = exp_moment(0, sig);
     double c1, c2;
     if (th < 1e-2) {
-        c1 = exp_moment(1, sig) - th2 / 6.0 * exp_moment(3, sig) + th2 * th2 / 120.0 * exp_moment(5, sig);
-        c2 = 0.5 * exp_moment(2, sig) - th2 / 24.0 * exp_moment(4, sig) + th2 * th2 / 720.0 * exp_moment(6, sig);
+        c1 = exp_moment(1, sig) - th2 * (1.0 / 6.0) * exp_moment(3, sig) +
+             th2 * th2 * (1.0 / 120.0) * exp_moment(5, sig);
+        c2 = 0.5 * exp_moment(2, sig) - th2 * (1.0 / 24.0) * exp_moment(4, sig) +
+             th2 * th2 * (1.0 / 720.0) * exp_moment(6, sig);
     } else {
         const double es = exp(sig);
         const double den = sig * sig + th2;
@@ -148,23 +159,24 @@ __device__ inline bool solve7(const double* g, const double* Hu, double lambda, 
             return false;
         }
         const double ljj = sqrt(s);
-        L[8 * j] = ljj;
+        const double inv = 1.0 / ljj;
+        L[8 * j] = inv;   // the diagonal keeps the reciprocal pivot
         for (int i = j + 1; i < 7; ++i) {
             double v = L[7 * i + j];
             for (int m = 0; m < j; ++m) v -= L[7 * i + m] * L[7 * j + m];
-            L[7 * i + j] = v / ljj;
+            L[7 * i + j] = v * inv;
         }
     }
     double y[7];
     for (int i = 0; i < 7; ++i) {
         double v = -g[i];
         for (int m = 0; m < i; ++m) v -= L[7 * i + m] * y[m];
-        y[i] = v / L[8 * i];
+        y[i] = v * L[8 * i];
     }
     for (int i = 6; i >= 0; --i) {
         double v = y[i];
         for (int m = i + 1; m < 7; ++m) v -= L[7 * m + i] * d[m];
-        d[i] = v / L[8 * i];
+        d[i] = v * L[8 * i];
     }
     return true;
 }
@@ -250,27 +262,40 @@ __device__ __forceinline__ void accumulate(const PairTerm& t, double* acc) {
         for (int j = i; j < 7; ++j) acc[k++] += w * (J0[i] * J0[j] + J1[i] * J1[j]);
 }
 
-// Block reduction of NV doubles per thread (fixed order).  Result valid in
-// s_out[0..NV) after the call.
+// Block reduction of NV <= 64 doubles per thread, fixed order.  Inside a
+// wave a butterfly reduce-scatter halves the values a lane carries at every
+// step (63 exchanges for any NV instead of 6 * NV), leaving the wave total of
+// value l in lane l; the block then adds the wave totals in wave order.
+// Result in s_out[0..NV) after the call.
 template <int NV>
 __device__ __forceinline__ void block_reduce(double* v, double* s_red, double* s_out) {
+    static_assert(NV <= 64, "at most 64 values");
     const int lane = wave_lane();
     const int wid = threadIdx.x / kWave;
     const int nw = blockDim.x / kWave;
+    double w[32];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double x = v[i];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-        v[i] = x;
+    for (int i = 0; i < 32; ++i) {
+        const double lo = i < NV ? v[i] : 0.0;
+        const double hi = i + 32 < NV ? v[i + 32] : 0.0;
+        const bool up = (lane & 32) != 0;
+        const double send = up ? lo : hi;
+        w[i] = (up ? hi : lo) + __shfl_xor(send, 32);
     }
-    if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) s_red[wid * NV + i] = v[i];
+    for (int h = 16; h >= 1; h >>= 1) {
+        const bool up = (lane & h) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const double send = up ? w[i] : w[i + h];
+            w[i] = (up ? w[i + h] : w[i]) + __shfl_xor(send, h);
+        }
     }
+    if (lane < NV) s_red[wid * NV + lane] = w[0];
     __syncthreads();
     if ((int)threadIdx.x < NV) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += s_red[w * NV + threadIdx.x];
+        for (int q = 0; q < nw; ++q) s += s_red[q * NV + threadIdx.x];
         s_out[threadIdx.x] = s;
     }
     __syncthreads();

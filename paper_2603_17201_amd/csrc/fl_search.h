@@ -16,6 +16,7 @@ namespace fl {
 
 constexpr uint8_t kDecUndecided = 0xFF;
 constexpr int kSearchBlock = 1024;   // threads of a batched-search workgroup (16 waves)
+constexpr int kWavesPerWG = kSearchBlock / 64;
 
 struct SearchConst {
     float sf[32];
@@ -249,6 +250,18 @@ __global__ __launch_bounds__(kPrepBlock) void grid_single_kernel(KfDesc kd, int 
 }
 
 // ---------------------------------------------------------------------------
+// Per-call tables are fetched by the device from pinned host memory (a plain
+// copy kernel, in stream order with the kernels that read them).
+
+// It also advances the claim epoch of the launch that follows (counting
+// down, so claims of earlier launches always compare larger).
+__global__ __launch_bounds__(256) void fetch_blob_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                       int n16, uint32_t* __restrict__ epoch) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x) dst[i] = src[i];
+    if (epoch && blockIdx.x == 0 && threadIdx.x == 0) *epoch = *epoch - 1u;
+}
+
+// ---------------------------------------------------------------------------
 // Wave-aggregated append to a bounded list: one atomic per wave.
 
 template <typename T>
@@ -309,6 +322,8 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     int32_t* s_hash = nullptr;
     int32_t* s_tmp = nullptr;
     int32_t* s_flag = reinterpret_cast<int32_t*>(s_mem);
+    __shared__ uint32_t s_cnt[2 * PPL * kWavesPerWG + 2];   // per-wave list counts, then the two bases
+    const int wid = tid / kWave;
     if (MODE != kModeGlobal) {
         unsigned char* p = s_mem + 16 * (size_t)h.lds_kp_cap;
         if (MODE == kModeLdsDesc) {
@@ -329,7 +344,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     const float ratio = h.nn_ratio, r0w = h.r0;
     const bool dense = h.dense != 0;
     const bool want_matches = h.refine_iters > 0;
-    const unsigned long long tag = (unsigned long long)h.epoch << 32;
+    const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
     unsigned long long st_vis = 0, st_cells = 0, st_kp = 0, st_cand = 0;
 
     const int2 range = h.wg_range[blockIdx.x];
@@ -348,6 +363,43 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         const int k = h.kf_order[slot];
         const KfDesc kd = h.kf[k];            // by value: kept in registers across the stores below
         const EventDesc ed = h.ev[kd.event];
+        const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
+        const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
+
+        // Point loads of every pair of this thread are issued first, so their
+        // latency overlaps the keyframe staging below.
+        uint8_t dec[PPL];
+        int32_t gp[PPL], id[PPL];
+        float px[PPL], py[PPL], pz[PPL], pdm[PPL];
+        uint4 a0[PPL], a1[PPL];
+        bool add_want[PPL], acc_want[PPL];
+        int32_t add_kp[PPL];
+        float acc_u[PPL], acc_v[PPL];
+#pragma unroll
+        for (int r = 0; r < PPL; ++r) {
+            const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
+            dec[r] = o < pe ? kDecUndecided : (uint8_t)0;
+            gp[r] = 0;
+            id[r] = -1;
+            px[r] = py[r] = pz[r] = pdm[r] = 0.0f;
+            a0[r] = a1[r] = make_uint4(0, 0, 0, 0);
+            if (o < pe) {
+                const int64_t j = o - kd.pair_off;
+                const int32_t lp = dense ? (int32_t)j : h.pair_mp[o];
+                if (lp < 0 || lp >= kd.n_mp) {
+                    dec[r] = FL_INVALID;
+                } else {
+                    gp[r] = kd.mp_off + lp;
+                    id[r] = h.mp_id ? h.mp_id[gp[r]] : gp[r];
+                    px[r] = h.mp_xyz[3 * (int64_t)gp[r]];
+                    py[r] = h.mp_xyz[3 * (int64_t)gp[r] + 1];
+                    pz[r] = h.mp_xyz[3 * (int64_t)gp[r] + 2];
+                    if (gate) pdm[r] = h.mp_dmax[gp[r]];
+                    load_desc(h.mp_desc, gp[r], a0[r], a1[r]);
+                }
+            }
+        }
+
         KfView v;
         if (MODE == kModeGlobal) {
             v.cs = h.cell_start + kd.grid_off;
@@ -369,37 +421,18 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             v.hash = s_hash;
             v.hash_mask = h.lds_hash_mask;
         }
-        const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
-        const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
 
 #pragma unroll
         for (int r = 0; r < PPL; ++r) {
             const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
             const bool active = o < pe;
-            uint8_t dec = active ? kDecUndecided : (uint8_t)0;
-            int32_t gp = 0, id = -1;
-            float x = 0.0f, y = 0.0f, z = 0.0f, dmax = 0.0f;
-            if (active) {
-                const int64_t j = o - kd.pair_off;
-                const int32_t lp = dense ? (int32_t)j : h.pair_mp[o];
-                if (lp < 0 || lp >= kd.n_mp) {
-                    dec = FL_INVALID;
-                } else {
-                    gp = kd.mp_off + lp;
-                    id = h.mp_id ? h.mp_id[gp] : gp;
-                    x = h.mp_xyz[3 * (int64_t)gp];
-                    y = h.mp_xyz[3 * (int64_t)gp + 1];
-                    z = h.mp_xyz[3 * (int64_t)gp + 2];
-                    if (gate) dmax = h.mp_dmax[gp];
-                }
-            }
             // owner probe: a point already observed in this keyframe is skipped
-            if (dec == kDecUndecided && id >= 0) {
-                uint32_t hh = owner_slot(id, v.hash_mask);
+            if (dec[r] == kDecUndecided && id[r] >= 0) {
+                uint32_t hh = owner_slot(id[r], v.hash_mask);
                 for (int probe = 0; probe <= v.hash_mask; ++probe) {
                     const int32_t hv = v.hash[hh];
-                    if (hv == id) {
-                        dec = FL_SKIP;
+                    if (hv == id[r]) {
+                        dec[r] = FL_SKIP;
                         break;
                     }
                     if (hv < 0) break;
@@ -410,14 +443,12 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             best.init();
             int32_t target = -1;
             float ku = 0.0f, kv = 0.0f;
-            if (dec == kDecUndecided) {
+            if (dec[r] == kDecUndecided) {
                 Proj p;
-                if (!project(kd, x, y, z, dmax, gate, sf, N, p)) {
-                    dec = FL_NOT_VISIBLE;
+                if (!project(kd, px[r], py[r], pz[r], pdm[r], gate, sf, N, p)) {
+                    dec[r] = FL_NOT_VISIBLE;
                 } else {
                     if (STATS) ++st_vis;
-                    uint4 a0, a1;
-                    load_desc(h.mp_desc, gp, a0, a1);
                     const Window w = make_window(p, kd, sf, r0w, C, R);
                     for (int row = w.r0; row <= w.r1; ++row) {
                         const int s = v.cs[row * C + w.c0];
@@ -438,7 +469,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                                 b1 = v.desc[2 * i + 1];
                             }
                             const uint32_t before = best.key;
-                            best.offer(hamming(a0, a1, b0, b1), rc.idx);
+                            best.offer(hamming(a0[r], a1[r], b0, b1), rc.idx);
                             if (best.key != before) {
                                 ku = rc.x;
                                 kv = rc.y;
@@ -446,14 +477,14 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                         }
                     }
                     if (!accept_match(best, th, ratio)) {
-                        dec = FL_NO_MATCH;
+                        dec[r] = FL_NO_MATCH;
                     } else {
                         const int32_t ow = h.kp_owner[kd.kp_off + (int32_t)(best.key & 0xFFFFu)];
                         if (ow >= 0) {
-                            dec = FL_FUSE;
+                            dec[r] = FL_FUSE;
                             target = ow;
                         } else {
-                            dec = FL_ADD;   // provisional; losers are relabelled by the resolver
+                            dec[r] = FL_ADD;   // provisional; losers are relabelled by the resolver
                         }
                     }
                 }
@@ -464,29 +495,76 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 h.best_idx[o] = bidx;
                 h.best_dist[o] = (int16_t)(best.key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(best.key >> 16));
                 h.second_dist[o] = (int16_t)best.second;
-                h.decision[o] = dec;
+                h.decision[o] = dec[r];
                 h.target[o] = target;
             }
-            const bool is_add = active && dec == FL_ADD;
-            if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp);
-            AddRef ae;
-            ae.pair = (int32_t)o;
-            ae.kp = kpg;
-            ae.gp = gp;
-            ae.pad = 0;
-            wave_append(is_add, &h.kf_ctr[k * kKfCtrs + kKfAdd], h.add_list + kd.add_off, kd.add_cap, ae);
-            if (want_matches) {
-                const bool acc = active && (dec == FL_ADD || dec == FL_FUSE);
-                MatchRec me;
-                me.x = x;
-                me.y = y;
-                me.z = z;
-                me.u = ku;
-                me.v = kv;
-                me.kf = k;
-                me.pad0 = me.pad1 = 0;
-                wave_append(acc, &h.ev_ctr[kd.event * kEvCtrs + kEvMatch], h.match_list + ed.list_off,
-                            ed.list_cap, me);
+            const bool is_add = active && dec[r] == FL_ADD;
+            if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp[r]);
+            // list entries are written after the tile with one atomic per list
+            add_want[r] = is_add;
+            add_kp[r] = kpg;
+            acc_want[r] = want_matches && active && (dec[r] == FL_ADD || dec[r] == FL_FUSE);
+            acc_u[r] = ku;
+            acc_v[r] = kv;
+            const unsigned long long ma = __ballot(add_want[r]);
+            const unsigned long long mm = __ballot(acc_want[r]);
+            if (lane == 0) {
+                s_cnt[(2 * r) * kWavesPerWG + wid] = (uint32_t)__popcll(ma);
+                s_cnt[(2 * r + 1) * kWavesPerWG + wid] = (uint32_t)__popcll(mm);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run_a = 0, run_m = 0;
+            for (int r = 0; r < PPL; ++r)
+                for (int w = 0; w < kWavesPerWG; ++w) {
+                    uint32_t& ca = s_cnt[(2 * r) * kWavesPerWG + w];
+                    uint32_t& cm = s_cnt[(2 * r + 1) * kWavesPerWG + w];
+                    const uint32_t a = ca, m = cm;
+                    ca = run_a;
+                    cm = run_m;
+                    run_a += a;
+                    run_m += m;
+                }
+            s_cnt[2 * PPL * kWavesPerWG] = run_a ? atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfAdd], run_a) : 0u;
+            s_cnt[2 * PPL * kWavesPerWG + 1] =
+                run_m ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], run_m) : 0u;
+        }
+        __syncthreads();
+        {
+            const uint32_t base_a = s_cnt[2 * PPL * kWavesPerWG], base_m = s_cnt[2 * PPL * kWavesPerWG + 1];
+            const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+            for (int r = 0; r < PPL; ++r) {
+                const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
+                const unsigned long long ma = __ballot(add_want[r]);
+                const unsigned long long mm = __ballot(acc_want[r]);
+                if (add_want[r]) {
+                    const uint32_t idx = base_a + s_cnt[(2 * r) * kWavesPerWG + wid] + (uint32_t)__popcll(ma & below);
+                    if (idx < (uint32_t)kd.add_cap) {
+                        AddRef ae;
+                        ae.pair = (int32_t)o;
+                        ae.kp = add_kp[r];
+                        ae.gp = gp[r];
+                        ae.pad = 0;
+                        h.add_list[kd.add_off + idx] = ae;
+                    }
+                }
+                if (acc_want[r]) {
+                    const uint32_t idx =
+                        base_m + s_cnt[(2 * r + 1) * kWavesPerWG + wid] + (uint32_t)__popcll(mm & below);
+                    if (idx < (uint32_t)ed.list_cap) {
+                        MatchRec me;
+                        me.x = px[r];
+                        me.y = py[r];
+                        me.z = pz[r];
+                        me.u = acc_u[r];
+                        me.v = acc_v[r];
+                        me.kf = k;
+                        me.pad0 = me.pad1 = 0;
+                        h.match_list[ed.list_off + idx] = me;
+                    }
+                }
             }
         }
 
