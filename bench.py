@@ -11,12 +11,17 @@ on the accepted pairs.  Inputs are resident in HBM before timing starts.
             followed by a copy of its results to the host and a stream sync;
             then each refinement step as its own call, copy and sync)
 
-Prints one JSON line.  Workload (default): a loop event of 20 keyframes
+Prints one JSON line.  Headline workload: a loop event of 20 keyframes
 (752x480, 1,200 keypoints each) and 15,000 map points, 300,000 dense pairs.
+Secondary workloads (skipped with --quick): the uneven 60-keyframe event
+with sparse covisibility pairs, ten of them in one launch, the residual
+forward/backward on 50,000 pairs, and a stream of uneven events.
 """
 from __future__ import annotations
 
 import argparse
+import gc
+import hashlib
 import json
 import os
 import statistics
@@ -30,24 +35,41 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+FP64_PEAK_TFLOPS = 78.6                   # vector FP64
 GN_ITERS = 10
 HUBER = 2.45
+# per accepted pair and Gauss-Newton step: 7 gradient + 28 Hessian entries,
+# each w * (a*b + c*d) accumulated (5 FP64 flops), plus the match count
+REFINE_F64_PER_PAIR = 35 * 5 + 1
+REFINE_BYTES_PER_PAIR = 32   # one accepted-pair record read (then kept in registers)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_fused_kernel.loop_event_20kf.pmc.json")
+KERNEL_SOURCES = ("paper_2603_17201_amd/csrc/fl_search.h", "paper_2603_17201_amd/csrc/fl_internal.h")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def sources_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def search_bytes(ev, params, n_pairs):
     """Algorithmic bytes of one search-kernel launch: every point's xyz,
     descriptor, distance invariance and id once (52 B), every keypoint's
     cell-ordered record and descriptor and owner once (52 B), every grid
-    and owner-table entry once, every pair's 13 bytes of outputs once."""
+    and owner-table entry once, every pair's 13 bytes of outputs once (and
+    its 4-byte point index when pairs are sparse)."""
     cells = params.grid_cols * params.grid_rows
     n_kp = np.diff(ev.kp_offset)
     hash_bytes = 4 * sum(max(16, 1 << int(np.ceil(np.log2(max(2 * int(k), 1))))) for k in n_kp)
+    sparse = 0 if getattr(ev, "pair_mp", None) is None else 4 * n_pairs
     return (52 * ev.n_mp + 52 * int(ev.kp_offset[-1]) + 4 * (cells + 1) * ev.n_kf + hash_bytes
-            + 13 * n_pairs)
+            + 13 * n_pairs + sparse)
 
 
 def search_ops(st, n_pairs):
@@ -58,6 +80,18 @@ def search_ops(st, n_pairs):
     20 per descriptor comparison (8 xor + 8 popcount-accumulate + key/min)."""
     return (25 * n_pairs + 40 * st["n_visible"] + 6 * st["n_cells"] + 8 * st["n_kp_scanned"]
             + 20 * st["n_cand"])
+
+
+def sim3_error(S, S_ref):
+    """Rotation angle (deg), translation (m) and |log scale| of S o S_ref^-1
+    for 13-double Sim3s [R (9), t (3), s]."""
+    R, t, s = S[:9].reshape(3, 3), S[9:12], S[12]
+    R0, t0, s0 = S_ref[:9].reshape(3, 3), S_ref[9:12], S_ref[12]
+    Re = R @ R0.T
+    se = s / s0
+    te = t - se * (Re @ t0)
+    ang = np.degrees(np.arccos(np.clip((np.trace(Re) - 1.0) / 2.0, -1.0, 1.0)))
+    return float(ang), float(np.linalg.norm(te)), float(abs(np.log(se)))
 
 
 def cpu_baseline(ev, budget_s=12.0):
@@ -82,12 +116,331 @@ def cpu_baseline(ev, budget_s=12.0):
     return n, el
 
 
+class Bench:
+    def __init__(self, args):
+        import torch
+        import paper_2603_17201_amd as fl
+        self.torch, self.fl, self.args = torch, fl, args
+        self.dev = torch.device("cuda:0")
+        self.ctx = fl.Context(0)
+        self.stream = torch.cuda.current_stream(self.dev)
+
+    # -- helpers -------------------------------------------------------------
+    def events_time(self, fn, steps, warmup):
+        """Device time per call: HIP events on the launch stream around
+        `steps` back-to-back calls, after `warmup` calls; ms."""
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for _ in range(steps):
+            fn()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def host_buffers(self, n_pairs, n_events=1):
+        torch = self.torch
+        return ({k: torch.empty(n_pairs, dtype=dt, pin_memory=True) for k, dt in
+                 (("best_idx", torch.int32), ("best_dist", torch.int16), ("second_dist", torch.int16),
+                  ("decision", torch.uint8), ("target", torch.int32))},
+                torch.empty((n_events, 13), dtype=torch.float64, pin_memory=True))
+
+    def plain_plan(self, ev, b, out):
+        """Per-keyframe arguments of the plain path.  Sparse pairs get their
+        points gathered per keyframe once, before timing (the plain path
+        then searches exactly the keyframe's pairs)."""
+        torch, fl = self.torch, self.fl
+        plan = []
+        sparse = getattr(ev, "pair_mp", None) is not None
+        ekf = getattr(ev, "event_kf_offset", np.array([0, ev.n_kf]))
+        emp = getattr(ev, "event_mp_offset", np.array([0, ev.n_mp]))
+        for e in range(len(ekf) - 1):
+            for k in range(int(ekf[e]), int(ekf[e + 1])):
+                a, c = int(ev.kp_offset[k]), int(ev.kp_offset[k + 1])
+                p0, p1 = int(ev.pair_offset[k]), int(ev.pair_offset[k + 1])
+                if sparse:
+                    idx = torch.from_numpy(np.asarray(ev.pair_mp[p0:p1], np.int64) + int(emp[e])).to(self.dev)
+                    pts = (b.mp_xyz[idx].contiguous(), b.mp_desc[idx].contiguous(), b.mp_dmax[idx].contiguous(),
+                           b.mp_id[idx].contiguous())
+                else:
+                    m0, m1 = int(emp[e]), int(emp[e + 1])
+                    pts = (b.mp_xyz[m0:m1], b.mp_desc[m0:m1], b.mp_dmax[m0:m1], b.mp_id[m0:m1])
+                o = fl.FuseOutputs(out.best_idx[p0:p1], out.best_dist[p0:p1], out.second_dist[p0:p1],
+                                   out.decision[p0:p1], out.target[p0:p1])
+                plan.append((pts, (b.kp_xy[a:c], b.kp_oct[a:c], b.kp_desc[a:c], b.kp_owner[a:c]), o, p0, p1,
+                             ev.kf_sim3[k], ev.cams[k]))
+        return plan
+
+    def plain_event(self, plan, b, out, P, S, S_init, host, host_S):
+        """One event through the plain path; wall ms."""
+        ctx, stream = self.ctx, self.stream
+        t0 = time.perf_counter()
+        for pts, kps, o, p0, p1, sim3, cam in plan:
+            ctx.search_fuse(*pts, *kps, sim3, cam, P, out=o)
+            for name, h in host.items():
+                h[p0:p1].copy_(getattr(o, name), non_blocking=True)
+            stream.synchronize()
+        S.copy_(S_init)
+        for _ in range(GN_ITERS):
+            ctx.refine_events(b, out, (1, HUBER, S, None, None))
+            host_S.copy_(S, non_blocking=True)
+            stream.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    def copy_probe(self):
+        """A plain device copy of 256 MiB: the reference kernel for scaling
+        the HBM byte counters."""
+        torch = self.torch
+        x = torch.empty(64 << 20, dtype=torch.float32, device=self.dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    def traffic(self):
+        """HBM bytes per launch of the search kernel from the committed
+        counter summary, or None when the kernel sources changed since."""
+        try:
+            with open(TRAFFIC_FILE) as fh:
+                d = json.load(fh)
+        except (OSError, ValueError):
+            return None
+        if d.get("sources_sha256_16") != sources_hash():
+            return None
+        return d.get("bytes_per_launch")
+
+    # -- workloads -------------------------------------------------------------
+    def headline(self):
+        import synth
+        torch, fl, ctx, args = self.torch, self.fl, self.ctx, self.args
+        log("generating the loop event (20 keyframes x 1,200 keypoints, 15,000 points)")
+        ev = synth.gen_c2()
+        P = ev.params
+        b = fl.DeviceBatch(ev, device=self.dev)
+        n_pairs = b.n_pairs
+        out = fl.FuseOutputs.empty(n_pairs, self.dev)
+
+        tuning = None
+        if not args.no_autotune:
+            t, ms = ctx.autotune(b, P, out, reps=3)
+            tuning = dict(pairs_per_lane=t[0], lds_mode=t[1], wg_per_cu=t[2], xcd_aware=t[3])
+            log(f"autotune: {tuning} ({ms * 1e3:.1f} us per eager batched search)")
+
+        # exact per-class counters of this workload (one untimed counting launch)
+        ctx.set_stats(True)
+        ctx.search_fuse_batched(b, P, out)
+        torch.cuda.synchronize()
+        st = ctx.get_stats()
+        ctx.set_stats(False)
+
+        S_init = torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(self.dev)
+        S = S_init.clone()
+        n_matched = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        host, host_S = self.host_buffers(n_pairs)
+
+        gc.collect()
+        gc.disable()   # a full collection inside a ~100 us step would be timed as GPU work
+        # kernel times: eager search + refinement, HIP events around each kernel
+        ctx.set_profiling(True)
+        for _ in range(args.steps):
+            S.copy_(S_init)
+            ctx.search_fuse_batched(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched))
+        ks_ms, ks_n = ctx.get_profile("search")
+        kr_ms, kr_n = ctx.get_profile("refine")
+        ctx.set_profiling(False)
+        ks_ms /= max(ks_n, 1)
+        kr_ms /= max(kr_n, 1)
+        n_acc = int(n_matched.item())
+
+        plain = None
+        if not args.no_plain:
+            log(f"plain: {args.plain_steps} events, per-keyframe calls with copy + sync")
+            plan = self.plain_plan(ev, b, out)
+            times = [self.plain_event(plan, b, out, P, S, S_init, host, host_S)
+                     for _ in range(2 + args.plain_steps)][2:]
+            ms_plain = statistics.median(times)
+            plain = dict(ms_per_event=ms_plain, pairs_per_s=n_pairs / (ms_plain * 1e-3),
+                         p99_ms=float(np.percentile(times, 99)))
+            log(f"plain: {ms_plain:.3f} ms per event")
+
+        def step():
+            # the refinement continues from the previous step's Sim3: the same
+            # ten Gauss-Newton steps of work on every step
+            ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched))
+
+        log(f"batched: warmup {args.warmup}, timing {args.steps} steps")
+        ms_step = self.events_time(step, args.steps, args.warmup)
+        log(f"batched: {ms_step * 1e3:.1f} us per event (device-resident)")
+
+        e2e = []
+        for i in range(args.warmup + args.steps):
+            t0 = time.perf_counter()
+            step()
+            for k, h in host.items():
+                h.copy_(getattr(out, k), non_blocking=True)
+            host_S.copy_(S, non_blocking=True)
+            self.stream.synchronize()
+            if i >= args.warmup:
+                e2e.append((time.perf_counter() - t0) * 1e3)
+        ms_e2e = statistics.median(e2e)
+        gc.enable()
+
+        # rooflines of both kernels; the one with the larger time leads
+        nbytes = search_bytes(ev, P, n_pairs)
+        nops = search_ops(st, n_pairs)
+        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+        t_alu = nops / (ALU_PEAK_TOPS * 1e12)
+        if t_alu > t_hbm:
+            rs = dict(bound="alu", achieved=nops / (ks_ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
+        else:
+            rs = dict(bound="hbm", achieved=nbytes / (ks_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+        rs.update(frac=rs["achieved"] / rs["peak"], traffic=self.traffic(), kernel="search_fused_kernel",
+                  kernel_us=ks_ms * 1e3, alg_bytes=nbytes, alg_ops=nops, roofline_us=max(t_hbm, t_alu) * 1e6)
+        rflops = REFINE_F64_PER_PAIR * n_acc * GN_ITERS
+        t_f = rflops / (FP64_PEAK_TFLOPS * 1e12)
+        rr = dict(bound="alu", achieved=rflops / (kr_ms * 1e-3) / 1e12, peak=FP64_PEAK_TFLOPS,
+                  unit="TFLOP/s", traffic=None, kernel="refine_kernel", kernel_us=kr_ms * 1e3,
+                  alg_flops=rflops, alg_bytes=REFINE_BYTES_PER_PAIR * n_acc, roofline_us=t_f * 1e6,
+                  note="fp64; ten dependent steps, each one cross-CU exchange and one 7x7 solve: latency bound")
+        rr["frac"] = rr["achieved"] / rr["peak"]
+        roof, other = (rr, rs) if kr_ms > ks_ms else (rs, rr)
+        log(f"kernels: search {ks_ms * 1e3:.1f} us, refine {kr_ms * 1e3:.1f} us ({n_acc} accepted pairs)")
+        return dict(ev=ev, n_pairs=n_pairs, ms_step=ms_step, ms_e2e=ms_e2e, plain=plain, tuning=tuning,
+                    roof=roof, other=other, n_acc=n_acc)
+
+    def batch_graph(self, ev, label, steps):
+        """Graph launches (search + refinement) of one batch, device-resident,
+        and the plain path for a single event."""
+        fl, torch, ctx = self.fl, self.torch, self.ctx
+        P = ev.params
+        b = fl.DeviceBatch(ev, device=self.dev)
+        out = fl.FuseOutputs.empty(b.n_pairs, self.dev)
+        n_ev = b.n_events
+        S0 = np.asarray(ev.S_init if n_ev == 1 else ev.event_S_init).reshape(n_ev, 13)
+        S_init = torch.from_numpy(S0.copy()).to(self.dev)
+        S = S_init.clone()
+        gc.collect()
+        gc.disable()
+        ms = self.events_time(lambda: ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, None)),
+                              steps, 3)
+        res = dict(n_events=n_ev, n_kf=b.n_kf, n_pairs=b.n_pairs, ms_per_launch=ms, ms_per_event=ms / n_ev,
+                   pairs_per_s=b.n_pairs / (ms * 1e-3))
+        if n_ev == 1 and not self.args.no_plain:
+            host, host_S = self.host_buffers(b.n_pairs)
+            plan = self.plain_plan(ev, b, out)
+            times = [self.plain_event(plan, b, out, P, S, S_init, host, host_S) for _ in range(5)][2:]
+            res["plain_ms_per_event"] = statistics.median(times)
+            res["batched_vs_plain_device_resident"] = res["plain_ms_per_event"] / ms
+        gc.enable()
+        log(f"{label}: {ms * 1e3:.1f} us per launch ({n_ev} events, {b.n_pairs} pairs)")
+        return res
+
+    def residual(self):
+        import synth
+        torch, fl, ctx = self.torch, self.fl, self.ctx
+        d = synth.gen_c4()
+        S0 = d["S_eval"]
+        xyz = torch.from_numpy(d["xyz"]).to(self.dev)
+        uv = torch.from_numpy(d["uv"]).to(self.dev)
+        S32 = torch.from_numpy(d["S_eval_f32"]).to(self.dev)
+        gc.collect()
+        gc.disable()
+        f = self.events_time(lambda: ctx.residual_fwd(xyz, uv, None, None, S32, d["cam"], d["huber_delta"]), 50, 5)
+        bw = self.events_time(lambda: ctx.residual_bwd(xyz, uv, None, None, S32, d["cam"], d["huber_delta"]),
+                              50, 5)
+        S0t = torch.from_numpy(S0).to(self.dev)
+        xi = torch.zeros(7, dtype=torch.float64, device=self.dev, requires_grad=True)
+
+        def fb():
+            loss = fl.Sim3Residual.apply(xi, S0t, xyz, uv, None, None, d["cam"], d["huber_delta"], ctx)
+            loss.backward()
+        ab = self.events_time(fb, 20, 3)
+        gc.enable()
+        n = int(d["xyz"].shape[0])
+        log(f"residual: fwd {f * 1e3:.1f} us, bwd {bw * 1e3:.1f} us, autograd fwd+bwd {ab * 1e3:.1f} us")
+        return dict(n_pairs=n, fwd_us=f * 1e3, bwd_us=bw * 1e3, autograd_fwd_bwd_us=ab * 1e3,
+                    bwd_pairs_per_s=n / (bw * 1e-3))
+
+    def stream_events(self, n_events):
+        """The stream of uneven loop events: each event resident, one graph
+        launch (search + 10 GN steps) per event, back to back."""
+        import synth
+        torch, fl, ctx = self.torch, self.fl, self.ctx
+        log(f"stream: generating {n_events} uneven events")
+        evs = [synth.gen_c5_event(e) for e in range(n_events)]
+        bs = [fl.DeviceBatch(ev, device=self.dev) for ev in evs]
+        max_pairs = max(b.n_pairs for b in bs)
+        out = fl.FuseOutputs.empty(max_pairs, self.dev)
+        outs = [fl.FuseOutputs(out.best_idx[:b.n_pairs], out.best_dist[:b.n_pairs], out.second_dist[:b.n_pairs],
+                               out.decision[:b.n_pairs], out.target[:b.n_pairs]) for b in bs]
+        S_init = [torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(self.dev) for ev in evs]
+        S = [s.clone() for s in S_init]
+        nm = torch.zeros(n_events, dtype=torch.int32, device=self.dev)
+        P = evs[0].params
+
+        def launch(i):
+            ctx.search_fuse_graph(bs[i], P, outs[i], refine=(GN_ITERS, HUBER, S[i], None, nm[i:i + 1]))
+
+        gc.collect()
+        gc.disable()
+        for i in range(n_events):   # first pass: grows the workspace to the largest event, captures
+            launch(i)
+        torch.cuda.synchronize()
+        for i in range(n_events):
+            S[i].copy_(S_init[i])
+        torch.cuda.synchronize()
+        evts = [torch.cuda.Event(enable_timing=True) for _ in range(n_events + 1)]
+        t0 = time.perf_counter()
+        evts[0].record(self.stream)
+        for i in range(n_events):
+            launch(i)
+            evts[i + 1].record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = [evts[i].elapsed_time(evts[i + 1]) for i in range(n_events)]
+        total = int(sum(b.n_pairs for b in bs))
+        res = dict(n_events=n_events, total_pairs=total, events_per_s=n_events / wall, pairs_per_s=total / wall,
+                   p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)))
+        errs = np.array([sim3_error(S[i].cpu().numpy()[0], ev.S_true) for i, ev in enumerate(evs)])
+        res["final_rot_err_deg_median"] = float(np.median(errs[:, 0]))
+        res["final_trans_err_m_median"] = float(np.median(errs[:, 1]))
+        res["final_scale_err_median"] = float(np.median(errs[:, 2]))
+        init = np.array([sim3_error(ev.S_init, ev.S_true) for ev in evs])
+        res["init_rot_err_deg_median"] = float(np.median(init[:, 0]))
+        res["init_trans_err_m_median"] = float(np.median(init[:, 1]))
+        res["init_scale_err_median"] = float(np.median(init[:, 2]))
+        res["failed_events"] = int((nm < 0).sum().item())
+        if not self.args.no_plain:
+            n_plain = min(n_events, self.args.stream_plain_events)
+            ptimes = []
+            for i in range(n_plain):
+                host, host_S = self.host_buffers(bs[i].n_pairs)
+                plan = self.plain_plan(evs[i], bs[i], outs[i])
+                ptimes.append(self.plain_event(plan, bs[i], outs[i], P, S[i], S_init[i], host, host_S))
+            res["plain_events"] = n_plain
+            res["plain_p50_ms"] = float(np.percentile(ptimes, 50))
+            res["plain_p99_ms"] = float(np.percentile(ptimes, 99))
+            res["plain_events_per_s"] = n_plain / (sum(ptimes) * 1e-3)
+            res["batched_vs_plain_same_events"] = sum(ptimes) / sum(per[:n_plain])
+        gc.enable()
+        log(f"stream: {res['events_per_s']:.1f} events/s, p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms")
+        return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--stream-events", type=int, default=200)
+    ap.add_argument("--stream-plain-events", type=int, default=50)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -98,152 +451,53 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import paper_2603_17201_amd as fl
     import synth
+    bench = Bench(args)
+    if args.copy_probe:
+        bench.copy_probe()
+    h = bench.headline()
 
-    dev = torch.device("cuda:0")
-    log("generating the loop event (20 keyframes x 1,200 keypoints, 15,000 points)")
-    ev = synth.gen_c2()
-    P = ev.params
-    ctx = fl.Context(0)
-    b = fl.DeviceBatch(ev, device=dev)
-    n_pairs = b.n_pairs
-    out = fl.FuseOutputs.empty(n_pairs, dev)
-    stream = torch.cuda.current_stream(dev)
-
-    tuning = None
-    if not args.no_autotune:
-        t, ms = ctx.autotune(b, P, out, reps=3)
-        tuning = dict(pairs_per_lane=t[0], lds_mode=t[1], wg_per_cu=t[2], xcd_aware=t[3])
-        log(f"autotune: {tuning} ({ms * 1e3:.1f} us per eager batched search)")
-
-    # exact per-class counters of this workload (one untimed counting launch)
-    ctx.set_stats(True)
-    ctx.search_fuse_batched(b, P, out)
-    torch.cuda.synchronize()
-    st = ctx.get_stats()
-    ctx.set_stats(False)
-
-    S_init = torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(dev)
-    S = S_init.clone()
-    n_matched = torch.zeros(1, dtype=torch.int32, device=dev)
-
-    def step():
-        # the refinement continues from the previous step's Sim3: the same ten
-        # Gauss-Newton steps of work on every step
-        ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched))
-
-    log(f"batched: warmup {args.warmup}, timing {args.steps} steps")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
-    log(f"batched: {ms_step * 1e3:.1f} us per event (device-resident)")
-
-    # batched, results copied to the host and synchronised per event
-    host = {k: torch.empty(getattr(out, k).shape, dtype=getattr(out, k).dtype, pin_memory=True)
-            for k in ("best_idx", "best_dist", "second_dist", "decision", "target")}
-    host_S = torch.empty((1, 13), dtype=torch.float64, pin_memory=True)
-    e2e = []
-    for i in range(args.warmup + args.steps):
-        t0 = time.perf_counter()
-        step()
-        for k, h in host.items():
-            h.copy_(getattr(out, k), non_blocking=True)
-        host_S.copy_(S, non_blocking=True)
-        stream.synchronize()
-        if i >= args.warmup:
-            e2e.append((time.perf_counter() - t0) * 1e3)
-    ms_e2e = statistics.median(e2e)
-
-    # dominant kernel: search, timed with HIP events around each launch
-    ctx.set_profiling(True)
-    for _ in range(args.steps):
-        ctx.search_fuse_batched(b, P, out)
-    k_ms, k_n = ctx.get_profile()
-    ctx.set_profiling(False)
-    k_ms /= max(k_n, 1)
-    nbytes = search_bytes(ev, P, n_pairs)
-    nops = search_ops(st, n_pairs)
-    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-    t_alu = nops / (ALU_PEAK_TOPS * 1e12)
-    if t_alu > t_hbm:
-        roof = dict(bound="alu", achieved=nops / (k_ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
-    else:
-        roof = dict(bound="hbm", achieved=nbytes / (k_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = "search_fused_kernel"
-    roof["kernel_us"] = k_ms * 1e3
-    roof["alg_bytes"] = nbytes
-    roof["alg_ops"] = nops
-    log(f"search kernel: {k_ms * 1e3:.2f} us, {nbytes / 1e6:.2f} MB, {nops / 1e6:.1f} M ops")
-
-    plain = None
-    if not args.no_plain:
-        log(f"plain: {args.plain_steps} events, per-keyframe calls with copy + sync")
-        X, D, M, I = b.mp_xyz, b.mp_desc, b.mp_dmax, b.mp_id
-        kfs = []
-        for k in range(ev.n_kf):
-            a, c = int(ev.kp_offset[k]), int(ev.kp_offset[k + 1])
-            p0, p1 = int(ev.pair_offset[k]), int(ev.pair_offset[k + 1])
-            o = fl.FuseOutputs(out.best_idx[p0:p1], out.best_dist[p0:p1], out.second_dist[p0:p1],
-                               out.decision[p0:p1], out.target[p0:p1])
-            kfs.append((b.kp_xy[a:c], b.kp_oct[a:c], b.kp_desc[a:c], b.kp_owner[a:c], o, p0, p1))
-        times = []
-        for i in range(2 + args.plain_steps):
-            t0 = time.perf_counter()
-            for k, (kx, ko, kd, kw, o, p0, p1) in enumerate(kfs):
-                ctx.search_fuse(X, D, M, I, kx, ko, kd, kw, ev.kf_sim3[k], ev.cams[k], P, out=o)
-                for name, h in host.items():
-                    h[p0:p1].copy_(getattr(o, name), non_blocking=True)
-                stream.synchronize()
-            S.copy_(S_init)
-            for _ in range(GN_ITERS):
-                ctx.refine_events(b, out, (1, HUBER, S, None, None))
-                host_S.copy_(S, non_blocking=True)
-                stream.synchronize()
-            if i >= 2:
-                times.append((time.perf_counter() - t0) * 1e3)
-        ms_plain = statistics.median(times)
-        plain = dict(ms_per_event=ms_plain, pairs_per_s=n_pairs / (ms_plain * 1e-3),
-                     p99_ms=float(np.percentile(times, 99)))
-        log(f"plain: {ms_plain:.3f} ms per event")
+    secondary = None
+    if not args.quick:
+        secondary = {"uneven_event_60kf": bench.batch_graph(synth.gen_c3(), "uneven event", args.steps)}
+        evs = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
+               for i in range(10)]
+        B = synth.concat_events(evs)
+        B.event_S_init = np.stack([e.S_init for e in evs])
+        secondary["uneven_event_60kf_x10_one_launch"] = bench.batch_graph(B, "ten uneven events", 10)
+        secondary["residual_50k"] = bench.residual()
+        if args.stream_events > 0:
+            secondary["stream"] = bench.stream_events(args.stream_events)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle (brute-force search + float64 GN) on the same event")
-        n, el = cpu_baseline(ev)
-        cpu = dict(value=n * n_pairs / el, unit="pairs/s", cores=1, kind="oracle",
-                   sample=f"{n} full loop events of this workload ({n * n_pairs} pairs), "
+        n, el = cpu_baseline(h["ev"])
+        cpu = dict(value=n * h["n_pairs"] / el, unit="pairs/s", cores=1, kind="oracle",
+                   sample=f"{n} full loop events of this workload ({n * h['n_pairs']} pairs), "
                           f"single-threaded C oracle + NumPy float64 Gauss-Newton, {el:.1f} s",
                    ms_per_event=el / n * 1e3)
 
+    ev, plain = h["ev"], h["plain"]
     res = dict(
         metric="point-keyframe match candidates/s (batched loop event incl. 10 GN steps)",
-        value=n_pairs / (ms_step * 1e-3), unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
-        data="synthetic",
+        value=h["n_pairs"] / (h["ms_step"] * 1e-3), unit="pairs/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=h["ms_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32", data="synthetic",
         config=dict(workload="loop event: 20 keyframes 752x480 x 1,200 keypoints, 15,000 points, "
                              "300,000 dense pairs; search-and-fuse + 10 Gauss-Newton Sim3 steps",
-                    n_pairs=n_pairs, n_kf=ev.n_kf, n_mp=ev.n_mp, gn_iters=GN_ITERS, tuning=tuning),
-        ms_per_event_batched=ms_step, ms_per_event_batched_with_d2h=ms_e2e,
+                    n_pairs=h["n_pairs"], n_kf=ev.n_kf, n_mp=ev.n_mp, gn_iters=GN_ITERS, tuning=h["tuning"]),
+        ms_per_event_batched=h["ms_step"], ms_per_event_batched_with_d2h=h["ms_e2e"],
         plain=plain,
-        batched_vs_plain=(plain["ms_per_event"] / ms_e2e) if plain else None,
-        batched_vs_plain_device_resident=(plain["ms_per_event"] / ms_step) if plain else None,
-        matched_pairs=int(n_matched.item()),
-        roofline=roof,
+        batched_vs_plain=(plain["ms_per_event"] / h["ms_e2e"]) if plain else None,
+        batched_vs_plain_device_resident=(plain["ms_per_event"] / h["ms_step"]) if plain else None,
+        matched_pairs=h["n_acc"],
+        roofline=h["roof"],
+        roofline_other_kernel=h["other"],
         cpu_baseline=cpu,
+        secondary=secondary,
     )
-    ctx.close()
+    bench.ctx.close()
     print(json.dumps(res), flush=True)
 
 

@@ -183,19 +183,23 @@ int fl_search_fuse(fl_ctx* ctx, int32_t n_mp, const float* mp_xyz, const uint8_t
                    const fl_sim3* S /* host */, const fl_pinhole* K /* host */,
                    const fl_params* P /* host */, const fl_fuse_out* out /* host */, hipStream_t stream);
 
-/* Batched search-and-fuse over whole loop events (Sec. IV-D3: connected
- * keyframes evaluated concurrently on resident data): one upload of the
- * batch tables, a grid-build kernel over all keyframes, one persistent
- * search kernel over all pairs of all events, and a conflict-resolution
- * kernel.  Results are identical to fl_search_fuse applied per keyframe.
- * Errors: FL_EINVAL (inconsistent offsets or NULL arrays), FL_ERANGE. */
 /* Host-only check of a batch (every test fl_search_fuse_batched makes before
  * enqueuing anything; no device memory is touched, no context needed).
  * Returns FL_OK or the error code the batched call would return. */
 int fl_validate_batch(const fl_batch* B /* host */, const fl_params* P /* host */, const fl_fuse_out* out /* host */);
 
+/* Batched search-and-fuse over whole loop events (Sec. IV-D3: connected
+ * keyframes evaluated concurrently on resident data, Sec. IV-E: one transfer
+ * of compact tables): one upload of the batch tables and one fused kernel
+ * that stages each keyframe's grid in LDS, searches all pairs of all events
+ * and resolves the ADD conflicts of each keyframe.  Results are identical to
+ * fl_search_fuse applied per keyframe.  With refine non-NULL the search also
+ * records each event's accepted pairs and per-event Sim3 refinement follows
+ * on the same stream, as in fl_search_fuse_graph_launch.
+ * Errors: FL_EINVAL (inconsistent offsets or NULL arrays), FL_ERANGE. */
 int fl_search_fuse_batched(fl_ctx* ctx, const fl_batch* B /* host */, const fl_params* P /* host */,
-                           const fl_fuse_out* out /* host */, hipStream_t stream);
+                           const fl_fuse_out* out /* host */, const fl_refine* refine /* host, may be NULL */,
+                           hipStream_t stream);
 
 /* The same work as fl_search_fuse_batched, optionally followed by per-event
  * Sim3 refinement, replayed from a HIP graph captured on first use: one
@@ -272,13 +276,17 @@ int fl_autotune(fl_ctx* ctx, const fl_batch* B /* host */, const fl_params* P /*
 int fl_set_stats(fl_ctx* ctx, int enable);
 int fl_get_stats(fl_ctx* ctx, int64_t* out4 /* host [4] */);
 
-/* Kernel timing: when enabled, eager batched searches on this context record
- * a pair of HIP events around the search kernel on the launch stream;
- * fl_get_profile waits for the last of them and returns the summed kernel
- * time in milliseconds and the number of launches since profiling was
- * enabled (then clears them).  Graph launches are not timed. */
+/* Kernel timing: when enabled, eager calls on this context record a pair of
+ * HIP events on the launch stream around every search kernel
+ * (FL_PROF_SEARCH) and every refinement kernel (FL_PROF_REFINE).
+ * fl_get_profile waits for the last pair of the class `kernel` and returns
+ * its summed kernel time in milliseconds and its number of launches since
+ * profiling was enabled or the class was last read (then clears the class).
+ * Graph launches are not timed. */
+#define FL_PROF_SEARCH 0
+#define FL_PROF_REFINE 1
 int fl_set_profiling(fl_ctx* ctx, int enable);
-int fl_get_profile(fl_ctx* ctx, double* total_ms /* host */, int64_t* launches /* host */);
+int fl_get_profile(fl_ctx* ctx, int kernel, double* total_ms /* host */, int64_t* launches /* host */);
 
 /* Test hook: cap the provisional-ADD and matched-pair lists at `cap`
  * entries (0 restores the default) so that their overflow paths, full scans

@@ -66,6 +66,9 @@ class Tuning(ctypes.Structure):
 
 
 # (name, restype, argtypes) of every exported function
+PROF_SEARCH = 0   # FL_PROF_SEARCH
+PROF_REFINE = 1   # FL_PROF_REFINE
+
 SIGNATURES = [
     ("fl_create", c_int32, [ctypes.POINTER(c_void_p), c_int32]),
     ("fl_destroy", None, [c_void_p]),
@@ -78,7 +81,7 @@ SIGNATURES = [
                                  ctypes.POINTER(Params), ctypes.POINTER(FuseOut), c_void_p]),
     ("fl_validate_batch", c_int32, [ctypes.POINTER(Batch), ctypes.POINTER(Params), ctypes.POINTER(FuseOut)]),
     ("fl_search_fuse_batched", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Params),
-                                         ctypes.POINTER(FuseOut), c_void_p]),
+                                         ctypes.POINTER(FuseOut), ctypes.POINTER(Refine), c_void_p]),
     ("fl_search_fuse_graph_launch", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Params),
                                               ctypes.POINTER(FuseOut), ctypes.POINTER(Refine), c_void_p]),
     ("fl_refine_events", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(FuseOut),
@@ -98,7 +101,7 @@ SIGNATURES = [
     ("fl_set_stats", c_int32, [c_void_p, c_int32]),
     ("fl_get_stats", c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     ("fl_set_profiling", c_int32, [c_void_p, c_int32]),
-    ("fl_get_profile", c_int32, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]),
+    ("fl_get_profile", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]),
     ("fl_debug_set_list_cap", c_int32, [c_void_p, c_int32]),
 ]
 

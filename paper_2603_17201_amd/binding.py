@@ -92,13 +92,24 @@ class FuseOutputs:
                    torch.empty(n, dtype=torch.uint8, device=device),
                    torch.empty(n, dtype=torch.int32, device=device))
 
+    def __setattr__(self, name, value):
+        # rebinding an array drops the cached fl_fuse_out
+        object.__setattr__(self, "_struct", None)
+        object.__setattr__(self, name, value)
+
     def struct(self) -> FuseOut:
-        dev = self.best_idx.device
-        return FuseOut(_ptr(self.best_idx, torch.int32, "best_idx", device=dev),
-                       _ptr(self.best_dist, torch.int16, "best_dist", 2, dev),
-                       _ptr(self.second_dist, torch.int16, "second_dist", 2, dev),
-                       _ptr(self.decision, torch.uint8, "decision", 1, dev),
-                       _ptr(self.target, torch.int32, "target", device=dev))
+        """The fl_fuse_out of these arrays, built once and reused (a call
+        then allocates no Python objects for it)."""
+        st = self.__dict__.get("_struct")
+        if st is None:
+            dev = self.best_idx.device
+            st = FuseOut(_ptr(self.best_idx, torch.int32, "best_idx", device=dev),
+                         _ptr(self.best_dist, torch.int16, "best_dist", 2, dev),
+                         _ptr(self.second_dist, torch.int16, "second_dist", 2, dev),
+                         _ptr(self.decision, torch.uint8, "decision", 1, dev),
+                         _ptr(self.target, torch.int32, "target", device=dev))
+            object.__setattr__(self, "_struct", st)
+        return st
 
     def numpy(self) -> dict:
         return {k: getattr(self, k).cpu().numpy() for k in
@@ -152,7 +163,20 @@ class DeviceBatch:
         self.n_kp_total = int(self.h_kp_offset[-1])
         self.n_pairs = int(self.h_pair_offset[-1])
 
+    def __setattr__(self, name, value):
+        # rebinding an array drops the cached fl_batch structs
+        object.__setattr__(self, "_structs", {})
+        object.__setattr__(self, name, value)
+
     def struct(self, with_T: bool = True) -> Batch:
+        """The fl_batch of this batch, built once per with_T and reused."""
+        b = self.__dict__.get("_structs", {}).get(with_T)
+        if b is None:
+            b = self._make_struct(with_T)
+            self.__dict__.setdefault("_structs", {})[with_T] = b
+        return b
+
+    def _make_struct(self, with_T: bool) -> Batch:
         d = self.device
         b = Batch()
         b.n_events, b.n_kf, b.n_mp, b.n_kp_total, b.n_pairs = (self.n_events, self.n_kf, self.n_mp,
@@ -238,14 +262,17 @@ class Context:
         return out
 
     # -- batched search ----------------------------------------------------
-    def search_fuse_batched(self, batch: DeviceBatch, params, out: Optional[FuseOutputs] = None,
+    def search_fuse_batched(self, batch: DeviceBatch, params, out: Optional[FuseOutputs] = None, refine=None,
                             stream=None) -> FuseOutputs:
+        """refine: None or (n_iters, huber_delta, event_S, event_S32, n_matched)
+        as for search_fuse_graph."""
         if out is None:
             out = FuseOutputs.empty(batch.n_pairs, self.device)
         b = batch.struct()
         P = params_struct(params)
         o = out.struct()
-        _check(self._lib.fl_search_fuse_batched(self._h, ctypes.byref(b), ctypes.byref(P), ctypes.byref(o),
+        r, rp = self._refine_struct(batch, refine)
+        _check(self._lib.fl_search_fuse_batched(self._h, ctypes.byref(b), ctypes.byref(P), ctypes.byref(o), rp,
                                                 self._stream(stream)), "fl_search_fuse_batched")
         return out
 
@@ -360,10 +387,13 @@ class Context:
     def set_profiling(self, on: bool):
         _check(self._lib.fl_set_profiling(self._h, int(bool(on))), "fl_set_profiling")
 
-    def get_profile(self):
+    def get_profile(self, kernel: str = "search"):
+        """(summed ms, launches) of the eager kernels of class `kernel`
+        ("search" or "refine") since profiling was enabled or last read."""
+        k = {"search": _abi.PROF_SEARCH, "refine": _abi.PROF_REFINE}[kernel]
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        _check(self._lib.fl_get_profile(self._h, ctypes.byref(ms), ctypes.byref(n)), "fl_get_profile")
+        _check(self._lib.fl_get_profile(self._h, k, ctypes.byref(ms), ctypes.byref(n)), "fl_get_profile")
         return ms.value, n.value
 
     def debug_set_list_cap(self, cap: int):

@@ -98,6 +98,7 @@ struct fl_ctx {
     DevBuf ctrs;                // stats + per-keyframe + per-event counters, zero at rest
     DevBuf plain;               // plain-path workspace
     DevBuf res;                 // residual partials and done counter
+    DevBuf part;                // refinement partial sums and their tags, zero when the epoch restarts
     Pinned pin[kPinRing];
     int pin_next = 0;
     hipStream_t cap_stream = nullptr;
@@ -106,8 +107,8 @@ struct fl_ctx {
     Pinned* pin_last = nullptr; // ring buffer of the last eager upload
     int stats = 0;
     int add_cap_override = 0;   // test hook: >0 forces small ADD / match list capacities
-    int prof = 0;               // record events around eager search kernels
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+    int prof = 0;               // record events around eager search and refinement kernels
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2];   // by FL_PROF_* class
     // captured graph and its key
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // replayed alternately
     Pinned gpin[2];             // the pinned tables each graph fetches from
@@ -280,8 +281,12 @@ int pick_mode(const fl_ctx* c, int want, int kp_cap, int cells, int hash_cap) {
     return kModeGlobal;
 }
 
+// graph: the launch shape is kept stable across batches of different sizes,
+// so a captured graph can be replayed for them (the grid is always every
+// workgroup slot, empty ranges exit at once; the dynamic LDS is rounded up to
+// a 16 KB step).
 int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_out* out, const fl_refine* R,
-                  bool refine_scan, Prepared& pr) {
+                  bool refine_scan, Prepared& pr, bool graph = false) {
     const int cells = P->grid_cols * P->grid_rows;
     const int n_kf = B->n_kf, n_ev = B->n_events;
     const int ppl = c->tune.pairs_per_lane;
@@ -294,6 +299,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const int lds_hash_cap = std::max(64, next_pow2(kp_cap + 1));
     pr.mode = pick_mode(c, c->tune.lds_mode, kp_cap, cells, lds_hash_cap);
     pr.lds = search_lds_bytes(pr.mode, kp_cap, cells, lds_hash_cap);
+    if (graph && pr.mode != kModeGlobal) pr.lds = std::min(c->lds_max, align_up(pr.lds, 16384));
 
     std::vector<char>& blob = pr.blob;
     blob.clear();
@@ -365,7 +371,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     prefix[n_kf] = (int32_t)n_tiles;
     // workgroups and their contiguous, cost-balanced tile ranges
     int grid = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
-    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles));
+    if (!graph) grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles));
     pr.grid = grid;
     const size_t o_range = blob_take<int2>(blob, grid);
     kfd = (KfDesc*)(blob.data() + o_kf);
@@ -390,7 +396,13 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         std::vector<int64_t> bound(grid + 1);
         bound[0] = 0;
         bound[grid] = n_tiles;
-        for (int i = 1; i < grid; ++i) bound[i] = tile_at_cost(total * i / grid);
+        if (n_tiles <= 2 * (int64_t)grid) {
+            // at most two tiles per workgroup: equal counts (a single wave of
+            // tiles is latency bound, so a workgroup must not take more)
+            for (int i = 1; i < grid; ++i) bound[i] = n_tiles * i / grid;
+        } else {
+            for (int i = 1; i < grid; ++i) bound[i] = tile_at_cost(total * i / grid);
+        }
         for (int i = 1; i <= grid; ++i) bound[i] = std::max(bound[i], bound[i - 1]);
         for (int i = grid - 1; i >= 0; --i) bound[i] = std::min(bound[i], bound[i + 1]);
         // chunk i of the sequence goes to workgroup w(i); with xcd_aware the
@@ -426,9 +438,16 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const size_t L_hash = take(global_grid ? sizeof(int32_t) * (size_t)hash_total : 0);
     const size_t L_add = take(sizeof(AddRef) * (size_t)add_total);
     const size_t L_match = take(sizeof(MatchRec) * (size_t)list_total);
-    const int refine_blocks = std::max(1, std::min(64, kRefineGrid / std::max(1, n_ev)));
-    const size_t L_part = take(2 * sizeof(double) * kNAcc * (size_t)n_ev * refine_blocks);
+    const int refine_blocks = std::max(1, std::min(kRefMaxB, kRefineGrid / std::max(1, n_ev)));
+    const size_t n_rows = 2 * (size_t)n_ev * refine_blocks;
+    const size_t part_tags = align_up(sizeof(double) * kNAcc * n_rows, 256);
     int rc = c->ws.ensure(off);
+    if (rc) return rc;
+    // Tags in the partial-sum buffer must never match a tag of a later
+    // launch: the buffer is zeroed when allocated and whenever the epoch
+    // restarts.
+    const void* old_part = c->part.p;
+    rc = c->part.ensure(part_tags + sizeof(unsigned long long) * n_rows, 0x00);
     if (rc) return rc;
     rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(B->n_kp_total, 1), 0xFF);
     if (rc) return rc;
@@ -438,6 +457,8 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     if (c->ctrs.p != old_ctrs && old_ctrs != nullptr) {
         // a fresh counter block restarts the epoch: every stored claim must be reset too
         if (hipMemset(c->claims.p, 0xFF, c->claims.size) != hipSuccess) return fail(FL_EHIP, "hipMemset failed");
+        if (c->part.p == old_part && hipMemset(c->part.p, 0, c->part.size) != hipSuccess)
+            return fail(FL_EHIP, "hipMemset failed");
         c->launches = 0;
     }
     char* base = (char*)c->ws.p;
@@ -500,7 +521,8 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.match_list = (MatchRec*)(base + L_match);
     h.refine_blocks = refine_blocks;
     h.refine_scan = refine_scan ? 1 : 0;
-    h.refine_partial = (double*)(base + L_part);
+    h.refine_partial = (double*)c->part.p;
+    h.refine_tag = (unsigned long long*)((char*)c->part.p + part_tags);
     if (refine) {
         h.refine_iters = R->n_iters;
         h.huber_delta = R->huber_delta;
@@ -517,6 +539,7 @@ int next_epoch(fl_ctx* c, hipStream_t stream) {
     if (++c->launches >= 0xFFFFFFF0u) {
         FL_HIP(hipMemsetAsync(c->claims.p, 0xFF, c->claims.size, stream));
         FL_HIP(hipMemsetAsync((char*)c->ctrs.p + 32, 0, 4, stream));
+        if (c->part.p) FL_HIP(hipMemsetAsync(c->part.p, 0, c->part.size, stream));
         c->launches = 1;
     }
     return FL_OK;
@@ -588,15 +611,26 @@ int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t
     else launch_fused_m<4>(pr.mode, stats, dh, pr.grid, pr.lds, s);
     if (timed) {
         FL_HIP(hipEventRecord(t1, s));
-        c->prof_ev.emplace_back(t0, t1);
+        c->prof_ev[FL_PROF_SEARCH].emplace_back(t0, t1);
     }
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
 
-int launch_refine(const BatchHdr* dh, int n_iters, hipStream_t s) {
+int launch_refine(fl_ctx* c, const BatchHdr* dh, int n_iters, hipStream_t s, bool eager) {
     if (n_iters <= 0) return FL_OK;
+    const bool timed = eager && c->prof;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (timed) {
+        FL_HIP(hipEventCreate(&t0));
+        FL_HIP(hipEventCreate(&t1));
+        FL_HIP(hipEventRecord(t0, s));
+    }
     hipLaunchKernelGGL(refine_kernel, dim3(kRefineGrid), dim3(kResBlock), 0, s, dh);
+    if (timed) {
+        FL_HIP(hipEventRecord(t1, s));
+        c->prof_ev[FL_PROF_REFINE].emplace_back(t0, t1);
+    }
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
@@ -701,6 +735,7 @@ void fl_destroy(fl_ctx* c) {
     c->ctrs.release();
     c->plain.release();
     c->res.release();
+    c->part.release();
     delete c;
 }
 
@@ -820,18 +855,23 @@ int fl_validate_batch(const fl_batch* B, const fl_params* P, const fl_fuse_out* 
 }
 
 int fl_search_fuse_batched(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_out* out,
-                           hipStream_t stream) {
+                           const fl_refine* R, hipStream_t stream) {
     if (!c) return fail(FL_EINVAL, "ctx is NULL");
     int rc = validate_batch(B, P, out);
     if (rc) return rc;
+    rc = check_refine(B, R);
+    if (rc) return rc;
     if (B->n_pairs == 0) return FL_OK;
     Prepared pr;
-    rc = prepare_batch(c, B, P, out, nullptr, false, pr);
+    rc = prepare_batch(c, B, P, out, R, false, pr);
     if (rc) return rc;
     rc = upload_batch(c, pr, stream);
     if (rc) return rc;
     if (c->stats) FL_HIP(hipMemsetAsync(c->ctrs.p, 0, 32, stream));
-    return launch_search(c, pr, (const BatchHdr*)c->ws.p, stream, true, c->stats != 0);
+    const BatchHdr* dh = (const BatchHdr*)c->ws.p;
+    rc = launch_search(c, pr, dh, stream, true, c->stats != 0);
+    if (rc) return rc;
+    return launch_refine(c, dh, pr.refine_iters, stream, true);
 }
 
 int fl_refine_events(fl_ctx* c, const fl_batch* B, const fl_fuse_out* out, const fl_refine* R, hipStream_t stream) {
@@ -847,7 +887,7 @@ int fl_refine_events(fl_ctx* c, const fl_batch* B, const fl_fuse_out* out, const
     if (rc) return rc;
     rc = upload_batch(c, pr, stream);
     if (rc) return rc;
-    return launch_refine((const BatchHdr*)c->ws.p, R->n_iters, stream);
+    return launch_refine(c, (const BatchHdr*)c->ws.p, R->n_iters, stream, true);
 }
 
 int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_out* out,
@@ -859,7 +899,7 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
     if (rc) return rc;
     if (B->n_pairs == 0) return FL_OK;
     Prepared pr;
-    rc = prepare_batch(c, B, P, out, R, false, pr);
+    rc = prepare_batch(c, B, P, out, R, false, pr, true);
     if (rc) return rc;
     pr.hdr->stats = 0;   // counters are an eager-path feature
     const int refine_on = pr.refine_iters > 0 ? 1 : 0;
@@ -895,7 +935,7 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
             launch_fetch(c, c->gpin[gi].p, c->gpin[gi].size, c->cap_stream);
             int lrc = launch_search(c, pr, dh, c->cap_stream, false, false);
             c->prof = saved_prof;
-            if (lrc == FL_OK && refine_on) lrc = launch_refine(dh, pr.refine_iters, c->cap_stream);
+            if (lrc == FL_OK && refine_on) lrc = launch_refine(c, dh, pr.refine_iters, c->cap_stream, false);
             hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
             if (lrc) {
                 if (graph) hipGraphDestroy(graph);
@@ -1064,10 +1104,10 @@ int fl_autotune(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_
             for (int wpc = 1; wpc <= 2; ++wpc)
                 for (int xa = 0; xa <= 1 && rc == FL_OK; ++xa) {
                     c->tune = fl_tuning{ppl, mode, wpc, xa};
-                    rc = fl_search_fuse_batched(c, B, P, out, stream);   // warm-up
+                    rc = fl_search_fuse_batched(c, B, P, out, nullptr, stream);   // warm-up
                     if (rc) break;
                     (void)hipEventRecord(e0, stream);
-                    for (int r = 0; r < reps && rc == FL_OK; ++r) rc = fl_search_fuse_batched(c, B, P, out, stream);
+                    for (int r = 0; r < reps && rc == FL_OK; ++r) rc = fl_search_fuse_batched(c, B, P, out, nullptr, stream);
                     (void)hipEventRecord(e1, stream);
                     if (rc) break;
                     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -1110,12 +1150,17 @@ int fl_get_stats(fl_ctx* c, int64_t* out4) {
 
 }  // extern "C"
 
-static void clear_profile(fl_ctx* c) {
-    for (auto& pr : c->prof_ev) {
+static void clear_profile(fl_ctx* c, int kernel) {
+    for (auto& pr : c->prof_ev[kernel]) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
-    c->prof_ev.clear();
+    c->prof_ev[kernel].clear();
+}
+
+static void clear_profile(fl_ctx* c) {
+    clear_profile(c, FL_PROF_SEARCH);
+    clear_profile(c, FL_PROF_REFINE);
 }
 
 extern "C" {
@@ -1127,18 +1172,20 @@ int fl_set_profiling(fl_ctx* c, int enable) {
     return FL_OK;
 }
 
-int fl_get_profile(fl_ctx* c, double* total_ms, int64_t* launches) {
+int fl_get_profile(fl_ctx* c, int kernel, double* total_ms, int64_t* launches) {
     if (!c || !total_ms || !launches) return fail(FL_EINVAL, "NULL argument");
+    if (kernel != FL_PROF_SEARCH && kernel != FL_PROF_REFINE) return fail(FL_EINVAL, "unknown kernel class %d", kernel);
+    auto& ev = c->prof_ev[kernel];
     double sum = 0.0;
-    if (!c->prof_ev.empty()) FL_HIP(hipEventSynchronize(c->prof_ev.back().second));
-    for (auto& pr : c->prof_ev) {
+    if (!ev.empty()) FL_HIP(hipEventSynchronize(ev.back().second));
+    for (auto& pr : ev) {
         float ms = 0.0f;
         FL_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
         sum += ms;
     }
     *total_ms = sum;
-    *launches = (int64_t)c->prof_ev.size();
-    clear_profile(c);
+    *launches = (int64_t)ev.size();
+    clear_profile(c, kernel);
     return FL_OK;
 }
 

@@ -75,7 +75,7 @@ struct alignas(16) KpRec {
 // last resets them).
 enum : int { kKfDone = 0, kKfAdd = 1, kKfCtrs = 2 };
 // Per-event counters.
-enum : int { kEvMatch = 0, kEvBarrier = 1, kEvLeave = 2, kEvCtrs = 4 };
+enum : int { kEvMatch = 0, kEvCtrs = 1 };
 
 enum : int { kModeGlobal = 0, kModeLdsRec = 1, kModeLdsDesc = 2 };
 
@@ -138,7 +138,8 @@ struct alignas(16) BatchHdr {
     double* event_S;            // [n_events][13] caller's, in/out
     fl_sim3* event_S32_out;     // caller's (may be null)
     int32_t* event_n_matched;   // caller's (may be null)
-    double* refine_partial;     // [2][n_events * refine_blocks * kNAccPad] (ping-pong by step)
+    double* refine_partial;     // [2][n_events * refine_blocks][kNAccPad] (alternating by step)
+    unsigned long long* refine_tag;   // [2][n_events * refine_blocks]: launch epoch << 32 | step + 1
 };
 
 // ---------------------------------------------------------------------------

@@ -38,24 +38,6 @@ struct RecipTable {
 };
 __device__ constexpr RecipTable kRecip{};
 
-__device__ inline double exp_moment(int n, double s) {
-    // I_n(s) = integral_0^1 e^{s tau} tau^n d tau = sum_k s^k / (k! (n + k + 1))
-    if (fabs(s) < 2.0) {
-        double term = 1.0, sum = 0.0;
-        for (int k = 0; k < 60; ++k) {
-            const double c = term * kRecip.v[n + k];
-            sum += c;
-            if (fabs(c) < 1e-18 * fabs(sum)) break;
-            term *= s * kRecip.v[k];
-        }
-        return sum;
-    }
-    const double es = exp(s);
-    double I = expm1(s) / s;
-    for (int m = 1; m <= n; ++m) I = (es - (double)m * I) / s;
-    return I;
-}
-
 // exp of a tangent xi = (omega, upsilon, sigma):  R = exp([omega]x),
 // s = e^sigma, t = V upsilon with V = integral_0^1 e^{sigma tau} exp(tau [omega]x) d tau
 // = c0 I + c1 W + c2 W^2 (closed form; series for small rotation angles).
@@ -72,15 +54,31 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
         a = sin(th) / th;
         b = (1.0 - cos(th)) / th2;
     }
-    const double c0 = exp_moment(0, sig);
+    // I_n(sigma) for n = 0..6 and e^sigma = sum_k sigma^k / k! share one series
+    double I[7];
+    double es;
+    if (fabs(sig) < 2.0) {
+        double term = 1.0, e = 0.0;
+        for (int n = 0; n < 7; ++n) I[n] = 0.0;
+        for (int k = 0; k < 60; ++k) {
+            e += term;
+#pragma unroll
+            for (int n = 0; n < 7; ++n) I[n] += term * kRecip.v[n + k];
+            if (fabs(term) < 1e-18 * e) break;
+            term *= sig * kRecip.v[k];
+        }
+        es = e;
+    } else {
+        es = exp(sig);
+        I[0] = expm1(sig) / sig;
+        for (int m = 1; m < 7; ++m) I[m] = (es - (double)m * I[m - 1]) / sig;
+    }
+    const double c0 = I[0];
     double c1, c2;
     if (th < 1e-2) {
-        c1 = exp_moment(1, sig) - th2 * (1.0 / 6.0) * exp_moment(3, sig) +
-             th2 * th2 * (1.0 / 120.0) * exp_moment(5, sig);
-        c2 = 0.5 * exp_moment(2, sig) - th2 * (1.0 / 24.0) * exp_moment(4, sig) +
-             th2 * th2 * (1.0 / 720.0) * exp_moment(6, sig);
+        c1 = I[1] - th2 * (1.0 / 6.0) * I[3] + th2 * th2 * (1.0 / 120.0) * I[5];
+        c2 = 0.5 * I[2] - th2 * (1.0 / 24.0) * I[4] + th2 * th2 * (1.0 / 720.0) * I[6];
     } else {
-        const double es = exp(sig);
         const double den = sig * sig + th2;
         c1 = (es * (sig * sin(th) - th * cos(th)) + th) / (th * den);
         c2 = (c0 - (es * (sig * cos(th) + th * sin(th)) - sig) / den) / th2;
@@ -98,7 +96,7 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
         V[i] = c0 * I + c1 * W[i] + c2 * W2[i];
     }
     for (int i = 0; i < 3; ++i) S.t[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
-    S.s = exp(sig);
+    S.s = es;
     return S;
 }
 
@@ -135,48 +133,49 @@ __device__ inline void sim3_to_f32(const Sim3d& S, fl_sim3* o) {
     o->pad[0] = o->pad[1] = o->pad[2] = 0.0f;
 }
 
-// Solve (H + lambda diag H) d = -g by Cholesky; H given as its 28 upper
-// entries row by row.  Returns false (d = 0) for a non-positive pivot.
+// Solve (H + lambda diag H) d = -g by an LDL^T factorisation (no square
+// roots; one reciprocal per pivot); H given as its 28 upper entries row by
+// row.  Returns false (d = 0) for a pivot that is not clearly positive.
 __device__ inline bool solve7(const double* g, const double* Hu, double lambda, double* d) {
-    double L[49];
+    double A[7][7];
     int k = 0;
     double dmax = 0.0;
     for (int i = 0; i < 7; ++i)
         for (int j = i; j < 7; ++j) {
-            L[7 * i + j] = Hu[k];
-            L[7 * j + i] = Hu[k];
+            A[i][j] = Hu[k];
+            A[j][i] = Hu[k];
             ++k;
         }
     for (int i = 0; i < 7; ++i) {
-        L[8 * i] *= (1.0 + lambda);
-        dmax = fmax(dmax, fabs(L[8 * i]));
+        A[i][i] *= (1.0 + lambda);
+        dmax = fmax(dmax, fabs(A[i][i]));
     }
+    double L[7][7], D[7], Dinv[7];
     for (int j = 0; j < 7; ++j) {
-        double s = L[8 * j];
-        for (int m = 0; m < j; ++m) s -= L[7 * j + m] * L[7 * j + m];
-        if (!(s > 1e-14 * dmax)) {
+        double dj = A[j][j];
+        for (int m = 0; m < j; ++m) dj -= L[j][m] * L[j][m] * D[m];
+        if (!(dj > 1e-14 * dmax)) {
             for (int i = 0; i < 7; ++i) d[i] = 0.0;
             return false;
         }
-        const double ljj = sqrt(s);
-        const double inv = 1.0 / ljj;
-        L[8 * j] = inv;   // the diagonal keeps the reciprocal pivot
+        D[j] = dj;
+        Dinv[j] = 1.0 / dj;
         for (int i = j + 1; i < 7; ++i) {
-            double v = L[7 * i + j];
-            for (int m = 0; m < j; ++m) v -= L[7 * i + m] * L[7 * j + m];
-            L[7 * i + j] = v * inv;
+            double v = A[i][j];
+            for (int m = 0; m < j; ++m) v -= L[i][m] * L[j][m] * D[m];
+            L[i][j] = v * Dinv[j];
         }
     }
     double y[7];
     for (int i = 0; i < 7; ++i) {
         double v = -g[i];
-        for (int m = 0; m < i; ++m) v -= L[7 * i + m] * y[m];
-        y[i] = v * L[8 * i];
+        for (int m = 0; m < i; ++m) v -= L[i][m] * y[m];
+        y[i] = v;
     }
     for (int i = 6; i >= 0; --i) {
-        double v = y[i];
-        for (int m = i + 1; m < 7; ++m) v -= L[7 * m + i] * d[m];
-        d[i] = v * L[8 * i];
+        double v = y[i] * Dinv[i];
+        for (int m = i + 1; m < 7; ++m) v -= L[m][i] * d[m];
+        d[i] = v;
     }
     return true;
 }
@@ -356,15 +355,14 @@ __device__ __forceinline__ bool last_block(uint32_t* done, unsigned n_blocks) {
 // Sum `rows` partials of NV doubles (row stride kNAcc) in row order into
 // s_out[0..NV): rows are staged through LDS in chunks by the whole block so
 // the loads are issued in parallel, then column i is summed by thread i.
-template <int NV>
+template <int NV, int MAXR>
 __device__ __forceinline__ void sum_partials(const double* part, int rows, double* s_chunk, double* s_out) {
-    constexpr int kRows = 32;
     double acc = 0.0;
-    for (int r0 = 0; r0 < rows; r0 += kRows) {
-        const int nr = min(kRows, rows - r0);
+    for (int r0 = 0; r0 < rows; r0 += MAXR) {
+        const int nr = min(MAXR, rows - r0);
         for (int i = threadIdx.x; i < nr * NV; i += blockDim.x) {
-            const int r = i / NV, c = i % NV;
-            s_chunk[r * NV + c] = part[(int64_t)(r0 + r) * kNAcc + c];
+            const int r = i / NV, c = i - r * NV;
+            s_chunk[i] = part[(int64_t)(r0 + r) * kNAcc + c];
         }
         __syncthreads();
         if ((int)threadIdx.x < NV)
@@ -401,7 +399,7 @@ __global__ __launch_bounds__(kResBlock) void residual_fwd_kernel(ResArgs a) {
     block_reduce<1>(acc, s_red, s_out);
     if (threadIdx.x == 0) a.partial[blockIdx.x * kNAcc] = s_out[0];
     if (last_block(a.done, gridDim.x)) {
-        sum_partials<1>(a.partial, gridDim.x, s_chunk, s_out);
+        sum_partials<1, 32>(a.partial, gridDim.x, s_chunk, s_out);
         if (threadIdx.x == 0) {
             *a.loss = s_out[0];
             *a.done = 0;
@@ -428,7 +426,7 @@ __global__ __launch_bounds__(kResBlock) void residual_bwd_kernel(ResArgs a) {
     block_reduce<35>(acc, s_red, s_out);
     if ((int)threadIdx.x < 35) a.partial[blockIdx.x * kNAcc + threadIdx.x] = s_out[threadIdx.x];
     if (last_block(a.done, gridDim.x)) {
-        sum_partials<35>(a.partial, gridDim.x, s_chunk, s_out);
+        sum_partials<35, 32>(a.partial, gridDim.x, s_chunk, s_out);
         if (threadIdx.x < 7) a.g[threadIdx.x] = a.grad_scale * s_out[threadIdx.x];
         else if ((int)threadIdx.x < 35 && a.H) a.H[threadIdx.x - 7] = s_out[threadIdx.x];
         if (threadIdx.x == 0) *a.done = 0;
@@ -459,30 +457,41 @@ __global__ void gn_step_kernel(const double* __restrict__ g, const double* __res
 // ---------------------------------------------------------------------------
 // Per-event refinement inside a batch, all Gauss-Newton steps in one launch.
 // refine_blocks workgroups per event accumulate g and H over the event's
-// accepted pairs (recorded by the search as point + observation + keyframe),
-// publish their partials and meet at a barrier; every workgroup then sums the
-// partials in the same order and solves the same 7x7 system, so all of them
-// hold the bitwise-identical next Sim3 without a second barrier.  The
-// barrier only waits for workgroups of the same event, which are co-resident
-// (at most one workgroup per CU is launched when an event has more than
-// one); its spin is bounded and a timeout is reported as n_matched = -1.
+// accepted pairs (recorded by the search as point + observation + keyframe,
+// held in registers across the steps), publish their partial sums as tagged
+// rows and wait until every row of the step is tagged; every workgroup then
+// sums the rows in the same order and solves the same 7x7 system, so all of
+// them hold the bitwise-identical next Sim3 without a second exchange.  The
+// wait only involves workgroups of the same event, which are co-resident (the
+// whole grid is one workgroup per CU); its spin is bounded and a timeout is
+// reported as n_matched = -1.
 
+// s_waitcnt immediate with vmcnt = 0 and expcnt / lgkmcnt left at their
+// maxima (no wait): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ void refine_accumulate(const KfDesc& kd, float x, float y, float z, float uo, float vo,
-                                                  const fl_sim3& S, float delta, double* acc) {
+__device__ __forceinline__ void refine_accumulate(const float* T, float fx, float fy, float cx, float cy, float x,
+                                                  float y, float z, float uo, float vo, const fl_sim3& S, float delta,
+                                                  double* acc) {
     PairTerm t;
-    pair_term(S.sR, S.t, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, x, y, z, uo, vo, delta, true, t);
+    pair_term(S.sR, S.t, T, fx, fy, cx, cy, x, y, z, uo, vo, delta, true, t);
     if (t.valid) {
         accumulate(t, acc);
         acc[35] += 1.0;
     }
 }
 
+constexpr int kRefCache = 2;     // accepted pairs a thread keeps in registers across the steps
+constexpr int kRefKfLds = 64;    // keyframes of one event whose pose and intrinsics sit in LDS
+constexpr int kRefMaxB = 64;     // workgroups per event
+constexpr int kRefGather = (kRefMaxB * kNAcc + kResBlock - 1) / kResBlock;
+
 __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
     __shared__ double s_red[(kResBlock / kWave) * kNAcc];
     __shared__ double s_out[kNAcc];
-    __shared__ double s_chunk[32 * kNAcc];
+    __shared__ double s_chunk[kRefMaxB * kNAcc];
+    __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
     __shared__ double s_S64[13];
     __shared__ fl_sim3 s_S;
     __shared__ int s_fail;
@@ -491,32 +500,74 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
     const int n_units = h.n_events * B;
     const int iters = h.refine_iters;
     const float delta = h.huber_delta;
+    const int tid = threadIdx.x;
+    const unsigned long long tag0 = (unsigned long long)(*h.epoch) << 32;
     for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
         const int ev = unit / B, b = unit % B;
         const EventDesc ed = h.ev[ev];
-        if (threadIdx.x < 13) s_S64[threadIdx.x] = h.event_S[13 * (int64_t)ev + threadIdx.x];
-        if (threadIdx.x == 0) s_fail = 0;
+        const int n_kf_ev = ed.kf_end - ed.kf_begin;
+        const bool kf_lds = n_kf_ev <= kRefKfLds;
+        if (tid < 13) s_S64[tid] = h.event_S[13 * (int64_t)ev + tid];
+        if (tid == 0) s_fail = 0;
+        if (kf_lds) {
+            for (int i = tid; i < n_kf_ev * 16; i += blockDim.x) {
+                const KfDesc& kd = h.kf[ed.kf_begin + (i >> 4)];
+                const int f = i & 15;
+                s_kf[i] = f < 12 ? kd.T[f] : f == 12 ? kd.fx : f == 13 ? kd.fy : f == 14 ? kd.cx : kd.cy;
+            }
+        }
         __syncthreads();
-        if (threadIdx.x == 0) sim3_to_f32(sim3_load(s_S64), &s_S);
-        __syncthreads();
+        if (tid == 0) sim3_to_f32(sim3_load(s_S64), &s_S);
         const uint32_t cnt = h.ev_ctr[ev * kEvCtrs + kEvMatch];
         const bool use_list = !h.refine_scan && cnt <= (uint32_t)ed.list_cap;
         const int stride = B * blockDim.x;
+        // this thread's first kRefCache accepted pairs, loaded once
+        float cx_[kRefCache], cy_[kRefCache], cz_[kRefCache], cu_[kRefCache], cv_[kRefCache];
+        int ck_[kRefCache];
+#pragma unroll
+        for (int r = 0; r < kRefCache; ++r) {
+            const int i = b * blockDim.x + tid + r * stride;
+            ck_[r] = -1;
+            if (use_list && i < (int)cnt) {
+                const MatchRec m = h.match_list[ed.list_off + i];
+                cx_[r] = m.x;
+                cy_[r] = m.y;
+                cz_[r] = m.z;
+                cu_[r] = m.u;
+                cv_[r] = m.v;
+                ck_[r] = m.kf;
+            }
+        }
+        __syncthreads();
         for (int it = 0; it < iters; ++it) {
             const fl_sim3 S = s_S;
             double acc[kNAcc];
 #pragma unroll
             for (int i = 0; i < kNAcc; ++i) acc[i] = 0.0;
             if (use_list) {
-                for (int i = b * blockDim.x + threadIdx.x; i < (int)cnt; i += stride) {
+#pragma unroll
+                for (int r = 0; r < kRefCache; ++r) {
+                    if (ck_[r] < 0) continue;
+                    if (kf_lds) {
+                        const float* q = &s_kf[16 * (ck_[r] - ed.kf_begin)];
+                        refine_accumulate(q, q[12], q[13], q[14], q[15], cx_[r], cy_[r], cz_[r], cu_[r], cv_[r], S,
+                                          delta, acc);
+                    } else {
+                        const KfDesc& kd = h.kf[ck_[r]];
+                        refine_accumulate(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, cx_[r], cy_[r], cz_[r], cu_[r], cv_[r],
+                                          S, delta, acc);
+                    }
+                }
+                for (int i = b * blockDim.x + tid + kRefCache * stride; i < (int)cnt; i += stride) {
                     const MatchRec m = h.match_list[ed.list_off + i];
-                    refine_accumulate(h.kf[m.kf], m.x, m.y, m.z, m.u, m.v, S, delta, acc);
+                    const KfDesc& kd = h.kf[m.kf];
+                    refine_accumulate(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, m.x, m.y, m.z, m.u, m.v, S, delta, acc);
                 }
             } else {
                 // no list (or it overflowed): scan the event's pairs keyframe by keyframe
                 for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
                     const KfDesc& kd = h.kf[k];
-                    for (int64_t j = b * blockDim.x + threadIdx.x; j < kd.n_pairs; j += stride) {
+                    for (int64_t j = b * blockDim.x + tid; j < kd.n_pairs; j += stride) {
                         const int64_t o = kd.pair_off + j;
                         const uint8_t dec = h.decision[o];
                         if (dec != FL_ADD && dec != FL_FUSE) continue;
@@ -524,36 +575,75 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                         const int32_t bi = h.best_idx[o];
                         if (lp < 0 || lp >= kd.n_mp || bi < 0 || bi >= kd.n_kp) continue;
                         const int64_t gp = kd.mp_off + lp, kp = kd.kp_off + bi;
-                        refine_accumulate(kd, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1], h.mp_xyz[3 * gp + 2],
-                                          h.kp_xy[2 * kp], h.kp_xy[2 * kp + 1], S, delta, acc);
+                        refine_accumulate(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1],
+                                          h.mp_xyz[3 * gp + 2], h.kp_xy[2 * kp], h.kp_xy[2 * kp + 1], S, delta, acc);
                     }
                 }
             }
             block_reduce<kNAcc>(acc, s_red, s_out);
-            double* part = h.refine_partial + ((int64_t)(it & 1) * n_units + (int64_t)ev * B) * kNAcc;
             if (B > 1) {
-                if ((int)threadIdx.x < kNAcc) part[(int64_t)b * kNAcc + threadIdx.x] = s_out[threadIdx.x];
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    __threadfence();   // release this workgroup's partial
-                    uint32_t* bar = &h.ev_ctr[ev * kEvCtrs + kEvBarrier];
-                    atomicAdd(bar, 1u);
-                    const uint32_t goal = (uint32_t)(it + 1) * (uint32_t)B;
-                    unsigned spins = 0;
-                    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < goal) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (++spins > kSpinLimit) {
-                            s_fail = 1;
-                            break;
+                // Exchange of the B partial sums of this step.  Each workgroup
+                // writes its row with device-coherent (agent-scope) stores,
+                // waits until they have completed (vmcnt 0; the 36 stores are
+                // all in wave 0) and only then writes the row's tag (launch
+                // epoch, step).  Readers poll the B tags, one lane each, and
+                // load the rows after every tag matched, so no L2 write-back
+                // or invalidation is needed and no two workgroups write one
+                // address.  Rows alternate between two buffers by step: a
+                // workgroup writes step it + 2 only after every row of step
+                // it + 1 was tagged, i.e. after every reader of step it is done.
+                const size_t slot = ((size_t)(it & 1) * n_units + (size_t)ev * B);
+                double* rows = h.refine_partial + slot * kNAcc;
+                unsigned long long* tags = h.refine_tag + slot;
+                const unsigned long long tag = tag0 | (unsigned)(it + 1);
+                if (tid < kWave) {
+                    if (tid < kNAcc)
+                        __hip_atomic_store(&rows[(size_t)b * kNAcc + tid], s_out[tid], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+                    if (tid == 0) __hip_atomic_store(&tags[b], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (tid < B) {
+                        unsigned spins = 0;
+                        while (__hip_atomic_load(&tags[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+                            __builtin_amdgcn_s_sleep(1);
+                            if (++spins > kSpinLimit) {
+                                s_fail = 1;
+                                break;
+                            }
                         }
                     }
-                    __threadfence();   // acquire the other workgroups' partials
                 }
                 __syncthreads();
                 if (s_fail) break;
-                sum_partials<kNAcc>(part, B, s_chunk, s_out);
+                double gv[kRefGather];
+#pragma unroll
+                for (int q = 0; q < kRefGather; ++q) {
+                    const int i = tid + q * kResBlock;
+                    if (i < B * kNAcc) gv[q] = __hip_atomic_load(&rows[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+                for (int q = 0; q < kRefGather; ++q) {
+                    const int i = tid + q * kResBlock;
+                    if (i < B * kNAcc) s_chunk[i] = gv[q];
+                }
+                __syncthreads();
+                if (tid < kNAcc) {
+                    // the same fixed order in every workgroup: all of them
+                    // solve for bitwise the same step
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                    int r = 0;
+                    for (; r + 3 < B; r += 4) {
+                        a0 += s_chunk[(r + 0) * kNAcc + tid];
+                        a1 += s_chunk[(r + 1) * kNAcc + tid];
+                        a2 += s_chunk[(r + 2) * kNAcc + tid];
+                        a3 += s_chunk[(r + 3) * kNAcc + tid];
+                    }
+                    for (; r < B; ++r) a0 += s_chunk[r * kNAcc + tid];
+                    s_out[tid] = (a0 + a1) + (a2 + a3);
+                }
+                __syncthreads();
             }
-            if (threadIdx.x == 0) {
+            if (tid == 0) {
                 double d[7];
                 if (solve7(s_out, s_out + 7, 0.0, d)) {
                     const Sim3d Sd = sim3_mul(sim3_exp(d), sim3_load(s_S64));
@@ -563,15 +653,7 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
             }
             __syncthreads();
         }
-        if (B > 1) {   // the last workgroup to leave resets the event's barrier
-            if (threadIdx.x == 0) {
-                if (atomicAdd(&h.ev_ctr[ev * kEvCtrs + kEvLeave], 1u) == (uint32_t)(B - 1)) {
-                    h.ev_ctr[ev * kEvCtrs + kEvBarrier] = 0;
-                    h.ev_ctr[ev * kEvCtrs + kEvLeave] = 0;
-                }
-            }
-        }
-        if (b == 0 && threadIdx.x == 0) {
+        if (b == 0 && tid == 0) {
             if (!s_fail) {
                 for (int i = 0; i < 13; ++i) h.event_S[13 * (int64_t)ev + i] = s_S64[i];
                 if (h.event_S32_out) h.event_S32_out[ev] = s_S;

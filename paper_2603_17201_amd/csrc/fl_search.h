@@ -136,7 +136,33 @@ __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_c
     for (int c = tid; c <= cells; c += nt) s_cs[c] = 0;
     for (int s = tid; s <= hmask; s += nt) s_hash[s] = -1;
     __syncthreads();
-    for (int i = tid; i < n; i += nt) {
+    // The first kStageRegs keypoints of each thread are loaded once, with
+    // their descriptors, and kept in registers across the scan; any further
+    // keypoints (keyframes larger than kStageRegs * blockDim) are reloaded.
+    constexpr int kStageRegs = 1;
+    float kx[kStageRegs], ky[kStageRegs];
+    int ko[kStageRegs], kc[kStageRegs];
+    uint4 kd0[kStageRegs], kd1[kStageRegs];
+#pragma unroll
+    for (int q = 0; q < kStageRegs; ++q) {
+        const int i = tid + q * nt;
+        kc[q] = -1;
+        if (i < n) {
+            kx[q] = xy[2 * i];
+            ky[q] = xy[2 * i + 1];
+            ko[q] = (int)h.kp_oct[kd.kp_off + i];
+            if (STAGE_DESC) {
+                const uint4* src = reinterpret_cast<const uint4*>(h.kp_desc + 32 * ((int64_t)kd.kp_off + i));
+                kd0[q] = src[0];
+                kd1[q] = src[1];
+            }
+            const int32_t o = h.kp_owner[kd.kp_off + i];
+            kc[q] = cell_of(ky[q], kd.invh, R) * C + cell_of(kx[q], kd.invw, C);
+            atomicAdd(&s_cs[kc[q] + 1], 1);
+            if (o >= 0) owner_insert(s_hash, hmask, o);
+        }
+    }
+    for (int i = tid + kStageRegs * nt; i < n; i += nt) {
         const int c = cell_of(xy[2 * i + 1], kd.invh, R) * C + cell_of(xy[2 * i], kd.invw, C);
         atomicAdd(&s_cs[c + 1], 1);
         const int32_t o = h.kp_owner[kd.kp_off + i];
@@ -144,10 +170,25 @@ __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_c
     }
     __syncthreads();
     block_exclusive_scan(s_cs + 1, cells, s_tmp);   // s_cs[1 + c] = first slot of c
-    for (int i = tid; i < n; i += nt) {
+#pragma unroll
+    for (int q = 0; q < kStageRegs; ++q) {
+        if (kc[q] < 0) continue;
+        const int slot = atomicAdd(&s_cs[kc[q] + 1], 1);   // ends as the first slot of c + 1
+        KpRec r;
+        r.x = kx[q];
+        r.y = ky[q];
+        r.idx = tid + q * nt;
+        r.oct = ko[q];
+        s_rec[slot] = r;
+        if (STAGE_DESC) {
+            s_desc[2 * slot] = kd0[q];
+            s_desc[2 * slot + 1] = kd1[q];
+        }
+    }
+    for (int i = tid + kStageRegs * nt; i < n; i += nt) {
         const float x = xy[2 * i], y = xy[2 * i + 1];
         const int c = cell_of(y, kd.invh, R) * C + cell_of(x, kd.invw, C);
-        const int slot = atomicAdd(&s_cs[c + 1], 1);   // ends as the first slot of c + 1
+        const int slot = atomicAdd(&s_cs[c + 1], 1);
         KpRec r;
         r.x = x;
         r.y = y;
@@ -526,9 +567,11 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                     run_a += a;
                     run_m += m;
                 }
-            s_cnt[2 * PPL * kWavesPerWG] = run_a ? atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfAdd], run_a) : 0u;
-            s_cnt[2 * PPL * kWavesPerWG + 1] =
-                run_m ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], run_m) : 0u;
+            // both list reservations are issued before either result is used
+            const uint32_t ba = run_a ? atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfAdd], run_a) : 0u;
+            const uint32_t bm = run_m ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], run_m) : 0u;
+            s_cnt[2 * PPL * kWavesPerWG] = ba;
+            s_cnt[2 * PPL * kWavesPerWG + 1] = bm;
         }
         __syncthreads();
         {

@@ -462,8 +462,14 @@ def gen_c4(seed: int = 404, n: int = 50000, outlier_frac: float = 0.1, outlier_p
     th = rng.uniform(0.0, 2 * np.pi, n)
     uv[out] += outlier_px * np.stack([np.cos(th[out]), np.sin(th[out])], axis=1)
     xi0 = np.array([np.deg2rad(1.0), 0.0, 0.0, 0.0, 0.05, 0.0, 0.02])
+    # an evaluation point near the truth built from plain pose algebra (for
+    # timing runs): rotate 1 deg about x, shift 5 cm along y, scale by e^0.02
+    R, t, s = _split(S)
+    Rd = _rodrigues(np.array([1.0, 0.0, 0.0]), np.deg2rad(1.0))
+    sd = float(np.exp(0.02))
+    S_eval = _sim3(Rd @ R, sd * (Rd @ t) + np.array([0.0, 0.05, 0.0]), sd * s)
     return dict(xyz=X, uv=uv.astype(np.float32), S_true=S, cam=_cam_row(CAM_752),
-                xi0=xi0, outlier=out, huber_delta=2.45)
+                xi0=xi0, S_eval=S_eval, S_eval_f32=_sim3_f32(S_eval), outlier=out, huber_delta=2.45)
 
 
 def gen_c5_event(e: int, n_kf: Optional[int] = None, n_mp: Optional[int] = None) -> Event:

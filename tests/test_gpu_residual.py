@@ -149,22 +149,32 @@ def test_refine_events_matches_oracle_gn(ctx):
     xyz, uv = ev.mp_xyz[mp], ev.kp_xy[kp]
     T32 = ev.kf_T.astype(np.float32).astype(np.float64)   # the keyframe poses the GPU sees
     S_ref = R.gauss_newton(ev.S_init, xyz, uv, kf, T32, ev.cams[0], 2.45, iters=10)
-    for graph in (False, True):
+    finals = {}
+    for mode in ("scan", "graph", "batched"):
         event_S = t(ev.S_init.reshape(1, 13).copy())
         nm = torch.zeros(1, dtype=torch.int32, device=dev())
         ref = (10, 2.45, event_S, None, nm)
-        if graph:
+        if mode == "graph":
             ctx.search_fuse_graph(b, ev.params, refine=ref)
+        elif mode == "batched":
+            got2 = ctx.search_fuse_batched(b, ev.params, refine=ref).numpy()
+            for k in got2:
+                assert np.array_equal(got2[k], out[k]), k
         else:
             ctx.refine_events(b, res, ref)
         S_gpu = event_S.cpu().numpy()[0]
+        finals[mode] = S_gpu
         assert nm.item() == len(acc)
         err = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(S_ref))))
-        assert err < 1e-6, (graph, err)
+        assert err < 1e-6, (mode, err)
         # and the refinement moved toward the truth
         e_true = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(ev.S_true))))
         e_init = np.linalg.norm(sim3.log(sim3.compose(ev.S_init, sim3.inverse(ev.S_true))))
         assert e_true < e_init
+    # the list-driven refinements see the same pairs (their order follows the
+    # order in which tiles finish, so the float64 sums may differ in rounding)
+    d = np.linalg.norm(sim3.log(sim3.compose(finals["graph"], sim3.inverse(finals["batched"]))))
+    assert d < 1e-9, d
 
 
 def test_zero_pairs(ctx):
