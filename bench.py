@@ -275,6 +275,10 @@ class Bench:
         log(f"batched: warmup {args.warmup}, timing {args.steps} steps")
         ms_step = self.events_time(step, args.steps, args.warmup)
         log(f"batched: {ms_step * 1e3:.1f} us per event (device-resident)")
+        ms_eager = self.events_time(
+            lambda: ctx.search_fuse_batched(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched)),
+            args.steps, args.warmup)
+        log(f"batched, eager launches: {ms_eager * 1e3:.1f} us per event (device-resident)")
 
         e2e = []
         for i in range(args.warmup + args.steps):
@@ -309,8 +313,8 @@ class Bench:
         rr["frac"] = rr["achieved"] / rr["peak"]
         roof, other = (rr, rs) if kr_ms > ks_ms else (rs, rr)
         log(f"kernels: search {ks_ms * 1e3:.1f} us, refine {kr_ms * 1e3:.1f} us ({n_acc} accepted pairs)")
-        return dict(ev=ev, n_pairs=n_pairs, ms_step=ms_step, ms_e2e=ms_e2e, plain=plain, tuning=tuning,
-                    roof=roof, other=other, n_acc=n_acc)
+        return dict(ev=ev, n_pairs=n_pairs, ms_step=ms_step, ms_e2e=ms_e2e, ms_eager=ms_eager, plain=plain,
+                    tuning=tuning, roof=roof, other=other, n_acc=n_acc)
 
     def batch_graph(self, ev, label, steps):
         """Graph launches (search + refinement) of one batch, device-resident,
@@ -488,6 +492,7 @@ def main():
                              "300,000 dense pairs; search-and-fuse + 10 Gauss-Newton Sim3 steps",
                     n_pairs=h["n_pairs"], n_kf=ev.n_kf, n_mp=ev.n_mp, gn_iters=GN_ITERS, tuning=h["tuning"]),
         ms_per_event_batched=h["ms_step"], ms_per_event_batched_with_d2h=h["ms_e2e"],
+        ms_per_event_batched_eager_launches=h["ms_eager"],
         plain=plain,
         batched_vs_plain=(plain["ms_per_event"] / h["ms_e2e"]) if plain else None,
         batched_vs_plain_device_resident=(plain["ms_per_event"] / h["ms_step"]) if plain else None,

@@ -127,7 +127,7 @@ __device__ void block_exclusive_scan(int32_t* a, int n, int32_t* s_tmp) {
 
 template <bool STAGE_DESC>
 __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_cs, KpRec* s_rec, uint4* s_desc,
-                               int32_t* s_hash, int32_t* s_tmp) {
+                               int32_t* s_own, int32_t* s_hash, int32_t* s_tmp) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int n = kd.n_kp;
     const int cells = h.cells, C = h.grid_cols, R = h.grid_rows;
@@ -141,7 +141,7 @@ __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_c
     // keypoints (keyframes larger than kStageRegs * blockDim) are reloaded.
     constexpr int kStageRegs = 1;
     float kx[kStageRegs], ky[kStageRegs];
-    int ko[kStageRegs], kc[kStageRegs];
+    int ko[kStageRegs], kc[kStageRegs], kw[kStageRegs];
     uint4 kd0[kStageRegs], kd1[kStageRegs];
 #pragma unroll
     for (int q = 0; q < kStageRegs; ++q) {
@@ -157,6 +157,7 @@ __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_c
                 kd1[q] = src[1];
             }
             const int32_t o = h.kp_owner[kd.kp_off + i];
+            kw[q] = o;
             kc[q] = cell_of(ky[q], kd.invh, R) * C + cell_of(kx[q], kd.invw, C);
             atomicAdd(&s_cs[kc[q] + 1], 1);
             if (o >= 0) owner_insert(s_hash, hmask, o);
@@ -180,6 +181,7 @@ __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_c
         r.idx = tid + q * nt;
         r.oct = ko[q];
         s_rec[slot] = r;
+        s_own[slot] = kw[q];
         if (STAGE_DESC) {
             s_desc[2 * slot] = kd0[q];
             s_desc[2 * slot + 1] = kd1[q];
@@ -195,6 +197,7 @@ __device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_c
         r.idx = i;
         r.oct = (int)h.kp_oct[kd.kp_off + i];
         s_rec[slot] = r;
+        s_own[slot] = h.kp_owner[kd.kp_off + i];
         if (STAGE_DESC) {
             const uint4* src = reinterpret_cast<const uint4*>(h.kp_desc + 32 * ((int64_t)kd.kp_off + i));
             s_desc[2 * slot] = src[0];
@@ -335,6 +338,7 @@ struct KfView {
     const KpRec* rec;
     const uint4* desc;          // cell-ordered descriptors (LDS or workspace), or null
     const uint8_t* desc_orig;   // keypoint descriptors by original index (when desc is null)
+    const int32_t* own;         // cell-ordered owners (LDS), or null: read kp_owner by index
     const int32_t* hash;
     int32_t hash_mask;
 };
@@ -342,7 +346,7 @@ struct KfView {
 // LDS bytes of the search kernel (shared with the host).
 __host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cells, int hash_cap) {
     if (mode == kModeGlobal) return 16;
-    size_t b = 16 * (size_t)kp_cap;
+    size_t b = 20 * (size_t)kp_cap;   // records + owners
     if (mode == kModeLdsDesc) b += 32 * (size_t)kp_cap;
     b += 4 * (size_t)((cells + 4 + 3) & ~3);
     b += 4 * (size_t)hash_cap;
@@ -360,6 +364,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     KpRec* s_rec = reinterpret_cast<KpRec*>(s_mem);
     uint4* s_desc = nullptr;
     int32_t* s_cs = nullptr;
+    int32_t* s_own = nullptr;
     int32_t* s_hash = nullptr;
     int32_t* s_tmp = nullptr;
     int32_t* s_flag = reinterpret_cast<int32_t*>(s_mem);
@@ -371,6 +376,8 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             s_desc = reinterpret_cast<uint4*>(p);
             p += 32 * (size_t)h.lds_kp_cap;
         }
+        s_own = reinterpret_cast<int32_t*>(p);
+        p += 4 * (size_t)h.lds_kp_cap;
         s_cs = reinterpret_cast<int32_t*>(p);
         p += 4 * (size_t)((h.cells + 4 + 3) & ~3);
         s_hash = reinterpret_cast<int32_t*>(p);
@@ -447,18 +454,20 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             v.rec = h.recs + kd.kp_off;
             v.desc = h.desc_sorted + 2 * (int64_t)kd.kp_off;
             v.desc_orig = nullptr;
+            v.own = nullptr;
             v.hash = h.hash + kd.hash_off;
             v.hash_mask = kd.hash_mask;
         } else {
             if (staged != k) {
                 __syncthreads();   // every reader of the previous keyframe is done
-                stage_keyframe<MODE == kModeLdsDesc>(h, kd, s_cs, s_rec, s_desc, s_hash, s_tmp);
+                stage_keyframe<MODE == kModeLdsDesc>(h, kd, s_cs, s_rec, s_desc, s_own, s_hash, s_tmp);
                 staged = k;
             }
             v.cs = s_cs;
             v.rec = s_rec;
             v.desc = MODE == kModeLdsDesc ? s_desc : nullptr;
             v.desc_orig = h.kp_desc + 32 * (int64_t)kd.kp_off;
+            v.own = s_own;
             v.hash = s_hash;
             v.hash_mask = h.lds_hash_mask;
         }
@@ -484,6 +493,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             best.init();
             int32_t target = -1;
             float ku = 0.0f, kv = 0.0f;
+            int bslot = 0;
             if (dec[r] == kDecUndecided) {
                 Proj p;
                 if (!project(kd, px[r], py[r], pz[r], pdm[r], gate, sf, N, p)) {
@@ -514,13 +524,15 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                             if (best.key != before) {
                                 ku = rc.x;
                                 kv = rc.y;
+                                bslot = i;
                             }
                         }
                     }
                     if (!accept_match(best, th, ratio)) {
                         dec[r] = FL_NO_MATCH;
                     } else {
-                        const int32_t ow = h.kp_owner[kd.kp_off + (int32_t)(best.key & 0xFFFFu)];
+                        const int32_t ow = v.own ? v.own[bslot]
+                                                 : h.kp_owner[kd.kp_off + (int32_t)(best.key & 0xFFFFu)];
                         if (ow >= 0) {
                             dec[r] = FL_FUSE;
                             target = ow;
