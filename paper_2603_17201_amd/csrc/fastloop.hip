@@ -347,7 +347,10 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             kd.pair_off = B->pair_offset[k];
             kd.n_pairs = B->pair_offset[k + 1] - B->pair_offset[k];
             kd.n_tiles = (int32_t)((kd.n_pairs + tile_pairs - 1) / tile_pairs);
-            int64_t acap = std::min<int64_t>(kd.n_pairs, (int64_t)kd.n_kp + 256);
+            // room for every pair: no provisional ADD can overflow the list, so
+            // the kernel resolves them without cache write-backs (the test
+            // hook's smaller caps exercise the overflow protocol)
+            int64_t acap = kd.n_pairs;
             if (c->add_cap_override > 0) acap = std::min<int64_t>(acap, c->add_cap_override);
             kd.add_off = (int32_t)add_total;
             kd.add_cap = (int32_t)acap;
@@ -373,12 +376,12 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     int grid = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
     if (!graph) grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles));
     pr.grid = grid;
-    const size_t o_range = blob_take<int2>(blob, grid);
+    const size_t o_range = blob_take<int4>(blob, grid);
     kfd = (KfDesc*)(blob.data() + o_kf);
     evd = (EventDesc*)(blob.data() + o_ev);
     order = (int32_t*)(blob.data() + o_order);
     prefix = (int32_t*)(blob.data() + o_prefix);
-    int2* wr = (int2*)(blob.data() + o_range);
+    int4* wr = (int4*)(blob.data() + o_range);
     {
         // cumulative cost at each tile boundary, by keyframe
         std::vector<double> kcum(n_kf + 1, 0.0);
@@ -415,7 +418,13 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         } else {
             for (int i = 0; i < grid; ++i) wg_of[i] = i;
         }
-        for (int i = 0; i < grid; ++i) wr[wg_of[i]] = make_int2((int)bound[i], (int)bound[i + 1]);
+        for (int i = 0; i < grid; ++i) {
+            // slot of the first tile: prefix[slot] <= tile < prefix[slot + 1]
+            const int64_t t0 = bound[i];
+            int slot = (int)(std::upper_bound(prefix, prefix + n_kf + 1, (int32_t)t0) - prefix) - 1;
+            slot = std::min(std::max(slot, 0), std::max(n_kf - 1, 0));
+            wr[wg_of[i]] = make_int4((int)t0, (int)bound[i + 1], slot, order[slot]);
+        }
     }
 
     // workspace layout
@@ -440,14 +449,13 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const size_t L_match = take(sizeof(MatchRec) * (size_t)list_total);
     const int refine_blocks = std::max(1, std::min(kRefMaxB, kRefineGrid / std::max(1, n_ev)));
     const size_t n_rows = 2 * (size_t)n_ev * refine_blocks;
-    const size_t part_tags = align_up(sizeof(double) * kNAcc * n_rows, 256);
     int rc = c->ws.ensure(off);
     if (rc) return rc;
     // Tags in the partial-sum buffer must never match a tag of a later
     // launch: the buffer is zeroed when allocated and whenever the epoch
     // restarts.
     const void* old_part = c->part.p;
-    rc = c->part.ensure(part_tags + sizeof(unsigned long long) * n_rows, 0x00);
+    rc = c->part.ensure(sizeof(unsigned long long) * kRefWords * n_rows, 0x00);
     if (rc) return rc;
     rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(B->n_kp_total, 1), 0xFF);
     if (rc) return rc;
@@ -492,7 +500,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.ev = (const EventDesc*)(base + L_blob + o_ev);
     h.kf_order = (const int32_t*)(base + L_blob + o_order);
     h.tile_prefix = (const int32_t*)(base + L_blob + o_prefix);
-    h.wg_range = (const int2*)(base + L_blob + o_range);
+    h.wg_range = (const int4*)(base + L_blob + o_range);
     h.kp_xy = B->kp_xy;
     h.kp_oct = B->kp_octave;
     h.kp_desc = B->kp_desc;
@@ -521,8 +529,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.match_list = (MatchRec*)(base + L_match);
     h.refine_blocks = refine_blocks;
     h.refine_scan = refine_scan ? 1 : 0;
-    h.refine_partial = (double*)c->part.p;
-    h.refine_tag = (unsigned long long*)((char*)c->part.p + part_tags);
+    h.refine_rows = (unsigned long long*)c->part.p;
     if (refine) {
         h.refine_iters = R->n_iters;
         h.huber_delta = R->huber_delta;

@@ -48,6 +48,10 @@ struct alignas(16) EventDesc {
 };
 
 // Provisional ADD: a pair whose point claimed a free keypoint.
+// s_waitcnt immediate with vmcnt = 0 and expcnt / lgkmcnt left at their
+// maxima (no wait): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 struct alignas(16) AddRef {
     int32_t pair;     // global pair index
     int32_t kp;       // global keypoint index
@@ -104,7 +108,7 @@ struct alignas(16) BatchHdr {
     const EventDesc* ev;
     const int32_t* kf_order;    // keyframes in tile order
     const int32_t* tile_prefix; // [n_kf+1] first tile of each keyframe in tile order
-    const int2* wg_range;       // [n_wg] tile range of each workgroup
+    const int4* wg_range;       // [n_wg] tiles [x, y) of each workgroup, slot z and keyframe w of tile x
     // inputs (caller-owned)
     const float* kp_xy;
     const int8_t* kp_oct;
@@ -138,8 +142,7 @@ struct alignas(16) BatchHdr {
     double* event_S;            // [n_events][13] caller's, in/out
     fl_sim3* event_S32_out;     // caller's (may be null)
     int32_t* event_n_matched;   // caller's (may be null)
-    double* refine_partial;     // [2][n_events * refine_blocks][kNAccPad] (alternating by step)
-    unsigned long long* refine_tag;   // [2][n_events * refine_blocks]: launch epoch << 32 | step + 1
+    unsigned long long* refine_rows;   // [2][n_events * refine_blocks][2 * kNAccPad] tagged partial-sum words
 };
 
 // ---------------------------------------------------------------------------

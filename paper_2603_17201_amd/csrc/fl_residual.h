@@ -38,6 +38,17 @@ struct RecipTable {
 };
 __device__ constexpr RecipTable kRecip{};
 
+// 1/x to within about one ulp: the hardware estimate refined by two Newton
+// steps (cheaper on the serial path of a step than a correctly rounded
+// division).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // exp of a tangent xi = (omega, upsilon, sigma):  R = exp([omega]x),
 // s = e^sigma, t = V upsilon with V = integral_0^1 e^{sigma tau} exp(tau [omega]x) d tau
 // = c0 I + c1 W + c2 W^2 (closed form; series for small rotation angles).
@@ -47,9 +58,12 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
     const double th = sqrt(th2);
     double a, b;
-    if (th < 1e-4) {
-        a = 1.0 - th2 * (1.0 / 6.0) + th2 * th2 * (1.0 / 120.0);
-        b = 0.5 - th2 * (1.0 / 24.0) + th2 * th2 * (1.0 / 720.0);
+    if (th < 1e-2) {
+        // sin(th)/th and (1 - cos(th))/th^2 by their Taylor series: the next
+        // terms are below th^8/9! < 3e-22 here
+        const double t4 = th2 * th2;
+        a = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t4 * th2 * (1.0 / 5040.0);
+        b = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t4 * th2 * (1.0 / 40320.0);
     } else {
         a = sin(th) / th;
         b = (1.0 - cos(th)) / th2;
@@ -57,7 +71,22 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     // I_n(sigma) for n = 0..6 and e^sigma = sum_k sigma^k / k! share one series
     double I[7];
     double es;
-    if (fabs(sig) < 2.0) {
+    if (fabs(sig) < 0.01) {
+        // |sigma| < 0.01: nine terms of each series (the rest is below
+        // 0.01^9 / 9! < 3e-24); I_n = sum_k sigma^k / (k! (n + k + 1))
+        double p[9];
+        p[0] = 1.0;
+        for (int k = 1; k < 9; ++k) p[k] = p[k - 1] * sig * kRecip.v[k - 1];   // sigma^k / k!
+        es = 0.0;
+        for (int k = 8; k >= 0; --k) es += p[k];
+#pragma unroll
+        for (int n = 0; n < 7; ++n) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 8; k >= 0; --k) v = fma(p[k], kRecip.v[n + k], v);
+            I[n] = v;
+        }
+    } else if (fabs(sig) < 2.0) {
         double term = 1.0, e = 0.0;
         for (int n = 0; n < 7; ++n) I[n] = 0.0;
         for (int k = 0; k < 60; ++k) {
@@ -133,9 +162,18 @@ __device__ inline void sim3_to_f32(const Sim3d& S, fl_sim3* o) {
     o->pad[0] = o->pad[1] = o->pad[2] = 0.0f;
 }
 
+// The part of the float32 form the residual reads (sR, t), for the steps
+// inside a refinement; inv_s is filled in once at the end.
+__device__ inline void sim3_to_f32_pose(const Sim3d& S, fl_sim3* o) {
+    for (int i = 0; i < 9; ++i) o->sR[i] = (float)(S.s * S.R[i]);
+    for (int i = 0; i < 3; ++i) o->t[i] = (float)S.t[i];
+}
+
 // Solve (H + lambda diag H) d = -g by an LDL^T factorisation (no square
 // roots; one reciprocal per pivot); H given as its 28 upper entries row by
 // row.  Returns false (d = 0) for a pivot that is not clearly positive.
+// Written with explicit fused multiply-adds: it runs on one lane, so its
+// dependency chains are its cost.
 __device__ inline bool solve7(const double* g, const double* Hu, double lambda, double* d) {
     double A[7][7];
     int k = 0;
@@ -150,31 +188,31 @@ __device__ inline bool solve7(const double* g, const double* Hu, double lambda, 
         A[i][i] *= (1.0 + lambda);
         dmax = fmax(dmax, fabs(A[i][i]));
     }
-    double L[7][7], D[7], Dinv[7];
+    double L[7][7], LD[7][7], Dinv[7];   // LD[i][m] = L[i][m] D[m]
     for (int j = 0; j < 7; ++j) {
         double dj = A[j][j];
-        for (int m = 0; m < j; ++m) dj -= L[j][m] * L[j][m] * D[m];
+        for (int m = 0; m < j; ++m) dj = fma(-L[j][m], LD[j][m], dj);
         if (!(dj > 1e-14 * dmax)) {
             for (int i = 0; i < 7; ++i) d[i] = 0.0;
             return false;
         }
-        D[j] = dj;
-        Dinv[j] = 1.0 / dj;
+        Dinv[j] = recip(dj);
         for (int i = j + 1; i < 7; ++i) {
             double v = A[i][j];
-            for (int m = 0; m < j; ++m) v -= L[i][m] * L[j][m] * D[m];
+            for (int m = 0; m < j; ++m) v = fma(-L[i][m], LD[j][m], v);
             L[i][j] = v * Dinv[j];
+            LD[i][j] = v;   // L[i][j] * D[j]
         }
     }
     double y[7];
     for (int i = 0; i < 7; ++i) {
         double v = -g[i];
-        for (int m = 0; m < i; ++m) v -= L[i][m] * y[m];
+        for (int m = 0; m < i; ++m) v = fma(-L[i][m], y[m], v);
         y[i] = v;
     }
     for (int i = 6; i >= 0; --i) {
         double v = y[i] * Dinv[i];
-        for (int m = i + 1; m < 7; ++m) v -= L[m][i] * d[m];
+        for (int m = i + 1; m < 7; ++m) v = fma(-L[m][i], d[m], v);
         d[i] = v;
     }
     return true;
@@ -206,7 +244,7 @@ __device__ __forceinline__ void pair_term(const float* A, const float* tS, const
         o.r0 = o.r1 = o.w = o.rho = 0.0f;
         return;
     }
-    const float iz = 1.0f / q2;
+    const float iz = __builtin_amdgcn_rcpf(q2);   // within 1 ulp
     o.r0 = fx * q0 * iz + cx - uo;
     o.r1 = fy * q1 * iz + cy - vo;
     const float e = sqrtf(o.r0 * o.r0 + o.r1 * o.r1);
@@ -214,7 +252,7 @@ __device__ __forceinline__ void pair_term(const float* A, const float* tS, const
         o.w = 1.0f;
         o.rho = 0.5f * e * e;
     } else {
-        o.w = delta / e;
+        o.w = delta * __builtin_amdgcn_rcpf(e);
         o.rho = delta * e - 0.5f * delta * delta;
     }
     if (!need_J) return;
@@ -243,22 +281,18 @@ __device__ __forceinline__ void pair_term(const float* A, const float* tS, const
     }
 }
 
-// acc[0..6] += w J^T r, acc[7..34] += w J^T J (upper, row by row), in float64
+// acc[0..6] += w J^T r, acc[7..34] += w J^T J (upper, row by row): each
+// pair's terms in float32 (as its residual and Jacobian are), accumulated
+// over pairs in float64.
 __device__ __forceinline__ void accumulate(const PairTerm& t, double* acc) {
-    const double w = t.w, r0 = t.r0, r1 = t.r1;
-    double J0[7], J1[7];
+    const float w = t.w, r0 = t.r0, r1 = t.r1;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        J0[i] = t.J[0][i];
-        J1[i] = t.J[1][i];
-    }
-#pragma unroll
-    for (int i = 0; i < 7; ++i) acc[i] += w * (J0[i] * r0 + J1[i] * r1);
+    for (int i = 0; i < 7; ++i) acc[i] += (double)(w * fmaf(t.J[0][i], r0, t.J[1][i] * r1));
     int k = 7;
 #pragma unroll
     for (int i = 0; i < 7; ++i)
 #pragma unroll
-        for (int j = i; j < 7; ++j) acc[k++] += w * (J0[i] * J0[j] + J1[i] * J1[j]);
+        for (int j = i; j < 7; ++j) acc[k++] += (double)(w * fmaf(t.J[0][i], t.J[0][j], t.J[1][i] * t.J[1][j]));
 }
 
 // Block reduction of NV <= 64 doubles per thread, fixed order.  Inside a
@@ -297,6 +331,50 @@ __device__ __forceinline__ void block_reduce(double* v, double* s_red, double* s
         for (int q = 0; q < nw; ++q) s += s_red[q * NV + threadIdx.x];
         s_out[threadIdx.x] = s;
     }
+    __syncthreads();
+}
+
+// The same sums in float32, for a thread's few register-held pairs (it adds
+// at most two terms before they are widened to float64).
+__device__ __forceinline__ void accumulate_f32(const PairTerm& t, float* acc) {
+    const float w = t.w, r0 = t.r0, r1 = t.r1;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] += w * fmaf(t.J[0][i], r0, t.J[1][i] * r1);
+    int k = 7;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = i; j < 7; ++j) acc[k++] += w * fmaf(t.J[0][i], t.J[0][j], t.J[1][i] * t.J[1][j]);
+}
+
+// Fixed-order block reduction through LDS for the refinement: every thread
+// writes its NV values into column-major s_t (column stride blockDim + 1,
+// so both passes are free of bank conflicts), then 4 NV threads each add a
+// quarter of one column and NV threads add the four quarters.  s_t holds
+// NV * (NT + 1) doubles, s_q 4 NV; the block has NT threads, a multiple of
+// 16.  Result in s_out[0..NV) after the call.
+template <int NV, int NT>
+__device__ __forceinline__ void block_reduce_lds(const double* v, double* s_t, double* s_q, double* s_out) {
+    constexpr int ld = NT + 1, per = NT / 4;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) s_t[c * ld + tid] = v[c];
+    __syncthreads();
+    if (tid < 4 * NV) {
+        const int c = tid % NV, q = tid / NV;
+        const double* col = s_t + c * ld + q * per;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int r = 0; r < per; r += 4) {
+            a0 += col[r];
+            a1 += col[r + 1];
+            a2 += col[r + 2];
+            a3 += col[r + 3];
+        }
+        s_q[q * NV + c] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    if (tid < NV) s_out[tid] = (s_q[tid] + s_q[NV + tid]) + (s_q[2 * NV + tid] + s_q[3 * NV + tid]);
     __syncthreads();
 }
 
@@ -466,9 +544,6 @@ __global__ void gn_step_kernel(const double* __restrict__ g, const double* __res
 // whole grid is one workgroup per CU); its spin is bounded and a timeout is
 // reported as n_matched = -1.
 
-// s_waitcnt immediate with vmcnt = 0 and expcnt / lgkmcnt left at their
-// maxima (no wait): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
-constexpr int kWaitVmcnt0 = 0x0F70;
 constexpr unsigned kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ void refine_accumulate(const float* T, float fx, float fy, float cx, float cy, float x,
@@ -482,15 +557,33 @@ __device__ __forceinline__ void refine_accumulate(const float* T, float fx, floa
     }
 }
 
+__device__ __forceinline__ void refine_accumulate_f32(const float* T, float fx, float fy, float cx, float cy, float x,
+                                                      float y, float z, float uo, float vo, const fl_sim3& S,
+                                                      float delta, float* acc) {
+    PairTerm t;
+    pair_term(S.sR, S.t, T, fx, fy, cx, cy, x, y, z, uo, vo, delta, true, t);
+    if (t.valid) {
+        accumulate_f32(t, acc);
+        acc[35] += 1.0f;
+    }
+}
+
 constexpr int kRefCache = 2;     // accepted pairs a thread keeps in registers across the steps
 constexpr int kRefKfLds = 64;    // keyframes of one event whose pose and intrinsics sit in LDS
 constexpr int kRefMaxB = 64;     // workgroups per event
-constexpr int kRefGather = (kRefMaxB * kNAcc + kResBlock - 1) / kResBlock;
+// Each float64 partial travels as two 64-bit words, (high half << 32 | tag)
+// and (low half << 32 | tag): a word is written and read in one piece, so a
+// reader that sees the tag of the current launch and step in both words has
+// the value, without a separate flag or any cache maintenance.
+constexpr int kRefWords = 2 * kNAcc;
+constexpr int kRefGather = (kRefMaxB * kRefWords + kResBlock - 1) / kResBlock;
+
+constexpr int kRefLds = kNAcc * (kResBlock + 1) > kRefMaxB * kNAcc ? kNAcc * (kResBlock + 1) : kRefMaxB * kNAcc;
 
 __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
-    __shared__ double s_red[(kResBlock / kWave) * kNAcc];
+    __shared__ double s_big[kRefLds];   // the block reduction's transpose, then the gathered rows
+    __shared__ double s_q[4 * kNAcc];
     __shared__ double s_out[kNAcc];
-    __shared__ double s_chunk[kRefMaxB * kNAcc];
     __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
     __shared__ double s_S64[13];
     __shared__ fl_sim3 s_S;
@@ -501,7 +594,7 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
     const int iters = h.refine_iters;
     const float delta = h.huber_delta;
     const int tid = threadIdx.x;
-    const unsigned long long tag0 = (unsigned long long)(*h.epoch) << 32;
+    const uint32_t tag0 = *h.epoch << 10;   // tag of step it: tag0 | (it + 1), it < 1000
     for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
         const int ev = unit / B, b = unit % B;
         const EventDesc ed = h.ev[ev];
@@ -545,19 +638,24 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
 #pragma unroll
             for (int i = 0; i < kNAcc; ++i) acc[i] = 0.0;
             if (use_list) {
+                float accf[kNAcc];
+#pragma unroll
+                for (int i = 0; i < kNAcc; ++i) accf[i] = 0.0f;
 #pragma unroll
                 for (int r = 0; r < kRefCache; ++r) {
                     if (ck_[r] < 0) continue;
                     if (kf_lds) {
                         const float* q = &s_kf[16 * (ck_[r] - ed.kf_begin)];
-                        refine_accumulate(q, q[12], q[13], q[14], q[15], cx_[r], cy_[r], cz_[r], cu_[r], cv_[r], S,
-                                          delta, acc);
+                        refine_accumulate_f32(q, q[12], q[13], q[14], q[15], cx_[r], cy_[r], cz_[r], cu_[r], cv_[r],
+                                              S, delta, accf);
                     } else {
                         const KfDesc& kd = h.kf[ck_[r]];
-                        refine_accumulate(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, cx_[r], cy_[r], cz_[r], cu_[r], cv_[r],
-                                          S, delta, acc);
+                        refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, cx_[r], cy_[r], cz_[r], cu_[r],
+                                              cv_[r], S, delta, accf);
                     }
                 }
+#pragma unroll
+                for (int i = 0; i < kNAcc; ++i) acc[i] = (double)accf[i];
                 for (int i = b * blockDim.x + tid + kRefCache * stride; i < (int)cnt; i += stride) {
                     const MatchRec m = h.match_list[ed.list_off + i];
                     const KfDesc& kd = h.kf[m.kf];
@@ -580,67 +678,71 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                     }
                 }
             }
-            block_reduce<kNAcc>(acc, s_red, s_out);
+            block_reduce_lds<kNAcc, kResBlock>(acc, s_big, s_q, s_out);
             if (B > 1) {
-                // Exchange of the B partial sums of this step.  Each workgroup
-                // writes its row with device-coherent (agent-scope) stores,
-                // waits until they have completed (vmcnt 0; the 36 stores are
-                // all in wave 0) and only then writes the row's tag (launch
-                // epoch, step).  Readers poll the B tags, one lane each, and
-                // load the rows after every tag matched, so no L2 write-back
-                // or invalidation is needed and no two workgroups write one
-                // address.  Rows alternate between two buffers by step: a
-                // workgroup writes step it + 2 only after every row of step
-                // it + 1 was tagged, i.e. after every reader of step it is done.
+                // Exchange of the B partial sums of this step as tagged words
+                // (device-coherent stores and loads).  Rows alternate between
+                // two buffers by step: a workgroup writes step it + 2 only
+                // after it has read every row of step it + 1, which every
+                // workgroup writes only after reading all rows of step it.
                 const size_t slot = ((size_t)(it & 1) * n_units + (size_t)ev * B);
-                double* rows = h.refine_partial + slot * kNAcc;
-                unsigned long long* tags = h.refine_tag + slot;
-                const unsigned long long tag = tag0 | (unsigned)(it + 1);
-                if (tid < kWave) {
-                    if (tid < kNAcc)
-                        __hip_atomic_store(&rows[(size_t)b * kNAcc + tid], s_out[tid], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-                    if (tid == 0) __hip_atomic_store(&tags[b], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (tid < B) {
-                        unsigned spins = 0;
-                        while (__hip_atomic_load(&tags[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
-                            __builtin_amdgcn_s_sleep(1);
-                            if (++spins > kSpinLimit) {
-                                s_fail = 1;
-                                break;
-                            }
+                unsigned long long* rows = h.refine_rows + slot * kRefWords;
+                const uint32_t tag = tag0 | (uint32_t)(it + 1);
+                if (tid < kRefWords) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(s_out[tid >> 1]);
+                    const uint32_t half = (tid & 1) ? (uint32_t)bits : (uint32_t)(bits >> 32);
+                    __hip_atomic_store(&rows[(size_t)b * kRefWords + tid], ((unsigned long long)half << 32) | tag,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                unsigned long long wv[kRefGather];
+                uint32_t pending = 0;
+#pragma unroll
+                for (int q = 0; q < kRefGather; ++q)
+                    if (tid + q * kResBlock < B * kRefWords) pending |= 1u << q;
+                unsigned spins = 0;
+                while (pending) {
+#pragma unroll
+                    for (int q = 0; q < kRefGather; ++q)
+                        if (pending >> q & 1u)
+                            wv[q] = __hip_atomic_load(&rows[tid + q * kResBlock], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int q = 0; q < kRefGather; ++q)
+                        if ((pending >> q & 1u) && (uint32_t)wv[q] == tag) pending &= ~(1u << q);
+                    if (pending) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kSpinLimit) {
+                            s_fail = 1;
+                            break;
                         }
                     }
                 }
+                uint32_t* s_half = reinterpret_cast<uint32_t*>(s_big);
+#pragma unroll
+                for (int q = 0; q < kRefGather; ++q)
+                    if (tid + q * kResBlock < B * kRefWords) s_half[tid + q * kResBlock] = (uint32_t)(wv[q] >> 32);
                 __syncthreads();
                 if (s_fail) break;
-                double gv[kRefGather];
+                // the same fixed order in every workgroup, so all of them
+                // solve for bitwise the same step: quarter q adds rows
+                // q, q + 4, ..., then the quarters are added pairwise
+                if (tid < 4 * kNAcc) {
+                    const int c = tid % kNAcc, q = tid / kNAcc;
+                    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-                for (int q = 0; q < kRefGather; ++q) {
-                    const int i = tid + q * kResBlock;
-                    if (i < B * kNAcc) gv[q] = __hip_atomic_load(&rows[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-#pragma unroll
-                for (int q = 0; q < kRefGather; ++q) {
-                    const int i = tid + q * kResBlock;
-                    if (i < B * kNAcc) s_chunk[i] = gv[q];
+                    for (int j = 0; j < kRefMaxB / 4; ++j) {
+                        const int r = q + 4 * j;
+                        if (r < B) {
+                            const uint32_t hi = s_half[r * kRefWords + 2 * c], lo = s_half[r * kRefWords + 2 * c + 1];
+                            const double x = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+                            if (j & 1) a1 += x; else a0 += x;
+                        }
+                    }
+                    s_q[q * kNAcc + c] = a0 + a1;
                 }
                 __syncthreads();
-                if (tid < kNAcc) {
-                    // the same fixed order in every workgroup: all of them
-                    // solve for bitwise the same step
-                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                    int r = 0;
-                    for (; r + 3 < B; r += 4) {
-                        a0 += s_chunk[(r + 0) * kNAcc + tid];
-                        a1 += s_chunk[(r + 1) * kNAcc + tid];
-                        a2 += s_chunk[(r + 2) * kNAcc + tid];
-                        a3 += s_chunk[(r + 3) * kNAcc + tid];
-                    }
-                    for (; r < B; ++r) a0 += s_chunk[r * kNAcc + tid];
-                    s_out[tid] = (a0 + a1) + (a2 + a3);
-                }
+                if (tid < kNAcc)
+                    s_out[tid] = (s_q[tid] + s_q[kNAcc + tid]) + (s_q[2 * kNAcc + tid] + s_q[3 * kNAcc + tid]);
                 __syncthreads();
             }
             if (tid == 0) {
@@ -648,7 +750,7 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                 if (solve7(s_out, s_out + 7, 0.0, d)) {
                     const Sim3d Sd = sim3_mul(sim3_exp(d), sim3_load(s_S64));
                     sim3_store(Sd, s_S64);
-                    sim3_to_f32(Sd, &s_S);
+                    sim3_to_f32_pose(Sd, &s_S);
                 }
             }
             __syncthreads();
@@ -656,7 +758,7 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
         if (b == 0 && tid == 0) {
             if (!s_fail) {
                 for (int i = 0; i < 13; ++i) h.event_S[13 * (int64_t)ev + i] = s_S64[i];
-                if (h.event_S32_out) h.event_S32_out[ev] = s_S;
+                if (h.event_S32_out) sim3_to_f32(sim3_load(s_S64), &h.event_S32_out[ev]);
             }
             if (h.event_n_matched) h.event_n_matched[ev] = s_fail ? -1 : (int32_t)s_out[35];
             h.ev_ctr[ev * kEvCtrs + kEvMatch] = 0;   // the event's list is spent

@@ -395,24 +395,24 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
     unsigned long long st_vis = 0, st_cells = 0, st_kp = 0, st_cand = 0;
 
-    const int2 range = h.wg_range[blockIdx.x];
-    int slot = 0;
-    {   // keyframe (in tile order) of the first tile: tile_prefix[slot] <= t < tile_prefix[slot + 1]
-        int lo = 0, hi = h.n_kf;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (h.tile_prefix[mid] <= range.x) lo = mid; else hi = mid;
-        }
-        slot = lo;
-    }
+    // tiles [x, y); the first one belongs to slot z (keyframe w) of the tile order
+    const int4 range = h.wg_range[blockIdx.x];
+    int slot = range.z;
     int staged = -1;
     for (int t = range.x; t < range.y; ++t) {
         while (t >= h.tile_prefix[slot + 1]) ++slot;
-        const int k = h.kf_order[slot];
+        const int k = t == range.x ? range.w : h.kf_order[slot];
         const KfDesc kd = h.kf[k];            // by value: kept in registers across the stores below
         const EventDesc ed = h.ev[kd.event];
         const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
         const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
+        // With room for every pair in the ADD list (the normal case) each output
+        // has a single writer: the decision and target of a provisional ADD are
+        // written only by the keyframe's resolver, from coherent list entries
+        // and claims, so no tile needs an L2 write-back.  With a capped list a
+        // provisional ADD may be written here and relabelled later, and tiles
+        // release their stores with a device-scope fence.
+        const bool single_writer = kd.add_cap >= kd.n_pairs;
 
         // Point loads of every pair of this thread are issued first, so their
         // latency overlaps the keyframe staging below.
@@ -544,14 +544,16 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             }
             const int bidx = best.key == 0xFFFFFFFFu ? -1 : (int)(best.key & 0xFFFFu);
             const int kpg = kd.kp_off + (bidx < 0 ? 0 : bidx);
+            const bool is_add = active && dec[r] == FL_ADD;
             if (active) {
                 h.best_idx[o] = bidx;
                 h.best_dist[o] = (int16_t)(best.key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(best.key >> 16));
                 h.second_dist[o] = (int16_t)best.second;
-                h.decision[o] = dec[r];
-                h.target[o] = target;
+                if (!(is_add && single_writer)) {
+                    h.decision[o] = dec[r];
+                    h.target[o] = target;
+                }
             }
-            const bool is_add = active && dec[r] == FL_ADD;
             if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp[r]);
             // list entries are written after the tile with one atomic per list
             add_want[r] = is_add;
@@ -597,12 +599,22 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 if (add_want[r]) {
                     const uint32_t idx = base_a + s_cnt[(2 * r) * kWavesPerWG + wid] + (uint32_t)__popcll(ma & below);
                     if (idx < (uint32_t)kd.add_cap) {
-                        AddRef ae;
-                        ae.pair = (int32_t)o;
-                        ae.kp = add_kp[r];
-                        ae.gp = gp[r];
-                        ae.pad = 0;
-                        h.add_list[kd.add_off + idx] = ae;
+                        AddRef* ae = &h.add_list[kd.add_off + idx];
+                        if (single_writer) {   // read by the resolver with coherent loads
+                            const unsigned long long lo = (uint32_t)o | ((unsigned long long)(uint32_t)add_kp[r] << 32);
+                            const unsigned long long hi = (uint32_t)gp[r];
+                            __hip_atomic_store(reinterpret_cast<unsigned long long*>(ae), lo, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(reinterpret_cast<unsigned long long*>(ae) + 1, hi, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            AddRef e;
+                            e.pair = (int32_t)o;
+                            e.kp = add_kp[r];
+                            e.gp = gp[r];
+                            e.pad = 0;
+                            *ae = e;
+                        }
                     }
                 }
                 if (acc_want[r]) {
@@ -624,7 +636,45 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         }
 
         // Tile done; the workgroup completing a keyframe resolves its ADD
-        // conflicts.  The barrier orders every wave's stores before thread 0's
+        // conflicts.
+        if (single_writer) {
+            // Every list entry and claim of this tile has completed (coherent
+            // stores and device atomics, vmcnt 0) before thread 0 counts the tile.
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            __syncthreads();
+            if (tid == 0)
+                s_flag[0] = atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfDone], 1u) == (uint32_t)(kd.n_tiles - 1);
+            __syncthreads();
+            if (s_flag[0]) {
+                const uint32_t n_add = min(__hip_atomic_load(&h.kf_ctr[k * kKfCtrs + kKfAdd], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT),
+                                           (uint32_t)kd.add_cap);
+                for (uint32_t i = tid; i < n_add; i += kSearchBlock) {
+                    const unsigned long long* ae =
+                        reinterpret_cast<const unsigned long long*>(&h.add_list[kd.add_off + i]);
+                    const unsigned long long lo = __hip_atomic_load(ae, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long hi = __hip_atomic_load(ae + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int32_t pair = (int32_t)(uint32_t)lo, kp = (int32_t)(uint32_t)(lo >> 32);
+                    const int32_t gpi = (int32_t)(uint32_t)hi;
+                    const int32_t w = (int32_t)(__hip_atomic_load(&h.claim[kp], __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT) - tag);
+                    if (w == gpi) {
+                        h.decision[pair] = FL_ADD;
+                        h.target[pair] = -1;
+                    } else {
+                        h.decision[pair] = FL_FUSE;
+                        h.target[pair] = h.mp_id ? h.mp_id[w] : w;
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    h.kf_ctr[k * kKfCtrs + kKfDone] = 0;
+                    h.kf_ctr[k * kKfCtrs + kKfAdd] = 0;
+                }
+            }
+            continue;
+        }
+        // Capped list: the barrier orders every wave's stores before thread 0's
         // device-scope release (an L2 write-back, so one per tile, not one per
         // wave); the resolver's acquire invalidates this CU's caches.
         __syncthreads();
