@@ -633,7 +633,7 @@ int launch_refine(fl_ctx* c, const BatchHdr* dh, int n_iters, hipStream_t s, boo
         FL_HIP(hipEventCreate(&t1));
         FL_HIP(hipEventRecord(t0, s));
     }
-    hipLaunchKernelGGL(refine_kernel, dim3(kRefineGrid), dim3(kResBlock), 0, s, dh);
+    hipLaunchKernelGGL(refine_kernel, dim3(kRefineGrid), dim3(kRefBlock), 0, s, dh);
     if (timed) {
         FL_HIP(hipEventRecord(t1, s));
         c->prof_ev[FL_PROF_REFINE].emplace_back(t0, t1);

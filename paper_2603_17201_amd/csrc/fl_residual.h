@@ -172,47 +172,52 @@ __device__ inline void sim3_to_f32_pose(const Sim3d& S, fl_sim3* o) {
 // Solve (H + lambda diag H) d = -g by an LDL^T factorisation (no square
 // roots; one reciprocal per pivot); H given as its 28 upper entries row by
 // row.  Returns false (d = 0) for a pivot that is not clearly positive.
-// Written with explicit fused multiply-adds: it runs on one lane, so its
-// dependency chains are its cost.
+// In place on the packed lower triangle (a[i(i+1)/2 + j] = H[i][j], then
+// L[i][j] D[j] below the diagonal), with explicit fused multiply-adds: it
+// runs on one lane, so its dependency chains and registers are its cost.
 __device__ inline bool solve7(const double* g, const double* Hu, double lambda, double* d) {
-    double A[7][7];
-    int k = 0;
+    double a[28];
     double dmax = 0.0;
-    for (int i = 0; i < 7; ++i)
-        for (int j = i; j < 7; ++j) {
-            A[i][j] = Hu[k];
-            A[j][i] = Hu[k];
-            ++k;
-        }
+#pragma unroll
     for (int i = 0; i < 7; ++i) {
-        A[i][i] *= (1.0 + lambda);
-        dmax = fmax(dmax, fabs(A[i][i]));
+#pragma unroll
+        for (int j = 0; j <= i; ++j) a[i * (i + 1) / 2 + j] = Hu[j * 7 - j * (j - 1) / 2 + (i - j)];
+        a[i * (i + 1) / 2 + i] *= (1.0 + lambda);
+        dmax = fmax(dmax, fabs(a[i * (i + 1) / 2 + i]));
     }
-    double L[7][7], LD[7][7], Dinv[7];   // LD[i][m] = L[i][m] D[m]
+    double L[21], Dinv[7];   // L[i(i-1)/2 + j] = L[i][j], j < i
+#pragma unroll
     for (int j = 0; j < 7; ++j) {
-        double dj = A[j][j];
-        for (int m = 0; m < j; ++m) dj = fma(-L[j][m], LD[j][m], dj);
+        double dj = a[j * (j + 1) / 2 + j];
+#pragma unroll
+        for (int m = 0; m < j; ++m) dj = fma(-L[j * (j - 1) / 2 + m], a[j * (j + 1) / 2 + m], dj);
         if (!(dj > 1e-14 * dmax)) {
             for (int i = 0; i < 7; ++i) d[i] = 0.0;
             return false;
         }
         Dinv[j] = recip(dj);
+#pragma unroll
         for (int i = j + 1; i < 7; ++i) {
-            double v = A[i][j];
-            for (int m = 0; m < j; ++m) v = fma(-L[i][m], LD[j][m], v);
-            L[i][j] = v * Dinv[j];
-            LD[i][j] = v;   // L[i][j] * D[j]
+            double v = a[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int m = 0; m < j; ++m) v = fma(-L[i * (i - 1) / 2 + m], a[j * (j + 1) / 2 + m], v);
+            a[i * (i + 1) / 2 + j] = v;   // L[i][j] D[j]
+            L[i * (i - 1) / 2 + j] = v * Dinv[j];
         }
     }
     double y[7];
+#pragma unroll
     for (int i = 0; i < 7; ++i) {
         double v = -g[i];
-        for (int m = 0; m < i; ++m) v = fma(-L[i][m], y[m], v);
+#pragma unroll
+        for (int m = 0; m < i; ++m) v = fma(-L[i * (i - 1) / 2 + m], y[m], v);
         y[i] = v;
     }
+#pragma unroll
     for (int i = 6; i >= 0; --i) {
         double v = y[i] * Dinv[i];
-        for (int m = i + 1; m < 7; ++m) v = fma(-L[m][i], d[m], v);
+#pragma unroll
+        for (int m = i + 1; m < 7; ++m) v = fma(-L[m * (m - 1) / 2 + i], d[m], v);
         d[i] = v;
     }
     return true;
@@ -348,19 +353,29 @@ __device__ __forceinline__ void accumulate_f32(const PairTerm& t, float* acc) {
 }
 
 // Fixed-order block reduction through LDS for the refinement: every thread
-// writes its NV values into column-major s_t (column stride blockDim + 1,
-// so both passes are free of bank conflicts), then 4 NV threads each add a
-// quarter of one column and NV threads add the four quarters.  s_t holds
-// NV * (NT + 1) doubles, s_q 4 NV; the block has NT threads, a multiple of
-// 16.  Result in s_out[0..NV) after the call.
+// writes its NV values into column-major s_t (column stride NT + 1, so both
+// passes are free of bank conflicts), then kSeg NV threads each add one of
+// kSeg segments of a column and NV threads add the segments pairwise.  s_t
+// holds NV * (NT + 1) doubles, s_q kSeg NV; the block has NT threads, a
+// multiple of 4 kSeg and at least kSeg NV.  Result in s_out[0..NV) after the
+// call.
+constexpr int kSeg = 8;
+
+template <int NV>
+__device__ __forceinline__ double add_segments(const double* s_q, int c) {
+    return ((s_q[c] + s_q[NV + c]) + (s_q[2 * NV + c] + s_q[3 * NV + c])) +
+           ((s_q[4 * NV + c] + s_q[5 * NV + c]) + (s_q[6 * NV + c] + s_q[7 * NV + c]));
+}
+
 template <int NV, int NT>
 __device__ __forceinline__ void block_reduce_lds(const double* v, double* s_t, double* s_q, double* s_out) {
-    constexpr int ld = NT + 1, per = NT / 4;
+    static_assert(NT % (4 * kSeg) == 0 && NT >= kSeg * NV, "block shape");
+    constexpr int ld = NT + 1, per = NT / kSeg;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int c = 0; c < NV; ++c) s_t[c * ld + tid] = v[c];
     __syncthreads();
-    if (tid < 4 * NV) {
+    if (tid < kSeg * NV) {
         const int c = tid % NV, q = tid / NV;
         const double* col = s_t + c * ld + q * per;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -374,7 +389,7 @@ __device__ __forceinline__ void block_reduce_lds(const double* v, double* s_t, d
         s_q[q * NV + c] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
-    if (tid < NV) s_out[tid] = (s_q[tid] + s_q[NV + tid]) + (s_q[2 * NV + tid] + s_q[3 * NV + tid]);
+    if (tid < NV) s_out[tid] = add_segments<NV>(s_q, tid);
     __syncthreads();
 }
 
@@ -571,18 +586,19 @@ __device__ __forceinline__ void refine_accumulate_f32(const float* T, float fx, 
 constexpr int kRefCache = 2;     // accepted pairs a thread keeps in registers across the steps
 constexpr int kRefKfLds = 64;    // keyframes of one event whose pose and intrinsics sit in LDS
 constexpr int kRefMaxB = 64;     // workgroups per event
+constexpr int kRefBlock = 320;   // threads of a refinement workgroup: 64 x 320 pairs at one per thread
 // Each float64 partial travels as two 64-bit words, (high half << 32 | tag)
 // and (low half << 32 | tag): a word is written and read in one piece, so a
 // reader that sees the tag of the current launch and step in both words has
 // the value, without a separate flag or any cache maintenance.
 constexpr int kRefWords = 2 * kNAcc;
-constexpr int kRefGather = (kRefMaxB * kRefWords + kResBlock - 1) / kResBlock;
+constexpr int kRefGather = (kRefMaxB * kRefWords + kRefBlock - 1) / kRefBlock;
 
-constexpr int kRefLds = kNAcc * (kResBlock + 1) > kRefMaxB * kNAcc ? kNAcc * (kResBlock + 1) : kRefMaxB * kNAcc;
+constexpr int kRefLds = kNAcc * (kRefBlock + 1) > kRefMaxB * kNAcc ? kNAcc * (kRefBlock + 1) : kRefMaxB * kNAcc;
 
-__global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
+__global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
     __shared__ double s_big[kRefLds];   // the block reduction's transpose, then the gathered rows
-    __shared__ double s_q[4 * kNAcc];
+    __shared__ double s_q[kSeg * kNAcc];
     __shared__ double s_out[kNAcc];
     __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
     __shared__ double s_S64[13];
@@ -613,7 +629,15 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
         if (tid == 0) sim3_to_f32(sim3_load(s_S64), &s_S);
         const uint32_t cnt = h.ev_ctr[ev * kEvCtrs + kEvMatch];
         const bool use_list = !h.refine_scan && cnt <= (uint32_t)ed.list_cap;
-        const int stride = B * blockDim.x;
+        // With the list, the event uses only as many workgroups as give each
+        // thread one pair (every workgroup reads the same count, so all agree
+        // on Be); the others have nothing to add and skip the event.
+        const int Be = use_list ? max(1, min(B, (int)((cnt + blockDim.x - 1) / blockDim.x))) : B;
+        if (b >= Be) {
+            __syncthreads();
+            continue;
+        }
+        const int stride = Be * blockDim.x;
         // this thread's first kRefCache accepted pairs, loaded once
         float cx_[kRefCache], cy_[kRefCache], cz_[kRefCache], cu_[kRefCache], cv_[kRefCache];
         int ck_[kRefCache];
@@ -634,13 +658,14 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
         __syncthreads();
         for (int it = 0; it < iters; ++it) {
             const fl_sim3 S = s_S;
-            double acc[kNAcc];
+            // Each thread adds its few pairs' terms in float32 (one pair per
+            // thread when the list fits the workgroups, a couple of dozen at
+            // most when the event's pairs are scanned); everything across
+            // threads and workgroups is summed in float64.
+            float accf[kNAcc];
 #pragma unroll
-            for (int i = 0; i < kNAcc; ++i) acc[i] = 0.0;
+            for (int i = 0; i < kNAcc; ++i) accf[i] = 0.0f;
             if (use_list) {
-                float accf[kNAcc];
-#pragma unroll
-                for (int i = 0; i < kNAcc; ++i) accf[i] = 0.0f;
 #pragma unroll
                 for (int r = 0; r < kRefCache; ++r) {
                     if (ck_[r] < 0) continue;
@@ -654,12 +679,10 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                                               cv_[r], S, delta, accf);
                     }
                 }
-#pragma unroll
-                for (int i = 0; i < kNAcc; ++i) acc[i] = (double)accf[i];
                 for (int i = b * blockDim.x + tid + kRefCache * stride; i < (int)cnt; i += stride) {
                     const MatchRec m = h.match_list[ed.list_off + i];
                     const KfDesc& kd = h.kf[m.kf];
-                    refine_accumulate(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, m.x, m.y, m.z, m.u, m.v, S, delta, acc);
+                    refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, m.x, m.y, m.z, m.u, m.v, S, delta, accf);
                 }
             } else {
                 // no list (or it overflowed): scan the event's pairs keyframe by keyframe
@@ -673,19 +696,23 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                         const int32_t bi = h.best_idx[o];
                         if (lp < 0 || lp >= kd.n_mp || bi < 0 || bi >= kd.n_kp) continue;
                         const int64_t gp = kd.mp_off + lp, kp = kd.kp_off + bi;
-                        refine_accumulate(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1],
-                                          h.mp_xyz[3 * gp + 2], h.kp_xy[2 * kp], h.kp_xy[2 * kp + 1], S, delta, acc);
+                        refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1],
+                                              h.mp_xyz[3 * gp + 2], h.kp_xy[2 * kp], h.kp_xy[2 * kp + 1], S, delta,
+                                              accf);
                     }
                 }
             }
-            block_reduce_lds<kNAcc, kResBlock>(acc, s_big, s_q, s_out);
-            if (B > 1) {
-                // Exchange of the B partial sums of this step as tagged words
+            double acc[kNAcc];
+#pragma unroll
+            for (int i = 0; i < kNAcc; ++i) acc[i] = (double)accf[i];
+            block_reduce_lds<kNAcc, kRefBlock>(acc, s_big, s_q, s_out);
+            if (Be > 1) {
+                // Exchange of the Be partial sums of this step as tagged words
                 // (device-coherent stores and loads).  Rows alternate between
                 // two buffers by step: a workgroup writes step it + 2 only
                 // after it has read every row of step it + 1, which every
                 // workgroup writes only after reading all rows of step it.
-                const size_t slot = ((size_t)(it & 1) * n_units + (size_t)ev * B);
+                const size_t slot = ((size_t)(it & 1) * n_units + (size_t)ev * B);   // rows of this step: Be
                 unsigned long long* rows = h.refine_rows + slot * kRefWords;
                 const uint32_t tag = tag0 | (uint32_t)(it + 1);
                 if (tid < kRefWords) {
@@ -694,21 +721,28 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                     __hip_atomic_store(&rows[(size_t)b * kRefWords + tid], ((unsigned long long)half << 32) | tag,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                // every word of this thread is loaded at once; words whose
+                // tag is not yet the current one are loaded again
+                uint32_t* s_half = reinterpret_cast<uint32_t*>(s_big);
+                const int n_words = Be * kRefWords;
                 unsigned long long wv[kRefGather];
-                uint32_t pending = 0;
+                unsigned long long pending = 0;
 #pragma unroll
                 for (int q = 0; q < kRefGather; ++q)
-                    if (tid + q * kResBlock < B * kRefWords) pending |= 1u << q;
+                    if (tid + q * kRefBlock < n_words) pending |= 1ull << q;
                 unsigned spins = 0;
                 while (pending) {
 #pragma unroll
                     for (int q = 0; q < kRefGather; ++q)
-                        if (pending >> q & 1u)
-                            wv[q] = __hip_atomic_load(&rows[tid + q * kResBlock], __ATOMIC_RELAXED,
+                        if (pending >> q & 1ull)
+                            wv[q] = __hip_atomic_load(&rows[tid + q * kRefBlock], __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
                     for (int q = 0; q < kRefGather; ++q)
-                        if ((pending >> q & 1u) && (uint32_t)wv[q] == tag) pending &= ~(1u << q);
+                        if ((pending >> q & 1ull) && (uint32_t)wv[q] == tag) {
+                            s_half[tid + q * kRefBlock] = (uint32_t)(wv[q] >> 32);
+                            pending &= ~(1ull << q);
+                        }
                     if (pending) {
                         __builtin_amdgcn_s_sleep(1);
                         if (++spins > kSpinLimit) {
@@ -717,22 +751,18 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                         }
                     }
                 }
-                uint32_t* s_half = reinterpret_cast<uint32_t*>(s_big);
-#pragma unroll
-                for (int q = 0; q < kRefGather; ++q)
-                    if (tid + q * kResBlock < B * kRefWords) s_half[tid + q * kResBlock] = (uint32_t)(wv[q] >> 32);
                 __syncthreads();
                 if (s_fail) break;
                 // the same fixed order in every workgroup, so all of them
-                // solve for bitwise the same step: quarter q adds rows
-                // q, q + 4, ..., then the quarters are added pairwise
-                if (tid < 4 * kNAcc) {
+                // solve for bitwise the same step: segment q adds rows
+                // q, q + kSeg, ..., then the segments are added pairwise
+                if (tid < kSeg * kNAcc) {
                     const int c = tid % kNAcc, q = tid / kNAcc;
                     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-                    for (int j = 0; j < kRefMaxB / 4; ++j) {
-                        const int r = q + 4 * j;
-                        if (r < B) {
+                    for (int j = 0; j < kRefMaxB / kSeg; ++j) {
+                        const int r = q + kSeg * j;
+                        if (r < Be) {
                             const uint32_t hi = s_half[r * kRefWords + 2 * c], lo = s_half[r * kRefWords + 2 * c + 1];
                             const double x = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
                             if (j & 1) a1 += x; else a0 += x;
@@ -741,8 +771,7 @@ __global__ __launch_bounds__(kResBlock) void refine_kernel(const BatchHdr* __res
                     s_q[q * kNAcc + c] = a0 + a1;
                 }
                 __syncthreads();
-                if (tid < kNAcc)
-                    s_out[tid] = (s_q[tid] + s_q[kNAcc + tid]) + (s_q[2 * kNAcc + tid] + s_q[3 * kNAcc + tid]);
+                if (tid < kNAcc) s_out[tid] = add_segments<kNAcc>(s_q, tid);
                 __syncthreads();
             }
             if (tid == 0) {

@@ -387,7 +387,12 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         s_flag = reinterpret_cast<int32_t*>(p);
     }
 
-    const float* sf = h.sf;
+    // the octave scale table in LDS: the octave search and the window radius
+    // index it per lane
+    __shared__ float s_sf[FL_MAX_OCTAVES];
+    if (tid < FL_MAX_OCTAVES) s_sf[tid] = h.sf[tid];
+    __syncthreads();
+    const float* sf = s_sf;
     const int N = h.n_octaves, gate = h.gate, C = h.grid_cols, R = h.grid_rows, th = h.hamming_th;
     const float ratio = h.nn_ratio, r0w = h.r0;
     const bool dense = h.dense != 0;
@@ -773,6 +778,9 @@ struct PlainArgs {
 };
 
 __global__ __launch_bounds__(256) void search_plain_kernel(PlainArgs a) {
+    __shared__ float s_sf[FL_MAX_OCTAVES];
+    if (threadIdx.x < FL_MAX_OCTAVES) s_sf[threadIdx.x] = a.sc.sf[threadIdx.x];
+    __syncthreads();
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = o < a.n_mp;
     const KfDesc& kd = a.kd;
@@ -788,12 +796,12 @@ __global__ __launch_bounds__(256) void search_plain_kernel(PlainArgs a) {
         const float x = a.mp_xyz[3 * o], y = a.mp_xyz[3 * o + 1], z = a.mp_xyz[3 * o + 2];
         const float dmax = sc.gate ? a.mp_dmax[o] : 0.0f;
         Proj p;
-        if (!project(kd, x, y, z, dmax, sc.gate, sc.sf, sc.N, p)) {
+        if (!project(kd, x, y, z, dmax, sc.gate, s_sf, sc.N, p)) {
             dec = FL_NOT_VISIBLE;
         } else {
             uint4 a0, a1;
             load_desc(a.mp_desc, o, a0, a1);
-            const Window w = make_window(p, kd, sc.sf, sc.r0, sc.C, sc.R);
+            const Window w = make_window(p, kd, s_sf, sc.r0, sc.C, sc.R);
             for (int row = w.r0; row <= w.r1; ++row) {
                 // a caller-supplied grid is clamped to the keypoint range
                 const int s = max(a.cell_start[row * sc.C + w.c0], 0);
