@@ -301,10 +301,24 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     pr.lds = search_lds_bytes(pr.mode, kp_cap, cells, lds_hash_cap);
     if (graph && pr.mode != kModeGlobal) pr.lds = std::min(c->lds_max, align_up(pr.lds, 16384));
 
+    // workgroups of the search launch (every slot in graph mode, at most one
+    // per tile otherwise)
+    int64_t n_tiles_all = 0;
+    for (int k = 0; k < n_kf; ++k)
+        n_tiles_all += (B->pair_offset[k + 1] - B->pair_offset[k] + tile_pairs - 1) / tile_pairs;
+    int grid = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
+    if (!graph) grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles_all));
+    pr.grid = grid;
+
+    // Table blob: header, the workgroups' tile ranges and the keyframe table
+    // first, at offsets the kernel derives from its grid size alone.
     std::vector<char>& blob = pr.blob;
     blob.clear();
     const size_t o_hdr = blob_take<BatchHdr>(blob, 1);
+    const size_t o_range = blob_take<int4>(blob, grid);
     const size_t o_kf = blob_take<KfDesc>(blob, n_kf);
+    if (o_hdr != 0 || o_range != blob_range_offset() || o_kf != blob_kf_offset(grid))
+        return fail(FL_EINVAL, "internal: table layout mismatch");
     const size_t o_ev = blob_take<EventDesc>(blob, n_ev);
     const size_t o_order = blob_take<int32_t>(blob, n_kf);
     const size_t o_prefix = blob_take<int32_t>(blob, n_kf + 1);
@@ -372,15 +386,8 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         if (n_tiles > INT32_MAX / 2) return fail(FL_ERANGE, "too many tiles");
     }
     prefix[n_kf] = (int32_t)n_tiles;
-    // workgroups and their contiguous, cost-balanced tile ranges
-    int grid = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
-    if (!graph) grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles));
-    pr.grid = grid;
-    const size_t o_range = blob_take<int4>(blob, grid);
-    kfd = (KfDesc*)(blob.data() + o_kf);
-    evd = (EventDesc*)(blob.data() + o_ev);
-    order = (int32_t*)(blob.data() + o_order);
-    prefix = (int32_t*)(blob.data() + o_prefix);
+    if (n_tiles != n_tiles_all) return fail(FL_EINVAL, "internal: tile count mismatch");
+    // the workgroups' contiguous, cost-balanced tile ranges
     int4* wr = (int4*)(blob.data() + o_range);
     {
         // cumulative cost at each tile boundary, by keyframe

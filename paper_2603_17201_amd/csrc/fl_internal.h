@@ -48,6 +48,13 @@ struct alignas(16) EventDesc {
 };
 
 // Provisional ADD: a pair whose point claimed a free keypoint.
+// Offsets in the table blob (which starts at the batch header) of the
+// workgroups' tile ranges and of the keyframe table: fixed by the header size
+// and the search grid, so a workgroup finds its range and first keyframe
+// without first loading pointers.
+constexpr size_t kBlobAlign = 256;
+__host__ __device__ constexpr size_t blob_align(size_t x) { return (x + kBlobAlign - 1) / kBlobAlign * kBlobAlign; }
+
 // s_waitcnt immediate with vmcnt = 0 and expcnt / lgkmcnt left at their
 // maxima (no wait): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -144,6 +151,12 @@ struct alignas(16) BatchHdr {
     int32_t* event_n_matched;   // caller's (may be null)
     unsigned long long* refine_rows;   // [2][n_events * refine_blocks][2 * kNAccPad] tagged partial-sum words
 };
+
+__host__ __device__ constexpr size_t blob_range_offset() { return blob_align(sizeof(BatchHdr)); }
+__host__ __device__ constexpr size_t blob_kf_offset(int grid) {
+    return blob_align(blob_range_offset() + sizeof(int4) * (size_t)(grid > 1 ? grid : 1));
+}
+
 
 // ---------------------------------------------------------------------------
 // float32 helpers whose rounding is fixed: every multiply-add written as

@@ -367,8 +367,8 @@ __device__ __forceinline__ double add_segments(const double* s_q, int c) {
            ((s_q[4 * NV + c] + s_q[5 * NV + c]) + (s_q[6 * NV + c] + s_q[7 * NV + c]));
 }
 
-template <int NV, int NT>
-__device__ __forceinline__ void block_reduce_lds(const double* v, double* s_t, double* s_q, double* s_out) {
+template <int NV, int NT, typename T>
+__device__ __forceinline__ void block_reduce_lds(const T* v, T* s_t, double* s_q, double* s_out) {
     static_assert(NT % (4 * kSeg) == 0 && NT >= kSeg * NV, "block shape");
     constexpr int ld = NT + 1, per = NT / kSeg;
     const int tid = threadIdx.x;
@@ -377,14 +377,14 @@ __device__ __forceinline__ void block_reduce_lds(const double* v, double* s_t, d
     __syncthreads();
     if (tid < kSeg * NV) {
         const int c = tid % NV, q = tid / NV;
-        const double* col = s_t + c * ld + q * per;
+        const T* col = s_t + c * ld + q * per;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
         for (int r = 0; r < per; r += 4) {
-            a0 += col[r];
-            a1 += col[r + 1];
-            a2 += col[r + 2];
-            a3 += col[r + 3];
+            a0 += (double)col[r];
+            a1 += (double)col[r + 1];
+            a2 += (double)col[r + 2];
+            a3 += (double)col[r + 3];
         }
         s_q[q * NV + c] = (a0 + a1) + (a2 + a3);
     }
@@ -594,10 +594,12 @@ constexpr int kRefBlock = 320;   // threads of a refinement workgroup: 64 x 320 
 constexpr int kRefWords = 2 * kNAcc;
 constexpr int kRefGather = (kRefMaxB * kRefWords + kRefBlock - 1) / kRefBlock;
 
-constexpr int kRefLds = kNAcc * (kRefBlock + 1) > kRefMaxB * kNAcc ? kNAcc * (kRefBlock + 1) : kRefMaxB * kNAcc;
+// 32-bit words of the shared buffer: the block reduction's float32 transpose,
+// later the gathered 32-bit halves of the partial sums
+constexpr int kRefLds = kNAcc * (kRefBlock + 1) > kRefMaxB * kRefWords ? kNAcc * (kRefBlock + 1) : kRefMaxB * kRefWords;
 
 __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
-    __shared__ double s_big[kRefLds];   // the block reduction's transpose, then the gathered rows
+    __shared__ uint32_t s_big[kRefLds];   // the block reduction's transpose, then the gathered rows
     __shared__ double s_q[kSeg * kNAcc];
     __shared__ double s_out[kNAcc];
     __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
@@ -702,10 +704,9 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                     }
                 }
             }
-            double acc[kNAcc];
-#pragma unroll
-            for (int i = 0; i < kNAcc; ++i) acc[i] = (double)accf[i];
-            block_reduce_lds<kNAcc, kRefBlock>(acc, s_big, s_q, s_out);
+            // the per-thread float32 sums go through LDS as they are and are
+            // widened as the segments are added
+            block_reduce_lds<kNAcc, kRefBlock>(accf, reinterpret_cast<float*>(s_big), s_q, s_out);
             if (Be > 1) {
                 // Exchange of the Be partial sums of this step as tagged words
                 // (device-coherent stores and loads).  Rows alternate between
@@ -723,7 +724,7 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                 }
                 // every word of this thread is loaded at once; words whose
                 // tag is not yet the current one are loaded again
-                uint32_t* s_half = reinterpret_cast<uint32_t*>(s_big);
+                uint32_t* s_half = s_big;
                 const int n_words = Be * kRefWords;
                 unsigned long long wv[kRefGather];
                 unsigned long long pending = 0;

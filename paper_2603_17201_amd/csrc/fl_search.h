@@ -400,14 +400,18 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
     unsigned long long st_vis = 0, st_cells = 0, st_kp = 0, st_cand = 0;
 
-    // tiles [x, y); the first one belongs to slot z (keyframe w) of the tile order
-    const int4 range = h.wg_range[blockIdx.x];
+    // tiles [x, y); the first one belongs to slot z (keyframe w) of the tile
+    // order.  The ranges and the keyframe table sit at offsets of the table
+    // blob that follow from the grid size, so neither waits for a pointer.
+    const char* blob = reinterpret_cast<const char*>(hp);
+    const int4 range = reinterpret_cast<const int4*>(blob + blob_range_offset())[blockIdx.x];
+    const KfDesc* kf_tab = reinterpret_cast<const KfDesc*>(blob + blob_kf_offset((int)gridDim.x));
     int slot = range.z;
     int staged = -1;
     for (int t = range.x; t < range.y; ++t) {
         while (t >= h.tile_prefix[slot + 1]) ++slot;
         const int k = t == range.x ? range.w : h.kf_order[slot];
-        const KfDesc kd = h.kf[k];            // by value: kept in registers across the stores below
+        const KfDesc kd = kf_tab[k];          // by value: kept in registers across the stores below
         const EventDesc ed = h.ev[kd.event];
         const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
         const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
