@@ -196,6 +196,16 @@ class Bench:
             stream.synchronize()
         return (time.perf_counter() - t0) * 1e3
 
+    def hbm_copy_gbs(self):
+        """Device-to-device copy of 1 GiB (read + write counted), for context
+        beside the published HBM peak."""
+        torch = self.torch
+        x = torch.empty(256 << 20, dtype=torch.float32, device=self.dev)
+        y = torch.empty_like(x)
+        ms = self.events_time(lambda: y.copy_(x), 10, 2)
+        del x, y
+        return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
     def copy_probe(self):
         """A plain device copy of 256 MiB: the reference kernel for scaling
         the HBM byte counters."""
@@ -471,6 +481,8 @@ def main():
     h = bench.headline()
 
     secondary = None
+    hbm_meas = bench.hbm_copy_gbs()
+    log(f"measured device copy: {hbm_meas:.0f} GB/s (read + write)")
     if not args.quick:
         secondary = {"uneven_event_60kf": bench.batch_graph(synth.gen_c3(), "uneven event", args.steps)}
         evs = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
@@ -513,6 +525,7 @@ def main():
         roofline=h["roof"],
         roofline_other_kernel=h["other"],
         cpu_baseline=cpu,
+        measured_hbm_copy_gbs=hbm_meas,
         secondary=secondary,
     )
     bench.ctx.close()
