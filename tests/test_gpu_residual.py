@@ -184,3 +184,58 @@ def test_zero_pairs(ctx):
     _, _, loss = ctx.residual_fwd(z3, z2, None, None, S, synth.scenes._cam_row(synth.CAM_752), 2.45)
     g, H = ctx.residual_bwd(z3, z2, None, None, S, synth.scenes._cam_row(synth.CAM_752), 2.45)
     assert loss.item() == 0.0 and torch.all(g == 0) and torch.all(H == 0)
+
+
+def _event_gn(B, out, e, iters=10):
+    """Float64 Gauss-Newton of event e of batch B on the pairs the oracle
+    accepted, with the keyframe poses the device sees (float32)."""
+    ekf, emp = B.event_kf_offset, B.event_mp_offset
+    xyz, uv, kfl = [], [], []
+    for k in range(int(ekf[e]), int(ekf[e + 1])):
+        p0, p1 = int(B.pair_offset[k]), int(B.pair_offset[k + 1])
+        d = out["decision"][p0:p1]
+        acc = np.nonzero((d == oracle.ADD) | (d == oracle.FUSE))[0]
+        local = B.pair_mp[p0 + acc] if B.pair_mp is not None else acc
+        xyz.append(B.mp_xyz[int(emp[e]) + np.asarray(local, np.int64)])
+        uv.append(B.kp_xy[int(B.kp_offset[k]) + out["best_idx"][p0 + acc]])
+        kfl.append(np.full(len(acc), k - int(ekf[e]), np.int32))
+    xyz, uv, kfl = np.concatenate(xyz), np.concatenate(uv), np.concatenate(kfl)
+    if len(xyz) == 0:
+        return None, 0
+    T32 = B.kf_T[int(ekf[e]):int(ekf[e + 1])].astype(np.float32).astype(np.float64)
+    S = R.gauss_newton(B.events[e].S_init, xyz, uv, kfl, T32, B.cams[int(ekf[e])], 2.45, iters=iters)
+    return S, len(xyz)
+
+
+def test_refine_multi_event_batch(ctx):
+    """Several uneven events in one launch (the refinement grid split among
+    them), one of which accepts no pair, in both launch modes."""
+    import paper_2603_17201_amd as fl
+    e0 = synth.gen_c3(seed=321, n_kf=10, n_mp=5000, id_base=1000, fresh_base=10 ** 9)
+    e1 = synth.gen_tiny(62, n_kf=3, n_mp=400)
+    e2 = synth.gen_c2(seed=207, n_kf=5, n_mp=3000)
+    e3 = synth.gen_tiny(63, n_kf=2, n_mp=150)
+    e3.kp_desc = e3.kp_desc ^ np.uint8(0xFF)   # every distance far above the threshold
+    B = synth.concat_events([e0, e1, e2, e3])
+    exp = oracle.search_fuse(B, use_grid=True)
+    refs = [_event_gn(B, exp, e) for e in range(4)]
+    assert refs[3][1] == 0 and all(n > 100 for _, n in refs[:3])
+    b = fl.DeviceBatch(B, device=dev())
+    S0 = np.stack([ev.S_init for ev in B.events])
+    for mode in ("batched", "graph"):
+        S = t(S0.copy())
+        nm = torch.zeros(4, dtype=torch.int32, device=dev())
+        ref = (10, 2.45, S, None, nm)
+        res = (ctx.search_fuse_batched(b, B.params, refine=ref) if mode == "batched"
+               else ctx.search_fuse_graph(b, B.params, refine=ref))
+        got = res.numpy()
+        for k in got:
+            assert np.array_equal(got[k], exp[k]), (mode, k)
+        S_gpu, n_gpu = S.cpu().numpy(), nm.cpu().numpy()
+        for e, (S_ref, n_ref) in enumerate(refs):
+            assert n_gpu[e] == n_ref, (mode, e)
+            if S_ref is None:   # no pair: the system is singular and the Sim3 is left as it was
+                assert np.array_equal(S_gpu[e], S0[e]), (mode, e)
+                continue
+            err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
+            assert err < 1e-6, (mode, e, err)
