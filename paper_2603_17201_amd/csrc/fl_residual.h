@@ -592,7 +592,6 @@ constexpr int kRefBlock = 320;   // threads of a refinement workgroup: 64 x 320 
 // reader that sees the tag of the current launch and step in both words has
 // the value, without a separate flag or any cache maintenance.
 constexpr int kRefWords = 2 * kNAcc;
-constexpr int kRefGather = (kRefMaxB * kRefWords + kRefBlock - 1) / kRefBlock;
 
 // 32-bit words of the shared buffer: the block reduction's float32 transpose,
 // later the gathered 32-bit halves of the partial sums
@@ -722,56 +721,53 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                     __hip_atomic_store(&rows[(size_t)b * kRefWords + tid], ((unsigned long long)half << 32) | tag,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                // every word of this thread is loaded at once; words whose
-                // tag is not yet the current one are loaded again
-                uint32_t* s_half = s_big;
-                const int n_words = Be * kRefWords;
-                unsigned long long wv[kRefGather];
-                unsigned long long pending = 0;
-#pragma unroll
-                for (int q = 0; q < kRefGather; ++q)
-                    if (tid + q * kRefBlock < n_words) pending |= 1ull << q;
-                unsigned spins = 0;
-                while (pending) {
-#pragma unroll
-                    for (int q = 0; q < kRefGather; ++q)
-                        if (pending >> q & 1ull)
-                            wv[q] = __hip_atomic_load(&rows[tid + q * kRefBlock], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-                    for (int q = 0; q < kRefGather; ++q)
-                        if ((pending >> q & 1ull) && (uint32_t)wv[q] == tag) {
-                            s_half[tid + q * kRefBlock] = (uint32_t)(wv[q] >> 32);
-                            pending &= ~(1ull << q);
-                        }
-                    if (pending) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (++spins > kSpinLimit) {
-                            s_fail = 1;
-                            break;
-                        }
-                    }
-                }
-                __syncthreads();
-                if (s_fail) break;
-                // the same fixed order in every workgroup, so all of them
-                // solve for bitwise the same step: segment q adds rows
-                // q, q + kSeg, ..., then the segments are added pairwise
+                // Thread (c, q) loads the two words of value c of rows q,
+                // q + kSeg, ... (words whose tag is not yet the current one are
+                // loaded again) and adds those rows in that order; then the
+                // segments are added pairwise.  The order is the same in every
+                // workgroup, so all of them solve for bitwise the same step.
                 if (tid < kSeg * kNAcc) {
                     const int c = tid % kNAcc, q = tid / kNAcc;
+                    constexpr int kRowsPer = kRefMaxB / kSeg;
+                    unsigned long long wh[kRowsPer], wl[kRowsPer];
+                    uint32_t pending = 0;
+#pragma unroll
+                    for (int j = 0; j < kRowsPer; ++j)
+                        if (q + kSeg * j < Be) pending |= 1u << j;
+                    unsigned spins = 0;
+                    while (pending) {
+#pragma unroll
+                        for (int j = 0; j < kRowsPer; ++j)
+                            if (pending >> j & 1u) {
+                                const unsigned long long* w = rows + (size_t)(q + kSeg * j) * kRefWords + 2 * c;
+                                wh[j] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                wl[j] = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            }
+#pragma unroll
+                        for (int j = 0; j < kRowsPer; ++j)
+                            if ((pending >> j & 1u) && (uint32_t)wh[j] == tag && (uint32_t)wl[j] == tag)
+                                pending &= ~(1u << j);
+                        if (pending) {
+                            __builtin_amdgcn_s_sleep(1);
+                            if (++spins > kSpinLimit) {
+                                s_fail = 1;
+                                break;
+                            }
+                        }
+                    }
                     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-                    for (int j = 0; j < kRefMaxB / kSeg; ++j) {
-                        const int r = q + kSeg * j;
-                        if (r < Be) {
-                            const uint32_t hi = s_half[r * kRefWords + 2 * c], lo = s_half[r * kRefWords + 2 * c + 1];
-                            const double x = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+                    for (int j = 0; j < kRowsPer; ++j) {
+                        if (q + kSeg * j < Be) {
+                            const double x = __longlong_as_double(
+                                (long long)((wh[j] >> 32 << 32) | (wl[j] >> 32)));
                             if (j & 1) a1 += x; else a0 += x;
                         }
                     }
                     s_q[q * kNAcc + c] = a0 + a1;
                 }
                 __syncthreads();
+                if (s_fail) break;
                 if (tid < kNAcc) s_out[tid] = add_segments<kNAcc>(s_q, tid);
                 __syncthreads();
             }
