@@ -352,6 +352,29 @@ class Bench:
                               steps, 3)
         res = dict(n_events=n_ev, n_kf=b.n_kf, n_pairs=b.n_pairs, ms_per_launch=ms, ms_per_event=ms / n_ev,
                    pairs_per_s=b.n_pairs / (ms * 1e-3))
+        # kernel times of eager launches and the search kernel's roofline at this size
+        ctx.set_stats(True)
+        ctx.search_fuse_batched(b, P, out)
+        torch.cuda.synchronize()
+        st = ctx.get_stats()
+        ctx.set_stats(False)
+        ctx.set_profiling(True)
+        for _ in range(5):
+            S.copy_(S_init)
+            ctx.search_fuse_batched(b, P, out, refine=(GN_ITERS, HUBER, S, None, None))
+        ks_ms, ks_n = ctx.get_profile("search")
+        kr_ms, kr_n = ctx.get_profile("refine")
+        ctx.set_profiling(False)
+        ks_ms /= max(ks_n, 1)
+        kr_ms /= max(kr_n, 1)
+        nbytes, nops = search_bytes(ev, P, b.n_pairs), search_ops(st, b.n_pairs)
+        t_hbm, t_alu = nbytes / (HBM_PEAK_GBS * 1e9), nops / (ALU_PEAK_TOPS * 1e12)
+        if t_alu > t_hbm:
+            roof = dict(bound="alu", achieved=nops / (ks_ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
+        else:
+            roof = dict(bound="hbm", achieved=nbytes / (ks_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+        roof.update(frac=roof["achieved"] / roof["peak"], kernel_us=ks_ms * 1e3, alg_bytes=nbytes, alg_ops=nops)
+        res.update(search_kernel_us=ks_ms * 1e3, refine_kernel_us=kr_ms * 1e3, search_roofline=roof)
         if n_ev == 1 and not self.args.no_plain:
             host, host_S = self.host_buffers(b.n_pairs)
             plan = self.plain_plan(ev, b, out)

@@ -253,4 +253,19 @@ __device__ __forceinline__ bool owner_lookup(const int32_t* __restrict__ table, 
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
 
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
+// lanes inside each row of 16 (DPP row_shr), then the last lane of row 0 is
+// added to row 1 and of row 2 to row 3 (row_bcast:15), and the last lane of
+// row 1 to rows 2 and 3 (row_bcast:31).  Lanes with no source add 0.  Every
+// lane of the wave must be active.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15, rows 1 and 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31, rows 2 and 3
+    return x;
+}
+
 }  // namespace fl

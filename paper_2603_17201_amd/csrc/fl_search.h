@@ -83,37 +83,50 @@ __device__ __forceinline__ void owner_insert(int32_t* tab, int32_t mask, int32_t
     }
 }
 
-// Workgroup exclusive scan of a[0..n) in place (n may exceed blockDim).
-// s_tmp needs blockDim / 64 + 1 ints.
+// Workgroup exclusive scan of a[0..n) in place (n may exceed blockDim): each
+// thread sums a run of consecutive elements, the runs are scanned inside each
+// wave and the wave totals by wave 0.  s_tmp needs blockDim / 64 + 1 ints
+// (s_tmp[blockDim / 64] = total); blockDim is a multiple of 64, at most 4096.
 __device__ void block_exclusive_scan(int32_t* a, int n, int32_t* s_tmp) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = wave_lane(), wid = tid / kWave, nw = nt / kWave;
     const int chunk = (n + nt - 1) / nt;
     const int b = min(tid * chunk, n), e = min(b + chunk, n);
+    constexpr int kRun = 4;   // runs up to this length are loaded at once
+    int v[kRun];
     int sum = 0;
-    for (int i = b; i < e; ++i) sum += a[i];
-    int incl = sum;
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
+    if (chunk <= kRun) {
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) v[j] = b + j < e ? a[b + j] : 0;
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) sum += v[j];
+    } else {
+        for (int i = b; i < e; ++i) sum += a[i];
     }
+    const int incl = wave_incl_scan(sum);
     if (lane == kWave - 1) s_tmp[wid] = incl;
     __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int w = 0; w < nw; ++w) {
-            const int v = s_tmp[w];
-            s_tmp[w] = run;
-            run += v;
-        }
-        s_tmp[nw] = run;
+    if (wid == 0) {
+        const int t = lane < nw ? s_tmp[lane] : 0;
+        const int x = wave_incl_scan(t);
+        if (lane < nw) s_tmp[lane] = x - t;
+        if (lane == nw - 1) s_tmp[nw] = x;
     }
     __syncthreads();
     int run = s_tmp[wid] + incl - sum;
-    for (int i = b; i < e; ++i) {
-        const int v = a[i];
-        a[i] = run;
-        run += v;
+    if (chunk <= kRun) {
+#pragma unroll
+        for (int j = 0; j < kRun; ++j)
+            if (b + j < e) {
+                a[b + j] = run;
+                run += v[j];
+            }
+    } else {
+        for (int i = b; i < e; ++i) {
+            const int x = a[i];
+            a[i] = run;
+            run += x;
+        }
     }
     __syncthreads();
 }
@@ -578,23 +591,29 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             }
         }
         __syncthreads();
-        if (tid == 0) {
-            uint32_t run_a = 0, run_m = 0;
-            for (int r = 0; r < PPL; ++r)
-                for (int w = 0; w < kWavesPerWG; ++w) {
-                    uint32_t& ca = s_cnt[(2 * r) * kWavesPerWG + w];
-                    uint32_t& cm = s_cnt[(2 * r + 1) * kWavesPerWG + w];
-                    const uint32_t a = ca, m = cm;
-                    ca = run_a;
-                    cm = run_m;
-                    run_a += a;
-                    run_m += m;
-                }
-            // both list reservations are issued before either result is used
-            const uint32_t ba = run_a ? atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfAdd], run_a) : 0u;
-            const uint32_t bm = run_m ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], run_m) : 0u;
-            s_cnt[2 * PPL * kWavesPerWG] = ba;
-            s_cnt[2 * PPL * kWavesPerWG + 1] = bm;
+        if (wid == 0) {
+            // wave 0 turns the per-wave counts (pair slot major, wave minor)
+            // into offsets and reserves both lists
+            static_assert(PPL * kWavesPerWG <= kWave, "one count per lane");
+            constexpr int nv = PPL * kWavesPerWG;
+            const int r = lane / kWavesPerWG, w = lane % kWavesPerWG;
+            const bool in = lane < nv;
+            const int ca = in ? (int)s_cnt[(2 * r) * kWavesPerWG + w] : 0;
+            const int cm = in ? (int)s_cnt[(2 * r + 1) * kWavesPerWG + w] : 0;
+            const int ia = wave_incl_scan(ca), im = wave_incl_scan(cm);
+            if (in) {
+                s_cnt[(2 * r) * kWavesPerWG + w] = (uint32_t)(ia - ca);
+                s_cnt[(2 * r + 1) * kWavesPerWG + w] = (uint32_t)(im - cm);
+            }
+            const uint32_t run_a = (uint32_t)__builtin_amdgcn_readlane(ia, nv - 1);
+            const uint32_t run_m = (uint32_t)__builtin_amdgcn_readlane(im, nv - 1);
+            if (lane == 0) {
+                // both list reservations are issued before either result is used
+                const uint32_t ba = run_a ? atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfAdd], run_a) : 0u;
+                const uint32_t bm = run_m ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], run_m) : 0u;
+                s_cnt[2 * PPL * kWavesPerWG] = ba;
+                s_cnt[2 * PPL * kWavesPerWG + 1] = bm;
+            }
         }
         __syncthreads();
         {
