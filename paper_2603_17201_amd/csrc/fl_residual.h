@@ -352,13 +352,16 @@ __device__ __forceinline__ void accumulate_f32(const PairTerm& t, float* acc) {
         for (int j = i; j < 7; ++j) acc[k++] += w * fmaf(t.J[0][i], t.J[0][j], t.J[1][i] * t.J[1][j]);
 }
 
-// Fixed-order block reduction through LDS for the refinement: every thread
-// writes its NV values into column-major s_t (column stride NT + 1, so both
-// passes are free of bank conflicts), then kSeg NV threads each add one of
-// kSeg segments of a column and NV threads add the segments pairwise.  s_t
-// holds NV * (NT + 1) doubles, s_q kSeg NV; the block has NT threads, a
-// multiple of 4 kSeg and at least kSeg NV.  Result in s_out[0..NV) after the
-// call.
+// Fixed-order block reduction for the refinement.  The four lanes of each
+// quad first add their values pairwise in float32 (DPP quad permutations:
+// lanes 2i and 2i + 1 swap halves and add, then lanes 4i + {0, 1} and
+// 4i + {2, 3} swap quarters and add), so each lane keeps NV / 4 of the quad's
+// sums.  Those go through LDS column-major (column stride NT / 4 + 1), kSeg
+// NV threads each add one of kSeg segments of a column in float64 and NV
+// threads add the segments pairwise.  s_t holds NV (NT / 4 + 1) floats, s_q
+// kSeg NV doubles; the block has NT threads (whole waves), a multiple of
+// 4 kSeg and at least kSeg NV; NV is a multiple of 4.  Result in
+// s_out[0..NV) after the call.
 constexpr int kSeg = 8;
 
 template <int NV>
@@ -367,26 +370,46 @@ __device__ __forceinline__ double add_segments(const double* s_q, int c) {
            ((s_q[4 * NV + c] + s_q[5 * NV + c]) + (s_q[6 * NV + c] + s_q[7 * NV + c]));
 }
 
-template <int NV, int NT, typename T>
-__device__ __forceinline__ void block_reduce_lds(const T* v, T* s_t, double* s_q, double* s_out) {
-    static_assert(NT % (4 * kSeg) == 0 && NT >= kSeg * NV, "block shape");
-    constexpr int ld = NT + 1, per = NT / kSeg;
+template <int CTRL>
+__device__ __forceinline__ float quad_perm_f32(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+template <int NV, int NT>
+__device__ __forceinline__ void block_reduce_quad(const float* v, float* s_t, double* s_q, double* s_out) {
+    static_assert(NV % 4 == 0 && NT % (4 * kSeg) == 0 && NT >= kSeg * NV && NT % kWave == 0, "block shape");
+    constexpr int H = NV / 2, Q = NV / 4, NQ = NT / 4, ld = NQ + 1, per = NQ / kSeg;
     const int tid = threadIdx.x;
+    const bool odd = tid & 1, hi = tid & 2;
+    float h[H];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) s_t[c * ld + tid] = v[c];
+    for (int j = 0; j < H; ++j) {
+        const float keep = odd ? v[j + H] : v[j];
+        const float send = odd ? v[j] : v[j + H];
+        h[j] = keep + quad_perm_f32<0xB1>(send);   // quad_perm [1, 0, 3, 2]
+    }
+    float q[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const float keep = hi ? h[j + Q] : h[j];
+        const float send = hi ? h[j] : h[j + Q];
+        q[j] = keep + quad_perm_f32<0x4E>(send);   // quad_perm [2, 3, 0, 1]
+    }
+    const int base = (odd ? H : 0) + (hi ? Q : 0);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) s_t[(base + j) * ld + (tid >> 2)] = q[j];
     __syncthreads();
     if (tid < kSeg * NV) {
-        const int c = tid % NV, q = tid / NV;
-        const T* col = s_t + c * ld + q * per;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        const int c = tid % NV, sg = tid / NV;
+        const float* col = s_t + c * ld + sg * per;
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < per; r += 4) {
+        for (int r = 0; r + 1 < per; r += 2) {
             a0 += (double)col[r];
             a1 += (double)col[r + 1];
-            a2 += (double)col[r + 2];
-            a3 += (double)col[r + 3];
         }
-        s_q[q * NV + c] = (a0 + a1) + (a2 + a3);
+        if (per & 1) a0 += (double)col[per - 1];
+        s_q[sg * NV + c] = a0 + a1;
     }
     __syncthreads();
     if (tid < NV) s_out[tid] = add_segments<NV>(s_q, tid);
@@ -595,10 +618,10 @@ constexpr int kRefWords = 2 * kNAcc;
 
 // 32-bit words of the shared buffer: the block reduction's float32 transpose,
 // later the gathered 32-bit halves of the partial sums
-constexpr int kRefLds = kNAcc * (kRefBlock + 1) > kRefMaxB * kRefWords ? kNAcc * (kRefBlock + 1) : kRefMaxB * kRefWords;
+constexpr int kRefLds = kNAcc * (kRefBlock / 4 + 1);   // the block reduction's transpose (floats)
 
 __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
-    __shared__ uint32_t s_big[kRefLds];   // the block reduction's transpose, then the gathered rows
+    __shared__ float s_big[kRefLds];   // the block reduction's transpose
     __shared__ double s_q[kSeg * kNAcc];
     __shared__ double s_out[kNAcc];
     __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
@@ -705,7 +728,7 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
             }
             // the per-thread float32 sums go through LDS as they are and are
             // widened as the segments are added
-            block_reduce_lds<kNAcc, kRefBlock>(accf, reinterpret_cast<float*>(s_big), s_q, s_out);
+            block_reduce_quad<kNAcc, kRefBlock>(accf, s_big, s_q, s_out);
             if (Be > 1) {
                 // Exchange of the Be partial sums of this step as tagged words
                 // (device-coherent stores and loads).  Rows alternate between
