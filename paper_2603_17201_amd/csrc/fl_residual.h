@@ -49,6 +49,26 @@ __device__ __forceinline__ double recip(double x) {
     return fma(r, e, r);
 }
 
+// The first NT terms of e^sigma = sum_k sigma^k / k! and of
+// I_n(sigma) = integral_0^1 tau^n e^{sigma tau} d tau = sum_k sigma^k / (k! (n + k + 1)), n = 0..6.
+template <int NT>
+__device__ __forceinline__ void sigma_series(double sig, double* I, double& es) {
+    double p[NT];
+    p[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < NT; ++k) p[k] = p[k - 1] * sig * kRecip.v[k - 1];   // sigma^k / k!
+    es = 0.0;
+#pragma unroll
+    for (int k = NT - 1; k >= 0; --k) es += p[k];
+#pragma unroll
+    for (int n = 0; n < 7; ++n) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = NT - 1; k >= 0; --k) v = fma(p[k], kRecip.v[n + k], v);
+        I[n] = v;
+    }
+}
+
 // exp of a tangent xi = (omega, upsilon, sigma):  R = exp([omega]x),
 // s = e^sigma, t = V upsilon with V = integral_0^1 e^{sigma tau} exp(tau [omega]x) d tau
 // = c0 I + c1 W + c2 W^2 (closed form; series for small rotation angles).
@@ -56,9 +76,10 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
     const double sig = xi[6];
     const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
-    const double th = sqrt(th2);
+    const bool small = th2 < 1e-4;   // angle below 1e-2: the series need only th^2
+    const double th = small ? 0.0 : sqrt(th2);
     double a, b;
-    if (th < 1e-2) {
+    if (small) {
         // sin(th)/th and (1 - cos(th))/th^2 by their Taylor series: the next
         // terms are below th^8/9! < 3e-22 here
         const double t4 = th2 * th2;
@@ -71,21 +92,13 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     // I_n(sigma) for n = 0..6 and e^sigma = sum_k sigma^k / k! share one series
     double I[7];
     double es;
-    if (fabs(sig) < 0.01) {
-        // |sigma| < 0.01: nine terms of each series (the rest is below
-        // 0.01^9 / 9! < 3e-24); I_n = sum_k sigma^k / (k! (n + k + 1))
-        double p[9];
-        p[0] = 1.0;
-        for (int k = 1; k < 9; ++k) p[k] = p[k - 1] * sig * kRecip.v[k - 1];   // sigma^k / k!
-        es = 0.0;
-        for (int k = 8; k >= 0; --k) es += p[k];
-#pragma unroll
-        for (int n = 0; n < 7; ++n) {
-            double v = 0.0;
-#pragma unroll
-            for (int k = 8; k >= 0; --k) v = fma(p[k], kRecip.v[n + k], v);
-            I[n] = v;
-        }
+    const double asig = fabs(sig);
+    if (asig < 2.5e-4) {
+        sigma_series<5>(sig, I, es);   // remainder below 2.5e-4^5 / 5! < 1e-20
+    } else if (asig < 4e-3) {
+        sigma_series<7>(sig, I, es);   // below 4e-3^7 / 7! < 1e-20
+    } else if (asig < 0.01) {
+        sigma_series<9>(sig, I, es);   // below 0.01^9 / 9! < 3e-24
     } else if (fabs(sig) < 2.0) {
         double term = 1.0, e = 0.0;
         for (int n = 0; n < 7; ++n) I[n] = 0.0;
@@ -104,7 +117,7 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     }
     const double c0 = I[0];
     double c1, c2;
-    if (th < 1e-2) {
+    if (small) {
         c1 = I[1] - th2 * (1.0 / 6.0) * I[3] + th2 * th2 * (1.0 / 120.0) * I[5];
         c2 = 0.5 * I[2] - th2 * (1.0 / 24.0) * I[4] + th2 * th2 * (1.0 / 720.0) * I[6];
     } else {
