@@ -98,6 +98,22 @@ def test_sim3_exp_mul_matches_expm(ctx):
         assert np.max(np.abs(S32.cpu().numpy() - sim3.to_f32_rows(exp))) < 1e-6
 
 
+def test_sim3_exp_series_branches(ctx):
+    # sigma on both sides of each switch between series lengths (2.5e-4, 4e-3,
+    # 1e-2) and of the switch to the summed series, of both signs; rotation
+    # angles on both sides of the small-angle switch (1e-2)
+    rng = np.random.default_rng(9)
+    S_in = sim3.exp(rng.normal(size=7) * 0.3)
+    for sig in (0.0, 1e-9, 2.4e-4, -2.4e-4, 2.6e-4, 3.9e-3, -3.9e-3, 4.1e-3, 9.9e-3, -9.9e-3, 1.01e-2, -1.01e-2):
+        for th in (0.0, 3e-5, 9.9e-3, 1.01e-2):
+            w = rng.normal(size=3)
+            w *= th / np.linalg.norm(w)
+            xi = np.concatenate([w, rng.normal(size=3) * 0.05, [sig]])
+            S_out, _ = ctx.sim3_exp_mul(t(xi), t(S_in))
+            exp = sim3.compose(sim3.exp(xi), S_in)
+            assert np.max(np.abs(S_out.cpu().numpy() - exp)) < 1e-12 * max(1.0, np.max(np.abs(exp))), (sig, th)
+
+
 def test_gn_step_matches_oracle(ctx, c4):
     d, xyz, uv, kf, T = multi_view(20000, 8)
     S0 = sim3.compose(sim3.exp(d["xi0"]), d["S_true"])
