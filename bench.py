@@ -99,10 +99,10 @@ def sim3_error(S, S_ref):
     return float(ang), float(np.linalg.norm(te)), float(abs(np.log(se)))
 
 
-def cpu_baseline(ev, budget_s=12.0):
-    """The oracle as it stands on this host's cores: brute-force search-and-
-    fuse of the event, then 10 float64 Gauss-Newton steps on its accepted
-    pairs; repeated until about budget_s."""
+def cpu_baseline(ev, budget_s=12.0, max_events=20):
+    """The oracle as it stands: brute-force search-and-fuse of the event,
+    then 10 float64 Gauss-Newton steps on its accepted pairs; repeated until
+    about budget_s."""
     import oracle
     from oracle import residual as R
     n = 0
@@ -116,9 +116,58 @@ def cpu_baseline(ev, budget_s=12.0):
         R.gauss_newton(ev.S_init, ev.mp_xyz[mp], ev.kp_xy[kp], kf, ev.kf_T, ev.cams[0], HUBER, iters=GN_ITERS)
         n += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 20:
+        if el >= budget_s or n >= max_events:
             break
     return n, el
+
+
+def cpu_worker(budget_s, start_at):
+    """Child process of the CPU baseline (never touches the GPU): the loop
+    event's oracle run from start_at (a wall-clock time shared by all
+    workers of one measurement) for about budget_s; prints {n, el}."""
+    import synth
+    ev = synth.gen_c2()
+    import oracle  # noqa: F401  (library loaded before the clock starts)
+    delay = start_at - time.time()
+    if delay > 0:
+        time.sleep(delay)
+    n, el = cpu_baseline(ev, budget_s, max_events=10 ** 6)
+    print(json.dumps(dict(n=n, el=el, n_pairs=int(ev.pair_offset[-1]))), flush=True)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(nproc=avail, cpu_count=os.cpu_count(), model=model)
+
+
+def run_cpu_workers(n_workers, budget_s):
+    """The oracle in n_workers concurrent single-threaded child processes
+    (BLAS and OpenMP held at one thread, no GPU visible); returns the
+    aggregate pairs/s and the per-worker results."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    start_at = time.time() + 6.0 + 0.2 * n_workers
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(budget_s),
+                               "--cpu-start", repr(start_at)], stdout=subprocess.PIPE, env=env, text=True)
+             for _ in range(n_workers)]
+    res = []
+    for p in procs:
+        out, _ = p.communicate(timeout=budget_s * 4 + 300)
+        if p.returncode != 0:
+            raise RuntimeError(f"cpu baseline worker failed ({p.returncode})")
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    rate = sum(r["n"] * r["n_pairs"] / r["el"] for r in res)
+    return rate, res
 
 
 class Bench:
@@ -129,6 +178,7 @@ class Bench:
         self.dev = torch.device("cuda:0")
         self.ctx = fl.Context(0)
         self.stream = torch.cuda.current_stream(self.dev)
+        self.peaks = None   # measured HBM copy and VALU issue rates, once taken
 
     # -- helpers -------------------------------------------------------------
     def events_time(self, fn, steps, warmup):
@@ -374,6 +424,9 @@ class Bench:
         else:
             roof = dict(bound="hbm", achieved=nbytes / (ks_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
         roof.update(frac=roof["achieved"] / roof["peak"], kernel_us=ks_ms * 1e3, alg_bytes=nbytes, alg_ops=nops)
+        if self.peaks:
+            roof["frac_of_measured_peak"] = (roof["achieved"] / self.peaks["hbm_copy_gbs"] if roof["bound"] == "hbm"
+                                             else roof["achieved"] * 1e12 / self.peaks["valu_lane_ops_per_s"])
         res.update(search_kernel_us=ks_ms * 1e3, refine_kernel_us=kr_ms * 1e3, search_roofline=roof)
         if n_ev == 1 and not self.args.no_plain:
             host, host_S = self.host_buffers(b.n_pairs)
@@ -490,12 +543,37 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-start", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker, args.cpu_start)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(events and keyframes shard across GPUs without exchange, see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+
+    # The CPU baselines run first, in child processes started before this
+    # process touches the GPU.
+    cpu = cpu_all = None
+    if not args.no_cpu_baseline:
+        host = host_cpu()
+        log(f"cpu baseline: oracle (brute-force search + float64 GN) on the same event, one thread "
+            f"({host['nproc']} cores available, {host['model']})")
+        rate1, r1 = run_cpu_workers(1, 12.0)
+        n, el = r1[0]["n"], r1[0]["el"]
+        cpu = dict(value=rate1, unit="pairs/s", cores=1, kind="oracle",
+                   sample=f"{n} full loop events of this workload ({n * r1[0]['n_pairs']} pairs), "
+                          f"single-threaded C oracle + NumPy float64 Gauss-Newton in one child process, {el:.1f} s",
+                   ms_per_event=el / n * 1e3, host=host)
+        workers = max(1, min(16, host["nproc"]))
+        log(f"cpu baseline: the same oracle in {workers} concurrent single-threaded processes")
+        rate_all, rs = run_cpu_workers(workers, 10.0)
+        cpu_all = dict(value=rate_all, unit="pairs/s", cores=workers, kind="oracle",
+                       sample=f"{sum(r['n'] for r in rs)} full loop events over {workers} concurrent processes "
+                              f"(one thread each, ~10 s each, started together)", host=host)
 
     import synth
     bench = Bench(args)
@@ -505,7 +583,19 @@ def main():
 
     secondary = None
     hbm_meas = bench.hbm_copy_gbs()
-    log(f"measured device copy: {hbm_meas:.0f} GB/s (read + write)")
+    valu_meas = max(bench.ctx.valu_rate(iters=10000) for _ in range(3))
+    log(f"measured device copy: {hbm_meas:.0f} GB/s (read + write); "
+        f"measured VALU issue rate: {valu_meas / 1e12:.1f} T lane-ops/s")
+    peaks = dict(hbm_copy_gbs=hbm_meas, valu_lane_ops_per_s=valu_meas,
+                 note="1 GiB device copy (read + write bytes); eight independent v_xor_b32 + v_bcnt_u32_b32 "
+                      "chains per lane on every CU; the rooflines use the published peaks, "
+                      "frac_of_measured_peak these")
+    bench.peaks = peaks
+    for roof in (h["roof"], h["other"]):
+        if roof["bound"] == "hbm":
+            roof["frac_of_measured_peak"] = roof["achieved"] / hbm_meas
+        elif roof["unit"] == "Tops/s":
+            roof["frac_of_measured_peak"] = roof["achieved"] * 1e12 / valu_meas
     if not args.quick:
         secondary = {"uneven_event_60kf": bench.batch_graph(synth.gen_c3(), "uneven event", args.steps)}
         evs = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
@@ -516,15 +606,6 @@ def main():
         secondary["residual_50k"] = bench.residual()
         if args.stream_events > 0:
             secondary["stream"] = bench.stream_events(args.stream_events)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle (brute-force search + float64 GN) on the same event")
-        n, el = cpu_baseline(h["ev"])
-        cpu = dict(value=n * h["n_pairs"] / el, unit="pairs/s", cores=1, kind="oracle",
-                   sample=f"{n} full loop events of this workload ({n * h['n_pairs']} pairs), "
-                          f"single-threaded C oracle + NumPy float64 Gauss-Newton, {el:.1f} s",
-                   ms_per_event=el / n * 1e3)
 
     ev, plain = h["ev"], h["plain"]
     # the batched path: one table upload and one launch sequence per event,
@@ -548,12 +629,12 @@ def main():
         roofline=h["roof"],
         roofline_other_kernel=h["other"],
         cpu_baseline=cpu,
-        measured_hbm_copy_gbs=hbm_meas,
+        cpu_baseline_all_cores=cpu_all,
+        measured_peaks=peaks,
         secondary=secondary,
     )
     bench.ctx.close()
     print(json.dumps(res), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -288,6 +288,15 @@ int fl_get_stats(fl_ctx* ctx, int64_t* out4 /* host [4] */);
 int fl_set_profiling(fl_ctx* ctx, int enable);
 int fl_get_profile(fl_ctx* ctx, int kernel, double* total_ms /* host */, int64_t* launches /* host */);
 
+/* Measured VALU issue rate for roofline reporting (not a step of the
+ * method): a kernel on every compute unit runs `iters` rounds of eight
+ * independent v_xor_b32 + v_bcnt_u32_b32 chains per lane (the instructions
+ * of the 256-bit Hamming distance), timed by HIP events on `stream`, which
+ * is synchronised.  *lane_ops_per_s receives lanes x instructions per
+ * second.  FL_ERANGE for iters outside [1, 2^20]; FL_ENOMEM / FL_EHIP from
+ * the 4 KB sink allocation or the launch. */
+int fl_valu_rate(fl_ctx* ctx, int32_t iters, double* lane_ops_per_s /* host */, hipStream_t stream);
+
 /* Test hook: cap the provisional-ADD and matched-pair lists at `cap`
  * entries (0 restores the default) so that their overflow paths, full scans
  * of the pair outputs, run.  Results are unchanged. */

@@ -102,6 +102,7 @@ SIGNATURES = [
     ("fl_get_stats", c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     ("fl_set_profiling", c_int32, [c_void_p, c_int32]),
     ("fl_get_profile", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]),
+    ("fl_valu_rate", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double), c_void_p]),
     ("fl_debug_set_list_cap", c_int32, [c_void_p, c_int32]),
 ]
 

@@ -396,6 +396,13 @@ class Context:
         _check(self._lib.fl_get_profile(self._h, k, ctypes.byref(ms), ctypes.byref(n)), "fl_get_profile")
         return ms.value, n.value
 
+    def valu_rate(self, iters: int = 10000, stream=None) -> float:
+        """Measured issue rate (lane-ops/s) of the Hamming instructions on
+        every compute unit; synchronises the stream."""
+        r = ctypes.c_double()
+        _check(self._lib.fl_valu_rate(self._h, int(iters), ctypes.byref(r), self._stream(stream)), "fl_valu_rate")
+        return r.value
+
     def debug_set_list_cap(self, cap: int):
         _check(self._lib.fl_debug_set_list_cap(self._h, int(cap)), "fl_debug_set_list_cap")
 

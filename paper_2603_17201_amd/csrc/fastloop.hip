@@ -96,6 +96,7 @@ struct fl_ctx {
     DevBuf ws;                  // batched workspace (tables, global grids, lists, partials)
     DevBuf claims;              // ADD claims, 0xFF.. between epochs
     DevBuf ctrs;                // stats + per-keyframe + per-event counters, zero at rest
+    DevBuf diag;                // sink of the VALU issue-rate probe
     DevBuf plain;               // plain-path workspace
     DevBuf res;                 // residual partials and done counter
     DevBuf part;                // refinement partial sums and their tags, zero when the epoch restarts
@@ -747,6 +748,7 @@ void fl_destroy(fl_ctx* c) {
     c->ws.release();
     c->claims.release();
     c->ctrs.release();
+    c->diag.release();
     c->plain.release();
     c->res.release();
     c->part.release();
@@ -1200,6 +1202,62 @@ int fl_get_profile(fl_ctx* c, int kernel, double* total_ms, int64_t* launches) {
     *total_ms = sum;
     *launches = (int64_t)ev.size();
     clear_profile(c, kernel);
+    return FL_OK;
+}
+
+namespace fl {
+// Issue rate of the search's Hamming instructions: eight independent chains
+// of v_xor_b32 + v_bcnt_u32_b32 per lane, 16 lane-ops per iteration, on every
+// CU at full occupancy.  The sink is written only if the chains end on one
+// particular value, which keeps them live without memory traffic.
+__global__ __launch_bounds__(256) void valu_rate_kernel(uint32_t* sink, int iters) {
+    uint32_t a[8], b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = threadIdx.x * 0x9E3779B1u + (uint32_t)j;
+        b[j] = blockIdx.x + 77u * (uint32_t)j;
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            a[j] ^= b[j];
+            b[j] = (uint32_t)__popc(a[j]) + b[j];
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r ^= a[j] + b[j];
+    if (r == 0x9E3779B9u) sink[0] = r;
+}
+}  // namespace fl
+
+int fl_valu_rate(fl_ctx* c, int32_t iters, double* lane_ops_per_s, hipStream_t stream) {
+    if (!c || !lane_ops_per_s) return fail(FL_EINVAL, "NULL argument");
+    if (iters < 1 || iters > (1 << 20)) return fail(FL_ERANGE, "iters %d outside [1, 2^20]", iters);
+    const int rc = c->diag.ensure(4096, 0x00);
+    if (rc) return rc;
+    const int grid = c->n_cu * 8, block = 256;
+    hipEvent_t e0, e1;
+    FL_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(FL_EHIP, "hipEventCreate failed");
+    }
+    hipError_t err = hipEventRecord(e0, stream);
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(fl::valu_rate_kernel, dim3(grid), dim3(block), 0, stream,
+                           reinterpret_cast<uint32_t*>(c->diag.p), iters);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(FL_EHIP, "valu rate: %s", hipGetErrorString(err));
+    if (!(ms > 0.0f)) return fail(FL_EHIP, "valu rate: no elapsed time");
+    *lane_ops_per_s = (double)grid * block * (double)iters * 16.0 / ((double)ms * 1e-3);
     return FL_OK;
 }
 

@@ -129,6 +129,9 @@ def test_null_context_is_rejected(lib):
     assert rc == _abi.FL_EINVAL
     rc = lib.fl_set_stats(None, 1)
     assert rc == _abi.FL_EINVAL
+    r = ctypes.c_double()
+    rc = lib.fl_valu_rate(None, 100, ctypes.byref(r), None)
+    assert rc == _abi.FL_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -255,3 +255,31 @@ def test_refine_multi_event_batch(ctx):
                 continue
             err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
             assert err < 1e-6, (mode, e, err)
+
+
+def test_stream_largest_event_graph_with_refine(ctx):
+    """The largest event of the 200-event stream (73 keyframes, 97,969 points,
+    7.15 M dense pairs) in the stream's launch configuration (graph replay
+    with ten refinement steps): every output bit-exact against the oracle and
+    the refined Sim3 against float64 Gauss-Newton on the same pairs."""
+    import paper_2603_17201_amd as fl
+    ev = synth.gen_c5_event(59)
+    B = synth.concat_events([ev])
+    assert int(B.pair_offset[-1]) == 73 * 97969
+    exp = oracle.search_fuse(B, use_grid=True)
+    S_ref, n_ref = _event_gn(B, exp, 0)
+    assert n_ref > 50000
+    b = fl.DeviceBatch(B, device=dev())
+    try:
+        for tuning in ((2, 2, 1, 1), (1, 2, 2, 1)):
+            ctx.set_tuning(*tuning)
+            S = t(ev.S_init.reshape(1, 13).copy())
+            nm = torch.zeros(1, dtype=torch.int32, device=dev())
+            got = ctx.search_fuse_graph(b, B.params, refine=(10, 2.45, S, None, nm)).numpy()
+            for k in got:
+                assert np.array_equal(got[k], exp[k]), (tuning, k)
+            assert int(nm.item()) == n_ref, tuning
+            err = np.linalg.norm(sim3.log(sim3.compose(S.cpu().numpy()[0], sim3.inverse(S_ref))))
+            assert err < 1e-6, (tuning, err)
+    finally:
+        ctx.set_tuning()

@@ -207,3 +207,14 @@ def test_host_validation_errors(ctx):
         ctx.search_fuse(torch.zeros((4, 3)), t(np.zeros((4, 32), np.uint8)), None, None,
                         t(np.zeros((1, 2), np.float32)), t(np.zeros(1, np.int8)), t(np.zeros((1, 32), np.uint8)),
                         t(np.zeros(1, np.int32)), np.zeros(16, np.float32), ev.cams[0], ev.params)
+
+
+def test_valu_rate_probe(ctx):
+    # the issue-rate probe used for roofline reporting: a plausible rate
+    # (between 1 and 200 T lane-ops/s) and its argument range enforced
+    rate = ctx.valu_rate(iters=2000)
+    assert 1e12 < rate < 2e14, rate
+    import paper_2603_17201_amd as fl
+    with pytest.raises(ValueError):
+        ctx.valu_rate(iters=0)
+    assert fl.last_error()
