@@ -622,7 +622,7 @@ __device__ __forceinline__ void refine_accumulate_f32(const float* T, float fx, 
 constexpr int kRefCache = 2;     // accepted pairs a thread keeps in registers across the steps
 constexpr int kRefKfLds = 64;    // keyframes of one event whose pose and intrinsics sit in LDS
 constexpr int kRefMaxB = 64;     // workgroups per event
-constexpr int kRefBlock = 320;   // threads of a refinement workgroup: 64 x 320 pairs at one per thread
+constexpr int kRefBlock = 512;   // threads of a refinement workgroup: 64 x 512 pairs at one per thread
 // Each float64 partial travels as two 64-bit words, (high half << 32 | tag)
 // and (low half << 32 | tag): a word is written and read in one piece, so a
 // reader that sees the tag of the current launch and step in both words has
@@ -784,7 +784,8 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                             if ((pending >> j & 1u) && (uint32_t)wh[j] == tag && (uint32_t)wl[j] == tag)
                                 pending &= ~(1u << j);
                         if (pending) {
-                            __builtin_amdgcn_s_sleep(1);
+                            // no back-off: each round is a device-memory round
+                            // trip already, and a pause only delays the last row
                             if (++spins > kSpinLimit) {
                                 s_fail = 1;
                                 break;
