@@ -191,8 +191,11 @@ int fl_validate_batch(const fl_batch* B /* host */, const fl_params* P /* host *
 /* Batched search-and-fuse over whole loop events (Sec. IV-D3: connected
  * keyframes evaluated concurrently on resident data, Sec. IV-E: one transfer
  * of compact tables): one upload of the batch tables and one fused kernel
- * that stages each keyframe's grid in LDS, searches all pairs of all events
- * and resolves the ADD conflicts of each keyframe.  Results are identical to
+ * that stages each keyframe's grid in LDS and searches all pairs of all
+ * events; the ADD conflicts of each keyframe are resolved by the kernel that
+ * follows on the stream (the refinement, or a resolution kernel when refine
+ * is NULL), so the outputs are final when the stream reaches the end of the
+ * call's work.  Results are identical to
  * fl_search_fuse applied per keyframe.  With refine non-NULL the search also
  * records each event's accepted pairs and per-event Sim3 refinement follows
  * on the same stream, as in fl_search_fuse_graph_launch.

@@ -266,6 +266,7 @@ struct Prepared {
     size_t lds = 16;
     size_t blob_cap = 0;
     int refine_iters = 0;
+    bool resolve_in_refine = false;   // the refinement launch resolves the ADD conflicts
 };
 
 template <typename T>
@@ -537,6 +538,10 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.match_list = (MatchRec*)(base + L_match);
     h.refine_blocks = refine_blocks;
     h.refine_scan = refine_scan ? 1 : 0;
+    // a refinement that follows a search in the same call resolves its ADD
+    // conflicts; otherwise launch_search adds the resolution kernel
+    pr.resolve_in_refine = refine && !refine_scan;
+    h.resolve_in_refine = pr.resolve_in_refine ? 1 : 0;
     h.refine_rows = (unsigned long long*)c->part.p;
     if (refine) {
         h.refine_iters = R->n_iters;
@@ -627,6 +632,10 @@ int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t
     if (timed) {
         FL_HIP(hipEventRecord(t1, s));
         c->prof_ev[FL_PROF_SEARCH].emplace_back(t0, t1);
+    }
+    if (!pr.resolve_in_refine) {
+        const int rg = eager ? std::max(1, std::min(pr.hdr->n_kf, kResolveGrid)) : kResolveGrid;
+        hipLaunchKernelGGL(resolve_adds_kernel, dim3(rg), dim3(kResolveBlock), 0, s, dh);
     }
     FL_HIP(hipGetLastError());
     return FL_OK;

@@ -55,10 +55,6 @@ struct alignas(16) EventDesc {
 constexpr size_t kBlobAlign = 256;
 __host__ __device__ constexpr size_t blob_align(size_t x) { return (x + kBlobAlign - 1) / kBlobAlign * kBlobAlign; }
 
-// s_waitcnt immediate with vmcnt = 0 and expcnt / lgkmcnt left at their
-// maxima (no wait): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
-constexpr int kWaitVmcnt0 = 0x0F70;
-
 struct alignas(16) AddRef {
     int32_t pair;     // global pair index
     int32_t kp;       // global keypoint index
@@ -82,9 +78,9 @@ struct alignas(16) KpRec {
     int32_t oct;
 };
 
-// Per-keyframe counters (zero between launches: the kernel that uses them
-// last resets them).
-enum : int { kKfDone = 0, kKfAdd = 1, kKfCtrs = 2 };
+// Per-keyframe counters (zero between launches: the ADD resolution that
+// follows every batched search resets them).
+enum : int { kKfAdd = 0, kKfCtrs = 1 };
 // Per-event counters.
 enum : int { kEvMatch = 0, kEvCtrs = 1 };
 
@@ -108,6 +104,7 @@ struct alignas(16) BatchHdr {
     float huber_delta;
     int32_t refine_blocks;      // blocks per event
     int32_t refine_scan;        // 1: take accepted pairs from the decisions, not the list
+    int32_t resolve_in_refine;  // 1: the refinement kernel resolves the search's ADD conflicts
     int32_t lds_kp_cap;         // keypoint capacity of the LDS records in the LDS modes
     float sf[32];               // scale_factor^n rounded to float32
     // tables in the uploaded blob
@@ -266,6 +263,43 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15, rows 1 and 3
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31, rows 2 and 3
     return x;
+}
+
+// ADD conflicts of keyframe k, resolved by a kernel that runs after the
+// whole batched search on the same stream.  Of the provisional ADDs on one
+// keypoint the lowest point index (the claim it left, tagged with the launch
+// epoch) keeps ADD; the others become FUSE to that point (Sec. IV-D3, with
+// the lowest-index reading of concurrent additions).  The keyframe's ADD list
+// names the provisional ADDs; if it overflowed, the keyframe's decisions are
+// scanned instead.  Every thread of the workgroup calls it; the counter is
+// reset at the end.
+__device__ inline void resolve_keyframe_adds(const BatchHdr& h, int k, unsigned long long tag) {
+    const KfDesc& kd = h.kf[k];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t n_add = h.kf_ctr[k * kKfCtrs + kKfAdd];
+    if (n_add <= (uint32_t)kd.add_cap) {
+        for (uint32_t i = tid; i < n_add; i += nt) {
+            const AddRef e = h.add_list[kd.add_off + i];
+            const int32_t w = (int32_t)(h.claim[e.kp] - tag);
+            if (w != e.gp) {
+                h.decision[e.pair] = FL_FUSE;
+                h.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
+            }
+        }
+    } else {
+        for (int64_t j = tid; j < kd.n_pairs; j += nt) {
+            const int64_t o = kd.pair_off + j;
+            if (h.decision[o] != FL_ADD) continue;
+            const int32_t gp = kd.mp_off + (h.dense ? (int32_t)j : h.pair_mp[o]);
+            const int32_t w = (int32_t)(h.claim[kd.kp_off + h.best_idx[o]] - tag);
+            if (w != gp) {
+                h.decision[o] = FL_FUSE;
+                h.target[o] = h.mp_id ? h.mp_id[w] : w;
+            }
+        }
+    }
+    __syncthreads();   // every thread has read the count
+    if (tid == 0) h.kf_ctr[k * kKfCtrs + kKfAdd] = 0;
 }
 
 }  // namespace fl

@@ -364,7 +364,6 @@ __host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cel
     b += 4 * (size_t)((cells + 4 + 3) & ~3);
     b += 4 * (size_t)hash_cap;
     b += 4 * (size_t)(kSearchBlock / kWave + 4);
-    b += 16;
     return b;
 }
 
@@ -380,7 +379,6 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     int32_t* s_own = nullptr;
     int32_t* s_hash = nullptr;
     int32_t* s_tmp = nullptr;
-    int32_t* s_flag = reinterpret_cast<int32_t*>(s_mem);
     __shared__ uint32_t s_cnt[2 * PPL * kWavesPerWG + 2];   // per-wave list counts, then the two bases
     const int wid = tid / kWave;
     if (MODE != kModeGlobal) {
@@ -397,14 +395,15 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         p += 4 * (size_t)(h.lds_hash_mask + 1);
         s_tmp = reinterpret_cast<int32_t*>(p);
         p += 4 * (size_t)(kSearchBlock / kWave + 4);
-        s_flag = reinterpret_cast<int32_t*>(p);
     }
 
     // the octave scale table in LDS: the octave search and the window radius
-    // index it per lane
+    // index it per lane.  In the LDS modes the barrier that opens the first
+    // keyframe's staging publishes it, so the tile's table and point loads
+    // below are issued without waiting here.
     __shared__ float s_sf[FL_MAX_OCTAVES];
     if (tid < FL_MAX_OCTAVES) s_sf[tid] = h.sf[tid];
-    __syncthreads();
+    if (MODE == kModeGlobal) __syncthreads();
     const float* sf = s_sf;
     const int N = h.n_octaves, gate = h.gate, C = h.grid_cols, R = h.grid_rows, th = h.hamming_th;
     const float ratio = h.nn_ratio, r0w = h.r0;
@@ -428,13 +427,10 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         const EventDesc ed = h.ev[kd.event];
         const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
         const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
-        // With room for every pair in the ADD list (the normal case) each output
-        // has a single writer: the decision and target of a provisional ADD are
-        // written only by the keyframe's resolver, from coherent list entries
-        // and claims, so no tile needs an L2 write-back.  With a capped list a
-        // provisional ADD may be written here and relabelled later, and tiles
-        // release their stores with a device-scope fence.
-        const bool single_writer = kd.add_cap >= kd.n_pairs;
+        // A provisional ADD is written as ADD here; the ADD conflicts are
+        // resolved after the whole search, by the next kernel on the stream
+        // (the refinement, or the resolution kernel when there is none), which
+        // relabels the losers.  No tile waits for another.
 
         // Point loads of every pair of this thread are issued first, so their
         // latency overlaps the keyframe staging below.
@@ -571,10 +567,8 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 h.best_idx[o] = bidx;
                 h.best_dist[o] = (int16_t)(best.key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(best.key >> 16));
                 h.second_dist[o] = (int16_t)best.second;
-                if (!(is_add && single_writer)) {
-                    h.decision[o] = dec[r];
-                    h.target[o] = target;
-                }
+                h.decision[o] = dec[r];
+                h.target[o] = target;
             }
             if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp[r]);
             // list entries are written after the tile with one atomic per list
@@ -627,22 +621,12 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 if (add_want[r]) {
                     const uint32_t idx = base_a + s_cnt[(2 * r) * kWavesPerWG + wid] + (uint32_t)__popcll(ma & below);
                     if (idx < (uint32_t)kd.add_cap) {
-                        AddRef* ae = &h.add_list[kd.add_off + idx];
-                        if (single_writer) {   // read by the resolver with coherent loads
-                            const unsigned long long lo = (uint32_t)o | ((unsigned long long)(uint32_t)add_kp[r] << 32);
-                            const unsigned long long hi = (uint32_t)gp[r];
-                            __hip_atomic_store(reinterpret_cast<unsigned long long*>(ae), lo, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            __hip_atomic_store(reinterpret_cast<unsigned long long*>(ae) + 1, hi, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                        } else {
-                            AddRef e;
-                            e.pair = (int32_t)o;
-                            e.kp = add_kp[r];
-                            e.gp = gp[r];
-                            e.pad = 0;
-                            *ae = e;
-                        }
+                        AddRef e;
+                        e.pair = (int32_t)o;
+                        e.kp = add_kp[r];
+                        e.gp = gp[r];
+                        e.pad = 0;
+                        h.add_list[kd.add_off + idx] = e;
                     }
                 }
                 if (acc_want[r]) {
@@ -662,85 +646,6 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 }
             }
         }
-
-        // Tile done; the workgroup completing a keyframe resolves its ADD
-        // conflicts.
-        if (single_writer) {
-            // Every list entry and claim of this tile has completed (coherent
-            // stores and device atomics, vmcnt 0) before thread 0 counts the tile.
-            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-            __syncthreads();
-            if (tid == 0)
-                s_flag[0] = atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfDone], 1u) == (uint32_t)(kd.n_tiles - 1);
-            __syncthreads();
-            if (s_flag[0]) {
-                const uint32_t n_add = min(__hip_atomic_load(&h.kf_ctr[k * kKfCtrs + kKfAdd], __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT),
-                                           (uint32_t)kd.add_cap);
-                for (uint32_t i = tid; i < n_add; i += kSearchBlock) {
-                    const unsigned long long* ae =
-                        reinterpret_cast<const unsigned long long*>(&h.add_list[kd.add_off + i]);
-                    const unsigned long long lo = __hip_atomic_load(ae, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const unsigned long long hi = __hip_atomic_load(ae + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const int32_t pair = (int32_t)(uint32_t)lo, kp = (int32_t)(uint32_t)(lo >> 32);
-                    const int32_t gpi = (int32_t)(uint32_t)hi;
-                    const int32_t w = (int32_t)(__hip_atomic_load(&h.claim[kp], __ATOMIC_RELAXED,
-                                                                  __HIP_MEMORY_SCOPE_AGENT) - tag);
-                    if (w == gpi) {
-                        h.decision[pair] = FL_ADD;
-                        h.target[pair] = -1;
-                    } else {
-                        h.decision[pair] = FL_FUSE;
-                        h.target[pair] = h.mp_id ? h.mp_id[w] : w;
-                    }
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    h.kf_ctr[k * kKfCtrs + kKfDone] = 0;
-                    h.kf_ctr[k * kKfCtrs + kKfAdd] = 0;
-                }
-            }
-            continue;
-        }
-        // Capped list: the barrier orders every wave's stores before thread 0's
-        // device-scope release (an L2 write-back, so one per tile, not one per
-        // wave); the resolver's acquire invalidates this CU's caches.
-        __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            s_flag[0] = atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfDone], 1u) == (uint32_t)(kd.n_tiles - 1);
-            if (s_flag[0]) __threadfence();
-        }
-        __syncthreads();
-        if (s_flag[0]) {
-            const uint32_t n_add = h.kf_ctr[k * kKfCtrs + kKfAdd];
-            if (n_add <= (uint32_t)kd.add_cap) {
-                for (uint32_t i = tid; i < n_add; i += kSearchBlock) {
-                    const AddRef e = h.add_list[kd.add_off + i];
-                    const int32_t w = (int32_t)(h.claim[e.kp] - tag);
-                    if (w != e.gp) {
-                        h.decision[e.pair] = FL_FUSE;
-                        h.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
-                    }
-                }
-            } else {   // the list overflowed: scan the keyframe's pairs
-                for (int64_t j = tid; j < kd.n_pairs; j += kSearchBlock) {
-                    const int64_t o = kd.pair_off + j;
-                    if (h.decision[o] != FL_ADD) continue;
-                    const int32_t gp = kd.mp_off + (dense ? (int32_t)j : h.pair_mp[o]);
-                    const int32_t w = (int32_t)(h.claim[kd.kp_off + h.best_idx[o]] - tag);
-                    if (w != gp) {
-                        h.decision[o] = FL_FUSE;
-                        h.target[o] = h.mp_id ? h.mp_id[w] : w;
-                    }
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                h.kf_ctr[k * kKfCtrs + kKfDone] = 0;
-                h.kf_ctr[k * kKfCtrs + kKfAdd] = 0;
-            }
-        }
     }
     if (STATS) {
         unsigned long long vals[4] = {st_vis, st_cells, st_kp, st_cand};
@@ -751,6 +656,17 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             if (lane == 0 && xv) atomicAdd(&h.stats_out[i], xv);
         }
     }
+}
+
+// ADD resolution after a batched search launched without refinement: one
+// workgroup per keyframe, grid-stride.
+constexpr int kResolveBlock = 256;
+constexpr int kResolveGrid = 1024;   // workgroups in graph mode (any count is correct)
+
+__global__ __launch_bounds__(kResolveBlock) void resolve_adds_kernel(const BatchHdr* __restrict__ hp) {
+    const BatchHdr& h = *hp;
+    const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
+    for (int k = blockIdx.x; k < h.n_kf; k += gridDim.x) resolve_keyframe_adds(h, k, tag);
 }
 
 // ---------------------------------------------------------------------------
