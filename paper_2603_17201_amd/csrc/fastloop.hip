@@ -82,8 +82,22 @@ struct Pinned {
     void* p = nullptr;
     size_t size = 0;
     size_t used = 0;            // bytes of tables staged in it
-    hipEvent_t done = nullptr;
-    bool pending = false;
+    hipEvent_t done = nullptr;  // graph buffers: recorded after each replay
+    bool pending = false;       // a fetch from it may still be queued
+    uint64_t seq = 0;           // eager ring: upload number of its last fetch
+    hipStream_t stream = nullptr;   // ... and the stream it was queued on
+};
+
+// Eager uploads record an event only every kFenceEvery uploads.  A ring
+// buffer is rewritten kPinRing distinct uploads after its last fetch, by which
+// time a fence recorded on the same stream after that fetch exists.
+constexpr int kFenceEvery = 8;
+constexpr int kFences = 4;
+static_assert(kPinRing >= kFenceEvery, "a fence must follow every fetch before its buffer returns");
+struct Fence {
+    hipEvent_t ev = nullptr;
+    uint64_t seq = 0;           // upload number it follows; 0: never recorded
+    hipStream_t stream = nullptr;
 };
 
 
@@ -102,6 +116,9 @@ struct fl_ctx {
     DevBuf part;                // refinement partial sums and their tags, zero when the epoch restarts
     Pinned pin[kPinRing];
     int pin_next = 0;
+    Fence fence[kFences];
+    int fence_next = 0;
+    uint64_t upload_seq = 0;    // eager uploads so far
     hipStream_t cap_stream = nullptr;
     fl_tuning tune{1, kModeLdsDesc, 1, 1};
     uint32_t launches = 0;      // table fetches since the claims were last reset
@@ -181,8 +198,14 @@ int get_pinned(fl_ctx* c, size_t need, Pinned** out) {
     Pinned& p = c->pin[c->pin_next];
     c->pin_next = (c->pin_next + 1) % kPinRing;
     if (p.pending) {
-        // the fetch from this buffer kPinRing uploads ago must have run
-        FL_HIP(hipEventSynchronize(p.done));
+        // the fetch from this buffer kPinRing uploads ago must have run: wait
+        // for the oldest fence recorded after it on its stream (a device-wide
+        // wait if the uploads have changed streams since)
+        const Fence* f = nullptr;
+        for (const Fence& g : c->fence)
+            if (g.seq >= p.seq && g.stream == p.stream && g.seq != 0 && (!f || g.seq < f->seq)) f = &g;
+        if (f) FL_HIP(hipEventSynchronize(f->ev));
+        else FL_HIP(hipDeviceSynchronize());
         p.pending = false;
     }
     if (p.size < need) {
@@ -589,9 +612,18 @@ int upload_batch(fl_ctx* c, Prepared& pr, hipStream_t stream) {
     }
     launch_fetch(c, pin->p, pr.blob.size(), stream);
     FL_HIP(hipGetLastError());
-    FL_HIP(hipEventRecord(pin->done, stream));
+    const uint64_t seq = ++c->upload_seq;
+    pin->seq = seq;
+    pin->stream = stream;
     pin->pending = true;
     c->pin_last = pin;
+    if (seq % kFenceEvery == 0) {
+        Fence& f = c->fence[c->fence_next];
+        c->fence_next = (c->fence_next + 1) % kFences;
+        FL_HIP(hipEventRecord(f.ev, stream));
+        f.seq = seq;
+        f.stream = stream;
+    }
     return FL_OK;
 }
 
@@ -719,8 +751,8 @@ int fl_create(fl_ctx** out, int device) {
             return fail(FL_EHIP, "hipEventCreate failed");
         }
     }
-    for (auto& p : c->pin) {
-        if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) {
+    for (auto& f : c->fence) {
+        if (hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess) {
             fl_destroy(c);
             return fail(FL_EHIP, "hipEventCreate failed");
         }
@@ -745,10 +777,10 @@ void fl_destroy(fl_ctx* c) {
     for (auto& g : c->gexec)
         if (g) hipGraphExecDestroy(g);
     clear_profile(c);
-    for (auto& p : c->pin) {
+    for (auto& p : c->pin)
         if (p.p) hipHostFree(p.p);
-        if (p.done) hipEventDestroy(p.done);
-    }
+    for (auto& f : c->fence)
+        if (f.ev) hipEventDestroy(f.ev);
     for (auto& p : c->gpin) {
         if (p.p) hipHostFree(p.p);
         if (p.done) hipEventDestroy(p.done);

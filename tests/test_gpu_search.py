@@ -218,3 +218,19 @@ def test_valu_rate_probe(ctx):
     with pytest.raises(ValueError):
         ctx.valu_rate(iters=0)
     assert fl.last_error()
+
+
+def test_staging_ring_reuse_with_changing_tables(ctx):
+    # 60 eager calls cycling through three batches: every call uploads new
+    # tables, so each staging buffer is rewritten several times, each time
+    # after a fence that follows its previous fetch; every result must hold
+    import paper_2603_17201_amd as fl
+    evs = [synth.gen_tiny(70 + i, n_kf=2 + i, n_mp=300 + 50 * i) for i in range(3)]
+    exps = [oracle.search_fuse(ev) for ev in evs]
+    bs = [fl.DeviceBatch(ev, device=dev()) for ev in evs]
+    outs = [fl.FuseOutputs.empty(b.n_pairs, dev()) for b in bs]
+    for it in range(60):
+        i = it % 3
+        ctx.search_fuse_batched(bs[i], evs[i].params, outs[i])
+        if it % 7 == 0 or it >= 57:
+            assert_same(outs[i].numpy(), exps[i], f"call {it}")
