@@ -82,18 +82,21 @@ struct Pinned {
     void* p = nullptr;
     size_t size = 0;
     size_t used = 0;            // bytes of tables staged in it
-    hipEvent_t done = nullptr;  // graph buffers: recorded after each replay
     bool pending = false;       // a fetch from it may still be queued
-    uint64_t seq = 0;           // eager ring: upload number of its last fetch
+    uint64_t seq = 0;           // upload number of its last fetch
     hipStream_t stream = nullptr;   // ... and the stream it was queued on
 };
 
-// Eager uploads record an event only every kFenceEvery uploads.  A ring
-// buffer is rewritten kPinRing distinct uploads after its last fetch, by which
-// time a fence recorded on the same stream after that fetch exists.
+// Table fetches (eager uploads and graph replays) record an event only every
+// kFenceEvery fetches.  A staging buffer is rewritten at least kFenceEvery
+// fetches after its last one (kPinRing distinct eager uploads, kGraphRing
+// graph replays), by which time a fence recorded on the same stream after
+// that fetch exists.
 constexpr int kFenceEvery = 8;
 constexpr int kFences = 4;
-static_assert(kPinRing >= kFenceEvery, "a fence must follow every fetch before its buffer returns");
+constexpr int kGraphRing = 8;   // graph executables replayed in turn, each with its own tables
+static_assert(kPinRing >= kFenceEvery && kGraphRing >= kFenceEvery,
+              "a fence must follow every fetch before its buffer returns");
 struct Fence {
     hipEvent_t ev = nullptr;
     uint64_t seq = 0;           // upload number it follows; 0: never recorded
@@ -128,8 +131,8 @@ struct fl_ctx {
     int prof = 0;               // record events around eager search and refinement kernels
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2];   // by FL_PROF_* class
     // captured graph and its key
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // replayed alternately
-    Pinned gpin[2];             // the pinned tables each graph fetches from
+    hipGraphExec_t gexec[kGraphRing] = {};   // replayed in turn
+    Pinned gpin[kGraphRing];    // the pinned tables each graph fetches from
     int g_next = 0;
     void* g_ws = nullptr;
     void* g_claims = nullptr;
@@ -194,20 +197,40 @@ void fill_kf_geometry(KfDesc& k, const fl_sim3& S, const fl_pinhole& K, const fl
     for (int i = 0; i < 12; ++i) k.T[i] = (i == 0 || i == 4 || i == 8) ? 1.0f : 0.0f;
 }
 
+// Wait until the last fetch from p has run: the oldest fence recorded after
+// it on its stream, or a device-wide wait if the fetches changed streams.
+int wait_fetched(fl_ctx* c, Pinned& p) {
+    if (!p.pending) return FL_OK;
+    const Fence* f = nullptr;
+    for (const Fence& g : c->fence)
+        if (g.seq != 0 && g.seq >= p.seq && g.stream == p.stream && (!f || g.seq < f->seq)) f = &g;
+    if (f) FL_HIP(hipEventSynchronize(f->ev));
+    else FL_HIP(hipDeviceSynchronize());
+    p.pending = false;
+    return FL_OK;
+}
+
+// A fetch from p was just queued on stream.
+int note_fetch(fl_ctx* c, Pinned& p, hipStream_t stream) {
+    const uint64_t seq = ++c->upload_seq;
+    p.seq = seq;
+    p.stream = stream;
+    p.pending = true;
+    if (seq % kFenceEvery == 0) {
+        Fence& f = c->fence[c->fence_next];
+        c->fence_next = (c->fence_next + 1) % kFences;
+        FL_HIP(hipEventRecord(f.ev, stream));
+        f.seq = seq;
+        f.stream = stream;
+    }
+    return FL_OK;
+}
+
 int get_pinned(fl_ctx* c, size_t need, Pinned** out) {
     Pinned& p = c->pin[c->pin_next];
     c->pin_next = (c->pin_next + 1) % kPinRing;
-    if (p.pending) {
-        // the fetch from this buffer kPinRing uploads ago must have run: wait
-        // for the oldest fence recorded after it on its stream (a device-wide
-        // wait if the uploads have changed streams since)
-        const Fence* f = nullptr;
-        for (const Fence& g : c->fence)
-            if (g.seq >= p.seq && g.stream == p.stream && g.seq != 0 && (!f || g.seq < f->seq)) f = &g;
-        if (f) FL_HIP(hipEventSynchronize(f->ev));
-        else FL_HIP(hipDeviceSynchronize());
-        p.pending = false;
-    }
+    const int rc = wait_fetched(c, p);
+    if (rc) return rc;
     if (p.size < need) {
         if (p.p) hipHostFree(p.p);
         p.p = nullptr;
@@ -428,35 +451,40 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             return prefix[k] + j;
         };
         const double total = kcum[n_kf];
-        std::vector<int64_t> bound(grid + 1);
+        // The tiles are laid out over ge = min(grid, tiles) workgroups, as an
+        // eager launch has them; a graph's further workgroups (its grid is
+        // fixed) get empty ranges and exit at once.
+        const int ge = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles));
+        std::vector<int64_t> bound(ge + 1);
         bound[0] = 0;
-        bound[grid] = n_tiles;
-        if (n_tiles <= 2 * (int64_t)grid) {
+        bound[ge] = n_tiles;
+        if (n_tiles <= 2 * (int64_t)ge) {
             // at most two tiles per workgroup: equal counts (a single wave of
             // tiles is latency bound, so a workgroup must not take more)
-            for (int i = 1; i < grid; ++i) bound[i] = n_tiles * i / grid;
+            for (int i = 1; i < ge; ++i) bound[i] = n_tiles * i / ge;
         } else {
-            for (int i = 1; i < grid; ++i) bound[i] = tile_at_cost(total * i / grid);
+            for (int i = 1; i < ge; ++i) bound[i] = tile_at_cost(total * i / ge);
         }
-        for (int i = 1; i <= grid; ++i) bound[i] = std::max(bound[i], bound[i - 1]);
-        for (int i = grid - 1; i >= 0; --i) bound[i] = std::min(bound[i], bound[i + 1]);
+        for (int i = 1; i <= ge; ++i) bound[i] = std::max(bound[i], bound[i - 1]);
+        for (int i = ge - 1; i >= 0; --i) bound[i] = std::min(bound[i], bound[i + 1]);
         // chunk i of the sequence goes to workgroup w(i); with xcd_aware the
         // chunks of one XCD's share are consecutive in the sequence
-        std::vector<int> wg_of(grid);
-        if (c->tune.xcd_aware && grid >= 2 * kMaxQueues) {
+        std::vector<int> wg_of(ge);
+        if (c->tune.xcd_aware && ge >= 2 * kMaxQueues) {
             int i = 0;
             for (int x = 0; x < kMaxQueues; ++x)
-                for (int b = x; b < grid; b += kMaxQueues) wg_of[i++] = b;
+                for (int b = x; b < ge; b += kMaxQueues) wg_of[i++] = b;
         } else {
-            for (int i = 0; i < grid; ++i) wg_of[i] = i;
+            for (int i = 0; i < ge; ++i) wg_of[i] = i;
         }
-        for (int i = 0; i < grid; ++i) {
+        for (int i = 0; i < ge; ++i) {
             // slot of the first tile: prefix[slot] <= tile < prefix[slot + 1]
             const int64_t t0 = bound[i];
             int slot = (int)(std::upper_bound(prefix, prefix + n_kf + 1, (int32_t)t0) - prefix) - 1;
             slot = std::min(std::max(slot, 0), std::max(n_kf - 1, 0));
             wr[wg_of[i]] = make_int4((int)t0, (int)bound[i + 1], slot, order[slot]);
         }
+        for (int i = ge; i < grid; ++i) wr[i] = make_int4((int)n_tiles, (int)n_tiles, 0, order[0]);
     }
 
     // workspace layout
@@ -612,19 +640,8 @@ int upload_batch(fl_ctx* c, Prepared& pr, hipStream_t stream) {
     }
     launch_fetch(c, pin->p, pr.blob.size(), stream);
     FL_HIP(hipGetLastError());
-    const uint64_t seq = ++c->upload_seq;
-    pin->seq = seq;
-    pin->stream = stream;
-    pin->pending = true;
     c->pin_last = pin;
-    if (seq % kFenceEvery == 0) {
-        Fence& f = c->fence[c->fence_next];
-        c->fence_next = (c->fence_next + 1) % kFences;
-        FL_HIP(hipEventRecord(f.ev, stream));
-        f.seq = seq;
-        f.stream = stream;
-    }
-    return FL_OK;
+    return note_fetch(c, *pin, stream);
 }
 
 template <int PPL, int MODE, bool STATS>
@@ -745,12 +762,6 @@ int fl_create(fl_ctx** out, int device) {
     allow_lds_all<1>(c->lds_max);
     allow_lds_all<2>(c->lds_max);
     allow_lds_all<4>(c->lds_max);
-    for (auto& p : c->gpin) {
-        if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) {
-            fl_destroy(c);
-            return fail(FL_EHIP, "hipEventCreate failed");
-        }
-    }
     for (auto& f : c->fence) {
         if (hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess) {
             fl_destroy(c);
@@ -781,10 +792,8 @@ void fl_destroy(fl_ctx* c) {
         if (p.p) hipHostFree(p.p);
     for (auto& f : c->fence)
         if (f.ev) hipEventDestroy(f.ev);
-    for (auto& p : c->gpin) {
+    for (auto& p : c->gpin)
         if (p.p) hipHostFree(p.p);
-        if (p.done) hipEventDestroy(p.done);
-    }
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     c->ws.release();
     c->claims.release();
@@ -965,11 +974,12 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
                        c->g_refine != refine_on || c->g_lds != pr.lds || c->gpin[0].size != pr.blob_cap;
     if (stale) {
         FL_HIP(hipStreamSynchronize(stream));
-        for (int gi = 0; gi < 2; ++gi) {
+        for (int gi = 0; gi < kGraphRing; ++gi) {
+            Pinned& gp = c->gpin[gi];
+            const int wrc = wait_fetched(c, gp);   // a replay may still fetch from it
+            if (wrc) return wrc;
             if (c->gexec[gi]) hipGraphExecDestroy(c->gexec[gi]);
             c->gexec[gi] = nullptr;
-            Pinned& gp = c->gpin[gi];
-            gp.pending = false;
             gp.used = 0;
             if (gp.size != pr.blob_cap) {
                 if (gp.p) hipHostFree(gp.p);
@@ -984,7 +994,7 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
             }
         }
         const BatchHdr* dh = (const BatchHdr*)c->ws.p;
-        for (int gi = 0; gi < 2; ++gi) {
+        for (int gi = 0; gi < kGraphRing; ++gi) {
             hipGraph_t graph = nullptr;
             FL_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             const int saved_prof = c->prof;
@@ -1005,7 +1015,10 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
                 c->gexec[gi] = nullptr;
                 return fail(FL_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
             }
+            // resources of the executable set up now, not on its first replay
+            FL_HIP(hipGraphUpload(c->gexec[gi], c->cap_stream));
         }
+        FL_HIP(hipStreamSynchronize(c->cap_stream));
         c->g_ws = c->ws.p;
         c->g_claims = c->claims.p;
         c->g_ctrs = c->ctrs.p;
@@ -1017,21 +1030,19 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
     }
     // The graph fetches its tables from its own pinned buffer.  Unchanged
     // tables are left in place; otherwise wait until the previous replay of
-    // this graph has fetched them before overwriting.
+    // this graph (kGraphRing replays ago) has fetched them before overwriting.
     Pinned& gp = c->gpin[c->g_next];
     if (!(gp.used == pr.blob.size() && memcmp(gp.p, pr.blob.data(), pr.blob.size()) == 0)) {
-        if (gp.pending) FL_HIP(hipEventSynchronize(gp.done));
-        gp.pending = false;
+        rc = wait_fetched(c, gp);
+        if (rc) return rc;
         memcpy(gp.p, pr.blob.data(), pr.blob.size());
         gp.used = pr.blob.size();
     }
     rc = next_epoch(c, stream);
     if (rc) return rc;
     FL_HIP(hipGraphLaunch(c->gexec[c->g_next], stream));
-    FL_HIP(hipEventRecord(gp.done, stream));
-    gp.pending = true;
-    c->g_next ^= 1;
-    return FL_OK;
+    c->g_next = (c->g_next + 1) % kGraphRing;
+    return note_fetch(c, gp, stream);
 }
 
 

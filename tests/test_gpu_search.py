@@ -234,3 +234,19 @@ def test_staging_ring_reuse_with_changing_tables(ctx):
         ctx.search_fuse_batched(bs[i], evs[i].params, outs[i])
         if it % 7 == 0 or it >= 57:
             assert_same(outs[i].numpy(), exps[i], f"call {it}")
+
+
+def test_graph_ring_reuse_with_changing_tables(ctx):
+    # 30 graph launches cycling through three batches of one shape (so the
+    # captured graphs are reused): each graph's table buffer is rewritten
+    # after a fence that follows its previous replay; every result must hold
+    import paper_2603_17201_amd as fl
+    evs = [synth.gen_tiny(80 + i, n_kf=3, n_mp=400) for i in range(3)]
+    exps = [oracle.search_fuse(ev) for ev in evs]
+    bs = [fl.DeviceBatch(ev, device=dev()) for ev in evs]
+    outs = [fl.FuseOutputs.empty(b.n_pairs, dev()) for b in bs]
+    for it in range(30):
+        i = it % 3
+        ctx.search_fuse_graph(bs[i], evs[i].params, outs[i])
+        if it % 4 == 0 or it >= 27:
+            assert_same(outs[i].numpy(), exps[i], f"graph call {it}")
