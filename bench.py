@@ -385,24 +385,10 @@ class Bench:
         return dict(ev=ev, n_pairs=n_pairs, ms_step=ms_step, ms_e2e=ms_e2e, ms_eager=ms_eager, plain=plain,
                     tuning=tuning, roof=roof, other=other, n_acc=n_acc)
 
-    def batch_graph(self, ev, label, steps):
-        """Graph launches (search + refinement) of one batch, device-resident,
-        and the plain path for a single event."""
-        fl, torch, ctx = self.fl, self.torch, self.ctx
-        P = ev.params
-        b = fl.DeviceBatch(ev, device=self.dev)
-        out = fl.FuseOutputs.empty(b.n_pairs, self.dev)
-        n_ev = b.n_events
-        S0 = np.asarray(ev.S_init if n_ev == 1 else ev.event_S_init).reshape(n_ev, 13)
-        S_init = torch.from_numpy(S0.copy()).to(self.dev)
-        S = S_init.clone()
-        gc.collect()
-        gc.disable()
-        ms = self.events_time(lambda: ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, None)),
-                              steps, 3)
-        res = dict(n_events=n_ev, n_kf=b.n_kf, n_pairs=b.n_pairs, ms_per_launch=ms, ms_per_event=ms / n_ev,
-                   pairs_per_s=b.n_pairs / (ms * 1e-3))
-        # kernel times of eager launches and the search kernel's roofline at this size
+    def kernel_rooflines(self, ev, b, P, out, S, S_init):
+        """Kernel times of eager launches (search + refinement) of one batch
+        and the search kernel's roofline at that size."""
+        ctx, torch = self.ctx, self.torch
         ctx.set_stats(True)
         ctx.search_fuse_batched(b, P, out)
         torch.cuda.synchronize()
@@ -427,7 +413,26 @@ class Bench:
         if self.peaks:
             roof["frac_of_measured_peak"] = (roof["achieved"] / self.peaks["hbm_copy_gbs"] if roof["bound"] == "hbm"
                                              else roof["achieved"] * 1e12 / self.peaks["valu_lane_ops_per_s"])
-        res.update(search_kernel_us=ks_ms * 1e3, refine_kernel_us=kr_ms * 1e3, search_roofline=roof)
+        return dict(search_kernel_us=ks_ms * 1e3, refine_kernel_us=kr_ms * 1e3, search_roofline=roof)
+
+    def batch_graph(self, ev, label, steps):
+        """Graph launches (search + refinement) of one batch, device-resident,
+        and the plain path for a single event."""
+        fl, torch, ctx = self.fl, self.torch, self.ctx
+        P = ev.params
+        b = fl.DeviceBatch(ev, device=self.dev)
+        out = fl.FuseOutputs.empty(b.n_pairs, self.dev)
+        n_ev = b.n_events
+        S0 = np.asarray(ev.S_init if n_ev == 1 else ev.event_S_init).reshape(n_ev, 13)
+        S_init = torch.from_numpy(S0.copy()).to(self.dev)
+        S = S_init.clone()
+        gc.collect()
+        gc.disable()
+        ms = self.events_time(lambda: ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, None)),
+                              steps, 3)
+        res = dict(n_events=n_ev, n_kf=b.n_kf, n_pairs=b.n_pairs, ms_per_launch=ms, ms_per_event=ms / n_ev,
+                   pairs_per_s=b.n_pairs / (ms * 1e-3))
+        res.update(self.kernel_rooflines(ev, b, P, out, S, S_init))
         if n_ev == 1 and not self.args.no_plain:
             host, host_S = self.host_buffers(b.n_pairs)
             plan = self.plain_plan(ev, b, out)
@@ -513,6 +518,10 @@ class Bench:
         res["init_trans_err_m_median"] = float(np.median(init[:, 1]))
         res["init_scale_err_median"] = float(np.median(init[:, 2]))
         res["failed_events"] = int((nm < 0).sum().item())
+        # kernel times and the search roofline of the stream's largest event
+        big = max(range(n_events), key=lambda i: bs[i].n_pairs)
+        kr = self.kernel_rooflines(evs[big], bs[big], P, outs[big], S[big], S_init[big])
+        res["largest_event"] = dict(event=big, n_pairs=bs[big].n_pairs, n_kf=bs[big].n_kf, **kr)
         if not self.args.no_plain:
             n_plain = min(n_events, self.args.stream_plain_events)
             ptimes = []

@@ -283,3 +283,29 @@ def test_stream_largest_event_graph_with_refine(ctx):
             assert err < 1e-6, (tuning, err)
     finally:
         ctx.set_tuning()
+
+
+def test_ten_uneven_events_one_launch(ctx):
+    """Ten uneven 60-keyframe events (4.68 M sparse pairs) in one graph launch
+    with ten refinement steps each, as the benchmark times them: every
+    search output bit-exact, every event's Sim3 within 1e-6 of float64
+    Gauss-Newton on the oracle's accepted pairs."""
+    import paper_2603_17201_amd as fl
+    evs = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
+           for i in range(10)]
+    B = synth.concat_events(evs)
+    assert int(B.pair_offset[-1]) == 4675858
+    exp = oracle.search_fuse(B, use_grid=True)
+    refs = [_event_gn(B, exp, e) for e in range(10)]
+    b = fl.DeviceBatch(B, device=dev())
+    S0 = np.stack([ev.S_init for ev in evs])
+    S = t(S0.copy())
+    nm = torch.zeros(10, dtype=torch.int32, device=dev())
+    got = ctx.search_fuse_graph(b, B.params, refine=(10, 2.45, S, None, nm)).numpy()
+    for k in got:
+        assert np.array_equal(got[k], exp[k]), k
+    S_gpu, n_gpu = S.cpu().numpy(), nm.cpu().numpy()
+    for e, (S_ref, n_ref) in enumerate(refs):
+        assert n_gpu[e] == n_ref, e
+        err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
+        assert err < 1e-6, (e, err)
