@@ -80,9 +80,12 @@ struct alignas(16) KpRec {
 
 // Per-keyframe counters (zero between launches: the ADD resolution that
 // follows every batched search resets them).
-enum : int { kKfAdd = 0, kKfCtrs = 1 };
+// Each keyframe's and each event's counters sit on a 128-byte line of their
+// own: device-scope atomics on one line serialise (about 12 ns apiece), and
+// the tiles of different keyframes reserve their lists at the same moment.
+enum : int { kKfAdd = 0, kKfCtrs = 32 };
 // Per-event counters.
-enum : int { kEvMatch = 0, kEvCtrs = 1 };
+enum : int { kEvMatch = 0, kEvCtrs = 32 };
 
 enum : int { kModeGlobal = 0, kModeLdsRec = 1, kModeLdsDesc = 2 };
 
