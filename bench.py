@@ -471,44 +471,67 @@ class Bench:
 
     def stream_events(self, n_events):
         """The stream of uneven loop events: each event resident, one graph
-        launch (search + 10 GN steps) per event, back to back."""
+        launch (search + 10 GN steps) per event.  Consecutive events alternate
+        between two contexts on two streams, so one event's search overlaps
+        the previous one's refinement (which keeps few CUs busy); the same
+        stream on one context and one stream is reported beside it."""
         import synth
-        torch, fl, ctx = self.torch, self.fl, self.ctx
+        torch, fl = self.torch, self.fl
         log(f"stream: generating {n_events} uneven events")
         evs = [synth.gen_c5_event(e) for e in range(n_events)]
         bs = [fl.DeviceBatch(ev, device=self.dev) for ev in evs]
         max_pairs = max(b.n_pairs for b in bs)
-        out = fl.FuseOutputs.empty(max_pairs, self.dev)
-        outs = [fl.FuseOutputs(out.best_idx[:b.n_pairs], out.best_dist[:b.n_pairs], out.second_dist[:b.n_pairs],
-                               out.decision[:b.n_pairs], out.target[:b.n_pairs]) for b in bs]
+        ctxs = [self.ctx, fl.Context(0)]
+        tv = self.ctx.get_tuning()
+        ctxs[1].set_tuning(tv.pairs_per_lane, tv.lds_mode, tv.wg_per_cu, tv.xcd_aware)
+        streams = [self.stream, torch.cuda.Stream(self.dev)]
+        bufs = [fl.FuseOutputs.empty(max_pairs, self.dev) for _ in range(2)]
+
+        def view(k, b):
+            o = bufs[k]
+            return fl.FuseOutputs(o.best_idx[:b.n_pairs], o.best_dist[:b.n_pairs], o.second_dist[:b.n_pairs],
+                                  o.decision[:b.n_pairs], o.target[:b.n_pairs])
+
+        outs = [[view(k, b) for b in bs] for k in range(2)]
         S_init = [torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(self.dev) for ev in evs]
         S = [s.clone() for s in S_init]
         nm = torch.zeros(n_events, dtype=torch.int32, device=self.dev)
         P = evs[0].params
 
-        def launch(i):
-            ctx.search_fuse_graph(bs[i], P, outs[i], refine=(GN_ITERS, HUBER, S[i], None, nm[i:i + 1]))
+        def launch(i, n_ctx):
+            k = i % n_ctx
+            ctxs[k].search_fuse_graph(bs[i], P, outs[k][i], refine=(GN_ITERS, HUBER, S[i], None, nm[i:i + 1]),
+                                      stream=streams[k])
+
+        def timed(n_ctx):
+            for i in range(n_events):
+                S[i].copy_(S_init[i])
+            torch.cuda.synchronize()
+            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(n_events)]
+            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(n_events)]
+            t0 = time.perf_counter()
+            for i in range(n_events):
+                e0[i].record(streams[i % n_ctx])
+                launch(i, n_ctx)
+                e1[i].record(streams[i % n_ctx])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            return wall, [e0[i].elapsed_time(e1[i]) for i in range(n_events)]
 
         gc.collect()
         gc.disable()
-        for i in range(n_events):   # first pass: grows the workspace to the largest event, captures
-            launch(i)
-        torch.cuda.synchronize()
-        for i in range(n_events):
-            S[i].copy_(S_init[i])
-        torch.cuda.synchronize()
-        evts = [torch.cuda.Event(enable_timing=True) for _ in range(n_events + 1)]
-        t0 = time.perf_counter()
-        evts[0].record(self.stream)
-        for i in range(n_events):
-            launch(i)
-            evts[i + 1].record(self.stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        per = [evts[i].elapsed_time(evts[i + 1]) for i in range(n_events)]
+        for n_ctx in (1, 2):   # first passes: grow the workspaces to the largest event, capture
+            for i in range(n_events):
+                launch(i, n_ctx)
+            torch.cuda.synchronize()
+        wall1, per1 = timed(1)
+        wall, per = timed(2)
         total = int(sum(b.n_pairs for b in bs))
         res = dict(n_events=n_events, total_pairs=total, events_per_s=n_events / wall, pairs_per_s=total / wall,
-                   p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)))
+                   p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
+                   launch="graph replays alternating between two contexts on two streams",
+                   one_context=dict(events_per_s=n_events / wall1, pairs_per_s=total / wall1,
+                                    p50_ms=float(np.percentile(per1, 50)), p99_ms=float(np.percentile(per1, 99))))
         errs = np.array([sim3_error(S[i].cpu().numpy()[0], ev.S_true) for i, ev in enumerate(evs)])
         res["final_rot_err_deg_median"] = float(np.median(errs[:, 0]))
         res["final_trans_err_m_median"] = float(np.median(errs[:, 1]))
@@ -520,22 +543,24 @@ class Bench:
         res["failed_events"] = int((nm < 0).sum().item())
         # kernel times and the search roofline of the stream's largest event
         big = max(range(n_events), key=lambda i: bs[i].n_pairs)
-        kr = self.kernel_rooflines(evs[big], bs[big], P, outs[big], S[big], S_init[big])
+        kr = self.kernel_rooflines(evs[big], bs[big], P, outs[0][big], S[big], S_init[big])
         res["largest_event"] = dict(event=big, n_pairs=bs[big].n_pairs, n_kf=bs[big].n_kf, **kr)
         if not self.args.no_plain:
             n_plain = min(n_events, self.args.stream_plain_events)
             ptimes = []
             for i in range(n_plain):
                 host, host_S = self.host_buffers(bs[i].n_pairs)
-                plan = self.plain_plan(evs[i], bs[i], outs[i])
-                ptimes.append(self.plain_event(plan, bs[i], outs[i], P, S[i], S_init[i], host, host_S))
+                plan = self.plain_plan(evs[i], bs[i], outs[0][i])
+                ptimes.append(self.plain_event(plan, bs[i], outs[0][i], P, S[i], S_init[i], host, host_S))
             res["plain_events"] = n_plain
             res["plain_p50_ms"] = float(np.percentile(ptimes, 50))
             res["plain_p99_ms"] = float(np.percentile(ptimes, 99))
             res["plain_events_per_s"] = n_plain / (sum(ptimes) * 1e-3)
-            res["batched_vs_plain_same_events"] = sum(ptimes) / sum(per[:n_plain])
+            res["batched_vs_plain_same_events"] = sum(ptimes) / sum(per1[:n_plain])
         gc.enable()
-        log(f"stream: {res['events_per_s']:.1f} events/s, p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms")
+        log(f"stream: {res['events_per_s']:.1f} events/s on two contexts and streams "
+            f"({res['one_context']['events_per_s']:.1f} on one), p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms")
+        ctxs[1].close()
         return res
 
 

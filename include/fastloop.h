@@ -147,7 +147,16 @@ typedef struct {
 } fl_batch;
 
 /* Refinement of each event's loop Sim3 after matching (Gauss-Newton on the
- * Huber reprojection residual of the accepted pairs). */
+ * Huber reprojection residual of the accepted pairs).
+ * The workgroups that refine one event exchange partial sums every step and
+ * wait for one another, so they must be resident together: one launch keeps
+ * at most one such workgroup per compute unit (at most 64 per event, 256 in
+ * all), and a single-event launch uses at most 64.  Launches from several
+ * contexts may overlap on different streams (for instance consecutive events
+ * alternating between two contexts) as long as their events' workgroups
+ * together stay within the compute units, which two single-event launches
+ * always do.  A wait that does not end within its bound reports the event as
+ * failed (event_n_matched = -1); it never blocks the device. */
 typedef struct {
     int32_t n_iters;        /* 0 = no refinement */
     float huber_delta;      /* pixels */

@@ -309,3 +309,42 @@ def test_ten_uneven_events_one_launch(ctx):
         assert n_gpu[e] == n_ref, e
         err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
         assert err < 1e-6, (e, err)
+
+
+def test_two_contexts_on_two_streams(ctx):
+    """Consecutive events alternating between two contexts on two streams
+    (one event's search overlapping the previous one's refinement), graph
+    launches with ten refinement steps: every event's outputs bit-exact and
+    its Sim3 within 1e-6 of float64 Gauss-Newton."""
+    import paper_2603_17201_amd as fl
+    evs = [synth.gen_c3(seed=330 + i, n_kf=10 + 2 * i, n_mp=6000 + 500 * i, id_base=1000 + 10 ** 6 * i,
+                        fresh_base=10 ** 9 + 10 ** 7 * i) for i in range(6)]
+    Bs = [synth.concat_events([ev]) for ev in evs]
+    exps = [oracle.search_fuse(B, use_grid=True) for B in Bs]
+    refs = [_event_gn(B, exp, 0) for B, exp in zip(Bs, exps)]
+    ctx2 = fl.Context(0)
+    try:
+        ctxs = [ctx, ctx2]
+        streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+        bs = [fl.DeviceBatch(B, device=dev()) for B in Bs]
+        outs = [fl.FuseOutputs.empty(b.n_pairs, dev()) for b in bs]
+        S = [t(ev.S_init.reshape(1, 13).copy()) for ev in evs]
+        nm = torch.zeros(len(evs), dtype=torch.int32, device=dev())
+        torch.cuda.synchronize()
+        for rep in range(2):
+            for i in range(len(evs)):
+                k = i % 2
+                ctxs[k].search_fuse_graph(bs[i], Bs[i].params, outs[i], refine=(10, 2.45, S[i], None, nm[i:i + 1]),
+                                          stream=streams[k])
+            torch.cuda.synchronize()
+            for i, (exp, (S_ref, n_ref)) in enumerate(zip(exps, refs)):
+                got = outs[i].numpy()
+                for key in got:
+                    assert np.array_equal(got[key], exp[key]), (rep, i, key)
+                assert int(nm[i].item()) == n_ref, (rep, i)
+                if rep == 0:
+                    err = np.linalg.norm(sim3.log(sim3.compose(S[i].cpu().numpy()[0], sim3.inverse(S_ref))))
+                    assert err < 1e-6, (i, err)
+                S[i].copy_(t(evs[i].S_init.reshape(1, 13).copy()))
+    finally:
+        ctx2.close()
