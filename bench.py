@@ -15,7 +15,8 @@ Prints one JSON line.  Headline workload: a loop event of 20 keyframes
 (752x480, 1,200 keypoints each) and 15,000 map points, 300,000 dense pairs.
 Secondary workloads (skipped with --quick): the uneven 60-keyframe event
 with sparse covisibility pairs, ten of them in one launch, the residual
-forward/backward on 50,000 pairs, and a stream of uneven events.
+forward/backward on 50,000 pairs, the projection searches of loop verification
+(one keyframe; three keyframes in one launch) and a stream of uneven events.
 """
 from __future__ import annotations
 
@@ -443,6 +444,38 @@ class Bench:
         log(f"{label}: {ms * 1e3:.1f} us per launch ({n_ev} events, {b.n_pairs} pairs)")
         return res
 
+    def projection_search(self, steps):
+        """The projection searches of loop verification (ratio test on, the
+        wider window), search only and device-resident: one keyframe, and
+        three keyframes in one launch against three one-keyframe calls."""
+        import synth
+        fl, ctx = self.fl, self.ctx
+        P = synth.verification_params()
+        res = dict(params=dict(win_px=P.win_px, nn_ratio=P.nn_ratio, hamming_th=P.hamming_th))
+        for name, ev in (("one_keyframe", synth.gen_c1()), ("three_keyframes", synth.gen_c2(seed=212, n_kf=3))):
+            b = fl.DeviceBatch(ev, device=self.dev)
+            out = fl.FuseOutputs.empty(b.n_pairs, self.dev)
+            plan = self.plain_plan(ev, b, out)
+
+            def plain():
+                for pts, kps, o, _p0, _p1, sim3, cam in plan:
+                    ctx.search_fuse(*pts, *kps, sim3, cam, P, out=o)
+            gc.collect()
+            gc.disable()
+            ms_plain = self.events_time(plain, steps, 3)
+            ms_eager = self.events_time(lambda: ctx.search_fuse_batched(b, P, out), steps, 3)
+            ms_graph = self.events_time(lambda: ctx.search_fuse_graph(b, P, out), steps, 3)
+            gc.enable()
+            dec = out.numpy()["decision"]
+            best = min(ms_eager, ms_graph)
+            res[name] = dict(n_kf=b.n_kf, n_pairs=b.n_pairs, accepted=int(((dec == fl.ADD) | (dec == fl.FUSE)).sum()),
+                             us_plain_calls=ms_plain * 1e3, us_batched_eager=ms_eager * 1e3,
+                             us_batched_graph=ms_graph * 1e3, pairs_per_s=b.n_pairs / (best * 1e-3),
+                             batched_vs_plain=ms_plain / best)
+            log(f"projection search, {name}: {best * 1e3:.1f} us batched, {ms_plain * 1e3:.1f} us in "
+                f"{b.n_kf} plain call(s) ({b.n_pairs} pairs)")
+        return res
+
     def residual(self):
         import synth
         torch, fl, ctx = self.torch, self.fl, self.ctx
@@ -638,6 +671,7 @@ def main():
         B.event_S_init = np.stack([e.S_init for e in evs])
         secondary["uneven_event_60kf_x10_one_launch"] = bench.batch_graph(B, "ten uneven events", 10)
         secondary["residual_50k"] = bench.residual()
+        secondary["projection_search"] = bench.projection_search(args.steps)
         if args.stream_events > 0:
             secondary["stream"] = bench.stream_events(args.stream_events)
 

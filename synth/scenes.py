@@ -58,6 +58,14 @@ class LoopParams:
     nn_ratio: float = 0.0
 
 
+def verification_params() -> LoopParams:
+    """Thresholds taken for the projection searches of loop verification
+    (one keyframe, or three in one launch): a 10 px x 1.2^octave window and
+    the nearest-neighbour ratio test at 0.75, Hamming threshold 50.  The
+    paper gives no constants for that stage; these are a reading."""
+    return LoopParams(win_px=10.0, nn_ratio=0.75)
+
+
 @dataclass
 class Event:
     """One loop event.  Keyframe-major arrays are concatenated over keyframes."""

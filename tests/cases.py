@@ -75,3 +75,30 @@ def conflict_case(order):
         cam8=[100, 100, 50, 50, 100, 100, 0, 0],
         params=LoopParams(win_px=3.0, n_octaves=4, grid_cols=8, grid_rows=8), name="conflict")
     return ev
+
+
+def with_near_duplicates(ev, frac=0.4, flips=(2, 10), seed=7):
+    """A one-keyframe event with extra keypoints next to a fraction of its
+    planted ones: 0.4 px away, same octave, free, with a few descriptor bits
+    flipped, so the second-best distance of those points comes close to the
+    best and the ratio test has something to reject."""
+    import dataclasses
+    assert ev.n_kf == 1
+    rng = np.random.default_rng(seed)
+    planted = np.asarray(ev.planted_kp[ev.planted_kf == 0], np.int64)
+    pick = rng.choice(planted, size=int(frac * len(planted)), replace=False)
+    desc = ev.kp_desc[pick].copy()
+    for r in range(len(pick)):
+        bits = rng.choice(256, size=int(rng.integers(flips[0], flips[1] + 1)), replace=False)
+        for b in bits:
+            desc[r, b // 8] ^= np.uint8(1 << (b % 8))
+    xy = ev.kp_xy[pick] + np.float32(0.4)
+    n0 = int(ev.kp_offset[1])
+    return dataclasses.replace(
+        ev,
+        kp_xy=np.concatenate([ev.kp_xy, xy.astype(np.float32)]),
+        kp_oct=np.concatenate([ev.kp_oct, ev.kp_oct[pick]]),
+        kp_desc=np.concatenate([ev.kp_desc, desc]),
+        kp_owner=np.concatenate([ev.kp_owner, np.full(len(pick), -1, np.int32)]),
+        kp_offset=np.array([0, n0 + len(pick)], dtype=ev.kp_offset.dtype),
+        name=ev.name + "+dup")

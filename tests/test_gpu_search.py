@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import synth
-from cases import conflict_case, hand_case
+from cases import conflict_case, hand_case, with_near_duplicates
 from gpu_util import FIELDS, assert_same, dev, plain_per_keyframe, t
 
 pytestmark = pytest.mark.gpu
@@ -250,3 +250,46 @@ def test_graph_ring_reuse_with_changing_tables(ctx):
         ctx.search_fuse_graph(bs[i], evs[i].params, outs[i])
         if it % 4 == 0 or it >= 27:
             assert_same(outs[i].numpy(), exps[i], f"graph call {it}")
+
+
+def _accepted(o):
+    return int(((o["decision"] == oracle.ADD) | (o["decision"] == oracle.FUSE)).sum())
+
+
+def test_projection_search_one_keyframe(ctx):
+    """Loop verification's single projection search: every point against one
+    keyframe with near-duplicate keypoints, the wider window and the ratio
+    test on; the plain call and a batched launch, bit-exact."""
+    ev = with_near_duplicates(synth.gen_c1())
+    P = synth.verification_params()
+    exp = oracle.search_fuse(ev, params=P)
+    loose = oracle.search_fuse(ev, params=synth.LoopParams(win_px=P.win_px))
+    assert _accepted(exp) < _accepted(loose)   # the ratio test rejects some matches here
+    assert_same(plain_per_keyframe(ctx, ev, P), exp, "PS1 plain")
+    assert_same(batched(ctx, ev, params=P), exp, "PS1 batched")
+    assert_same(batched(ctx, ev, params=P, graph=True), exp, "PS1 graph")
+
+
+def test_projection_search_three_keyframes_one_launch(ctx):
+    """Loop verification's triple projection search in one launch: the same
+    points against three keyframes (one event, dense pairs), and three
+    independent one-keyframe searches batched together; ratio test on."""
+    P = synth.verification_params()
+    ev = synth.gen_c2(seed=212, n_kf=3, n_mp=15000)
+    exp = oracle.search_fuse(ev, params=P, use_grid=True)
+    assert_same(batched(ctx, ev, params=P), exp, "PS3 one event")
+    assert_same(batched(ctx, ev, params=P, graph=True), exp, "PS3 one event, graph")
+    evs = [with_near_duplicates(synth.gen_c1(seed=101 + i), seed=7 + i) for i in range(3)]
+    B = synth.concat_events(evs)
+    exp3 = oracle.search_fuse(B, params=P)
+    assert _accepted(exp3) < _accepted(oracle.search_fuse(B, params=synth.LoopParams(win_px=P.win_px)))
+    assert_same(batched(ctx, B, params=P), exp3, "PS3 three events")
+
+
+def test_c2_with_ratio_test(ctx):
+    """The full loop event with the ratio test on (0.75) and the fusion
+    window."""
+    ev = synth.gen_c2()
+    P = synth.LoopParams(nn_ratio=0.75)
+    exp = oracle.search_fuse(ev, params=P, use_grid=True)
+    assert_same(batched(ctx, ev, params=P), exp, "c2 ratio")
