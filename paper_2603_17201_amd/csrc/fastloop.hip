@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <queue>
 #include <vector>
 
 #include "fastloop.h"
@@ -322,6 +323,54 @@ size_t blob_take(std::vector<char>& blob, size_t n) {
     return off;
 }
 
+// Pairs per tile of every keyframe; returns the number of tiles.  A
+// workgroup runs on one CU and spreads a tile's waves over its four SIMDs,
+// so a tile takes time in proportion to its waves per SIMD.  Full tiles
+// (tile_cap pairs) are the fewest; while they number fewer than the
+// workgroup slots, the spare slots go one at a time to the keyframe whose
+// tiles cost most (pairs times the keypoint density the candidate scan
+// meets), which cuts that keyframe into more, smaller tiles.  A tile of more
+// than 256 pairs is a multiple of 256 (the same waves on every SIMD), a
+// smaller one a multiple of 64.
+int64_t plan_tiles(const fl_batch* B, int cells, int64_t tile_cap, int slots, std::vector<int32_t>& tile) {
+    const int n_kf = B->n_kf;
+    tile.assign(n_kf, (int32_t)tile_cap);
+    std::vector<int64_t> nt(n_kf, 0), most(n_kf, 0);
+    std::vector<double> cost(n_kf, 0.0);
+    int64_t total = 0;
+    for (int k = 0; k < n_kf; ++k) {
+        const int64_t np = B->pair_offset[k + 1] - B->pair_offset[k];
+        const int n_kp = B->kp_offset[k + 1] - B->kp_offset[k];
+        nt[k] = (np + tile_cap - 1) / tile_cap;
+        most[k] = (np + kWave - 1) / kWave;
+        cost[k] = (double)np * (1.0 + 2.0 * n_kp / std::max(1, cells));
+        total += nt[k];
+    }
+    if (total < slots) {
+        std::priority_queue<std::pair<double, int>> q;   // (cost per tile, keyframe)
+        for (int k = 0; k < n_kf; ++k)
+            if (nt[k] > 0 && nt[k] < most[k]) q.push({cost[k] / (double)nt[k], k});
+        while (total < slots && !q.empty()) {
+            const int k = q.top().second;
+            q.pop();
+            ++nt[k];
+            ++total;
+            if (nt[k] < most[k]) q.push({cost[k] / (double)nt[k], k});
+        }
+    }
+    int64_t n = 0;
+    for (int k = 0; k < n_kf; ++k) {
+        const int64_t np = B->pair_offset[k + 1] - B->pair_offset[k];
+        if (np <= 0) continue;
+        int64_t ts = (np + nt[k] - 1) / nt[k];
+        const int64_t unit = ts > 256 ? 256 : kWave;
+        ts = std::min(tile_cap, (ts + unit - 1) / unit * unit);
+        tile[k] = (int32_t)ts;
+        n += (np + ts - 1) / ts;
+    }
+    return n;
+}
+
 // Choose the staging mode: the tuned one if its LDS footprint fits.
 int pick_mode(const fl_ctx* c, int want, int kp_cap, int cells, int hash_cap) {
     for (int m = want; m > kModeGlobal; --m)
@@ -338,7 +387,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const int cells = P->grid_cols * P->grid_rows;
     const int n_kf = B->n_kf, n_ev = B->n_events;
     const int ppl = c->tune.pairs_per_lane;
-    const int64_t tile_pairs = (int64_t)kSearchBlock * ppl;
+    const int64_t tile_cap = (int64_t)kSearchBlock * ppl;
     const bool refine = R && R->n_iters > 0;
     pr.ppl = ppl;
     pr.refine_iters = refine ? R->n_iters : 0;
@@ -351,10 +400,10 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
 
     // workgroups of the search launch (every slot in graph mode, at most one
     // per tile otherwise)
-    int64_t n_tiles_all = 0;
-    for (int k = 0; k < n_kf; ++k)
-        n_tiles_all += (B->pair_offset[k + 1] - B->pair_offset[k] + tile_pairs - 1) / tile_pairs;
-    int grid = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
+    const int slots = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
+    std::vector<int32_t> kf_tile;
+    const int64_t n_tiles_all = plan_tiles(B, cells, tile_cap, slots, kf_tile);
+    int grid = slots;
     if (!graph) grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles_all));
     pr.grid = grid;
 
@@ -408,7 +457,8 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             hash_total += hsize;
             kd.pair_off = B->pair_offset[k];
             kd.n_pairs = B->pair_offset[k + 1] - B->pair_offset[k];
-            kd.n_tiles = (int32_t)((kd.n_pairs + tile_pairs - 1) / tile_pairs);
+            kd.tile_pairs = kf_tile[k];
+            kd.n_tiles = (int32_t)((kd.n_pairs + kd.tile_pairs - 1) / kd.tile_pairs);
             // room for every pair: no provisional ADD can overflow the list, so
             // the kernel resolves them without cache write-backs (the test
             // hook's smaller caps exercise the overflow protocol)
@@ -418,7 +468,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             kd.add_cap = (int32_t)acap;
             add_total += acap;
             // a pair costs more where keypoints are dense (more candidates scanned)
-            tile_cost[k] = (double)tile_pairs * (1.0 + 2.0 * kd.n_kp / std::max(1, cells));
+            tile_cost[k] = (double)kd.tile_pairs * (1.0 + 2.0 * kd.n_kp / std::max(1, cells));
         }
     }
     if (add_total > INT32_MAX || list_total > INT32_MAX || hash_total > INT32_MAX)
@@ -540,7 +590,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.n_kp_total = B->n_kp_total;
     h.n_pairs = B->n_pairs;
     h.n_tiles = (int32_t)n_tiles;
-    h.tile_pairs = (int32_t)tile_pairs;
+    h.tile_cap = (int32_t)tile_cap;
     h.cells = cells;
     h.grid_cols = P->grid_cols;
     h.grid_rows = P->grid_rows;

@@ -35,7 +35,7 @@ struct alignas(16) KfDesc {
     int32_t n_tiles;
     int32_t add_off;     // region of the provisional-ADD list
     int32_t add_cap;
-    int32_t pad0;
+    int32_t tile_pairs;  // pairs per tile of this keyframe (a whole number of waves)
     int64_t pair_off;
     int64_t n_pairs;
 };
@@ -92,7 +92,7 @@ enum : int { kModeGlobal = 0, kModeLdsRec = 1, kModeLdsDesc = 2 };
 struct alignas(16) BatchHdr {
     int32_t n_events, n_kf, n_mp, n_kp_total;
     int64_t n_pairs;
-    int32_t n_tiles, tile_pairs;
+    int32_t n_tiles, tile_cap;   // tiles of the batch; the largest tile (workgroup size x pairs per lane)
     int32_t cells, grid_cols, grid_rows, n_octaves;
     int32_t hamming_th;
     float nn_ratio;

@@ -338,13 +338,14 @@ __device__ __forceinline__ void wave_append(bool want, uint32_t* counter, T* lis
 
 // ---------------------------------------------------------------------------
 // Fused batched search.  Each workgroup owns a contiguous, cost-balanced run
-// of tiles (1024 * PPL consecutive pairs of one keyframe) inside the range of
-// its XCD (workgroups are dispatched to the 8 XCDs round-robin), so the
-// keyframes of an XCD stay in its L2 and no atomic is spent on scheduling.
-// When its tile moves to a new keyframe the workgroup builds that keyframe's
-// grid, records (and descriptors) and owner hash set in LDS.  The workgroup
-// finishing the last tile of a keyframe resolves that keyframe's ADD
-// conflicts, so no second kernel is needed.
+// of tiles inside the range of its XCD (workgroups are dispatched to the 8
+// XCDs round-robin), so the keyframes of an XCD stay in its L2 and no atomic
+// is spent on scheduling.  A tile is up to 1024 * PPL consecutive pairs of
+// one keyframe, a whole number of waves; pair j of a tile goes to thread
+// j mod 1024, so a tile smaller than the workgroup leaves its last waves
+// idle.  When its tile moves to a new keyframe the workgroup builds that
+// keyframe's grid, records (and descriptors) and owner hash set in LDS.  The
+// ADD conflicts are resolved by the next kernel on the stream.
 
 struct KfView {
     const int32_t* cs;
@@ -425,8 +426,8 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         const int k = t == range.x ? range.w : h.kf_order[slot];
         const KfDesc kd = kf_tab[k];          // by value: kept in registers across the stores below
         const EventDesc ed = h.ev[kd.event];
-        const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * h.tile_pairs;
-        const int64_t pe = min(pb + (int64_t)h.tile_pairs, kd.pair_off + kd.n_pairs);
+        const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * kd.tile_pairs;
+        const int64_t pe = min(pb + (int64_t)kd.tile_pairs, kd.pair_off + kd.n_pairs);
         // A provisional ADD is written as ADD here; the ADD conflicts are
         // resolved after the whole search, by the next kernel on the stream
         // (the refinement, or the resolution kernel when there is none), which
