@@ -16,11 +16,13 @@ Prints one JSON line.  Headline workload: a loop event of 20 keyframes
 Secondary workloads (skipped with --quick): the uneven 60-keyframe event
 with sparse covisibility pairs, ten of them in one launch, the residual
 forward/backward on 50,000 pairs, the projection searches of loop verification
-(one keyframe; three keyframes in one launch) and a stream of uneven events.
+(one keyframe; three keyframes in one launch; two searches of one keyframe in
+one launch) and a stream of uneven events.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import gc
 import hashlib
 import json
@@ -474,6 +476,29 @@ class Bench:
                              batched_vs_plain=ms_plain / best)
             log(f"projection search, {name}: {best * 1e3:.1f} us batched, {ms_plain * 1e3:.1f} us in "
                 f"{b.n_kf} plain call(s) ({b.n_pairs} pairs)")
+        # the two searches on the current keyframe before and after the Sim3
+        # optimisation: both passes in one launch against two batched calls
+        ev = synth.gen_c1()
+        passes = synth.ps2_passes(ev)
+        b = fl.DeviceBatch(ev, device=self.dev)
+        b2 = fl.DeviceBatch(dataclasses.replace(ev, kf_sim3=passes[1][1]), device=self.dev)
+        outs = [fl.FuseOutputs.empty(b.n_pairs, self.dev) for _ in passes]
+        spec = [(P, S, o) for (P, S), o in zip(passes, outs)]
+
+        def two_calls():
+            ctx.search_fuse_batched(b, passes[0][0], outs[0])
+            ctx.search_fuse_batched(b2, passes[1][0], outs[1])
+        gc.collect()
+        gc.disable()
+        ms_two = self.events_time(two_calls, steps, 3)
+        ms_one = self.events_time(lambda: ctx.search_fuse_passes(b, spec), steps, 3)
+        gc.enable()
+        res["two_searches_one_keyframe"] = dict(n_pairs_per_search=b.n_pairs, us_one_launch=ms_one * 1e3,
+                                                us_two_calls=ms_two * 1e3, pairs_per_s=2 * b.n_pairs / (ms_one * 1e-3),
+                                                one_launch_vs_two_calls=ms_two / ms_one,
+                                                params=[dict(win_px=P.win_px, nn_ratio=P.nn_ratio) for P, _ in passes])
+        log(f"projection search, two searches on one keyframe: {ms_one * 1e3:.1f} us in one launch, "
+            f"{ms_two * 1e3:.1f} us in two calls")
         return res
 
     def residual(self):

@@ -222,6 +222,33 @@ int fl_search_fuse_graph_launch(fl_ctx* ctx, const fl_batch* B /* host */, const
                                 const fl_fuse_out* out /* host */, const fl_refine* refine /* host */,
                                 hipStream_t stream);
 
+/* One search of a batch in fl_search_fuse_passes: the search transform of
+ * each keyframe, the thresholds and the outputs of this pass. */
+#define FL_MAX_PASSES 4
+typedef struct {
+    const fl_sim3* kf_sim3;   /* host [n_kf] search transform of each keyframe for this pass; NULL: the batch's */
+    fl_params params;         /* win_px, hamming_th and nn_ratio may differ between passes; scale_factor,
+                                 n_octaves, grid_cols and grid_rows must equal those of pass 0 */
+    fl_fuse_out out;          /* device [n_pairs] each; no array shared with another pass */
+} fl_pass;
+
+/* Several independent searches of one resident batch, launched together
+ * (task parallelism, Sec. IV-C: searches of the same kind of input with no
+ * dependency between them, such as the projection searches on the current
+ * keyframe before and after the Sim3 optimization, run concurrently from one
+ * transfer and keep their outputs in separate batches).  The tiles of every
+ * pass share one launch, and a workgroup stages a keyframe's grid once for
+ * all passes of it.  Pass p's outputs are identical to those of
+ * fl_search_fuse_batched on the batch with passes[p].kf_sim3 (when given),
+ * &passes[p].params and &passes[p].out; the ADD conflicts of a pass are
+ * resolved within that pass.  No refinement.  Errors: those of
+ * fl_search_fuse_batched for any pass; FL_EINVAL for passes NULL, n_pass
+ * outside [1, FL_MAX_PASSES], grid or octave fields that differ from pass 0,
+ * or two passes sharing an output array; FL_ERANGE when n_pass * n_kp_total
+ * exceeds 2^31-1. */
+int fl_search_fuse_passes(fl_ctx* ctx, const fl_batch* B /* host */, int32_t n_pass,
+                          const fl_pass* passes /* host [n_pass] */, hipStream_t stream);
+
 /* Per-event Sim3 refinement on the pairs a previous search accepted (ADD or
  * FUSE; observation = matched keypoint position), eagerly launched.
  * B must describe the same batch and out hold that search's results. */

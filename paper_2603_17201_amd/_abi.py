@@ -55,6 +55,13 @@ class Batch(ctypes.Structure):
                 ("mp_xyz", c_void_p), ("mp_desc", c_void_p), ("mp_dmax", c_void_p), ("mp_id", c_void_p)]
 
 
+MAX_PASSES = 4   # FL_MAX_PASSES
+
+
+class Pass(ctypes.Structure):
+    _fields_ = [("kf_sim3", c_void_p), ("params", Params), ("out", FuseOut)]
+
+
 class Refine(ctypes.Structure):
     _fields_ = [("n_iters", c_int32), ("huber_delta", c_float), ("event_S", c_void_p),
                 ("event_S32", c_void_p), ("event_n_matched", c_void_p)]
@@ -82,6 +89,7 @@ SIGNATURES = [
     ("fl_validate_batch", c_int32, [ctypes.POINTER(Batch), ctypes.POINTER(Params), ctypes.POINTER(FuseOut)]),
     ("fl_search_fuse_batched", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Params),
                                          ctypes.POINTER(FuseOut), ctypes.POINTER(Refine), c_void_p]),
+    ("fl_search_fuse_passes", c_int32, [c_void_p, ctypes.POINTER(Batch), c_int32, ctypes.POINTER(Pass), c_void_p]),
     ("fl_search_fuse_graph_launch", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Params),
                                               ctypes.POINTER(FuseOut), ctypes.POINTER(Refine), c_void_p]),
     ("fl_refine_events", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(FuseOut),

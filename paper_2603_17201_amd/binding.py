@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import Batch, FuseOut, Keyframe, Params, Pinhole, Refine, Sim3, Tuning
+from ._abi import Batch, FuseOut, Keyframe, Params, Pass, Pinhole, Refine, Sim3, Tuning
 
 
 class FlError(ValueError):
@@ -275,6 +275,28 @@ class Context:
         _check(self._lib.fl_search_fuse_batched(self._h, ctypes.byref(b), ctypes.byref(P), ctypes.byref(o), rp,
                                                 self._stream(stream)), "fl_search_fuse_batched")
         return out
+
+    def search_fuse_passes(self, batch: DeviceBatch, passes, stream=None) -> list:
+        """Several searches of one resident batch in one launch.  passes: a
+        sequence of (params, kf_sim3, out): kf_sim3 is None (the batch's) or a
+        host array [n_kf, 16] in the batch's kf_sim3 form; out is a
+        FuseOutputs or None (allocated).  Returns the outputs of every pass."""
+        n = len(passes)
+        arr = (Pass * max(n, 1))()
+        keep, outs = [], []
+        for i, (params, kf_sim3, out) in enumerate(passes):
+            if out is None:
+                out = FuseOutputs.empty(batch.n_pairs, self.device)
+            outs.append(out)
+            arr[i].params = params_struct(params)
+            arr[i].out = out.struct()
+            if kf_sim3 is not None:
+                a = np.ascontiguousarray(kf_sim3, np.float32).reshape(batch.n_kf, 16)
+                keep.append(a)
+                arr[i].kf_sim3 = a.ctypes.data_as(ctypes.c_void_p)
+        _check(self._lib.fl_search_fuse_passes(self._h, ctypes.byref(batch.struct()), n, arr, self._stream(stream)),
+               "fl_search_fuse_passes")
+        return outs
 
     def _refine_struct(self, batch, refine):
         if refine is None:

@@ -332,15 +332,16 @@ size_t blob_take(std::vector<char>& blob, size_t n) {
 // meets), which cuts that keyframe into more, smaller tiles.  A tile of more
 // than 256 pairs is a multiple of 256 (the same waves on every SIMD), a
 // smaller one a multiple of 64.
-int64_t plan_tiles(const fl_batch* B, int cells, int64_t tile_cap, int slots, std::vector<int32_t>& tile) {
-    const int n_kf = B->n_kf;
+int64_t plan_tiles(const std::vector<int64_t>& pairs, const std::vector<int32_t>& kps, int cells, int64_t tile_cap,
+                   int slots, std::vector<int32_t>& tile) {
+    const int n_kf = (int)pairs.size();
     tile.assign(n_kf, (int32_t)tile_cap);
     std::vector<int64_t> nt(n_kf, 0), most(n_kf, 0);
     std::vector<double> cost(n_kf, 0.0);
     int64_t total = 0;
     for (int k = 0; k < n_kf; ++k) {
-        const int64_t np = B->pair_offset[k + 1] - B->pair_offset[k];
-        const int n_kp = B->kp_offset[k + 1] - B->kp_offset[k];
+        const int64_t np = pairs[k];
+        const int n_kp = kps[k];
         nt[k] = (np + tile_cap - 1) / tile_cap;
         most[k] = (np + kWave - 1) / kWave;
         cost[k] = (double)np * (1.0 + 2.0 * n_kp / std::max(1, cells));
@@ -360,7 +361,7 @@ int64_t plan_tiles(const fl_batch* B, int cells, int64_t tile_cap, int slots, st
     }
     int64_t n = 0;
     for (int k = 0; k < n_kf; ++k) {
-        const int64_t np = B->pair_offset[k + 1] - B->pair_offset[k];
+        const int64_t np = pairs[k];
         if (np <= 0) continue;
         int64_t ts = (np + nt[k] - 1) / nt[k];
         const int64_t unit = ts > 256 ? 256 : kWave;
@@ -382,10 +383,17 @@ int pick_mode(const fl_ctx* c, int want, int kp_cap, int cells, int hash_cap) {
 // so a captured graph can be replayed for them (the grid is always every
 // workgroup slot, empty ranges exit at once; the dynamic LDS is rounded up to
 // a 16 KB step).
+// passes: n_pass searches of the batch in one launch (NULL: one, with P, out
+// and the batch's kf_sim3).  P holds the grid and octave fields every pass
+// shares.  Each (keyframe, pass) gets a descriptor of its own, keyframe-major,
+// so the passes of a keyframe are consecutive in the tile order.
 int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_out* out, const fl_refine* R,
-                  bool refine_scan, Prepared& pr, bool graph = false) {
+                  bool refine_scan, Prepared& pr, bool graph = false, int n_pass = 1,
+                  const fl_pass* passes = nullptr) {
     const int cells = P->grid_cols * P->grid_rows;
     const int n_kf = B->n_kf, n_ev = B->n_events;
+    const int n_vk = n_kf * n_pass;   // descriptors
+    if ((int64_t)n_pass * B->n_kp_total > INT32_MAX) return fail(FL_ERANGE, "too many keypoints for %d passes", n_pass);
     const int ppl = c->tune.pairs_per_lane;
     const int64_t tile_cap = (int64_t)kSearchBlock * ppl;
     const bool refine = R && R->n_iters > 0;
@@ -402,7 +410,17 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     // per tile otherwise)
     const int slots = std::max(1, c->n_cu * std::max(1, c->tune.wg_per_cu));
     std::vector<int32_t> kf_tile;
-    const int64_t n_tiles_all = plan_tiles(B, cells, tile_cap, slots, kf_tile);
+    int64_t n_tiles_all = 0;
+    {
+        std::vector<int64_t> vp(n_vk);
+        std::vector<int32_t> vk(n_vk);
+        for (int v = 0; v < n_vk; ++v) {
+            const int k = v / n_pass;
+            vp[v] = B->pair_offset[k + 1] - B->pair_offset[k];
+            vk[v] = B->kp_offset[k + 1] - B->kp_offset[k];
+        }
+        n_tiles_all = plan_tiles(vp, vk, cells, tile_cap, slots, kf_tile);
+    }
     int grid = slots;
     if (!graph) grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, n_tiles_all));
     pr.grid = grid;
@@ -413,62 +431,73 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     blob.clear();
     const size_t o_hdr = blob_take<BatchHdr>(blob, 1);
     const size_t o_range = blob_take<int4>(blob, grid);
-    const size_t o_kf = blob_take<KfDesc>(blob, n_kf);
+    const size_t o_kf = blob_take<KfDesc>(blob, n_vk);
     if (o_hdr != 0 || o_range != blob_range_offset() || o_kf != blob_kf_offset(grid))
         return fail(FL_EINVAL, "internal: table layout mismatch");
     const size_t o_ev = blob_take<EventDesc>(blob, n_ev);
-    const size_t o_order = blob_take<int32_t>(blob, n_kf);
-    const size_t o_prefix = blob_take<int32_t>(blob, n_kf + 1);
+    const size_t o_order = blob_take<int32_t>(blob, n_vk);
+    const size_t o_prefix = blob_take<int32_t>(blob, n_vk + 1);
     KfDesc* kfd = (KfDesc*)(blob.data() + o_kf);
     EventDesc* evd = (EventDesc*)(blob.data() + o_ev);
 
     // keyframes, events, list regions, tiles
     int64_t hash_total = 0, add_total = 0, list_total = 0;
     std::vector<double> tile_cost;    // cost of each keyframe's tiles (per tile)
-    tile_cost.resize(n_kf);
+    tile_cost.resize(n_vk);
     for (int e = 0; e < n_ev; ++e) {
         EventDesc& ed = evd[e];
-        ed.kf_begin = B->event_kf_offset[e];
-        ed.kf_end = B->event_kf_offset[e + 1];
+        const int kb = B->event_kf_offset[e], ke = B->event_kf_offset[e + 1];
+        ed.kf_begin = kb * n_pass;   // descriptor range
+        ed.kf_end = ke * n_pass;
         ed.mp_off = B->event_mp_offset[e];
         ed.n_mp = B->event_mp_offset[e + 1] - ed.mp_off;
-        ed.pair_begin = B->pair_offset[ed.kf_begin];
-        ed.pair_end = B->pair_offset[ed.kf_end];
-        const int64_t kp_ev = B->kp_offset[ed.kf_end] - B->kp_offset[ed.kf_begin];
+        ed.pair_begin = B->pair_offset[kb];
+        ed.pair_end = B->pair_offset[ke];
+        const int64_t kp_ev = B->kp_offset[ke] - B->kp_offset[kb];
         int64_t cap = std::min<int64_t>(ed.pair_end - ed.pair_begin, std::max<int64_t>(2 * kp_ev, 4096));
         if (c->add_cap_override > 0) cap = std::min<int64_t>(cap, c->add_cap_override);
         ed.list_off = refine ? (int32_t)list_total : 0;
         ed.list_cap = refine ? (int32_t)cap : 0;
         if (refine) list_total += cap;
-        for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
-            KfDesc& kd = kfd[k];
-            fill_kf_geometry(kd, B->kf_sim3[k], B->kf_K[k], P);
-            if (B->kf_T)
-                for (int i = 0; i < 12; ++i) kd.T[i] = B->kf_T[12 * (int64_t)k + i];
-            kd.kp_off = B->kp_offset[k];
-            kd.n_kp = B->kp_offset[k + 1] - B->kp_offset[k];
-            kd.grid_off = k * (cells + 1);
-            kd.event = e;
-            kd.mp_off = ed.mp_off;
-            kd.n_mp = ed.n_mp;
-            const int hsize = next_pow2(2 * kd.n_kp);
-            kd.hash_off = (int32_t)hash_total;
-            kd.hash_mask = hsize - 1;
+        for (int k = kb; k < ke; ++k) {
+            // the keyframe's global grid and owner hash set serve every pass
+            const int n_kp = B->kp_offset[k + 1] - B->kp_offset[k];
+            const int hsize = next_pow2(2 * n_kp);
+            const int32_t hash_off = (int32_t)hash_total;
             hash_total += hsize;
-            kd.pair_off = B->pair_offset[k];
-            kd.n_pairs = B->pair_offset[k + 1] - B->pair_offset[k];
-            kd.tile_pairs = kf_tile[k];
-            kd.n_tiles = (int32_t)((kd.n_pairs + kd.tile_pairs - 1) / kd.tile_pairs);
-            // room for every pair: no provisional ADD can overflow the list, so
-            // the kernel resolves them without cache write-backs (the test
-            // hook's smaller caps exercise the overflow protocol)
-            int64_t acap = kd.n_pairs;
-            if (c->add_cap_override > 0) acap = std::min<int64_t>(acap, c->add_cap_override);
-            kd.add_off = (int32_t)add_total;
-            kd.add_cap = (int32_t)acap;
-            add_total += acap;
-            // a pair costs more where keypoints are dense (more candidates scanned)
-            tile_cost[k] = (double)kd.tile_pairs * (1.0 + 2.0 * kd.n_kp / std::max(1, cells));
+            for (int p = 0; p < n_pass; ++p) {
+                const int v = k * n_pass + p;
+                KfDesc& kd = kfd[v];
+                const fl_sim3& S = (passes && passes[p].kf_sim3) ? passes[p].kf_sim3[k] : B->kf_sim3[k];
+                fill_kf_geometry(kd, S, B->kf_K[k], P);
+                if (B->kf_T)
+                    for (int i = 0; i < 12; ++i) kd.T[i] = B->kf_T[12 * (int64_t)k + i];
+                kd.kp_off = B->kp_offset[k];
+                kd.n_kp = n_kp;
+                kd.grid_off = k * (cells + 1);
+                kd.event = e;
+                kd.mp_off = ed.mp_off;
+                kd.n_mp = ed.n_mp;
+                kd.hash_off = hash_off;
+                kd.hash_mask = hsize - 1;
+                kd.pair_off = B->pair_offset[k];
+                kd.n_pairs = B->pair_offset[k + 1] - B->pair_offset[k];
+                kd.tile_pairs = kf_tile[v];
+                kd.n_tiles = (int32_t)((kd.n_pairs + kd.tile_pairs - 1) / kd.tile_pairs);
+                // room for every pair: no provisional ADD can overflow the list, so
+                // the kernel resolves them without cache write-backs (the test
+                // hook's smaller caps exercise the overflow protocol)
+                int64_t acap = kd.n_pairs;
+                if (c->add_cap_override > 0) acap = std::min<int64_t>(acap, c->add_cap_override);
+                kd.add_off = (int32_t)add_total;
+                kd.add_cap = (int32_t)acap;
+                add_total += acap;
+                kd.pass = p;
+                kd.stage_key = k;
+                kd.claim_off = p * B->n_kp_total + kd.kp_off;
+                // a pair costs more where keypoints are dense (more candidates scanned)
+                tile_cost[v] = (double)kd.tile_pairs * (1.0 + 2.0 * kd.n_kp / std::max(1, cells));
+            }
         }
     }
     if (add_total > INT32_MAX || list_total > INT32_MAX || hash_total > INT32_MAX)
@@ -477,30 +506,30 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     int32_t* order = (int32_t*)(blob.data() + o_order);
     int32_t* prefix = (int32_t*)(blob.data() + o_prefix);
     int64_t n_tiles = 0;
-    for (int k = 0; k < n_kf; ++k) {
+    for (int k = 0; k < n_vk; ++k) {
         order[k] = k;
         prefix[k] = (int32_t)n_tiles;
         n_tiles += kfd[k].n_tiles;
         if (n_tiles > INT32_MAX / 2) return fail(FL_ERANGE, "too many tiles");
     }
-    prefix[n_kf] = (int32_t)n_tiles;
+    prefix[n_vk] = (int32_t)n_tiles;
     if (n_tiles != n_tiles_all) return fail(FL_EINVAL, "internal: tile count mismatch");
     // the workgroups' contiguous, cost-balanced tile ranges
     int4* wr = (int4*)(blob.data() + o_range);
     {
         // cumulative cost at each tile boundary, by keyframe
-        std::vector<double> kcum(n_kf + 1, 0.0);
-        for (int k = 0; k < n_kf; ++k) kcum[k + 1] = kcum[k] + tile_cost[k] * kfd[k].n_tiles;
+        std::vector<double> kcum(n_vk + 1, 0.0);
+        for (int k = 0; k < n_vk; ++k) kcum[k + 1] = kcum[k] + tile_cost[k] * kfd[k].n_tiles;
         auto tile_at_cost = [&](double target) -> int64_t {   // first tile whose end cost >= target
             if (target <= 0.0) return 0;
             int k = (int)(std::upper_bound(kcum.begin(), kcum.end(), target) - kcum.begin()) - 1;
-            k = std::min(std::max(k, 0), n_kf - 1);
+            k = std::min(std::max(k, 0), n_vk - 1);
             const double per = tile_cost[k] > 0 ? tile_cost[k] : 1.0;
             int64_t j = (int64_t)std::ceil((target - kcum[k]) / per);
             j = std::min<int64_t>(std::max<int64_t>(j, 0), kfd[k].n_tiles);
             return prefix[k] + j;
         };
-        const double total = kcum[n_kf];
+        const double total = kcum[n_vk];
         // The tiles are laid out over ge = min(grid, tiles) workgroups, as an
         // eager launch has them; a graph's further workgroups (its grid is
         // fixed) get empty ranges and exit at once.
@@ -530,8 +559,8 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         for (int i = 0; i < ge; ++i) {
             // slot of the first tile: prefix[slot] <= tile < prefix[slot + 1]
             const int64_t t0 = bound[i];
-            int slot = (int)(std::upper_bound(prefix, prefix + n_kf + 1, (int32_t)t0) - prefix) - 1;
-            slot = std::min(std::max(slot, 0), std::max(n_kf - 1, 0));
+            int slot = (int)(std::upper_bound(prefix, prefix + n_vk + 1, (int32_t)t0) - prefix) - 1;
+            slot = std::min(std::max(slot, 0), std::max(n_vk - 1, 0));
             wr[wg_of[i]] = make_int4((int)t0, (int)bound[i + 1], slot, order[slot]);
         }
         for (int i = ge; i < grid; ++i) wr[i] = make_int4((int)n_tiles, (int)n_tiles, 0, order[0]);
@@ -567,10 +596,10 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const void* old_part = c->part.p;
     rc = c->part.ensure(sizeof(unsigned long long) * kRefWords * n_rows, 0x00);
     if (rc) return rc;
-    rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(B->n_kp_total, 1), 0xFF);
+    rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(n_pass * B->n_kp_total, 1), 0xFF);
     if (rc) return rc;
     const void* old_ctrs = c->ctrs.p;
-    rc = c->ctrs.ensure(64 + sizeof(uint32_t) * ((size_t)kKfCtrs * n_kf + (size_t)kEvCtrs * n_ev), 0x00);
+    rc = c->ctrs.ensure(64 + sizeof(uint32_t) * ((size_t)kKfCtrs * n_vk + (size_t)kEvCtrs * n_ev), 0x00);
     if (rc) return rc;
     if (c->ctrs.p != old_ctrs && old_ctrs != nullptr) {
         // a fresh counter block restarts the epoch: every stored claim must be reset too
@@ -585,7 +614,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     BatchHdr& h = *(BatchHdr*)(blob.data() + o_hdr);
     pr.hdr = &h;
     h.n_events = n_ev;
-    h.n_kf = n_kf;
+    h.n_kf = n_vk;
     h.n_mp = B->n_mp;
     h.n_kp_total = B->n_kp_total;
     h.n_pairs = B->n_pairs;
@@ -595,9 +624,20 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.grid_cols = P->grid_cols;
     h.grid_rows = P->grid_rows;
     h.n_octaves = P->n_octaves;
-    h.hamming_th = P->hamming_th;
-    h.nn_ratio = P->nn_ratio;
-    h.r0 = P->win_px;
+    h.n_pass = n_pass;
+    for (int p = 0; p < n_pass; ++p) {
+        const fl_params& Pp = passes ? passes[p].params : *P;
+        const fl_fuse_out& op = passes ? passes[p].out : *out;
+        PassOut& po = h.out[p];
+        po.best_idx = op.best_idx;
+        po.best_dist = op.best_dist;
+        po.second_dist = op.second_dist;
+        po.decision = op.decision;
+        po.target = op.target;
+        po.hamming_th = Pp.hamming_th;
+        po.nn_ratio = Pp.nn_ratio;
+        po.r0 = Pp.win_px;
+    }
     h.gate = B->mp_dmax != nullptr;
     h.dense = B->pair_mp == nullptr;
     h.stats = c->stats;
@@ -620,11 +660,6 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.mp_dmax = B->mp_dmax;
     h.mp_id = B->mp_id;
     h.pair_mp = B->pair_mp;
-    h.best_idx = out->best_idx;
-    h.best_dist = out->best_dist;
-    h.second_dist = out->second_dist;
-    h.decision = out->decision;
-    h.target = out->target;
     h.cell_start = (int32_t*)(base + L_cs);
     h.recs = (KpRec*)(base + L_recs);
     h.desc_sorted = (uint4*)(base + L_desc);
@@ -634,7 +669,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.stats_out = (unsigned long long*)cb;
     h.epoch = (const uint32_t*)(cb + 32);
     h.kf_ctr = (uint32_t*)(cb + 64);
-    h.ev_ctr = (uint32_t*)(cb + 64 + sizeof(uint32_t) * (size_t)kKfCtrs * n_kf);
+    h.ev_ctr = (uint32_t*)(cb + 64 + sizeof(uint32_t) * (size_t)kKfCtrs * n_vk);
     h.add_list = (AddRef*)(base + L_add);
     h.match_list = (MatchRec*)(base + L_match);
     h.refine_blocks = refine_blocks;
@@ -988,6 +1023,35 @@ int fl_search_fuse_batched(fl_ctx* c, const fl_batch* B, const fl_params* P, con
     rc = launch_search(c, pr, dh, stream, true, c->stats != 0);
     if (rc) return rc;
     return launch_refine(c, dh, pr.refine_iters, stream, true);
+}
+
+int fl_search_fuse_passes(fl_ctx* c, const fl_batch* B, int32_t n_pass, const fl_pass* passes, hipStream_t stream) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if (!passes) return fail(FL_EINVAL, "passes is NULL");
+    if (n_pass < 1 || n_pass > FL_MAX_PASSES) return fail(FL_EINVAL, "n_pass %d outside [1, %d]", n_pass, FL_MAX_PASSES);
+    const fl_params* P = &passes[0].params;
+    for (int p = 0; p < n_pass; ++p) {
+        const int rc = validate_batch(B, &passes[p].params, &passes[p].out);
+        if (rc) return rc;
+        const fl_params& Q = passes[p].params;
+        if (Q.scale_factor != P->scale_factor || Q.n_octaves != P->n_octaves || Q.grid_cols != P->grid_cols ||
+            Q.grid_rows != P->grid_rows)
+            return fail(FL_EINVAL, "pass %d: scale_factor, n_octaves and the grid must equal those of pass 0", p);
+        for (int q = 0; q < p && B->n_pairs > 0; ++q) {
+            const fl_fuse_out &a = passes[p].out, &b = passes[q].out;
+            if (a.best_idx == b.best_idx || a.best_dist == b.best_dist || a.second_dist == b.second_dist ||
+                a.decision == b.decision || a.target == b.target)
+                return fail(FL_EINVAL, "passes %d and %d share an output array", q, p);
+        }
+    }
+    if (B->n_pairs == 0) return FL_OK;
+    Prepared pr;
+    int rc = prepare_batch(c, B, P, &passes[0].out, nullptr, false, pr, false, n_pass, passes);
+    if (rc) return rc;
+    rc = upload_batch(c, pr, stream);
+    if (rc) return rc;
+    if (c->stats) FL_HIP(hipMemsetAsync(c->ctrs.p, 0, 32, stream));
+    return launch_search(c, pr, (const BatchHdr*)c->ws.p, stream, true, c->stats != 0);
 }
 
 int fl_refine_events(fl_ctx* c, const fl_batch* B, const fl_fuse_out* out, const fl_refine* R, hipStream_t stream) {

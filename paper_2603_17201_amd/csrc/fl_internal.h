@@ -38,6 +38,25 @@ struct alignas(16) KfDesc {
     int32_t tile_pairs;  // pairs per tile of this keyframe (a whole number of waves)
     int64_t pair_off;
     int64_t n_pairs;
+    // A launch may search its batch several times (passes); each (keyframe,
+    // pass) has a descriptor of its own, keyframe-major.
+    int32_t pass;        // thresholds and outputs: BatchHdr::out[pass]
+    int32_t stage_key;   // the keyframe in the batch (its grid is the same in every pass)
+    int32_t claim_off;   // first ADD claim slot: pass * n_kp_total + kp_off
+    int32_t pad1;
+};
+
+// One search pass of a launch: its thresholds and its outputs (caller-owned).
+struct PassOut {
+    int32_t* best_idx;
+    int16_t* best_dist;
+    int16_t* second_dist;
+    uint8_t* decision;
+    int32_t* target;
+    int32_t hamming_th;
+    float nn_ratio;
+    float r0;            // window half-width at octave 0, pixels
+    int32_t pad;
 };
 
 struct alignas(16) EventDesc {
@@ -57,7 +76,7 @@ __host__ __device__ constexpr size_t blob_align(size_t x) { return (x + kBlobAli
 
 struct alignas(16) AddRef {
     int32_t pair;     // global pair index
-    int32_t kp;       // global keypoint index
+    int32_t kp;       // claim slot of the keypoint (KfDesc::claim_off + index)
     int32_t gp;       // global point index
     int32_t pad;
 };
@@ -94,9 +113,7 @@ struct alignas(16) BatchHdr {
     int64_t n_pairs;
     int32_t n_tiles, tile_cap;   // tiles of the batch; the largest tile (workgroup size x pairs per lane)
     int32_t cells, grid_cols, grid_rows, n_octaves;
-    int32_t hamming_th;
-    float nn_ratio;
-    float r0;
+    int32_t n_pass;             // search passes of the launch (1 .. FL_MAX_PASSES)
     int32_t gate;               // 1: point distance invariance given (octave gate on)
     int32_t dense;
     int32_t stats;              // 1: count visible / cells / keypoints / candidates
@@ -126,19 +143,15 @@ struct alignas(16) BatchHdr {
     const float* mp_dmax;
     const int32_t* mp_id;
     const int32_t* pair_mp;
-    // outputs (caller-owned)
-    int32_t* best_idx;
-    int16_t* best_dist;
-    int16_t* second_dist;
-    uint8_t* decision;
-    int32_t* target;
+    // thresholds and outputs of each pass
+    PassOut out[FL_MAX_PASSES];
     // workspace (library-owned)
     int32_t* cell_start;        // global-grid mode: [n_kf * (cells + 1)]
     KpRec* recs;                // global-grid mode: [n_kp_total]
     uint4* desc_sorted;         // global-grid mode: [n_kp_total * 2]
     int32_t* cell_kp;           // global-grid mode: [n_kp_total]
     int32_t* hash;              // global-grid mode: owner hash tables
-    unsigned long long* claim;  // [n_kp_total] (epoch << 32 | lowest claiming point)
+    unsigned long long* claim;  // [n_pass * n_kp_total] (epoch << 32 | lowest claiming point)
     const uint32_t* epoch;      // tag of this launch's claims, decremented by the table fetch
     uint32_t* kf_ctr;           // [n_kf * kKfCtrs]
     uint32_t* ev_ctr;           // [n_events * kEvCtrs]
@@ -278,6 +291,7 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 // reset at the end.
 __device__ inline void resolve_keyframe_adds(const BatchHdr& h, int k, unsigned long long tag) {
     const KfDesc& kd = h.kf[k];
+    const PassOut& po = h.out[kd.pass];
     const int tid = threadIdx.x, nt = blockDim.x;
     const uint32_t n_add = h.kf_ctr[k * kKfCtrs + kKfAdd];
     if (n_add <= (uint32_t)kd.add_cap) {
@@ -285,19 +299,19 @@ __device__ inline void resolve_keyframe_adds(const BatchHdr& h, int k, unsigned 
             const AddRef e = h.add_list[kd.add_off + i];
             const int32_t w = (int32_t)(h.claim[e.kp] - tag);
             if (w != e.gp) {
-                h.decision[e.pair] = FL_FUSE;
-                h.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
+                po.decision[e.pair] = FL_FUSE;
+                po.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
             }
         }
     } else {
         for (int64_t j = tid; j < kd.n_pairs; j += nt) {
             const int64_t o = kd.pair_off + j;
-            if (h.decision[o] != FL_ADD) continue;
+            if (po.decision[o] != FL_ADD) continue;
             const int32_t gp = kd.mp_off + (h.dense ? (int32_t)j : h.pair_mp[o]);
-            const int32_t w = (int32_t)(h.claim[kd.kp_off + h.best_idx[o]] - tag);
+            const int32_t w = (int32_t)(h.claim[kd.claim_off + po.best_idx[o]] - tag);
             if (w != gp) {
-                h.decision[o] = FL_FUSE;
-                h.target[o] = h.mp_id ? h.mp_id[w] : w;
+                po.decision[o] = FL_FUSE;
+                po.target[o] = h.mp_id ? h.mp_id[w] : w;
             }
         }
     }

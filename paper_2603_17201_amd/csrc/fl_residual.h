@@ -727,10 +727,10 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                     const KfDesc& kd = h.kf[k];
                     for (int64_t j = b * blockDim.x + tid; j < kd.n_pairs; j += stride) {
                         const int64_t o = kd.pair_off + j;
-                        const uint8_t dec = h.decision[o];
+                        const uint8_t dec = h.out[0].decision[o];
                         if (dec != FL_ADD && dec != FL_FUSE) continue;
                         const int32_t lp = h.dense ? (int32_t)j : h.pair_mp[o];
-                        const int32_t bi = h.best_idx[o];
+                        const int32_t bi = h.out[0].best_idx[o];
                         if (lp < 0 || lp >= kd.n_mp || bi < 0 || bi >= kd.n_kp) continue;
                         const int64_t gp = kd.mp_off + lp, kp = kd.kp_off + bi;
                         refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1],

@@ -270,6 +270,7 @@ __global__ __launch_bounds__(kPrepBlock) void prep_global_kernel(const BatchHdr*
     const BatchHdr& h = *hp;
     for (int k = blockIdx.x; k < h.n_kf; k += gridDim.x) {
         const KfDesc& kd = h.kf[k];
+        if (kd.pass != 0) continue;   // the other passes of a keyframe share its grid
         int32_t* cs = h.cell_start + kd.grid_off;
         int32_t* ck = h.cell_kp + kd.kp_off;
         build_grid_global(kd, h.cells, h.grid_cols, h.grid_rows, h.kp_xy, cs, ck, s_cnt, s_tmp);
@@ -406,8 +407,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     if (tid < FL_MAX_OCTAVES) s_sf[tid] = h.sf[tid];
     if (MODE == kModeGlobal) __syncthreads();
     const float* sf = s_sf;
-    const int N = h.n_octaves, gate = h.gate, C = h.grid_cols, R = h.grid_rows, th = h.hamming_th;
-    const float ratio = h.nn_ratio, r0w = h.r0;
+    const int N = h.n_octaves, gate = h.gate, C = h.grid_cols, R = h.grid_rows;
     const bool dense = h.dense != 0;
     const bool want_matches = h.refine_iters > 0;
     const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
@@ -426,6 +426,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         const int k = t == range.x ? range.w : h.kf_order[slot];
         const KfDesc kd = kf_tab[k];          // by value: kept in registers across the stores below
         const EventDesc ed = h.ev[kd.event];
+        const PassOut& po = h.out[kd.pass];
         const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * kd.tile_pairs;
         const int64_t pe = min(pb + (int64_t)kd.tile_pairs, kd.pair_off + kd.n_pairs);
         // A provisional ADD is written as ADD here; the ADD conflicts are
@@ -477,10 +478,10 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             v.hash = h.hash + kd.hash_off;
             v.hash_mask = kd.hash_mask;
         } else {
-            if (staged != k) {
+            if (staged != kd.stage_key) {
                 __syncthreads();   // every reader of the previous keyframe is done
                 stage_keyframe<MODE == kModeLdsDesc>(h, kd, s_cs, s_rec, s_desc, s_own, s_hash, s_tmp);
-                staged = k;
+                staged = kd.stage_key;
             }
             v.cs = s_cs;
             v.rec = s_rec;
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                     dec[r] = FL_NOT_VISIBLE;
                 } else {
                     if (STATS) ++st_vis;
-                    const Window w = make_window(p, kd, sf, r0w, C, R);
+                    const Window w = make_window(p, kd, sf, po.r0, C, R);
                     for (int row = w.r0; row <= w.r1; ++row) {
                         const int s = v.cs[row * C + w.c0];
                         const int e = v.cs[row * C + w.c1 + 1];
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                             }
                         }
                     }
-                    if (!accept_match(best, th, ratio)) {
+                    if (!accept_match(best, po.hamming_th, po.nn_ratio)) {
                         dec[r] = FL_NO_MATCH;
                     } else {
                         const int32_t ow = v.own ? v.own[bslot]
@@ -562,14 +563,14 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 }
             }
             const int bidx = best.key == 0xFFFFFFFFu ? -1 : (int)(best.key & 0xFFFFu);
-            const int kpg = kd.kp_off + (bidx < 0 ? 0 : bidx);
+            const int kpg = kd.claim_off + (bidx < 0 ? 0 : bidx);   // claim slot
             const bool is_add = active && dec[r] == FL_ADD;
             if (active) {
-                h.best_idx[o] = bidx;
-                h.best_dist[o] = (int16_t)(best.key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(best.key >> 16));
-                h.second_dist[o] = (int16_t)best.second;
-                h.decision[o] = dec[r];
-                h.target[o] = target;
+                po.best_idx[o] = bidx;
+                po.best_dist[o] = (int16_t)(best.key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(best.key >> 16));
+                po.second_dist[o] = (int16_t)best.second;
+                po.decision[o] = dec[r];
+                po.target[o] = target;
             }
             if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp[r]);
             // list entries are written after the tile with one atomic per list

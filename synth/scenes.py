@@ -66,6 +66,32 @@ def verification_params() -> LoopParams:
     return LoopParams(win_px=10.0, nn_ratio=0.75)
 
 
+def search_transforms(ev, S) -> np.ndarray:
+    """The float32 search transforms T_k o S of every keyframe of `ev` for a
+    float64 Sim3 S, in the form of Event.kf_sim3."""
+    T = np.asarray(ev.kf_T, np.float64).reshape(-1, 12)
+    return np.stack([_sim3_f32(_compose_T_S(r[:9].reshape(3, 3), r[9:], S)) for r in T])
+
+
+def perturbed(S, deg: float, metres: float, dscale: float, seed: int) -> np.ndarray:
+    """A float64 Sim3 near S (rotated by `deg`, shifted by `metres`, scaled
+    by 1 + dscale, in seeded random directions)."""
+    return _perturb(np.random.Generator(np.random.PCG64(seed)), np.asarray(S, np.float64), deg, metres, dscale)
+
+
+def ps2_passes(ev, seed: int = 5):
+    """The two projection searches on the current keyframe around the Sim3
+    optimisation, as (params, kf_sim3) pairs: one at the event's starting
+    Sim3 with the verification thresholds (10 px x 1.2^octave, ratio 0.75),
+    one at a Sim3 moved by 0.05 deg, 5 mm and 0.1% scale (a refined estimate)
+    with a 5 px window and ratio 0.9.  The paper gives no constants for these
+    searches; these are a reading."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S_b = _perturb(rng, np.asarray(ev.S_init, np.float64), 0.05, 0.005, 0.001)
+    return [(verification_params(), np.asarray(ev.kf_sim3, np.float32)),
+            (LoopParams(win_px=5.0, nn_ratio=0.9), search_transforms(ev, S_b))]
+
+
 @dataclass
 class Event:
     """One loop event.  Keyframe-major arrays are concatenated over keyframes."""

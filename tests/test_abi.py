@@ -44,6 +44,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.Params) == 32
     assert ctypes.sizeof(_abi.FuseOut) == 40
     assert ctypes.sizeof(_abi.Refine) == 32
+    assert ctypes.sizeof(_abi.Pass) == 80
 
 
 def _batch(n_kf=2, n_mp=10, n_kp=(5, 7), dense=True):
@@ -131,6 +132,10 @@ def test_null_context_is_rejected(lib):
     assert rc == _abi.FL_EINVAL
     r = ctypes.c_double()
     rc = lib.fl_valu_rate(None, 100, ctypes.byref(r), None)
+    assert rc == _abi.FL_EINVAL
+    b, P, o, _tables = _batch()
+    passes = (_abi.Pass * 2)(_abi.Pass(None, P, o), _abi.Pass(None, P, o))
+    rc = lib.fl_search_fuse_passes(None, ctypes.byref(b), 2, passes, None)
     assert rc == _abi.FL_EINVAL
 
 
