@@ -128,3 +128,79 @@ def gauss_newton(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=10):
         dxi = np.linalg.solve(H, -g)
         S = sim3.compose(sim3.exp(dxi), S)
     return S
+
+
+def _marquardt_solve(g, H, lam):
+    """Solve (H + lam diag H) dxi = -g."""
+    return np.linalg.solve(H + lam * np.diag(np.diag(H)), -g)
+
+
+def refine_robust(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=5, rounds=2, outlier_px=np.inf, lm_lambda=0.0,
+                  history=None):
+    """Robust refinement of the loop Sim3 in rounds (the Sim(3) optimisation
+    around the projection searches of Sec. IV-C; the paper gives no
+    algorithm, so the steps below are readings).
+
+    Round 0 uses every pair.  Each later round uses the pairs that lie in
+    front of their keyframe with reprojection error e <= outlier_px at the
+    Sim3 the previous round ended with (the set is chosen afresh each round).
+    A round is `iters` evaluations of g, H and the Huber loss L on its pairs:
+      * lm_lambda == 0: undamped Gauss-Newton, S <- exp(dxi) S after every
+        evaluation, dxi = -H^-1 g;
+      * lm_lambda > 0: Levenberg-Marquardt with Marquardt's scaling.  The
+        first evaluation of a round is at the round's starting Sim3; each
+        later one is at the candidate exp(dxi) S_acc, dxi solving
+        (H + lambda diag H) dxi = -g with g, H of S_acc.  A candidate with
+        L below L(S_acc) is accepted (S_acc moves there, lambda / 10), else
+        rejected (lambda * 10), lambda kept in [1e-12, 1e16] and reset to
+        lm_lambda at each round.  The round ends at S_acc; the candidate
+        solved after the last evaluation is not taken.
+    Returns (S, n_used): n_used counts the round's pairs in front of their
+    keyframe at the last evaluation that produced the result (GN: the last
+    evaluation; LM: the evaluation of the final S_acc).
+    `history`, if a list, receives (round, L, accepted) per evaluation.
+    """
+    S = np.asarray(S0, np.float64).copy()
+    X = np.asarray(xyz, np.float64)
+    U = np.asarray(uv, np.float64)
+    kf_idx = None if kf_idx is None else np.asarray(kf_idx)
+    n_used = 0
+    for rnd in range(rounds):
+        if rnd == 0:
+            sel = np.ones(len(X), bool)
+        else:
+            _, q, uvp, _ = project(S, X, kf_idx, kf_T, cam)
+            with np.errstate(invalid="ignore"):
+                e = np.linalg.norm(uvp - U, axis=1)
+                sel = (q[:, 2] > 0) & (e <= outlier_px)
+        Xs, Us = X[sel], U[sel]
+        ks = None if kf_idx is None else kf_idx[sel]
+
+        def evaluate(S_at):
+            g, H, L = grad_hess(S_at, Xs, Us, ks, kf_T, cam, delta)
+            _, q, _, _ = project(S_at, Xs, ks, kf_T, cam)
+            return g, H, L, int((q[:, 2] > 0).sum())
+
+        if lm_lambda <= 0.0:
+            for _ in range(iters):
+                g, H, L, n_used = evaluate(S)
+                if history is not None:
+                    history.append((rnd, L, True))
+                S = sim3.compose(sim3.exp(np.linalg.solve(H, -g)), S)
+        else:
+            lam = float(lm_lambda)
+            g, H, L, n_used = evaluate(S)
+            if history is not None:
+                history.append((rnd, L, True))
+            for _ in range(1, iters):
+                S_c = sim3.compose(sim3.exp(_marquardt_solve(g, H, lam)), S)
+                g_c, H_c, L_c, n_c = evaluate(S_c)
+                ok = L_c < L
+                if history is not None:
+                    history.append((rnd, L_c, ok))
+                if ok:
+                    S, g, H, L, n_used = S_c, g_c, H_c, L_c, n_c
+                    lam = max(lam / 10.0, 1e-12)
+                else:
+                    lam = min(lam * 10.0, 1e16)
+    return S, n_used

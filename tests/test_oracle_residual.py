@@ -108,3 +108,75 @@ def test_behind_camera_pairs_contribute_nothing(c4):
     behind = q[:, 2] <= 0
     assert behind.sum() >= 10
     assert np.all(w[behind] == 0) and np.all(r[behind] == 0)
+
+
+def _views_with_outliers(n, seed, sigma):
+    """Observations of C4's points from 6 keyframes, pixel noise `sigma`, and
+    10% of them moved 20 px in a random direction (the planted outliers)."""
+    rng = np.random.default_rng(seed)
+    d = synth.gen_c4(n=n, seed=seed, pix_sigma=0.0, outlier_frac=0.0)
+    T = np.array([sim3.exp(np.concatenate([rng.normal(size=3) * 0.1, rng.normal(size=3) * 0.5, [0.0]]))[:12]
+                  for _ in range(6)])
+    kf = rng.integers(0, 6, n)
+    _, q, uv, _ = residual.project(d["S_true"], d["xyz"], kf, T, d["cam"])
+    uv = uv + rng.normal(0, sigma, uv.shape) if sigma > 0 else uv
+    out = rng.random(n) < 0.1
+    th = rng.uniform(0, 2 * np.pi, n)
+    uv[out] += 20 * np.stack([np.cos(th[out]), np.sin(th[out])], 1)
+    keep = q[:, 2] > 0.1
+    return d, d["xyz"][keep], uv[keep], kf[keep], T, out[keep]
+
+
+def _err(S, S_ref):
+    return np.linalg.norm(sim3.log(sim3.compose(S, sim3.inverse(S_ref))))
+
+
+@pytest.mark.parametrize("lm", [0.0, 1e-3])
+def test_robust_rounds_recover_exact_sim3_despite_outliers(lm):
+    """Noise-free inliers and 10% gross outliers: the second round drops
+    exactly the outliers and converges to the planted Sim3, which the Huber
+    weights alone (one round) do not."""
+    d, xyz, uv, kf, T, out = _views_with_outliers(6000, 41, 0.0)
+    S0 = _S0(d)
+    S1, _ = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=10, rounds=1, lm_lambda=lm)
+    S2, n2 = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=10, rounds=2, outlier_px=3.035,
+                                    lm_lambda=lm)
+    assert _err(S2, d["S_true"]) < 1e-9
+    assert _err(S1, d["S_true"]) > 1e-6
+    assert n2 == int((~out).sum())
+
+
+def test_robust_round_zero_is_gauss_newton():
+    d, xyz, uv, kf, T, _ = _views_with_outliers(4000, 43, 1.0)
+    S0 = _S0(d)
+    S, n = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=7, rounds=1)
+    assert np.array_equal(S, residual.gauss_newton(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=7))
+    assert n == len(xyz)
+
+
+def test_lm_with_vanishing_damping_is_gauss_newton_one_step_behind():
+    """With lambda -> 0 every step is accepted and is the Gauss-Newton step:
+    k + 1 evaluations give k Gauss-Newton updates."""
+    d, xyz, uv, kf, T, _ = _views_with_outliers(4000, 45, 1.0)
+    S0 = _S0(d)
+    h = []
+    S, _ = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=5, rounds=1, lm_lambda=1e-14,
+                                  history=h)
+    assert all(a for _, _, a in h[:4])
+    assert _err(S, residual.gauss_newton(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=4)) < 1e-10
+
+
+def test_lm_accepted_loss_decreases_and_rejections_do_not_move():
+    d, xyz, uv, kf, T, _ = _views_with_outliers(6000, 47, 1.0)
+    S0 = _S0(d)
+    h = []
+    S, _ = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=8, rounds=2, outlier_px=3.035,
+                                  lm_lambda=1e-3, history=h)
+    for rnd in (0, 1):
+        acc = [L for r, L, a in h if r == rnd and a]
+        assert all(b < a for a, b in zip(acc, acc[1:])), acc
+        assert all(L >= min(acc) for r, L, a in h if r == rnd and not a)
+    assert h[0][1] > 10 * h[-1][1]
+    # a huge damping barely moves: each step is a tiny gradient step
+    S_big, _ = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=3, rounds=1, lm_lambda=1e12)
+    assert _err(S_big, S0) < 1e-8
