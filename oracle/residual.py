@@ -135,6 +135,9 @@ def _marquardt_solve(g, H, lam):
     return np.linalg.solve(H + lam * np.diag(np.diag(H)), -g)
 
 
+LM_CONVERGED = 1e-6   # relative loss change that ends a Levenberg-Marquardt round
+
+
 def refine_robust(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=5, rounds=2, outlier_px=np.inf, lm_lambda=0.0,
                   history=None):
     """Robust refinement of the loop Sim3 in rounds (the Sim(3) optimisation
@@ -150,15 +153,19 @@ def refine_robust(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=5, rounds=2, outl
       * lm_lambda > 0: Levenberg-Marquardt with Marquardt's scaling.  The
         first evaluation of a round is at the round's starting Sim3; each
         later one is at the candidate exp(dxi) S_acc, dxi solving
-        (H + lambda diag H) dxi = -g with g, H of S_acc.  A candidate with
-        L below L(S_acc) is accepted (S_acc moves there, lambda / 10), else
-        rejected (lambda * 10), lambda kept in [1e-12, 1e16] and reset to
-        lm_lambda at each round.  The round ends at S_acc; the candidate
-        solved after the last evaluation is not taken.
+        (H + lambda diag H) dxi = -g with g, H of S_acc.  With
+        rho = (L(S_acc) - L_c) / L(S_acc): rho > 1e-6 accepts the candidate
+        (S_acc moves there, lambda / 10); |rho| <= 1e-6 ends the round
+        (converged: the loss no longer changes beyond what its rounding can
+        decide); rho < -1e-6 rejects it (lambda * 10).  lambda is kept in
+        [1e-12, 1e16] and reset to lm_lambda at each round.  The round ends
+        at S_acc; a candidate solved after the last evaluation is not taken.
     Returns (S, n_used): n_used counts the round's pairs in front of their
     keyframe at the last evaluation that produced the result (GN: the last
     evaluation; LM: the evaluation of the final S_acc).
-    `history`, if a list, receives (round, L, accepted) per evaluation.
+    `history`, if a list, receives (round, L, status) per evaluation, status
+    "step" (GN), "start" (LM, a round's first), "accept", "reject" or
+    "converged".
     """
     S = np.asarray(S0, np.float64).copy()
     X = np.asarray(xyz, np.float64)
@@ -185,22 +192,25 @@ def refine_robust(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=5, rounds=2, outl
             for _ in range(iters):
                 g, H, L, n_used = evaluate(S)
                 if history is not None:
-                    history.append((rnd, L, True))
+                    history.append((rnd, L, "step"))
                 S = sim3.compose(sim3.exp(np.linalg.solve(H, -g)), S)
         else:
             lam = float(lm_lambda)
             g, H, L, n_used = evaluate(S)
             if history is not None:
-                history.append((rnd, L, True))
+                history.append((rnd, L, "start"))
             for _ in range(1, iters):
                 S_c = sim3.compose(sim3.exp(_marquardt_solve(g, H, lam)), S)
                 g_c, H_c, L_c, n_c = evaluate(S_c)
-                ok = L_c < L
+                rho = (L - L_c) / L if L > 0 else 0.0
+                ok = rho > LM_CONVERGED
                 if history is not None:
-                    history.append((rnd, L_c, ok))
+                    history.append((rnd, L_c, "accept" if ok else "reject" if rho < -LM_CONVERGED else "converged"))
                 if ok:
                     S, g, H, L, n_used = S_c, g_c, H_c, L_c, n_c
                     lam = max(lam / 10.0, 1e-12)
+                elif rho >= -LM_CONVERGED:
+                    break
                 else:
                     lam = min(lam * 10.0, 1e16)
     return S, n_used
