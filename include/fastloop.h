@@ -158,11 +158,24 @@ typedef struct {
  * always do.  A wait that does not end within its bound reports the event as
  * failed (event_n_matched = -1); it never blocks the device. */
 typedef struct {
-    int32_t n_iters;        /* 0 = no refinement */
+    int32_t n_iters;        /* evaluations per round; 0 = no refinement */
     float huber_delta;      /* pixels */
     double* event_S;        /* device [n_events][13] in: start, out: refined (float64 Sim3) */
     fl_sim3* event_S32;     /* device [n_events] out: float32 form of the refined Sim3 (may be NULL) */
-    int32_t* event_n_matched; /* device [n_events] out: pairs used (may be NULL) */
+    int32_t* event_n_matched; /* device [n_events] out: pairs of the result's last evaluation (may be NULL) */
+    /* Robust refinement (all zero: one round of Gauss-Newton).  Round 0 uses
+     * every accepted pair; each later round uses the pairs in front of their
+     * keyframe whose reprojection error at the round's starting Sim3 is at
+     * most outlier_px.  lm_lambda > 0 selects Levenberg-Marquardt: the first
+     * evaluation of a round is at its starting Sim3, each later one at the
+     * candidate exp(d) S_acc with (H + lambda diag H) d = -g at the accepted
+     * S_acc; a candidate with a lower Huber loss is accepted (lambda / 10),
+     * otherwise rejected (lambda x 10); lambda restarts at lm_lambda each
+     * round, and the round ends at S_acc.  n_iters * max(n_rounds, 1) <= 1000. */
+    int32_t n_rounds;       /* 0 or 1: one round */
+    float outlier_px;       /* > 0 when n_rounds > 1 (may be +inf) */
+    float lm_lambda;        /* 0: Gauss-Newton */
+    int32_t flags;          /* must be 0 */
 } fl_refine;
 
 /* ------------------------------------------------------------------ */

@@ -64,7 +64,8 @@ class Pass(ctypes.Structure):
 
 class Refine(ctypes.Structure):
     _fields_ = [("n_iters", c_int32), ("huber_delta", c_float), ("event_S", c_void_p),
-                ("event_S32", c_void_p), ("event_n_matched", c_void_p)]
+                ("event_S32", c_void_p), ("event_n_matched", c_void_p), ("n_rounds", c_int32),
+                ("outlier_px", c_float), ("lm_lambda", c_float), ("flags", c_int32)]
 
 
 class Tuning(ctypes.Structure):

@@ -299,13 +299,17 @@ class Context:
         return outs
 
     def _refine_struct(self, batch, refine):
+        """refine: (n_iters, huber_delta, event_S, event_S32, n_matched) and
+        optionally (n_rounds, outlier_px, lm_lambda) for robust refinement."""
         if refine is None:
             return None, None
-        n_iters, delta, event_S, event_S32, n_matched = refine
+        n_iters, delta, event_S, event_S32, n_matched = refine[:5]
+        n_rounds, outlier_px, lm_lambda = (tuple(refine[5:8]) + (0, 0.0, 0.0)[len(refine[5:8]):])
         r = Refine(int(n_iters), float(delta),
                    _ptr(event_S, torch.float64, "event_S", 8, self.device),
                    _ptr(event_S32, torch.float32, "event_S32", 16, self.device),
-                   _ptr(n_matched, torch.int32, "event_n_matched", device=self.device))
+                   _ptr(n_matched, torch.int32, "event_n_matched", device=self.device),
+                   int(n_rounds), float(outlier_px), float(lm_lambda), 0)
         return r, ctypes.byref(r)
 
     def search_fuse_graph(self, batch: DeviceBatch, params, out: Optional[FuseOutputs] = None, refine=None,

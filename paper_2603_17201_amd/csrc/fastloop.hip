@@ -313,6 +313,7 @@ struct Prepared {
     size_t lds = 16;
     size_t blob_cap = 0;
     int refine_iters = 0;
+    int refine_variant = 0;           // refinement kernel: bit 0 Levenberg-Marquardt, bit 1 rounds
     bool resolve_in_refine = false;   // the refinement launch resolves the ADD conflicts
 };
 
@@ -399,6 +400,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const bool refine = R && R->n_iters > 0;
     pr.ppl = ppl;
     pr.refine_iters = refine ? R->n_iters : 0;
+    pr.refine_variant = refine ? (R->lm_lambda > 0.0f ? 1 : 0) | (R->n_rounds > 1 ? 2 : 0) : 0;
     int kp_cap = 1;
     for (int k = 0; k < n_kf; ++k) kp_cap = std::max(kp_cap, B->kp_offset[k + 1] - B->kp_offset[k]);
     const int lds_hash_cap = std::max(64, next_pow2(kp_cap + 1));
@@ -682,6 +684,9 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     if (refine) {
         h.refine_iters = R->n_iters;
         h.huber_delta = R->huber_delta;
+        h.refine_rounds = std::max(R->n_rounds, 1);
+        h.outlier_px = R->n_rounds > 1 ? R->outlier_px : INFINITY;
+        h.lm_lambda = R->lm_lambda;
         h.event_S = R->event_S;
         h.event_S32_out = R->event_S32;
         h.event_n_matched = R->event_n_matched;
@@ -775,7 +780,7 @@ int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t
     return FL_OK;
 }
 
-int launch_refine(fl_ctx* c, const BatchHdr* dh, int n_iters, hipStream_t s, bool eager) {
+int launch_refine(fl_ctx* c, const BatchHdr* dh, int n_iters, int variant, hipStream_t s, bool eager) {
     if (n_iters <= 0) return FL_OK;
     const bool timed = eager && c->prof;
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -784,7 +789,11 @@ int launch_refine(fl_ctx* c, const BatchHdr* dh, int n_iters, hipStream_t s, boo
         FL_HIP(hipEventCreate(&t1));
         FL_HIP(hipEventRecord(t0, s));
     }
-    hipLaunchKernelGGL(refine_kernel, dim3(kRefineGrid), dim3(kRefBlock), 0, s, dh);
+    // variant: bit 0 Levenberg-Marquardt, bit 1 more than one round
+    if (variant == 0) hipLaunchKernelGGL((refine_kernel<false, false>), dim3(kRefineGrid), dim3(kRefBlock), 0, s, dh);
+    else if (variant == 1) hipLaunchKernelGGL((refine_kernel<true, false>), dim3(kRefineGrid), dim3(kRefBlock), 0, s, dh);
+    else if (variant == 2) hipLaunchKernelGGL((refine_kernel<false, true>), dim3(kRefineGrid), dim3(kRefBlock), 0, s, dh);
+    else hipLaunchKernelGGL((refine_kernel<true, true>), dim3(kRefineGrid), dim3(kRefBlock), 0, s, dh);
     if (timed) {
         FL_HIP(hipEventRecord(t1, s));
         c->prof_ev[FL_PROF_REFINE].emplace_back(t0, t1);
@@ -797,6 +806,12 @@ int check_refine(const fl_batch* B, const fl_refine* R) {
     if (!R || R->n_iters == 0) return FL_OK;
     if (R->n_iters < 0 || R->n_iters > 1000) return fail(FL_ERANGE, "refine.n_iters %d outside [0, 1000]", R->n_iters);
     if (!finite_pos(R->huber_delta)) return fail(FL_EINVAL, "refine.huber_delta must be finite and > 0");
+    if (R->flags != 0) return fail(FL_EINVAL, "refine.flags must be 0");
+    if (R->n_rounds < 0 || (int64_t)R->n_iters * std::max(R->n_rounds, 1) > 1000)
+        return fail(FL_ERANGE, "refine.n_iters * n_rounds must be at most 1000");
+    if (R->n_rounds > 1 && !(R->outlier_px > 0.0f)) return fail(FL_EINVAL, "refine.outlier_px must be > 0");
+    if (!(R->lm_lambda >= 0.0f) || !std::isfinite(R->lm_lambda))
+        return fail(FL_EINVAL, "refine.lm_lambda must be finite and >= 0");
     if (B->n_events > 0 && !R->event_S) return fail(FL_EINVAL, "refine.event_S must not be NULL");
     return FL_OK;
 }
@@ -1022,7 +1037,7 @@ int fl_search_fuse_batched(fl_ctx* c, const fl_batch* B, const fl_params* P, con
     const BatchHdr* dh = (const BatchHdr*)c->ws.p;
     rc = launch_search(c, pr, dh, stream, true, c->stats != 0);
     if (rc) return rc;
-    return launch_refine(c, dh, pr.refine_iters, stream, true);
+    return launch_refine(c, dh, pr.refine_iters, pr.refine_variant, stream, true);
 }
 
 int fl_search_fuse_passes(fl_ctx* c, const fl_batch* B, int32_t n_pass, const fl_pass* passes, hipStream_t stream) {
@@ -1067,7 +1082,7 @@ int fl_refine_events(fl_ctx* c, const fl_batch* B, const fl_fuse_out* out, const
     if (rc) return rc;
     rc = upload_batch(c, pr, stream);
     if (rc) return rc;
-    return launch_refine(c, (const BatchHdr*)c->ws.p, R->n_iters, stream, true);
+    return launch_refine(c, (const BatchHdr*)c->ws.p, R->n_iters, pr.refine_variant, stream, true);
 }
 
 int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fuse_out* out,
@@ -1082,7 +1097,7 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
     rc = prepare_batch(c, B, P, out, R, false, pr, true);
     if (rc) return rc;
     pr.hdr->stats = 0;   // counters are an eager-path feature
-    const int refine_on = pr.refine_iters > 0 ? 1 : 0;
+    const int refine_on = pr.refine_iters > 0 ? 1 + pr.refine_variant : 0;   // the captured kernel
     const bool stale = !c->gexec[0] || c->g_ws != c->ws.p || c->g_claims != c->claims.p || c->g_ctrs != c->ctrs.p ||
                        c->g_mode != pr.mode || c->g_ppl != pr.ppl || c->g_grid != pr.grid ||
                        c->g_refine != refine_on || c->g_lds != pr.lds || c->gpin[0].size != pr.blob_cap;
@@ -1116,7 +1131,8 @@ int fl_search_fuse_graph_launch(fl_ctx* c, const fl_batch* B, const fl_params* P
             launch_fetch(c, c->gpin[gi].p, c->gpin[gi].size, c->cap_stream);
             int lrc = launch_search(c, pr, dh, c->cap_stream, false, false);
             c->prof = saved_prof;
-            if (lrc == FL_OK && refine_on) lrc = launch_refine(c, dh, pr.refine_iters, c->cap_stream, false);
+            if (lrc == FL_OK && refine_on)
+                lrc = launch_refine(c, dh, pr.refine_iters, pr.refine_variant, c->cap_stream, false);
             hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
             if (lrc) {
                 if (graph) hipGraphDestroy(graph);

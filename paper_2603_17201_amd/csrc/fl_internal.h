@@ -120,8 +120,12 @@ struct alignas(16) BatchHdr {
     uint32_t pad_epoch;
     int32_t lds_hash_mask;      // owner hash capacity - 1 in the LDS modes
     int32_t n_wg;               // workgroups of the search launch
-    int32_t refine_iters;
+    int32_t refine_iters;       // evaluations per round
     float huber_delta;
+    int32_t refine_rounds;      // >= 1; rounds after the first keep the pairs within outlier_px
+    float outlier_px;
+    float lm_lambda;            // > 0: Levenberg-Marquardt from this damping; 0: Gauss-Newton
+    int32_t pad_refine;
     int32_t refine_blocks;      // blocks per event
     int32_t refine_scan;        // 1: take accepted pairs from the decisions, not the list
     int32_t resolve_in_refine;  // 1: the refinement kernel resolves the search's ADD conflicts

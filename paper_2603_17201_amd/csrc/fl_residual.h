@@ -241,6 +241,7 @@ __device__ inline bool solve7(const double* g, const double* Hu, double lambda, 
 
 struct PairTerm {
     float r0, r1, w, rho;
+    float e;             // |r| (0 when not valid)
     float J[2][7];
     bool valid;
 };
@@ -259,13 +260,14 @@ __device__ __forceinline__ void pair_term(const float* A, const float* tS, const
     }
     o.valid = q2 > 0.0f;
     if (!o.valid) {
-        o.r0 = o.r1 = o.w = o.rho = 0.0f;
+        o.r0 = o.r1 = o.w = o.rho = o.e = 0.0f;
         return;
     }
     const float iz = __builtin_amdgcn_rcpf(q2);   // within 1 ulp
     o.r0 = fx * q0 * iz + cx - uo;
     o.r1 = fy * q1 * iz + cy - vo;
     const float e = sqrtf(o.r0 * o.r0 + o.r1 * o.r1);
+    o.e = e;
     if (e <= delta) {
         o.w = 1.0f;
         o.rho = 0.5f * e * e;
@@ -597,17 +599,8 @@ __global__ void gn_step_kernel(const double* __restrict__ g, const double* __res
 
 constexpr unsigned kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ void refine_accumulate(const float* T, float fx, float fy, float cx, float cy, float x,
-                                                  float y, float z, float uo, float vo, const fl_sim3& S, float delta,
-                                                  double* acc) {
-    PairTerm t;
-    pair_term(S.sR, S.t, T, fx, fy, cx, cy, x, y, z, uo, vo, delta, true, t);
-    if (t.valid) {
-        accumulate(t, acc);
-        acc[35] += 1.0;
-    }
-}
-
+// One pair's terms at S (float32), added when the pair is in front of its
+// keyframe; acc[35] counts the pairs added.
 __device__ __forceinline__ void refine_accumulate_f32(const float* T, float fx, float fy, float cx, float cy, float x,
                                                       float y, float z, float uo, float vo, const fl_sim3& S,
                                                       float delta, float* acc) {
@@ -619,33 +612,98 @@ __device__ __forceinline__ void refine_accumulate_f32(const float* T, float fx, 
     }
 }
 
+// A pair's reprojection error at a float64 Sim3 (13 doubles: R, t, s), in
+// float64 throughout; false when the pair is behind its keyframe.  The
+// quantities that decide something (a Levenberg-Marquardt step's Huber loss,
+// whether a pair is an inlier of a round) are evaluated this way: their
+// float32 form carries ~1e-5 px of rounding per pair, enough to turn a
+// near-tie either way.
+__device__ __forceinline__ bool pair_error64(const double* S, const float* T, float fx, float fy, float cx, float cy,
+                                             float x, float y, float z, float uo, float vo, double& e) {
+    const double X = x, Y = y, Z = z, sc = S[12];
+    double p[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = sc * (S[3 * i] * X + S[3 * i + 1] * Y + S[3 * i + 2] * Z) + S[9 + i];
+    double q[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        q[i] = (double)T[3 * i] * p[0] + (double)T[3 * i + 1] * p[1] + (double)T[3 * i + 2] * p[2] + (double)T[9 + i];
+    if (!(q[2] > 0.0)) {
+        e = 0.0;
+        return false;
+    }
+    const double r0 = (double)fx * q[0] / q[2] + (double)cx - (double)uo;
+    const double r1 = (double)fy * q[1] / q[2] + (double)cy - (double)vo;
+    e = sqrt(r0 * r0 + r1 * r1);
+    return true;
+}
+
+__device__ __forceinline__ double huber64(double e, double delta) {
+    return e <= delta ? 0.5 * e * e : delta * e - 0.5 * delta * delta;
+}
+
+// Fixed-order float64 sum over the block: a wave butterfly (every lane ends
+// with the same value: each stage adds the same two numbers in both lanes),
+// then the wave totals in wave order.  s_w holds one double per wave.
+__device__ __forceinline__ double block_sum_f64(double v, double* s_w) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (wave_lane() == 0) s_w[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) sum += s_w[w];
+    return sum;
+}
+
 constexpr int kRefCache = 2;     // accepted pairs a thread keeps in registers across the steps
 constexpr int kRefKfLds = 64;    // keyframes of one event whose pose and intrinsics sit in LDS
 constexpr int kRefMaxB = 64;     // workgroups per event
 constexpr int kRefBlock = 512;   // threads of a refinement workgroup: 64 x 512 pairs at one per thread
+constexpr int kNAccLM = 40;      // the sums plus the Huber loss (slot 36), padded to a multiple of 4
 // Each float64 partial travels as two 64-bit words, (high half << 32 | tag)
 // and (low half << 32 | tag): a word is written and read in one piece, so a
 // reader that sees the tag of the current launch and step in both words has
-// the value, without a separate flag or any cache maintenance.
-constexpr int kRefWords = 2 * kNAcc;
+// the value, without a separate flag or any cache maintenance.  Rows are
+// laid out for the larger (Levenberg-Marquardt) sum set.
+constexpr int kRefWords = 2 * kNAccLM;
+constexpr double kLmConverged = 1e-6;   // relative loss change that ends a round
 
-// 32-bit words of the shared buffer: the block reduction's float32 transpose,
-// later the gathered 32-bit halves of the partial sums
-constexpr int kRefLds = kNAcc * (kRefBlock / 4 + 1);   // the block reduction's transpose (floats)
-
+// The refinement of each event in rounds.  Round 0 uses every accepted
+// pair; a later round uses the pairs in front of their keyframe whose error
+// at the round's starting Sim3 is within outlier_px.  A round is
+// refine_iters evaluations of the sums.  Gauss-Newton (LM false) steps to
+// S <- exp(d) S after every evaluation, d solving H d = -g.  Levenberg-
+// Marquardt (LM true) evaluates the round's starting Sim3, then candidates
+// exp(d) S_acc with (H + lambda diag H) d = -g at the accepted S_acc.  With
+// rho the candidate's relative drop of the Huber loss below S_acc's: rho >
+// 1e-6 takes it (lambda / 10, at least 1e-12), |rho| <= 1e-6 ends the round
+// (converged; every workgroup holds the same sums, so all of them leave the
+// round together), rho < -1e-6 drops it (lambda x 10, at most 1e16).
+// lambda restarts at lm_lambda each round and the round ends at S_acc.
+// ROUNDS false compiles the single-round kernel (no inlier tests).
+template <bool LM, bool ROUNDS>
 __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __restrict__ hp) {
-    __shared__ float s_big[kRefLds];   // the block reduction's transpose
-    __shared__ double s_q[kSeg * kNAcc];
-    __shared__ double s_out[kNAcc];
+    constexpr int NV = LM ? kNAccLM : kNAcc;
+    __shared__ float s_big[NV * (kRefBlock / 4 + 1)];   // the block reduction's transpose
+    __shared__ double s_q[kSeg * NV];
+    __shared__ double s_out[NV];
     __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
     __shared__ double s_S64[13];
     __shared__ fl_sim3 s_S;
+    __shared__ double s_Srs64[13];           // the round's starting Sim3 (inlier tests)
+    __shared__ double s_wsum[kRefBlock / kWave];
+    __shared__ double s_acc[kNAcc];          // LM: g, H and count at S_acc
+    __shared__ double s_Sacc[13];            // LM: S_acc
+    __shared__ double s_lm[2];               // LM: loss at S_acc, lambda
     __shared__ int s_fail;
+    __shared__ int s_round_end;              // LM: the round converged at this step
     const BatchHdr& h = *hp;
     const int B = h.refine_blocks;
     const int n_units = h.n_events * B;
     const int iters = h.refine_iters;
+    const int total = iters * (ROUNDS ? h.refine_rounds : 1);
     const float delta = h.huber_delta;
+    const float tau = h.outlier_px;
     const int tid = threadIdx.x;
     const uint32_t tag0 = *h.epoch << 10;   // tag of step it: tag0 | (it + 1), it < 1000
     for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
@@ -675,13 +733,16 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
             continue;
         }
         const int stride = Be * blockDim.x;
-        // this thread's first kRefCache accepted pairs, loaded once
+        // this thread's first kRefCache accepted pairs, loaded once, and
+        // whether each is an inlier of the current round
         float cx_[kRefCache], cy_[kRefCache], cz_[kRefCache], cu_[kRefCache], cv_[kRefCache];
         int ck_[kRefCache];
+        bool in_[kRefCache];
 #pragma unroll
         for (int r = 0; r < kRefCache; ++r) {
             const int i = b * blockDim.x + tid + r * stride;
             ck_[r] = -1;
+            in_[r] = true;
             if (use_list && i < (int)cnt) {
                 const MatchRec m = h.match_list[ed.list_off + i];
                 cx_[r] = m.x;
@@ -693,65 +754,110 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
             }
         }
         __syncthreads();
-        for (int it = 0; it < iters; ++it) {
+        // it: evaluation index (round it / iters); seq: exchanges done, which
+        // picks the row buffer and the tag (a converged round skips the rest
+        // of its evaluations, in every workgroup alike)
+        for (int it = 0, seq = 0; it < total; ++it, ++seq) {
+            const int rnd = it / iters, j = it - rnd * iters;
             const fl_sim3 S = s_S;
+            // a round after the first keeps its inliers: a pair held in
+            // registers is classified at the round's first evaluation (at the
+            // round's starting Sim3); any other pair is tested against that
+            // Sim3 at every step
+            const bool bounded = ROUNDS && rnd > 0;
+            const bool classify = bounded && j == 0;
             // Each thread adds its few pairs' terms in float32 (one pair per
             // thread when the list fits the workgroups, a couple of dozen at
             // most when the event's pairs are scanned); everything across
             // threads and workgroups is summed in float64.
-            float accf[kNAcc];
+            float accf[NV];
 #pragma unroll
-            for (int i = 0; i < kNAcc; ++i) accf[i] = 0.0f;
+            for (int i = 0; i < NV; ++i) accf[i] = 0.0f;
+            double lossd = 0.0;   // LM: the Huber loss of this thread's pairs, float64
             if (use_list) {
 #pragma unroll
                 for (int r = 0; r < kRefCache; ++r) {
-                    if (ck_[r] < 0) continue;
+                    if (ck_[r] < 0 || !(in_[r] || classify)) continue;
+                    const float* T;
+                    float fx, fy, px, py;
                     if (kf_lds) {
                         const float* q = &s_kf[16 * (ck_[r] - ed.kf_begin)];
-                        refine_accumulate_f32(q, q[12], q[13], q[14], q[15], cx_[r], cy_[r], cz_[r], cu_[r], cv_[r],
-                                              S, delta, accf);
+                        T = q;
+                        fx = q[12];
+                        fy = q[13];
+                        px = q[14];
+                        py = q[15];
                     } else {
                         const KfDesc& kd = h.kf[ck_[r]];
-                        refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, cx_[r], cy_[r], cz_[r], cu_[r],
-                                              cv_[r], S, delta, accf);
+                        T = kd.T;
+                        fx = kd.fx;
+                        fy = kd.fy;
+                        px = kd.cx;
+                        py = kd.cy;
                     }
+                    double e;
+                    if (classify) {
+                        in_[r] = pair_error64(s_Srs64, T, fx, fy, px, py, cx_[r], cy_[r], cz_[r], cu_[r], cv_[r], e) &&
+                                 e <= (double)tau;
+                        if (!in_[r]) continue;
+                    }
+                    refine_accumulate_f32(T, fx, fy, px, py, cx_[r], cy_[r], cz_[r], cu_[r], cv_[r], S, delta, accf);
+                    if (LM && pair_error64(s_S64, T, fx, fy, px, py, cx_[r], cy_[r], cz_[r], cu_[r], cv_[r], e))
+                        lossd += huber64(e, (double)delta);
                 }
                 for (int i = b * blockDim.x + tid + kRefCache * stride; i < (int)cnt; i += stride) {
                     const MatchRec m = h.match_list[ed.list_off + i];
                     const KfDesc& kd = h.kf[m.kf];
+                    double e;
+                    if (bounded && !(pair_error64(s_Srs64, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, m.x, m.y, m.z, m.u, m.v,
+                                                  e) && e <= (double)tau))
+                        continue;
                     refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, m.x, m.y, m.z, m.u, m.v, S, delta, accf);
+                    if (LM && pair_error64(s_S64, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, m.x, m.y, m.z, m.u, m.v, e))
+                        lossd += huber64(e, (double)delta);
                 }
             } else {
                 // no list (or it overflowed): scan the event's pairs keyframe by keyframe
                 for (int k = ed.kf_begin; k < ed.kf_end; ++k) {
                     const KfDesc& kd = h.kf[k];
-                    for (int64_t j = b * blockDim.x + tid; j < kd.n_pairs; j += stride) {
-                        const int64_t o = kd.pair_off + j;
+                    for (int64_t jj = b * blockDim.x + tid; jj < kd.n_pairs; jj += stride) {
+                        const int64_t o = kd.pair_off + jj;
                         const uint8_t dec = h.out[0].decision[o];
                         if (dec != FL_ADD && dec != FL_FUSE) continue;
-                        const int32_t lp = h.dense ? (int32_t)j : h.pair_mp[o];
+                        const int32_t lp = h.dense ? (int32_t)jj : h.pair_mp[o];
                         const int32_t bi = h.out[0].best_idx[o];
                         if (lp < 0 || lp >= kd.n_mp || bi < 0 || bi >= kd.n_kp) continue;
                         const int64_t gp = kd.mp_off + lp, kp = kd.kp_off + bi;
-                        refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, h.mp_xyz[3 * gp], h.mp_xyz[3 * gp + 1],
-                                              h.mp_xyz[3 * gp + 2], h.kp_xy[2 * kp], h.kp_xy[2 * kp + 1], S, delta,
-                                              accf);
+                        const float x = h.mp_xyz[3 * gp], y = h.mp_xyz[3 * gp + 1], z = h.mp_xyz[3 * gp + 2];
+                        const float uo = h.kp_xy[2 * kp], vo = h.kp_xy[2 * kp + 1];
+                        double e;
+                        if (bounded && !(pair_error64(s_Srs64, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, x, y, z, uo, vo, e) &&
+                                         e <= (double)tau))
+                            continue;
+                        refine_accumulate_f32(kd.T, kd.fx, kd.fy, kd.cx, kd.cy, x, y, z, uo, vo, S, delta, accf);
+                        if (LM && pair_error64(s_S64, kd.T, kd.fx, kd.fy, kd.cx, kd.cy, x, y, z, uo, vo, e))
+                            lossd += huber64(e, (double)delta);
                     }
                 }
             }
             // the per-thread float32 sums go through LDS as they are and are
             // widened as the segments are added
-            block_reduce_quad<kNAcc, kRefBlock>(accf, s_big, s_q, s_out);
+            block_reduce_quad<NV, kRefBlock>(accf, s_big, s_q, s_out);
+            if (LM) {
+                const double loss = block_sum_f64(lossd, s_wsum);
+                if (tid == 0) s_out[36] = loss;
+                __syncthreads();
+            }
             if (Be > 1) {
                 // Exchange of the Be partial sums of this step as tagged words
                 // (device-coherent stores and loads).  Rows alternate between
                 // two buffers by step: a workgroup writes step it + 2 only
                 // after it has read every row of step it + 1, which every
                 // workgroup writes only after reading all rows of step it.
-                const size_t slot = ((size_t)(it & 1) * n_units + (size_t)ev * B);   // rows of this step: Be
+                const size_t slot = ((size_t)(seq & 1) * n_units + (size_t)ev * B);   // rows of this step: Be
                 unsigned long long* rows = h.refine_rows + slot * kRefWords;
-                const uint32_t tag = tag0 | (uint32_t)(it + 1);
-                if (tid < kRefWords) {
+                const uint32_t tag = tag0 | (uint32_t)(seq + 1);
+                if (tid < 2 * NV) {
                     const unsigned long long bits = (unsigned long long)__double_as_longlong(s_out[tid >> 1]);
                     const uint32_t half = (tid & 1) ? (uint32_t)bits : (uint32_t)(bits >> 32);
                     __hip_atomic_store(&rows[(size_t)b * kRefWords + tid], ((unsigned long long)half << 32) | tag,
@@ -762,27 +868,27 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                 // loaded again) and adds those rows in that order; then the
                 // segments are added pairwise.  The order is the same in every
                 // workgroup, so all of them solve for bitwise the same step.
-                if (tid < kSeg * kNAcc) {
-                    const int c = tid % kNAcc, q = tid / kNAcc;
+                if (tid < kSeg * NV) {
+                    const int c = tid % NV, q = tid / NV;
                     constexpr int kRowsPer = kRefMaxB / kSeg;
                     unsigned long long wh[kRowsPer], wl[kRowsPer];
                     uint32_t pending = 0;
 #pragma unroll
-                    for (int j = 0; j < kRowsPer; ++j)
-                        if (q + kSeg * j < Be) pending |= 1u << j;
+                    for (int jr = 0; jr < kRowsPer; ++jr)
+                        if (q + kSeg * jr < Be) pending |= 1u << jr;
                     unsigned spins = 0;
                     while (pending) {
 #pragma unroll
-                        for (int j = 0; j < kRowsPer; ++j)
-                            if (pending >> j & 1u) {
-                                const unsigned long long* w = rows + (size_t)(q + kSeg * j) * kRefWords + 2 * c;
-                                wh[j] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                wl[j] = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        for (int jr = 0; jr < kRowsPer; ++jr)
+                            if (pending >> jr & 1u) {
+                                const unsigned long long* w = rows + (size_t)(q + kSeg * jr) * kRefWords + 2 * c;
+                                wh[jr] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                wl[jr] = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             }
 #pragma unroll
-                        for (int j = 0; j < kRowsPer; ++j)
-                            if ((pending >> j & 1u) && (uint32_t)wh[j] == tag && (uint32_t)wl[j] == tag)
-                                pending &= ~(1u << j);
+                        for (int jr = 0; jr < kRowsPer; ++jr)
+                            if ((pending >> jr & 1u) && (uint32_t)wh[jr] == tag && (uint32_t)wl[jr] == tag)
+                                pending &= ~(1u << jr);
                         if (pending) {
                             // no back-off: each round is a device-memory round
                             // trip already, and a pause only delays the last row
@@ -794,36 +900,73 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                     }
                     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-                    for (int j = 0; j < kRowsPer; ++j) {
-                        if (q + kSeg * j < Be) {
+                    for (int jr = 0; jr < kRowsPer; ++jr) {
+                        if (q + kSeg * jr < Be) {
                             const double x = __longlong_as_double(
-                                (long long)((wh[j] >> 32 << 32) | (wl[j] >> 32)));
-                            if (j & 1) a1 += x; else a0 += x;
+                                (long long)((wh[jr] >> 32 << 32) | (wl[jr] >> 32)));
+                            if (jr & 1) a1 += x; else a0 += x;
                         }
                     }
-                    s_q[q * kNAcc + c] = a0 + a1;
+                    s_q[q * NV + c] = a0 + a1;
                 }
                 __syncthreads();
                 if (s_fail) break;
-                if (tid < kNAcc) s_out[tid] = add_segments<kNAcc>(s_q, tid);
+                if (tid < NV) s_out[tid] = add_segments<NV>(s_q, tid);
                 __syncthreads();
             }
             if (tid == 0) {
-                double d[7];
-                if (solve7(s_out, s_out + 7, 0.0, d)) {
-                    const Sim3d Sd = sim3_mul(sim3_exp(d), sim3_load(s_S64));
-                    sim3_store(Sd, s_S64);
-                    sim3_to_f32_pose(Sd, &s_S);
+                bool round_end = j == iters - 1;
+                if (!LM) {
+                    double d[7];
+                    if (solve7(s_out, s_out + 7, 0.0, d)) {
+                        const Sim3d Sd = sim3_mul(sim3_exp(d), sim3_load(s_S64));
+                        sim3_store(Sd, s_S64);
+                        sim3_to_f32_pose(Sd, &s_S);
+                    }
+                } else {
+                    // the evaluation just summed was at s_S64: the round's start
+                    // (j = 0) or the last candidate
+                    bool take = j == 0;
+                    if (j == 0) {
+                        s_lm[1] = (double)h.lm_lambda;
+                    } else {
+                        const double rho = s_lm[0] > 0.0 ? (s_lm[0] - s_out[36]) / s_lm[0] : 0.0;
+                        take = rho > kLmConverged;
+                        if (!take && rho >= -kLmConverged) round_end = true;   // converged
+                    }
+                    if (take) {
+                        for (int i = 0; i < kNAcc; ++i) s_acc[i] = s_out[i];
+                        for (int i = 0; i < 13; ++i) s_Sacc[i] = s_S64[i];
+                        s_lm[0] = s_out[36];
+                        if (j > 0) s_lm[1] = fmax(s_lm[1] * 0.1, 1e-12);
+                    } else if (!round_end) {
+                        s_lm[1] = fmin(s_lm[1] * 10.0, 1e16);
+                    }
+                    const Sim3d Sa = sim3_load(s_Sacc);
+                    double d[7];
+                    if (!round_end && solve7(s_acc, s_acc + 7, s_lm[1], d)) {
+                        const Sim3d Sd = sim3_mul(sim3_exp(d), Sa);
+                        sim3_store(Sd, s_S64);
+                        sim3_to_f32_pose(Sd, &s_S);
+                    } else {
+                        sim3_store(Sa, s_S64);
+                        sim3_to_f32_pose(Sa, &s_S);
+                    }
                 }
+                if (round_end)
+                    for (int i = 0; i < 13; ++i) s_Srs64[i] = s_S64[i];   // the next round's starting Sim3
+                s_round_end = round_end;
             }
             __syncthreads();
+            if (LM && s_round_end) it = (rnd + 1) * iters - 1;   // on to the next round
         }
         if (b == 0 && tid == 0) {
             if (!s_fail) {
                 for (int i = 0; i < 13; ++i) h.event_S[13 * (int64_t)ev + i] = s_S64[i];
                 if (h.event_S32_out) sim3_to_f32(sim3_load(s_S64), &h.event_S32_out[ev]);
             }
-            if (h.event_n_matched) h.event_n_matched[ev] = s_fail ? -1 : (int32_t)s_out[35];
+            if (h.event_n_matched)
+                h.event_n_matched[ev] = s_fail ? -1 : (int32_t)(LM ? s_acc[35] : s_out[35]);
             h.ev_ctr[ev * kEvCtrs + kEvMatch] = 0;   // the event's list is spent
         }
         __syncthreads();

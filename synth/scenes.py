@@ -79,6 +79,19 @@ def perturbed(S, deg: float, metres: float, dscale: float, seed: int) -> np.ndar
     return _perturb(np.random.Generator(np.random.PCG64(seed)), np.asarray(S, np.float64), deg, metres, dscale)
 
 
+# Robust refinement after the verification search: 2 rounds of 5 steps, the
+# inlier bound at the 99% quantile of a chi-square with 2 degrees of freedom
+# for 1 px noise (sqrt(9.21) px), Levenberg-Marquardt from lambda = 1e-3.
+# The paper gives no constants for its Sim3 optimisation; these are a reading.
+ROBUST_ITERS, ROBUST_ROUNDS, ROBUST_OUTLIER_PX, ROBUST_LM_LAMBDA = 5, 2, 3.035, 1e-3
+
+
+def gen_c2_misplaced(seed: int = 202) -> Event:
+    """The loop event with 10% of its planted keypoints moved 6-9 px away
+    (wrong associations the verification window still matches)."""
+    return gen_c2(seed=seed, misplace=(0.1, 6.0, 9.0))
+
+
 def ps2_passes(ev, seed: int = 5):
     """The two projection searches on the current keyframe around the Sim3
     optimisation, as (params, kf_sim3) pairs: one at the event's starting
@@ -283,7 +296,7 @@ def _flip_bits(rng, desc, p):
 
 def gen_event(rng, *, cam, kf_poses, S_true, S_init, n_mp, depth, anchors,
               covis=None, kp_counts, frac_planted, frac_outlier, frac_dup,
-              pix_sigma=1.0, flip_p=0.05, skip_frac=0.0, id_base=POINT_ID_BASE,
+              pix_sigma=1.0, flip_p=0.05, skip_frac=0.0, misplace=None, id_base=POINT_ID_BASE,
               fresh_base=FRESH_ID_BASE, params=None, name="") -> Event:
     """Build one loop event.
 
@@ -364,6 +377,14 @@ def gen_event(rng, *, cam, kf_poses, S_true, S_init, n_mp, depth, anchors,
         d_k = np.linalg.norm(q[chosen], axis=1) / S_kf_true[k][12]
         oct_pl = _detect_octave(d_k, mp_dmax[chosen].astype(np.float64), params.n_octaves)
         xy_pl = np.stack([uu[chosen], vv[chosen]], axis=1) + rng.normal(0.0, pix_sigma, (len(chosen), 2))
+        if misplace is not None and n_pl > 0:
+            # wrong associations: planted keypoints moved away from their point's
+            # projection, descriptor kept (gross outliers of the refinement)
+            frac, lo, hi = misplace
+            m = rng.random(n_pl) < frac
+            ang = rng.uniform(0.0, 2 * np.pi, n_pl)
+            dist = rng.uniform(lo, hi, n_pl)
+            xy_pl[:n_pl][m] += (dist[:, None] * np.stack([np.cos(ang), np.sin(ang)], axis=1))[m]
         desc_pl = _flip_bits(rng, mp_desc[chosen], flip_p)
         owner_pl = np.full(len(chosen), -1, np.int64)
         kind = np.zeros(len(chosen), np.int8)
@@ -428,13 +449,15 @@ def gen_c1(seed: int = 101) -> Event:
 
 
 def gen_c2(seed: int = 202, skip_frac: float = 0.0, n_kf: int = 20, n_mp: int = 15000,
-           n_kp: int = 1200, perturb: bool = True) -> Event:
+           n_kp: int = 1200, perturb: bool = True, misplace=None) -> Event:
     """Loop event: 20 keyframes 752x480 on a 3 m arc of radius 5 m, 1,200
     keypoints each (50% planted, 30% outliers, 20% pre-owned duplicates),
     15,000 points at depth 0.5-20 m in the middle keyframe's frustum, loop
     Sim3 with scale U[0.95, 1.05], rotation <= 5 deg, 0.1 m translation.
     The search runs at a Sim3 perturbed from the truth by 0.1 deg, 1 cm and
-    0.2% scale (the state before refinement)."""
+    0.2% scale (the state before refinement).  misplace = (fraction, lo, hi)
+    moves that fraction of the planted keypoints U[lo, hi] px away from their
+    point's projection (wrong associations)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     S = _random_loop_sim3(rng, 0.95, 1.05, 5.0, 0.1)
     S_init = _perturb(rng, S, 0.1, 0.01, 0.002) if perturb else S
@@ -443,7 +466,7 @@ def gen_c2(seed: int = 202, skip_frac: float = 0.0, n_kf: int = 20, n_mp: int = 
     return gen_event(rng, cam=CAM_752, kf_poses=poses, S_true=S, S_init=S_init, n_mp=n_mp,
                      depth=(0.5, 20.0), anchors=np.full(n_mp, mid), kp_counts=[n_kp] * n_kf,
                      frac_planted=0.5, frac_outlier=0.3, frac_dup=0.2, skip_frac=skip_frac,
-                     name="c2")
+                     misplace=misplace, name="c2")
 
 
 def _trunc_geom(rng, n, p, lo, hi):

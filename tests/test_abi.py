@@ -43,7 +43,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.Pinhole) == 32
     assert ctypes.sizeof(_abi.Params) == 32
     assert ctypes.sizeof(_abi.FuseOut) == 40
-    assert ctypes.sizeof(_abi.Refine) == 32
+    assert ctypes.sizeof(_abi.Refine) == 48
     assert ctypes.sizeof(_abi.Pass) == 80
 
 

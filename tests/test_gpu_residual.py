@@ -348,3 +348,62 @@ def test_two_contexts_on_two_streams(ctx):
                 S[i].copy_(t(evs[i].S_init.reshape(1, 13).copy()))
     finally:
         ctx2.close()
+
+
+def _accepted(ev, out):
+    acc = np.nonzero((out["decision"] == oracle.ADD) | (out["decision"] == oracle.FUSE))[0]
+    kf = (np.searchsorted(ev.pair_offset, acc, side="right") - 1).astype(np.int32)
+    mp = acc - ev.pair_offset[kf]
+    kp = ev.kp_offset[kf] + out["best_idx"][acc]
+    return ev.mp_xyz[mp], ev.kp_xy[kp], kf
+
+
+@pytest.mark.parametrize("lm", [0.0, synth.ROBUST_LM_LAMBDA])
+def test_robust_refinement_matches_oracle(ctx, lm):
+    """The verification search on an event with 10% wrong associations, then
+    two rounds of five evaluations, the second on the pairs within 3.035 px:
+    Gauss-Newton and Levenberg-Marquardt, through the scan path, the graph
+    and the eager batched call, against the float64 oracle."""
+    import paper_2603_17201_amd as fl
+    ev = synth.gen_c2_misplaced()
+    P = synth.verification_params()
+    out = oracle.search_fuse(ev, params=P, use_grid=True)
+    xyz, uv, kf = _accepted(ev, out)
+    T32 = ev.kf_T.astype(np.float32).astype(np.float64)
+    it, rounds, tau = synth.ROBUST_ITERS, synth.ROBUST_ROUNDS, synth.ROBUST_OUTLIER_PX
+    # the device takes the Huber threshold and the inlier bound as float32
+    d32, tau32 = float(np.float32(2.45)), float(np.float32(tau))
+    S_ref, n_ref = R.refine_robust(ev.S_init, xyz, uv, kf, T32, ev.cams[0], d32, iters=it, rounds=rounds,
+                                   outlier_px=tau32, lm_lambda=lm)
+    assert n_ref < len(xyz) - 1000   # the wrong associations are dropped
+    b = fl.DeviceBatch(ev, device=dev())
+    res = ctx.search_fuse_batched(b, P)
+    for mode in ("scan", "graph", "batched"):
+        event_S = t(ev.S_init.reshape(1, 13).copy())
+        nm = torch.zeros(1, dtype=torch.int32, device=dev())
+        ref = (it, 2.45, event_S, None, nm, rounds, tau, lm)
+        if mode == "graph":
+            ctx.search_fuse_graph(b, P, refine=ref)
+        elif mode == "batched":
+            got = ctx.search_fuse_batched(b, P, refine=ref).numpy()
+            for k in got:
+                assert np.array_equal(got[k], out[k]), k
+        else:
+            ctx.refine_events(b, res, ref)
+        S_gpu = event_S.cpu().numpy()[0]
+        err = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(S_ref))))
+        assert err < 1e-6, (mode, lm, err)
+        assert nm.item() == n_ref, (mode, lm, nm.item(), n_ref)
+
+
+def test_robust_refinement_rejects_bad_arguments(ctx):
+    import paper_2603_17201_amd as fl
+    ev = synth.gen_c1()
+    b = fl.DeviceBatch(ev, device=dev())
+    S = t(ev.S_init.reshape(1, 13).copy())
+    for ref in [(5, 2.45, S, None, None, 2, 0.0, 0.0),       # no inlier bound
+                (5, 2.45, S, None, None, 2, 3.0, -1.0),      # negative damping
+                (500, 2.45, S, None, None, 3, 3.0, 0.0),     # more than 1000 evaluations
+                (5, 2.45, S, None, None, -1, 3.0, 0.0)]:
+        with pytest.raises(fl.FlError):
+            ctx.search_fuse_batched(b, ev.params, refine=ref)
