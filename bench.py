@@ -501,6 +501,54 @@ class Bench:
             f"{ms_two * 1e3:.1f} us in two calls")
         return res
 
+    def robust_refinement(self, steps):
+        """Verification search and Sim3 refinement on a loop event with 10%
+        wrong associations: ten Gauss-Newton steps, two rounds of five with
+        the inlier bound, and the same rounds with Levenberg-Marquardt; one
+        eager batched call per event, device-resident."""
+        import synth
+        fl, torch, ctx = self.fl, self.torch, self.ctx
+        ev = synth.gen_c2_misplaced()
+        P = synth.verification_params()
+        b = fl.DeviceBatch(ev, device=self.dev)
+        out = fl.FuseOutputs.empty(b.n_pairs, self.dev)
+        S_init = torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(self.dev)
+        S = S_init.clone()
+        nm = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        it, rounds, tau, lm = (synth.ROBUST_ITERS, synth.ROBUST_ROUNDS, synth.ROBUST_OUTLIER_PX,
+                               synth.ROBUST_LM_LAMBDA)
+        variants = {"gauss_newton_10": (GN_ITERS, HUBER, S, None, nm),
+                    "rounds_gauss_newton": (it, HUBER, S, None, nm, rounds, tau, 0.0),
+                    "rounds_levenberg_marquardt": (it, HUBER, S, None, nm, rounds, tau, lm)}
+        res = dict(workload="loop event, 20 keyframes, 300,000 pairs, 10% of planted keypoints moved 6-9 px; "
+                            "verification thresholds", rounds=rounds, iters_per_round=it, outlier_px=tau,
+                   lm_lambda=lm)
+
+        def call(ref):
+            S.copy_(S_init)
+            ctx.search_fuse_batched(b, P, out, refine=ref)
+        for name, ref in variants.items():
+            gc.collect()
+            gc.disable()
+            ms = self.events_time(lambda: call(ref), steps, 3)
+            ctx.set_profiling(True)
+            for _ in range(10):
+                call(ref)
+            torch.cuda.synchronize()
+            ms_ref, n_ref = ctx.get_profile("refine")
+            ctx.get_profile("search")
+            ctx.set_profiling(False)
+            gc.enable()
+            call(ref)
+            torch.cuda.synchronize()
+            deg, m, ls = sim3_error(S.cpu().numpy()[0], np.asarray(ev.S_true, np.float64).reshape(13))
+            res[name] = dict(us_per_event=ms * 1e3, refine_kernel_us=ms_ref / max(n_ref, 1) * 1e3,
+                             pairs_used=int(nm.item()), error_vs_true_sim3=dict(deg=deg, m=m, log_scale=ls))
+            log(f"robust refinement, {name}: {ms * 1e3:.1f} us per event (refine kernel "
+                f"{ms_ref / max(n_ref, 1) * 1e3:.1f} us), {int(nm.item())} pairs used, error vs true Sim3 "
+                f"{deg:.2e} deg, {m:.2e} m, {ls:.2e} log scale")
+        return res
+
     def residual(self):
         import synth
         torch, fl, ctx = self.torch, self.fl, self.ctx
@@ -697,6 +745,7 @@ def main():
         secondary["uneven_event_60kf_x10_one_launch"] = bench.batch_graph(B, "ten uneven events", 10)
         secondary["residual_50k"] = bench.residual()
         secondary["projection_search"] = bench.projection_search(args.steps)
+        secondary["robust_refinement"] = bench.robust_refinement(args.steps)
         if args.stream_events > 0:
             secondary["stream"] = bench.stream_events(args.stream_events)
 
