@@ -214,3 +214,59 @@ def refine_robust(S0, xyz, uv, kf_idx, kf_T, cam, delta, iters=5, rounds=2, outl
                 else:
                     lam = min(lam * 10.0, 1e16)
     return S, n_used
+
+
+# ---------------------------------------------------------------------------
+# The other direction of a loop match: a point X of the current side, mapped
+# into the loop side by S^-1 and observed in a keyframe k there,
+#     r = pi(T_k S^-1 X) - uv.
+# Its gradient is still taken with respect to the left perturbation of S:
+# S^-1 <- S^-1 exp(-xi), so d(S^-1 X)/dxi = -(1/s) R^T [ -[X]x | I | X ].
+
+
+def forward_inv(S, xyz, uv, kf_idx, kf_T, cam, delta):
+    """r, w, L of the other direction (forward() at S^-1)."""
+    return forward(sim3.inverse(S), xyz, uv, kf_idx, kf_T, cam, delta)
+
+
+def jacobian_inv(S, xyz, kf_idx, kf_T, cam):
+    """J [n, 2, 7] = d pi(q)/d q . R_k . (-(1/s) R^T) . [ -[X]x | I | X ]."""
+    X = np.asarray(xyz, np.float64)
+    _, q, _, Rk = project(sim3.inverse(S), X, kf_idx, kf_T, cam)
+    fx, fy = float(cam[0]), float(cam[1])
+    n = len(X)
+    dpi = np.zeros((n, 2, 3))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        iz = 1.0 / q[:, 2]
+        dpi[:, 0, 0] = fx * iz
+        dpi[:, 0, 2] = -fx * q[:, 0] * iz * iz
+        dpi[:, 1, 1] = fy * iz
+        dpi[:, 1, 2] = -fy * q[:, 1] * iz * iz
+    R, s = np.asarray(S[:9], np.float64).reshape(3, 3), float(S[12])
+    G = np.zeros((n, 3, 7))
+    G[:, 0, 1], G[:, 0, 2] = X[:, 2], -X[:, 1]
+    G[:, 1, 0], G[:, 1, 2] = -X[:, 2], X[:, 0]
+    G[:, 2, 0], G[:, 2, 1] = X[:, 1], -X[:, 0]
+    G[:, 0, 3] = G[:, 1, 4] = G[:, 2, 5] = 1.0
+    G[:, :, 6] = X
+    J = np.einsum("nab,nbc,cd,nde->nae", dpi, Rk, -R.T / s, G)
+    J[q[:, 2] <= 0] = 0.0
+    return J
+
+
+def grad_hess_inv(S, xyz, uv, kf_idx, kf_T, cam, delta):
+    r, w, L = forward_inv(S, xyz, uv, kf_idx, kf_T, cam, delta)
+    J = jacobian_inv(S, xyz, kf_idx, kf_T, cam)
+    return np.einsum("n,nai,na->i", w, J, r), np.einsum("n,nai,naj->ij", w, J, J), L
+
+
+def gauss_newton_bidir(S0, fwd, bwd, cam, delta, iters=10):
+    """Undamped IRLS Gauss-Newton on both directions: g and H are the sums of
+    the two sets' (fwd = (xyz, uv, kf_idx, kf_T) observed through S, bwd the
+    same observed through S^-1)."""
+    S = np.asarray(S0, np.float64).copy()
+    for _ in range(iters):
+        g1, H1, _ = grad_hess(S, *fwd, cam, delta)
+        g2, H2, _ = grad_hess_inv(S, *bwd, cam, delta)
+        S = sim3.compose(sim3.exp(np.linalg.solve(H1 + H2, -(g1 + g2))), S)
+    return S

@@ -529,6 +529,45 @@ def gen_c4(seed: int = 404, n: int = 50000, outlier_frac: float = 0.1, outlier_p
                 xi0=xi0, S_eval=S_eval, S_eval_f32=_sim3_f32(S_eval), outlier=out, huber_delta=2.45)
 
 
+def gen_bidir(seed: int = 505, n_fwd: int = 20000, n_bwd: int = 20000, n_views: int = 4,
+              pix_sigma: float = 1.0, outlier_frac: float = 0.1, outlier_px: float = 20.0):
+    """Matches seen from both sides of a loop (752x480 camera, depth 1-10 m):
+    loop-side points observed in current-side keyframes through T_k o S
+    ("fwd"), and current-side points observed in loop-side keyframes through
+    T_m o S^-1 ("bwd"); n_views keyframes per side with poses of ~6 deg and
+    ~0.5 m, pixel noise N(0, pix_sigma), a fraction displaced by outlier_px.
+    The start S0 is the truth moved by 0.5 deg, 2 cm and 1% scale.  Each set
+    is (xyz f32 [n,3], uv f32 [n,2], keyframe index i32 [n], poses f32
+    [n_views,12])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S = _random_loop_sim3(rng, 0.95, 1.05, 5.0, 0.1)
+    R, t, sc = _split(S)
+    S_inv = _sim3(R.T, -(R.T @ t) / sc, 1.0 / sc)
+    fx, fy, cx, cy, W, H = CAM_752
+
+    def side(n, S_map):
+        poses = [(_rodrigues(_unit(rng), np.deg2rad(rng.uniform(0.0, 6.0))), _unit(rng) * rng.uniform(0.0, 0.5))
+                 for _ in range(n_views)]
+        T = np.stack([np.concatenate([Rk.reshape(9), tk]) for Rk, tk in poses]).astype(np.float32)
+        kf = rng.integers(0, n_views, n).astype(np.int32)
+        u, v, z = rng.uniform(0.0, W, n), rng.uniform(0.0, H, n), rng.uniform(1.0, 10.0, n)
+        X = np.empty((n, 3))
+        for k, (Rk, tk) in enumerate(poses):
+            m = kf == k
+            X[m] = _backproject(CAM_752, u[m], v[m], z[m], _compose_T_S(Rk, tk, S_map))
+        uv = np.stack([u, v], axis=1) + rng.normal(0.0, pix_sigma, (n, 2))
+        out = rng.random(n) < outlier_frac
+        th = rng.uniform(0.0, 2 * np.pi, n)
+        uv[out] += outlier_px * np.stack([np.cos(th[out]), np.sin(th[out])], axis=1)
+        return (X.astype(np.float32), uv.astype(np.float32), kf, T), out
+
+    fwd, out_f = side(n_fwd, S)
+    bwd, out_b = side(n_bwd, S_inv)
+    S0 = _perturb(rng, S, 0.5, 0.02, 0.01)
+    return dict(S_true=S, S0=S0, cam=_cam_row(CAM_752), fwd=fwd, bwd=bwd, outlier_fwd=out_f, outlier_bwd=out_b,
+                huber_delta=2.45)
+
+
 def gen_c5_event(e: int, n_kf: Optional[int] = None, n_mp: Optional[int] = None) -> Event:
     """Event e of the 200-event stream (seed 5000 + e): n_kf ~ U{5..80},
     camera 752x480 or 512x512 with probability 1/2, keypoints U{300..2500}

@@ -184,3 +184,47 @@ def test_lm_accepted_loss_decreases_and_rejections_do_not_move():
     # a huge damping barely moves: each step is a tiny gradient step
     S_big, _ = residual.refine_robust(S0, xyz, uv, kf, T, d["cam"], 2.45, iters=3, rounds=1, lm_lambda=1e12)
     assert _err(S_big, S0) < 1e-8
+
+
+@pytest.fixture(scope="module")
+def bidir():
+    return synth.gen_bidir(n_fwd=4000, n_bwd=4000)
+
+
+def test_inverse_direction_gradient_matches_central_differences(bidir):
+    """The other direction's analytic gradient (chain rule through S^-1)
+    against central differences of its loss under S <- exp(xi) S."""
+    S0 = bidir["S0"]
+    xyz, uv, kf, T = bidir["bwd"]
+    T = T.astype(np.float64)
+    g, H, _ = residual.grad_hess_inv(S0, xyz, uv, kf, T, bidir["cam"], 2.45)
+    fd = np.zeros(7)
+    for i in range(7):
+        e = np.zeros(7)
+        e[i] = 1e-6   # central differences: truncation ~h^2 (2e-9 relative here)
+        fd[i] = (residual.forward_inv(sim3.compose(sim3.exp(e), S0), xyz, uv, kf, T, bidir["cam"], 2.45)[2]
+                 - residual.forward_inv(sim3.compose(sim3.exp(-e), S0), xyz, uv, kf, T, bidir["cam"], 2.45)[2]) / 2e-6
+    assert np.max(np.abs(g - fd)) / np.max(np.abs(fd)) < 1e-7
+    assert np.allclose(H, H.T) and np.all(np.linalg.eigvalsh(H) > -1e-9 * np.max(np.abs(H)))
+
+
+def test_inverse_direction_of_the_inverse_is_the_forward_residual(bidir):
+    """Observing X through S^-1 with S replaced by its inverse is the forward
+    residual: the two directions agree on the residual itself."""
+    S0 = bidir["S0"]
+    xyz, uv, kf, T = bidir["fwd"]
+    T = T.astype(np.float64)
+    r1, w1, L1 = residual.forward(S0, xyz, uv, kf, T, bidir["cam"], 2.45)
+    r2, w2, L2 = residual.forward_inv(sim3.inverse(S0), xyz, uv, kf, T, bidir["cam"], 2.45)
+    assert np.max(np.abs(r1 - r2)) < 1e-9 and abs(L1 - L2) < 1e-9 * L1
+
+
+def test_bidirectional_gauss_newton_recovers_exact_sim3():
+    d = synth.gen_bidir(seed=506, n_fwd=3000, n_bwd=3000, pix_sigma=0.0, outlier_frac=0.0)
+    fwd = d["fwd"][:3] + (d["fwd"][3].astype(np.float64),)
+    bwd = d["bwd"][:3] + (d["bwd"][3].astype(np.float64),)
+    S = residual.gauss_newton_bidir(d["S0"], fwd, bwd, d["cam"], 2.45, iters=10)
+    assert _err(S, d["S_true"]) < 1e-7 < _err(d["S0"], d["S_true"])
+    # each direction alone also pins the truth: the sets are consistent
+    S1 = residual.gauss_newton(d["S0"], *fwd, d["cam"], 2.45, iters=10)
+    assert _err(S1, d["S_true"]) < 1e-7
