@@ -290,6 +290,25 @@ int fl_reproj_residual_bwd(fl_ctx* ctx, int32_t n, const float* xyz, const float
                            const fl_pinhole* K /* host */, float huber_delta, double grad_scale,
                            double* g, double* H, hipStream_t stream);
 
+/* The other direction of a loop match: a point X of the current side mapped
+ * to the loop side by S^-1 and observed in keyframe k there,
+ * r = pi(T_k S^-1 X) - uv.  fl_reproj_residual_fwd given the float32 form of
+ * S^-1 (fl_sim3_inverse) computes these residuals, weights and loss.  This
+ * backward takes that same form, S_inv, but returns g and H with respect to
+ * the left perturbation of S itself (S^-1 <- S^-1 exp(-xi)):
+ * J = dpi/dq R_k (-(1/s) R^T) [ -[X]x | I | X ], so the sums of both
+ * directions add into one Gauss-Newton system for S (fl_gn_step).
+ * Arguments, layouts and errors as fl_reproj_residual_bwd. */
+int fl_reproj_residual_bwd_inv(fl_ctx* ctx, int32_t n, const float* xyz, const float* uv,
+                               const int32_t* kf_idx, int32_t n_kf, const float* kf_T, const fl_sim3* S_inv,
+                               const fl_pinhole* K /* host */, float huber_delta, double grad_scale,
+                               double* g, double* H, hipStream_t stream);
+
+/* S^-1 = (R^T, -R^T t / s, 1 / s) of S_in (device [13], float64) into
+ * S_out (device [13], may be NULL) and its float32 form S32_out (device,
+ * may be NULL; not both NULL).  Errors: FL_EINVAL for NULL arguments. */
+int fl_sim3_inverse(fl_ctx* ctx, const double* S_in, double* S_out, fl_sim3* S32_out, hipStream_t stream);
+
 /* S_out = exp(xi) S_in (float64, device [7], [13], [13]); S32_out (device,
  * may be NULL) receives the float32 search form. */
 int fl_sim3_exp_mul(fl_ctx* ctx, const double* xi, const double* S_in, double* S_out, fl_sim3* S32_out,

@@ -101,6 +101,10 @@ SIGNATURES = [
     ("fl_reproj_residual_bwd", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                          c_void_p, ctypes.POINTER(Pinhole), c_float, c_double, c_void_p,
                                          c_void_p, c_void_p]),
+    ("fl_reproj_residual_bwd_inv", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                             c_void_p, ctypes.POINTER(Pinhole), c_float, c_double, c_void_p,
+                                             c_void_p, c_void_p]),
+    ("fl_sim3_inverse", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fl_sim3_exp_mul", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fl_gn_step", c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     ("fl_get_tuning", c_int32, [c_void_p, ctypes.POINTER(Tuning)]),

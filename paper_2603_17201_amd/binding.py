@@ -355,16 +355,30 @@ class Context:
         return r, w, loss
 
     def residual_bwd(self, xyz, uv, kf_idx, kf_T, S32, cam8, delta, grad_scale: float = 1.0, want_H: bool = True,
-                     stream=None):
+                     inverse: bool = False, stream=None):
+        """inverse: the pairs are observed through S^-1 and S32 is the float32
+        form of S^-1 (fl_reproj_residual_bwd_inv); g and H are still with
+        respect to S."""
         n, px, pu, pk, nkf, pT, pS = self._res_common(xyz, uv, kf_idx, kf_T, S32)
         g = torch.empty(7, dtype=torch.float64, device=self.device)
         H = torch.empty(28, dtype=torch.float64, device=self.device) if want_H else None
         K = pinhole_struct(cam8)
-        _check(self._lib.fl_reproj_residual_bwd(self._h, n, px, pu, pk, nkf, pT, pS, ctypes.byref(K),
-                                                float(delta), float(grad_scale), _ptr(g, torch.float64, "g", 8),
-                                                _ptr(H, torch.float64, "H", 8), self._stream(stream)),
-               "fl_reproj_residual_bwd")
+        name = "fl_reproj_residual_bwd_inv" if inverse else "fl_reproj_residual_bwd"
+        _check(getattr(self._lib, name)(self._h, n, px, pu, pk, nkf, pT, pS, ctypes.byref(K), float(delta),
+                                        float(grad_scale), _ptr(g, torch.float64, "g", 8),
+                                        _ptr(H, torch.float64, "H", 8), self._stream(stream)), name)
         return g, H
+
+    def sim3_inverse(self, S_in, S_out=None, S32=None, stream=None):
+        """S^-1 in float64 and its float32 form (device tensors)."""
+        if S_out is None:
+            S_out = torch.empty(13, dtype=torch.float64, device=self.device)
+        if S32 is None:
+            S32 = torch.empty(16, dtype=torch.float32, device=self.device)
+        _check(self._lib.fl_sim3_inverse(self._h, _ptr(S_in, torch.float64, "S_in", 8),
+                                         _ptr(S_out, torch.float64, "S_out", 8), _ptr(S32, torch.float32, "S32", 16),
+                                         self._stream(stream)), "fl_sim3_inverse")
+        return S_out, S32
 
     def sim3_exp_mul(self, xi, S_in, S_out=None, S32=None, stream=None):
         if S_out is None:

@@ -1234,7 +1234,32 @@ int fl_reproj_residual_bwd(fl_ctx* c, int32_t n, const float* xyz, const float* 
     a.g = g;
     a.H = H;
     a.grad_scale = grad_scale;
-    hipLaunchKernelGGL(residual_bwd_kernel, dim3(grid), dim3(kResBlock), 0, stream, a);
+    hipLaunchKernelGGL(residual_bwd_kernel<false>, dim3(grid), dim3(kResBlock), 0, stream, a);
+    FL_HIP(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_reproj_residual_bwd_inv(fl_ctx* c, int32_t n, const float* xyz, const float* uv, const int32_t* kf_idx,
+                               int32_t n_kf, const float* kf_T, const fl_sim3* S_inv, const fl_pinhole* K,
+                               float huber_delta, double grad_scale, double* g, double* H, hipStream_t stream) {
+    ResArgs a;
+    int grid = 1;
+    int rc = residual_args(c, n, xyz, uv, kf_idx, n_kf, kf_T, S_inv, K, huber_delta, a, grid);
+    if (rc) return rc;
+    if (!g) return fail(FL_EINVAL, "g must not be NULL");
+    if (!std::isfinite(grad_scale)) return fail(FL_EINVAL, "grad_scale must be finite");
+    a.g = g;
+    a.H = H;
+    a.grad_scale = grad_scale;
+    hipLaunchKernelGGL(residual_bwd_kernel<true>, dim3(grid), dim3(kResBlock), 0, stream, a);
+    FL_HIP(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_sim3_inverse(fl_ctx* c, const double* S_in, double* S_out, fl_sim3* S32_out, hipStream_t stream) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if (!S_in || (!S_out && !S32_out)) return fail(FL_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(sim3_inverse_kernel, dim3(1), dim3(64), 0, stream, S_in, S_out, S32_out);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }

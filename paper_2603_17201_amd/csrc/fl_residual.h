@@ -246,6 +246,11 @@ struct PairTerm {
     bool valid;
 };
 
+// INV: (A, tS) is the float32 form of S^-1 and the pair is a point of the
+// current side observed on the loop side, p = S^-1 X; its Jacobian is still
+// taken with respect to the left perturbation of S, under which
+// S^-1 <- S^-1 exp(-xi):  J = dpi/dq R_k (-A) [ -[X]x | I | X ].
+template <bool INV = false>
 __device__ __forceinline__ void pair_term(const float* A, const float* tS, const float* T, float fx, float fy,
                                           float cx, float cy, float x, float y, float z, float uo, float vo,
                                           float delta, bool need_J, PairTerm& o) {
@@ -290,14 +295,27 @@ __device__ __forceinline__ void pair_term(const float* A, const float* tS, const
         M[1][0] = 0.0f; M[1][1] = b1; M[1][2] = b2;
     }
     for (int r = 0; r < 2; ++r) {
-        const float m0 = M[r][0], m1 = M[r][1], m2 = M[r][2];
-        o.J[r][0] = p1 * m2 - p2 * m1;   // p x m: derivative along omega
-        o.J[r][1] = p2 * m0 - p0 * m2;
-        o.J[r][2] = p0 * m1 - p1 * m0;
+        float m0 = M[r][0], m1 = M[r][1], m2 = M[r][2];
+        float a0 = p0, a1 = p1, a2 = p2;   // the point the perturbation acts on
+        if (INV) {
+            // row of -M A, acting on X
+            const float b0 = -(m0 * A[0] + m1 * A[3] + m2 * A[6]);
+            const float b1 = -(m0 * A[1] + m1 * A[4] + m2 * A[7]);
+            const float b2 = -(m0 * A[2] + m1 * A[5] + m2 * A[8]);
+            m0 = b0;
+            m1 = b1;
+            m2 = b2;
+            a0 = x;
+            a1 = y;
+            a2 = z;
+        }
+        o.J[r][0] = a1 * m2 - a2 * m1;   // a x m: derivative along omega
+        o.J[r][1] = a2 * m0 - a0 * m2;
+        o.J[r][2] = a0 * m1 - a1 * m0;
         o.J[r][3] = m0;                  // upsilon
         o.J[r][4] = m1;
         o.J[r][5] = m2;
-        o.J[r][6] = m0 * p0 + m1 * p1 + m2 * p2;   // sigma
+        o.J[r][6] = m0 * a0 + m1 * a1 + m2 * a2;   // sigma
     }
 }
 
@@ -538,6 +556,7 @@ __global__ __launch_bounds__(kResBlock) void residual_fwd_kernel(ResArgs a) {
     }
 }
 
+template <bool INV>
 __global__ __launch_bounds__(kResBlock) void residual_bwd_kernel(ResArgs a) {
     __shared__ double s_red[(kResBlock / kWave) * 35];
     __shared__ double s_out[35];
@@ -551,7 +570,7 @@ __global__ __launch_bounds__(kResBlock) void residual_bwd_kernel(ResArgs a) {
         const float* T;
         if (!load_pair(a, i, x, y, z, uo, vo, T)) continue;
         PairTerm t;
-        pair_term(S.sR, S.t, T, a.fx, a.fy, a.cx, a.cy, x, y, z, uo, vo, a.delta, true, t);
+        pair_term<INV>(S.sR, S.t, T, a.fx, a.fy, a.cx, a.cy, x, y, z, uo, vo, a.delta, true, t);
         if (t.valid) accumulate(t, acc);
     }
     block_reduce<35>(acc, s_red, s_out);
@@ -571,6 +590,21 @@ __global__ void sim3_exp_mul_kernel(const double* __restrict__ xi, const double*
     const Sim3d S = sim3_mul(E, sim3_load(S_in));
     sim3_store(S, S_out);
     if (S32) sim3_to_f32(S, S32);
+}
+
+// S_inv = S^-1 = (R^T, -R^T t / s, 1 / s) in float64, and its float32 form.
+__global__ void sim3_inverse_kernel(const double* __restrict__ S_in, double* __restrict__ S_out,
+                                    fl_sim3* __restrict__ S32) {
+    if (threadIdx.x != 0) return;
+    const Sim3d S = sim3_load(S_in);
+    Sim3d V;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V.R[3 * i + j] = S.R[3 * j + i];
+    V.s = 1.0 / S.s;
+    for (int i = 0; i < 3; ++i)
+        V.t[i] = -(V.R[3 * i] * S.t[0] + V.R[3 * i + 1] * S.t[1] + V.R[3 * i + 2] * S.t[2]) * V.s;
+    if (S_out) sim3_store(V, S_out);
+    if (S32) sim3_to_f32(V, S32);
 }
 
 __global__ void gn_step_kernel(const double* __restrict__ g, const double* __restrict__ H, double lambda,

@@ -137,6 +137,7 @@ def test_null_context_is_rejected(lib):
     passes = (_abi.Pass * 2)(_abi.Pass(None, P, o), _abi.Pass(None, P, o))
     rc = lib.fl_search_fuse_passes(None, ctypes.byref(b), 2, passes, None)
     assert rc == _abi.FL_EINVAL
+    assert lib.fl_sim3_inverse(None, None, None, None, None) == _abi.FL_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -407,3 +407,61 @@ def test_robust_refinement_rejects_bad_arguments(ctx):
                 (5, 2.45, S, None, None, -1, 3.0, 0.0)]:
         with pytest.raises(fl.FlError):
             ctx.search_fuse_batched(b, ev.params, refine=ref)
+
+
+@pytest.fixture(scope="module")
+def bidir():
+    return synth.gen_bidir()
+
+
+def test_sim3_inverse_matches_oracle(ctx, bidir):
+    for S in (bidir["S0"], bidir["S_true"], sim3.exp(np.array([0.3, -0.2, 0.1, 1.0, -2.0, 0.5, 0.4]))):
+        S_inv, S32 = ctx.sim3_inverse(t(S))
+        exp = sim3.inverse(S)
+        assert np.max(np.abs(S_inv.cpu().numpy() - exp)) < 1e-14 * max(1.0, np.max(np.abs(exp)))
+        assert np.max(np.abs(S32.cpu().numpy() - sim3.to_f32_rows(exp))) < 1e-6
+
+
+def test_inverse_direction_matches_fp64(ctx, bidir):
+    """Points of the current side observed on the loop side through S^-1:
+    residuals, weights and loss from the forward call given S^-1's float32
+    form; g and H with respect to S from the inverse backward, against the
+    float64 oracle."""
+    xyz, uv, kf, T = bidir["bwd"]
+    S0, cam = bidir["S0"], bidir["cam"]
+    _, S32_inv = ctx.sim3_inverse(t(S0))
+    r, w, loss = ctx.residual_fwd(t(xyz), t(uv), t(kf), t(T), S32_inv, cam, 2.45)
+    r64, w64, L64 = R.forward_inv(S0, xyz, uv, kf, T.astype(np.float64), cam, 2.45)
+    assert rel(r.cpu().numpy(), r64) < REL
+    assert rel(w.cpu().numpy(), w64) < REL
+    assert abs(loss.item() - L64) / L64 < REL
+    g, H = ctx.residual_bwd(t(xyz), t(uv), t(kf), t(T), S32_inv, cam, 2.45, inverse=True)
+    g64, H64, _ = R.grad_hess_inv(S0, xyz, uv, kf, T.astype(np.float64), cam, 2.45)
+    assert rel(g.cpu().numpy(), g64) < REL
+    assert rel(H.cpu().numpy(), R.H_upper(H64)) < REL
+
+
+def test_two_sided_gauss_newton_matches_oracle(ctx, bidir):
+    """Ten Gauss-Newton steps on both directions through the C ABI: two
+    backward calls, their sums added, one step, the inverse refreshed."""
+    fwd, bwd, cam = bidir["fwd"], bidir["bwd"], bidir["cam"]
+    S = t(bidir["S0"].copy())
+    S32 = torch.empty(16, dtype=torch.float32, device=dev())
+    S32_inv = torch.empty(16, dtype=torch.float32, device=dev())
+    ctx.sim3_exp_mul(t(np.zeros(7)), S.clone(), S, S32)
+    Xf, Uf, Kf, Tf = (t(a) for a in fwd)
+    Xb, Ub, Kb, Tb = (t(a) for a in bwd)
+    for _ in range(10):
+        ctx.sim3_inverse(S, None, S32_inv)
+        g1, H1 = ctx.residual_bwd(Xf, Uf, Kf, Tf, S32, cam, 2.45)
+        g2, H2 = ctx.residual_bwd(Xb, Ub, Kb, Tb, S32_inv, cam, 2.45, inverse=True)
+        ctx.gn_step(g1 + g2, H1 + H2, S, S32)
+    f64 = fwd[:3] + (fwd[3].astype(np.float64),)
+    b64 = bwd[:3] + (bwd[3].astype(np.float64),)
+    S_ref = R.gauss_newton_bidir(bidir["S0"], f64, b64, cam, 2.45, iters=10)
+    S_gpu = S.cpu().numpy()
+    err = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(S_ref))))
+    assert err < 1e-6, err
+    e_true = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(bidir["S_true"]))))
+    e_init = np.linalg.norm(sim3.log(sim3.compose(bidir["S0"], sim3.inverse(bidir["S_true"]))))
+    assert e_true < 0.1 * e_init
