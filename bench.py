@@ -562,6 +562,10 @@ class Bench:
         f = self.events_time(lambda: ctx.residual_fwd(xyz, uv, None, None, S32, d["cam"], d["huber_delta"]), 50, 5)
         bw = self.events_time(lambda: ctx.residual_bwd(xyz, uv, None, None, S32, d["cam"], d["huber_delta"]),
                               50, 5)
+        # the same pairs taken as the other direction (observed through S^-1)
+        S_inv32 = ctx.sim3_inverse(torch.from_numpy(S0).to(self.dev))[1]
+        bwi = self.events_time(lambda: ctx.residual_bwd(xyz, uv, None, None, S_inv32, d["cam"], d["huber_delta"],
+                                                        inverse=True), 50, 5)
         S0t = torch.from_numpy(S0).to(self.dev)
         xi = torch.zeros(7, dtype=torch.float64, device=self.dev, requires_grad=True)
 
@@ -571,9 +575,10 @@ class Bench:
         ab = self.events_time(fb, 20, 3)
         gc.enable()
         n = int(d["xyz"].shape[0])
-        log(f"residual: fwd {f * 1e3:.1f} us, bwd {bw * 1e3:.1f} us, autograd fwd+bwd {ab * 1e3:.1f} us")
-        return dict(n_pairs=n, fwd_us=f * 1e3, bwd_us=bw * 1e3, autograd_fwd_bwd_us=ab * 1e3,
-                    bwd_pairs_per_s=n / (bw * 1e-3))
+        log(f"residual: fwd {f * 1e3:.1f} us, bwd {bw * 1e3:.1f} us, inverse-direction bwd {bwi * 1e3:.1f} us, "
+            f"autograd fwd+bwd {ab * 1e3:.1f} us")
+        return dict(n_pairs=n, fwd_us=f * 1e3, bwd_us=bw * 1e3, bwd_inverse_direction_us=bwi * 1e3,
+                    autograd_fwd_bwd_us=ab * 1e3, bwd_pairs_per_s=n / (bw * 1e-3))
 
     def stream_events(self, n_events):
         """The stream of uneven loop events: each event resident, one graph
