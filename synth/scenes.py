@@ -568,6 +568,60 @@ def gen_bidir(seed: int = 505, n_fwd: int = 20000, n_bwd: int = 20000, n_views: 
                 huber_delta=2.45)
 
 
+def gen_pose_graph(n: int = 1000, seed: int = 606, covis: int = 3, n_loops: int = 8, noise_deg: float = 0.1,
+                   noise_m: float = 0.01, noise_scale: float = 0.001, drift: bool = True):
+    """An essential graph after a loop closure: n keyframes on a closed loop
+    of radius 5 m (world -> camera poses, scale 1), edges (i, i + d) for
+    d = 1..covis along the trajectory (spanning tree and covisibility), and
+    n_loops loop edges joining the trajectory's last keyframes to its first
+    ones.  Each edge measures M_ij = S_j S_i^-1 of the true poses, moved by
+    N(0, noise) in rotation (deg), translation (m) and log scale.  The start
+    chains the odometry edges (i, i + 1) from keyframe 0 with an extra drift
+    of 0.02 deg, 2 mm and 0.2% scale per step (the state before the loop is
+    corrected).  Keyframe 0 is fixed.  Returns dict(S_true [n,13],
+    S0 [n,13], edges int32 [E,2] (host), M [E,13], fixed bool [n])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S_true = []
+    for i in range(n):
+        a = 2 * np.pi * i / n
+        R = _rodrigues(np.array([0.0, 1.0, 0.0]), -a)            # facing along the loop
+        c = np.array([5.0 * np.cos(a), 0.1 * np.sin(3 * a), 5.0 * np.sin(a)])
+        S_true.append(_sim3(R, -R @ c, 1.0))
+    S_true = np.stack(S_true)
+
+    def inv(S):
+        R, t, sc = _split(S)
+        return _sim3(R.T, -(R.T @ t) / sc, 1.0 / sc)
+
+    def mul(A, B):
+        Ra, ta, sa = _split(A)
+        Rb, tb, sb = _split(B)
+        return _sim3(Ra @ Rb, sa * (Ra @ tb) + ta, sa * sb)
+
+    def noisy(S, deg, m, ls):
+        R, t, sc = _split(S)
+        Rn = _rodrigues(_unit(rng), np.deg2rad(abs(rng.normal(0.0, deg)))) if deg > 0 else np.eye(3)
+        return _sim3(Rn @ R, Rn @ t + rng.normal(0.0, m, 3), sc * float(np.exp(rng.normal(0.0, ls))))
+
+    edges = [(i, i + d) for d in range(1, covis + 1) for i in range(n - d)]
+    for k in range(n_loops):
+        edges.append((n - 1 - k, k))
+    edges = np.array(sorted(edges), np.int32)
+    M = np.stack([noisy(mul(S_true[j], inv(S_true[i])), noise_deg, noise_m, noise_scale) for i, j in edges])
+    # the start: odometry chained from keyframe 0, with drift
+    odo = {(int(i), int(j)): M[k] for k, (i, j) in enumerate(edges) if j == i + 1}
+    S0 = [S_true[0]]
+    for i in range(n - 1):
+        step = odo[(i, i + 1)]
+        if drift:
+            step = mul(_sim3(_rodrigues(np.array([0.0, 1.0, 0.0]), np.deg2rad(0.02)), np.array([0.002, 0.0, 0.0]),
+                             1.002), step)
+        S0.append(mul(step, S0[-1]))
+    fixed = np.zeros(n, bool)
+    fixed[0] = True
+    return dict(S_true=S_true, S0=np.stack(S0), edges=edges, M=M, fixed=fixed)
+
+
 def gen_c5_event(e: int, n_kf: Optional[int] = None, n_mp: Optional[int] = None) -> Event:
     """Event e of the 200-event stream (seed 5000 + e): n_kf ~ U{5..80},
     camera 752x480 or 512x512 with probability 1/2, keypoints U{300..2500}
