@@ -17,7 +17,8 @@ Secondary workloads (skipped with --quick): the uneven 60-keyframe event
 with sparse covisibility pairs, ten of them in one launch, the residual
 forward/backward on 50,000 pairs, the projection searches of loop verification
 (one keyframe; three keyframes in one launch; two searches of one keyframe in
-one launch) and a stream of uneven events.
+one launch), robust Sim3 refinement, essential-graph optimisation and a stream
+of uneven events.
 """
 from __future__ import annotations
 
@@ -549,6 +550,39 @@ class Bench:
                 f"{deg:.2e} deg, {m:.2e} m, {ls:.2e} log scale")
         return res
 
+    def essential_graph(self, steps):
+        """Essential-graph optimisation of a loop of 1,000 keyframes (about
+        3,000 odometry, covisibility and loop edges) from its drifted start:
+        10 outer steps, conjugate gradients to 1e-10."""
+        import synth
+        torch, ctx = self.torch, self.ctx
+        d = synth.gen_pose_graph(n=1000, seed=606)
+        S0 = torch.from_numpy(d["S0"]).to(self.dev)
+        S = S0.clone()
+        M = torch.from_numpy(d["M"]).to(self.dev)
+        out = {}
+
+        def run():
+            S.copy_(S0)
+            out["r"] = ctx.pose_graph_optimize(S, M, d["edges"], None, iters=10)
+        gc.collect()
+        gc.disable()
+        ms = self.events_time(run, max(3, steps // 5), 1)
+        gc.enable()
+        run()
+        cost, used = (x.cpu().numpy() for x in out["r"])
+        Sf = S.cpu().numpy()
+
+        def worst(A):
+            e = [sim3_error(a, b) for a, b in zip(A, d["S_true"])]
+            return dict(deg=max(x[0] for x in e), m=max(x[1] for x in e), log_scale=max(x[2] for x in e))
+        res = dict(n_nodes=int(S.shape[0]), n_edges=int(d["edges"].shape[0]), iters=10, ms_per_optimisation=ms,
+                   cost_start=float(cost[0]), cost_end=float(cost[-1]), cg_iterations=[int(u) for u in used],
+                   worst_node_error_start=worst(d["S0"]), worst_node_error_end=worst(Sf))
+        log(f"essential graph: {ms:.2f} ms for 10 steps ({res['n_nodes']} keyframes, {res['n_edges']} edges), cost "
+            f"{cost[0]:.3e} -> {cost[-1]:.3e}, CG iterations {res['cg_iterations']}")
+        return res
+
     def residual(self):
         import synth
         torch, fl, ctx = self.torch, self.fl, self.ctx
@@ -751,6 +785,7 @@ def main():
         secondary["residual_50k"] = bench.residual()
         secondary["projection_search"] = bench.projection_search(args.steps)
         secondary["robust_refinement"] = bench.robust_refinement(args.steps)
+        secondary["essential_graph"] = bench.essential_graph(args.steps)
         if args.stream_events > 0:
             secondary["stream"] = bench.stream_events(args.stream_events)
 

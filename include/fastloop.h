@@ -322,6 +322,41 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
                hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
+/* Essential-graph optimisation (loop correction, Sec. III-B; graph
+ * optimisation, Sec. IV-F).  Nodes are keyframe poses S_i (world -> camera
+ * Sim3s, 13 doubles each: R row-major, t, s); an edge (i, j) measures
+ * M_ij ~ S_j S_i^-1 and contributes e_ij = log(M_ij^-1 S_j S_i^-1) to
+ * F = sum e^T e.  Nodes move by left perturbations S_i <- exp(d_i) S_i; the
+ * Jacobians of e_ij are central differences (step fd_step) of the float64
+ * Sim3 algebra; each of `iters` steps solves (H + lambda diag H) d = -g over
+ * the free nodes by block-Jacobi preconditioned conjugate gradients (at most
+ * cg_iters, stopping when |r| <= cg_tol |g|).  Deterministic: every sum has
+ * a fixed order. */
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_edges;
+    double* S;              /* device [n_nodes][13] in: start, out: optimised */
+    const double* M;        /* device [n_edges][13] measured S_j S_i^-1 */
+    const int32_t* edges;   /* host [n_edges][2] (i, j), i != j */
+    const uint8_t* fixed;   /* host [n_nodes] nonzero: held; NULL: node 0 held */
+} fl_pose_graph;
+
+typedef struct {
+    int32_t iters;          /* outer steps, 0..1000 */
+    int32_t cg_iters;       /* 1..100000 */
+    double lambda;          /* >= 0 */
+    double cg_tol;          /* >= 0 */
+    double fd_step;         /* > 0; 0: 1e-5 */
+    double* cost;           /* device [iters + 1] (may be NULL): F before each step and after the last */
+    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each step */
+} fl_pgo_params;
+
+/* Errors: FL_EINVAL (NULL arrays, an edge outside the graph or joining a
+ * node to itself, bad parameters), FL_ERANGE (sizes), FL_ENOMEM. */
+int fl_pose_graph_optimize(fl_ctx* ctx, const fl_pose_graph* G /* host */, const fl_pgo_params* P /* host */,
+                           hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
 /* Tuning of the batched search kernel.  Any tuning gives identical
  * results; fl_autotune times the candidates on the given batch (the stream
  * is synchronised) and keeps the fastest in the context. */

@@ -62,6 +62,16 @@ class Pass(ctypes.Structure):
     _fields_ = [("kf_sim3", c_void_p), ("params", Params), ("out", FuseOut)]
 
 
+class PoseGraph(ctypes.Structure):
+    _fields_ = [("n_nodes", c_int32), ("n_edges", c_int32), ("S", c_void_p), ("M", c_void_p), ("edges", c_void_p),
+                ("fixed", c_void_p)]
+
+
+class PgoParams(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("cg_iters", c_int32), ("lam", c_double), ("cg_tol", c_double),
+                ("fd_step", c_double), ("cost", c_void_p), ("cg_used", c_void_p)]
+
+
 class Refine(ctypes.Structure):
     _fields_ = [("n_iters", c_int32), ("huber_delta", c_float), ("event_S", c_void_p),
                 ("event_S32", c_void_p), ("event_n_matched", c_void_p), ("n_rounds", c_int32),
@@ -104,6 +114,7 @@ SIGNATURES = [
     ("fl_reproj_residual_bwd_inv", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                              c_void_p, ctypes.POINTER(Pinhole), c_float, c_double, c_void_p,
                                              c_void_p, c_void_p]),
+    ("fl_pose_graph_optimize", c_int32, [c_void_p, ctypes.POINTER(PoseGraph), ctypes.POINTER(PgoParams), c_void_p]),
     ("fl_sim3_inverse", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fl_sim3_exp_mul", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fl_gn_step", c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),

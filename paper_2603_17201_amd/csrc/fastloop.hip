@@ -14,6 +14,7 @@
 
 #include "fastloop.h"
 #include "fl_internal.h"
+#include "fl_pgo.h"
 #include "fl_residual.h"
 #include "fl_search.h"
 
@@ -118,6 +119,7 @@ struct fl_ctx {
     DevBuf plain;               // plain-path workspace
     DevBuf res;                 // residual partials and done counter
     DevBuf part;                // refinement partial sums and their tags, zero when the epoch restarts
+    DevBuf pgo;                 // pose-graph tables and workspace
     Pinned pin[kPinRing];
     int pin_next = 0;
     Fence fence[kFences];
@@ -902,6 +904,7 @@ void fl_destroy(fl_ctx* c) {
     c->plain.release();
     c->res.release();
     c->part.release();
+    c->pgo.release();
     delete c;
 }
 
@@ -1252,6 +1255,102 @@ int fl_reproj_residual_bwd_inv(fl_ctx* c, int32_t n, const float* xyz, const flo
     a.H = H;
     a.grad_scale = grad_scale;
     hipLaunchKernelGGL(residual_bwd_kernel<true>, dim3(grid), dim3(kResBlock), 0, stream, a);
+    FL_HIP(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_params* P, hipStream_t stream) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if (!G || !P) return fail(FL_EINVAL, "graph or params is NULL");
+    const int N = G->n_nodes, E = G->n_edges;
+    if (N < 1 || E < 0) return fail(FL_EINVAL, "n_nodes must be >= 1 and n_edges >= 0");
+    if (N > (1 << 24) || E > (1 << 26)) return fail(FL_ERANGE, "graph too large (%d nodes, %d edges)", N, E);
+    if (!G->S || (E > 0 && (!G->M || !G->edges))) return fail(FL_EINVAL, "NULL graph array");
+    if (P->iters < 0 || P->iters > 1000) return fail(FL_ERANGE, "iters %d outside [0, 1000]", P->iters);
+    if (P->cg_iters < 1 || P->cg_iters > 100000) return fail(FL_ERANGE, "cg_iters %d outside [1, 100000]", P->cg_iters);
+    if (!(P->lambda >= 0.0) || !std::isfinite(P->lambda)) return fail(FL_EINVAL, "lambda must be finite and >= 0");
+    if (!(P->cg_tol >= 0.0) || !std::isfinite(P->cg_tol)) return fail(FL_EINVAL, "cg_tol must be finite and >= 0");
+    const double h = P->fd_step == 0.0 ? 1e-5 : P->fd_step;
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_EINVAL, "fd_step must be finite and > 0");
+    // incident edges of every node, in edge order (the gathers' fixed order)
+    std::vector<int32_t> tab((size_t)2 * E + (N + 1) + 2 * (size_t)E, 0);
+    int32_t* t_edges = tab.data();
+    int32_t* off = t_edges + 2 * (size_t)E;
+    int32_t* adj = off + (N + 1);
+    for (int k = 0; k < E; ++k) {
+        const int i = G->edges[2 * k], j = G->edges[2 * k + 1];
+        if (i < 0 || i >= N || j < 0 || j >= N || i == j)
+            return fail(FL_EINVAL, "edge %d joins %d and %d (n_nodes %d)", k, i, j, N);
+        t_edges[2 * k] = i;
+        t_edges[2 * k + 1] = j;
+        ++off[i + 1];
+        ++off[j + 1];
+    }
+    for (int n = 0; n < N; ++n) off[n + 1] += off[n];
+    {
+        std::vector<int32_t> fill(off, off + N);
+        for (int k = 0; k < E; ++k) {
+            adj[fill[t_edges[2 * k]]++] = 2 * k;
+            adj[fill[t_edges[2 * k + 1]]++] = 2 * k + 1;
+        }
+    }
+    const size_t tab_bytes = sizeof(int32_t) * tab.size();
+    size_t off_b = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off_b;
+        off_b = align_up(off_b + std::max<size_t>(bytes, 16), 256);
+        return o;
+    };
+    const size_t L_tab = take(tab_bytes);
+    const size_t L_fix = take((size_t)N);
+    const size_t L_e = take(sizeof(double) * 7 * (size_t)E);
+    const size_t L_J = take(sizeof(double) * 98 * (size_t)E);
+    const size_t L_u = take(sizeof(double) * 7 * (size_t)E);
+    const size_t L_vec = take(sizeof(double) * 6 * 7 * (size_t)N);
+    const size_t L_D = take(sizeof(double) * 49 * (size_t)N);
+    int rc = c->pgo.ensure(off_b);
+    if (rc) return rc;
+    char* base = (char*)c->pgo.p;
+    // tables and fixed flags through the pinned ring (node 0 held when no flags are given)
+    const size_t up = L_fix + (size_t)N;
+    Pinned* pin = nullptr;
+    rc = get_pinned(c, up, &pin);
+    if (rc) return rc;
+    memcpy(pin->p, tab.data(), tab_bytes);
+    uint8_t* fx = (uint8_t*)pin->p + L_fix;
+    for (int n = 0; n < N; ++n) fx[n] = G->fixed ? (G->fixed[n] != 0) : (n == 0);
+    pin->used = up;
+    FL_HIP(hipMemcpyAsync(base, pin->p, up, hipMemcpyHostToDevice, stream));
+    rc = note_fetch(c, *pin, stream);
+    if (rc) return rc;
+    PgoArgs a{};
+    a.n_nodes = N;
+    a.n_edges = E;
+    a.S = G->S;
+    a.M = G->M;
+    a.edges = (const int32_t*)(base + L_tab);
+    a.adj_off = a.edges + 2 * (size_t)E;
+    a.adj = a.adj_off + (N + 1);
+    a.fixed = (const uint8_t*)(base + L_fix);
+    a.fd_step = h;
+    a.lambda = P->lambda;
+    a.cg_iters = P->cg_iters;
+    a.cg_tol = P->cg_tol;
+    a.e = (double*)(base + L_e);
+    a.J = (double*)(base + L_J);
+    a.u = (double*)(base + L_u);
+    a.vec = (double*)(base + L_vec);
+    a.Dfac = (double*)(base + L_D);
+    a.cost = P->cost;
+    a.cg_used = P->cg_used;
+    const int jac_grid = std::max(1, (int)((7 * (int64_t)E + kPgoJacBlock - 1) / kPgoJacBlock));
+    for (int it = 0; it < P->iters; ++it) {
+        a.step = it;
+        if (E > 0) hipLaunchKernelGGL(pgo_jacobian_kernel, dim3(jac_grid), dim3(kPgoJacBlock), 0, stream, a);
+        hipLaunchKernelGGL(pgo_solve_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);
+    }
+    a.step = P->iters;
+    if (P->cost) hipLaunchKernelGGL(pgo_cost_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }

@@ -69,25 +69,28 @@ __device__ __forceinline__ void sigma_series(double sig, double* I, double& es) 
     }
 }
 
-// exp of a tangent xi = (omega, upsilon, sigma):  R = exp([omega]x),
-// s = e^sigma, t = V upsilon with V = integral_0^1 e^{sigma tau} exp(tau [omega]x) d tau
-// = c0 I + c1 W + c2 W^2 (closed form; series for small rotation angles).
-__device__ inline Sim3d sim3_exp(const double* xi) {
-    const double w0 = xi[0], w1 = xi[1], w2 = xi[2];
-    const double sig = xi[6];
+// Coefficients of the exponential of xi = (omega, upsilon, sigma):
+// R = I + a W + b W^2 with W = [omega]x, s = e^sigma, and
+// V = c0 I + c1 W + c2 W^2 = integral_0^1 e^{sigma tau} exp(tau W) d tau
+// (closed form; series for small rotation angles), t = V upsilon.
+struct ExpCoef {
+    double a, b, c0, c1, c2, es;
+};
+
+__device__ inline ExpCoef sim3_exp_coef(double w0, double w1, double w2, double sig) {
     const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
     const bool small = th2 < 1e-4;   // angle below 1e-2: the series need only th^2
     const double th = small ? 0.0 : sqrt(th2);
-    double a, b;
+    ExpCoef k;
     if (small) {
         // sin(th)/th and (1 - cos(th))/th^2 by their Taylor series: the next
         // terms are below th^8/9! < 3e-22 here
         const double t4 = th2 * th2;
-        a = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t4 * th2 * (1.0 / 5040.0);
-        b = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t4 * th2 * (1.0 / 40320.0);
+        k.a = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t4 * th2 * (1.0 / 5040.0);
+        k.b = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t4 * th2 * (1.0 / 40320.0);
     } else {
-        a = sin(th) / th;
-        b = (1.0 - cos(th)) / th2;
+        k.a = sin(th) / th;
+        k.b = (1.0 - cos(th)) / th2;
     }
     // I_n(sigma) for n = 0..6 and e^sigma = sum_k sigma^k / k! share one series
     double I[7];
@@ -102,12 +105,12 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
     } else if (fabs(sig) < 2.0) {
         double term = 1.0, e = 0.0;
         for (int n = 0; n < 7; ++n) I[n] = 0.0;
-        for (int k = 0; k < 60; ++k) {
+        for (int kk = 0; kk < 60; ++kk) {
             e += term;
 #pragma unroll
-            for (int n = 0; n < 7; ++n) I[n] += term * kRecip.v[n + k];
+            for (int n = 0; n < 7; ++n) I[n] += term * kRecip.v[n + kk];
             if (fabs(term) < 1e-18 * e) break;
-            term *= sig * kRecip.v[k];
+            term *= sig * kRecip.v[kk];
         }
         es = e;
     } else {
@@ -115,31 +118,101 @@ __device__ inline Sim3d sim3_exp(const double* xi) {
         I[0] = expm1(sig) / sig;
         for (int m = 1; m < 7; ++m) I[m] = (es - (double)m * I[m - 1]) / sig;
     }
-    const double c0 = I[0];
-    double c1, c2;
+    k.es = es;
+    k.c0 = I[0];
     if (small) {
-        c1 = I[1] - th2 * (1.0 / 6.0) * I[3] + th2 * th2 * (1.0 / 120.0) * I[5];
-        c2 = 0.5 * I[2] - th2 * (1.0 / 24.0) * I[4] + th2 * th2 * (1.0 / 720.0) * I[6];
+        k.c1 = I[1] - th2 * (1.0 / 6.0) * I[3] + th2 * th2 * (1.0 / 120.0) * I[5];
+        k.c2 = 0.5 * I[2] - th2 * (1.0 / 24.0) * I[4] + th2 * th2 * (1.0 / 720.0) * I[6];
     } else {
         const double den = sig * sig + th2;
-        c1 = (es * (sig * sin(th) - th * cos(th)) + th) / (th * den);
-        c2 = (c0 - (es * (sig * cos(th) + th * sin(th)) - sig) / den) / th2;
+        k.c1 = (es * (sig * sin(th) - th * cos(th)) + th) / (th * den);
+        k.c2 = (k.c0 - (es * (sig * cos(th) + th * sin(th)) - sig) / den) / th2;
     }
-    const double W[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
-    double W2[9];
+    return k;
+}
+
+__device__ inline void hat_sq(double w0, double w1, double w2, double* W, double* W2) {
+    W[0] = 0.0; W[1] = -w2; W[2] = w1;
+    W[3] = w2; W[4] = 0.0; W[5] = -w0;
+    W[6] = -w1; W[7] = w0; W[8] = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             W2[3 * i + j] = W[3 * i] * W[j] + W[3 * i + 1] * W[3 + j] + W[3 * i + 2] * W[6 + j];
+}
+
+// exp of a tangent xi = (omega, upsilon, sigma)
+__device__ inline Sim3d sim3_exp(const double* xi) {
+    const ExpCoef k = sim3_exp_coef(xi[0], xi[1], xi[2], xi[6]);
+    double W[9], W2[9];
+    hat_sq(xi[0], xi[1], xi[2], W, W2);
     Sim3d S;
     double V[9];
     for (int i = 0; i < 9; ++i) {
         const double I = (i % 4 == 0) ? 1.0 : 0.0;
-        S.R[i] = I + a * W[i] + b * W2[i];
-        V[i] = c0 * I + c1 * W[i] + c2 * W2[i];
+        S.R[i] = I + k.a * W[i] + k.b * W2[i];
+        V[i] = k.c0 * I + k.c1 * W[i] + k.c2 * W2[i];
     }
     for (int i = 0; i < 3; ++i) S.t[i] = V[3 * i] * xi[3] + V[3 * i + 1] * xi[4] + V[3 * i + 2] * xi[5];
-    S.s = es;
+    S.s = k.es;
     return S;
+}
+
+// log of a Sim3: omega from R (axis-angle, atan2 of the skew part's norm and
+// the trace), sigma = ln s, upsilon solving V upsilon = t (Cramer's rule).
+__device__ inline void sim3_log(const Sim3d& S, double* xi) {
+    const double* R = S.R;
+    const double v0 = 0.5 * (R[7] - R[5]), v1 = 0.5 * (R[2] - R[6]), v2 = 0.5 * (R[3] - R[1]);
+    const double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    const double sn = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    const double th = atan2(sn, c);
+    double w0, w1, w2;
+    if (sn > 1e-7 || c > 0.0) {
+        // omega = th / sin(th) v; the series 1 + th^2/6 + 7 th^4/360 below 1e-4
+        const double f = th < 1e-4 ? 1.0 + th * th * (1.0 / 6.0) + 7.0 * th * th * th * th / 360.0 : th / sn;
+        w0 = f * v0;
+        w1 = f * v1;
+        w2 = f * v2;
+    } else {
+        // th near pi: the axis from the largest diagonal entry of (R + I) / 2
+        int m = 0;
+        if (R[4] > R[0]) m = 1;
+        if (R[8] > R[4 * m]) m = 2;
+        double ax[3];
+        ax[m] = sqrt(fmax(0.0, 0.5 * (R[4 * m] + 1.0)));
+        for (int j = 0; j < 3; ++j)
+            if (j != m) ax[j] = 0.5 * (R[3 * m + j] + R[3 * j + m]) / (2.0 * ax[m]);
+        w0 = th * ax[0];
+        w1 = th * ax[1];
+        w2 = th * ax[2];
+    }
+    const double sig = log(S.s);
+    const ExpCoef k = sim3_exp_coef(w0, w1, w2, sig);
+    double W[9], W2[9], V[9];
+    hat_sq(w0, w1, w2, W, W2);
+    for (int i = 0; i < 9; ++i) V[i] = k.c0 * ((i % 4 == 0) ? 1.0 : 0.0) + k.c1 * W[i] + k.c2 * W2[i];
+    const double A0 = V[4] * V[8] - V[5] * V[7], A1 = V[5] * V[6] - V[3] * V[8], A2 = V[3] * V[7] - V[4] * V[6];
+    const double det = V[0] * A0 + V[1] * A1 + V[2] * A2;
+    const double id = 1.0 / det;
+    const double* t = S.t;
+    // upsilon = V^-1 t = adj(V) t / det(V)
+    xi[3] = (A0 * t[0] + (V[2] * V[7] - V[1] * V[8]) * t[1] + (V[1] * V[5] - V[2] * V[4]) * t[2]) * id;
+    xi[4] = (A1 * t[0] + (V[0] * V[8] - V[2] * V[6]) * t[1] + (V[2] * V[3] - V[0] * V[5]) * t[2]) * id;
+    xi[5] = (A2 * t[0] + (V[1] * V[6] - V[0] * V[7]) * t[1] + (V[0] * V[4] - V[1] * V[3]) * t[2]) * id;
+    xi[0] = w0;
+    xi[1] = w1;
+    xi[2] = w2;
+    xi[6] = sig;
+}
+
+// S^-1 = (R^T, -R^T t / s, 1 / s)
+__device__ inline Sim3d sim3_inv(const Sim3d& S) {
+    Sim3d V;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V.R[3 * i + j] = S.R[3 * j + i];
+    V.s = 1.0 / S.s;
+    for (int i = 0; i < 3; ++i)
+        V.t[i] = -(V.R[3 * i] * S.t[0] + V.R[3 * i + 1] * S.t[1] + V.R[3 * i + 2] * S.t[2]) * V.s;
+    return V;
 }
 
 // A o B  (X -> A(B(X)))
@@ -596,13 +669,7 @@ __global__ void sim3_exp_mul_kernel(const double* __restrict__ xi, const double*
 __global__ void sim3_inverse_kernel(const double* __restrict__ S_in, double* __restrict__ S_out,
                                     fl_sim3* __restrict__ S32) {
     if (threadIdx.x != 0) return;
-    const Sim3d S = sim3_load(S_in);
-    Sim3d V;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) V.R[3 * i + j] = S.R[3 * j + i];
-    V.s = 1.0 / S.s;
-    for (int i = 0; i < 3; ++i)
-        V.t[i] = -(V.R[3 * i] * S.t[0] + V.R[3 * i + 1] * S.t[1] + V.R[3 * i + 2] * S.t[2]) * V.s;
+    const Sim3d V = sim3_inv(sim3_load(S_in));
     if (S_out) sim3_store(V, S_out);
     if (S32) sim3_to_f32(V, S32);
 }

@@ -45,6 +45,8 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.FuseOut) == 40
     assert ctypes.sizeof(_abi.Refine) == 48
     assert ctypes.sizeof(_abi.Pass) == 80
+    assert ctypes.sizeof(_abi.PoseGraph) == 40
+    assert ctypes.sizeof(_abi.PgoParams) == 48
 
 
 def _batch(n_kf=2, n_mp=10, n_kp=(5, 7), dense=True):
@@ -138,6 +140,7 @@ def test_null_context_is_rejected(lib):
     rc = lib.fl_search_fuse_passes(None, ctypes.byref(b), 2, passes, None)
     assert rc == _abi.FL_EINVAL
     assert lib.fl_sim3_inverse(None, None, None, None, None) == _abi.FL_EINVAL
+    assert lib.fl_pose_graph_optimize(None, None, None, None) == _abi.FL_EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):
