@@ -331,7 +331,11 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
  * Sim3 algebra; each of `iters` steps solves (H + lambda diag H) d = -g over
  * the free nodes by block-Jacobi preconditioned conjugate gradients (at most
  * cg_iters, stopping when |r| <= cg_tol |g|).  Deterministic: every sum has
- * a fixed order. */
+ * a fixed order.  The solve runs one workgroup per compute unit, all
+ * resident together and synchronised by a grid barrier; other work on the
+ * device at the same time can keep them from being resident, and a barrier
+ * wait that runs past its bound reports the step as failed (cg_used = -1,
+ * the poses of that step unchanged) instead of blocking. */
 typedef struct {
     int32_t n_nodes;
     int32_t n_edges;
@@ -348,7 +352,7 @@ typedef struct {
     double cg_tol;          /* >= 0 */
     double fd_step;         /* > 0; 0: 1e-5 */
     double* cost;           /* device [iters + 1] (may be NULL): F before each step and after the last */
-    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each step */
+    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each step, -1: failed */
 } fl_pgo_params;
 
 /* Errors: FL_EINVAL (NULL arrays, an edge outside the graph or joining a

@@ -1308,6 +1308,12 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     const size_t L_u = take(sizeof(double) * 7 * (size_t)E);
     const size_t L_vec = take(sizeof(double) * 6 * 7 * (size_t)N);
     const size_t L_D = take(sizeof(double) * 49 * (size_t)N);
+    // co-resident solve workgroups: enough threads for every edge and node,
+    // at most one per CU (each grid barrier costs every workgroup a fence)
+    const int solve_grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(c->n_cu, (std::max(E, N) + (int64_t)kPgoBlock - 1) / kPgoBlock));
+    const size_t L_bar = take(sizeof(uint32_t));
+    const size_t L_red = take(sizeof(double) * 2 * 4 * (size_t)solve_grid);
     int rc = c->pgo.ensure(off_b);
     if (rc) return rc;
     char* base = (char*)c->pgo.p;
@@ -1341,13 +1347,16 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     a.u = (double*)(base + L_u);
     a.vec = (double*)(base + L_vec);
     a.Dfac = (double*)(base + L_D);
+    a.bar = (uint32_t*)(base + L_bar);
+    a.red = (double*)(base + L_red);
     a.cost = P->cost;
     a.cg_used = P->cg_used;
     const int jac_grid = std::max(1, (int)((7 * (int64_t)E + kPgoJacBlock - 1) / kPgoJacBlock));
     for (int it = 0; it < P->iters; ++it) {
         a.step = it;
         if (E > 0) hipLaunchKernelGGL(pgo_jacobian_kernel, dim3(jac_grid), dim3(kPgoJacBlock), 0, stream, a);
-        hipLaunchKernelGGL(pgo_solve_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);
+        FL_HIP(hipMemsetAsync(a.bar, 0, sizeof(uint32_t), stream));
+        hipLaunchKernelGGL(pgo_solve_kernel, dim3(solve_grid), dim3(kPgoBlock), 0, stream, a);
     }
     a.step = P->iters;
     if (P->cost) hipLaunchKernelGGL(pgo_cost_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);

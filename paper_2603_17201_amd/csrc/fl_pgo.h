@@ -10,10 +10,11 @@
 // conjugate gradients.
 //
 // Per outer step two kernels run: pgo_jacobian_kernel over (edge, column)
-// items on every CU, then pgo_solve_kernel, one workgroup that gathers g and
-// the diagonal blocks per node over its incident edges (fixed order, no
-// floating-point atomics), runs the conjugate gradients with fixed-order
-// float64 reductions and updates the nodes.
+// items on every CU, then pgo_solve_kernel, one co-resident workgroup per CU
+// synchronised by a grid barrier, which gathers g and the diagonal blocks per
+// node over its incident edges (fixed order, no floating-point atomics), runs
+// the conjugate gradients with fixed-order float64 reductions and updates
+// the nodes.
 
 #pragma once
 
@@ -21,7 +22,7 @@
 
 namespace fl {
 
-constexpr int kPgoBlock = 1024;     // threads of the solve workgroup
+constexpr int kPgoBlock = 256;      // threads of a solve workgroup (one per CU, all co-resident)
 constexpr int kPgoJacBlock = 256;   // threads of a Jacobian workgroup
 
 struct PgoArgs {
@@ -43,6 +44,8 @@ struct PgoArgs {
     double* u;                  // [n_edges][7] conjugate-gradient edge products
     double* vec;                // [6][n_nodes][7]: g, x, r, z, p, q
     double* Dfac;               // [n_nodes][49] LDL^T factors of the preconditioner blocks
+    uint32_t* bar;              // grid-barrier counter, zero at launch
+    double* red;                // [2][gridDim][4] reduction rows
     // outputs (may be null)
     double* cost;               // [iters + 1]
     int32_t* cg_used;           // [iters]
@@ -138,9 +141,60 @@ __device__ inline void ldl7_solve(const double* F, const double* b, double* x) {
     }
 }
 
+// Grid-wide barrier of the solve kernel's co-resident workgroups: a
+// counter that every workgroup increments once per barrier (zeroed before
+// the launch), with device-scope release and acquire around it so that the
+// vectors written before it are visible on every XCD after it.  The wait is
+// bounded: on a timeout the kernel reports failure instead of hanging.
+__device__ inline bool pgo_grid_sync(uint32_t* bar, uint32_t target) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(bar, 1u);
+        int ok = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpinLimit) {
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Fixed-order grid sum of up to 4 values: each workgroup's block sums go to
+// its row of red[buf], then every workgroup adds the rows in workgroup order
+// (all of them end with the same bits).  Consecutive reductions alternate
+// between two row buffers: a buffer is written again only after the barrier
+// that follows every workgroup's reading of it.
+template <int NV>
+__device__ inline bool pgo_grid_sum(double* v, double* red, int buf, uint32_t* bar, uint32_t& seq, double* s_w) {
+    double tot[NV];
+    for (int i = 0; i < NV; ++i) tot[i] = pgo_sum(v[i], s_w);
+    const int G = gridDim.x;
+    double* rows = red + (size_t)buf * 4 * G;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NV; ++i) rows[4 * blockIdx.x + i] = tot[i];
+    if (!pgo_grid_sync(bar, ++seq * (uint32_t)G)) return false;
+    for (int i = 0; i < NV; ++i) {
+        double sum = 0.0;
+        for (int w = 0; w < G; ++w) sum += rows[4 * w + i];
+        v[i] = sum;
+    }
+    return true;
+}
+
+// One outer step after the Jacobians: cost, g and the preconditioner blocks
+// node by node, the conjugate gradients, the node update.  Every workgroup
+// of the grid takes part; nodes and edges are spread over all threads.
 __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
     __shared__ double s_w[kPgoBlock / kWave];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x, gnt = gridDim.x * blockDim.x;
     const int N = a.n_nodes, E = a.n_edges;
     const int64_t V = 7 * (int64_t)N;
     double* g = a.vec;
@@ -149,17 +203,15 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
     double* z = a.vec + 3 * V;
     double* p = a.vec + 4 * V;
     double* q = a.vec + 5 * V;
+    uint32_t seq = 0;
+    int rb = 0;   // row buffer of the next reduction
+    bool ok = true;
 
-    // cost of the current poses
-    double part = 0.0;
-    for (int k = tid; k < E; k += nt)
-        for (int c = 0; c < 7; ++c) part = fma(a.e[7 * (int64_t)k + c], a.e[7 * (int64_t)k + c], part);
-    const double F = pgo_sum(part, s_w);
-    if (tid == 0 && a.cost) a.cost[a.step] = F;
-
-    // g and the preconditioner blocks, node by node over incident edges
-    double gg = 0.0;
-    for (int n = tid; n < N; n += nt) {
+    // cost, g, preconditioner blocks, r = -g, z = M^-1 r, p = z
+    double red3[3] = {0.0, 0.0, 0.0};   // F, |g|^2, r.z
+    for (int k = gtid; k < E; k += gnt)
+        for (int c = 0; c < 7; ++c) red3[0] = fma(a.e[7 * (int64_t)k + c], a.e[7 * (int64_t)k + c], red3[0]);
+    for (int n = gtid; n < N; n += gnt) {
         double gn[7] = {0, 0, 0, 0, 0, 0, 0};
         double D[49];
         for (int t = 0; t < 49; ++t) D[t] = 0.0;
@@ -188,46 +240,60 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
             for (int c = 0; c < 7; ++c) D[8 * c] = 1.0;
         }
         for (int t = 0; t < 49; ++t) a.Dfac[49 * (int64_t)n + t] = D[t];
+        double rn[7], zn[7];
+        for (int c = 0; c < 7; ++c) rn[c] = -gn[c];
+        ldl7_solve(D, rn, zn);
         for (int c = 0; c < 7; ++c) {
             g[7 * n + c] = gn[c];
             x[7 * n + c] = 0.0;
-            r[7 * n + c] = -gn[c];
-            gg = fma(gn[c], gn[c], gg);
-        }
-        double zn[7];
-        ldl7_solve(D, r + 7 * n, zn);
-        for (int c = 0; c < 7; ++c) {
+            r[7 * n + c] = rn[c];
             z[7 * n + c] = zn[c];
             p[7 * n + c] = zn[c];
+            red3[1] = fma(gn[c], gn[c], red3[1]);
+            red3[2] = fma(rn[c], zn[c], red3[2]);
         }
     }
-    const double gnorm2 = pgo_sum(gg, s_w);
-    double rz = 0.0;
-    for (int64_t v = tid; v < V; v += nt) rz = fma(r[v], z[v], rz);
-    rz = pgo_sum(rz, s_w);
+    ok = pgo_grid_sum<3>(red3, a.red, rb, a.bar, seq, s_w);
+    rb ^= 1;
+    if (gtid == 0 && a.cost) a.cost[a.step] = red3[0];
+    const double gnorm2 = red3[1];
+    double rz = red3[2];
 
-    // conjugate gradients on H x = -g over the free nodes (fixed nodes keep
-    // p = r = 0)
+    // Conjugate gradients on H x = -g over the free nodes (fixed nodes keep
+    // p = r = z = 0).  The direction update p = z + beta p of an iteration is
+    // folded into the next: its edge products use z + beta p directly, and
+    // each node's p is rewritten in the node phase that follows.
     int used = 0;
+    double beta = 0.0;
     const double stop2 = a.cg_tol * a.cg_tol * gnorm2;
-    for (int it = 0; it < a.cg_iters && gnorm2 > 0.0; ++it) {
-        // u_k = J_i p_i + J_j p_j
-        for (int k = tid; k < E; k += nt) {
+    for (int it = 0; ok && it < a.cg_iters && gnorm2 > 0.0; ++it) {
+        // u_k = J_i p'_i + J_j p'_j with p' = z + beta p (p' = p at it = 0)
+        for (int k = gtid; k < E; k += gnt) {
             const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
             const double* Ji = a.J + 98 * (int64_t)k;
             const double* Jj = Ji + 49;
+            double pi[7], pj[7];
+            for (int c = 0; c < 7; ++c) {
+                pi[c] = it ? fma(beta, p[7 * i + c], z[7 * i + c]) : p[7 * i + c];
+                pj[c] = it ? fma(beta, p[7 * j + c], z[7 * j + c]) : p[7 * j + c];
+            }
             for (int rr = 0; rr < 7; ++rr) {
                 double s = 0.0;
-                for (int c = 0; c < 7; ++c) s = fma(Ji[7 * rr + c], p[7 * i + c], s);
-                for (int c = 0; c < 7; ++c) s = fma(Jj[7 * rr + c], p[7 * j + c], s);
+                for (int c = 0; c < 7; ++c) s = fma(Ji[7 * rr + c], pi[c], s);
+                for (int c = 0; c < 7; ++c) s = fma(Jj[7 * rr + c], pj[c], s);
                 a.u[7 * (int64_t)k + rr] = s;
             }
         }
-        __syncthreads();
-        // q_n = sum over incident edges of J^T u (+ lambda diag H p via the blocks)
-        double pq = 0.0;
-        for (int n = tid; n < N; n += nt) {
-            double qn[7] = {0, 0, 0, 0, 0, 0, 0};
+        ok = pgo_grid_sync(a.bar, ++seq * (uint32_t)gridDim.x);
+        if (!ok) break;
+        // p_n = p'_n; q_n = sum over incident edges of J^T u (+ lambda diag H p)
+        double pq[1] = {0.0};
+        for (int n = gtid; n < N; n += gnt) {
+            double pn[7], qn[7] = {0, 0, 0, 0, 0, 0, 0};
+            for (int c = 0; c < 7; ++c) {
+                pn[c] = it ? fma(beta, p[7 * n + c], z[7 * n + c]) : p[7 * n + c];
+                p[7 * n + c] = pn[c];
+            }
             if (!a.fixed[n]) {
                 double dg[7] = {0, 0, 0, 0, 0, 0, 0};
                 for (int t = a.adj_off[n]; t < a.adj_off[n + 1]; ++t) {
@@ -239,43 +305,45 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
                             for (int rr = 0; rr < 7; ++rr) dg[c] = fma(Jk[7 * rr + c], Jk[7 * rr + c], dg[c]);
                 }
                 if (a.lambda > 0.0)
-                    for (int c = 0; c < 7; ++c) qn[c] = fma(a.lambda * dg[c], p[7 * n + c], qn[c]);
+                    for (int c = 0; c < 7; ++c) qn[c] = fma(a.lambda * dg[c], pn[c], qn[c]);
             }
             for (int c = 0; c < 7; ++c) {
                 q[7 * n + c] = qn[c];
-                pq = fma(p[7 * n + c], qn[c], pq);
+                pq[0] = fma(pn[c], qn[c], pq[0]);
             }
         }
-        pq = pgo_sum(pq, s_w);
-        if (!(pq > 0.0)) break;
-        const double alpha = rz / pq;
-        double rr2 = 0.0, rz_new = 0.0;
-        for (int n = tid; n < N; n += nt) {
+        ok = pgo_grid_sum<1>(pq, a.red, rb, a.bar, seq, s_w);
+        rb ^= 1;
+        if (!ok || !(pq[0] > 0.0)) break;
+        const double alpha = rz / pq[0];
+        double red2[2] = {0.0, 0.0};   // |r|^2, r.z
+        for (int n = gtid; n < N; n += gnt) {
+            double rn[7], zn[7];
             for (int c = 0; c < 7; ++c) {
                 x[7 * n + c] = fma(alpha, p[7 * n + c], x[7 * n + c]);
-                r[7 * n + c] = fma(-alpha, q[7 * n + c], r[7 * n + c]);
-                rr2 = fma(r[7 * n + c], r[7 * n + c], rr2);
+                rn[c] = fma(-alpha, q[7 * n + c], r[7 * n + c]);
+                r[7 * n + c] = rn[c];
+                red2[0] = fma(rn[c], rn[c], red2[0]);
             }
-            double zn[7];
-            ldl7_solve(a.Dfac + 49 * (int64_t)n, r + 7 * n, zn);
+            ldl7_solve(a.Dfac + 49 * (int64_t)n, rn, zn);
             for (int c = 0; c < 7; ++c) {
-                z[7 * n + c] = a.fixed[n] ? 0.0 : zn[c];
-                rz_new = fma(r[7 * n + c], z[7 * n + c], rz_new);
+                const double zc = a.fixed[n] ? 0.0 : zn[c];
+                z[7 * n + c] = zc;
+                red2[1] = fma(rn[c], zc, red2[1]);
             }
         }
-        rr2 = pgo_sum(rr2, s_w);
-        rz_new = pgo_sum(rz_new, s_w);
+        ok = pgo_grid_sum<2>(red2, a.red, rb, a.bar, seq, s_w);
+        rb ^= 1;
+        if (!ok) break;
         used = it + 1;
-        if (rr2 <= stop2) break;
-        const double beta = rz_new / rz;
-        rz = rz_new;
-        for (int64_t v = tid; v < V; v += nt) p[v] = fma(beta, p[v], z[v]);
-        __syncthreads();
+        if (red2[0] <= stop2) break;
+        beta = red2[1] / rz;
+        rz = red2[1];
     }
-    if (tid == 0 && a.cg_used) a.cg_used[a.step] = used;
-    __syncthreads();
-    // S_n <- exp(x_n) S_n
-    for (int n = tid; n < N; n += nt) {
+    if (gtid == 0 && a.cg_used) a.cg_used[a.step] = ok ? used : -1;
+    if (!ok) return;
+    // S_n <- exp(x_n) S_n (each node by the thread that owns it)
+    for (int n = gtid; n < N; n += gnt) {
         if (a.fixed[n]) continue;
         double d[7];
         for (int c = 0; c < 7; ++c) d[c] = x[7 * n + c];
