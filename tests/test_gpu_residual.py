@@ -465,3 +465,62 @@ def test_two_sided_gauss_newton_matches_oracle(ctx, bidir):
     e_true = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(bidir["S_true"]))))
     e_init = np.linalg.norm(sim3.log(sim3.compose(bidir["S0"], sim3.inverse(bidir["S_true"]))))
     assert e_true < 0.1 * e_init
+
+
+def _event_pairs(B, out, e):
+    """The accepted pairs of event e of batch B (points, observations, local
+    keyframe index) and the event's keyframe poses as the device sees them."""
+    ekf, emp = B.event_kf_offset, B.event_mp_offset
+    xyz, uv, kfl = [], [], []
+    for k in range(int(ekf[e]), int(ekf[e + 1])):
+        p0, p1 = int(B.pair_offset[k]), int(B.pair_offset[k + 1])
+        d = out["decision"][p0:p1]
+        acc = np.nonzero((d == oracle.ADD) | (d == oracle.FUSE))[0]
+        local = B.pair_mp[p0 + acc] if B.pair_mp is not None else acc
+        xyz.append(B.mp_xyz[int(emp[e]) + np.asarray(local, np.int64)])
+        uv.append(B.kp_xy[int(B.kp_offset[k]) + out["best_idx"][p0 + acc]])
+        kfl.append(np.full(len(acc), k - int(ekf[e]), np.int32))
+    T32 = B.kf_T[int(ekf[e]):int(ekf[e + 1])].astype(np.float32).astype(np.float64)
+    return np.concatenate(xyz), np.concatenate(uv), np.concatenate(kfl), T32
+
+
+@pytest.mark.parametrize("lm", [0.0, synth.ROBUST_LM_LAMBDA])
+def test_robust_refinement_multi_event_batch(ctx, lm):
+    """Rounds with an inlier bound (and Levenberg-Marquardt) on four events
+    in one launch: two with wrong associations, one uneven with sparse
+    pairs, one that accepts no pair.  The events leave their rounds at
+    different steps; each must match its own float64 refinement."""
+    import paper_2603_17201_amd as fl
+    e0 = synth.gen_c2(seed=231, n_kf=5, n_mp=4000, misplace=(0.1, 6.0, 9.0))
+    e1 = synth.gen_c3(seed=322, n_kf=8, n_mp=4000, id_base=10 ** 6, fresh_base=2 * 10 ** 9)
+    e2 = synth.gen_c2(seed=232, n_kf=4, n_mp=3000, misplace=(0.15, 6.0, 9.0))
+    e3 = synth.gen_tiny(64, n_kf=2, n_mp=150)
+    e3.kp_desc = e3.kp_desc ^ np.uint8(0xFF)   # no candidate within the threshold
+    B = synth.concat_events([e0, e1, e2, e3])
+    P = synth.verification_params()
+    exp = oracle.search_fuse(B, params=P, use_grid=True)
+    it, rounds, tau = synth.ROBUST_ITERS, synth.ROBUST_ROUNDS, synth.ROBUST_OUTLIER_PX
+    d32, tau32 = float(np.float32(2.45)), float(np.float32(tau))
+    refs = []
+    for e in range(3):
+        xyz, uv, kfl, T32 = _event_pairs(B, exp, e)
+        refs.append(R.refine_robust(B.events[e].S_init, xyz, uv, kfl, T32, B.cams[int(B.event_kf_offset[e])], d32,
+                                    iters=it, rounds=rounds, outlier_px=tau32, lm_lambda=lm))
+    assert all(n > 100 for _, n in refs)
+    b = fl.DeviceBatch(B, device=dev())
+    S0 = np.stack([ev.S_init for ev in B.events])
+    for mode in ("batched", "graph"):
+        S = t(S0.copy())
+        nm = torch.zeros(4, dtype=torch.int32, device=dev())
+        ref = (it, 2.45, S, None, nm, rounds, tau, lm)
+        res = (ctx.search_fuse_batched(b, P, refine=ref) if mode == "batched"
+               else ctx.search_fuse_graph(b, P, refine=ref))
+        got = res.numpy()
+        for k in got:
+            assert np.array_equal(got[k], exp[k]), (mode, k)
+        S_gpu, n_gpu = S.cpu().numpy(), nm.cpu().numpy()
+        for e, (S_ref, n_ref) in enumerate(refs):
+            assert n_gpu[e] == n_ref, (mode, lm, e, n_gpu[e], n_ref)
+            err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
+            assert err < 1e-6, (mode, lm, e, err)
+        assert n_gpu[3] == 0 and np.array_equal(S_gpu[3], S0[3]), mode
