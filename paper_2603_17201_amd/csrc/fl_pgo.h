@@ -39,11 +39,14 @@ struct PgoArgs {
     double cg_tol;
     int32_t step;               // outer step index (cost and count outputs)
     // workspace
-    double* e;                  // [n_edges][7]
-    double* J;                  // [n_edges][2][49] J_i then J_j, row-major 7x7
-    double* u;                  // [n_edges][7] conjugate-gradient edge products
-    double* vec;                // [6][n_nodes][7]: g, x, r, z, p, q
-    double* Dfac;               // [n_nodes][49] LDL^T factors of the preconditioner blocks
+    // Component-major layouts (entry, then edge or node), so that the
+    // threads of a wave, which take consecutive edges or nodes, load
+    // consecutive addresses.
+    double* e;                  // [7][n_edges]
+    double* J;                  // [2][49][n_edges]: J_i then J_j, entry 7 r + c of each
+    double* u;                  // [7][n_edges] conjugate-gradient edge products
+    double* vec;                // [6][7][n_nodes]: g, x, r, z, p, q
+    double* Dfac;               // [49][n_nodes] LDL^T factors of the preconditioner blocks
     uint32_t* bar;              // grid-barrier counter, zero at launch
     double* red;                // [2][gridDim][4] reduction rows
     // outputs (may be null)
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(kPgoJacBlock) void pgo_jacobian_kernel(PgoArgs a) {
     if (c == 0) {
         double e[7];
         pgo_edge_error(Si, Sj, Minv, e);
-        for (int r = 0; r < 7; ++r) a.e[7 * (int64_t)k + r] = e[r];
+        for (int r = 0; r < 7; ++r) a.e[(int64_t)r * a.n_edges + k] = e[r];
     }
     const double h = a.fd_step;
     double d[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -95,16 +98,19 @@ __global__ __launch_bounds__(kPgoJacBlock) void pgo_jacobian_kernel(PgoArgs a) {
             pgo_edge_error(Pp, Sj, Minv, ep);
             pgo_edge_error(Pm, Sj, Minv, em);
         }
-        double* Jk = a.J + 98 * (int64_t)k + 49 * side;
-        for (int r = 0; r < 7; ++r) Jk[7 * r + c] = (ep[r] - em[r]) / (2.0 * h);
+        double* Jk = a.J + (int64_t)49 * side * a.n_edges + k;
+        for (int r = 0; r < 7; ++r) Jk[(int64_t)(7 * r + c) * a.n_edges] = (ep[r] - em[r]) / (2.0 * h);
     }
 }
 
-// y += J^T v (J 7x7 row-major)
-__device__ __forceinline__ void add_JTv(const double* J, const double* v, double* y) {
+// y += J^T v with J's entry 7 r + c at J[(7 r + c) st] and v's entry r at
+// v[r st] (the component-major layouts)
+__device__ __forceinline__ void add_JTv(const double* J, const double* v, int64_t st, double* y) {
+    double vr[7];
+    for (int r = 0; r < 7; ++r) vr[r] = v[r * st];
     for (int c = 0; c < 7; ++c) {
         double s = y[c];
-        for (int r = 0; r < 7; ++r) s = fma(J[7 * r + c], v[r], s);
+        for (int r = 0; r < 7; ++r) s = fma(J[(7 * r + c) * st], vr[r], s);
         y[c] = s;
     }
 }
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
     // cost, g, preconditioner blocks, r = -g, z = M^-1 r, p = z
     double red3[3] = {0.0, 0.0, 0.0};   // F, |g|^2, r.z
     for (int k = gtid; k < E; k += gnt)
-        for (int c = 0; c < 7; ++c) red3[0] = fma(a.e[7 * (int64_t)k + c], a.e[7 * (int64_t)k + c], red3[0]);
+        for (int c = 0; c < 7; ++c) red3[0] = fma(a.e[(int64_t)c * E + k], a.e[(int64_t)c * E + k], red3[0]);
     for (int n = gtid; n < N; n += gnt) {
         double gn[7] = {0, 0, 0, 0, 0, 0, 0};
         double D[49];
@@ -218,12 +224,14 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         if (!a.fixed[n]) {
             for (int t = a.adj_off[n]; t < a.adj_off[n + 1]; ++t) {
                 const int k = a.adj[t] >> 1, side = a.adj[t] & 1;
-                const double* Jk = a.J + 98 * (int64_t)k + 49 * side;
-                add_JTv(Jk, a.e + 7 * (int64_t)k, gn);
+                const double* Jk = a.J + (int64_t)49 * side * E + k;
+                add_JTv(Jk, a.e + k, E, gn);
+                double Jl[49];
+                for (int q2 = 0; q2 < 49; ++q2) Jl[q2] = Jk[(int64_t)q2 * E];
                 for (int c1 = 0; c1 < 7; ++c1)
                     for (int c2 = 0; c2 < 7; ++c2) {
                         double s = D[7 * c1 + c2];
-                        for (int rr = 0; rr < 7; ++rr) s = fma(Jk[7 * rr + c1], Jk[7 * rr + c2], s);
+                        for (int rr = 0; rr < 7; ++rr) s = fma(Jl[7 * rr + c1], Jl[7 * rr + c2], s);
                         D[7 * c1 + c2] = s;
                     }
             }
@@ -239,16 +247,16 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         } else {
             for (int c = 0; c < 7; ++c) D[8 * c] = 1.0;
         }
-        for (int t = 0; t < 49; ++t) a.Dfac[49 * (int64_t)n + t] = D[t];
+        for (int t = 0; t < 49; ++t) a.Dfac[(int64_t)t * N + n] = D[t];
         double rn[7], zn[7];
         for (int c = 0; c < 7; ++c) rn[c] = -gn[c];
         ldl7_solve(D, rn, zn);
         for (int c = 0; c < 7; ++c) {
-            g[7 * n + c] = gn[c];
-            x[7 * n + c] = 0.0;
-            r[7 * n + c] = rn[c];
-            z[7 * n + c] = zn[c];
-            p[7 * n + c] = zn[c];
+            g[(int64_t)c * N + n] = gn[c];
+            x[(int64_t)c * N + n] = 0.0;
+            r[(int64_t)c * N + n] = rn[c];
+            z[(int64_t)c * N + n] = zn[c];
+            p[(int64_t)c * N + n] = zn[c];
             red3[1] = fma(gn[c], gn[c], red3[1]);
             red3[2] = fma(rn[c], zn[c], red3[2]);
         }
@@ -270,18 +278,19 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         // u_k = J_i p'_i + J_j p'_j with p' = z + beta p (p' = p at it = 0)
         for (int k = gtid; k < E; k += gnt) {
             const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
-            const double* Ji = a.J + 98 * (int64_t)k;
-            const double* Jj = Ji + 49;
+            const double* Ji = a.J + k;
+            const double* Jj = a.J + (int64_t)49 * E + k;
             double pi[7], pj[7];
             for (int c = 0; c < 7; ++c) {
-                pi[c] = it ? fma(beta, p[7 * i + c], z[7 * i + c]) : p[7 * i + c];
-                pj[c] = it ? fma(beta, p[7 * j + c], z[7 * j + c]) : p[7 * j + c];
+                const int64_t ci = (int64_t)c * N + i, cj = (int64_t)c * N + j;
+                pi[c] = it ? fma(beta, p[ci], z[ci]) : p[ci];
+                pj[c] = it ? fma(beta, p[cj], z[cj]) : p[cj];
             }
             for (int rr = 0; rr < 7; ++rr) {
                 double s = 0.0;
-                for (int c = 0; c < 7; ++c) s = fma(Ji[7 * rr + c], pi[c], s);
-                for (int c = 0; c < 7; ++c) s = fma(Jj[7 * rr + c], pj[c], s);
-                a.u[7 * (int64_t)k + rr] = s;
+                for (int c = 0; c < 7; ++c) s = fma(Ji[(int64_t)(7 * rr + c) * E], pi[c], s);
+                for (int c = 0; c < 7; ++c) s = fma(Jj[(int64_t)(7 * rr + c) * E], pj[c], s);
+                a.u[(int64_t)rr * E + k] = s;
             }
         }
         ok = pgo_grid_sync(a.bar, ++seq * (uint32_t)gridDim.x);
@@ -291,24 +300,28 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         for (int n = gtid; n < N; n += gnt) {
             double pn[7], qn[7] = {0, 0, 0, 0, 0, 0, 0};
             for (int c = 0; c < 7; ++c) {
-                pn[c] = it ? fma(beta, p[7 * n + c], z[7 * n + c]) : p[7 * n + c];
-                p[7 * n + c] = pn[c];
+                const int64_t cn = (int64_t)c * N + n;
+                pn[c] = it ? fma(beta, p[cn], z[cn]) : p[cn];
+                p[cn] = pn[c];
             }
             if (!a.fixed[n]) {
                 double dg[7] = {0, 0, 0, 0, 0, 0, 0};
                 for (int t = a.adj_off[n]; t < a.adj_off[n + 1]; ++t) {
                     const int k = a.adj[t] >> 1, side = a.adj[t] & 1;
-                    const double* Jk = a.J + 98 * (int64_t)k + 49 * side;
-                    add_JTv(Jk, a.u + 7 * (int64_t)k, qn);
+                    const double* Jk = a.J + (int64_t)49 * side * E + k;
+                    add_JTv(Jk, a.u + k, E, qn);
                     if (a.lambda > 0.0)
                         for (int c = 0; c < 7; ++c)
-                            for (int rr = 0; rr < 7; ++rr) dg[c] = fma(Jk[7 * rr + c], Jk[7 * rr + c], dg[c]);
+                            for (int rr = 0; rr < 7; ++rr) {
+                                const double jv = Jk[(int64_t)(7 * rr + c) * E];
+                                dg[c] = fma(jv, jv, dg[c]);
+                            }
                 }
                 if (a.lambda > 0.0)
                     for (int c = 0; c < 7; ++c) qn[c] = fma(a.lambda * dg[c], pn[c], qn[c]);
             }
             for (int c = 0; c < 7; ++c) {
-                q[7 * n + c] = qn[c];
+                q[(int64_t)c * N + n] = qn[c];
                 pq[0] = fma(pn[c], qn[c], pq[0]);
             }
         }
@@ -320,15 +333,18 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         for (int n = gtid; n < N; n += gnt) {
             double rn[7], zn[7];
             for (int c = 0; c < 7; ++c) {
-                x[7 * n + c] = fma(alpha, p[7 * n + c], x[7 * n + c]);
-                rn[c] = fma(-alpha, q[7 * n + c], r[7 * n + c]);
-                r[7 * n + c] = rn[c];
+                const int64_t cn = (int64_t)c * N + n;
+                x[cn] = fma(alpha, p[cn], x[cn]);
+                rn[c] = fma(-alpha, q[cn], r[cn]);
+                r[cn] = rn[c];
                 red2[0] = fma(rn[c], rn[c], red2[0]);
             }
-            ldl7_solve(a.Dfac + 49 * (int64_t)n, rn, zn);
+            double F[49];
+            for (int t = 0; t < 49; ++t) F[t] = a.Dfac[(int64_t)t * N + n];
+            ldl7_solve(F, rn, zn);
             for (int c = 0; c < 7; ++c) {
                 const double zc = a.fixed[n] ? 0.0 : zn[c];
-                z[7 * n + c] = zc;
+                z[(int64_t)c * N + n] = zc;
                 red2[1] = fma(rn[c], zc, red2[1]);
             }
         }
@@ -346,7 +362,7 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
     for (int n = gtid; n < N; n += gnt) {
         if (a.fixed[n]) continue;
         double d[7];
-        for (int c = 0; c < 7; ++c) d[c] = x[7 * n + c];
+        for (int c = 0; c < 7; ++c) d[c] = x[(int64_t)c * N + n];
         const Sim3d Sn = sim3_mul(sim3_exp(d), sim3_load(a.S + 13 * (int64_t)n));
         sim3_store(Sn, a.S + 13 * (int64_t)n);
     }
