@@ -155,8 +155,9 @@ __device__ inline void ldl7_solve(const double* F, const double* b, double* x) {
 __device__ inline bool pgo_grid_sync(uint32_t* bar, uint32_t target) {
     __shared__ int s_ok;
     __syncthreads();
+    if (gridDim.x == 1) return true;   // one workgroup: its own barrier is enough
     if (threadIdx.x == 0) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this workgroup's writes, before the count
         atomicAdd(bar, 1u);
         int ok = 1;
         unsigned spins = 0;
@@ -166,7 +167,7 @@ __device__ inline bool pgo_grid_sync(uint32_t* bar, uint32_t target) {
                 break;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every workgroup's writes, after the count
         s_ok = ok;
     }
     __syncthreads();
