@@ -6,7 +6,11 @@ keyframes, Sim3 search-and-fuse over every (point, keyframe) pair, ADD
 conflict resolution, then 10 Gauss-Newton refinement steps of the loop Sim3
 on the accepted pairs.  Inputs are resident in HBM before timing starts.
 
-  batched : one upload of the event tables + one HIP-graph launch per event
+  batched : one upload of the event tables + one launch sequence per event,
+            replayed from a HIP graph, launched eagerly, or launched eagerly
+            with consecutive events alternating between two contexts on two
+            streams (one event's search overlaps the previous one's
+            refinement); the headline takes the highest throughput
   plain   : the per-call pattern (one fl_search_fuse per keyframe, each
             followed by a copy of its results to the host and a stream sync;
             then each refinement step as its own call, copy and sync)
@@ -351,6 +355,32 @@ class Bench:
             args.steps, args.warmup)
         log(f"batched, eager launches: {ms_eager * 1e3:.1f} us per event (device-resident)")
 
+        # consecutive steps alternating between two contexts on two streams
+        # (each with its own outputs and Sim3; the inputs are shared, read
+        # only): one step's search runs beside the previous step's refinement
+        ctx2 = fl.Context(0)
+        tv = ctx.get_tuning()
+        ctx2.set_tuning(tv.pairs_per_lane, tv.lds_mode, tv.wg_per_cu, tv.xcd_aware)
+        ctxs = [ctx, ctx2]
+        strs = [self.stream, torch.cuda.Stream(self.dev)]
+        outs = [out, fl.FuseOutputs.empty(n_pairs, self.dev)]
+        Ss = [S, S.clone()]
+        nms = [n_matched, torch.zeros_like(n_matched)]
+
+        def two(i):
+            k = i & 1
+            ctxs[k].search_fuse_batched(b, P, outs[k], refine=(GN_ITERS, HUBER, Ss[k], None, nms[k]), stream=strs[k])
+        for i in range(args.warmup):
+            two(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            two(i)
+        torch.cuda.synchronize()
+        ms_two = (time.perf_counter() - t0) * 1e3 / args.steps
+        ctx2.close()
+        log(f"batched, two contexts on two streams: {ms_two * 1e3:.1f} us per event (throughput)")
+
         e2e = []
         for i in range(args.warmup + args.steps):
             t0 = time.perf_counter()
@@ -387,7 +417,7 @@ class Bench:
         roof, other = (rr, rs) if kr_ms > ks_ms else (rs, rr)
         log(f"kernels: search {ks_ms * 1e3:.1f} us, refine {kr_ms * 1e3:.1f} us ({n_acc} accepted pairs)")
         return dict(ev=ev, n_pairs=n_pairs, ms_step=ms_step, ms_e2e=ms_e2e, ms_eager=ms_eager, plain=plain,
-                    tuning=tuning, roof=roof, other=other, n_acc=n_acc)
+                    tuning=tuning, roof=roof, other=other, n_acc=n_acc, ms_two=ms_two)
 
     def kernel_rooflines(self, ev, b, P, out, S, S_init):
         """Kernel times of eager launches (search + refinement) of one batch
@@ -791,8 +821,13 @@ def main():
 
     ev, plain = h["ev"], h["plain"]
     # the batched path: one table upload and one launch sequence per event,
-    # replayed from a HIP graph or launched eagerly, whichever is faster here
-    launch, ms_best = ("graph", h["ms_step"]) if h["ms_step"] <= h["ms_eager"] else ("eager", h["ms_eager"])
+    # replayed from a HIP graph, launched eagerly, or launched eagerly with
+    # consecutive events alternating between two contexts on two streams
+    # (every event still runs its whole search and refinement), whichever
+    # gives the higher throughput here
+    launch, ms_best = min((("graph", h["ms_step"]), ("eager", h["ms_eager"]),
+                           ("eager, consecutive events on two contexts and streams", h["ms_two"])),
+                          key=lambda c: c[1])
     res = dict(
         metric="point-keyframe match candidates/s (batched loop event incl. 10 GN steps)",
         value=h["n_pairs"] / (ms_best * 1e-3), unit="pairs/s", n_gpus=1, steps=args.steps,
@@ -804,6 +839,8 @@ def main():
                     launch=launch),
         ms_per_event_batched_graph=h["ms_step"], ms_per_event_batched_eager=h["ms_eager"],
         ms_per_event_batched_graph_with_d2h=h["ms_e2e"],
+        ms_per_event_two_contexts_two_streams=h["ms_two"],
+        pairs_per_s_two_contexts_two_streams=h["n_pairs"] / (h["ms_two"] * 1e-3),
         plain=plain,
         batched_vs_plain=(plain["ms_per_event"] / h["ms_e2e"]) if plain else None,
         batched_vs_plain_device_resident=(plain["ms_per_event"] / ms_best) if plain else None,
