@@ -583,34 +583,38 @@ class Bench:
     def essential_graph(self, steps):
         """Essential-graph optimisation of a loop of 1,000 keyframes (about
         3,000 odometry, covisibility and loop edges) from its drifted start:
-        10 outer steps, conjugate gradients to 1e-10."""
+        10 outer steps, each solved directly (banded Cholesky under a reverse
+        Cuthill-McKee order) and, for comparison, by block-Jacobi conjugate
+        gradients (at most 500 iterations, to 1e-10)."""
         import synth
-        torch, ctx = self.torch, self.ctx
+        torch, fl, ctx = self.torch, self.fl, self.ctx
         d = synth.gen_pose_graph(n=1000, seed=606)
         S0 = torch.from_numpy(d["S0"]).to(self.dev)
         S = S0.clone()
         M = torch.from_numpy(d["M"]).to(self.dev)
-        out = {}
-
-        def run():
-            S.copy_(S0)
-            out["r"] = ctx.pose_graph_optimize(S, M, d["edges"], None, iters=10)
-        gc.collect()
-        gc.disable()
-        ms = self.events_time(run, max(3, steps // 5), 1)
-        gc.enable()
-        run()
-        cost, used = (x.cpu().numpy() for x in out["r"])
-        Sf = S.cpu().numpy()
 
         def worst(A):
             e = [sim3_error(a, b) for a, b in zip(A, d["S_true"])]
             return dict(deg=max(x[0] for x in e), m=max(x[1] for x in e), log_scale=max(x[2] for x in e))
-        res = dict(n_nodes=int(S.shape[0]), n_edges=int(d["edges"].shape[0]), iters=10, ms_per_optimisation=ms,
-                   cost_start=float(cost[0]), cost_end=float(cost[-1]), cg_iterations=[int(u) for u in used],
-                   worst_node_error_start=worst(d["S0"]), worst_node_error_end=worst(Sf))
-        log(f"essential graph: {ms:.2f} ms for 10 steps ({res['n_nodes']} keyframes, {res['n_edges']} edges), cost "
-            f"{cost[0]:.3e} -> {cost[-1]:.3e}, CG iterations {res['cg_iterations']}")
+        res = dict(n_nodes=int(S.shape[0]), n_edges=int(d["edges"].shape[0]), iters=10,
+                   worst_node_error_start=worst(d["S0"]))
+        for name, solver in (("direct", fl._abi.PGO_SOLVER_DIRECT), ("conjugate_gradients", fl._abi.PGO_SOLVER_CG)):
+            out = {}
+
+            def run():
+                S.copy_(S0)
+                out["r"] = ctx.pose_graph_optimize(S, M, d["edges"], None, iters=10, solver=solver)
+            gc.collect()
+            gc.disable()
+            ms = self.events_time(run, max(3, steps // 5), 1)
+            gc.enable()
+            run()
+            cost, used = (x.cpu().numpy() for x in out["r"])
+            res[name] = dict(ms_per_optimisation=ms, cost_start=float(cost[0]), cost_end=float(cost[-1]),
+                             cg_iterations=[int(u) for u in used], worst_node_error_end=worst(S.cpu().numpy()))
+            log(f"essential graph, {name}: {ms:.2f} ms for 10 steps ({res['n_nodes']} keyframes, "
+                f"{res['n_edges']} edges), cost {cost[0]:.3e} -> {cost[-1]:.3e}, CG iterations "
+                f"{res[name]['cg_iterations']}")
         return res
 
     def residual(self):

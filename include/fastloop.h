@@ -329,13 +329,25 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
  * F = sum e^T e.  Nodes move by left perturbations S_i <- exp(d_i) S_i; the
  * Jacobians of e_ij are central differences (step fd_step) of the float64
  * Sim3 algebra; each of `iters` steps solves (H + lambda diag H) d = -g over
- * the free nodes by block-Jacobi preconditioned conjugate gradients (at most
- * cg_iters, stopping when |r| <= cg_tol |g|).  Deterministic: every sum has
- * a fixed order.  The solve runs one workgroup per compute unit, all
- * resident together and synchronised by a grid barrier; other work on the
- * device at the same time can keep them from being resident, and a barrier
- * wait that runs past its bound reports the step as failed (cg_used = -1,
- * the poses of that step unchanged) instead of blocking. */
+ * the free nodes, by one of two solvers (`solver`):
+ *  - direct: the free nodes are renumbered by reverse Cuthill-McKee on the
+ *    host; when no edge then spans more than FL_PGO_MAX_BAND_NODES - 1
+ *    positions, the banded H is factored by float64 Cholesky in one
+ *    workgroup and solved exactly (cg_used = 0; a pivot that is not
+ *    positive reports -1 and leaves that step's poses unchanged);
+ *  - block-Jacobi preconditioned conjugate gradients (at most cg_iters,
+ *    stopping when |r| <= cg_tol |g|).  This solve runs one workgroup per
+ *    compute unit, all resident together and synchronised by a grid
+ *    barrier; other work on the device at the same time can keep them from
+ *    being resident, and a barrier wait that runs past its bound reports the
+ *    step as failed (cg_used = -1, the poses of that step unchanged) instead
+ *    of blocking.
+ * A graph with no edges or no free node takes the conjugate gradients under
+ * every setting.  Deterministic: every sum has a fixed order. */
+#define FL_PGO_MAX_BAND_NODES 12   /* widest band of the direct solver, in keyframes */
+#define FL_PGO_SOLVER_AUTO 0       /* direct when the band fits, else conjugate gradients */
+#define FL_PGO_SOLVER_CG 1
+#define FL_PGO_SOLVER_DIRECT 2     /* FL_ERANGE when the band does not fit */
 typedef struct {
     int32_t n_nodes;
     int32_t n_edges;
@@ -352,7 +364,10 @@ typedef struct {
     double cg_tol;          /* >= 0 */
     double fd_step;         /* > 0; 0: 1e-5 */
     double* cost;           /* device [iters + 1] (may be NULL): F before each step and after the last */
-    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each step, -1: failed */
+    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each step
+                               (0 for a direct solve), -1: failed */
+    int32_t solver;         /* FL_PGO_SOLVER_* */
+    int32_t reserved;       /* 0 */
 } fl_pgo_params;
 
 /* Errors: FL_EINVAL (NULL arrays, an edge outside the graph or joining a

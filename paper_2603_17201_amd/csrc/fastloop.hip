@@ -1272,11 +1272,16 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     if (!(P->cg_tol >= 0.0) || !std::isfinite(P->cg_tol)) return fail(FL_EINVAL, "cg_tol must be finite and >= 0");
     const double h = P->fd_step == 0.0 ? 1e-5 : P->fd_step;
     if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_EINVAL, "fd_step must be finite and > 0");
-    // incident edges of every node, in edge order (the gathers' fixed order)
-    std::vector<int32_t> tab((size_t)2 * E + (N + 1) + 2 * (size_t)E, 0);
+    if (P->solver < FL_PGO_SOLVER_AUTO || P->solver > FL_PGO_SOLVER_DIRECT || P->reserved != 0)
+        return fail(FL_EINVAL, "solver %d / reserved %d", P->solver, P->reserved);
+    // incident edges of every node, in edge order (the gathers' fixed order),
+    // then the band position of every node and the node of every position
+    std::vector<int32_t> tab((size_t)2 * E + (N + 1) + 2 * (size_t)E + 2 * (size_t)N, 0);
     int32_t* t_edges = tab.data();
     int32_t* off = t_edges + 2 * (size_t)E;
     int32_t* adj = off + (N + 1);
+    int32_t* posn = adj + 2 * (size_t)E;
+    int32_t* order = posn + N;
     for (int k = 0; k < E; ++k) {
         const int i = G->edges[2 * k], j = G->edges[2 * k + 1];
         if (i < 0 || i >= N || j < 0 || j >= N || i == j)
@@ -1294,6 +1299,64 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
             adj[fill[t_edges[2 * k + 1]]++] = 2 * k + 1;
         }
     }
+    // Band ordering of the free nodes: reverse Cuthill-McKee (breadth-first
+    // from a node of least degree in each component, neighbours by rising
+    // degree, the whole order reversed); b = the widest span of an edge
+    // between free nodes.
+    std::vector<uint8_t> held(N);
+    for (int n = 0; n < N; ++n) held[n] = G->fixed ? (G->fixed[n] != 0) : (n == 0);
+    int nf = 0, bw = 0;
+    {
+        std::vector<int32_t> deg(N, 0), seq, nb;
+        for (int k = 0; k < E; ++k)
+            if (!held[t_edges[2 * k]] && !held[t_edges[2 * k + 1]]) {
+                ++deg[t_edges[2 * k]];
+                ++deg[t_edges[2 * k + 1]];
+            }
+        std::vector<int32_t> roots;
+        for (int n = 0; n < N; ++n)
+            if (!held[n]) roots.push_back(n);
+        std::stable_sort(roots.begin(), roots.end(), [&](int x, int y) { return deg[x] < deg[y]; });
+        std::vector<uint8_t> seen(N, 0);
+        seq.reserve(roots.size());
+        for (int root : roots) {
+            if (seen[root]) continue;
+            seen[root] = 1;
+            size_t head = seq.size();
+            seq.push_back(root);
+            while (head < seq.size()) {
+                const int v = seq[head++];
+                nb.clear();
+                for (int t = off[v]; t < off[v + 1]; ++t) {
+                    const int k = adj[t] >> 1, u = t_edges[2 * k + 1 - (adj[t] & 1)];
+                    if (!held[u] && !seen[u]) {
+                        seen[u] = 1;
+                        nb.push_back(u);
+                    }
+                }
+                std::stable_sort(nb.begin(), nb.end(), [&](int x, int y) {
+                    return deg[x] != deg[y] ? deg[x] < deg[y] : x < y;
+                });
+                seq.insert(seq.end(), nb.begin(), nb.end());
+            }
+        }
+        nf = (int)seq.size();
+        for (int n = 0; n < N; ++n) posn[n] = -1;
+        for (int p = 0; p < nf; ++p) {
+            order[p] = seq[nf - 1 - p];
+            posn[order[p]] = p;
+        }
+        for (int k = 0; k < E; ++k) {
+            const int pi = posn[t_edges[2 * k]], pj = posn[t_edges[2 * k + 1]];
+            if (pi >= 0 && pj >= 0) bw = std::max(bw, std::abs(pi - pj));
+        }
+    }
+    const bool band_fits = bw + 1 <= FL_PGO_MAX_BAND_NODES;
+    if (P->solver == FL_PGO_SOLVER_DIRECT && !band_fits && E > 0 && nf > 0)
+        return fail(FL_ERANGE, "reordered band spans %d keyframes (at most %d)", bw + 1, FL_PGO_MAX_BAND_NODES);
+    const bool direct = E > 0 && nf > 0 && band_fits && P->solver != FL_PGO_SOLVER_CG;
+    const int band_w = 7 * (bw + 1);
+    const int64_t band_vs = 7 * (int64_t)nf;
     const size_t tab_bytes = sizeof(int32_t) * tab.size();
     size_t off_b = 0;
     auto take = [&](size_t bytes) {
@@ -1314,6 +1377,9 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
         1, std::min<int64_t>(c->n_cu, (std::max(E, N) + (int64_t)kPgoBlock - 1) / kPgoBlock));
     const size_t L_bar = take(sizeof(uint32_t));
     const size_t L_red = take(sizeof(double) * 2 * 4 * (size_t)solve_grid);
+    const size_t L_band = take(direct ? sizeof(double) * (size_t)band_vs * band_w : 0);
+    const size_t L_rhs = take(direct ? sizeof(double) * (size_t)band_vs : 0);
+    const size_t L_xs = take(direct ? sizeof(double) * (size_t)band_vs : 0);
     int rc = c->pgo.ensure(off_b);
     if (rc) return rc;
     char* base = (char*)c->pgo.p;
@@ -1324,7 +1390,7 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     if (rc) return rc;
     memcpy(pin->p, tab.data(), tab_bytes);
     uint8_t* fx = (uint8_t*)pin->p + L_fix;
-    for (int n = 0; n < N; ++n) fx[n] = G->fixed ? (G->fixed[n] != 0) : (n == 0);
+    for (int n = 0; n < N; ++n) fx[n] = held[n];
     pin->used = up;
     FL_HIP(hipMemcpyAsync(base, pin->p, up, hipMemcpyHostToDevice, stream));
     rc = note_fetch(c, *pin, stream);
@@ -1349,14 +1415,28 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     a.Dfac = (double*)(base + L_D);
     a.bar = (uint32_t*)(base + L_bar);
     a.red = (double*)(base + L_red);
+    a.band_w = band_w;
+    a.band_vs = (int32_t)band_vs;
+    a.pos = a.adj + 2 * (size_t)E;
+    a.order = a.pos + N;
+    a.band = (double*)(base + L_band);
+    a.rhs = (double*)(base + L_rhs);
+    a.xs = (double*)(base + L_xs);
     a.cost = P->cost;
     a.cg_used = P->cg_used;
     const int jac_grid = std::max(1, (int)((7 * (int64_t)E + kPgoJacBlock - 1) / kPgoJacBlock));
     for (int it = 0; it < P->iters; ++it) {
         a.step = it;
         if (E > 0) hipLaunchKernelGGL(pgo_jacobian_kernel, dim3(jac_grid), dim3(kPgoJacBlock), 0, stream, a);
-        FL_HIP(hipMemsetAsync(a.bar, 0, sizeof(uint32_t), stream));
-        hipLaunchKernelGGL(pgo_solve_kernel, dim3(solve_grid), dim3(kPgoBlock), 0, stream, a);
+        if (direct) {
+            hipLaunchKernelGGL(pgo_band_assemble_kernel, dim3((unsigned)((band_vs + kBandBlock - 1) / kBandBlock)),
+                               dim3(kBandBlock), 0, stream, a);
+            hipLaunchKernelGGL(pgo_band_solve_kernel, dim3(1), dim3(kBandBlock),
+                               sizeof(double) * ((size_t)band_w * band_w + 2 * band_w + 1), stream, a);
+        } else {
+            FL_HIP(hipMemsetAsync(a.bar, 0, sizeof(uint32_t), stream));
+            hipLaunchKernelGGL(pgo_solve_kernel, dim3(solve_grid), dim3(kPgoBlock), 0, stream, a);
+        }
     }
     a.step = P->iters;
     if (P->cost) hipLaunchKernelGGL(pgo_cost_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);

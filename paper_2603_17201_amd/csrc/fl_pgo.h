@@ -9,12 +9,21 @@
 // outer step solves (H + lambda diag H) d = -g by block-Jacobi preconditioned
 // conjugate gradients.
 //
-// Per outer step two kernels run: pgo_jacobian_kernel over (edge, column)
-// items on every CU, then pgo_solve_kernel, one co-resident workgroup per CU
-// synchronised by a grid barrier, which gathers g and the diagonal blocks per
-// node over its incident edges (fixed order, no floating-point atomics), runs
-// the conjugate gradients with fixed-order float64 reductions and updates
-// the nodes.
+// Per outer step pgo_jacobian_kernel runs over (edge, column) items on every
+// CU, then one of two solves:
+//  - direct (the paper's is a direct LDL^T): with the free nodes renumbered
+//    so that every edge spans at most b positions (reverse Cuthill-McKee on
+//    the host), H is a band of W = 7 (b + 1) scalars.  pgo_band_assemble_kernel
+//    writes each band row from its node's incident edges;
+//    pgo_band_solve_kernel, one workgroup, factors the band by Cholesky with
+//    the forward substitution folded in, keeping the W rows still being
+//    updated in an LDS window that slides down the matrix, then back-
+//    substitutes and updates the nodes;
+//  - pgo_solve_kernel, one co-resident workgroup per CU synchronised by a
+//    grid barrier, which gathers g and the diagonal blocks per node over its
+//    incident edges (fixed order, no floating-point atomics), runs block-
+//    Jacobi preconditioned conjugate gradients with fixed-order float64
+//    reductions and updates the nodes.
 
 #pragma once
 
@@ -24,6 +33,10 @@ namespace fl {
 
 constexpr int kPgoBlock = 256;      // threads of a solve workgroup (one per CU, all co-resident)
 constexpr int kPgoJacBlock = 256;   // threads of a Jacobian workgroup
+constexpr int kBandBlock = 512;     // threads of the band assembly and of the one band-solve workgroup
+constexpr int kBandMaxW = 7 * FL_PGO_MAX_BAND_NODES;   // widest band row, in scalars
+constexpr int kBandPairs = ((kBandMaxW - 1) * kBandMaxW / 2 + kBandBlock - 1) / kBandBlock;
+static_assert(kBandMaxW <= kBandBlock, "one thread per band offset");
 
 struct PgoArgs {
     int32_t n_nodes, n_edges;
@@ -49,6 +62,16 @@ struct PgoArgs {
     double* Dfac;               // [49][n_nodes] LDL^T factors of the preconditioner blocks
     uint32_t* bar;              // grid-barrier counter, zero at launch
     double* red;                // [2][gridDim][4] reduction rows
+    // direct solve: free nodes by band position, the band [Vs][W] (row R
+    // holds columns R - W + 1 .. R, the diagonal last; H, then L in place),
+    // the right-hand side (-g, then the forward solution) and the step
+    int32_t band_w;             // W
+    int32_t band_vs;            // Vs = 7 free nodes
+    const int32_t* order;       // [Vs / 7] node of each position
+    const int32_t* pos;         // [n_nodes] position of each node, -1 held
+    double* band;
+    double* rhs;                // [Vs]
+    double* xs;                 // [Vs]
     // outputs (may be null)
     double* cost;               // [iters + 1]
     int32_t* cg_used;           // [iters]
@@ -365,6 +388,220 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         double d[7];
         for (int c = 0; c < 7; ++c) d[c] = x[(int64_t)c * N + n];
         const Sim3d Sn = sim3_mul(sim3_exp(d), sim3_load(a.S + 13 * (int64_t)n));
+        sim3_store(Sn, a.S + 13 * (int64_t)n);
+    }
+}
+
+// Row R = 7 P + r of the band (free node n at position P): entries
+// (J_a^T J_a)[r][c <= r] over the node's edges on the diagonal block, and
+// (J_a^T J_b)[r][.] of each edge to a free node m at an earlier position in
+// block (P, pos m); lambda scales the diagonal; rhs = -g.  A node without
+// edges is held (unit diagonal, zero right-hand side).  Each thread owns its
+// row, so the sums take the incident edges in their fixed order.
+__global__ __launch_bounds__(kBandBlock) void pgo_band_assemble_kernel(PgoArgs a) {
+    const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (R >= a.band_vs) return;
+    const int W = a.band_w, w = W - 1, E = a.n_edges;
+    const int P = (int)(R / 7), r = (int)(R % 7);
+    const int n = a.order[P];
+    double* row = a.band + R * W;
+    for (int o = 0; o < W; ++o) row[o] = 0.0;
+    double gr = 0.0;
+    for (int t = a.adj_off[n]; t < a.adj_off[n + 1]; ++t) {
+        const int k = a.adj[t] >> 1, side = a.adj[t] & 1;
+        const int m = a.edges[2 * k + 1 - side];
+        const double* Ja = a.J + (int64_t)49 * side * E + k;
+        const double* Jb = a.J + (int64_t)49 * (1 - side) * E + k;
+        double ja[7];
+        for (int rr = 0; rr < 7; ++rr) {
+            ja[rr] = Ja[(int64_t)(7 * rr + r) * E];
+            gr = fma(ja[rr], a.e[(int64_t)rr * E + k], gr);
+        }
+        for (int c = 0; c <= r; ++c) {
+            double v = 0.0;
+            for (int rr = 0; rr < 7; ++rr) v = fma(ja[rr], Ja[(int64_t)(7 * rr + c) * E], v);
+            row[c - r + w] += v;
+        }
+        const int pm = a.pos[m];
+        const int64_t base = 7 * (int64_t)pm - R + w;
+        if (pm >= 0 && pm < P && base >= 0) {
+            for (int c = 0; c < 7; ++c) {
+                double v = 0.0;
+                for (int rr = 0; rr < 7; ++rr) v = fma(ja[rr], Jb[(int64_t)(7 * rr + c) * E], v);
+                row[base + c] += v;
+            }
+        }
+    }
+    if (a.adj_off[n] == a.adj_off[n + 1]) {
+        row[w] = 1.0;
+        gr = 0.0;
+    } else {
+        row[w] *= 1.0 + a.lambda;
+    }
+    a.rhs[R] = -gr;
+}
+
+// Barrier for LDS traffic only: waits for this wave's LDS operations, not
+// for its outstanding global loads (the prefetches below stay in flight
+// across it).  Global data is exchanged between threads only across a full
+// __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Cost, then the banded Cholesky H = L L^T with L y = rhs solved alongside,
+// L^T x = y, and S_n <- exp(x_n) S_n, in one workgroup.
+//
+// Factorisation, column k: rows k .. k + W - 1 sit in the LDS window, row R
+// in slot R mod W (its W band entries).  Phase A scales column k below the
+// pivot (L(i,k) = A(i,k) / sqrt(A(k,k))); phase B subtracts L(i,k) L(j,k)
+// from A(i,j) for k < j <= i <= k + W - 1, takes y_k out of the right-hand
+// side, writes the finished row k of L back and admits row k + W into its
+// slot.  The threads form G = 512 / W admission groups; group k mod G admits
+// at column k the row it loaded into a register G columns earlier, so the
+// loads' latency is spread over G columns.  Back substitution walks the rows
+// of L upwards, staged into the LDS window W rows at a time, with a ring of
+// W + 1 right-hand-side entries (the slots read and written in one step are
+// then all different).
+__global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
+    extern __shared__ __align__(16) unsigned char s_mem[];
+    __shared__ double s_w[kBandBlock / kWave];
+    const int tid = threadIdx.x;
+    const int W = a.band_w, w = W - 1, Vs = a.band_vs, E = a.n_edges;
+    const int G = kBandBlock / W;                  // >= 6
+    const int grp = tid / W, off = tid % W;         // grp < G: an admission thread
+    double* win = (double*)s_mem;      // [W][W]
+    double* sv = win + W * W;          // [W + 1]
+    double* sr = sv + W + 1;           // [W] right-hand sides of a back-substitution chunk
+
+    double part = 0.0;
+    for (int k = tid; k < E; k += kBandBlock)
+        for (int c = 0; c < 7; ++c) part = fma(a.e[(int64_t)c * E + k], a.e[(int64_t)c * E + k], part);
+    const double F = pgo_sum(part, s_w);
+    if (tid == 0 && a.cost) a.cost[a.step] = F;
+
+    // this thread's (a, b) pairs of the phase-B triangle, a >= b in [0, w)
+    int pk[kBandPairs];
+    const int npair = w * (w + 1) / 2;
+    for (int q = 0; q < kBandPairs; ++q) {
+        const int t = tid + q * kBandBlock;
+        pk[q] = -1;
+        if (t < npair) {
+            int ra = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+            while (ra * (ra + 1) / 2 > t) --ra;
+            while ((ra + 1) * (ra + 2) / 2 <= t) ++ra;
+            pk[q] = (ra << 8) | (t - ra * (ra + 1) / 2);
+        }
+    }
+    for (int idx = tid; idx < W * W; idx += kBandBlock) {
+        const int R = idx / W;
+        win[idx] = R < Vs ? a.band[(int64_t)R * W + idx % W] : 0.0;
+    }
+    for (int idx = tid; idx < W; idx += kBandBlock) sv[idx] = idx < Vs ? a.rhs[idx] : 0.0;
+    // group grp first admits row W + grp (at column grp)
+    double pre = 0.0, preb = 0.0;
+    if (grp < G && W + grp < Vs) {
+        pre = a.band[(int64_t)(W + grp) * W + off];
+        if (off == 0) preb = a.rhs[W + grp];
+    }
+    __syncthreads();
+
+    // ring slots advance by one per column (no integer division in the loop)
+    bool ok = true;
+    int sk = 0, kg = 0;   // k mod W, k mod G
+    for (int k = 0; k < Vs; ++k) {
+        const int s1 = sk + 1 == W ? 0 : sk + 1;   // slot of row k + 1
+        const double d = win[sk * W + w];
+        if (!(d > 0.0)) {   // the same value in every thread
+            ok = false;
+            break;
+        }
+        const double rd = sqrt(d);
+        const double ird = 1.0 / rd;
+        const double yk = sv[sk] * ird;
+        int st = s1 + tid;   // slot of row k + 1 + tid (tid < w)
+        if (st >= W) st -= W;
+        if (tid < w && k + 1 + tid < Vs) win[st * W + w - 1 - tid] *= ird;
+        lds_barrier();
+        // every read of this phase (column k) before any write (columns > k):
+        // the reads then issue back to back instead of one round trip per pair
+        double lv[kBandPairs], lw[kBandPairs], av[kBandPairs];
+        int at[kBandPairs];
+#pragma unroll
+        for (int q = 0; q < kBandPairs; ++q) {
+            const int pa = pk[q] >> 8, pb = pk[q] & 255;
+            at[q] = -1;
+            if (pk[q] >= 0 && k + 1 + pa < Vs) {
+                int si = s1 + pa, sj = s1 + pb;
+                if (si >= W) si -= W;
+                if (sj >= W) sj -= W;
+                at[q] = si * W + w - pa + pb;
+                lv[q] = win[si * W + w - 1 - pa];
+                lw[q] = win[sj * W + w - 1 - pb];
+                av[q] = win[at[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kBandPairs; ++q)
+            if (at[q] >= 0) win[at[q]] = fma(-lv[q], lw[q], av[q]);
+        if (tid < w && k + 1 + tid < Vs) sv[st] = fma(-win[st * W + w - 1 - tid], yk, sv[st]);
+        if (grp == kg) {
+            const double v = off == w ? rd : win[sk * W + off];
+            a.band[(int64_t)k * W + off] = v;
+            win[sk * W + off] = pre;
+            const int nr = k + W + G;
+            pre = nr < Vs ? a.band[(int64_t)nr * W + off] : 0.0;
+            if (off == 0) {
+                a.rhs[k] = yk;
+                sv[sk] = preb;
+                preb = nr < Vs ? a.rhs[nr] : 0.0;
+            }
+        }
+        lds_barrier();
+        sk = s1;
+        kg = kg + 1 == G ? 0 : kg + 1;
+    }
+    if (tid == 0 && a.cg_used) a.cg_used[a.step] = ok ? 0 : -1;
+    if (!ok) return;
+    __syncthreads();   // L and y in global memory, visible to every thread
+
+    const int W1 = W + 1;
+    if (tid < W && Vs - W + tid >= 0) sv[(Vs - W + tid) % W1] = a.rhs[Vs - W + tid];
+    int si = (Vs - 1) % W1;   // ring slot of row i, one down per step
+    for (int top = Vs - 1; top >= 0; top -= W) {
+        // rows top - W + 1 .. top of L into the window, row i at (top - i)
+        const int lo = top - W + 1 < 0 ? 0 : top - W + 1;
+        const int nrow = top - lo + 1;
+        for (int idx = tid; idx < nrow * W; idx += kBandBlock) {
+            const int ii = idx / W;
+            win[idx] = a.band[(int64_t)(top - ii) * W + idx % W];
+        }
+        for (int ii = tid; ii < nrow; ii += kBandBlock) sr[ii] = top - ii - W >= 0 ? a.rhs[top - ii - W] : 0.0;
+        __syncthreads();
+        for (int ii = 0; ii < nrow; ++ii) {
+            const int i = top - ii;
+            const double* Li = win + ii * W;
+            const double xi = sv[si] / Li[w];
+            if (tid < w && i - w + tid >= 0) {
+                int sj = si - w + tid;   // slot of row i - w + tid
+                if (sj < 0) sj += W1;
+                sv[sj] = fma(-Li[tid], xi, sv[sj]);
+            }
+            if (tid == w) {
+                a.xs[i] = xi;
+                if (i - W >= 0) sv[si + 1 == W1 ? 0 : si + 1] = sr[ii];   // (i - W) mod (W + 1)
+            }
+            lds_barrier();
+            si = si == 0 ? W1 - 1 : si - 1;
+        }
+        __syncthreads();   // the window is refilled next
+    }
+    for (int n = tid; n < a.n_nodes; n += kBandBlock) {
+        const int P = a.pos[n];
+        if (P < 0) continue;
+        double dn[7];
+        for (int c = 0; c < 7; ++c) dn[c] = a.xs[7 * (int64_t)P + c];
+        const Sim3d Sn = sim3_mul(sim3_exp(dn), sim3_load(a.S + 13 * (int64_t)n));
         sim3_store(Sn, a.S + 13 * (int64_t)n);
     }
 }

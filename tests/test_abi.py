@@ -38,6 +38,15 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(s[0] for s in _abi.SIGNATURES) == names
 
 
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    for name, val in (("FL_MAX_PASSES", _abi.MAX_PASSES), ("FL_PGO_MAX_BAND_NODES", _abi.PGO_MAX_BAND_NODES),
+                      ("FL_PGO_SOLVER_AUTO", _abi.PGO_SOLVER_AUTO), ("FL_PGO_SOLVER_CG", _abi.PGO_SOLVER_CG),
+                      ("FL_PGO_SOLVER_DIRECT", _abi.PGO_SOLVER_DIRECT)):
+        m = re.search(r"#define\s+%s\s+(\d+)" % name, src)
+        assert m and int(m.group(1)) == val, name
+
+
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.Sim3) == 64
     assert ctypes.sizeof(_abi.Pinhole) == 32
@@ -46,7 +55,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.Refine) == 48
     assert ctypes.sizeof(_abi.Pass) == 80
     assert ctypes.sizeof(_abi.PoseGraph) == 40
-    assert ctypes.sizeof(_abi.PgoParams) == 48
+    assert ctypes.sizeof(_abi.PgoParams) == 56
 
 
 def _batch(n_kf=2, n_mp=10, n_kp=(5, 7), dense=True):
