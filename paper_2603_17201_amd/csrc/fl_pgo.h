@@ -460,9 +460,10 @@ __device__ __forceinline__ void lds_barrier() {
 // slot.  The threads form G = 512 / W admission groups; group k mod G admits
 // at column k the row it loaded into a register G columns earlier, so the
 // loads' latency is spread over G columns.  Back substitution walks the rows
-// of L upwards, staged into the LDS window W rows at a time, with a ring of
-// W + 1 right-hand-side entries (the slots read and written in one step are
-// then all different).
+// of L upwards, staged into the LDS window W rows at a time together with
+// each row's 1 / L(i,i) (a step then multiplies instead of dividing), with a
+// ring of W + 1 right-hand-side entries (the slots read and written in one
+// step are then all different).
 __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     extern __shared__ __align__(16) unsigned char s_mem[];
     __shared__ double s_w[kBandBlock / kWave];
@@ -473,6 +474,7 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     double* win = (double*)s_mem;      // [W][W]
     double* sv = win + W * W;          // [W + 1]
     double* sr = sv + W + 1;           // [W] right-hand sides of a back-substitution chunk
+    double* sd = sr + W;               // [W] 1 / L(i,i) of the chunk's rows
 
     double part = 0.0;
     for (int k = tid; k < E; k += kBandBlock)
@@ -576,12 +578,15 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
             const int ii = idx / W;
             win[idx] = a.band[(int64_t)(top - ii) * W + idx % W];
         }
-        for (int ii = tid; ii < nrow; ii += kBandBlock) sr[ii] = top - ii - W >= 0 ? a.rhs[top - ii - W] : 0.0;
+        for (int ii = tid; ii < nrow; ii += kBandBlock) {
+            sr[ii] = top - ii - W >= 0 ? a.rhs[top - ii - W] : 0.0;
+            sd[ii] = 1.0 / a.band[(int64_t)(top - ii) * W + w];
+        }
         __syncthreads();
         for (int ii = 0; ii < nrow; ++ii) {
             const int i = top - ii;
             const double* Li = win + ii * W;
-            const double xi = sv[si] / Li[w];
+            const double xi = sv[si] * sd[ii];
             if (tid < w && i - w + tid >= 0) {
                 int sj = si - w + tid;   // slot of row i - w + tid
                 if (sj < 0) sj += W1;
