@@ -292,11 +292,14 @@ int orc_search_fuse(int n_kf, const int32_t* kp_offset, const float* kp_xy, cons
  * projection, visibility, predicted octave and candidate set in double
  * precision from the same (float) inputs and compare with float32:
  *   out[0] = pairs whose visibility, pred or candidate set differ
- *   out[1] = pairs lying within eps px of an image or window edge (FP64):
- *            |u|, |u-W|, |v|, |v-H| < eps, or a keypoint with an eligible
- *            octave whose x or y is within eps of a box edge while the other
- *            coordinate is inside the (eps-widened) box
+ *   out[1] = pairs with a keypoint within eps px of an edge of the (FP64)
+ *            window: an eligible-octave keypoint whose x (or y) is within
+ *            eps of a box edge while its y (or x) lies in the box widened
+ *            by eps (the window-edge cases the bound is stated for)
  *   out[2] = pairs examined
+ *   out[3] = pairs whose FP64 projection lies within eps px of an image
+ *            edge: |u|, |u-W|, |v|, |v-H| < eps (the visibility boundary;
+ *            such a pair is not examined for window edges)
  */
 int orc_census_fp64(int n_kf, const int32_t* kp_offset, const float* kp_xy, const int8_t* kp_oct,
                     const int32_t* kp_owner, const float* kf_sim3, const float* kf_cam,
@@ -311,7 +314,7 @@ int orc_census_fp64(int n_kf, const int32_t* kp_offset, const float* kp_xy, cons
         sf64[n] = pow((double)P->scale_factor, (double)n);
         sf[n] = (float)sf64[n];
     }
-    int64_t n_diff = 0, n_near = 0, n_exam = 0;
+    int64_t n_diff = 0, n_near = 0, n_exam = 0, n_image = 0;
     for (int k = 0; k < n_kf; ++k) {
         const int kp0 = kp_offset[k];
         const int nkp = kp_offset[k + 1] - kp0;
@@ -370,7 +373,7 @@ int orc_census_fp64(int n_kf, const int32_t* kp_offset, const float* kp_xy, cons
                 }
                 RAD = (double)P->win_px * sf64[pred64];
                 if (fabs(U) < eps || fabs(U - K[4]) < eps || fabs(V) < eps || fabs(V - K[5]) < eps) {
-                    ++n_near;
+                    ++n_image;
                     if (vis32 != vis64) ++n_diff;
                     continue;
                 }
@@ -398,6 +401,7 @@ int orc_census_fp64(int n_kf, const int32_t* kp_offset, const float* kp_xy, cons
     out[0] = n_diff;
     out[1] = n_near;
     out[2] = n_exam;
+    out[3] = n_image;
     return 0;
 }
 

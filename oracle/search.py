@@ -117,13 +117,18 @@ def search_fuse(src, params=None, use_grid: bool = False, use_dmax: bool = True,
     return out
 
 
-def census_fp64(src, params=None, eps: float = 1e-3):
-    """(pairs whose float32 and float64 visibility / octave / candidate set
-    differ, pairs within eps px of an image or window edge, pairs examined)."""
+def census_fp64(src, params=None, eps: float = 1e-3, overrides: dict | None = None):
+    """FP64 boundary census of every valid, unobserved pair: a dict with
+    n_diff (pairs whose float32 and float64 visibility, octave or candidate
+    set differ), n_near_window (a keypoint within eps px of a window edge),
+    n_near_image (the projection within eps px of an image edge) and n
+    (pairs examined)."""
     lib = _load()
     L = _layout(src)
+    if overrides:
+        L.update(overrides)
     P = _params(params if params is not None else src.params)
-    out = np.zeros(3, np.int64)
+    out = np.zeros(4, np.int64)
     rc = lib.orc_census_fp64(
         ctypes.c_int(L["n_kf"]), _ptr(L["kp_offset"]), _ptr(L["kp_xy"]), _ptr(L["kp_oct"]),
         _ptr(L["kp_owner"]), _ptr(L["kf_sim3"]), _ptr(L["kf_cam"]), _ptr(L["kf_event"]),
@@ -132,7 +137,7 @@ def census_fp64(src, params=None, eps: float = 1e-3):
         _ptr(out))
     if rc != 0:
         raise ValueError("oracle rejected the parameters")
-    return int(out[0]), int(out[1]), int(out[2])
+    return dict(n_diff=int(out[0]), n_near_window=int(out[1]), n=int(out[2]), n_near_image=int(out[3]))
 
 
 def hamming256(a: np.ndarray, b: np.ndarray) -> int:

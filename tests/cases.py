@@ -102,3 +102,17 @@ def with_near_duplicates(ev, frac=0.4, flips=(2, 10), seed=7):
         kp_owner=np.concatenate([ev.kp_owner, np.full(len(pick), -1, np.int32)]),
         kp_offset=np.array([0, n0 + len(pick)], dtype=ev.kp_offset.dtype),
         name=ev.name + "+dup")
+
+
+def census_case():
+    """The hand-worked census fixture: (event, eps, expected counts)."""
+    with open(os.path.join(GOLDEN, "census_hand_case.json")) as f:
+        g = json.load(f)
+    pts, kps = g["points"], g["keypoints"]
+    n = len(pts)
+    ev = single_kf_event(
+        xyz=[p["xyz"] for p in pts], desc=np.zeros((n, 32), np.uint8), dmax=np.ones(n),
+        ids=[p["id"] for p in pts], kp_xy=[k["xy"] for k in kps], kp_oct=[k["octave"] for k in kps],
+        kp_desc=np.zeros((len(kps), 32), np.uint8), kp_owner=[k["owner"] for k in kps],
+        sim3_16=g["sim3"], cam8=g["camera"], params=LoopParams(**g["params"]), name="census")
+    return ev, g["eps"], g["expected"]
