@@ -314,6 +314,19 @@ int fl_sim3_inverse(fl_ctx* ctx, const double* S_in, double* S_out, fl_sim3* S32
 int fl_sim3_exp_mul(fl_ctx* ctx, const double* xi, const double* S_in, double* S_out, fl_sim3* S32_out,
                     hipStream_t stream);
 
+/* Gradient of a loss L(S) with respect to the tangent coordinates xi of
+ * S = exp(xi) S0 (the Sim3 refinement of Sec. IV-C differentiated with
+ * respect to its parameters, Sec. IV-F): given g = dL/d(left perturbation
+ * of S) from fl_reproj_residual_bwd at S, out = scale * J_l(xi)^T g, where
+ * J_l(xi) = sum_k ad(xi)^k / (k+1)! is the Sim3 left Jacobian
+ * (exp(xi + d) = exp(J_l(xi) d) exp(xi) to first order).  xi, g, out:
+ * device float64 [7] in the order (omega, upsilon, sigma); scale: device
+ * float64 [1], or NULL for 1.  The series is summed to float64 rounding for
+ * |omega| <= pi and |sigma| of order one.  out may alias g.
+ * Errors: FL_EINVAL for NULL xi, g or out. */
+int fl_sim3_grad_xi(fl_ctx* ctx, const double* xi, const double* g, const double* scale, double* out,
+                    hipStream_t stream);
+
 /* One Gauss-Newton / Levenberg-Marquardt step: solve (H + lambda diag(H)) d = -g
  * by float64 Cholesky (g [7], H [28] upper as above, device), then
  * S <- exp(d) S in place (device [13]) and S32 (device, may be NULL) <- its
@@ -426,6 +439,15 @@ int fl_valu_rate(fl_ctx* ctx, int32_t iters, double* lane_ops_per_s /* host */, 
  * entries (0 restores the default) so that their overflow paths, full scans
  * of the pair outputs, run.  Results are unchanged. */
 int fl_debug_set_list_cap(fl_ctx* ctx, int32_t cap);
+
+/* Test hooks of the refinement's tagged partial sums (host-only, no GPU
+ * needed): the 32-bit tag a launch with device epoch `epoch` gives step
+ * `step` (0 <= step < 1000; the epoch is decremented by every table fetch,
+ * so launch L of a context has epoch -L mod 2^32), and whether the partial
+ * sums are zeroed before the launch numbered `launches` (1, 2, ... since the
+ * last epoch reset).  Between two clears no two launches share a tag. */
+uint32_t fl_debug_refine_tag(uint32_t epoch, int32_t step);
+int fl_debug_refine_rows_cleared(uint32_t launches);
 
 #ifdef __cplusplus
 }

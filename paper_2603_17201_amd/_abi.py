@@ -122,6 +122,7 @@ SIGNATURES = [
     ("fl_pose_graph_optimize", c_int32, [c_void_p, ctypes.POINTER(PoseGraph), ctypes.POINTER(PgoParams), c_void_p]),
     ("fl_sim3_inverse", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fl_sim3_exp_mul", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("fl_sim3_grad_xi", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("fl_gn_step", c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     ("fl_get_tuning", c_int32, [c_void_p, ctypes.POINTER(Tuning)]),
     ("fl_set_tuning", c_int32, [c_void_p, ctypes.POINTER(Tuning)]),
@@ -133,6 +134,8 @@ SIGNATURES = [
     ("fl_get_profile", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]),
     ("fl_valu_rate", c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double), c_void_p]),
     ("fl_debug_set_list_cap", c_int32, [c_void_p, c_int32]),
+    ("fl_debug_refine_tag", ctypes.c_uint32, [ctypes.c_uint32, c_int32]),
+    ("fl_debug_refine_rows_cleared", c_int32, [ctypes.c_uint32]),
 ]
 
 _lib = None

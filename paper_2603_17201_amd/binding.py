@@ -413,6 +413,16 @@ class Context:
                                          self._stream(stream)), "fl_sim3_exp_mul")
         return S_out, S32
 
+    def sim3_grad_xi(self, xi, g, scale=None, out=None, stream=None):
+        """scale * J_l(xi)^T g: the gradient with respect to xi of S = exp(xi) S0
+        from the left-perturbation gradient g at S (device float64 tensors)."""
+        if out is None:
+            out = torch.empty(7, dtype=torch.float64, device=self.device)
+        _check(self._lib.fl_sim3_grad_xi(self._h, _ptr(xi, torch.float64, "xi", 8), _ptr(g, torch.float64, "g", 8),
+                                         _ptr(scale, torch.float64, "scale", 8), _ptr(out, torch.float64, "out", 8),
+                                         self._stream(stream)), "fl_sim3_grad_xi")
+        return out
+
     def gn_step(self, g, H, S, S32=None, lam: float = 0.0, stream=None):
         _check(self._lib.fl_gn_step(self._h, _ptr(g, torch.float64, "g", 8), _ptr(H, torch.float64, "H", 8),
                                     float(lam), _ptr(S, torch.float64, "S", 8), _ptr(S32, torch.float32, "S32", 16),
@@ -474,15 +484,18 @@ class Sim3Residual(torch.autograd.Function):
     """loss = sum_i Huber(|pi(T_k exp(xi) S0 X_i) - uv_i|).
 
     forward(xi [7] f64, S0 [13] f64, xyz, uv, kf_idx, kf_T, cam8, delta, ctx)
-    The backward is the hand-written kernel: it returns grad_out * g where g
-    is the gradient with respect to a left perturbation of S = exp(xi) S0,
-    which equals dL/dxi at xi = 0 (re-anchor S0 between steps)."""
+    The backward is the hand-written kernel pair: the residual backward
+    gives g, the gradient with respect to a left perturbation of
+    S = exp(xi) S0, and fl_sim3_grad_xi turns it into dL/dxi =
+    grad_out * J_l(xi)^T g (J_l the Sim3 left Jacobian; the identity at
+    xi = 0)."""
 
     @staticmethod
     def forward(fctx, xi, S0, xyz, uv, kf_idx, kf_T, cam8, delta, flctx: Context):
-        S, S32 = flctx.sim3_exp_mul(xi.detach().contiguous(), S0.contiguous())
+        xi = xi.detach().contiguous()
+        S, S32 = flctx.sim3_exp_mul(xi, S0.contiguous())
         _, _, loss = flctx.residual_fwd(xyz, uv, kf_idx, kf_T, S32, cam8, delta, want_r=False)
-        fctx.save_for_backward(xyz, uv, S32)
+        fctx.save_for_backward(xyz, uv, S32, xi)
         fctx.kf_idx = kf_idx
         fctx.kf_T = kf_T
         fctx.cam8 = cam8
@@ -492,7 +505,9 @@ class Sim3Residual(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, grad_out):
-        xyz, uv, S32 = fctx.saved_tensors
+        xyz, uv, S32, xi = fctx.saved_tensors
         g, _ = fctx.flctx.residual_bwd(xyz, uv, fctx.kf_idx, fctx.kf_T, S32, fctx.cam8, fctx.delta, 1.0,
                                        want_H=False)
-        return (g * grad_out, None, None, None, None, None, None, None, None)
+        scale = grad_out.detach().to(torch.float64).contiguous().reshape(1)
+        gx = fctx.flctx.sim3_grad_xi(xi, g, scale)
+        return (gx, None, None, None, None, None, None, None, None)

@@ -696,15 +696,39 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     return FL_OK;
 }
 
-// Count launches; when the device epoch (decremented by every table fetch)
-// is about to run out, reset every claim and the epoch.
+// Fill n 32-bit words with a value (used in place of memset nodes, which a
+// caller's stream capture would record).
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u32(void* p, size_t bytes, uint32_t v, hipStream_t stream) {
+    const size_t n = bytes / 4;
+    if (n == 0) return;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(256), 0, stream, (uint32_t*)p, n, v);
+}
+
+// Count launches.  When the device epoch (decremented by every table fetch)
+// is about to run out, reset every claim and the epoch.  The refinement's
+// partial-sum rows are zeroed whenever their tags are about to repeat
+// (every 2^kTagEpochBits launches) and at every epoch reset.
 int next_epoch(fl_ctx* c, hipStream_t stream) {
     if (++c->launches >= 0xFFFFFFF0u) {
-        FL_HIP(hipMemsetAsync(c->claims.p, 0xFF, c->claims.size, stream));
-        FL_HIP(hipMemsetAsync((char*)c->ctrs.p + 32, 0, 4, stream));
-        if (c->part.p) FL_HIP(hipMemsetAsync(c->part.p, 0, c->part.size, stream));
+        fill_u32(c->claims.p, c->claims.size, 0xFFFFFFFFu, stream);
+        fill_u32((char*)c->ctrs.p + 32, 4, 0u, stream);
+        if (c->part.p) fill_u32(c->part.p, c->part.size, 0u, stream);
         c->launches = 1;
+    } else if (refine_rows_cleared_before(c->launches) && c->part.p) {
+        // a refinement of this context still running on another stream would
+        // lose its rows: let it finish first (once per 2^22 launches)
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        FL_HIP(hipStreamIsCapturing(stream, &cs));
+        if (cs == hipStreamCaptureStatusNone) FL_HIP(hipDeviceSynchronize());
+        fill_u32(c->part.p, c->part.size, 0u, stream);
     }
+    FL_HIP(hipGetLastError());
     return FL_OK;
 }
 
@@ -1461,6 +1485,15 @@ int fl_sim3_exp_mul(fl_ctx* c, const double* xi, const double* S_in, double* S_o
     return FL_OK;
 }
 
+int fl_sim3_grad_xi(fl_ctx* c, const double* xi, const double* g, const double* scale, double* out,
+                    hipStream_t stream) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if (!xi || !g || !out) return fail(FL_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(sim3_grad_xi_kernel, dim3(1), dim3(64), 0, stream, xi, g, scale, out);
+    FL_HIP(hipGetLastError());
+    return FL_OK;
+}
+
 int fl_gn_step(fl_ctx* c, const double* g, const double* H, double lambda, double* S, fl_sim3* S32,
                hipStream_t stream) {
     if (!c) return fail(FL_EINVAL, "ctx is NULL");
@@ -1655,6 +1688,10 @@ int fl_valu_rate(fl_ctx* c, int32_t iters, double* lane_ops_per_s, hipStream_t s
     *lane_ops_per_s = (double)grid * block * (double)iters * 16.0 / ((double)ms * 1e-3);
     return FL_OK;
 }
+
+uint32_t fl_debug_refine_tag(uint32_t epoch, int32_t step) { return refine_tag(epoch, step); }
+
+int fl_debug_refine_rows_cleared(uint32_t launches) { return refine_rows_cleared_before(launches) ? 1 : 0; }
 
 int fl_debug_set_list_cap(fl_ctx* c, int32_t cap) {
     if (!c || cap < 0) return fail(FL_EINVAL, "bad argument");

@@ -268,6 +268,21 @@ __device__ __forceinline__ bool owner_lookup(const int32_t* __restrict__ table, 
     return false;
 }
 
+// Tag of the refinement's partial-sum words: the low kTagEpochBits bits of
+// the launch epoch (decremented by every table fetch) above ten bits of
+// step number (step + 1 < 1024).  Tags repeat every 2^kTagEpochBits
+// launches, so the host zeroes the partial-sum rows before every launch
+// whose count is a multiple of that period (refine_rows_cleared_before):
+// between two clears no two launches share a tag, and a zeroed word (tag 0)
+// matches none.
+constexpr uint32_t kTagEpochBits = 22;
+__host__ __device__ constexpr uint32_t refine_tag(uint32_t epoch, int step) {
+    return (epoch << 10) | (uint32_t)(step + 1);
+}
+__host__ __device__ constexpr bool refine_rows_cleared_before(uint32_t launches) {
+    return (launches & ((1u << kTagEpochBits) - 1u)) == 0u;
+}
+
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
 
 // Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8

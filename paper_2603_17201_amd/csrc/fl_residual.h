@@ -665,6 +665,67 @@ __global__ void sim3_exp_mul_kernel(const double* __restrict__ xi, const double*
     if (S32) sim3_to_f32(S, S32);
 }
 
+// Gradient with respect to the coordinates xi of S = exp(xi) S0, from the
+// gradient g with respect to a left perturbation of S: exp(xi + d) equals
+// exp(J_l(xi) d) exp(xi) to first order, so dL/dxi = J_l(xi)^T g, with the
+// left Jacobian J_l(xi) = sum_k ad(xi)^k / (k + 1)!.  For xi = (w, u, sig)
+// (omega, upsilon, sigma) the commutator of the 4x4 generators gives, in
+// the rows and columns (omega, upsilon, sigma),
+//   ad(xi) = [ [w]x        0          0 ]
+//            [ [u]x   [w]x + sig I   -u ]
+//            [ 0           0          0 ].
+// The series is summed in float64 until a term's largest entry falls below
+// 1e-18 of the sum's (at most 64 terms; |w| <= pi and |sig| of order one
+// converge in about 25).  out = scale * J_l^T g (scale: device, may be null).
+__global__ void sim3_grad_xi_kernel(const double* __restrict__ xi, const double* __restrict__ g,
+                                    const double* __restrict__ scale, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double A[49];
+    for (int i = 0; i < 49; ++i) A[i] = 0.0;
+    const double w0 = xi[0], w1 = xi[1], w2 = xi[2], u0 = xi[3], u1 = xi[4], u2 = xi[5], sg = xi[6];
+    auto set_hat = [&](int r, int c, double a0, double a1, double a2) {   // [a]x at block (r, c)
+        A[(r + 0) * 7 + c + 1] = -a2;
+        A[(r + 0) * 7 + c + 2] = a1;
+        A[(r + 1) * 7 + c + 0] = a2;
+        A[(r + 1) * 7 + c + 2] = -a0;
+        A[(r + 2) * 7 + c + 0] = -a1;
+        A[(r + 2) * 7 + c + 1] = a0;
+    };
+    set_hat(0, 0, w0, w1, w2);
+    set_hat(3, 0, u0, u1, u2);
+    set_hat(3, 3, w0, w1, w2);
+    for (int i = 3; i < 6; ++i) A[i * 7 + i] += sg;
+    A[3 * 7 + 6] = -u0;
+    A[4 * 7 + 6] = -u1;
+    A[5 * 7 + 6] = -u2;
+    // J = sum_k T_k with T_0 = I, T_k = A T_{k-1} / (k + 1)
+    double T[49], J[49], N[49];
+    for (int i = 0; i < 49; ++i) T[i] = J[i] = (i % 8 == 0) ? 1.0 : 0.0;
+    for (int k = 1; k < 64; ++k) {
+        double tmax = 0.0, jmax = 0.0;
+        const double f = 1.0 / (double)(k + 1);
+        for (int r = 0; r < 7; ++r)
+            for (int c = 0; c < 7; ++c) {
+                double v = 0.0;
+                for (int m = 0; m < 7; ++m) v = fma(A[r * 7 + m], T[m * 7 + c], v);
+                N[r * 7 + c] = v * f;
+            }
+        for (int i = 0; i < 49; ++i) {
+            T[i] = N[i];
+            J[i] += N[i];
+            tmax = fmax(tmax, fabs(N[i]));
+            jmax = fmax(jmax, fabs(J[i]));
+        }
+        if (tmax <= 1e-18 * jmax) break;
+    }
+    const double sc = scale ? *scale : 1.0;
+    for (int c = 0; c < 7; ++c) {
+        double v = 0.0;
+        for (int r = 0; r < 7; ++r) v = fma(J[r * 7 + c], g[r], v);
+        out[c] = sc * v;
+    }
+}
+
 // S_inv = S^-1 = (R^T, -R^T t / s, 1 / s) in float64, and its float32 form.
 __global__ void sim3_inverse_kernel(const double* __restrict__ S_in, double* __restrict__ S_out,
                                     fl_sim3* __restrict__ S32) {
@@ -806,7 +867,7 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
     const float delta = h.huber_delta;
     const float tau = h.outlier_px;
     const int tid = threadIdx.x;
-    const uint32_t tag0 = *h.epoch << 10;   // tag of step it: tag0 | (it + 1), it < 1000
+    const uint32_t epoch = *h.epoch;
     for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
         const int ev = unit / B, b = unit % B;
         const EventDesc ed = h.ev[ev];
@@ -957,7 +1018,7 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                 // workgroup writes only after reading all rows of step it.
                 const size_t slot = ((size_t)(seq & 1) * n_units + (size_t)ev * B);   // rows of this step: Be
                 unsigned long long* rows = h.refine_rows + slot * kRefWords;
-                const uint32_t tag = tag0 | (uint32_t)(seq + 1);
+                const uint32_t tag = refine_tag(epoch, seq);
                 if (tid < 2 * NV) {
                     const unsigned long long bits = (unsigned long long)__double_as_longlong(s_out[tid >> 1]);
                     const uint32_t half = (tid & 1) ? (uint32_t)bits : (uint32_t)(bits >> 32);

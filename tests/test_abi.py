@@ -159,3 +159,29 @@ def test_missing_library_fails_loudly(tmp_path):
             _abi.load(str(tmp_path / "nope.so"))
         finally:
             _abi._lib = saved
+
+
+def test_refine_tags_never_repeat_between_clears(lib):
+    # The refinement's partial-sum words carry a 32-bit tag of (launch epoch,
+    # step); the epoch of launch L is -L mod 2^32.  Across every clear of the
+    # rows and around the 2^22 wrap of the tag's epoch bits, two launches that
+    # share a tag must have a clear between them.
+    period = 1 << 22
+    clears = [L for L in range(1, 3 * period + 8) if L % (period // 4) < 3 or L % period > period - 3
+              if lib.fl_debug_refine_rows_cleared(L)]
+    assert clears == [period, 2 * period, 3 * period]
+    for step in (0, 7, 999):
+        seen = {}
+        last_clear = 0
+        for L in list(range(1, 40)) + list(range(period - 40, period + 40)) + list(range(2 * period - 5, 2 * period + 40)):
+            if lib.fl_debug_refine_rows_cleared(L):
+                last_clear = L
+            tag = lib.fl_debug_refine_tag((-L) & 0xFFFFFFFF, step)
+            assert tag != 0   # a zeroed word never matches
+            if tag in seen:
+                assert seen[tag] < last_clear <= L, (L, seen[tag], last_clear)
+            seen[tag] = L
+    # launches one period apart share their tag (hence the clears)
+    assert lib.fl_debug_refine_tag((-5) & 0xFFFFFFFF, 3) == lib.fl_debug_refine_tag((-5 - period) & 0xFFFFFFFF, 3)
+    # distinct steps of one launch have distinct tags
+    assert len({lib.fl_debug_refine_tag(12345, s) for s in range(1000)}) == 1000

@@ -148,6 +148,54 @@ def test_autograd_function(ctx, c4):
     assert np.max(np.abs(fd[big] - g64[big])) / np.max(np.abs(g64)) < 1e-3
 
 
+def test_sim3_grad_xi_matches_numerical_left_jacobian(ctx):
+    # J_l(xi) column i is d/dh log(exp(xi + h e_i) exp(xi)^-1) at h = 0
+    # (central differences of scipy's expm / logm in float64); the kernel
+    # returns scale * J_l^T g.
+    rng = np.random.default_rng(21)
+    for scale in (1e-6, 0.05, 0.3, 1.0):
+        xi = rng.normal(size=7) * scale
+        h = 1e-6
+        J = np.zeros((7, 7))
+        for i in range(7):
+            e = np.zeros(7)
+            e[i] = h
+            Sp = sim3.compose(sim3.exp(xi + e), sim3.inverse(sim3.exp(xi)))
+            Sm = sim3.compose(sim3.exp(xi - e), sim3.inverse(sim3.exp(xi)))
+            J[:, i] = (sim3.log(Sp) - sim3.log(Sm)) / (2 * h)
+        g = rng.normal(size=7)
+        out = ctx.sim3_grad_xi(t(xi), t(g), t(np.array([2.5]))).cpu().numpy()
+        assert rel(out, 2.5 * J.T @ g) < 1e-7, scale
+        out1 = ctx.sim3_grad_xi(t(xi), t(g)).cpu().numpy()
+        assert rel(out1, J.T @ g) < 1e-7, scale
+
+
+def test_autograd_function_away_from_zero(ctx, c4):
+    # At xi = 0.05 on every component the Function's gradient is dL/dxi of
+    # L(exp(xi) S0): compared with float64 central differences of the
+    # oracle's loss at the same xi.
+    import paper_2603_17201_amd as fl
+    S0 = t(c4["S0"])
+    xi1 = np.full(7, 0.05)
+    xi = torch.tensor(xi1, dtype=torch.float64, device=dev(), requires_grad=True)
+    loss = fl.Sim3Residual.apply(xi, S0, t(c4["xyz"]), t(c4["uv"]), None, None, c4["cam"], c4["huber_delta"], ctx)
+    (3.0 * loss).backward()
+    h = 1e-5
+    fd = np.zeros(7)
+    for i in range(7):
+        e = np.zeros(7)
+        e[i] = h
+        fd[i] = (R.loss_at(xi1 + e, c4["S0"], c4["xyz"], c4["uv"], None, None, c4["cam"], c4["huber_delta"])
+                 - R.loss_at(xi1 - e, c4["S0"], c4["xyz"], c4["uv"], None, None, c4["cam"], c4["huber_delta"])) / (2 * h)
+    L64 = R.loss_at(xi1, c4["S0"], c4["xyz"], c4["uv"], None, None, c4["cam"], c4["huber_delta"])
+    assert abs(loss.item() - L64) / L64 < REL
+    assert rel(xi.grad.cpu().numpy(), 3.0 * fd) < REL
+    # the left-perturbation gradient alone is not dL/dxi here
+    g_left, _, _ = R.grad_hess(sim3.compose(sim3.exp(xi1), c4["S0"]), c4["xyz"], c4["uv"], None, None, c4["cam"],
+                               c4["huber_delta"])
+    assert rel(g_left, fd) > 10 * REL
+
+
 def test_refine_events_matches_oracle_gn(ctx):
     import paper_2603_17201_amd as fl
     ev = synth.gen_c2()
