@@ -340,23 +340,31 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
  * Sim3s, 13 doubles each: R row-major, t, s); an edge (i, j) measures
  * M_ij ~ S_j S_i^-1 and contributes e_ij = log(M_ij^-1 S_j S_i^-1) to
  * F = sum e^T e.  Nodes move by left perturbations S_i <- exp(d_i) S_i; the
- * Jacobians of e_ij are central differences (step fd_step) of the float64
- * Sim3 algebra; each of `iters` steps solves (H + lambda diag H) d = -g over
- * the free nodes, by one of two solvers (`solver`):
+ * Jacobians of e_ij are exact (J_j = J_l(e)^-1 Ad(M^-1),
+ * J_i = -J_l(e)^-1 Ad(M^-1 S_j S_i^-1), J_l the Sim3 left Jacobian; the
+ * paper obtains exact derivatives by automatic differentiation).  The poses
+ * are optimised by `iters` Levenberg-Marquardt iterations (Sec. VI): each
+ * solves (H + lambda diag H) d = -g at the accepted poses and evaluates F at
+ * the candidate exp(d_i) S_i, which is taken if F decreases (lambda / 10,
+ * at least 1e-12) and refused otherwise (lambda x 10, at most 1e12; the
+ * linearisation is kept).  lambda = 0 takes every Gauss-Newton step.  The
+ * solve is one of two (`solver`):
  *  - direct: the free nodes are renumbered by reverse Cuthill-McKee on the
  *    host; when no edge then spans more than FL_PGO_MAX_BAND_NODES - 1
  *    positions, the banded H is factored by float64 Cholesky in one
  *    workgroup and solved exactly (cg_used = 0; a pivot that is not
- *    positive reports -1 and leaves that step's poses unchanged);
+ *    positive reports -1 and refuses that iteration's candidate);
  *  - block-Jacobi preconditioned conjugate gradients (at most cg_iters,
  *    stopping when |r| <= cg_tol |g|).  This solve runs one workgroup per
  *    compute unit, all resident together and synchronised by a grid
  *    barrier; other work on the device at the same time can keep them from
- *    being resident, and a barrier wait that runs past its bound reports the
- *    step as failed (cg_used = -1, the poses of that step unchanged) instead
- *    of blocking.
+ *    being resident, and a barrier wait that runs past its bound in any
+ *    workgroup reports the iteration as failed (cg_used = -1) and refuses
+ *    its candidate instead of blocking.
  * A graph with no edges or no free node takes the conjugate gradients under
- * every setting.  Deterministic: every sum has a fixed order. */
+ * every setting.  Deterministic: every sum has a fixed order; the host
+ * enqueues the same kernels every iteration and never waits for the
+ * device (the damping and the decision stay in device memory). */
 #define FL_PGO_MAX_BAND_NODES 12   /* widest band of the direct solver, in keyframes */
 #define FL_PGO_SOLVER_AUTO 0       /* direct when the band fits, else conjugate gradients */
 #define FL_PGO_SOLVER_CG 1
@@ -371,14 +379,16 @@ typedef struct {
 } fl_pose_graph;
 
 typedef struct {
-    int32_t iters;          /* outer steps, 0..1000 */
+    int32_t iters;          /* Levenberg-Marquardt iterations, 0..1000 */
     int32_t cg_iters;       /* 1..100000 */
-    double lambda;          /* >= 0 */
+    double lambda;          /* first damping, >= 0; 0: Gauss-Newton */
     double cg_tol;          /* >= 0 */
-    double fd_step;         /* > 0; 0: 1e-5 */
-    double* cost;           /* device [iters + 1] (may be NULL): F before each step and after the last */
-    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each step
-                               (0 for a direct solve), -1: failed */
+    double* cost;           /* device [iters + 1] (may be NULL): F of the accepted poses before each
+                               iteration and after the last */
+    int32_t* cg_used;       /* device [iters] (may be NULL): conjugate-gradient iterations of each
+                               iteration (0 for a direct solve), -1: the solve failed */
+    double* lambdas;        /* device [iters] (may be NULL): the damping each iteration solved with */
+    uint8_t* accepted;      /* device [iters] (may be NULL): 1 when the iteration's candidate was taken */
     int32_t solver;         /* FL_PGO_SOLVER_* */
     int32_t reserved;       /* 0 */
 } fl_pgo_params;

@@ -106,13 +106,14 @@ def normal_equations(S, edges, M, col, n_free):
     return g, H, F
 
 
-def optimize(S0, edges, M, fixed, iters=10, lam=1e-4, history=None, lambdas=None, accepted=None):
+def optimize(S0, edges, M, fixed, iters=10, lam=1e-4, history=None, lambdas=None, accepted=None, candidates=None):
     """`iters` Levenberg-Marquardt iterations from damping `lam` over the
     free nodes (fixed[i] true holds node i).  lam = 0 takes plain
     Gauss-Newton steps, every one accepted.  Returns the poses.  Optional
     lists receive: `history` F of the accepted poses before every iteration
     and at the end, `lambdas` the damping each iteration solved with,
-    `accepted` whether each iteration's candidate was taken."""
+    `accepted` whether each iteration's candidate was taken, `candidates`
+    F of each iteration's candidate."""
     S = np.array(S0, np.float64, copy=True)
     n = len(S)
     free = np.nonzero(~np.asarray(fixed, bool))[0]
@@ -131,7 +132,10 @@ def optimize(S0, edges, M, fixed, iters=10, lam=1e-4, history=None, lambdas=None
         C = S.copy()
         for a in free:
             C[a] = sim3.compose(sim3.exp(d[7 * col[a]:7 * col[a] + 7]), S[a])
-        take = lam == 0.0 or cost(C, edges, M) < F
+        Fc = cost(C, edges, M)
+        if candidates is not None:
+            candidates.append(Fc)
+        take = lam == 0.0 or Fc < F
         if accepted is not None:
             accepted.append(bool(take))
         if take:

@@ -69,8 +69,8 @@ class PoseGraph(ctypes.Structure):
 
 class PgoParams(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("cg_iters", c_int32), ("lam", c_double), ("cg_tol", c_double),
-                ("fd_step", c_double), ("cost", c_void_p), ("cg_used", c_void_p), ("solver", c_int32),
-                ("reserved", c_int32)]
+                ("cost", c_void_p), ("cg_used", c_void_p), ("lambdas", c_void_p), ("accepted", c_void_p),
+                ("solver", c_int32), ("reserved", c_int32)]
 
 
 PGO_MAX_BAND_NODES = 12   # FL_PGO_MAX_BAND_NODES

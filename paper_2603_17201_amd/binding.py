@@ -369,27 +369,34 @@ class Context:
                                         _ptr(H, torch.float64, "H", 8), self._stream(stream)), name)
         return g, H
 
-    def pose_graph_optimize(self, S, M, edges, fixed=None, iters: int = 10, cg_iters: int = 500, lam: float = 0.0,
-                            cg_tol: float = 1e-10, fd_step: float = 1e-5, solver: int = 0, stream=None):
-        """Essential-graph optimisation in place: S device float64 [n, 13],
+    def pose_graph_optimize(self, S, M, edges, fixed=None, iters: int = 10, cg_iters: int = 500, lam: float = 1e-4,
+                            cg_tol: float = 1e-10, solver: int = 0, history: bool = False, stream=None):
+        """Essential-graph optimisation in place (Levenberg-Marquardt from
+        damping lam; lam = 0: Gauss-Newton): S device float64 [n, 13],
         M device float64 [E, 13], edges host int32 [E, 2], fixed host bool
         [n] or None (node 0 held); solver 0 (direct when the reordered band
         fits, else conjugate gradients), 1 (conjugate gradients) or 2
         (direct).  Returns (cost [iters + 1], cg_used [iters], 0 for a
-        direct step) as device tensors."""
+        direct solve) as device tensors, and with history=True also
+        (lambdas [iters], accepted [iters])."""
         n = int(S.shape[0])
         e = np.ascontiguousarray(edges, np.int32).reshape(-1, 2)
         fx = None if fixed is None else np.ascontiguousarray(fixed, np.uint8).reshape(n)
         cost = torch.empty(iters + 1, dtype=torch.float64, device=self.device)
         used = torch.empty(max(iters, 1), dtype=torch.int32, device=self.device)
+        lams = torch.empty(max(iters, 1), dtype=torch.float64, device=self.device)
+        acc = torch.empty(max(iters, 1), dtype=torch.uint8, device=self.device)
         G = PoseGraph(n, int(e.shape[0]), _ptr(S, torch.float64, "S", 8, self.device),
                       _ptr(M, torch.float64, "M", 8, self.device), e.ctypes.data_as(ctypes.c_void_p),
                       None if fx is None else fx.ctypes.data_as(ctypes.c_void_p))
-        Pp = PgoParams(int(iters), int(cg_iters), float(lam), float(cg_tol), float(fd_step),
+        Pp = PgoParams(int(iters), int(cg_iters), float(lam), float(cg_tol),
                        _ptr(cost, torch.float64, "cost", 8, self.device), _ptr(used, torch.int32, "cg_used"),
+                       _ptr(lams, torch.float64, "lambdas", 8, self.device), _ptr(acc, torch.uint8, "accepted", 1),
                        int(solver), 0)
         _check(self._lib.fl_pose_graph_optimize(self._h, ctypes.byref(G), ctypes.byref(Pp), self._stream(stream)),
                "fl_pose_graph_optimize")
+        if history:
+            return cost, used[:iters], lams[:iters], acc[:iters]
         return cost, used[:iters]
 
     def sim3_inverse(self, S_in, S_out=None, S32=None, stream=None):

@@ -1294,8 +1294,6 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     if (P->cg_iters < 1 || P->cg_iters > 100000) return fail(FL_ERANGE, "cg_iters %d outside [1, 100000]", P->cg_iters);
     if (!(P->lambda >= 0.0) || !std::isfinite(P->lambda)) return fail(FL_EINVAL, "lambda must be finite and >= 0");
     if (!(P->cg_tol >= 0.0) || !std::isfinite(P->cg_tol)) return fail(FL_EINVAL, "cg_tol must be finite and >= 0");
-    const double h = P->fd_step == 0.0 ? 1e-5 : P->fd_step;
-    if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_EINVAL, "fd_step must be finite and > 0");
     if (P->solver < FL_PGO_SOLVER_AUTO || P->solver > FL_PGO_SOLVER_DIRECT || P->reserved != 0)
         return fail(FL_EINVAL, "solver %d / reserved %d", P->solver, P->reserved);
     // incident edges of every node, in edge order (the gathers' fixed order),
@@ -1404,6 +1402,9 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     const size_t L_band = take(direct ? sizeof(double) * (size_t)band_vs * band_w : 0);
     const size_t L_rhs = take(direct ? sizeof(double) * (size_t)band_vs : 0);
     const size_t L_xs = take(direct ? sizeof(double) * (size_t)band_vs : 0);
+    const size_t L_lm = take(sizeof(double) * kLmWords);
+    const size_t L_Sc = take(sizeof(double) * 13 * (size_t)N);
+    const size_t L_ec = take(sizeof(double) * (size_t)E);
     int rc = c->pgo.ensure(off_b);
     if (rc) return rc;
     char* base = (char*)c->pgo.p;
@@ -1428,8 +1429,6 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     a.adj_off = a.edges + 2 * (size_t)E;
     a.adj = a.adj_off + (N + 1);
     a.fixed = (const uint8_t*)(base + L_fix);
-    a.fd_step = h;
-    a.lambda = P->lambda;
     a.cg_iters = P->cg_iters;
     a.cg_tol = P->cg_tol;
     a.e = (double*)(base + L_e);
@@ -1446,9 +1445,20 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     a.band = (double*)(base + L_band);
     a.rhs = (double*)(base + L_rhs);
     a.xs = (double*)(base + L_xs);
+    a.lm = (double*)(base + L_lm);
+    a.S_c = (double*)(base + L_Sc);
+    a.ecost = (double*)(base + L_ec);
     a.cost = P->cost;
     a.cg_used = P->cg_used;
-    const int jac_grid = std::max(1, (int)((7 * (int64_t)E + kPgoJacBlock - 1) / kPgoJacBlock));
+    a.lambdas = P->lambdas;
+    a.accepted = P->accepted;
+    // Every iteration enqueues the same kernels: the damping, the decision
+    // and whether to relinearise are read from the device state.
+    const int edge_grid = std::max(1, (E + kPgoBlock - 1) / kPgoBlock);
+    const int jac_grid = std::max(1, (E + kPgoJacBlock - 1) / kPgoJacBlock);
+    const int node_grid = std::max(1, (int)((13 * (int64_t)N + kPgoBlock - 1) / kPgoBlock));
+    hipLaunchKernelGGL(pgo_edge_cost_kernel, dim3(edge_grid), dim3(kPgoBlock), 0, stream, a, (const double*)a.S);
+    hipLaunchKernelGGL(pgo_init_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a, P->lambda);
     for (int it = 0; it < P->iters; ++it) {
         a.step = it;
         if (E > 0) hipLaunchKernelGGL(pgo_jacobian_kernel, dim3(jac_grid), dim3(kPgoJacBlock), 0, stream, a);
@@ -1458,12 +1468,13 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
             hipLaunchKernelGGL(pgo_band_solve_kernel, dim3(1), dim3(kBandBlock),
                                sizeof(double) * ((size_t)band_w * band_w + 3 * band_w + 1), stream, a);
         } else {
-            FL_HIP(hipMemsetAsync(a.bar, 0, sizeof(uint32_t), stream));
+            fill_u32(a.bar, sizeof(uint32_t), 0u, stream);
             hipLaunchKernelGGL(pgo_solve_kernel, dim3(solve_grid), dim3(kPgoBlock), 0, stream, a);
         }
+        hipLaunchKernelGGL(pgo_edge_cost_kernel, dim3(edge_grid), dim3(kPgoBlock), 0, stream, a, (const double*)a.S_c);
+        hipLaunchKernelGGL(pgo_decide_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);
+        hipLaunchKernelGGL(pgo_accept_kernel, dim3(node_grid), dim3(kPgoBlock), 0, stream, a);
     }
-    a.step = P->iters;
-    if (P->cost) hipLaunchKernelGGL(pgo_cost_kernel, dim3(1), dim3(kPgoBlock), 0, stream, a);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }

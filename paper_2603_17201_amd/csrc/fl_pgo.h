@@ -4,13 +4,19 @@
 // the essential graph (Sec. III-B, Sec. IV-F).  Nodes are keyframe poses S_i
 // (world -> camera Sim3s); an edge (i, j) measures M_ij ~ S_j S_i^-1 and
 // contributes e_ij = log(M_ij^-1 S_j S_i^-1) to F = sum e^T e.  Nodes move by
-// left perturbations S_i <- exp(d_i) S_i.  The Jacobians of e_ij with respect
-// to d_i and d_j are central differences of the float64 Sim3 algebra.  Each
-// outer step solves (H + lambda diag H) d = -g by block-Jacobi preconditioned
-// conjugate gradients.
+// left perturbations S_i <- exp(d_i) S_i.  The Jacobians are exact (the
+// paper differentiates automatically): with E = M^-1 S_j S_i^-1 and
+// e = log E, J_j = J_l(e)^-1 Ad(M^-1) and J_i = -J_l(e)^-1 Ad(E), J_l the
+// Sim3 left Jacobian.  The poses are optimised by Levenberg-Marquardt
+// (Sec. VI): an iteration solves (H + lambda diag H) d = -g at the accepted
+// poses, evaluates F at the candidate exp(d_i) S_i and takes it when F
+// decreases (lambda / 10; the next iteration relinearises) or refuses it
+// (lambda x 10; the linearisation is kept).  The damping and the decision
+// live in device memory, so the host enqueues the same kernels every
+// iteration and never waits.
 //
-// Per outer step pgo_jacobian_kernel runs over (edge, column) items on every
-// CU, then one of two solves:
+// Per iteration pgo_jacobian_kernel runs one thread per edge (it exits at
+// once after a refusal), then one of two solves writes the candidate:
 //  - direct (the paper's is a direct LDL^T): with the free nodes renumbered
 //    so that every edge spans at most b positions (reverse Cuthill-McKee on
 //    the host), H is a band of W = 7 (b + 1) scalars.  pgo_band_assemble_kernel
@@ -18,12 +24,15 @@
 //    pgo_band_solve_kernel, one workgroup, factors the band by Cholesky with
 //    the forward substitution folded in, keeping the W rows still being
 //    updated in an LDS window that slides down the matrix, then back-
-//    substitutes and updates the nodes;
+//    substitutes;
 //  - pgo_solve_kernel, one co-resident workgroup per CU synchronised by a
 //    grid barrier, which gathers g and the diagonal blocks per node over its
-//    incident edges (fixed order, no floating-point atomics), runs block-
+//    incident edges (fixed order, no floating-point atomics) and runs block-
 //    Jacobi preconditioned conjugate gradients with fixed-order float64
-//    reductions and updates the nodes.
+//    reductions.
+// pgo_edge_cost_kernel then evaluates every edge at the candidate,
+// pgo_decide_kernel sums F in a fixed order and decides, and
+// pgo_accept_kernel copies an accepted candidate into the poses.
 
 #pragma once
 
@@ -46,8 +55,6 @@ struct PgoArgs {
     const int32_t* adj_off;     // [n_nodes + 1] incident edges of each node
     const int32_t* adj;         // [2 n_edges] 2 * edge + (1 if the node is the edge's j)
     const uint8_t* fixed;       // [n_nodes]
-    double fd_step;
-    double lambda;
     int32_t cg_iters;
     double cg_tol;
     int32_t step;               // outer step index (cost and count outputs)
@@ -72,10 +79,23 @@ struct PgoArgs {
     double* band;
     double* rhs;                // [Vs]
     double* xs;                 // [Vs]
+    // Levenberg-Marquardt state (device): lm[kLmLambda] damping of the next
+    // solve, lm[kLmF] F of the accepted poses, lm[kLmRelin] 1 when the next
+    // iteration relinearises, lm[kLmFail] set by a solve that failed,
+    // lm[kLmUsed] conjugate-gradient iterations of the last solve,
+    // lm[kLmTake] 1 when the last candidate was accepted
+    double* lm;
+    double* S_c;                // [n_nodes][13] candidate poses
+    double* ecost;              // [n_edges] e^T e of each edge at the evaluated poses
     // outputs (may be null)
     double* cost;               // [iters + 1]
     int32_t* cg_used;           // [iters]
+    double* lambdas;            // [iters]
+    uint8_t* accepted;          // [iters]
 };
+
+enum : int { kLmLambda = 0, kLmF = 1, kLmRelin = 2, kLmFail = 3, kLmUsed = 4, kLmTake = 5, kLmWords = 8 };
+constexpr double kLmLambdaMin = 1e-12, kLmLambdaMax = 1e12;
 
 // A fixed-order block sum that may be called back to back (the closing
 // barrier keeps the next call's partials from overwriting ones still read).
@@ -90,40 +110,136 @@ __device__ inline void pgo_edge_error(const Sim3d& Si, const Sim3d& Sj, const Si
     sim3_log(sim3_mul(Minv, sim3_mul(Sj, sim3_inv(Si))), e);
 }
 
-// Column c of J_i and J_j of edge k (item k * 7 + c); item c = 0 also
-// writes e.
-__global__ __launch_bounds__(kPgoJacBlock) void pgo_jacobian_kernel(PgoArgs a) {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= 7 * (int64_t)a.n_edges) return;
-    const int k = (int)(item / 7), c = (int)(item % 7);
-    const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
-    const Sim3d Si = sim3_load(a.S + 13 * (int64_t)i);
-    const Sim3d Sj = sim3_load(a.S + 13 * (int64_t)j);
-    const Sim3d Minv = sim3_inv(sim3_load(a.M + 13 * (int64_t)k));
-    if (c == 0) {
-        double e[7];
-        pgo_edge_error(Si, Sj, Minv, e);
-        for (int r = 0; r < 7; ++r) a.e[(int64_t)r * a.n_edges + k] = e[r];
+// The Sim3 left Jacobian J_l(x) = sum_k ad(x)^k / (k + 1)! of x = (w, u, sig)
+// in its block form: with ad(x) = [[W, 0, 0], [U, W + sig I, -u], [0, 0, 0]]
+// (W = [w]x, U = [u]x) every term T_k = ad(x) T_{k-1} / (k + 1) keeps the
+// blocks T11, T21, T22 and the column t23 (rows 3..5 of column 6); the
+// sum runs until a term's entries fall below 1e-18 of the sum's (at most
+// 64 terms).  J = [[J11, 0, 0], [J21, J22, j23], [0, 0, 1]].
+struct LeftJac {
+    double J11[9], J21[9], J22[9], j23[3];
+};
+
+__device__ inline void mul33(const double* A, const double* B, double* C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = fma(A[3 * i], B[j], fma(A[3 * i + 1], B[3 + j], A[3 * i + 2] * B[6 + j]));
+}
+
+__device__ inline void inv33(const double* A, double* B) {
+    const double c0 = A[4] * A[8] - A[5] * A[7], c1 = A[5] * A[6] - A[3] * A[8], c2 = A[3] * A[7] - A[4] * A[6];
+    const double id = 1.0 / (A[0] * c0 + A[1] * c1 + A[2] * c2);
+    B[0] = c0 * id;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    B[3] = c1 * id;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    B[6] = c2 * id;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+}
+
+__device__ inline LeftJac sim3_left_jacobian(const double* x) {
+    double W[9], Wd[9], U[9], W2[9];
+    hat_sq(x[0], x[1], x[2], W, W2);
+    hat_sq(x[3], x[4], x[5], U, W2);
+    for (int i = 0; i < 9; ++i) Wd[i] = W[i] + ((i % 4 == 0) ? x[6] : 0.0);
+    double T11[9], T21[9], T22[9], t23[3];
+    LeftJac J;
+    for (int i = 0; i < 9; ++i) {
+        const double I = (i % 4 == 0) ? 1.0 : 0.0;
+        T11[i] = T22[i] = J.J11[i] = J.J22[i] = I;
+        T21[i] = J.J21[i] = 0.0;
     }
-    const double h = a.fd_step;
-    double d[7] = {0, 0, 0, 0, 0, 0, 0};
-    double ep[7], em[7];
-    for (int side = 0; side < 2; ++side) {
-        d[c] = h;
-        const Sim3d Pp = sim3_mul(sim3_exp(d), side ? Sj : Si);
-        d[c] = -h;
-        const Sim3d Pm = sim3_mul(sim3_exp(d), side ? Sj : Si);
-        d[c] = 0.0;
-        if (side) {
-            pgo_edge_error(Si, Pp, Minv, ep);
-            pgo_edge_error(Si, Pm, Minv, em);
-        } else {
-            pgo_edge_error(Pp, Sj, Minv, ep);
-            pgo_edge_error(Pm, Sj, Minv, em);
+    for (int i = 0; i < 3; ++i) t23[i] = J.j23[i] = 0.0;
+    for (int k = 1; k < 64; ++k) {
+        const double f = 1.0 / (double)(k + 1);
+        double N11[9], N21[9], N22[9], A[9], B[9], n23[3];
+        mul33(W, T11, N11);
+        mul33(U, T11, A);
+        mul33(Wd, T21, B);
+        for (int i = 0; i < 9; ++i) N21[i] = A[i] + B[i];
+        mul33(Wd, T22, N22);
+        for (int i = 0; i < 3; ++i) {
+            n23[i] = fma(Wd[3 * i], t23[0], fma(Wd[3 * i + 1], t23[1], Wd[3 * i + 2] * t23[2]));
+            if (k == 1) n23[i] -= x[3 + i];   // -u times row 6 of T_0 = I
         }
-        double* Jk = a.J + (int64_t)49 * side * a.n_edges + k;
-        for (int r = 0; r < 7; ++r) Jk[(int64_t)(7 * r + c) * a.n_edges] = (ep[r] - em[r]) / (2.0 * h);
+        double tmax = 0.0, jmax = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            T11[i] = N11[i] * f;
+            T21[i] = N21[i] * f;
+            T22[i] = N22[i] * f;
+            J.J11[i] += T11[i];
+            J.J21[i] += T21[i];
+            J.J22[i] += T22[i];
+            tmax = fmax(tmax, fmax(fabs(T11[i]), fmax(fabs(T21[i]), fabs(T22[i]))));
+            jmax = fmax(jmax, fmax(fabs(J.J11[i]), fmax(fabs(J.J21[i]), fabs(J.J22[i]))));
+        }
+        for (int i = 0; i < 3; ++i) {
+            t23[i] = n23[i] * f;
+            J.j23[i] += t23[i];
+            tmax = fmax(tmax, fabs(t23[i]));
+            jmax = fmax(jmax, fabs(J.j23[i]));
+        }
+        if (tmax <= 1e-18 * jmax) break;
     }
+    return J;
+}
+
+// P = sign * J^-1 Ad(S) for J = J_l (block lower triangular as above) and
+// Ad(S) = [[R, 0, 0], [[t]x R, sR, -t], [0, 0, 1]]: with K = J^-1,
+// K11 = J11^-1, K22 = J22^-1, K21 = -K22 J21 K11, k23 = -K22 j23,
+//   P11 = K11 R, P21 = K21 R + K22 [t]x R, P22 = s K22 R, p23 = k23 - K22 t,
+// row 6 = e6 (times sign).  Written as the 7x7 row-major P.
+__device__ inline void jl_inv_adjoint(const double* K11, const double* K21, const double* K22, const double* k23,
+                                      const Sim3d& S, double sign, double* P) {
+    double TR[9], Tx[9], W2[9], A[9], B[9];
+    hat_sq(S.t[0], S.t[1], S.t[2], Tx, W2);
+    mul33(Tx, S.R, TR);
+    for (int i = 0; i < 49; ++i) P[i] = 0.0;
+    mul33(K11, S.R, A);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) P[7 * r + c] = sign * A[3 * r + c];
+    mul33(K21, S.R, A);
+    mul33(K22, TR, B);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) P[7 * (3 + r) + c] = sign * (A[3 * r + c] + B[3 * r + c]);
+    mul33(K22, S.R, A);
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) P[7 * (3 + r) + 3 + c] = sign * S.s * A[3 * r + c];
+        const double kt = fma(K22[3 * r], S.t[0], fma(K22[3 * r + 1], S.t[1], K22[3 * r + 2] * S.t[2]));
+        P[7 * (3 + r) + 6] = sign * (k23[r] - kt);
+    }
+    P[48] = sign;
+}
+
+// e and the exact J_i, J_j of edge k (one thread per edge); nothing after a
+// refused step (the linearisation at the accepted poses is kept).
+__global__ __launch_bounds__(kPgoJacBlock) void pgo_jacobian_kernel(PgoArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_edges || a.lm[kLmRelin] == 0.0) return;
+    const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
+    const Sim3d Minv = sim3_inv(sim3_load(a.M + 13 * (int64_t)k));
+    const Sim3d Ed = sim3_mul(Minv, sim3_mul(sim3_load(a.S + 13 * (int64_t)j), sim3_inv(sim3_load(a.S + 13 * (int64_t)i))));
+    double e[7];
+    sim3_log(Ed, e);
+    for (int r = 0; r < 7; ++r) a.e[(int64_t)r * a.n_edges + k] = e[r];
+    const LeftJac J = sim3_left_jacobian(e);
+    double K11[9], K22[9], K21[9], k23[3], A[9];
+    inv33(J.J11, K11);
+    inv33(J.J22, K22);
+    mul33(J.J21, K11, A);
+    mul33(K22, A, K21);
+    for (int q = 0; q < 9; ++q) K21[q] = -K21[q];
+    for (int r = 0; r < 3; ++r) k23[r] = -fma(K22[3 * r], J.j23[0], fma(K22[3 * r + 1], J.j23[1], K22[3 * r + 2] * J.j23[2]));
+    double P[49];
+    jl_inv_adjoint(K11, K21, K22, k23, Ed, -1.0, P);   // J_i = -J_l^-1 Ad(E)
+    double* Ji = a.J + k;
+    for (int q = 0; q < 49; ++q) Ji[(int64_t)q * a.n_edges] = P[q];
+    jl_inv_adjoint(K11, K21, K22, k23, Minv, 1.0, P);  // J_j = J_l^-1 Ad(M^-1)
+    double* Jj = a.J + (int64_t)49 * a.n_edges + k;
+    for (int q = 0; q < 49; ++q) Jj[(int64_t)q * a.n_edges] = P[q];
 }
 
 // y += J^T v with J's entry 7 r + c at J[(7 r + c) st] and v's entry r at
@@ -237,10 +353,9 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
     int rb = 0;   // row buffer of the next reduction
     bool ok = true;
 
-    // cost, g, preconditioner blocks, r = -g, z = M^-1 r, p = z
-    double red3[3] = {0.0, 0.0, 0.0};   // F, |g|^2, r.z
-    for (int k = gtid; k < E; k += gnt)
-        for (int c = 0; c < 7; ++c) red3[0] = fma(a.e[(int64_t)c * E + k], a.e[(int64_t)c * E + k], red3[0]);
+    const double lambda = a.lm[kLmLambda];
+    // g, preconditioner blocks, r = -g, z = M^-1 r, p = z
+    double red3[3] = {0.0, 0.0, 0.0};   // (unused), |g|^2, r.z
     for (int n = gtid; n < N; n += gnt) {
         double gn[7] = {0, 0, 0, 0, 0, 0, 0};
         double D[49];
@@ -259,7 +374,7 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
                         D[7 * c1 + c2] = s;
                     }
             }
-            for (int c = 0; c < 7; ++c) D[8 * c] *= 1.0 + a.lambda;
+            for (int c = 0; c < 7; ++c) D[8 * c] *= 1.0 + lambda;
             if (!ldl7(D)) {
                 // no information on this node: hold it
                 for (int t = 0; t < 49; ++t) D[t] = 0.0;
@@ -287,7 +402,6 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
     }
     ok = pgo_grid_sum<3>(red3, a.red, rb, a.bar, seq, s_w);
     rb ^= 1;
-    if (gtid == 0 && a.cost) a.cost[a.step] = red3[0];
     const double gnorm2 = red3[1];
     double rz = red3[2];
 
@@ -334,15 +448,15 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
                     const int k = a.adj[t] >> 1, side = a.adj[t] & 1;
                     const double* Jk = a.J + (int64_t)49 * side * E + k;
                     add_JTv(Jk, a.u + k, E, qn);
-                    if (a.lambda > 0.0)
+                    if (lambda > 0.0)
                         for (int c = 0; c < 7; ++c)
                             for (int rr = 0; rr < 7; ++rr) {
                                 const double jv = Jk[(int64_t)(7 * rr + c) * E];
                                 dg[c] = fma(jv, jv, dg[c]);
                             }
                 }
-                if (a.lambda > 0.0)
-                    for (int c = 0; c < 7; ++c) qn[c] = fma(a.lambda * dg[c], pn[c], qn[c]);
+                if (lambda > 0.0)
+                    for (int c = 0; c < 7; ++c) qn[c] = fma(lambda * dg[c], pn[c], qn[c]);
             }
             for (int c = 0; c < 7; ++c) {
                 q[(int64_t)c * N + n] = qn[c];
@@ -380,15 +494,24 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_solve_kernel(PgoArgs a) {
         beta = red2[1] / rz;
         rz = red2[1];
     }
-    if (gtid == 0 && a.cg_used) a.cg_used[a.step] = ok ? used : -1;
-    if (!ok) return;
-    // S_n <- exp(x_n) S_n (each node by the thread that owns it)
+    // Any workgroup whose barrier wait ran out marks the solve failed; the
+    // decision, a later kernel, then refuses the candidate whatever the
+    // other workgroups wrote.
+    if (!ok) {
+        if (threadIdx.x == 0) a.lm[kLmFail] = 1.0;
+        return;
+    }
+    if (gtid == 0) a.lm[kLmUsed] = (double)used;
+    // candidate C_n = exp(x_n) S_n (each node by the thread that owns it)
     for (int n = gtid; n < N; n += gnt) {
-        if (a.fixed[n]) continue;
+        const Sim3d Sn = sim3_load(a.S + 13 * (int64_t)n);
+        if (a.fixed[n]) {
+            sim3_store(Sn, a.S_c + 13 * (int64_t)n);
+            continue;
+        }
         double d[7];
         for (int c = 0; c < 7; ++c) d[c] = x[(int64_t)c * N + n];
-        const Sim3d Sn = sim3_mul(sim3_exp(d), sim3_load(a.S + 13 * (int64_t)n));
-        sim3_store(Sn, a.S + 13 * (int64_t)n);
+        sim3_store(sim3_mul(sim3_exp(d), Sn), a.S_c + 13 * (int64_t)n);
     }
 }
 
@@ -436,7 +559,7 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_assemble_kernel(PgoArgs a
         row[w] = 1.0;
         gr = 0.0;
     } else {
-        row[w] *= 1.0 + a.lambda;
+        row[w] *= 1.0 + a.lm[kLmLambda];
     }
     a.rhs[R] = -gr;
 }
@@ -475,12 +598,6 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     double* sv = win + W * W;          // [W + 1]
     double* sr = sv + W + 1;           // [W] right-hand sides of a back-substitution chunk
     double* sd = sr + W;               // [W] 1 / L(i,i) of the chunk's rows
-
-    double part = 0.0;
-    for (int k = tid; k < E; k += kBandBlock)
-        for (int c = 0; c < 7; ++c) part = fma(a.e[(int64_t)c * E + k], a.e[(int64_t)c * E + k], part);
-    const double F = pgo_sum(part, s_w);
-    if (tid == 0 && a.cost) a.cost[a.step] = F;
 
     // this thread's (a, b) pairs of the phase-B triangle, a >= b in [0, w)
     int pk[kBandPairs];
@@ -563,8 +680,11 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
         sk = s1;
         kg = kg + 1 == G ? 0 : kg + 1;
     }
-    if (tid == 0 && a.cg_used) a.cg_used[a.step] = ok ? 0 : -1;
-    if (!ok) return;
+    if (!ok) {   // the same in every thread
+        if (tid == 0) a.lm[kLmFail] = 1.0;
+        return;
+    }
+    if (tid == 0) a.lm[kLmUsed] = 0.0;
     __syncthreads();   // L and y in global memory, visible to every thread
 
     const int W1 = W + 1;
@@ -601,29 +721,85 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
         }
         __syncthreads();   // the window is refilled next
     }
+    __syncthreads();   // every x in global memory
     for (int n = tid; n < a.n_nodes; n += kBandBlock) {
         const int P = a.pos[n];
-        if (P < 0) continue;
+        const Sim3d Sn = sim3_load(a.S + 13 * (int64_t)n);
+        if (P < 0) {
+            sim3_store(Sn, a.S_c + 13 * (int64_t)n);
+            continue;
+        }
         double dn[7];
         for (int c = 0; c < 7; ++c) dn[c] = a.xs[7 * (int64_t)P + c];
-        const Sim3d Sn = sim3_mul(sim3_exp(dn), sim3_load(a.S + 13 * (int64_t)n));
-        sim3_store(Sn, a.S + 13 * (int64_t)n);
+        sim3_store(sim3_mul(sim3_exp(dn), Sn), a.S_c + 13 * (int64_t)n);
     }
 }
 
-// Cost after the last step (e of the final poses, summed in fixed order).
-__global__ __launch_bounds__(kPgoBlock) void pgo_cost_kernel(PgoArgs a) {
-    __shared__ double s_w[kPgoBlock / kWave];
+// e^T e of every edge at the poses P (one thread per edge).
+__global__ __launch_bounds__(kPgoBlock) void pgo_edge_cost_kernel(PgoArgs a, const double* __restrict__ P) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_edges) return;
+    const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
+    double e[7];
+    pgo_edge_error(sim3_load(P + 13 * (int64_t)i), sim3_load(P + 13 * (int64_t)j),
+                   sim3_inv(sim3_load(a.M + 13 * (int64_t)k)), e);
+    double v = 0.0;
+    for (int c = 0; c < 7; ++c) v = fma(e[c], e[c], v);
+    a.ecost[k] = v;
+}
+
+// F = the edge costs summed in a fixed order (thread strides, then the block sum).
+__device__ inline double pgo_total_cost(const PgoArgs& a, double* s_w) {
     double part = 0.0;
-    for (int k = threadIdx.x; k < a.n_edges; k += blockDim.x) {
-        const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
-        double e[7];
-        pgo_edge_error(sim3_load(a.S + 13 * (int64_t)i), sim3_load(a.S + 13 * (int64_t)j),
-                       sim3_inv(sim3_load(a.M + 13 * (int64_t)k)), e);
-        for (int c = 0; c < 7; ++c) part = fma(e[c], e[c], part);
+    for (int k = threadIdx.x; k < a.n_edges; k += blockDim.x) part += a.ecost[k];
+    return block_sum_f64(part, s_w);
+}
+
+// Start: F of the starting poses (edge costs already evaluated), the first
+// damping, relinearise.
+__global__ __launch_bounds__(kPgoBlock) void pgo_init_kernel(PgoArgs a, double lambda0) {
+    __shared__ double s_w[kPgoBlock / kWave];
+    const double F = pgo_total_cost(a, s_w);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < kLmWords; ++q) a.lm[q] = 0.0;
+        a.lm[kLmLambda] = lambda0;
+        a.lm[kLmF] = F;
+        a.lm[kLmRelin] = 1.0;
+        if (a.cost) a.cost[0] = F;
     }
-    const double F = block_sum_f64(part, s_w);
-    if (threadIdx.x == 0 && a.cost) a.cost[a.step] = F;
+}
+
+// The decision of iteration a.step (edge costs of the candidate evaluated):
+// take the candidate if its F is below the accepted F (every candidate when
+// the damping is 0: Gauss-Newton) and the solve did not fail.
+__global__ __launch_bounds__(kPgoBlock) void pgo_decide_kernel(PgoArgs a) {
+    __shared__ double s_w[kPgoBlock / kWave];
+    const double Fc = pgo_total_cost(a, s_w);
+    if (threadIdx.x == 0) {
+        const double lam = a.lm[kLmLambda];
+        const bool fail = a.lm[kLmFail] != 0.0;
+        const bool take = !fail && (lam == 0.0 || Fc < a.lm[kLmF]);
+        if (a.lambdas) a.lambdas[a.step] = lam;
+        if (a.accepted) a.accepted[a.step] = take ? 1 : 0;
+        if (a.cg_used) a.cg_used[a.step] = fail ? -1 : (int32_t)a.lm[kLmUsed];
+        if (take) {
+            a.lm[kLmF] = Fc;
+            if (lam > 0.0) a.lm[kLmLambda] = fmax(lam * 0.1, kLmLambdaMin);
+        } else {
+            a.lm[kLmLambda] = fmin(lam * 10.0, kLmLambdaMax);
+        }
+        a.lm[kLmRelin] = take ? 1.0 : 0.0;
+        a.lm[kLmTake] = take ? 1.0 : 0.0;
+        a.lm[kLmFail] = 0.0;
+        if (a.cost) a.cost[a.step + 1] = a.lm[kLmF];
+    }
+}
+
+// An accepted candidate becomes the poses.
+__global__ __launch_bounds__(kPgoBlock) void pgo_accept_kernel(PgoArgs a) {
+    if (a.lm[kLmTake] == 0.0) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < 13 * (int64_t)a.n_nodes) a.S[q] = a.S_c[q];
 }
 
 }  // namespace fl

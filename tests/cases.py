@@ -116,3 +116,25 @@ def census_case():
         kp_desc=np.zeros((len(kps), 32), np.uint8), kp_owner=[k["owner"] for k in kps],
         sim3_16=g["sim3"], cam8=g["camera"], params=LoopParams(**g["params"]), name="census")
     return ev, g["eps"], g["expected"]
+
+
+def overshoot_graph():
+    """A 10-keyframe loop (synth.gen_pose_graph seed 14) whose start has three
+    free keyframes turned by 2-3 rad about random axes, moved by ~2 m and
+    rescaled: from there the first undamped steps overshoot (the candidate's
+    cost is 30-45% above the accepted one), so Levenberg-Marquardt refuses
+    them before it converges."""
+    import synth
+    from oracle import sim3
+    d = dict(synth.gen_pose_graph(n=10, seed=14, covis=2, n_loops=2))
+    rng = np.random.default_rng(0)
+    S0 = d["S0"].copy()
+    for node in rng.choice(np.arange(1, 10), 3, replace=False):
+        xi = np.zeros(7)
+        xi[:3] = rng.normal(size=3)
+        xi[:3] *= rng.uniform(2.0, 3.0) / np.linalg.norm(xi[:3])
+        xi[3:6] = rng.normal(size=3) * 2
+        xi[6] = rng.normal() * 0.8
+        S0[node] = sim3.compose(sim3.exp(xi), S0[node])
+    d["S0"] = S0
+    return d

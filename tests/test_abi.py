@@ -55,7 +55,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.Refine) == 48
     assert ctypes.sizeof(_abi.Pass) == 80
     assert ctypes.sizeof(_abi.PoseGraph) == 40
-    assert ctypes.sizeof(_abi.PgoParams) == 56
+    assert ctypes.sizeof(_abi.PgoParams) == 64
 
 
 def _batch(n_kf=2, n_mp=10, n_kp=(5, 7), dense=True):

@@ -132,12 +132,17 @@ def test_large_damping_barely_moves_and_rejects_raise_it():
     steps = [_err(pgo.optimize(d["S0"], d["edges"], d["M"], d["fixed"], iters=1, lam=lam), d["S0"])
              for lam in (1e-2, 1.0, 1e2, 1e9)]
     assert all(b < a for a, b in zip(steps, steps[1:])) and steps[-1] < 1e-6, steps
-    # a start 170 degrees off on one free node: the undamped step overshoots
-    S0 = d["S0"].copy()
-    S0[5] = sim3.compose(sim3.exp(np.array([0.0, 2.97, 0.0, 0.0, 0.0, 0.0, 0.0])), S0[5])
-    h, acc, lams = [], [], []
-    S = pgo.optimize(S0, d["edges"], d["M"], d["fixed"], iters=8, lam=1e-6, history=h, accepted=acc, lambdas=lams)
-    assert not all(acc), acc
-    k = acc.index(False)
-    assert lams[k + 1] == pytest.approx(10 * lams[k]) and h[k + 1] == h[k]
-    assert all(b <= a for a, b in zip(h, h[1:]))
+    # a start from which the undamped steps overshoot: refused, poses kept,
+    # damping up tenfold, with a margin far above rounding
+    from cases import overshoot_graph
+    d = overshoot_graph()
+    h, acc, lams, cand = [], [], [], []
+    pgo.optimize(d["S0"], d["edges"], d["M"], d["fixed"], iters=8, lam=1e-6, history=h, accepted=acc,
+                 lambdas=lams, candidates=cand)
+    assert acc == [True, False, False, False, False, True, True, True], acc
+    for k in range(8):
+        assert abs(cand[k] - h[k]) > 0.2 * h[k]          # every decision is far from a tie
+        assert (cand[k] < h[k]) == acc[k]
+        assert h[k + 1] == (cand[k] if acc[k] else h[k])
+        if k < 7:
+            assert lams[k + 1] == pytest.approx(lams[k] / 10 if acc[k] else 10 * lams[k])
