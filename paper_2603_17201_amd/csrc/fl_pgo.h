@@ -784,7 +784,7 @@ __global__ __launch_bounds__(kPgoBlock) void pgo_decide_kernel(PgoArgs a) {
         if (a.cg_used) a.cg_used[a.step] = fail ? -1 : (int32_t)a.lm[kLmUsed];
         if (take) {
             a.lm[kLmF] = Fc;
-            if (lam > 0.0) a.lm[kLmLambda] = fmax(lam * 0.1, kLmLambdaMin);
+            if (lam > 0.0) a.lm[kLmLambda] = fmax(lam / 10.0, kLmLambdaMin);   // lambda / 10, as the definition states
         } else {
             a.lm[kLmLambda] = fmin(lam * 10.0, kLmLambdaMax);
         }
