@@ -120,10 +120,13 @@ def optimize(S0, edges, M, fixed, iters=10, lam=1e-4, history=None, lambdas=None
     col = -np.ones(n, np.int64)
     col[free] = np.arange(len(free))
     lin = None
+    F = None   # F of the accepted poses: evaluated once, at the start or as the accepted candidate
     for _ in range(iters):
         if lin is None:
             lin = normal_equations(S, edges, M, col, len(free))
-        g, H, F = lin
+            if F is None:
+                F = lin[2]
+        g, H, _ = lin
         if history is not None:
             history.append(F)
         if lambdas is not None:
@@ -140,10 +143,11 @@ def optimize(S0, edges, M, fixed, iters=10, lam=1e-4, history=None, lambdas=None
             accepted.append(bool(take))
         if take:
             S = C
+            F = Fc
             lin = None
             lam = max(lam / 10.0, LAMBDA_MIN) if lam > 0.0 else 0.0
         else:
             lam = min(lam * 10.0, LAMBDA_MAX)
     if history is not None:
-        history.append(cost(S, edges, M))
+        history.append(cost(S, edges, M) if F is None else F)
     return S
