@@ -130,9 +130,10 @@ struct fl_ctx {
     uint32_t launches = 0;      // table fetches since the claims were last reset
     Pinned* pin_last = nullptr; // ring buffer of the last eager upload
     int stats = 0;
-    int add_cap_override = 0;   // test hook: >0 forces small ADD / match list capacities
+    int add_cap_override = 0;   // test hook: >0 forces small accepted-pair (and plain-path ADD) list capacities
     int prof = 0;               // record events around eager search and refinement kernels
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2];   // by FL_PROF_* class
+    std::vector<hipEvent_t> ev_pool;   // events of read profiles, reused (no event creation per launch)
     // captured graph and its key
     hipGraphExec_t gexec[kGraphRing] = {};   // replayed in turn
     Pinned gpin[kGraphRing];    // the pinned tables each graph fetches from
@@ -434,7 +435,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     std::vector<char>& blob = pr.blob;
     blob.clear();
     const size_t o_hdr = blob_take<BatchHdr>(blob, 1);
-    const size_t o_range = blob_take<int4>(blob, grid);
+    const size_t o_range = blob_take<WgRange>(blob, grid);
     const size_t o_kf = blob_take<KfDesc>(blob, n_vk);
     if (o_hdr != 0 || o_range != blob_range_offset() || o_kf != blob_kf_offset(grid))
         return fail(FL_EINVAL, "internal: table layout mismatch");
@@ -445,7 +446,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     EventDesc* evd = (EventDesc*)(blob.data() + o_ev);
 
     // keyframes, events, list regions, tiles
-    int64_t hash_total = 0, add_total = 0, list_total = 0;
+    int64_t hash_total = 0, list_total = 0;
     std::vector<double> tile_cost;    // cost of each keyframe's tiles (per tile)
     tile_cost.resize(n_vk);
     for (int e = 0; e < n_ev; ++e) {
@@ -488,14 +489,6 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
                 kd.n_pairs = B->pair_offset[k + 1] - B->pair_offset[k];
                 kd.tile_pairs = kf_tile[v];
                 kd.n_tiles = (int32_t)((kd.n_pairs + kd.tile_pairs - 1) / kd.tile_pairs);
-                // room for every pair: no provisional ADD can overflow the list, so
-                // the kernel resolves them without cache write-backs (the test
-                // hook's smaller caps exercise the overflow protocol)
-                int64_t acap = kd.n_pairs;
-                if (c->add_cap_override > 0) acap = std::min<int64_t>(acap, c->add_cap_override);
-                kd.add_off = (int32_t)add_total;
-                kd.add_cap = (int32_t)acap;
-                add_total += acap;
                 kd.pass = p;
                 kd.stage_key = k;
                 kd.claim_off = p * B->n_kp_total + kd.kp_off;
@@ -504,7 +497,11 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             }
         }
     }
-    if (add_total > INT32_MAX || list_total > INT32_MAX || hash_total > INT32_MAX)
+    // every (keyframe, pass) descriptor's pairs, in tile order: the index
+    // space of the workgroups' list regions
+    int64_t n_virtual = 0;
+    for (int v = 0; v < n_vk; ++v) n_virtual += kfd[v].n_pairs;
+    if (n_virtual > INT32_MAX || list_total > INT32_MAX || hash_total > INT32_MAX)
         return fail(FL_ERANGE, "batch too large for the workspace indexing");
     // tile order: keyframes in batch order
     int32_t* order = (int32_t*)(blob.data() + o_order);
@@ -519,8 +516,17 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     prefix[n_vk] = (int32_t)n_tiles;
     if (n_tiles != n_tiles_all) return fail(FL_EINVAL, "internal: tile count mismatch");
     // the workgroups' contiguous, cost-balanced tile ranges
-    int4* wr = (int4*)(blob.data() + o_range);
+    WgRange* wr = (WgRange*)(blob.data() + o_range);
     {
+        // first pair of tile t in the list index space (t = n_tiles: its end)
+        std::vector<int64_t> vbase(n_vk + 1, 0);
+        for (int k = 0; k < n_vk; ++k) vbase[k + 1] = vbase[k] + kfd[order[k]].n_pairs;
+        auto tile_pair = [&](int64_t t) -> int64_t {
+            if (t >= n_tiles) return n_virtual;
+            const int s = (int)(std::upper_bound(prefix, prefix + n_vk + 1, (int32_t)t) - prefix) - 1;
+            const KfDesc& kd = kfd[order[s]];
+            return vbase[s] + std::min<int64_t>((t - prefix[s]) * (int64_t)kd.tile_pairs, kd.n_pairs);
+        };
         // cumulative cost at each tile boundary, by keyframe
         std::vector<double> kcum(n_vk + 1, 0.0);
         for (int k = 0; k < n_vk; ++k) kcum[k + 1] = kcum[k] + tile_cost[k] * kfd[k].n_tiles;
@@ -565,9 +571,23 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
             const int64_t t0 = bound[i];
             int slot = (int)(std::upper_bound(prefix, prefix + n_vk + 1, (int32_t)t0) - prefix) - 1;
             slot = std::min(std::max(slot, 0), std::max(n_vk - 1, 0));
-            wr[wg_of[i]] = make_int4((int)t0, (int)bound[i + 1], slot, order[slot]);
+            WgRange& g = wr[wg_of[i]];
+            g.t0 = (int32_t)t0;
+            g.t1 = (int32_t)bound[i + 1];
+            g.slot = slot;
+            g.kf = order[slot];
+            const int64_t p0 = tile_pair(t0), p1 = tile_pair(bound[i + 1]);
+            g.priv_off = (int32_t)p0;
+            g.priv_cap = (int32_t)(p1 - p0);
         }
-        for (int i = ge; i < grid; ++i) wr[i] = make_int4((int)n_tiles, (int)n_tiles, 0, order[0]);
+        for (int i = ge; i < grid; ++i) {
+            WgRange& g = wr[i];
+            g.t0 = g.t1 = (int32_t)n_tiles;
+            g.slot = 0;
+            g.kf = order[0];
+            g.priv_off = (int32_t)n_virtual;
+            g.priv_cap = 0;
+        }
     }
 
     // workspace layout
@@ -588,7 +608,9 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     const size_t L_desc = take(global_grid ? 32 * (size_t)B->n_kp_total : 0);
     const size_t L_ck = take(global_grid ? sizeof(int32_t) * (size_t)B->n_kp_total : 0);
     const size_t L_hash = take(global_grid ? sizeof(int32_t) * (size_t)hash_total : 0);
-    const size_t L_add = take(sizeof(AddRef) * (size_t)add_total);
+    const size_t L_add = take(sizeof(AddRef) * (size_t)n_virtual);
+    const size_t L_add_count = take(sizeof(uint32_t) * (size_t)grid);
+    const size_t L_stage = take(refine ? sizeof(MatchRec) * (size_t)n_virtual : 0);
     const size_t L_match = take(sizeof(MatchRec) * (size_t)list_total);
     const int refine_blocks = std::max(1, std::min(kRefMaxB, kRefineGrid / std::max(1, n_ev)));
     const size_t n_rows = 2 * (size_t)n_ev * refine_blocks;
@@ -603,7 +625,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     rc = c->claims.ensure(sizeof(unsigned long long) * (size_t)std::max(n_pass * B->n_kp_total, 1), 0xFF);
     if (rc) return rc;
     const void* old_ctrs = c->ctrs.p;
-    rc = c->ctrs.ensure(64 + sizeof(uint32_t) * ((size_t)kKfCtrs * n_vk + (size_t)kEvCtrs * n_ev), 0x00);
+    rc = c->ctrs.ensure(64 + sizeof(uint32_t) * (size_t)kEvCtrs * n_ev, 0x00);
     if (rc) return rc;
     if (c->ctrs.p != old_ctrs && old_ctrs != nullptr) {
         // a fresh counter block restarts the epoch: every stored claim must be reset too
@@ -654,7 +676,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.ev = (const EventDesc*)(base + L_blob + o_ev);
     h.kf_order = (const int32_t*)(base + L_blob + o_order);
     h.tile_prefix = (const int32_t*)(base + L_blob + o_prefix);
-    h.wg_range = (const int4*)(base + L_blob + o_range);
+    h.wg_range = (const WgRange*)(base + L_blob + o_range);
     h.kp_xy = B->kp_xy;
     h.kp_oct = B->kp_octave;
     h.kp_desc = B->kp_desc;
@@ -672,9 +694,10 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.claim = (unsigned long long*)c->claims.p;
     h.stats_out = (unsigned long long*)cb;
     h.epoch = (const uint32_t*)(cb + 32);
-    h.kf_ctr = (uint32_t*)(cb + 64);
-    h.ev_ctr = (uint32_t*)(cb + 64 + sizeof(uint32_t) * (size_t)kKfCtrs * n_vk);
+    h.ev_ctr = (uint32_t*)(cb + 64);
     h.add_list = (AddRef*)(base + L_add);
+    h.add_count = (uint32_t*)(base + L_add_count);
+    h.match_stage = (MatchRec*)(base + L_stage);
     h.match_list = (MatchRec*)(base + L_match);
     h.refine_blocks = refine_blocks;
     h.refine_scan = refine_scan ? 1 : 0;
@@ -779,6 +802,17 @@ void launch_fused_m(int mode, bool stats, const BatchHdr* dh, int grid, size_t l
 }
 
 
+// An event for a profiled launch: from the context's pool, else new.
+int prof_event(fl_ctx* c, hipEvent_t* e) {
+    if (!c->ev_pool.empty()) {
+        *e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return FL_OK;
+    }
+    FL_HIP(hipEventCreate(e));
+    return FL_OK;
+}
+
 int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t s, bool eager, bool stats) {
     if (pr.mode == kModeGlobal) {
         const int pg = eager ? std::max(1, std::min(pr.hdr->n_kf, kPrepGrid)) : kPrepGrid;
@@ -787,8 +821,9 @@ int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t
     const bool timed = eager && c->prof;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (timed) {
-        FL_HIP(hipEventCreate(&t0));
-        FL_HIP(hipEventCreate(&t1));
+        int rc = prof_event(c, &t0);
+        if (!rc) rc = prof_event(c, &t1);
+        if (rc) return rc;
         FL_HIP(hipEventRecord(t0, s));
     }
     if (pr.ppl == 1) launch_fused_m<1>(pr.mode, stats, dh, pr.grid, pr.lds, s);
@@ -799,7 +834,7 @@ int launch_search(fl_ctx* c, const Prepared& pr, const BatchHdr* dh, hipStream_t
         c->prof_ev[FL_PROF_SEARCH].emplace_back(t0, t1);
     }
     if (!pr.resolve_in_refine) {
-        const int rg = eager ? std::max(1, std::min(pr.hdr->n_kf, kResolveGrid)) : kResolveGrid;
+        const int rg = eager ? std::max(1, std::min(pr.hdr->n_wg, kResolveGrid)) : kResolveGrid;
         hipLaunchKernelGGL(resolve_adds_kernel, dim3(rg), dim3(kResolveBlock), 0, s, dh);
     }
     FL_HIP(hipGetLastError());
@@ -811,8 +846,9 @@ int launch_refine(fl_ctx* c, const BatchHdr* dh, int n_iters, int variant, hipSt
     const bool timed = eager && c->prof;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (timed) {
-        FL_HIP(hipEventCreate(&t0));
-        FL_HIP(hipEventCreate(&t1));
+        int rc = prof_event(c, &t0);
+        if (!rc) rc = prof_event(c, &t1);
+        if (rc) return rc;
         FL_HIP(hipEventRecord(t0, s));
     }
     // variant: bit 0 Levenberg-Marquardt, bit 1 more than one round
@@ -914,6 +950,7 @@ void fl_destroy(fl_ctx* c) {
     for (auto& g : c->gexec)
         if (g) hipGraphExecDestroy(g);
     clear_profile(c);
+    for (auto e : c->ev_pool) hipEventDestroy(e);
     for (auto& p : c->pin)
         if (p.p) hipHostFree(p.p);
     for (auto& f : c->fence)
@@ -953,10 +990,13 @@ int fl_build_grid(fl_ctx* c, int32_t n_kp, const float* kp_xy, const fl_pinhole*
 }
 
 
-int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc, const float* mp_dmax,
-                   const int32_t* mp_id, const fl_keyframe* kf, const fl_sim3* S, const fl_pinhole* K,
-                   const fl_params* P, const fl_fuse_out* out, hipStream_t stream) {
-    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+}  // extern "C"
+
+namespace {
+
+// Checks of a plain search call (before any launch).
+int check_plain(int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc, const fl_keyframe* kf, const fl_sim3* S,
+                const fl_pinhole* K, const fl_params* P, const fl_fuse_out* out) {
     int rc = check_params(P);
     if (rc) return rc;
     rc = check_cam(K, "keyframe");
@@ -973,36 +1013,56 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
         return fail(FL_EINVAL, "descriptor arrays must be 16-byte aligned");
     if (n_mp > 0 && (!out->best_idx || !out->best_dist || !out->second_dist || !out->decision || !out->target))
         return fail(FL_EINVAL, "output arrays must not be NULL");
-    if (n_mp == 0) return FL_OK;
-    const int cells = P->grid_cols * P->grid_rows;
-    const int n_kp = kf->n_kp;
-    const int hsize = next_pow2(2 * n_kp);
-    int64_t cap = std::min<int64_t>(n_mp, std::max<int64_t>(2 * (int64_t)n_kp, 4096));
-    if (c->add_cap_override > 0) cap = std::min<int64_t>(cap, c->add_cap_override);
+    return FL_OK;
+}
+
+// Scratch layout of a plain search: the keyframe's grid (when the caller
+// gives none), owner hash set, ADD claims, the ADD counter and the ADD list.
+struct PlainLayout {
+    int hsize = 0;
+    int64_t cap = 0;
+    size_t o_cs = 0, o_ck = 0, o_hash = 0, o_claim = 0, o_ctr = 0, o_list = 0, bytes = 0;
+};
+
+PlainLayout plain_layout(int32_t n_mp, int n_kp, int cells, int cap_override) {
+    PlainLayout L;
+    L.hsize = next_pow2(2 * n_kp);
+    L.cap = std::min<int64_t>(n_mp, std::max<int64_t>(2 * (int64_t)n_kp, 4096));
+    if (cap_override > 0) L.cap = std::min<int64_t>(L.cap, cap_override);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
         off = align_up(off + bytes, 256);
         return o;
     };
-    const size_t o_cs = take(sizeof(int32_t) * (cells + 1));
-    const size_t o_ck = take(sizeof(int32_t) * (size_t)std::max(n_kp, 1));
-    const size_t o_hash = take(sizeof(int32_t) * (size_t)hsize);
-    const size_t o_claim = take(sizeof(int32_t) * (size_t)std::max(n_kp, 1));
-    const size_t o_ctr = take(sizeof(uint32_t) * 4);
-    const size_t o_list = take(sizeof(AddRef) * (size_t)cap);
-    rc = c->plain.ensure(off);
-    if (rc) return rc;
-    char* base = (char*)c->plain.p;
+    L.o_cs = take(sizeof(int32_t) * (cells + 1));
+    L.o_ck = take(sizeof(int32_t) * (size_t)std::max(n_kp, 1));
+    L.o_hash = take(sizeof(int32_t) * (size_t)L.hsize);
+    L.o_claim = take(sizeof(int32_t) * (size_t)std::max(n_kp, 1));
+    L.o_ctr = take(sizeof(uint32_t) * 4);
+    L.o_list = take(sizeof(AddRef) * (size_t)L.cap);
+    L.bytes = off;
+    return L;
+}
+
+// The plain search's launches with its scratch at `base` (laid out as L).
+// Every scratch word the kernels read is written first in the same call:
+// plain_prep_kernel resets the hash set, the claims and the counter, and
+// the grid is built when the caller gives none.
+int plain_launch(char* base, const PlainLayout& L, int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc,
+                 const float* mp_dmax, const int32_t* mp_id, const fl_keyframe* kf, const fl_sim3* S,
+                 const fl_pinhole* K, const fl_params* P, const fl_fuse_out* out, hipStream_t stream) {
+    const int cells = P->grid_cols * P->grid_rows;
+    const int n_kp = kf->n_kp;
     PlainArgs a{};
     fill_kf_geometry(a.kd, *S, *K, P);
     a.kd.n_kp = n_kp;
-    a.kd.hash_mask = hsize - 1;
+    a.kd.hash_mask = L.hsize - 1;
     float sf[32];
     fill_search_const(P, a.sc, sf);
     a.sc.gate = mp_dmax != nullptr;
     a.n_mp = n_mp;
-    a.add_cap = (int32_t)cap;
+    a.add_cap = (int32_t)L.cap;
     a.mp_xyz = mp_xyz;
     a.mp_desc = mp_desc;
     a.mp_dmax = mp_dmax;
@@ -1011,10 +1071,10 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
     a.kp_oct = kf->kp_octave;
     a.kp_desc = kf->kp_desc;
     a.kp_owner = kf->kp_owner;
-    a.hash = (const int32_t*)(base + o_hash);
-    a.claim = (int32_t*)(base + o_claim);
-    a.counter = (uint32_t*)(base + o_ctr);
-    a.add_list = (AddRef*)(base + o_list);
+    a.hash = (const int32_t*)(base + L.o_hash);
+    a.claim = (int32_t*)(base + L.o_claim);
+    a.counter = (uint32_t*)(base + L.o_ctr);
+    a.add_list = (AddRef*)(base + L.o_list);
     a.best_idx = out->best_idx;
     a.best_dist = out->best_dist;
     a.second_dist = out->second_dist;
@@ -1024,24 +1084,40 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
         a.cell_start = kf->cell_start;
         a.cell_kp = kf->cell_kp;
     } else {
-        int32_t* cs = (int32_t*)(base + o_cs);
-        int32_t* ck = (int32_t*)(base + o_ck);
+        int32_t* cs = (int32_t*)(base + L.o_cs);
+        int32_t* ck = (int32_t*)(base + L.o_ck);
         hipLaunchKernelGGL(grid_single_kernel, dim3(1), dim3(kPrepBlock), 0, stream, a.kd, cells, P->grid_cols,
                            P->grid_rows, kf->kp_xy, cs, ck);
         a.cell_start = cs;
         a.cell_kp = ck;
     }
     hipLaunchKernelGGL(plain_prep_kernel, dim3(1), dim3(kPrepBlock), 0, stream, n_kp, kf->kp_owner,
-                       (int32_t*)(base + o_hash), hsize - 1, a.claim, a.counter);
+                       (int32_t*)(base + L.o_hash), L.hsize - 1, a.claim, a.counter);
     const int grid = (n_mp + 255) / 256;
     hipLaunchKernelGGL(search_plain_kernel, dim3(grid), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(resolve_plain_kernel, dim3(std::min(grid, 256)), dim3(256), 0, stream, n_mp,
-                       (const uint32_t*)a.counter, (const AddRef*)a.add_list, (int32_t)cap,
+                       (const uint32_t*)a.counter, (const AddRef*)a.add_list, (int32_t)L.cap,
                        (const int32_t*)a.claim, mp_id, (const int32_t*)out->best_idx, out->decision, out->target);
     FL_HIP(hipGetLastError());
     return FL_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc, const float* mp_dmax,
+                   const int32_t* mp_id, const fl_keyframe* kf, const fl_sim3* S, const fl_pinhole* K,
+                   const fl_params* P, const fl_fuse_out* out, hipStream_t stream) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_plain(n_mp, mp_xyz, mp_desc, kf, S, K, P, out);
+    if (rc) return rc;
+    if (n_mp == 0) return FL_OK;
+    const PlainLayout L = plain_layout(n_mp, kf->n_kp, P->grid_cols * P->grid_rows, c->add_cap_override);
+    rc = c->plain.ensure(L.bytes);
+    if (rc) return rc;
+    return plain_launch((char*)c->plain.p, L, n_mp, mp_xyz, mp_desc, mp_dmax, mp_id, kf, S, K, P, out, stream);
+}
 
 int fl_validate_batch(const fl_batch* B, const fl_params* P, const fl_fuse_out* out) {
     return validate_batch(B, P, out);
@@ -1607,8 +1683,8 @@ int fl_get_stats(fl_ctx* c, int64_t* out4) {
 
 static void clear_profile(fl_ctx* c, int kernel) {
     for (auto& pr : c->prof_ev[kernel]) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
     }
     c->prof_ev[kernel].clear();
 }

@@ -33,8 +33,7 @@ struct alignas(16) KfDesc {
     int32_t hash_off;    // owner hash table of this keyframe (global-grid mode)
     int32_t hash_mask;
     int32_t n_tiles;
-    int32_t add_off;     // region of the provisional-ADD list
-    int32_t add_cap;
+    int32_t pad0, pad2;
     int32_t tile_pairs;  // pairs per tile of this keyframe (a whole number of waves)
     int64_t pair_off;
     int64_t n_pairs;
@@ -66,7 +65,6 @@ struct alignas(16) EventDesc {
     int64_t pair_begin, pair_end;  // pair range (pairs of the event are contiguous)
 };
 
-// Provisional ADD: a pair whose point claimed a free keypoint.
 // Offsets in the table blob (which starts at the batch header) of the
 // workgroups' tile ranges and of the keyframe table: fixed by the header size
 // and the search grid, so a workgroup finds its range and first keyframe
@@ -74,11 +72,22 @@ struct alignas(16) EventDesc {
 constexpr size_t kBlobAlign = 256;
 __host__ __device__ constexpr size_t blob_align(size_t x) { return (x + kBlobAlign - 1) / kBlobAlign * kBlobAlign; }
 
+// Provisional ADD: a pair whose point claimed a free keypoint.
 struct alignas(16) AddRef {
     int32_t pair;     // global pair index
     int32_t kp;       // claim slot of the keypoint (KfDesc::claim_off + index)
     int32_t gp;       // global point index
-    int32_t pad;
+    int32_t pass;     // search pass (its outputs)
+};
+
+// The share of the search launch of one workgroup: tiles [t0, t1) of the
+// tile order, the slot of tile t0 and its keyframe descriptor, and the
+// workgroup's region of the provisional-ADD and accepted-pair staging lists:
+// entries [priv_off, priv_off + priv_cap), as many as the pairs it searches
+// (each pair adds at most one entry to each list).
+struct alignas(16) WgRange {
+    int32_t t0, t1, slot, kf;
+    int32_t priv_off, priv_cap, pad0, pad1;
 };
 
 // Accepted pair kept for refinement: point, observation, keyframe.
@@ -97,13 +106,10 @@ struct alignas(16) KpRec {
     int32_t oct;
 };
 
-// Per-keyframe counters (zero between launches: the ADD resolution that
-// follows every batched search resets them).
-// Each keyframe's and each event's counters sit on a 128-byte line of their
-// own: device-scope atomics on one line serialise (about 12 ns apiece), and
-// the tiles of different keyframes reserve their lists at the same moment.
-enum : int { kKfAdd = 0, kKfCtrs = 32 };
-// Per-event counters.
+// Per-event counters (the accepted-pair count, zero between launches: the
+// refinement that reads the list resets it).  Each event's counters sit on a
+// 128-byte line of their own: device-scope atomics on one line serialise
+// (about 12 ns apiece).
 enum : int { kEvMatch = 0, kEvCtrs = 32 };
 
 enum : int { kModeGlobal = 0, kModeLdsRec = 1, kModeLdsDesc = 2 };
@@ -136,7 +142,7 @@ struct alignas(16) BatchHdr {
     const EventDesc* ev;
     const int32_t* kf_order;    // keyframes in tile order
     const int32_t* tile_prefix; // [n_kf+1] first tile of each keyframe in tile order
-    const int4* wg_range;       // [n_wg] tiles [x, y) of each workgroup, slot z and keyframe w of tile x
+    const WgRange* wg_range;    // [n_wg] each workgroup's tiles and list regions
     // inputs (caller-owned)
     const float* kp_xy;
     const int8_t* kp_oct;
@@ -157,9 +163,10 @@ struct alignas(16) BatchHdr {
     int32_t* hash;              // global-grid mode: owner hash tables
     unsigned long long* claim;  // [n_pass * n_kp_total] (epoch << 32 | lowest claiming point)
     const uint32_t* epoch;      // tag of this launch's claims, decremented by the table fetch
-    uint32_t* kf_ctr;           // [n_kf * kKfCtrs]
     uint32_t* ev_ctr;           // [n_events * kEvCtrs]
-    AddRef* add_list;           // per-keyframe regions
+    AddRef* add_list;           // per-workgroup regions (WgRange::priv_off)
+    uint32_t* add_count;        // [n_wg] entries of each workgroup's ADD region
+    MatchRec* match_stage;      // per-workgroup regions of accepted pairs, before they join their event's list
     MatchRec* match_list;       // per-event regions
     unsigned long long* stats_out;  // [4]
     // refinement
@@ -171,7 +178,7 @@ struct alignas(16) BatchHdr {
 
 __host__ __device__ constexpr size_t blob_range_offset() { return blob_align(sizeof(BatchHdr)); }
 __host__ __device__ constexpr size_t blob_kf_offset(int grid) {
-    return blob_align(blob_range_offset() + sizeof(int4) * (size_t)(grid > 1 ? grid : 1));
+    return blob_align(blob_range_offset() + sizeof(WgRange) * (size_t)(grid > 1 ? grid : 1));
 }
 
 
@@ -180,11 +187,12 @@ __host__ __device__ constexpr size_t blob_kf_offset(int grid) {
 // fmaf is one fused operation, every other operation rounds on its own (the
 // library is compiled with -ffp-contract=off).
 
+// floor(x * inv) clamped to [0, n): a negative or NaN product gives cell 0.
+// Branch free: fmaxf returns its other operand for a NaN, and floor of a
+// product below n is at most n - 1.
 __device__ __forceinline__ int cell_of(float x, float inv, int n) {
     const float f = floorf(x * inv);
-    if (!(f >= 0.0f)) return 0;   // negative or NaN
-    if (f >= (float)n) return n - 1;
-    return (int)f;
+    return (int)fminf(fmaxf(f, 0.0f), (float)(n - 1));
 }
 
 struct Proj {
@@ -192,10 +200,10 @@ struct Proj {
     int pred;
 };
 
-// Transform by the keyframe's Sim3, pinhole projection, image test and
-// predicted octave.  Returns false when the point is not visible.
-__device__ __forceinline__ bool project(const KfDesc& k, float x, float y, float z, float dmax, int gate,
-                                        const float* sf, int N, Proj& p) {
+// Transform by the keyframe's Sim3, pinhole projection and image test:
+// false when the point is not visible; u, v and the metric distance d
+// otherwise.
+__device__ __forceinline__ bool project_uv(const KfDesc& k, float x, float y, float z, Proj& p) {
     const float q0 = fmaf(k.A[2], z, fmaf(k.A[1], y, fmaf(k.A[0], x, k.t[0])));
     const float q1 = fmaf(k.A[5], z, fmaf(k.A[4], y, fmaf(k.A[3], x, k.t[1])));
     const float q2 = fmaf(k.A[8], z, fmaf(k.A[7], y, fmaf(k.A[6], x, k.t[2])));
@@ -204,16 +212,23 @@ __device__ __forceinline__ bool project(const KfDesc& k, float x, float y, float
     const float u = fmaf(k.fx, q0 * iz, k.cx);
     const float v = fmaf(k.fy, q1 * iz, k.cy);
     if (!(u >= 0.0f && u < k.W && v >= 0.0f && v < k.H)) return false;
-    const float d = sqrtf(fmaf(q0, q0, fmaf(q1, q1, q2 * q2))) * k.inv_s;
+    p.u = u;
+    p.v = v;
+    p.d = sqrtf(fmaf(q0, q0, fmaf(q1, q1, q2 * q2))) * k.inv_s;
+    return true;
+}
+
+// Transform, projection, image test and predicted octave: the first n with
+// d * sf[n] >= dmax, else N - 1 (gate off: N - 1).
+__device__ __forceinline__ bool project(const KfDesc& k, float x, float y, float z, float dmax, int gate,
+                                        const float* sf, int N, Proj& p) {
+    if (!project_uv(k, x, y, z, p)) return false;
     int pred = N - 1;
     if (gate) {
         for (int n = 0; n < N; ++n) {
-            if (d * sf[n] >= dmax) { pred = n; break; }
+            if (p.d * sf[n] >= dmax) { pred = n; break; }
         }
     }
-    p.u = u;
-    p.v = v;
-    p.d = d;
     p.pred = pred;
     return true;
 }
@@ -285,6 +300,61 @@ __host__ __device__ constexpr bool refine_rows_cleared_before(uint32_t launches)
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
 
+// A value known to be the same in every lane, moved to a scalar register
+// (the compiler cannot always tell that a loaded value is uniform, and
+// would otherwise hold it in a vector register of every lane).
+__device__ __forceinline__ int32_t uniform_i(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int64_t uniform_l(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uniform_p(T* p) {
+    return reinterpret_cast<T*>(uniform_l((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+// The search fields of a keyframe descriptor, in scalar registers.
+__device__ __forceinline__ KfDesc uniform_kf(const KfDesc& s) {
+    KfDesc k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) k.A[i] = uniform_f(s.A[i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k.t[i] = uniform_f(s.t[i]);
+    k.inv_s = uniform_f(s.inv_s);
+    k.fx = uniform_f(s.fx);
+    k.fy = uniform_f(s.fy);
+    k.cx = uniform_f(s.cx);
+    k.cy = uniform_f(s.cy);
+    k.W = uniform_f(s.W);
+    k.H = uniform_f(s.H);
+    k.invw = uniform_f(s.invw);
+    k.invh = uniform_f(s.invh);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) k.T[i] = 0.0f;   // not used by the search
+    k.kp_off = uniform_i(s.kp_off);
+    k.n_kp = uniform_i(s.n_kp);
+    k.grid_off = uniform_i(s.grid_off);
+    k.event = uniform_i(s.event);
+    k.mp_off = uniform_i(s.mp_off);
+    k.n_mp = uniform_i(s.n_mp);
+    k.hash_off = uniform_i(s.hash_off);
+    k.hash_mask = uniform_i(s.hash_mask);
+    k.n_tiles = uniform_i(s.n_tiles);
+    k.pad0 = k.pad2 = 0;
+    k.tile_pairs = uniform_i(s.tile_pairs);
+    k.pair_off = uniform_l(s.pair_off);
+    k.n_pairs = uniform_l(s.n_pairs);
+    k.pass = uniform_i(s.pass);
+    k.stage_key = uniform_i(s.stage_key);
+    k.claim_off = uniform_i(s.claim_off);
+    k.pad1 = 0;
+    return k;
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
 // lanes inside each row of 16 (DPP row_shr), then the last lane of row 0 is
 // added to row 1 and of row 2 to row 3 (row_bcast:15), and the last lane of
@@ -300,42 +370,25 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     return x;
 }
 
-// ADD conflicts of keyframe k, resolved by a kernel that runs after the
-// whole batched search on the same stream.  Of the provisional ADDs on one
-// keypoint the lowest point index (the claim it left, tagged with the launch
-// epoch) keeps ADD; the others become FUSE to that point (Sec. IV-D3, with
-// the lowest-index reading of concurrent additions).  The keyframe's ADD list
-// names the provisional ADDs; if it overflowed, the keyframe's decisions are
-// scanned instead.  Every thread of the workgroup calls it; the counter is
-// reset at the end.
-__device__ inline void resolve_keyframe_adds(const BatchHdr& h, int k, unsigned long long tag) {
-    const KfDesc& kd = h.kf[k];
-    const PassOut& po = h.out[kd.pass];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const uint32_t n_add = h.kf_ctr[k * kKfCtrs + kKfAdd];
-    if (n_add <= (uint32_t)kd.add_cap) {
-        for (uint32_t i = tid; i < n_add; i += nt) {
-            const AddRef e = h.add_list[kd.add_off + i];
-            const int32_t w = (int32_t)(h.claim[e.kp] - tag);
-            if (w != e.gp) {
-                po.decision[e.pair] = FL_FUSE;
-                po.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
-            }
-        }
-    } else {
-        for (int64_t j = tid; j < kd.n_pairs; j += nt) {
-            const int64_t o = kd.pair_off + j;
-            if (po.decision[o] != FL_ADD) continue;
-            const int32_t gp = kd.mp_off + (h.dense ? (int32_t)j : h.pair_mp[o]);
-            const int32_t w = (int32_t)(h.claim[kd.claim_off + po.best_idx[o]] - tag);
-            if (w != gp) {
-                po.decision[o] = FL_FUSE;
-                po.target[o] = h.mp_id ? h.mp_id[w] : w;
-            }
+// ADD conflicts, resolved by a kernel that runs after the whole batched
+// search on the same stream.  Of the provisional ADDs on one keypoint the
+// lowest point index (the claim it left, tagged with the launch epoch) keeps
+// ADD; the others become FUSE to that point (Sec. IV-D3, with the
+// lowest-index reading of concurrent additions).  Workgroup r of the search
+// listed its provisional ADDs in its region of the ADD list; every thread of
+// the calling workgroup takes part.
+__device__ inline void resolve_region_adds(const BatchHdr& h, int r, unsigned long long tag) {
+    const WgRange g = h.wg_range[r];
+    const uint32_t n = h.add_count[r];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const AddRef e = h.add_list[g.priv_off + i];
+        const int32_t w = (int32_t)(h.claim[e.kp] - tag);
+        if (w != e.gp) {
+            const PassOut& po = h.out[e.pass];
+            po.decision[e.pair] = FL_FUSE;
+            po.target[e.pair] = h.mp_id ? h.mp_id[w] : w;
         }
     }
-    __syncthreads();   // every thread has read the count
-    if (tid == 0) h.kf_ctr[k * kKfCtrs + kKfAdd] = 0;
 }
 
 }  // namespace fl

@@ -1133,15 +1133,15 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
         }
         __syncthreads();
     }
-    // The ADD conflicts of the search that precedes this launch: keyframes go
-    // to workgroups from the last one down, so workgroups with no refinement
-    // work (most of them for a single event) take them while the others
-    // iterate.  The refinement reads accepted pairs only, which an ADD and
-    // its relabelling as FUSE both are.
+    // The ADD conflicts of the search that precedes this launch: the search
+    // workgroups' ADD regions go to workgroups from the last one down, so
+    // workgroups with no refinement work (most of them for a single event)
+    // take them while the others iterate.  The refinement reads accepted
+    // pairs only, which an ADD and its relabelling as FUSE both are.
     if (h.resolve_in_refine) {
         const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
-        for (int k = (int)(gridDim.x - 1 - blockIdx.x); k < h.n_kf; k += (int)gridDim.x)
-            resolve_keyframe_adds(h, k, tag);
+        for (int r = (int)(gridDim.x - 1 - blockIdx.x); r < h.n_wg; r += (int)gridDim.x)
+            resolve_region_adds(h, r, tag);
     }
 }
 

@@ -63,10 +63,11 @@ __device__ __forceinline__ Window make_window(const Proj& p, const KfDesc& kd, c
     return w;
 }
 
+// Closed box and octave gate, evaluated without branches.
 __device__ __forceinline__ bool in_window(const Window& w, float x, float y, int oct, int pred, int gate) {
-    if (!(x >= w.lx && x <= w.hx && y >= w.ly && y <= w.hy)) return false;
-    if (gate && (oct < pred - 1 || oct > pred)) return false;
-    return true;
+    const bool box = (x >= w.lx) & (x <= w.hx) & (y >= w.ly) & (y <= w.hy);
+    const bool oct_ok = (gate == 0) | ((oct >= pred - 1) & (oct <= pred));
+    return box & oct_ok;
 }
 
 __device__ __forceinline__ uint32_t owner_slot(int32_t id, int32_t mask) {
@@ -339,14 +340,18 @@ __device__ __forceinline__ void wave_append(bool want, uint32_t* counter, T* lis
 
 // ---------------------------------------------------------------------------
 // Fused batched search.  Each workgroup owns a contiguous, cost-balanced run
-// of tiles inside the range of its XCD (workgroups are dispatched to the 8
-// XCDs round-robin), so the keyframes of an XCD stay in its L2 and no atomic
-// is spent on scheduling.  A tile is up to 1024 * PPL consecutive pairs of
-// one keyframe, a whole number of waves; pair j of a tile goes to thread
-// j mod 1024, so a tile smaller than the workgroup leaves its last waves
-// idle.  When its tile moves to a new keyframe the workgroup builds that
-// keyframe's grid, records (and descriptors) and owner hash set in LDS.  The
-// ADD conflicts are resolved by the next kernel on the stream.
+// of tiles (workgroups are dispatched to the 8 XCDs round-robin, and the runs
+// of one XCD are neighbours in the tile order, so the keyframes of an XCD
+// stay in its L2).  The workgroup's consecutive tiles of one keyframe
+// descriptor form a segment.  When a segment's keyframe is not the one in
+// LDS, the workgroup builds that keyframe's grid, records (and descriptors)
+// and owner hash set in LDS; then its waves take the segment's pairs in
+// chunks of 64 x PPL (pair j of a chunk on lane j mod 64), each wave on its
+// own, with no barrier between chunks.  Provisional ADDs and accepted pairs
+// go to the workgroup's own list regions through LDS counters; at the end of
+// a segment its accepted pairs join their event's list with one device-scope
+// reservation.  The ADD conflicts are resolved by the next kernel on the
+// stream.
 
 struct KfView {
     const int32_t* cs;
@@ -369,6 +374,212 @@ __host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cel
     return b;
 }
 
+// One pair's point, loaded before its evaluation.
+struct PairIn {
+    int32_t gp, id;
+    float x, y, z, dm;
+    uint4 a0, a1;
+    uint8_t dec;
+};
+
+__device__ __forceinline__ void load_pair(const BatchHdr& h, const KfDesc& kd, bool dense, int gate, int64_t o,
+                                          int64_t se, PairIn& p) {
+    p.dec = o < se ? kDecUndecided : (uint8_t)0;
+    p.gp = 0;
+    p.id = -1;
+    p.x = p.y = p.z = p.dm = 0.0f;
+    p.a0 = p.a1 = make_uint4(0, 0, 0, 0);
+    if (o < se) {
+        const int64_t j = o - kd.pair_off;
+        const int32_t lp = dense ? (int32_t)j : h.pair_mp[o];
+        if (lp < 0 || lp >= kd.n_mp) {
+            p.dec = FL_INVALID;
+        } else {
+            p.gp = kd.mp_off + lp;
+            p.id = h.mp_id ? h.mp_id[p.gp] : p.gp;
+            p.x = h.mp_xyz[3 * (int64_t)p.gp];
+            p.y = h.mp_xyz[3 * (int64_t)p.gp + 1];
+            p.z = h.mp_xyz[3 * (int64_t)p.gp + 2];
+            if (gate) p.dm = h.mp_dmax[p.gp];
+            load_desc(h.mp_desc, p.gp, p.a0, p.a1);
+        }
+    }
+}
+
+// Search result of one pair beyond its decision.
+struct PairRes {
+    Best best;
+    int32_t target;
+    float ku, kv;   // the best candidate's keypoint
+};
+
+// The octave scale table sf[n] = scale_factor^n of a launch: its first
+// kOctReg entries, and the window half-widths r0 * sf[n] of the pass, in
+// registers; every entry in LDS.
+constexpr int kOctReg = 8;
+struct OctaveTable {
+    float sf[kOctReg];
+    float rad[kOctReg];
+    const float* all;   // LDS, n_octaves entries
+    int N;
+    float r0;
+};
+
+// The first n with d * sf[n] >= dmax, else N - 1 (the oracle's loop; the
+// first kOctReg tests without branches).
+__device__ __forceinline__ int predict_octave(const OctaveTable& T, float d, float dmax) {
+    int pred = T.N - 1;
+    bool found = false;
+#pragma unroll
+    for (int n = 0; n < kOctReg; ++n) {
+        const bool hit = (!found) & (n < T.N) & (d * T.sf[n] >= dmax);
+        pred = hit ? n : pred;
+        found = found | hit;
+    }
+    if (!found)
+        for (int n = kOctReg; n < T.N; ++n)
+            if (d * T.all[n] >= dmax) {
+                pred = n;
+                break;
+            }
+    return pred;
+}
+
+// Window half-width r0 * sf[pred], the same float32 product for every pred.
+__device__ __forceinline__ float window_radius(const OctaveTable& T, int pred) {
+    if (pred >= kOctReg) return T.r0 * T.all[pred];
+    float r = T.rad[0];
+#pragma unroll
+    for (int n = 1; n < kOctReg; ++n) r = pred == n ? T.rad[n] : r;
+    return r;
+}
+
+// Evaluation of one pair (point p, keyframe kd): observed-set test, Sim3
+// projection, window gather over the grid rows, Hamming distances, best and
+// second best, and the fuse / add decision (provisional for ADD).  The
+// record ranges of the window's first kRowSeg grid rows are read at once and
+// walked as one flat sequence, so a lane's trip count is its own number of
+// records rather than a sum of per-row maxima over the wave; rows beyond
+// those (wide windows) are walked after.  st: visible pairs, cells scanned,
+// records scanned, candidates.
+constexpr int kRowSeg = 4;
+
+template <int MODE, bool STATS>
+__device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, float nn_ratio, const int32_t* kp_owner,
+                                          const KfView& v, const OctaveTable& T, int gate, int C, int R, PairIn& p,
+                                          PairRes& res, unsigned long long* st) {
+    res.best.init();
+    res.target = -1;
+    res.ku = res.kv = 0.0f;
+    // owner probe: a point already observed in this keyframe is skipped
+    if (p.dec == kDecUndecided && p.id >= 0) {
+        uint32_t hh = owner_slot(p.id, v.hash_mask);
+        for (int probe = 0; probe <= v.hash_mask; ++probe) {
+            const int32_t hv = v.hash[hh];
+            if (hv == p.id) {
+                p.dec = FL_SKIP;
+                break;
+            }
+            if (hv < 0) break;
+            hh = (hh + 1) & (uint32_t)v.hash_mask;
+        }
+    }
+    if (p.dec != kDecUndecided) return;
+    Proj pr;
+    if (!project_uv(kd, p.x, p.y, p.z, pr)) {
+        p.dec = FL_NOT_VISIBLE;
+        return;
+    }
+    pr.pred = gate ? predict_octave(T, pr.d, p.dm) : T.N - 1;
+    if (STATS) ++st[0];
+    const float rad = window_radius(T, pr.pred);
+    Window w;
+    w.lx = pr.u - rad;
+    w.hx = pr.u + rad;
+    w.ly = pr.v - rad;
+    w.hy = pr.v + rad;
+    w.c0 = cell_of(w.lx, kd.invw, C);
+    w.c1 = cell_of(w.hx, kd.invw, C);
+    w.r0 = cell_of(w.ly, kd.invh, R);
+    w.r1 = cell_of(w.hy, kd.invh, R);
+    // record ranges of the first kRowSeg rows: slot = base[j] + m for the
+    // m-th record of the flat sequence when cum[j] <= m < cum[j + 1]
+    int base[kRowSeg], cum[kRowSeg + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kRowSeg; ++j) {
+        const int row = w.r0 + j;
+        const bool in = row <= w.r1;
+        const int rr = in ? row : w.r0;
+        const int s = v.cs[rr * C + w.c0], e = v.cs[rr * C + w.c1 + 1];
+        const int n = in ? e - s : 0;
+        base[j] = s - cum[j];
+        cum[j + 1] = cum[j] + n;
+        if (STATS && in) {
+            st[1] += (unsigned long long)(w.c1 - w.c0 + 1);
+            st[2] += (unsigned long long)n;
+        }
+    }
+    int bslot = 0;
+    auto visit = [&](int i, const KpRec& rc) {
+        if (in_window(w, rc.x, rc.y, rc.oct, pr.pred, gate)) {
+            if (STATS) ++st[3];
+            uint4 b0, b1;
+            if (MODE == kModeLdsRec) {
+                load_desc(v.desc_orig, rc.idx, b0, b1);
+            } else {
+                b0 = v.desc[2 * i];
+                b1 = v.desc[2 * i + 1];
+            }
+            const uint32_t before = res.best.key;
+            res.best.offer(hamming(p.a0, p.a1, b0, b1), rc.idx);
+            if (res.best.key != before) {
+                res.ku = rc.x;
+                res.kv = rc.y;
+                bslot = i;
+            }
+        }
+    };
+    auto slot_of = [&](int m) {
+        int b = base[0];
+#pragma unroll
+        for (int j = 1; j < kRowSeg; ++j) b = m >= cum[j] ? base[j] : b;
+        return b + m;
+    };
+    // each record is loaded one step ahead of its test, so the LDS latency
+    // overlaps the previous record's test (and comparison)
+    const int total = cum[kRowSeg];
+    int i_next = slot_of(0);
+    KpRec r_next{};
+    if (total > 0) r_next = v.rec[i_next];
+    for (int m = 0; m < total; ++m) {
+        const int i = i_next;
+        const KpRec rc = r_next;
+        i_next = slot_of(m + 1);
+        if (m + 1 < total) r_next = v.rec[i_next];
+        visit(i, rc);
+    }
+    for (int row = w.r0 + kRowSeg; row <= w.r1; ++row) {
+        const int s = v.cs[row * C + w.c0], e = v.cs[row * C + w.c1 + 1];
+        if (STATS) {
+            st[1] += (unsigned long long)(w.c1 - w.c0 + 1);
+            st[2] += (unsigned long long)(e - s);
+        }
+        for (int i = s; i < e; ++i) visit(i, v.rec[i]);
+    }
+    if (!accept_match(res.best, hamming_th, nn_ratio)) {
+        p.dec = FL_NO_MATCH;
+    } else {
+        const int32_t ow = v.own ? v.own[bslot] : kp_owner[kd.kp_off + (int32_t)(res.best.key & 0xFFFFu)];
+        if (ow >= 0) {
+            p.dec = FL_FUSE;
+            res.target = ow;
+        } else {
+            p.dec = FL_ADD;   // provisional; losers are relabelled by the resolver
+        }
+    }
+}
+
 template <int PPL, int MODE, bool STATS>
 __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchHdr* __restrict__ hp) {
     extern __shared__ __align__(16) unsigned char s_mem[];
@@ -381,8 +592,10 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     int32_t* s_own = nullptr;
     int32_t* s_hash = nullptr;
     int32_t* s_tmp = nullptr;
-    __shared__ uint32_t s_cnt[2 * PPL * kWavesPerWG + 2];   // per-wave list counts, then the two bases
-    const int wid = tid / kWave;
+    // running counts of the workgroup's ADD and accepted-pair regions, then
+    // the segment's accepted-pair total and its base in the event's list
+    __shared__ uint32_t s_list[4];
+    const int wid = tid / kWave, nw = (int)(blockDim.x / kWave);
     if (MODE != kModeGlobal) {
         unsigned char* p = s_mem + 16 * (size_t)h.lds_kp_cap;
         if (MODE == kModeLdsDesc) {
@@ -398,75 +611,66 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         s_tmp = reinterpret_cast<int32_t*>(p);
         p += 4 * (size_t)(kSearchBlock / kWave + 4);
     }
+    if (tid == 0) {
+        s_list[0] = 0;
+        s_list[1] = 0;
+    }
 
     // the octave scale table in LDS: the octave search and the window radius
     // index it per lane.  In the LDS modes the barrier that opens the first
-    // keyframe's staging publishes it, so the tile's table and point loads
-    // below are issued without waiting here.
+    // keyframe's staging publishes it (and the counters above), so the first
+    // point loads are issued without waiting here.
     __shared__ float s_sf[FL_MAX_OCTAVES];
     if (tid < FL_MAX_OCTAVES) s_sf[tid] = h.sf[tid];
     if (MODE == kModeGlobal) __syncthreads();
-    const float* sf = s_sf;
-    const int N = h.n_octaves, gate = h.gate, C = h.grid_cols, R = h.grid_rows;
-    const bool dense = h.dense != 0;
-    const bool want_matches = h.refine_iters > 0;
-    const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
-    unsigned long long st_vis = 0, st_cells = 0, st_kp = 0, st_cand = 0;
-
-    // tiles [x, y); the first one belongs to slot z (keyframe w) of the tile
-    // order.  The ranges and the keyframe table sit at offsets of the table
-    // blob that follow from the grid size, so neither waits for a pointer.
-    const char* blob = reinterpret_cast<const char*>(hp);
-    const int4 range = reinterpret_cast<const int4*>(blob + blob_range_offset())[blockIdx.x];
-    const KfDesc* kf_tab = reinterpret_cast<const KfDesc*>(blob + blob_kf_offset((int)gridDim.x));
-    int slot = range.z;
-    int staged = -1;
-    for (int t = range.x; t < range.y; ++t) {
-        while (t >= h.tile_prefix[slot + 1]) ++slot;
-        const int k = t == range.x ? range.w : h.kf_order[slot];
-        const KfDesc kd = kf_tab[k];          // by value: kept in registers across the stores below
-        const EventDesc ed = h.ev[kd.event];
-        const PassOut& po = h.out[kd.pass];
-        const int64_t pb = kd.pair_off + (int64_t)(t - h.tile_prefix[slot]) * kd.tile_pairs;
-        const int64_t pe = min(pb + (int64_t)kd.tile_pairs, kd.pair_off + kd.n_pairs);
-        // A provisional ADD is written as ADD here; the ADD conflicts are
-        // resolved after the whole search, by the next kernel on the stream
-        // (the refinement, or the resolution kernel when there is none), which
-        // relabels the losers.  No tile waits for another.
-
-        // Point loads of every pair of this thread are issued first, so their
-        // latency overlaps the keyframe staging below.
-        uint8_t dec[PPL];
-        int32_t gp[PPL], id[PPL];
-        float px[PPL], py[PPL], pz[PPL], pdm[PPL];
-        uint4 a0[PPL], a1[PPL];
-        bool add_want[PPL], acc_want[PPL];
-        int32_t add_kp[PPL];
-        float acc_u[PPL], acc_v[PPL];
+    OctaveTable T;
+    T.all = s_sf;
+    T.N = h.n_octaves;
 #pragma unroll
-        for (int r = 0; r < PPL; ++r) {
-            const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
-            dec[r] = o < pe ? kDecUndecided : (uint8_t)0;
-            gp[r] = 0;
-            id[r] = -1;
-            px[r] = py[r] = pz[r] = pdm[r] = 0.0f;
-            a0[r] = a1[r] = make_uint4(0, 0, 0, 0);
-            if (o < pe) {
-                const int64_t j = o - kd.pair_off;
-                const int32_t lp = dense ? (int32_t)j : h.pair_mp[o];
-                if (lp < 0 || lp >= kd.n_mp) {
-                    dec[r] = FL_INVALID;
-                } else {
-                    gp[r] = kd.mp_off + lp;
-                    id[r] = h.mp_id ? h.mp_id[gp[r]] : gp[r];
-                    px[r] = h.mp_xyz[3 * (int64_t)gp[r]];
-                    py[r] = h.mp_xyz[3 * (int64_t)gp[r] + 1];
-                    pz[r] = h.mp_xyz[3 * (int64_t)gp[r] + 2];
-                    if (gate) pdm[r] = h.mp_dmax[gp[r]];
-                    load_desc(h.mp_desc, gp[r], a0[r], a1[r]);
-                }
-            }
-        }
+    for (int n = 0; n < kOctReg; ++n) T.sf[n] = uniform_f(h.sf[n]);
+    T.N = uniform_i(T.N);
+    const int gate = uniform_i(h.gate), C = uniform_i(h.grid_cols), R = uniform_i(h.grid_rows);
+    const bool dense = uniform_i(h.dense) != 0;
+    const bool want_matches = uniform_i(h.refine_iters) > 0;
+    const unsigned long long tag = (unsigned long long)(uint32_t)uniform_i((int32_t)*h.epoch) << 32;
+    // header fields read per pair, held in scalar registers (the output
+    // stores below could otherwise be taken to alias the header)
+    const int32_t* const kp_owner = uniform_p(h.kp_owner);
+    unsigned long long* const claim = uniform_p(h.claim);
+    AddRef* const add_list = uniform_p(h.add_list);
+    MatchRec* const match_stage = uniform_p(h.match_stage);
+    unsigned long long st[4] = {0, 0, 0, 0};
+
+    // The range and the keyframe table sit at offsets of the table blob that
+    // follow from the grid size, so neither waits for a pointer.
+    const char* blob = reinterpret_cast<const char*>(hp);
+    const WgRange rg = reinterpret_cast<const WgRange*>(blob + blob_range_offset())[blockIdx.x];
+    const KfDesc* kf_tab = reinterpret_cast<const KfDesc*>(blob + blob_kf_offset((int)gridDim.x));
+    int slot = rg.slot;
+    int staged = -1;
+    uint32_t seg_m0 = 0;   // first staged accepted pair of the current segment
+    for (int t = rg.t0; t < rg.t1;) {
+        while (t >= h.tile_prefix[slot + 1]) ++slot;
+        const int k = t == rg.t0 ? rg.kf : h.kf_order[slot];
+        const int tb = h.tile_prefix[slot];
+        const int t_end = min(rg.t1, h.tile_prefix[slot + 1]);
+        const KfDesc kd = uniform_kf(kf_tab[k]);   // scalar registers, kept across the stores below
+        PassOut po = h.out[kd.pass];
+        po.best_idx = uniform_p(po.best_idx);
+        po.best_dist = uniform_p(po.best_dist);
+        po.second_dist = uniform_p(po.second_dist);
+        po.decision = uniform_p(po.decision);
+        po.target = uniform_p(po.target);
+        po.hamming_th = uniform_i(po.hamming_th);
+        po.nn_ratio = uniform_f(po.nn_ratio);
+        po.r0 = uniform_f(po.r0);
+        T.r0 = po.r0;
+#pragma unroll
+        for (int n = 0; n < kOctReg; ++n) T.rad[n] = po.r0 * T.sf[n];
+        const int64_t kend = kd.pair_off + kd.n_pairs;
+        const int64_t sb = kd.pair_off + (int64_t)(t - tb) * kd.tile_pairs;
+        const int64_t se = min(kd.pair_off + (int64_t)(t_end - tb) * kd.tile_pairs, kend);
+        t = t_end;
 
         KfView v;
         if (MODE == kModeGlobal) {
@@ -492,183 +696,104 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             v.hash_mask = h.lds_hash_mask;
         }
 
+        constexpr int kChunk = kWave * PPL;
+        const int64_t n_chunks = (se - sb + kChunk - 1) / kChunk;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        for (int64_t c = wid; c < n_chunks; c += nw) {
+            const int64_t cb = sb + c * kChunk;
+            // the point loads of every pair of this lane are issued first
+            PairIn p[PPL];
 #pragma unroll
-        for (int r = 0; r < PPL; ++r) {
-            const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
-            const bool active = o < pe;
-            // owner probe: a point already observed in this keyframe is skipped
-            if (dec[r] == kDecUndecided && id[r] >= 0) {
-                uint32_t hh = owner_slot(id[r], v.hash_mask);
-                for (int probe = 0; probe <= v.hash_mask; ++probe) {
-                    const int32_t hv = v.hash[hh];
-                    if (hv == id[r]) {
-                        dec[r] = FL_SKIP;
-                        break;
-                    }
-                    if (hv < 0) break;
-                    hh = (hh + 1) & (uint32_t)v.hash_mask;
-                }
-            }
-            Best best;
-            best.init();
-            int32_t target = -1;
-            float ku = 0.0f, kv = 0.0f;
-            int bslot = 0;
-            if (dec[r] == kDecUndecided) {
-                Proj p;
-                if (!project(kd, px[r], py[r], pz[r], pdm[r], gate, sf, N, p)) {
-                    dec[r] = FL_NOT_VISIBLE;
-                } else {
-                    if (STATS) ++st_vis;
-                    const Window w = make_window(p, kd, sf, po.r0, C, R);
-                    for (int row = w.r0; row <= w.r1; ++row) {
-                        const int s = v.cs[row * C + w.c0];
-                        const int e = v.cs[row * C + w.c1 + 1];
-                        if (STATS) {
-                            st_cells += (unsigned long long)(w.c1 - w.c0 + 1);
-                            st_kp += (unsigned long long)(e - s);
-                        }
-                        for (int i = s; i < e; ++i) {
-                            const KpRec rc = v.rec[i];
-                            if (!in_window(w, rc.x, rc.y, rc.oct, p.pred, gate)) continue;
-                            if (STATS) ++st_cand;
-                            uint4 b0, b1;
-                            if (MODE == kModeLdsRec) {
-                                load_desc(v.desc_orig, rc.idx, b0, b1);
-                            } else {
-                                b0 = v.desc[2 * i];
-                                b1 = v.desc[2 * i + 1];
-                            }
-                            const uint32_t before = best.key;
-                            best.offer(hamming(a0[r], a1[r], b0, b1), rc.idx);
-                            if (best.key != before) {
-                                ku = rc.x;
-                                kv = rc.y;
-                                bslot = i;
-                            }
-                        }
-                    }
-                    if (!accept_match(best, po.hamming_th, po.nn_ratio)) {
-                        dec[r] = FL_NO_MATCH;
-                    } else {
-                        const int32_t ow = v.own ? v.own[bslot]
-                                                 : h.kp_owner[kd.kp_off + (int32_t)(best.key & 0xFFFFu)];
-                        if (ow >= 0) {
-                            dec[r] = FL_FUSE;
-                            target = ow;
-                        } else {
-                            dec[r] = FL_ADD;   // provisional; losers are relabelled by the resolver
-                        }
-                    }
-                }
-            }
-            const int bidx = best.key == 0xFFFFFFFFu ? -1 : (int)(best.key & 0xFFFFu);
-            const int kpg = kd.claim_off + (bidx < 0 ? 0 : bidx);   // claim slot
-            const bool is_add = active && dec[r] == FL_ADD;
-            if (active) {
-                po.best_idx[o] = bidx;
-                po.best_dist[o] = (int16_t)(best.key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(best.key >> 16));
-                po.second_dist[o] = (int16_t)best.second;
-                po.decision[o] = dec[r];
-                po.target[o] = target;
-            }
-            if (is_add) atomicMin(&h.claim[kpg], tag | (uint32_t)gp[r]);
-            // list entries are written after the tile with one atomic per list
-            add_want[r] = is_add;
-            add_kp[r] = kpg;
-            acc_want[r] = want_matches && active && (dec[r] == FL_ADD || dec[r] == FL_FUSE);
-            acc_u[r] = ku;
-            acc_v[r] = kv;
-            const unsigned long long ma = __ballot(add_want[r]);
-            const unsigned long long mm = __ballot(acc_want[r]);
-            if (lane == 0) {
-                s_cnt[(2 * r) * kWavesPerWG + wid] = (uint32_t)__popcll(ma);
-                s_cnt[(2 * r + 1) * kWavesPerWG + wid] = (uint32_t)__popcll(mm);
-            }
-        }
-        __syncthreads();
-        if (wid == 0) {
-            // wave 0 turns the per-wave counts (pair slot major, wave minor)
-            // into offsets and reserves both lists
-            static_assert(PPL * kWavesPerWG <= kWave, "one count per lane");
-            constexpr int nv = PPL * kWavesPerWG;
-            const int r = lane / kWavesPerWG, w = lane % kWavesPerWG;
-            const bool in = lane < nv;
-            const int ca = in ? (int)s_cnt[(2 * r) * kWavesPerWG + w] : 0;
-            const int cm = in ? (int)s_cnt[(2 * r + 1) * kWavesPerWG + w] : 0;
-            const int ia = wave_incl_scan(ca), im = wave_incl_scan(cm);
-            if (in) {
-                s_cnt[(2 * r) * kWavesPerWG + w] = (uint32_t)(ia - ca);
-                s_cnt[(2 * r + 1) * kWavesPerWG + w] = (uint32_t)(im - cm);
-            }
-            const uint32_t run_a = (uint32_t)__builtin_amdgcn_readlane(ia, nv - 1);
-            const uint32_t run_m = (uint32_t)__builtin_amdgcn_readlane(im, nv - 1);
-            if (lane == 0) {
-                // both list reservations are issued before either result is used
-                const uint32_t ba = run_a ? atomicAdd(&h.kf_ctr[k * kKfCtrs + kKfAdd], run_a) : 0u;
-                const uint32_t bm = run_m ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], run_m) : 0u;
-                s_cnt[2 * PPL * kWavesPerWG] = ba;
-                s_cnt[2 * PPL * kWavesPerWG + 1] = bm;
-            }
-        }
-        __syncthreads();
-        {
-            const uint32_t base_a = s_cnt[2 * PPL * kWavesPerWG], base_m = s_cnt[2 * PPL * kWavesPerWG + 1];
-            const unsigned long long below = (1ull << lane) - 1ull;
+            for (int r = 0; r < PPL; ++r) load_pair(h, kd, dense, gate, cb + r * kWave + lane, se, p[r]);
 #pragma unroll
             for (int r = 0; r < PPL; ++r) {
-                const int64_t o = pb + (int64_t)r * kSearchBlock + tid;
-                const unsigned long long ma = __ballot(add_want[r]);
-                const unsigned long long mm = __ballot(acc_want[r]);
-                if (add_want[r]) {
-                    const uint32_t idx = base_a + s_cnt[(2 * r) * kWavesPerWG + wid] + (uint32_t)__popcll(ma & below);
-                    if (idx < (uint32_t)kd.add_cap) {
-                        AddRef e;
-                        e.pair = (int32_t)o;
-                        e.kp = add_kp[r];
-                        e.gp = gp[r];
-                        e.pad = 0;
-                        h.add_list[kd.add_off + idx] = e;
-                    }
+                const int64_t o = cb + r * kWave + lane;
+                const bool active = o < se;
+                PairRes res;
+                eval_pair<MODE, STATS>(kd, po.hamming_th, po.nn_ratio, kp_owner, v, T, gate, C, R, p[r], res, st);
+                const uint32_t key = res.best.key;
+                const int bidx = key == 0xFFFFFFFFu ? -1 : (int)(key & 0xFFFFu);
+                const int kpg = kd.claim_off + (bidx < 0 ? 0 : bidx);   // claim slot
+                if (active) {
+                    po.best_idx[o] = bidx;
+                    po.best_dist[o] = (int16_t)(key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(key >> 16));
+                    po.second_dist[o] = (int16_t)res.best.second;
+                    po.decision[o] = p[r].dec;
+                    po.target[o] = res.target;
                 }
-                if (acc_want[r]) {
-                    const uint32_t idx =
-                        base_m + s_cnt[(2 * r + 1) * kWavesPerWG + wid] + (uint32_t)__popcll(mm & below);
-                    if (idx < (uint32_t)ed.list_cap) {
-                        MatchRec me;
-                        me.x = px[r];
-                        me.y = py[r];
-                        me.z = pz[r];
-                        me.u = acc_u[r];
-                        me.v = acc_v[r];
-                        me.kf = k;
-                        me.pad0 = me.pad1 = 0;
-                        h.match_list[ed.list_off + idx] = me;
-                    }
+                const bool is_add = active && p[r].dec == FL_ADD;
+                const bool acc = want_matches && active && (p[r].dec == FL_ADD || p[r].dec == FL_FUSE);
+                if (is_add) atomicMin(&claim[kpg], tag | (uint32_t)p[r].gp);
+                // one LDS reservation per wave and list
+                const unsigned long long ma = __ballot(is_add), mm = __ballot(acc);
+                uint32_t ba = 0, bm = 0;
+                if (lane == 0) {
+                    if (ma) ba = atomicAdd(&s_list[0], (uint32_t)__popcll(ma));
+                    if (mm) bm = atomicAdd(&s_list[1], (uint32_t)__popcll(mm));
+                }
+                ba = (uint32_t)__shfl((int)ba, 0);
+                bm = (uint32_t)__shfl((int)bm, 0);
+                if (is_add) {
+                    AddRef e;
+                    e.pair = (int32_t)o;
+                    e.kp = kpg;
+                    e.gp = p[r].gp;
+                    e.pass = kd.pass;
+                    add_list[rg.priv_off + ba + (uint32_t)__popcll(ma & below)] = e;
+                }
+                if (acc) {
+                    MatchRec me;
+                    me.x = p[r].x;
+                    me.y = p[r].y;
+                    me.z = p[r].z;
+                    me.u = res.ku;
+                    me.v = res.kv;
+                    me.kf = k;
+                    me.pad0 = me.pad1 = 0;
+                    match_stage[rg.priv_off + bm + (uint32_t)__popcll(mm & below)] = me;
                 }
             }
         }
+        if (want_matches) {
+            // the segment's accepted pairs join their event's list
+            __syncthreads();
+            if (tid == 0) {
+                const uint32_t tot = s_list[1];
+                s_list[2] = tot;
+                s_list[3] = tot > seg_m0 ? atomicAdd(&h.ev_ctr[kd.event * kEvCtrs + kEvMatch], tot - seg_m0) : 0u;
+            }
+            __syncthreads();
+            const uint32_t tot = s_list[2], base = s_list[3];
+            const EventDesc& ed = h.ev[kd.event];
+            const int32_t list_off = ed.list_off, list_cap = ed.list_cap;
+            for (uint32_t i = seg_m0 + tid; i < tot; i += blockDim.x) {
+                const uint32_t idx = base + (i - seg_m0);
+                if (idx < (uint32_t)list_cap) h.match_list[list_off + idx] = h.match_stage[rg.priv_off + i];
+            }
+            seg_m0 = tot;
+        }
     }
+    __syncthreads();   // every ADD of the workgroup is counted
+    if (tid == 0) h.add_count[blockIdx.x] = s_list[0];
     if (STATS) {
-        unsigned long long vals[4] = {st_vis, st_cells, st_kp, st_cand};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            unsigned long long xv = vals[i];
+            unsigned long long xv = st[i];
             for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
             if (lane == 0 && xv) atomicAdd(&h.stats_out[i], xv);
         }
     }
 }
 
-// ADD resolution after a batched search launched without refinement: one
-// workgroup per keyframe, grid-stride.
+// ADD resolution after a batched search launched without refinement: the
+// search workgroups' ADD regions, grid-stride.
 constexpr int kResolveBlock = 256;
 constexpr int kResolveGrid = 1024;   // workgroups in graph mode (any count is correct)
 
 __global__ __launch_bounds__(kResolveBlock) void resolve_adds_kernel(const BatchHdr* __restrict__ hp) {
     const BatchHdr& h = *hp;
     const unsigned long long tag = (unsigned long long)(*h.epoch) << 32;
-    for (int k = blockIdx.x; k < h.n_kf; k += gridDim.x) resolve_keyframe_adds(h, k, tag);
+    for (int r = blockIdx.x; r < h.n_wg; r += gridDim.x) resolve_region_adds(h, r, tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -784,7 +909,7 @@ __global__ __launch_bounds__(256) void search_plain_kernel(PlainArgs a) {
     e.pair = (int32_t)o;
     e.kp = bidx < 0 ? 0 : bidx;
     e.gp = gp;
-    e.pad = 0;
+    e.pass = 0;
     wave_append(is_add, a.counter, a.add_list, a.add_cap, e);
 }
 
