@@ -1,28 +1,31 @@
 """Benchmark: point-keyframe match candidates/s and ms per loop event, batched
 vs plain, on one MI355X.
 
-One step is one loop event through the whole hot path: keypoint grids of all
-keyframes, Sim3 search-and-fuse over every (point, keyframe) pair, ADD
-conflict resolution, then 10 Gauss-Newton refinement steps of the loop Sim3
-on the accepted pairs.  Inputs are resident in HBM before timing starts.
+One step is one loop event of the stream through the whole hot path:
+keypoint grids of all keyframes, Sim3 search-and-fuse over every (point,
+keyframe) pair, ADD conflict resolution, then 10 Gauss-Newton refinement steps
+of the loop Sim3 on the accepted pairs.  Inputs are resident in HBM before
+timing starts.
 
-  batched : one upload of the event tables + one launch sequence per event,
-            replayed from a HIP graph, launched eagerly, or launched eagerly
-            with consecutive events alternating between two contexts on two
-            streams (one event's search overlaps the previous one's
-            refinement); the headline takes the highest throughput
-  plain   : the per-call pattern (one fl_search_fuse per keyframe, each
-            followed by a copy of its results to the host and a stream sync;
-            then each refinement step as its own call, copy and sync)
+Headline workload: the stream of 200 uneven loop events (5-80 keyframes of
+752x480 or 512x512, 300-2,500 keypoints each, 5,000-100,000 points, every
+point against every keyframe of its event: 2.2 M pairs per event on average,
+7.2 M at most).  The timed steps are consecutive events of the stream, each
+one batched launch sequence (table fetch, search, refinement) issued eagerly
+on one stream, with HIP events around every event and every search and
+refinement kernel.  value = pairs of the timed events / their wall time;
+ms_per_step = that wall time / steps (one stream, so each event's own time).
+Beside it: the same events replayed from HIP graphs, consecutive events
+alternating between two contexts on two streams (one event's search overlaps
+the previous one's refinement), and the plain path (the per-call pattern: one
+fl_search_fuse per keyframe, each followed by a copy of its results to the
+host and a stream sync; then each refinement step as its own call, copy and
+sync) on the stream's first events.
 
-Prints one JSON line.  Headline workload: a loop event of 20 keyframes
-(752x480, 1,200 keypoints each) and 15,000 map points, 300,000 dense pairs.
-Secondary workloads (skipped with --quick): the uneven 60-keyframe event
-with sparse covisibility pairs, ten of them in one launch, the residual
-forward/backward on 50,000 pairs, the projection searches of loop verification
-(one keyframe; three keyframes in one launch; two searches of one keyframe in
-one launch), robust Sim3 refinement, essential-graph optimisation and a stream
-of uneven events.
+Secondary workloads (skipped with --quick): the 20-keyframe loop event, the
+uneven 60-keyframe event with sparse covisibility pairs, ten of them in one
+launch, the residual forward/backward on 50,000 pairs, the projection searches
+of loop verification, robust Sim3 refinement and essential-graph optimisation.
 """
 from __future__ import annotations
 
@@ -41,18 +44,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "point-keyframe match candidates/s and ms per loop event, batched vs plain"
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
-FP64_PEAK_TFLOPS = 78.6                   # vector FP64
+FP32_PEAK_TFLOPS = 157.3                  # vector FP32
 GN_ITERS = 10
 HUBER = 2.45
+STREAM_EVENTS = 200
 # per accepted pair and Gauss-Newton step: 7 gradient + 28 Hessian entries,
-# each w * (a*b + c*d) accumulated (5 FP64 flops), plus the match count
-REFINE_F64_PER_PAIR = 35 * 5 + 1
+# each w * (a*b + c*d) accumulated in float32 (5 flops), plus the match count
+REFINE_FLOPS_PER_PAIR = 35 * 5 + 1
 REFINE_BYTES_PER_PAIR = 32   # one accepted-pair record read (then kept in registers)
-# HBM bytes per launch measured with rocprofv3 counters, one "traffic:" line
-# per kernel with the hash of the sources it was measured on
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loop_event_20kf.hbm_counters.md")
+# HBM bytes per launch measured with rocprofv3 counters, one
+# "traffic: <kernel> <workload> <bytes> <sources hash>" line per kernel and
+# workload
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_counters.md")
 KERNEL_SOURCES = {
     "search_fused_kernel": ("paper_2603_17201_amd/csrc/fl_search.h", "paper_2603_17201_amd/csrc/fl_internal.h"),
     "refine_kernel": ("paper_2603_17201_amd/csrc/fl_residual.h", "paper_2603_17201_amd/csrc/fl_internal.h"),
@@ -72,17 +78,26 @@ def sources_hash(kernel):
 
 
 def search_bytes(ev, params, n_pairs):
-    """Algorithmic bytes of one search-kernel launch: every point's xyz,
-    descriptor, distance invariance and id once (52 B), every keypoint's
-    cell-ordered record and descriptor and owner once (52 B), every grid
-    and owner-table entry once, every pair's 13 bytes of outputs once (and
-    its 4-byte point index when pairs are sparse)."""
+    """Algorithmic bytes of one search launch (the compulsory traffic, each
+    input once and each output once), summed over the launch's events: 48 B
+    per point (xyz, descriptor, distance invariance), 45 B per keypoint (xy,
+    octave, descriptor, owner), each keyframe's grid (cell starts and cell
+    list) written once and read once, 4 B per pair of a sparse pair list,
+    each keyframe's observed-point bitset over its event's points written
+    once and read once, and 13 B of outputs per pair."""
     cells = params.grid_cols * params.grid_rows
-    n_kp = np.diff(ev.kp_offset)
-    hash_bytes = 4 * sum(max(16, 1 << int(np.ceil(np.log2(max(2 * int(k), 1))))) for k in n_kp)
-    sparse = 0 if getattr(ev, "pair_mp", None) is None else 4 * n_pairs
-    return (52 * ev.n_mp + 52 * int(ev.kp_offset[-1]) + 4 * (cells + 1) * ev.n_kf + hash_bytes
-            + 13 * n_pairs + sparse)
+    kp_off = np.asarray(ev.kp_offset, np.int64)
+    ekf = np.asarray(getattr(ev, "event_kf_offset", [0, ev.n_kf]), np.int64)
+    emp = np.asarray(getattr(ev, "event_mp_offset", [0, ev.n_mp]), np.int64)
+    sparse = getattr(ev, "pair_mp", None) is not None
+    total = 13 * n_pairs + (4 * n_pairs if sparse else 0)
+    for e in range(len(ekf) - 1):
+        k0, k1 = int(ekf[e]), int(ekf[e + 1])
+        n_mp = int(emp[e + 1] - emp[e])
+        n_kp = kp_off[k0 + 1:k1 + 1] - kp_off[k0:k1]
+        total += 48 * n_mp + 45 * int(n_kp.sum()) + int(sum(2 * (4 * (cells + 1) + 4 * int(k)) for k in n_kp))
+        total += -(-n_mp // 8) * 2 * (k1 - k0)
+    return total
 
 
 def search_ops(st, n_pairs):
@@ -107,40 +122,40 @@ def sim3_error(S, S_ref):
     return float(ang), float(np.linalg.norm(te)), float(abs(np.log(se)))
 
 
-def cpu_baseline(ev, budget_s=12.0, max_events=20):
-    """The oracle as it stands: brute-force search-and-fuse of the event,
-    then 10 float64 Gauss-Newton steps on its accepted pairs; repeated until
-    about budget_s."""
+def oracle_event(ev, use_grid):
+    """The oracle on one loop event as it stands: search-and-fuse (grid or
+    brute force), then 10 float64 Gauss-Newton steps on its accepted pairs."""
     import oracle
     from oracle import residual as R
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        out = oracle.search_fuse(ev, use_grid=False)
-        acc = np.nonzero((out["decision"] == oracle.ADD) | (out["decision"] == oracle.FUSE))[0]
-        kf = np.searchsorted(ev.pair_offset, acc, side="right") - 1
-        mp = acc - ev.pair_offset[kf]
-        kp = ev.kp_offset[kf] + out["best_idx"][acc]
-        R.gauss_newton(ev.S_init, ev.mp_xyz[mp], ev.kp_xy[kp], kf, ev.kf_T, ev.cams[0], HUBER, iters=GN_ITERS)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= max_events:
-            break
-    return n, el
+    out = oracle.search_fuse(ev, use_grid=use_grid)
+    acc = np.nonzero((out["decision"] == oracle.ADD) | (out["decision"] == oracle.FUSE))[0]
+    kf = np.searchsorted(ev.pair_offset, acc, side="right") - 1
+    mp = acc - ev.pair_offset[kf]
+    kp = ev.kp_offset[kf] + out["best_idx"][acc]
+    R.gauss_newton(ev.S_init, ev.mp_xyz[mp], ev.kp_xy[kp], kf, ev.kf_T, ev.cams[0], HUBER, iters=GN_ITERS)
 
 
-def cpu_worker(budget_s, start_at):
-    """Child process of the CPU baseline (never touches the GPU): the loop
-    event's oracle run from start_at (a wall-clock time shared by all
-    workers of one measurement) for about budget_s; prints {n, el}."""
+def cpu_worker(budget_s, start_at, first, stride, use_grid):
+    """Child process of the CPU baseline (never touches the GPU): events
+    first, first + stride, ... of the stream through the oracle, from
+    start_at (a wall-clock time shared by all workers of one measurement)
+    until about budget_s of oracle time; the events are generated outside
+    the timed part.  Prints {n, el, pairs}."""
     import synth
-    ev = synth.gen_c2()
     import oracle  # noqa: F401  (library loaded before the clock starts)
     delay = start_at - time.time()
     if delay > 0:
         time.sleep(delay)
-    n, el = cpu_baseline(ev, budget_s, max_events=10 ** 6)
-    print(json.dumps(dict(n=n, el=el, n_pairs=int(ev.pair_offset[-1]))), flush=True)
+    n, el, pairs, e = 0, 0.0, 0, first
+    while el < budget_s:
+        ev = synth.gen_c5_event(e % STREAM_EVENTS)
+        t0 = time.perf_counter()
+        oracle_event(ev, use_grid)
+        el += time.perf_counter() - t0
+        n += 1
+        pairs += int(ev.pair_offset[-1])
+        e += stride
+    print(json.dumps(dict(n=n, el=el, pairs=pairs)), flush=True)
 
 
 def host_cpu():
@@ -157,25 +172,56 @@ def host_cpu():
     return dict(nproc=avail, cpu_count=os.cpu_count(), model=model)
 
 
-def run_cpu_workers(n_workers, budget_s):
+def run_cpu_workers(n_workers, budget_s, use_grid):
     """The oracle in n_workers concurrent single-threaded child processes
-    (BLAS and OpenMP held at one thread, no GPU visible); returns the
-    aggregate pairs/s and the per-worker results."""
+    (BLAS and OpenMP held at one thread, no GPU visible), worker w on stream
+    events w, w + n_workers, ...; returns the aggregate pairs/s and the
+    per-worker results."""
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                HIP_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
     start_at = time.time() + 6.0 + 0.2 * n_workers
     procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(budget_s),
-                               "--cpu-start", repr(start_at)], stdout=subprocess.PIPE, env=env, text=True)
-             for _ in range(n_workers)]
+                               "--cpu-start", repr(start_at), "--cpu-first", str(w), "--cpu-stride", str(n_workers),
+                               "--cpu-grid", str(int(use_grid))], stdout=subprocess.PIPE, env=env, text=True)
+             for w in range(n_workers)]
     res = []
     for p in procs:
-        out, _ = p.communicate(timeout=budget_s * 4 + 300)
+        out, _ = p.communicate(timeout=budget_s * 6 + 300)
         if p.returncode != 0:
             raise RuntimeError(f"cpu baseline worker failed ({p.returncode})")
         res.append(json.loads(out.strip().splitlines()[-1]))
-    rate = sum(r["n"] * r["n_pairs"] / r["el"] for r in res)
+    rate = sum(r["pairs"] / r["el"] for r in res)
     return rate, res
+
+
+def search_roofline(nbytes, nops, ms, peaks=None):
+    """Roofline of search launches that moved nbytes algorithmic bytes and ran
+    nops algorithmic lane-ops in ms: the bound is whichever peak the work
+    would take longer on."""
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = nops / (ALU_PEAK_TOPS * 1e12)
+    if t_alu > t_hbm:
+        r = dict(bound="alu", achieved=nops / (ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
+    else:
+        r = dict(bound="hbm", achieved=nbytes / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    r.update(frac=r["achieved"] / r["peak"], kernel_us=ms * 1e3, alg_bytes=nbytes, alg_ops=nops,
+             roofline_us=max(t_hbm, t_alu) * 1e6)
+    if peaks:
+        r["frac_of_measured_peak"] = (r["achieved"] / peaks["hbm_copy_gbs"] if r["bound"] == "hbm"
+                                      else r["achieved"] * 1e12 / peaks["valu_lane_ops_per_s"])
+    return r
+
+
+def refine_roofline(n_acc, ms):
+    """Roofline of refinement launches over n_acc accepted pairs in ms: the
+    float32 sums of g and H against the FP32 vector peak."""
+    flops = REFINE_FLOPS_PER_PAIR * n_acc * GN_ITERS
+    return dict(bound="alu", achieved=flops / (ms * 1e-3) / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, kernel_us=ms * 1e3, alg_flops=flops,
+                alg_bytes=REFINE_BYTES_PER_PAIR * n_acc, roofline_us=flops / (FP32_PEAK_TFLOPS * 1e12) * 1e6,
+                note="float32 per-pair sums, float64 across workgroups; ten dependent steps, each one cross-CU "
+                     "exchange and one 7x7 solve: latency bound")
 
 
 class Bench:
@@ -274,9 +320,9 @@ class Bench:
             y.copy_(x)
         torch.cuda.synchronize()
 
-    def traffic(self, kernel):
-        """HBM bytes per launch of `kernel` from the committed counter
-        summary, or None when its sources changed since it was measured."""
+    def traffic(self, kernel, workload):
+        """HBM bytes per launch of `kernel` on `workload` from the committed
+        counter summary, or None when its sources changed since then."""
         try:
             with open(TRAFFIC_FILE) as fh:
                 lines = [ln.split() for ln in fh if ln.startswith("traffic:")]
@@ -284,140 +330,60 @@ class Bench:
             return None
         src = "search_fused_kernel" if kernel.startswith("search_fused_kernel") else kernel
         for ln in lines:
-            if len(ln) == 4 and ln[1] == kernel and ln[3] == sources_hash(src):
-                return int(ln[2])
+            if len(ln) == 5 and ln[1] == kernel and ln[2] == workload and ln[4] == sources_hash(src):
+                return int(float(ln[3]))
         return None
 
     # -- workloads -------------------------------------------------------------
-    def headline(self):
+    def loop_event(self):
+        """The loop event of 20 keyframes (752x480, 1,200 keypoints each) and
+        15,000 points, 300,000 dense pairs: batched (graph, eager, two
+        contexts) against the plain path."""
         import synth
         torch, fl, ctx, args = self.torch, self.fl, self.ctx, self.args
-        log("generating the loop event (20 keyframes x 1,200 keypoints, 15,000 points)")
         ev = synth.gen_c2()
         P = ev.params
         b = fl.DeviceBatch(ev, device=self.dev)
         n_pairs = b.n_pairs
         out = fl.FuseOutputs.empty(n_pairs, self.dev)
-
-        tuning = None
-        if not args.no_autotune:
-            t, ms = ctx.autotune(b, P, out, reps=3)
-            tuning = dict(pairs_per_lane=t[0], lds_mode=t[1], wg_per_cu=t[2], xcd_aware=t[3])
-            log(f"autotune: {tuning} ({ms * 1e3:.1f} us per eager batched search)")
-
-        # exact per-class counters of this workload (one untimed counting launch)
-        ctx.set_stats(True)
-        ctx.search_fuse_batched(b, P, out)
-        torch.cuda.synchronize()
-        st = ctx.get_stats()
-        ctx.set_stats(False)
-
         S_init = torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(self.dev)
         S = S_init.clone()
         n_matched = torch.zeros(1, dtype=torch.int32, device=self.dev)
         host, host_S = self.host_buffers(n_pairs)
-
         gc.collect()
         gc.disable()   # a full collection inside a ~100 us step would be timed as GPU work
-        # kernel times: eager search + refinement, HIP events around each kernel
-        ctx.set_profiling(True)
-        for _ in range(args.steps):
-            S.copy_(S_init)
-            ctx.search_fuse_batched(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched))
-        ks_ms, ks_n = ctx.get_profile("search")
-        kr_ms, kr_n = ctx.get_profile("refine")
-        ctx.set_profiling(False)
-        ks_ms /= max(ks_n, 1)
-        kr_ms /= max(kr_n, 1)
-        n_acc = int(n_matched.item())
-
-        plain = None
-        if not args.no_plain:
-            log(f"plain: {args.plain_steps} events, per-keyframe calls with copy + sync")
-            plan = self.plain_plan(ev, b, out)
-            times = [self.plain_event(plan, b, out, P, S, S_init, host, host_S)
-                     for _ in range(2 + args.plain_steps)][2:]
-            ms_plain = statistics.median(times)
-            plain = dict(ms_per_event=ms_plain, pairs_per_s=n_pairs / (ms_plain * 1e-3),
-                         p99_ms=float(np.percentile(times, 99)))
-            log(f"plain: {ms_plain:.3f} ms per event")
 
         def step():
-            # the refinement continues from the previous step's Sim3: the same
-            # ten Gauss-Newton steps of work on every step
             ctx.search_fuse_graph(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched))
-
-        log(f"batched: warmup {args.warmup}, timing {args.steps} steps")
-        ms_step = self.events_time(step, args.steps, args.warmup)
-        log(f"batched: {ms_step * 1e3:.1f} us per event (device-resident)")
+        ms_graph = self.events_time(step, args.steps, args.warmup)
         ms_eager = self.events_time(
             lambda: ctx.search_fuse_batched(b, P, out, refine=(GN_ITERS, HUBER, S, None, n_matched)),
             args.steps, args.warmup)
-        log(f"batched, eager launches: {ms_eager * 1e3:.1f} us per event (device-resident)")
-
-        # consecutive steps alternating between two contexts on two streams
-        # (each with its own outputs and Sim3; the inputs are shared, read
-        # only): one step's search runs beside the previous step's refinement
-        ctx2 = fl.Context(0)
-        tv = ctx.get_tuning()
-        ctx2.set_tuning(tv.pairs_per_lane, tv.lds_mode, tv.wg_per_cu, tv.xcd_aware)
-        ctxs = [ctx, ctx2]
-        strs = [self.stream, torch.cuda.Stream(self.dev)]
-        outs = [out, fl.FuseOutputs.empty(n_pairs, self.dev)]
-        Ss = [S, S.clone()]
-        nms = [n_matched, torch.zeros_like(n_matched)]
-
-        def two(i):
-            k = i & 1
-            ctxs[k].search_fuse_batched(b, P, outs[k], refine=(GN_ITERS, HUBER, Ss[k], None, nms[k]), stream=strs[k])
-        for i in range(args.warmup):
-            two(i)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            two(i)
-        torch.cuda.synchronize()
-        ms_two = (time.perf_counter() - t0) * 1e3 / args.steps
-        ctx2.close()
-        log(f"batched, two contexts on two streams: {ms_two * 1e3:.1f} us per event (throughput)")
-
         e2e = []
         for i in range(args.warmup + args.steps):
             t0 = time.perf_counter()
             step()
-            for k, h in host.items():
-                h.copy_(getattr(out, k), non_blocking=True)
+            for k, hb in host.items():
+                hb.copy_(getattr(out, k), non_blocking=True)
             host_S.copy_(S, non_blocking=True)
             self.stream.synchronize()
             if i >= args.warmup:
                 e2e.append((time.perf_counter() - t0) * 1e3)
-        ms_e2e = statistics.median(e2e)
+        res = dict(n_pairs=n_pairs, n_kf=ev.n_kf, n_mp=ev.n_mp, ms_per_event_graph=ms_graph,
+                   ms_per_event_eager=ms_eager, ms_per_event_graph_with_d2h=statistics.median(e2e),
+                   pairs_per_s=n_pairs / (min(ms_graph, ms_eager) * 1e-3))
+        res.update(self.kernel_rooflines(ev, b, P, out, S, S_init))
+        if not args.no_plain:
+            plan = self.plain_plan(ev, b, out)
+            times = [self.plain_event(plan, b, out, P, S, S_init, host, host_S)
+                     for _ in range(2 + args.plain_steps)][2:]
+            res["plain_ms_per_event"] = statistics.median(times)
+            res["batched_vs_plain"] = res["plain_ms_per_event"] / res["ms_per_event_graph_with_d2h"]
+            res["batched_vs_plain_device_resident"] = res["plain_ms_per_event"] / min(ms_graph, ms_eager)
         gc.enable()
-
-        # rooflines of both kernels; the one with the larger time leads
-        nbytes = search_bytes(ev, P, n_pairs)
-        nops = search_ops(st, n_pairs)
-        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-        t_alu = nops / (ALU_PEAK_TOPS * 1e12)
-        if t_alu > t_hbm:
-            rs = dict(bound="alu", achieved=nops / (ks_ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
-        else:
-            rs = dict(bound="hbm", achieved=nbytes / (ks_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-        tv = ctx.get_tuning()
-        variant = f"search_fused_kernel<{tv.pairs_per_lane},{tv.lds_mode}>"   # <pairs per lane, LDS mode>
-        rs.update(frac=rs["achieved"] / rs["peak"], traffic=self.traffic(variant), kernel=variant,
-                  kernel_us=ks_ms * 1e3, alg_bytes=nbytes, alg_ops=nops, roofline_us=max(t_hbm, t_alu) * 1e6)
-        rflops = REFINE_F64_PER_PAIR * n_acc * GN_ITERS
-        t_f = rflops / (FP64_PEAK_TFLOPS * 1e12)
-        rr = dict(bound="alu", achieved=rflops / (kr_ms * 1e-3) / 1e12, peak=FP64_PEAK_TFLOPS,
-                  unit="TFLOP/s", traffic=self.traffic("refine_kernel"), kernel="refine_kernel", kernel_us=kr_ms * 1e3,
-                  alg_flops=rflops, alg_bytes=REFINE_BYTES_PER_PAIR * n_acc, roofline_us=t_f * 1e6,
-                  note="fp64; ten dependent steps, each one cross-CU exchange and one 7x7 solve: latency bound")
-        rr["frac"] = rr["achieved"] / rr["peak"]
-        roof, other = (rr, rs) if kr_ms > ks_ms else (rs, rr)
-        log(f"kernels: search {ks_ms * 1e3:.1f} us, refine {kr_ms * 1e3:.1f} us ({n_acc} accepted pairs)")
-        return dict(ev=ev, n_pairs=n_pairs, ms_step=ms_step, ms_e2e=ms_e2e, ms_eager=ms_eager, plain=plain,
-                    tuning=tuning, roof=roof, other=other, n_acc=n_acc, ms_two=ms_two)
+        log(f"loop event: {ms_graph * 1e3:.1f} us graph, {ms_eager * 1e3:.1f} us eager per event; search "
+            f"{res['search_kernel_us']:.1f} us, refine {res['refine_kernel_us']:.1f} us")
+        return res
 
     def kernel_rooflines(self, ev, b, P, out, S, S_init):
         """Kernel times of eager launches (search + refinement) of one batch
@@ -437,16 +403,7 @@ class Bench:
         ctx.set_profiling(False)
         ks_ms /= max(ks_n, 1)
         kr_ms /= max(kr_n, 1)
-        nbytes, nops = search_bytes(ev, P, b.n_pairs), search_ops(st, b.n_pairs)
-        t_hbm, t_alu = nbytes / (HBM_PEAK_GBS * 1e9), nops / (ALU_PEAK_TOPS * 1e12)
-        if t_alu > t_hbm:
-            roof = dict(bound="alu", achieved=nops / (ks_ms * 1e-3) / 1e12, peak=ALU_PEAK_TOPS, unit="Tops/s")
-        else:
-            roof = dict(bound="hbm", achieved=nbytes / (ks_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-        roof.update(frac=roof["achieved"] / roof["peak"], kernel_us=ks_ms * 1e3, alg_bytes=nbytes, alg_ops=nops)
-        if self.peaks:
-            roof["frac_of_measured_peak"] = (roof["achieved"] / self.peaks["hbm_copy_gbs"] if roof["bound"] == "hbm"
-                                             else roof["achieved"] * 1e12 / self.peaks["valu_lane_ops_per_s"])
+        roof = search_roofline(search_bytes(ev, P, b.n_pairs), search_ops(st, b.n_pairs), ks_ms, self.peaks)
         return dict(search_kernel_us=ks_ms * 1e3, refine_kernel_us=kr_ms * 1e3, search_roofline=roof)
 
     def batch_graph(self, ev, label, steps):
@@ -648,108 +605,171 @@ class Bench:
         return dict(n_pairs=n, fwd_us=f * 1e3, bwd_us=bw * 1e3, bwd_inverse_direction_us=bwi * 1e3,
                     autograd_fwd_bwd_us=ab * 1e3, bwd_pairs_per_s=n / (bw * 1e-3))
 
-    def stream_events(self, n_events):
-        """The stream of uneven loop events: each event resident, one graph
-        launch (search + 10 GN steps) per event.  Consecutive events alternate
-        between two contexts on two streams, so one event's search overlaps
-        the previous one's refinement (which keeps few CUs busy); the same
-        stream on one context and one stream is reported beside it."""
+    def stream_headline(self):
+        """The stream of uneven loop events, every event resident in HBM: the
+        timed steps are consecutive events, each one batched launch sequence
+        (table fetch, search with ADD resolution, 10 Gauss-Newton steps)."""
         import synth
-        torch, fl = self.torch, self.fl
+        torch, fl, ctx, args = self.torch, self.fl, self.ctx, self.args
+        n_events = args.stream_events
         log(f"stream: generating {n_events} uneven events")
         evs = [synth.gen_c5_event(e) for e in range(n_events)]
         bs = [fl.DeviceBatch(ev, device=self.dev) for ev in evs]
-        max_pairs = max(b.n_pairs for b in bs)
-        ctxs = [self.ctx, fl.Context(0)]
-        tv = self.ctx.get_tuning()
-        ctxs[1].set_tuning(tv.pairs_per_lane, tv.lds_mode, tv.wg_per_cu, tv.xcd_aware)
-        streams = [self.stream, torch.cuda.Stream(self.dev)]
-        bufs = [fl.FuseOutputs.empty(max_pairs, self.dev) for _ in range(2)]
+        P = evs[0].params
+        bufs = [fl.FuseOutputs.empty(max(b.n_pairs for b in bs), self.dev) for _ in range(2)]
 
         def view(k, b):
             o = bufs[k]
             return fl.FuseOutputs(o.best_idx[:b.n_pairs], o.best_dist[:b.n_pairs], o.second_dist[:b.n_pairs],
                                   o.decision[:b.n_pairs], o.target[:b.n_pairs])
 
-        outs = [[view(k, b) for b in bs] for k in range(2)]
+        big = max(range(n_events), key=lambda i: bs[i].n_pairs)
+        tuning = None
+        if not args.no_autotune:
+            t, ms = ctx.autotune(bs[big], P, view(0, bs[big]), reps=3)
+            tuning = dict(pairs_per_lane=t[0], lds_mode=t[1], wg_per_cu=t[2], xcd_aware=t[3])
+            log(f"autotune on the largest event: {tuning} ({ms * 1e3:.1f} us per eager search)")
+        # exact per-class counters of every event (untimed counting launches)
+        ctx.set_stats(True)
+        stats = []
+        for i in range(n_events):
+            ctx.search_fuse_batched(bs[i], P, view(0, bs[i]))
+            torch.cuda.synchronize()
+            stats.append(ctx.get_stats())
+        ctx.set_stats(False)
+        nbytes = [search_bytes(evs[i], P, bs[i].n_pairs) for i in range(n_events)]
+        nops = [search_ops(stats[i], bs[i].n_pairs) for i in range(n_events)]
         S_init = [torch.from_numpy(ev.S_init.reshape(1, 13).copy()).to(self.dev) for ev in evs]
-        S = [s.clone() for s in S_init]
+        S = [x.clone() for x in S_init]
         nm = torch.zeros(n_events, dtype=torch.int32, device=self.dev)
-        P = evs[0].params
+        ctx2 = fl.Context(0)
+        tv = ctx.get_tuning()
+        ctx2.set_tuning(tv.pairs_per_lane, tv.lds_mode, tv.wg_per_cu, tv.xcd_aware)
+        ctxs = [ctx, ctx2]
+        streams = [self.stream, torch.cuda.Stream(self.dev)]
+        K, W = args.steps, args.warmup
+        seq = [(W + j) % n_events for j in range(K)]   # the timed events, in order
 
-        def launch(i, n_ctx):
-            k = i % n_ctx
-            ctxs[k].search_fuse_graph(bs[i], P, outs[k][i], refine=(GN_ITERS, HUBER, S[i], None, nm[i:i + 1]),
-                                      stream=streams[k])
+        def launch(i, k=0, graph=False):
+            c = ctxs[k]
+            f = c.search_fuse_graph if graph else c.search_fuse_batched
+            f(bs[i], P, view(k, bs[i]), refine=(GN_ITERS, HUBER, S[i], None, nm[i:i + 1]), stream=streams[k])
 
-        def timed(n_ctx):
+        def reset():
             for i in range(n_events):
                 S[i].copy_(S_init[i])
             torch.cuda.synchronize()
-            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(n_events)]
-            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(n_events)]
-            t0 = time.perf_counter()
-            for i in range(n_events):
-                e0[i].record(streams[i % n_ctx])
-                launch(i, n_ctx)
-                e1[i].record(streams[i % n_ctx])
+
+        def timed(n_ctx, graph, profile=False):
+            """W warmup events, then the K timed events between a device
+            synchronisation and HIP events on both sides; returns (wall ms,
+            per-event ms)."""
+            for j in range(W):
+                launch(j % n_events, j % n_ctx, graph)
+            reset()
+            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            if profile:
+                ctx.set_profiling(True)
             torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            return wall, [e0[i].elapsed_time(e1[i]) for i in range(n_events)]
+            t0.record(streams[0])
+            for k in range(1, n_ctx):
+                streams[k].wait_event(t0)
+            for j, i in enumerate(seq):
+                k = j % n_ctx
+                e0[j].record(streams[k])
+                launch(i, k, graph)
+                e1[j].record(streams[k])
+            for k in range(1, n_ctx):
+                streams[0].wait_stream(streams[k])
+            t1.record(streams[0])
+            torch.cuda.synchronize()
+            return t0.elapsed_time(t1), [e0[j].elapsed_time(e1[j]) for j in range(K)]
 
         gc.collect()
         gc.disable()
-        for n_ctx in (1, 2):   # first passes: grow the workspaces to the largest event, capture
+        for k in range(2):   # grow every workspace to the largest event and capture, untimed
             for i in range(n_events):
-                launch(i, n_ctx)
-            torch.cuda.synchronize()
-        wall1, per1 = timed(1)
-        wall, per = timed(2)
-        total = int(sum(b.n_pairs for b in bs))
-        res = dict(n_events=n_events, total_pairs=total, events_per_s=n_events / wall, pairs_per_s=total / wall,
-                   p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
-                   launch="graph replays alternating between two contexts on two streams",
-                   one_context=dict(events_per_s=n_events / wall1, pairs_per_s=total / wall1,
-                                    p50_ms=float(np.percentile(per1, 50)), p99_ms=float(np.percentile(per1, 99))))
-        errs = np.array([sim3_error(S[i].cpu().numpy()[0], ev.S_true) for i, ev in enumerate(evs)])
-        res["final_rot_err_deg_median"] = float(np.median(errs[:, 0]))
-        res["final_trans_err_m_median"] = float(np.median(errs[:, 1]))
-        res["final_scale_err_median"] = float(np.median(errs[:, 2]))
+                launch(i, k, graph=True)
+                launch(i, k, graph=False)
+        torch.cuda.synchronize()
+        log(f"stream: timing {K} events after {W} warmup events (eager, one stream, kernel events)")
+        wall, per = timed(1, False, profile=True)
+        ks_ms, ks_n = ctx.get_profile("search")
+        kr_ms, kr_n = ctx.get_profile("refine")
+        ctx.set_profiling(False)
+        n_acc = int(sum(int(nm[i].item()) for i in seq))
+        errs = np.array([sim3_error(S[i].cpu().numpy()[0], evs[i].S_true) for i in range(n_events)])
         init = np.array([sim3_error(ev.S_init, ev.S_true) for ev in evs])
-        res["init_rot_err_deg_median"] = float(np.median(init[:, 0]))
-        res["init_trans_err_m_median"] = float(np.median(init[:, 1]))
-        res["init_scale_err_median"] = float(np.median(init[:, 2]))
-        res["failed_events"] = int((nm < 0).sum().item())
-        # kernel times and the search roofline of the stream's largest event
-        big = max(range(n_events), key=lambda i: bs[i].n_pairs)
-        kr = self.kernel_rooflines(evs[big], bs[big], P, outs[0][big], S[big], S_init[big])
+        failed = int((nm < 0).sum().item())
+        wall_g, per_g = timed(1, True)
+        wall_2, per_2 = timed(2, True)
+        gc.enable()
+        pairs = int(sum(bs[i].n_pairs for i in seq))
+        sb, so = int(sum(nbytes[i] for i in seq)), int(sum(nops[i] for i in seq))
+        rs = search_roofline(sb, so, ks_ms, self.peaks)
+        rs.update(kernel=f"search_fused_kernel<{tv.pairs_per_lane},{tv.lds_mode}>", launches=ks_n,
+                  kernel_us=ks_ms / max(ks_n, 1) * 1e3, alg_bytes=sb // max(ks_n, 1), alg_ops=so // max(ks_n, 1),
+                  roofline_us=rs["roofline_us"] / max(ks_n, 1))
+        rs["traffic"] = self.traffic(rs["kernel"], "stream")
+        rr = refine_roofline(n_acc, kr_ms)
+        rr.update(kernel="refine_kernel", launches=kr_n, kernel_us=kr_ms / max(kr_n, 1) * 1e3,
+                  alg_flops=rr["alg_flops"] // max(kr_n, 1), alg_bytes=rr["alg_bytes"] // max(kr_n, 1),
+                  roofline_us=rr["roofline_us"] / max(kr_n, 1), traffic=self.traffic("refine_kernel", "stream"))
+        roof, other = (rs, rr) if ks_ms >= kr_ms else (rr, rs)
+        res = dict(n_events=n_events, steps=K, warmup=W, pairs=pairs, wall_ms=wall, ms_per_event=wall / K,
+                   pairs_per_s=pairs / (wall * 1e-3), events_per_s=K / (wall * 1e-3),
+                   p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
+                   search_kernel_ms_total=ks_ms, refine_kernel_ms_total=kr_ms, matched_pairs=n_acc,
+                   tuning=tuning, roofline=roof, roofline_other_kernel=other,
+                   graph_one_stream=dict(ms_per_event=wall_g / K, pairs_per_s=pairs / (wall_g * 1e-3),
+                                         p50_ms=float(np.percentile(per_g, 50)),
+                                         p99_ms=float(np.percentile(per_g, 99))),
+                   two_contexts_two_streams=dict(ms_per_event=wall_2 / K, pairs_per_s=pairs / (wall_2 * 1e-3),
+                                                 events_per_s=K / (wall_2 * 1e-3),
+                                                 launch="graph replays, consecutive events alternating between "
+                                                        "two contexts on two streams"),
+                   final_rot_err_deg_median=float(np.median(errs[:, 0])),
+                   final_trans_err_m_median=float(np.median(errs[:, 1])),
+                   final_scale_err_median=float(np.median(errs[:, 2])),
+                   init_rot_err_deg_median=float(np.median(init[:, 0])),
+                   init_trans_err_m_median=float(np.median(init[:, 1])),
+                   init_scale_err_median=float(np.median(init[:, 2])), failed_events=failed)
+        log(f"stream: {wall / K * 1e3:.1f} us per event eager ({pairs / (wall * 1e-3) / 1e9:.2f} G pairs/s), "
+            f"{wall_g / K * 1e3:.1f} graph, {wall_2 / K * 1e3:.1f} on two contexts; p50 {res['p50_ms']:.3f} ms, "
+            f"p99 {res['p99_ms']:.3f} ms; kernels: search {ks_ms / max(ks_n, 1) * 1e3:.1f} us, "
+            f"refine {kr_ms / max(kr_n, 1) * 1e3:.1f} us per event")
+        # the stream's largest event on its own: kernel times and search roofline
+        kr = self.kernel_rooflines(evs[big], bs[big], P, view(0, bs[big]), S[big], S_init[big])
         res["largest_event"] = dict(event=big, n_pairs=bs[big].n_pairs, n_kf=bs[big].n_kf, **kr)
-        if not self.args.no_plain:
-            n_plain = min(n_events, self.args.stream_plain_events)
-            ptimes = []
+        if not args.no_plain:
+            n_plain = min(n_events, args.stream_plain_events)
+            ptimes, btimes = [], []
             for i in range(n_plain):
                 host, host_S = self.host_buffers(bs[i].n_pairs)
-                plan = self.plain_plan(evs[i], bs[i], outs[0][i])
-                ptimes.append(self.plain_event(plan, bs[i], outs[0][i], P, S[i], S_init[i], host, host_S))
-            res["plain_events"] = n_plain
-            res["plain_p50_ms"] = float(np.percentile(ptimes, 50))
-            res["plain_p99_ms"] = float(np.percentile(ptimes, 99))
-            res["plain_events_per_s"] = n_plain / (sum(ptimes) * 1e-3)
-            res["batched_vs_plain_same_events"] = sum(ptimes) / sum(per1[:n_plain])
-        gc.enable()
-        log(f"stream: {res['events_per_s']:.1f} events/s on two contexts and streams "
-            f"({res['one_context']['events_per_s']:.1f} on one), p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms")
-        ctxs[1].close()
+                plan = self.plain_plan(evs[i], bs[i], view(0, bs[i]))
+                ptimes.append(self.plain_event(plan, bs[i], view(0, bs[i]), P, S[i], S_init[i], host, host_S))
+                S[i].copy_(S_init[i])
+                btimes.append(self.events_time(lambda: launch(i), 3, 1))
+            res["plain"] = dict(events=n_plain, p50_ms=float(np.percentile(ptimes, 50)),
+                                p99_ms=float(np.percentile(ptimes, 99)),
+                                events_per_s=n_plain / (sum(ptimes) * 1e-3))
+            res["batched_vs_plain_same_events"] = sum(ptimes) / sum(btimes)
+            log(f"plain path on the first {n_plain} events: p50 {res['plain']['p50_ms']:.3f} ms; batched is "
+                f"{res['batched_vs_plain_same_events']:.1f}x faster on the same events")
+        ctx2.close()
+        res["_evs"] = evs
         return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=STREAM_EVENTS, help="timed events of the stream")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed events before them")
     ap.add_argument("--plain-steps", type=int, default=10)
-    ap.add_argument("--stream-events", type=int, default=200)
+    ap.add_argument("--stream-events", type=int, default=STREAM_EVENTS)
     ap.add_argument("--stream-plain-events", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (counter scaling)")
@@ -758,106 +778,111 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-start", type=float, default=0.0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-first", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-stride", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-grid", type=int, default=1, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker is not None:
-        cpu_worker(args.cpu_worker, args.cpu_start)
+        cpu_worker(args.cpu_worker, args.cpu_start, args.cpu_first, args.cpu_stride, bool(args.cpu_grid))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(events and keyframes shard across GPUs without exchange, see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0 or args.stream_events < 1:
+        print("bench.py: --steps must be >= 1, --warmup >= 0, --stream-events >= 1", file=sys.stderr)
+        sys.exit(2)
 
     # The CPU baselines run first, in child processes started before this
     # process touches the GPU.
-    cpu = cpu_all = None
+    cpu = cpu_extra = None
     if not args.no_cpu_baseline:
         host = host_cpu()
-        log(f"cpu baseline: oracle (brute-force search + float64 GN) on the same event, one thread "
+        log(f"cpu baseline: oracle (grid search + float64 GN) on stream events, one thread "
             f"({host['nproc']} cores available, {host['model']})")
-        rate1, r1 = run_cpu_workers(1, 12.0)
-        n, el = r1[0]["n"], r1[0]["el"]
+        rate1, r1 = run_cpu_workers(1, 12.0, True)
         cpu = dict(value=rate1, unit="pairs/s", cores=1, kind="oracle",
-                   sample=f"{n} full loop events of this workload ({n * r1[0]['n_pairs']} pairs), "
-                          f"single-threaded C oracle + NumPy float64 Gauss-Newton in one child process, {el:.1f} s",
-                   ms_per_event=el / n * 1e3, host=host)
+                   sample=f"stream events 0-{r1[0]['n'] - 1} ({r1[0]['pairs']} pairs), C oracle with its keypoint "
+                          f"grid + NumPy float64 Gauss-Newton, one thread in one child process, "
+                          f"{r1[0]['el']:.1f} s of oracle time", host=host)
+        log("cpu baseline: the brute-force oracle (every keypoint of the keyframe per pair), one thread")
+        rate_b, rb = run_cpu_workers(1, 12.0, False)
         workers = max(1, min(16, host["nproc"]))
-        log(f"cpu baseline: the same oracle in {workers} concurrent single-threaded processes")
-        rate_all, rs = run_cpu_workers(workers, 10.0)
-        cpu_all = dict(value=rate_all, unit="pairs/s", cores=workers, kind="oracle",
-                       sample=f"{sum(r['n'] for r in rs)} full loop events over {workers} concurrent processes "
-                              f"(one thread each, ~10 s each, started together)", host=host)
+        log(f"cpu baseline: the grid oracle in {workers} concurrent single-threaded processes")
+        rate_all, ra = run_cpu_workers(workers, 10.0, True)
+        cpu_extra = dict(
+            brute_force_one_thread=dict(value=rate_b, unit="pairs/s", cores=1, kind="oracle",
+                                        sample=f"stream events 0-{rb[0]['n'] - 1} ({rb[0]['pairs']} pairs), "
+                                               f"{rb[0]['el']:.1f} s of oracle time"),
+            grid_all_cores=dict(value=rate_all, unit="pairs/s", cores=workers, kind="oracle",
+                                sample=f"{sum(r['n'] for r in ra)} stream events over {workers} concurrent "
+                                       f"processes (one thread each, ~10 s of oracle time each)"))
 
     import synth
     bench = Bench(args)
     if args.copy_probe:
         bench.copy_probe()
-    h = bench.headline()
-
-    secondary = None
     hbm_meas = bench.hbm_copy_gbs()
     valu_meas = max(bench.ctx.valu_rate(iters=10000) for _ in range(3))
     log(f"measured device copy: {hbm_meas:.0f} GB/s (read + write); "
         f"measured VALU issue rate: {valu_meas / 1e12:.1f} T lane-ops/s")
-    peaks = dict(hbm_copy_gbs=hbm_meas, valu_lane_ops_per_s=valu_meas,
-                 note="1 GiB device copy (read + write bytes); eight independent v_xor_b32 + v_bcnt_u32_b32 "
-                      "chains per lane on every CU; the rooflines use the published peaks, "
-                      "frac_of_measured_peak these")
-    bench.peaks = peaks
-    for roof in (h["roof"], h["other"]):
-        if roof["bound"] == "hbm":
-            roof["frac_of_measured_peak"] = roof["achieved"] / hbm_meas
-        elif roof["unit"] == "Tops/s":
-            roof["frac_of_measured_peak"] = roof["achieved"] * 1e12 / valu_meas
+    bench.peaks = dict(hbm_copy_gbs=hbm_meas, valu_lane_ops_per_s=valu_meas,
+                       note="1 GiB device copy (read + write bytes); eight independent v_xor_b32 + v_bcnt_u32_b32 "
+                            "chains per lane on every CU; the rooflines use the published peaks, "
+                            "frac_of_measured_peak these")
+    h = bench.stream_headline()
+    evs = h.pop("_evs")
+
+    secondary = None
     if not args.quick:
-        secondary = {"uneven_event_60kf": bench.batch_graph(synth.gen_c3(), "uneven event", args.steps)}
-        evs = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
+        secondary = {"loop_event_20kf": bench.loop_event()}
+        secondary["uneven_event_60kf"] = bench.batch_graph(synth.gen_c3(), "uneven event", 30)
+        c3s = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
                for i in range(10)]
-        B = synth.concat_events(evs)
-        B.event_S_init = np.stack([e.S_init for e in evs])
+        B = synth.concat_events(c3s)
+        B.event_S_init = np.stack([e.S_init for e in c3s])
         secondary["uneven_event_60kf_x10_one_launch"] = bench.batch_graph(B, "ten uneven events", 10)
         secondary["residual_50k"] = bench.residual()
-        secondary["projection_search"] = bench.projection_search(args.steps)
-        secondary["robust_refinement"] = bench.robust_refinement(args.steps)
-        secondary["essential_graph"] = bench.essential_graph(args.steps)
-        if args.stream_events > 0:
-            secondary["stream"] = bench.stream_events(args.stream_events)
+        secondary["projection_search"] = bench.projection_search(30)
+        secondary["robust_refinement"] = bench.robust_refinement(30)
+        secondary["essential_graph"] = bench.essential_graph(30)
 
-    ev, plain = h["ev"], h["plain"]
-    # the batched path: one table upload and one launch sequence per event,
-    # replayed from a HIP graph, launched eagerly, or launched eagerly with
-    # consecutive events alternating between two contexts on two streams
-    # (every event still runs its whole search and refinement), whichever
-    # gives the higher throughput here
-    launch, ms_best = min((("graph", h["ms_step"]), ("eager", h["ms_eager"]),
-                           ("eager, consecutive events on two contexts and streams", h["ms_two"])),
-                          key=lambda c: c[1])
+    n_kf = [int(ev.n_kf) for ev in evs]
+    n_mp = [int(ev.n_mp) for ev in evs]
     res = dict(
-        metric="point-keyframe match candidates/s (batched loop event incl. 10 GN steps)",
-        value=h["n_pairs"] / (ms_best * 1e-3), unit="pairs/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=ms_best, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f32", data="synthetic",
-        config=dict(workload="loop event: 20 keyframes 752x480 x 1,200 keypoints, 15,000 points, "
-                             "300,000 dense pairs; search-and-fuse + 10 Gauss-Newton Sim3 steps",
-                    n_pairs=h["n_pairs"], n_kf=ev.n_kf, n_mp=ev.n_mp, gn_iters=GN_ITERS, tuning=h["tuning"],
-                    launch=launch),
-        ms_per_event_batched_graph=h["ms_step"], ms_per_event_batched_eager=h["ms_eager"],
-        ms_per_event_batched_graph_with_d2h=h["ms_e2e"],
-        ms_per_event_two_contexts_two_streams=h["ms_two"],
-        pairs_per_s_two_contexts_two_streams=h["n_pairs"] / (h["ms_two"] * 1e-3),
-        plain=plain,
-        batched_vs_plain=(plain["ms_per_event"] / h["ms_e2e"]) if plain else None,
-        batched_vs_plain_device_resident=(plain["ms_per_event"] / ms_best) if plain else None,
-        matched_pairs=h["n_acc"],
-        roofline=h["roof"],
-        roofline_other_kernel=h["other"],
+        metric=METRIC, value=h["pairs_per_s"], unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=h["ms_per_event"], higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload=f"stream of {args.stream_events} uneven loop events (seeds 5000+e): 5-80 keyframes of "
+                             "752x480 or 512x512, 300-2,500 keypoints each, 5,000-100,000 points, every point "
+                             "against every keyframe of its event; batched search-and-fuse + 10 Gauss-Newton "
+                             "Sim3 steps per event, eager launches on one stream",
+                    events=args.stream_events, pairs_per_event_mean=h["pairs"] / args.steps,
+                    n_kf_range=[min(n_kf), max(n_kf)], n_mp_range=[min(n_mp), max(n_mp)], gn_iters=GN_ITERS,
+                    tuning=h["tuning"]),
+        ms_per_event_p50=h["p50_ms"], ms_per_event_p99=h["p99_ms"], events_per_s=h["events_per_s"],
+        stream_graph_one_stream=h["graph_one_stream"],
+        stream_two_contexts_two_streams=h["two_contexts_two_streams"],
+        plain=h.get("plain"), batched_vs_plain_same_events=h.get("batched_vs_plain_same_events"),
+        matched_pairs=h["matched_pairs"],
+        sim3_error=dict(init_rot_deg_median=h["init_rot_err_deg_median"],
+                        final_rot_deg_median=h["final_rot_err_deg_median"],
+                        init_trans_m_median=h["init_trans_err_m_median"],
+                        final_trans_m_median=h["final_trans_err_m_median"],
+                        init_log_scale_median=h["init_scale_err_median"],
+                        final_log_scale_median=h["final_scale_err_median"], failed_events=h["failed_events"]),
+        roofline=h["roofline"],
+        roofline_other_kernel=h["roofline_other_kernel"],
+        largest_event=h["largest_event"],
         cpu_baseline=cpu,
-        cpu_baseline_all_cores=cpu_all,
-        measured_peaks=peaks,
+        cpu_baseline_other=cpu_extra,
+        measured_peaks=bench.peaks,
         secondary=secondary,
     )
     bench.ctx.close()
     print(json.dumps(res), flush=True)
+
 
 if __name__ == "__main__":
     main()
