@@ -205,6 +205,27 @@ int fl_search_fuse(fl_ctx* ctx, int32_t n_mp, const float* mp_xyz, const uint8_t
                    const fl_sim3* S /* host */, const fl_pinhole* K /* host */,
                    const fl_params* P /* host */, const fl_fuse_out* out /* host */, hipStream_t stream);
 
+/* fl_search_fuse without a context and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it).  Same arguments (less the
+ * context), same outputs and the same kernels.  Its scratch (the keyframe's
+ * grid when none is given, the owner hash set, the ADD claims and list) is
+ * one static device array of 1 MiB per GPU, resolved once per device (in
+ * fl_create, or at the first call on the current device): a keyframe of
+ * n_kp keypoints needs about 8 * n_kp + 4 * pow2(2 n_kp) + 16 * min(n_mp,
+ * max(2 n_kp, 4096)) + 4 * cells bytes, so keyframes of up to about 16,000
+ * keypoints fit whatever n_mp.
+ * Every call on one GPU shares that array and rewrites what it reads first;
+ * calls that overlap on one GPU (two streams, or threads, in flight at once)
+ * race on it and must be serialised by the caller.  Runs on the current
+ * device.  Errors: as fl_search_fuse; FL_ERANGE when the scratch would not
+ * hold the call (use fl_search_fuse); FL_EHIP when the array's address
+ * cannot be resolved. */
+int fl_search_fuse_noalloc(int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc, const float* mp_dmax,
+                           const int32_t* mp_id, const fl_keyframe* kf /* host */, const fl_sim3* S /* host */,
+                           const fl_pinhole* K /* host */, const fl_params* P /* host */,
+                           const fl_fuse_out* out /* host */, hipStream_t stream);
+
 /* Host-only check of a batch (every test fl_search_fuse_batched makes before
  * enqueuing anything; no device memory is touched, no context needed).
  * Returns FL_OK or the error code the batched call would return. */

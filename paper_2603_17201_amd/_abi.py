@@ -102,6 +102,9 @@ SIGNATURES = [
     ("fl_search_fuse", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                  ctypes.POINTER(Keyframe), ctypes.POINTER(Sim3), ctypes.POINTER(Pinhole),
                                  ctypes.POINTER(Params), ctypes.POINTER(FuseOut), c_void_p]),
+    ("fl_search_fuse_noalloc", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(Keyframe),
+                                         ctypes.POINTER(Sim3), ctypes.POINTER(Pinhole), ctypes.POINTER(Params),
+                                         ctypes.POINTER(FuseOut), c_void_p]),
     ("fl_validate_batch", c_int32, [ctypes.POINTER(Batch), ctypes.POINTER(Params), ctypes.POINTER(FuseOut)]),
     ("fl_search_fuse_batched", c_int32, [c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Params),
                                          ctypes.POINTER(FuseOut), ctypes.POINTER(Refine), c_void_p]),

@@ -487,6 +487,35 @@ class Context:
         _check(self._lib.fl_debug_set_list_cap(self._h, int(cap)), "fl_debug_set_list_cap")
 
 
+def search_fuse_noalloc(mp_xyz, mp_desc, mp_dmax, mp_id, kp_xy, kp_oct, kp_desc, kp_owner, sim3_16, cam8, params,
+                        grid=None, out: Optional[FuseOutputs] = None, stream=None) -> FuseOutputs:
+    """fl_search_fuse_noalloc on the current device: the plain search without a
+    context, its scratch in the library's static device array (the output
+    tensors, when not given, are still allocated here by torch)."""
+    lib = _abi.load()
+    d = mp_xyz.device
+    n = int(mp_xyz.shape[0])
+    if out is None:
+        out = FuseOutputs.empty(n, d)
+    kf = Keyframe(int(kp_xy.shape[0]), _ptr(kp_xy, torch.float32, "kp_xy", device=d),
+                  _ptr(kp_oct, torch.int8, "kp_oct", 1, d), _ptr(kp_desc, torch.uint8, "kp_desc", 16, d),
+                  _ptr(kp_owner, torch.int32, "kp_owner", device=d),
+                  _ptr(grid[0], torch.int32, "cell_start", device=d) if grid is not None else None,
+                  _ptr(grid[1], torch.int32, "cell_kp", device=d) if grid is not None else None)
+    S = sim3_struct(sim3_16)
+    K = pinhole_struct(cam8)
+    P = params_struct(params)
+    o = out.struct()
+    s = stream if stream is not None else torch.cuda.current_stream(d)
+    _check(lib.fl_search_fuse_noalloc(n, _ptr(mp_xyz, torch.float32, "mp_xyz", device=d),
+                                      _ptr(mp_desc, torch.uint8, "mp_desc", 16, d),
+                                      _ptr(mp_dmax, torch.float32, "mp_dmax", device=d),
+                                      _ptr(mp_id, torch.int32, "mp_id", device=d), ctypes.byref(kf), ctypes.byref(S),
+                                      ctypes.byref(K), ctypes.byref(P), ctypes.byref(o), ctypes.c_void_p(s.cuda_stream)),
+           "fl_search_fuse_noalloc")
+    return out
+
+
 class Sim3Residual(torch.autograd.Function):
     """loss = sum_i Huber(|pi(T_k exp(xi) S0 X_i) - uv_i|).
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <mutex>
 #include <queue>
 #include <vector>
 
@@ -899,6 +900,9 @@ void allow_lds_all(size_t bytes) {
 // C ABI
 
 static void clear_profile(fl_ctx* c);
+namespace {
+int scratch_of_current_device(void** out);
+}
 
 extern "C" {
 
@@ -917,6 +921,11 @@ int fl_create(fl_ctx** out, int device) {
     FL_HIP(hipGetDeviceProperties(&prop, device));
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(FL_ENOTSUP, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    {
+        void* sp = nullptr;   // the allocation-free search's scratch on this device, resolved at set-up
+        const int rs = scratch_of_current_device(&sp);
+        if (rs) return rs;
+    }
     fl_ctx* c = new fl_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -1102,6 +1111,35 @@ int plain_launch(char* base, const PlainLayout& L, int32_t n_mp, const float* mp
     return FL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free plain search: one static device array per
+// GPU (each device holds its own copy at its own address, found once per
+// device with hipGetSymbolAddress).  The array's name in host code is not a
+// device address; only the resolved pointer is passed to kernels.
+constexpr size_t kNoAllocScratch = 1u << 20;   // bytes per GPU
+__device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch array (resolved on the
+// first request for that device).
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    FL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FL_ENOTSUP, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FL_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1118,6 +1156,24 @@ int fl_search_fuse(fl_ctx* c, int32_t n_mp, const float* mp_xyz, const uint8_t* 
     if (rc) return rc;
     return plain_launch((char*)c->plain.p, L, n_mp, mp_xyz, mp_desc, mp_dmax, mp_id, kf, S, K, P, out, stream);
 }
+
+int fl_search_fuse_noalloc(int32_t n_mp, const float* mp_xyz, const uint8_t* mp_desc, const float* mp_dmax,
+                           const int32_t* mp_id, const fl_keyframe* kf, const fl_sim3* S, const fl_pinhole* K,
+                           const fl_params* P, const fl_fuse_out* out, hipStream_t stream) {
+    int rc = check_plain(n_mp, mp_xyz, mp_desc, kf, S, K, P, out);
+    if (rc) return rc;
+    const PlainLayout L = plain_layout(n_mp, kf->n_kp, P->grid_cols * P->grid_rows, 0);
+    if (L.bytes > kNoAllocScratch)
+        return fail(FL_ERANGE, "n_kp %d with %d grid cells needs %zu bytes of scratch; the allocation-free search "
+                    "holds %zu (use fl_search_fuse)", kf->n_kp, P->grid_cols * P->grid_rows, L.bytes,
+                    kNoAllocScratch);
+    void* base = nullptr;
+    rc = scratch_of_current_device(&base);
+    if (rc) return rc;
+    if (n_mp == 0) return FL_OK;
+    return plain_launch((char*)base, L, n_mp, mp_xyz, mp_desc, mp_dmax, mp_id, kf, S, K, P, out, stream);
+}
+
 
 int fl_validate_batch(const fl_batch* B, const fl_params* P, const fl_fuse_out* out) {
     return validate_batch(B, P, out);

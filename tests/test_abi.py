@@ -185,3 +185,24 @@ def test_refine_tags_never_repeat_between_clears(lib):
     assert lib.fl_debug_refine_tag((-5) & 0xFFFFFFFF, 3) == lib.fl_debug_refine_tag((-5 - period) & 0xFFFFFFFF, 3)
     # distinct steps of one launch have distinct tags
     assert len({lib.fl_debug_refine_tag(12345, s) for s in range(1000)}) == 1000
+
+
+def test_noalloc_search_rejects_what_its_scratch_cannot_hold(lib):
+    # a keyframe of 30,000 keypoints needs more than the 1 MiB static scratch
+    # of the allocation-free search: refused on the host, before any device
+    # work (the pointers are never dereferenced)
+    fake = 0x10000
+    P = _abi.Params(3.0, 1.2, 8, 64, 48, 50, 0.0, 0)
+    K = _abi.Pinhole(458, 458, 367, 248, 752, 480)
+    S = _abi.Sim3()
+    o = _abi.FuseOut(fake, fake, fake, fake, fake)
+    kf = _abi.Keyframe(30000, fake, fake, fake, fake, None, None)
+    rc = lib.fl_search_fuse_noalloc(100000, fake, fake, None, None, ctypes.byref(kf), ctypes.byref(S), ctypes.byref(K),
+                                    ctypes.byref(P), ctypes.byref(o), None)
+    assert rc == _abi.FL_ERANGE, (rc, fl.last_error())
+    assert "scratch" in fl.last_error()
+    # and argument errors are those of fl_search_fuse
+    kf = _abi.Keyframe(100, None, fake, fake, fake, None, None)
+    rc = lib.fl_search_fuse_noalloc(10, fake, fake, None, None, ctypes.byref(kf), ctypes.byref(S), ctypes.byref(K),
+                                    ctypes.byref(P), ctypes.byref(o), None)
+    assert rc == _abi.FL_EINVAL
