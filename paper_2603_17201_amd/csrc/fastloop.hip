@@ -377,10 +377,20 @@ int64_t plan_tiles(const std::vector<int64_t>& pairs, const std::vector<int32_t>
     return n;
 }
 
-// Choose the staging mode: the tuned one if its LDS footprint fits.
-int pick_mode(const fl_ctx* c, int want, int kp_cap, int cells, int hash_cap) {
-    for (int m = want; m > kModeGlobal; --m)
-        if (search_lds_bytes(m, kp_cap, cells, hash_cap) <= c->lds_max) return m;
+// Choose the staging mode and the octave groups per cell: the most groups
+// (up to one per octave, at most max_nb) whose LDS footprint fits in the
+// tuned mode or a smaller one, and whose record slots (two per keypoint with
+// more than one group) stay below 65536.
+int pick_mode(const fl_ctx* c, int want, int kp_cap, int cells, int hash_cap, int max_nb, int* nb_out) {
+    for (int nb = max_nb; nb >= 1; nb = nb > 4 ? 4 : nb / 2) {
+        if (search_slots(kp_cap, nb) > FL_MAX_KP) continue;
+        for (int m = want; m > kModeGlobal; --m)
+            if (search_lds_bytes(m, kp_cap, cells, hash_cap, nb) <= c->lds_max) {
+                *nb_out = nb;
+                return m;
+            }
+    }
+    *nb_out = 1;
     return kModeGlobal;
 }
 
@@ -408,8 +418,14 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     int kp_cap = 1;
     for (int k = 0; k < n_kf; ++k) kp_cap = std::max(kp_cap, B->kp_offset[k + 1] - B->kp_offset[k]);
     const int lds_hash_cap = std::max(64, next_pow2(kp_cap + 1));
-    pr.mode = pick_mode(c, c->tune.lds_mode, kp_cap, cells, lds_hash_cap);
-    pr.lds = search_lds_bytes(pr.mode, kp_cap, cells, lds_hash_cap);
+    // octave groups: one per octave (at most 8) with the gate on; one group
+    // (the plain grid) with the gate off and for counting launches, whose
+    // keypoint counts are per grid cell
+    const bool gate = B->mp_dmax != nullptr;
+    const int max_nb = (gate && !c->stats) ? std::min(P->n_octaves, 8) : 1;
+    int nb = 1;
+    pr.mode = pick_mode(c, c->tune.lds_mode, kp_cap, cells, lds_hash_cap, max_nb, &nb);
+    pr.lds = search_lds_bytes(pr.mode, kp_cap, cells, lds_hash_cap, nb);
     if (graph && pr.mode != kModeGlobal) pr.lds = std::min(c->lds_max, align_up(pr.lds, 16384));
 
     // workgroups of the search launch (every slot in graph mode, at most one
@@ -670,6 +686,7 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
     h.stats = c->stats;
     h.lds_hash_mask = lds_hash_cap - 1;
     h.lds_kp_cap = kp_cap;   // the record capacity search_lds_bytes sized
+    h.oct_buckets = nb;
     h.n_wg = grid;
     SearchConst sc;
     fill_search_const(P, sc, h.sf);

@@ -136,6 +136,8 @@ struct alignas(16) BatchHdr {
     int32_t refine_scan;        // 1: take accepted pairs from the decisions, not the list
     int32_t resolve_in_refine;  // 1: the refinement kernel resolves the search's ADD conflicts
     int32_t lds_kp_cap;         // keypoint capacity of the LDS records in the LDS modes
+    int32_t oct_buckets;        // octave buckets per grid cell in the LDS modes (1 .. 8)
+    int32_t pad_buckets[3];
     float sf[32];               // scale_factor^n rounded to float32
     // tables in the uploaded blob
     const KfDesc* kf;

@@ -132,90 +132,125 @@ __device__ void block_exclusive_scan(int32_t* a, int n, int32_t* s_tmp) {
     __syncthreads();
 }
 
+// Workgroup exclusive scan of n_words packed pairs of 16-bit counts in place
+// (low half first): word k becomes (P, P + lo) for P the sum of every count
+// before it.  Every sum must stay below 65536.  Same shape as
+// block_exclusive_scan.
+__device__ void block_exclusive_scan_u16(uint32_t* w, int n, int32_t* s_tmp) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = wave_lane(), wid = tid / kWave, nw = nt / kWave;
+    const int chunk = (n + nt - 1) / nt;
+    const int b = min(tid * chunk, n), e = min(b + chunk, n);
+    int sum = 0;
+    for (int i = b; i < e; ++i) sum += (int)(w[i] & 0xFFFFu) + (int)(w[i] >> 16);
+    const int incl = wave_incl_scan(sum);
+    if (lane == kWave - 1) s_tmp[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        const int t = lane < nw ? s_tmp[lane] : 0;
+        const int x = wave_incl_scan(t);
+        if (lane < nw) s_tmp[lane] = x - t;
+        if (lane == nw - 1) s_tmp[nw] = x;
+    }
+    __syncthreads();
+    uint32_t run = (uint32_t)(s_tmp[wid] + incl - sum);
+    for (int i = b; i < e; ++i) {
+        const uint32_t x = w[i], lo = x & 0xFFFFu, hi = x >> 16;
+        w[i] = run | ((run + lo) << 16);
+        run += lo + hi;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// Keyframe grid in LDS: histogram of cells, exclusive scan, scatter of
-// cell-ordered records (and descriptors), owner hash set.  On return s_cs[c]
-// is the first slot of cell c and s_cs[cells] = n_kp.  The order of the
-// keypoints inside a cell is arbitrary: the packed (distance, index) key
-// makes every output independent of it.
+// Keyframe grid in LDS by octave group.  With the octave gate on, a pair
+// whose point is predicted at octave p has as candidates the keypoints of
+// octaves p - 1 and p; group g = min(p, nb - 1) holds exactly those
+// keypoints for g < nb - 1, and the last group every octave from nb - 2 up,
+// so a pair reads the cells of one group.  A keypoint of octave o therefore
+// sits in up to two groups (o and o + 1 below nb - 1, the last group from
+// o = nb - 2 up; octaves below -1 can never be candidates).  With nb = 1
+// (the gate off, or too little LDS) group 0 is the plain grid of every
+// keypoint.  Slots are ordered by row, then group, then column, so a pair's
+// candidates are one run of slots per grid row.  Histogram of the (row,
+// group, column) cells (16-bit counts, two per 32-bit word), exclusive scan,
+// scatter of slot-ordered records (and descriptors), owner hash set.  On
+// return s_cs[j] is the first slot of cell j and s_cs[R * nb * C] the
+// number of slots (below 65536).  The order of the records inside a cell is
+// arbitrary: the packed (distance, index) key makes every output
+// independent of it.
+
+// The groups of a keypoint of octave o: a (or -1) and b (or -1).
+__device__ __forceinline__ void groups_of(int o, int nb, int& a, int& b) {
+    if (nb == 1) {
+        a = 0;
+        b = -1;
+        return;
+    }
+    a = (o >= 0 && o <= nb - 2) ? o : -1;
+    b = (o + 1 >= 0 && o + 1 <= nb - 2) ? o + 1 : (o >= nb - 2 ? nb - 1 : -1);
+}
+
+// 16-bit entry j of a packed array, incremented; returns its old value.
+__device__ __forceinline__ int u16_fetch_add(uint32_t* w, int j) {
+    const int sh = (j & 1) * 16;
+    return (int)((atomicAdd(&w[j >> 1], 1u << sh) >> sh) & 0xFFFFu);
+}
 
 template <bool STAGE_DESC>
-__device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, int32_t* s_cs, KpRec* s_rec, uint4* s_desc,
-                               int32_t* s_own, int32_t* s_hash, int32_t* s_tmp) {
+__device__ void stage_keyframe(const BatchHdr& h, const KfDesc& kd, uint16_t* s_cs, KpRec* s_rec, uint4* s_desc,
+                               int32_t* s_hash, int32_t* s_tmp) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int n = kd.n_kp;
-    const int cells = h.cells, C = h.grid_cols, R = h.grid_rows;
+    const int C = h.grid_cols, R = h.grid_rows, nb = h.oct_buckets;
+    const int entries = R * nb * C + 1;          // cell starts and the end
+    const int words = (entries + 1) / 2;
+    uint32_t* w = reinterpret_cast<uint32_t*>(s_cs);
     const int hmask = h.lds_hash_mask;
     const float* xy = h.kp_xy + 2 * (int64_t)kd.kp_off;
-    for (int c = tid; c <= cells; c += nt) s_cs[c] = 0;
+    for (int c = tid; c < words; c += nt) w[c] = 0;
     for (int s = tid; s <= hmask; s += nt) s_hash[s] = -1;
     __syncthreads();
-    // The first kStageRegs keypoints of each thread are loaded once, with
-    // their descriptors, and kept in registers across the scan; any further
-    // keypoints (keyframes larger than kStageRegs * blockDim) are reloaded.
-    constexpr int kStageRegs = 1;
-    float kx[kStageRegs], ky[kStageRegs];
-    int ko[kStageRegs], kc[kStageRegs], kw[kStageRegs];
-    uint4 kd0[kStageRegs], kd1[kStageRegs];
-#pragma unroll
-    for (int q = 0; q < kStageRegs; ++q) {
-        const int i = tid + q * nt;
-        kc[q] = -1;
-        if (i < n) {
-            kx[q] = xy[2 * i];
-            ky[q] = xy[2 * i + 1];
-            ko[q] = (int)h.kp_oct[kd.kp_off + i];
-            if (STAGE_DESC) {
-                const uint4* src = reinterpret_cast<const uint4*>(h.kp_desc + 32 * ((int64_t)kd.kp_off + i));
-                kd0[q] = src[0];
-                kd1[q] = src[1];
-            }
-            const int32_t o = h.kp_owner[kd.kp_off + i];
-            kw[q] = o;
-            kc[q] = cell_of(ky[q], kd.invh, R) * C + cell_of(kx[q], kd.invw, C);
-            atomicAdd(&s_cs[kc[q] + 1], 1);
-            if (o >= 0) owner_insert(s_hash, hmask, o);
-        }
-    }
-    for (int i = tid + kStageRegs * nt; i < n; i += nt) {
-        const int c = cell_of(xy[2 * i + 1], kd.invh, R) * C + cell_of(xy[2 * i], kd.invw, C);
-        atomicAdd(&s_cs[c + 1], 1);
+    // cell of group g of keypoint i: (row * nb + g) * C + col
+    for (int i = tid; i < n; i += nt) {
+        const float x = xy[2 * i], y = xy[2 * i + 1];
+        const int base = cell_of(y, kd.invh, R) * nb * C + cell_of(x, kd.invw, C);
+        int ga, gb;
+        groups_of((int)h.kp_oct[kd.kp_off + i], nb, ga, gb);
+        if (ga >= 0) u16_fetch_add(w, base + ga * C + 1);
+        if (gb >= 0) u16_fetch_add(w, base + gb * C + 1);
         const int32_t o = h.kp_owner[kd.kp_off + i];
         if (o >= 0) owner_insert(s_hash, hmask, o);
     }
     __syncthreads();
-    block_exclusive_scan(s_cs + 1, cells, s_tmp);   // s_cs[1 + c] = first slot of c
-#pragma unroll
-    for (int q = 0; q < kStageRegs; ++q) {
-        if (kc[q] < 0) continue;
-        const int slot = atomicAdd(&s_cs[kc[q] + 1], 1);   // ends as the first slot of c + 1
-        KpRec r;
-        r.x = kx[q];
-        r.y = ky[q];
-        r.idx = tid + q * nt;
-        r.oct = ko[q];
-        s_rec[slot] = r;
-        s_own[slot] = kw[q];
-        if (STAGE_DESC) {
-            s_desc[2 * slot] = kd0[q];
-            s_desc[2 * slot + 1] = kd1[q];
-        }
-    }
-    for (int i = tid + kStageRegs * nt; i < n; i += nt) {
+    block_exclusive_scan_u16(w, words, s_tmp);   // entry 1 + j = first slot of cell j
+    for (int i = tid; i < n; i += nt) {
         const float x = xy[2 * i], y = xy[2 * i + 1];
-        const int c = cell_of(y, kd.invh, R) * C + cell_of(x, kd.invw, C);
-        const int slot = atomicAdd(&s_cs[c + 1], 1);
+        const int oct = (int)h.kp_oct[kd.kp_off + i];
+        const int base = cell_of(y, kd.invh, R) * nb * C + cell_of(x, kd.invw, C);
+        int ga, gb;
+        groups_of(oct, nb, ga, gb);
         KpRec r;
         r.x = x;
         r.y = y;
         r.idx = i;
-        r.oct = (int)h.kp_oct[kd.kp_off + i];
-        s_rec[slot] = r;
-        s_own[slot] = h.kp_owner[kd.kp_off + i];
-        if (STAGE_DESC) {
+        r.oct = oct;
+        uint4 d0 = make_uint4(0, 0, 0, 0), d1 = d0;
+        if (STAGE_DESC && (ga >= 0 || gb >= 0)) {
             const uint4* src = reinterpret_cast<const uint4*>(h.kp_desc + 32 * ((int64_t)kd.kp_off + i));
-            s_desc[2 * slot] = src[0];
-            s_desc[2 * slot + 1] = src[1];
+            d0 = src[0];
+            d1 = src[1];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int g = q ? gb : ga;
+            if (g < 0) continue;
+            const int slot = u16_fetch_add(w, base + g * C + 1);   // ends as the first slot of the next cell
+            s_rec[slot] = r;
+            if (STAGE_DESC) {
+                s_desc[2 * slot] = d0;
+                s_desc[2 * slot + 1] = d1;
+            }
         }
     }
     __syncthreads();
@@ -354,21 +389,34 @@ __device__ __forceinline__ void wave_append(bool want, uint32_t* counter, T* lis
 // stream.
 
 struct KfView {
-    const int32_t* cs;
+    const int32_t* cs;          // global grid: cell starts (one bucket per cell)
+    const uint16_t* cs16;       // LDS: octave-bucket starts
+    int nb;                     // octave buckets per cell
     const KpRec* rec;
     const uint4* desc;          // cell-ordered descriptors (LDS or workspace), or null
     const uint8_t* desc_orig;   // keypoint descriptors by original index (when desc is null)
-    const int32_t* own;         // cell-ordered owners (LDS), or null: read kp_owner by index
+    const int32_t* own;         // unused: the owner of the best keypoint is read from kp_owner
     const int32_t* hash;
     int32_t hash_mask;
 };
 
+// Bytes of the 16-bit octave-bucket starts in LDS (a whole number of 16-byte
+// units).
+__host__ __device__ inline size_t search_cs_bytes(int cells, int nb) {
+    return ((size_t)cells * nb + 2 + 7) / 8 * 16;
+}
+
+// Record slots of a keyframe of kp_cap keypoints in nb octave groups (a
+// keypoint sits in up to two groups when nb > 1).
+__host__ __device__ inline int search_slots(int kp_cap, int nb) { return nb > 1 ? 2 * kp_cap : kp_cap; }
+
 // LDS bytes of the search kernel (shared with the host).
-__host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cells, int hash_cap) {
+__host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cells, int hash_cap, int nb) {
     if (mode == kModeGlobal) return 16;
-    size_t b = 20 * (size_t)kp_cap;   // records + owners
-    if (mode == kModeLdsDesc) b += 32 * (size_t)kp_cap;
-    b += 4 * (size_t)((cells + 4 + 3) & ~3);
+    const size_t slots = (size_t)search_slots(kp_cap, nb);
+    size_t b = 16 * slots;   // records
+    if (mode == kModeLdsDesc) b += 32 * slots;
+    b += search_cs_bytes(cells, nb);
     b += 4 * (size_t)hash_cap;
     b += 4 * (size_t)(kSearchBlock / kWave + 4);
     return b;
@@ -455,13 +503,12 @@ __device__ __forceinline__ float window_radius(const OctaveTable& T, int pred) {
 }
 
 // Evaluation of one pair (point p, keyframe kd): observed-set test, Sim3
-// projection, window gather over the grid rows, Hamming distances, best and
-// second best, and the fuse / add decision (provisional for ADD).  The
-// record ranges of the window's first kRowSeg grid rows are read at once and
-// walked as one flat sequence, so a lane's trip count is its own number of
-// records rather than a sum of per-row maxima over the wave; rows beyond
-// those (wide windows) are walked after.  st: visible pairs, cells scanned,
-// records scanned, candidates.
+// projection, window gather over the grid rows of the pair's octave group,
+// Hamming distances, best and second best, and the fuse / add decision
+// (provisional for ADD).  With the octave gate on, the group holds octaves
+// pred - 1 and pred only: a quarter of the window's keypoints when the eight
+// octaves are equally common.  st: visible pairs, cells scanned, keypoints
+// in them (every octave), candidates.
 constexpr int kRowSeg = 4;
 
 template <int MODE, bool STATS>
@@ -502,22 +549,22 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
     w.c1 = cell_of(w.hx, kd.invw, C);
     w.r0 = cell_of(w.ly, kd.invh, R);
     w.r1 = cell_of(w.hy, kd.invh, R);
-    // record ranges of the first kRowSeg rows: slot = base[j] + m for the
-    // m-th record of the flat sequence when cum[j] <= m < cum[j + 1]
-    int base[kRowSeg], cum[kRowSeg + 1];
-    cum[0] = 0;
-#pragma unroll
-    for (int j = 0; j < kRowSeg; ++j) {
-        const int row = w.r0 + j;
-        const bool in = row <= w.r1;
-        const int rr = in ? row : w.r0;
-        const int s = v.cs[rr * C + w.c0], e = v.cs[rr * C + w.c1 + 1];
-        const int n = in ? e - s : 0;
-        base[j] = s - cum[j];
-        cum[j + 1] = cum[j] + n;
-        if (STATS && in) {
+    // The window's candidates: rows r0..r1 of the pair's octave group (the
+    // group of pred; group 0 when there is one group), each row a run of
+    // slots over columns c0..c1.
+    const int nb = MODE == kModeGlobal ? 1 : v.nb;
+    auto cs_at = [&](int j) -> int { return MODE == kModeGlobal ? v.cs[j] : (int)v.cs16[j]; };
+    const int grp = min(pr.pred, nb - 1);
+    const int nrows = w.r1 - w.r0 + 1;
+    if (STATS) {
+        // cells and keypoints of the window's cells (every octave: the
+        // counting launch stages one group)
+        for (int row = w.r0; row <= w.r1; ++row) {
             st[1] += (unsigned long long)(w.c1 - w.c0 + 1);
-            st[2] += (unsigned long long)n;
+            for (int g = 0; g < nb; ++g) {
+                const int j = (row * nb + g) * C;
+                st[2] += (unsigned long long)(cs_at(j + w.c1 + 1) - cs_at(j + w.c0));
+            }
         }
     }
     int bslot = 0;
@@ -540,6 +587,20 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
             }
         }
     };
+    // The runs of the first kRowSeg rows, walked as one flat sequence: slot
+    // = base[j] + m for the m-th record when cum[j] <= m < cum[j + 1].  A
+    // lane's trip count is its own number of records, not a sum of per-row
+    // maxima over the wave.
+    int base[kRowSeg], cum[kRowSeg + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kRowSeg; ++j) {
+        const bool in = j < nrows;
+        const int idx = ((in ? w.r0 + j : w.r0) * nb + grp) * C;
+        const int s0 = cs_at(idx + w.c0), e0 = cs_at(idx + w.c1 + 1);
+        base[j] = s0 - cum[j];
+        cum[j + 1] = cum[j] + (in ? e0 - s0 : 0);
+    }
     auto slot_of = [&](int m) {
         int b = base[0];
 #pragma unroll
@@ -559,18 +620,16 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
         if (m + 1 < total) r_next = v.rec[i_next];
         visit(i, rc);
     }
+    // rows beyond the first kRowSeg (wide windows)
     for (int row = w.r0 + kRowSeg; row <= w.r1; ++row) {
-        const int s = v.cs[row * C + w.c0], e = v.cs[row * C + w.c1 + 1];
-        if (STATS) {
-            st[1] += (unsigned long long)(w.c1 - w.c0 + 1);
-            st[2] += (unsigned long long)(e - s);
-        }
-        for (int i = s; i < e; ++i) visit(i, v.rec[i]);
+        const int j = (row * nb + grp) * C;
+        const int s0 = cs_at(j + w.c0), e0 = cs_at(j + w.c1 + 1);
+        for (int i = s0; i < e0; ++i) visit(i, v.rec[i]);
     }
     if (!accept_match(res.best, hamming_th, nn_ratio)) {
         p.dec = FL_NO_MATCH;
     } else {
-        const int32_t ow = v.own ? v.own[bslot] : kp_owner[kd.kp_off + (int32_t)(res.best.key & 0xFFFFu)];
+        const int32_t ow = kp_owner[kd.kp_off + (int32_t)(res.best.key & 0xFFFFu)];
         if (ow >= 0) {
             p.dec = FL_FUSE;
             res.target = ow;
@@ -588,8 +647,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     const int lane = wave_lane();
     KpRec* s_rec = reinterpret_cast<KpRec*>(s_mem);
     uint4* s_desc = nullptr;
-    int32_t* s_cs = nullptr;
-    int32_t* s_own = nullptr;
+    uint16_t* s_cs = nullptr;
     int32_t* s_hash = nullptr;
     int32_t* s_tmp = nullptr;
     // running counts of the workgroup's ADD and accepted-pair regions, then
@@ -597,15 +655,14 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     __shared__ uint32_t s_list[4];
     const int wid = tid / kWave, nw = (int)(blockDim.x / kWave);
     if (MODE != kModeGlobal) {
-        unsigned char* p = s_mem + 16 * (size_t)h.lds_kp_cap;
+        const size_t slots = (size_t)search_slots(h.lds_kp_cap, h.oct_buckets);
+        unsigned char* p = s_mem + 16 * slots;
         if (MODE == kModeLdsDesc) {
             s_desc = reinterpret_cast<uint4*>(p);
-            p += 32 * (size_t)h.lds_kp_cap;
+            p += 32 * slots;
         }
-        s_own = reinterpret_cast<int32_t*>(p);
-        p += 4 * (size_t)h.lds_kp_cap;
-        s_cs = reinterpret_cast<int32_t*>(p);
-        p += 4 * (size_t)((h.cells + 4 + 3) & ~3);
+        s_cs = reinterpret_cast<uint16_t*>(p);
+        p += search_cs_bytes(h.cells, h.oct_buckets);
         s_hash = reinterpret_cast<int32_t*>(p);
         p += 4 * (size_t)(h.lds_hash_mask + 1);
         s_tmp = reinterpret_cast<int32_t*>(p);
@@ -675,6 +732,8 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         KfView v;
         if (MODE == kModeGlobal) {
             v.cs = h.cell_start + kd.grid_off;
+            v.cs16 = nullptr;
+            v.nb = 1;
             v.rec = h.recs + kd.kp_off;
             v.desc = h.desc_sorted + 2 * (int64_t)kd.kp_off;
             v.desc_orig = nullptr;
@@ -684,14 +743,16 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         } else {
             if (staged != kd.stage_key) {
                 __syncthreads();   // every reader of the previous keyframe is done
-                stage_keyframe<MODE == kModeLdsDesc>(h, kd, s_cs, s_rec, s_desc, s_own, s_hash, s_tmp);
+                stage_keyframe<MODE == kModeLdsDesc>(h, kd, s_cs, s_rec, s_desc, s_hash, s_tmp);
                 staged = kd.stage_key;
             }
-            v.cs = s_cs;
+            v.cs = nullptr;
+            v.cs16 = s_cs;
+            v.nb = uniform_i(h.oct_buckets);
             v.rec = s_rec;
             v.desc = MODE == kModeLdsDesc ? s_desc : nullptr;
             v.desc_orig = h.kp_desc + 32 * (int64_t)kd.kp_off;
-            v.own = s_own;
+            v.own = nullptr;
             v.hash = s_hash;
             v.hash_mask = h.lds_hash_mask;
         }
