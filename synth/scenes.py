@@ -449,7 +449,7 @@ def gen_c1(seed: int = 101) -> Event:
 
 
 def gen_c2(seed: int = 202, skip_frac: float = 0.0, n_kf: int = 20, n_mp: int = 15000,
-           n_kp: int = 1200, perturb: bool = True, misplace=None) -> Event:
+           n_kp: int = 1200, perturb: bool = True, misplace=None, kp_counts=None) -> Event:
     """Loop event: 20 keyframes 752x480 on a 3 m arc of radius 5 m, 1,200
     keypoints each (50% planted, 30% outliers, 20% pre-owned duplicates),
     15,000 points at depth 0.5-20 m in the middle keyframe's frustum, loop
@@ -457,14 +457,18 @@ def gen_c2(seed: int = 202, skip_frac: float = 0.0, n_kf: int = 20, n_mp: int = 
     The search runs at a Sim3 perturbed from the truth by 0.1 deg, 1 cm and
     0.2% scale (the state before refinement).  misplace = (fraction, lo, hi)
     moves that fraction of the planted keypoints U[lo, hi] px away from their
-    point's projection (wrong associations)."""
+    point's projection (wrong associations).  kp_counts (one per keyframe)
+    replaces n_kf x n_kp keypoint counts."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    if kp_counts is not None:
+        n_kf = len(kp_counts)
     S = _random_loop_sim3(rng, 0.95, 1.05, 5.0, 0.1)
     S_init = _perturb(rng, S, 0.1, 0.01, 0.002) if perturb else S
     poses = _arc_poses(n_kf, 5.0, 3.0 / max(n_kf - 1, 1))
     mid = n_kf // 2
     return gen_event(rng, cam=CAM_752, kf_poses=poses, S_true=S, S_init=S_init, n_mp=n_mp,
-                     depth=(0.5, 20.0), anchors=np.full(n_mp, mid), kp_counts=[n_kp] * n_kf,
+                     depth=(0.5, 20.0), anchors=np.full(n_mp, mid),
+                     kp_counts=list(kp_counts) if kp_counts is not None else [n_kp] * n_kf,
                      frac_planted=0.5, frac_outlier=0.3, frac_dup=0.2, skip_frac=skip_frac,
                      misplace=misplace, name="c2")
 

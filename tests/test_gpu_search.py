@@ -293,3 +293,34 @@ def test_c2_with_ratio_test(ctx):
     P = synth.LoopParams(nn_ratio=0.75)
     exp = oracle.search_fuse(ev, params=P, use_grid=True)
     assert_same(batched(ctx, ev, params=P), exp, "c2 ratio")
+
+
+def test_keyframe_at_the_packed_key_limit(ctx):
+    # a keyframe of FL_MAX_KP = 65,535 keypoints (the 16-bit index of the
+    # packed key) between two ordinary ones: too large for LDS, so the
+    # batched launch takes its global-grid mode; the plain path runs each
+    # keyframe on its own
+    import paper_2603_17201_amd as fl
+    ev = synth.gen_c2(seed=515, n_mp=4000, kp_counts=[1200, fl.MAX_KP, 1200])
+    exp = oracle.search_fuse(ev, use_grid=True)
+    assert int(exp["best_idx"].max()) > 60000   # indices near the limit are matched
+    assert_same(batched(ctx, ev), exp, "batched")
+    assert_same(batched(ctx, ev, graph=True), exp, "graph")
+    assert_same(plain_per_keyframe(ctx, ev, ev.params), exp, "plain")
+
+
+@pytest.mark.parametrize("big", [6000, 20000])
+def test_one_large_keyframe_among_small_ones(ctx, big):
+    # one keyframe of `big` keypoints among 1,200-keypoint ones: the LDS
+    # footprint is sized by the largest, so the launch stages fewer octave
+    # buckets (6,000) or falls back to global grids (20,000) for every
+    # keyframe; every tuning stays bit-exact
+    ev = synth.gen_c2(seed=616 + big, n_mp=3000, kp_counts=[1200, 1200, big, 1200, 1200])
+    exp = oracle.search_fuse(ev, use_grid=True)
+    saved = ctx.get_tuning()
+    try:
+        for ppl, mode in itertools.product((1, 2, 4), (0, 1, 2)):
+            ctx.set_tuning(ppl, mode, 1, 1)
+            assert_same(batched(ctx, ev), exp, f"ppl {ppl} mode {mode}")
+    finally:
+        ctx.set_tuning(saved.pairs_per_lane, saved.lds_mode, saved.wg_per_cu, saved.xcd_aware)
