@@ -625,7 +625,11 @@ class Bench:
 
         big = max(range(n_events), key=lambda i: bs[i].n_pairs)
         tuning = None
-        if not args.no_autotune:
+        if args.tuning:
+            t = [int(x) for x in args.tuning.split(",")]
+            ctx.set_tuning(*t)
+            tuning = dict(pairs_per_lane=t[0], lds_mode=t[1], wg_per_cu=t[2], xcd_aware=t[3], fixed=True)
+        elif not args.no_autotune:
             t, ms = ctx.autotune(bs[big], P, view(0, bs[big]), reps=3)
             tuning = dict(pairs_per_lane=t[0], lds_mode=t[1], wg_per_cu=t[2], xcd_aware=t[3])
             log(f"autotune on the largest event: {tuning} ({ms * 1e3:.1f} us per eager search)")
@@ -689,11 +693,13 @@ class Bench:
 
         gc.collect()
         gc.disable()
-        for k in range(2):   # grow every workspace to the largest event and capture, untimed
-            for i in range(n_events):
-                launch(i, k, graph=True)
-                launch(i, k, graph=False)
-        torch.cuda.synchronize()
+        only = args.only_eager
+        if not only:
+            for k in range(2):   # grow every workspace to the largest event and capture, untimed
+                for i in range(n_events):
+                    launch(i, k, graph=True)
+                    launch(i, k, graph=False)
+            torch.cuda.synchronize()
         log(f"stream: timing {K} events after {W} warmup events (eager, one stream, kernel events)")
         wall, per = timed(1, False, profile=True)
         ks_ms, ks_n = ctx.get_profile("search")
@@ -703,8 +709,8 @@ class Bench:
         errs = np.array([sim3_error(S[i].cpu().numpy()[0], evs[i].S_true) for i in range(n_events)])
         init = np.array([sim3_error(ev.S_init, ev.S_true) for ev in evs])
         failed = int((nm < 0).sum().item())
-        wall_g, per_g = timed(1, True)
-        wall_2, per_2 = timed(2, True)
+        wall_g, per_g = timed(1, True) if not only else (float("nan"), [float("nan")])
+        wall_2, per_2 = timed(2, True) if not only else (float("nan"), [float("nan")])
         gc.enable()
         pairs = int(sum(bs[i].n_pairs for i in seq))
         sb, so = int(sum(nbytes[i] for i in seq)), int(sum(nops[i] for i in seq))
@@ -741,9 +747,10 @@ class Bench:
             f"p99 {res['p99_ms']:.3f} ms; kernels: search {ks_ms / max(ks_n, 1) * 1e3:.1f} us, "
             f"refine {kr_ms / max(kr_n, 1) * 1e3:.1f} us per event")
         # the stream's largest event on its own: kernel times and search roofline
-        kr = self.kernel_rooflines(evs[big], bs[big], P, view(0, bs[big]), S[big], S_init[big])
-        res["largest_event"] = dict(event=big, n_pairs=bs[big].n_pairs, n_kf=bs[big].n_kf, **kr)
-        if not args.no_plain:
+        if not only:
+            kr = self.kernel_rooflines(evs[big], bs[big], P, view(0, bs[big]), S[big], S_init[big])
+            res["largest_event"] = dict(event=big, n_pairs=bs[big].n_pairs, n_kf=bs[big].n_kf, **kr)
+        if not args.no_plain and not only:
             n_plain = min(n_events, args.stream_plain_events)
             ptimes, btimes = [], []
             for i in range(n_plain):
@@ -776,6 +783,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--only-eager", action="store_true",
+                    help="profiling runs: the stream's eager pass alone (no graph or two-stream passes, no "
+                         "largest-event or plain runs), so each event's kernels are dispatched W + K times")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="pairs_per_lane,lds_mode,wg_per_cu,xcd_aware instead of the autotuner's choice")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-start", type=float, default=0.0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-first", type=int, default=0, help=argparse.SUPPRESS)
@@ -874,7 +886,7 @@ def main():
                         final_log_scale_median=h["final_scale_err_median"], failed_events=h["failed_events"]),
         roofline=h["roofline"],
         roofline_other_kernel=h["roofline_other_kernel"],
-        largest_event=h["largest_event"],
+        largest_event=h.get("largest_event"),
         cpu_baseline=cpu,
         cpu_baseline_other=cpu_extra,
         measured_peaks=bench.peaks,
