@@ -186,7 +186,9 @@ void fl_destroy(fl_ctx* ctx);
 const char* fl_last_error(void);
 int fl_version(void);
 
-/* Keypoint cell grid of one keyframe (the "grid" input of the search).
+/* Keypoint cell grid of one keyframe (the "grid" input of the search): the
+ * paper's loop fusion gathers a point's candidate keypoints from the cells
+ * around its projection (Sec. IV-D3, the projection search of Sec. IV-D1).
  * Cell of a keypoint = (clamp(floor(y*R/H)), clamp(floor(x*C/W))) in float32;
  * cell_start [C*R+1] is the exclusive prefix sum of the per-cell counts and
  * cell_kp [n_kp] lists keypoint indices cell by cell, increasing within a
@@ -330,8 +332,11 @@ int fl_reproj_residual_bwd_inv(fl_ctx* ctx, int32_t n, const float* xyz, const f
  * may be NULL; not both NULL).  Errors: FL_EINVAL for NULL arguments. */
 int fl_sim3_inverse(fl_ctx* ctx, const double* S_in, double* S_out, fl_sim3* S32_out, hipStream_t stream);
 
-/* S_out = exp(xi) S_in (float64, device [7], [13], [13]); S32_out (device,
- * may be NULL) receives the float32 search form. */
+/* S_out = exp(xi) S_in (float64, device [7], [13], [13]): the update of the
+ * Sim3 refinement that follows matching (Sec. IV-C), with the closed-form
+ * Sim3 exponential of Strasdat et al. (RSS 2010); S32_out (device, may be
+ * NULL) receives the float32 search form.  Errors: FL_EINVAL for NULL
+ * arguments. */
 int fl_sim3_exp_mul(fl_ctx* ctx, const double* xi, const double* S_in, double* S_out, fl_sim3* S32_out,
                     hipStream_t stream);
 
@@ -348,7 +353,9 @@ int fl_sim3_exp_mul(fl_ctx* ctx, const double* xi, const double* S_in, double* S
 int fl_sim3_grad_xi(fl_ctx* ctx, const double* xi, const double* g, const double* scale, double* out,
                     hipStream_t stream);
 
-/* One Gauss-Newton / Levenberg-Marquardt step: solve (H + lambda diag(H)) d = -g
+/* One Gauss-Newton / Levenberg-Marquardt step of the Sim3 refinement
+ * (Sec. IV-C; the paper's pose optimisation is Levenberg-Marquardt, Sec. VI):
+ * solve (H + lambda diag(H)) d = -g
  * by float64 Cholesky (g [7], H [28] upper as above, device), then
  * S <- exp(d) S in place (device [13]) and S32 (device, may be NULL) <- its
  * float32 form.  A non-positive pivot leaves S unchanged. */

@@ -302,6 +302,33 @@ __host__ __device__ constexpr bool refine_rows_cleared_before(uint32_t launches)
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & (kWave - 1); }
 
+// Global-memory accesses through the global address space: the compiler
+// then issues global (not flat) loads and stores, with a scalar base where
+// it can.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const gmem<T>*)p;   // address-space cast: generic to global
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, const T& v) {
+    *(gmem<T>*)p = v;
+}
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ldg_u4(const uint4* p) {
+    const v4u x = *(const gmem<v4u>*)p;
+    return make_uint4(x.x, x.y, x.z, x.w);
+}
+// A record of n 16-byte units stored with n dwordx4 global stores.
+template <typename T>
+__device__ __forceinline__ void stg_rec(T* p, const T& v) {
+    static_assert(sizeof(T) % 16 == 0, "whole 16-byte units");
+    const v4u* src = reinterpret_cast<const v4u*>(&v);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 16; ++i) ((gmem<v4u>*)p)[i] = src[i];
+}
+
 // A value known to be the same in every lane, moved to a scalar register
 // (the compiler cannot always tell that a loaded value is uniform, and
 // would otherwise hold it in a vector register of every lane).

@@ -30,8 +30,8 @@ struct SearchConst {
 
 __device__ __forceinline__ void load_desc(const uint8_t* __restrict__ base, int64_t row, uint4& a, uint4& b) {
     const uint4* p = reinterpret_cast<const uint4*>(base + row * 32);
-    a = p[0];
-    b = p[1];
+    a = ldg_u4(p);
+    b = ldg_u4(p + 1);
 }
 
 __device__ __forceinline__ bool accept_match(const Best& b, int th, float ratio) {
@@ -439,16 +439,16 @@ __device__ __forceinline__ void load_pair(const BatchHdr& h, const KfDesc& kd, b
     p.a0 = p.a1 = make_uint4(0, 0, 0, 0);
     if (o < se) {
         const int64_t j = o - kd.pair_off;
-        const int32_t lp = dense ? (int32_t)j : h.pair_mp[o];
+        const int32_t lp = dense ? (int32_t)j : ldg(h.pair_mp + o);
         if (lp < 0 || lp >= kd.n_mp) {
             p.dec = FL_INVALID;
         } else {
             p.gp = kd.mp_off + lp;
-            p.id = h.mp_id ? h.mp_id[p.gp] : p.gp;
-            p.x = h.mp_xyz[3 * (int64_t)p.gp];
-            p.y = h.mp_xyz[3 * (int64_t)p.gp + 1];
-            p.z = h.mp_xyz[3 * (int64_t)p.gp + 2];
-            if (gate) p.dm = h.mp_dmax[p.gp];
+            p.id = h.mp_id ? ldg(h.mp_id + p.gp) : p.gp;
+            p.x = ldg(h.mp_xyz + 3 * (int64_t)p.gp);
+            p.y = ldg(h.mp_xyz + 3 * (int64_t)p.gp + 1);
+            p.z = ldg(h.mp_xyz + 3 * (int64_t)p.gp + 2);
+            if (gate) p.dm = ldg(h.mp_dmax + p.gp);
             load_desc(h.mp_desc, p.gp, p.a0, p.a1);
         }
     }
@@ -462,12 +462,11 @@ struct PairRes {
 };
 
 // The octave scale table sf[n] = scale_factor^n of a launch: its first
-// kOctReg entries, and the window half-widths r0 * sf[n] of the pass, in
-// registers; every entry in LDS.
+// kOctReg entries in registers, every entry in LDS; and the pass's window
+// half-width at octave 0.
 constexpr int kOctReg = 8;
 struct OctaveTable {
     float sf[kOctReg];
-    float rad[kOctReg];
     const float* all;   // LDS, n_octaves entries
     int N;
     float r0;
@@ -493,14 +492,9 @@ __device__ __forceinline__ int predict_octave(const OctaveTable& T, float d, flo
     return pred;
 }
 
-// Window half-width r0 * sf[pred], the same float32 product for every pred.
-__device__ __forceinline__ float window_radius(const OctaveTable& T, int pred) {
-    if (pred >= kOctReg) return T.r0 * T.all[pred];
-    float r = T.rad[0];
-#pragma unroll
-    for (int n = 1; n < kOctReg; ++n) r = pred == n ? T.rad[n] : r;
-    return r;
-}
+// Window half-width r0 * sf[pred] (sf from LDS: a lane-dependent index into
+// registers would be compiled as a table in scratch memory).
+__device__ __forceinline__ float window_radius(const OctaveTable& T, int pred) { return T.r0 * T.all[pred]; }
 
 // Evaluation of one pair (point p, keyframe kd): observed-set test, Sim3
 // projection, window gather over the grid rows of the pair's octave group,
@@ -587,29 +581,32 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
             }
         }
     };
-    // The runs of the first kRowSeg rows, walked as one flat sequence: slot
-    // = base[j] + m for the m-th record when cum[j] <= m < cum[j + 1].  A
-    // lane's trip count is its own number of records, not a sum of per-row
-    // maxima over the wave.
-    int base[kRowSeg], cum[kRowSeg + 1];
-    cum[0] = 0;
-#pragma unroll
-    for (int j = 0; j < kRowSeg; ++j) {
+    // The runs of the first kRowSeg = 4 rows, walked as one flat sequence:
+    // slot = b_j + m for the m-th record when c_j <= m < c_(j+1) (c_0 = 0).
+    // A lane's trip count is its own number of records, not a sum of
+    // per-row maxima over the wave.  (Named values, not arrays: an array
+    // indexed by a lane-dependent value would be placed in scratch memory.)
+    static_assert(kRowSeg == 4, "four row runs");
+    auto run = [&](int j, int c_in, int& b_out, int& c_out) {
         const bool in = j < nrows;
         const int idx = ((in ? w.r0 + j : w.r0) * nb + grp) * C;
         const int s0 = cs_at(idx + w.c0), e0 = cs_at(idx + w.c1 + 1);
-        base[j] = s0 - cum[j];
-        cum[j + 1] = cum[j] + (in ? e0 - s0 : 0);
-    }
+        b_out = s0 - c_in;
+        c_out = c_in + (in ? e0 - s0 : 0);
+    };
+    int b0, b1, b2, b3, c1, c2, c3, total;
+    run(0, 0, b0, c1);
+    run(1, c1, b1, c2);
+    run(2, c2, b2, c3);
+    run(3, c3, b3, total);
+    // (masks, not a chain of selects, which the compiler would turn into a
+    // table in scratch memory)
+    const int d1 = b1 - b0, d2 = b2 - b1, d3 = b3 - b2;
     auto slot_of = [&](int m) {
-        int b = base[0];
-#pragma unroll
-        for (int j = 1; j < kRowSeg; ++j) b = m >= cum[j] ? base[j] : b;
-        return b + m;
+        return m + b0 + (d1 & -(int)(m >= c1)) + (d2 & -(int)(m >= c2)) + (d3 & -(int)(m >= c3));
     };
     // each record is loaded one step ahead of its test, so the LDS latency
     // overlaps the previous record's test (and comparison)
-    const int total = cum[kRowSeg];
     int i_next = slot_of(0);
     KpRec r_next{};
     if (total > 0) r_next = v.rec[i_next];
@@ -629,7 +626,7 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
     if (!accept_match(res.best, hamming_th, nn_ratio)) {
         p.dec = FL_NO_MATCH;
     } else {
-        const int32_t ow = kp_owner[kd.kp_off + (int32_t)(res.best.key & 0xFFFFu)];
+        const int32_t ow = ldg(kp_owner + kd.kp_off + (int32_t)(res.best.key & 0xFFFFu));
         if (ow >= 0) {
             p.dec = FL_FUSE;
             res.target = ow;
@@ -722,8 +719,6 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         po.nn_ratio = uniform_f(po.nn_ratio);
         po.r0 = uniform_f(po.r0);
         T.r0 = po.r0;
-#pragma unroll
-        for (int n = 0; n < kOctReg; ++n) T.rad[n] = po.r0 * T.sf[n];
         const int64_t kend = kd.pair_off + kd.n_pairs;
         const int64_t sb = kd.pair_off + (int64_t)(t - tb) * kd.tile_pairs;
         const int64_t se = min(kd.pair_off + (int64_t)(t_end - tb) * kd.tile_pairs, kend);
@@ -760,12 +755,24 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         constexpr int kChunk = kWave * PPL;
         const int64_t n_chunks = (se - sb + kChunk - 1) / kChunk;
         const unsigned long long below = (1ull << lane) - 1ull;
+        // The points of a wave's next chunk are loaded while its current
+        // chunk is evaluated (their latency overlaps the evaluation).
+        PairIn pn[PPL];
+        if (wid < n_chunks) {
+#pragma unroll
+            for (int r = 0; r < PPL; ++r)
+                load_pair(h, kd, dense, gate, sb + wid * kChunk + r * kWave + lane, se, pn[r]);
+        }
         for (int64_t c = wid; c < n_chunks; c += nw) {
             const int64_t cb = sb + c * kChunk;
-            // the point loads of every pair of this lane are issued first
             PairIn p[PPL];
 #pragma unroll
-            for (int r = 0; r < PPL; ++r) load_pair(h, kd, dense, gate, cb + r * kWave + lane, se, p[r]);
+            for (int r = 0; r < PPL; ++r) p[r] = pn[r];
+            if (c + nw < n_chunks) {
+#pragma unroll
+                for (int r = 0; r < PPL; ++r)
+                    load_pair(h, kd, dense, gate, cb + nw * kChunk + r * kWave + lane, se, pn[r]);
+            }
 #pragma unroll
             for (int r = 0; r < PPL; ++r) {
                 const int64_t o = cb + r * kWave + lane;
@@ -776,15 +783,17 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 const int bidx = key == 0xFFFFFFFFu ? -1 : (int)(key & 0xFFFFu);
                 const int kpg = kd.claim_off + (bidx < 0 ? 0 : bidx);   // claim slot
                 if (active) {
-                    po.best_idx[o] = bidx;
-                    po.best_dist[o] = (int16_t)(key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(key >> 16));
-                    po.second_dist[o] = (int16_t)res.best.second;
-                    po.decision[o] = p[r].dec;
-                    po.target[o] = res.target;
+                    stg(po.best_idx + o, (int32_t)bidx);
+                    stg(po.best_dist + o, (int16_t)(key == 0xFFFFFFFFu ? FL_NO_DIST : (int)(key >> 16)));
+                    stg(po.second_dist + o, (int16_t)res.best.second);
+                    stg(po.decision + o, p[r].dec);
+                    stg(po.target + o, res.target);
                 }
                 const bool is_add = active && p[r].dec == FL_ADD;
                 const bool acc = want_matches && active && (p[r].dec == FL_ADD || p[r].dec == FL_FUSE);
-                if (is_add) atomicMin(&claim[kpg], tag | (uint32_t)p[r].gp);
+                if (is_add)
+                    __hip_atomic_fetch_min((gmem<unsigned long long>*)(claim + kpg),
+                                           tag | (uint32_t)p[r].gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // one LDS reservation per wave and list
                 const unsigned long long ma = __ballot(is_add), mm = __ballot(acc);
                 uint32_t ba = 0, bm = 0;
@@ -800,7 +809,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                     e.kp = kpg;
                     e.gp = p[r].gp;
                     e.pass = kd.pass;
-                    add_list[rg.priv_off + ba + (uint32_t)__popcll(ma & below)] = e;
+                    stg_rec(add_list + rg.priv_off + ba + (uint32_t)__popcll(ma & below), e);
                 }
                 if (acc) {
                     MatchRec me;
@@ -811,7 +820,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                     me.v = res.kv;
                     me.kf = k;
                     me.pad0 = me.pad1 = 0;
-                    match_stage[rg.priv_off + bm + (uint32_t)__popcll(mm & below)] = me;
+                    stg_rec(match_stage + rg.priv_off + bm + (uint32_t)__popcll(mm & below), me);
                 }
             }
         }
