@@ -946,7 +946,7 @@ int fl_create(fl_ctx** out, int device) {
     fl_ctx* c = new fl_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    c->lds_max = std::max<size_t>(prop.sharedMemPerBlock, 65536) - 1024;   // room for static LDS
+    c->lds_max = std::max<size_t>(prop.sharedMemPerBlock, 65536) - kSearchStaticLds;   // room for static LDS
     allow_lds_all<1>(c->lds_max);
     allow_lds_all<2>(c->lds_max);
     allow_lds_all<4>(c->lds_max);

@@ -422,11 +422,11 @@ __host__ __device__ inline size_t search_lds_bytes(int mode, int kp_cap, int cel
     return b;
 }
 
-// One pair's point, loaded before its evaluation.
+// One pair's point, loaded before its evaluation (its descriptor is read
+// only for the pair's candidates, when their distances are computed).
 struct PairIn {
     int32_t gp, id;
     float x, y, z, dm;
-    uint4 a0, a1;
     uint8_t dec;
 };
 
@@ -436,7 +436,6 @@ __device__ __forceinline__ void load_pair(const BatchHdr& h, const KfDesc& kd, b
     p.gp = 0;
     p.id = -1;
     p.x = p.y = p.z = p.dm = 0.0f;
-    p.a0 = p.a1 = make_uint4(0, 0, 0, 0);
     if (o < se) {
         const int64_t j = o - kd.pair_off;
         const int32_t lp = dense ? (int32_t)j : ldg(h.pair_mp + o);
@@ -449,7 +448,6 @@ __device__ __forceinline__ void load_pair(const BatchHdr& h, const KfDesc& kd, b
             p.y = ldg(h.mp_xyz + 3 * (int64_t)p.gp + 1);
             p.z = ldg(h.mp_xyz + 3 * (int64_t)p.gp + 2);
             if (gate) p.dm = ldg(h.mp_dmax + p.gp);
-            load_desc(h.mp_desc, p.gp, p.a0, p.a1);
         }
     }
 }
@@ -496,22 +494,49 @@ __device__ __forceinline__ int predict_octave(const OctaveTable& T, float d, flo
 // registers would be compiled as a table in scratch memory).
 __device__ __forceinline__ float window_radius(const OctaveTable& T, int pred) { return T.r0 * T.all[pred]; }
 
-// Evaluation of one pair (point p, keyframe kd): observed-set test, Sim3
-// projection, window gather over the grid rows of the pair's octave group,
-// Hamming distances, best and second best, and the fuse / add decision
-// (provisional for ADD).  With the octave gate on, the group holds octaves
-// pred - 1 and pred only: a quarter of the window's keypoints when the eight
-// octaves are equally common.  st: visible pairs, cells scanned, keypoints
-// in them (every octave), candidates.
+// Evaluation of one pair (point p, keyframe kd) in three parts.  The front
+// (per lane): observed-set test, Sim3 projection, predicted octave, window,
+// and the runs of record slots to read: the window's grid rows of the pair's
+// octave group (with the octave gate on, the group holds octaves pred - 1
+// and pred only: a quarter of the window's keypoints when the eight octaves
+// are equally common).  The scan (the whole wave together): every lane walks
+// its runs as one flat sequence, testing box and octave; the records that
+// pass go to a per-wave queue, and each time the queue fills (and at the end)
+// the wave computes the queued Hamming distances one per lane, so the
+// distance instructions run with their lanes full instead of with the few
+// lanes that happen to have a candidate at one step.  Best and second best
+// are kept per lane in LDS with atomic minima: the packed (distance, index)
+// key of a candidate goes to the best slot, and whichever key the update
+// leaves out (the old best, or the candidate) offers its distance to the
+// second slot; so the second slot ends at the smallest distance of every
+// candidate but the best, whatever the order.  The back (per lane): the
+// fuse / add decision (provisional for ADD).  st: visible pairs, cells
+// scanned, keypoints in them (every octave), candidates.
 constexpr int kRowSeg = 4;
+static_assert(kRowSeg == 4, "four row runs");
+
+// What the front leaves for the scan of one pair.
+struct PairScan {
+    Window w;
+    int pred, grp;
+    int b0, d1, d2, d3, c1, c2, c3, total;   // slot = m + b0 + (d_j where m >= c_j)
+    int nrows;
+};
+
+// Per wave: the candidate queue, and each lane's best key and second
+// distance.
+struct WaveCand {
+    uint32_t q[kWave];        // owner lane << 17 | slot
+    uint32_t best[kWave];
+    uint32_t second[kWave];
+};
+constexpr size_t kSearchStaticLds = sizeof(WaveCand) * kWavesPerWG + 1024;   // beside the dynamic LDS
 
 template <int MODE, bool STATS>
-__device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, float nn_ratio, const int32_t* kp_owner,
-                                          const KfView& v, const OctaveTable& T, int gate, int C, int R, PairIn& p,
-                                          PairRes& res, unsigned long long* st) {
-    res.best.init();
-    res.target = -1;
-    res.ku = res.kv = 0.0f;
+__device__ __forceinline__ bool search_front(const KfDesc& kd, const KfView& v, const OctaveTable& T, int gate,
+                                             int C, int R, PairIn& p, PairScan& q, unsigned long long* st) {
+    q.total = 0;
+    q.nrows = 0;
     // owner probe: a point already observed in this keyframe is skipped
     if (p.dec == kDecUndecided && p.id >= 0) {
         uint32_t hh = owner_slot(p.id, v.hash_mask);
@@ -525,16 +550,16 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
             hh = (hh + 1) & (uint32_t)v.hash_mask;
         }
     }
-    if (p.dec != kDecUndecided) return;
+    if (p.dec != kDecUndecided) return false;
     Proj pr;
     if (!project_uv(kd, p.x, p.y, p.z, pr)) {
         p.dec = FL_NOT_VISIBLE;
-        return;
+        return false;
     }
-    pr.pred = gate ? predict_octave(T, pr.d, p.dm) : T.N - 1;
+    q.pred = gate ? predict_octave(T, pr.d, p.dm) : T.N - 1;
     if (STATS) ++st[0];
-    const float rad = window_radius(T, pr.pred);
-    Window w;
+    const float rad = window_radius(T, q.pred);
+    Window& w = q.w;
     w.lx = pr.u - rad;
     w.hx = pr.u + rad;
     w.ly = pr.v - rad;
@@ -543,13 +568,10 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
     w.c1 = cell_of(w.hx, kd.invw, C);
     w.r0 = cell_of(w.ly, kd.invh, R);
     w.r1 = cell_of(w.hy, kd.invh, R);
-    // The window's candidates: rows r0..r1 of the pair's octave group (the
-    // group of pred; group 0 when there is one group), each row a run of
-    // slots over columns c0..c1.
     const int nb = MODE == kModeGlobal ? 1 : v.nb;
     auto cs_at = [&](int j) -> int { return MODE == kModeGlobal ? v.cs[j] : (int)v.cs16[j]; };
-    const int grp = min(pr.pred, nb - 1);
-    const int nrows = w.r1 - w.r0 + 1;
+    q.grp = min(q.pred, nb - 1);
+    q.nrows = w.r1 - w.r0 + 1;
     if (STATS) {
         // cells and keypoints of the window's cells (every octave: the
         // counting launch stages one group)
@@ -561,68 +583,137 @@ __device__ __forceinline__ void eval_pair(const KfDesc& kd, int hamming_th, floa
             }
         }
     }
-    int bslot = 0;
-    auto visit = [&](int i, const KpRec& rc) {
-        if (in_window(w, rc.x, rc.y, rc.oct, pr.pred, gate)) {
-            if (STATS) ++st[3];
-            uint4 b0, b1;
-            if (MODE == kModeLdsRec) {
-                load_desc(v.desc_orig, rc.idx, b0, b1);
-            } else {
-                b0 = v.desc[2 * i];
-                b1 = v.desc[2 * i + 1];
-            }
-            const uint32_t before = res.best.key;
-            res.best.offer(hamming(p.a0, p.a1, b0, b1), rc.idx);
-            if (res.best.key != before) {
-                res.ku = rc.x;
-                res.kv = rc.y;
-                bslot = i;
-            }
-        }
-    };
-    // The runs of the first kRowSeg = 4 rows, walked as one flat sequence:
-    // slot = b_j + m for the m-th record when c_j <= m < c_(j+1) (c_0 = 0).
-    // A lane's trip count is its own number of records, not a sum of
-    // per-row maxima over the wave.  (Named values, not arrays: an array
-    // indexed by a lane-dependent value would be placed in scratch memory.)
-    static_assert(kRowSeg == 4, "four row runs");
+    // the runs of the first kRowSeg rows (named values, not arrays: an array
+    // indexed by a lane-dependent value would be placed in scratch memory)
     auto run = [&](int j, int c_in, int& b_out, int& c_out) {
-        const bool in = j < nrows;
-        const int idx = ((in ? w.r0 + j : w.r0) * nb + grp) * C;
+        const bool in = j < q.nrows;
+        const int idx = ((in ? w.r0 + j : w.r0) * nb + q.grp) * C;
         const int s0 = cs_at(idx + w.c0), e0 = cs_at(idx + w.c1 + 1);
         b_out = s0 - c_in;
         c_out = c_in + (in ? e0 - s0 : 0);
     };
-    int b0, b1, b2, b3, c1, c2, c3, total;
-    run(0, 0, b0, c1);
-    run(1, c1, b1, c2);
-    run(2, c2, b2, c3);
-    run(3, c3, b3, total);
-    // (masks, not a chain of selects, which the compiler would turn into a
-    // table in scratch memory)
-    const int d1 = b1 - b0, d2 = b2 - b1, d3 = b3 - b2;
-    auto slot_of = [&](int m) {
-        return m + b0 + (d1 & -(int)(m >= c1)) + (d2 & -(int)(m >= c2)) + (d3 & -(int)(m >= c3));
-    };
+    int b1, b2, b3;
+    run(0, 0, q.b0, q.c1);
+    run(1, q.c1, b1, q.c2);
+    run(2, q.c2, b2, q.c3);
+    run(3, q.c3, b3, q.total);
+    q.d1 = b1 - q.b0;
+    q.d2 = b2 - b1;
+    q.d3 = b3 - b2;
+    return true;
+}
+
+__device__ __forceinline__ int scan_slot(const PairScan& q, int m) {
+    // masks, not a chain of selects, which the compiler would turn into a
+    // table in scratch memory
+    return m + q.b0 + (q.d1 & -(int)(m >= q.c1)) + (q.d2 & -(int)(m >= q.c2)) + (q.d3 & -(int)(m >= q.c3));
+}
+
+// Descriptor of record slot i (keypoint index idx).
+template <int MODE>
+__device__ __forceinline__ void record_desc(const KfView& v, int i, int idx, uint4& b0, uint4& b1) {
+    if (MODE == kModeLdsRec) {
+        load_desc(v.desc_orig, idx, b0, b1);
+    } else if (MODE == kModeLdsDesc) {
+        b0 = v.desc[2 * i];
+        b1 = v.desc[2 * i + 1];
+    } else {
+        b0 = ldg_u4(v.desc + 2 * i);
+        b1 = ldg_u4(v.desc + 2 * i + 1);
+    }
+}
+
+// A candidate of key k for the pair of `owner`: the atomic-minimum update of
+// its best and second slots (see above).
+__device__ __forceinline__ void offer_lds(WaveCand& wc, int owner, uint32_t k) {
+    const uint32_t old = atomicMin(&wc.best[owner], k);
+    const uint32_t out = k < old ? old : k;
+    if (out != 0xFFFFFFFFu) atomicMin(&wc.second[owner], out >> 16);
+}
+
+// The queued candidates, one per lane: the owner's point descriptor (its
+// point index from the owner lane) against the keypoint's.  Every lane of
+// the wave takes part in the cross-lane read.
+template <int MODE>
+__device__ __forceinline__ void drain_queue(WaveCand& wc, int qn, const KfView& v, const uint8_t* mp_desc,
+                                            int32_t gp) {
+    const int lane = wave_lane();
+    const uint32_t e = lane < qn ? wc.q[lane] : 0u;
+    const int owner = (int)(e >> 17);
+    const int32_t ogp = __builtin_amdgcn_ds_bpermute(owner << 2, gp);
+    if (lane < qn) {
+        const int slot = (int)(e & 0x1FFFFu);
+        const int idx = v.rec[slot].idx;
+        uint4 a0, a1, b0, b1;
+        load_desc(mp_desc, ogp, a0, a1);
+        record_desc<MODE>(v, slot, idx, b0, b1);
+        offer_lds(wc, owner, ((uint32_t)hamming(a0, a1, b0, b1) << 16) | (uint32_t)idx);
+    }
+}
+
+// The wave's scan of its lanes' pairs (every lane of the wave calls it; a
+// lane with no pair to search has q.total = 0 and q.nrows = 0).
+template <int MODE, bool STATS>
+__device__ __forceinline__ void search_scan(const KfView& v, int gate, int C, const uint8_t* mp_desc,
+                                            const PairIn& p, const PairScan& q, WaveCand& wc,
+                                            unsigned long long* st) {
+    const int lane = wave_lane();
+    wc.best[lane] = 0xFFFFFFFFu;
+    wc.second[lane] = FL_NO_DIST;
+    int qn = 0;
     // each record is loaded one step ahead of its test, so the LDS latency
-    // overlaps the previous record's test (and comparison)
-    int i_next = slot_of(0);
+    // overlaps the previous record's test
+    int i_next = scan_slot(q, 0);
     KpRec r_next{};
-    if (total > 0) r_next = v.rec[i_next];
-    for (int m = 0; m < total; ++m) {
+    if (q.total > 0) r_next = v.rec[i_next];
+    for (int m = 0;; ++m) {
+        const bool act = m < q.total;
+        if (__ballot(act) == 0ull) break;
         const int i = i_next;
         const KpRec rc = r_next;
-        i_next = slot_of(m + 1);
-        if (m + 1 < total) r_next = v.rec[i_next];
-        visit(i, rc);
+        i_next = scan_slot(q, m + 1);
+        if (m + 1 < q.total) r_next = v.rec[i_next];
+        const bool cand = act && in_window(q.w, rc.x, rc.y, rc.oct, q.pred, gate);
+        const unsigned long long cm = __ballot(cand);
+        if (cm) {
+            const int n = __popcll(cm);
+            if (qn + n > kWave) {
+                drain_queue<MODE>(wc, qn, v, mp_desc, p.gp);
+                qn = 0;
+            }
+            if (cand) {
+                wc.q[qn + __popcll(cm & ((1ull << lane) - 1ull))] = ((uint32_t)lane << 17) | (uint32_t)i;
+                if (STATS) ++st[3];
+            }
+            qn += n;
+        }
     }
-    // rows beyond the first kRowSeg (wide windows)
-    for (int row = w.r0 + kRowSeg; row <= w.r1; ++row) {
-        const int j = (row * nb + grp) * C;
-        const int s0 = cs_at(j + w.c0), e0 = cs_at(j + w.c1 + 1);
-        for (int i = s0; i < e0; ++i) visit(i, v.rec[i]);
+    if (qn) drain_queue<MODE>(wc, qn, v, mp_desc, p.gp);
+    // rows beyond the first kRowSeg (wide windows): each lane its own, the
+    // distances computed on the spot
+    if (q.nrows > kRowSeg) {
+        const int nb = MODE == kModeGlobal ? 1 : v.nb;
+        uint4 a0, a1;
+        load_desc(mp_desc, p.gp, a0, a1);
+        for (int row = q.w.r0 + kRowSeg; row <= q.w.r1; ++row) {
+            const int j = (row * nb + q.grp) * C;
+            const int s0 = MODE == kModeGlobal ? v.cs[j + q.w.c0] : (int)v.cs16[j + q.w.c0];
+            const int e0 = MODE == kModeGlobal ? v.cs[j + q.w.c1 + 1] : (int)v.cs16[j + q.w.c1 + 1];
+            for (int i = s0; i < e0; ++i) {
+                const KpRec rc = v.rec[i];
+                if (!in_window(q.w, rc.x, rc.y, rc.oct, q.pred, gate)) continue;
+                if (STATS) ++st[3];
+                uint4 b0, b1;
+                record_desc<MODE>(v, i, rc.idx, b0, b1);
+                offer_lds(wc, lane, ((uint32_t)hamming(a0, a1, b0, b1) << 16) | (uint32_t)rc.idx);
+            }
+        }
     }
+}
+
+// The decision of a searched pair from its best and second.
+__device__ __forceinline__ void search_back(const KfDesc& kd, int hamming_th, float nn_ratio,
+                                            const int32_t* kp_owner, PairIn& p, PairRes& res) {
     if (!accept_match(res.best, hamming_th, nn_ratio)) {
         p.dec = FL_NO_MATCH;
     } else {
@@ -650,6 +741,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     // running counts of the workgroup's ADD and accepted-pair regions, then
     // the segment's accepted-pair total and its base in the event's list
     __shared__ uint32_t s_list[4];
+    __shared__ WaveCand s_wc[kWavesPerWG];   // each wave's candidate queue, best and second
     const int wid = tid / kWave, nw = (int)(blockDim.x / kWave);
     if (MODE != kModeGlobal) {
         const size_t slots = (size_t)search_slots(h.lds_kp_cap, h.oct_buckets);
@@ -690,6 +782,8 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
     // header fields read per pair, held in scalar registers (the output
     // stores below could otherwise be taken to alias the header)
     const int32_t* const kp_owner = uniform_p(h.kp_owner);
+    const float* const kp_xy = uniform_p(h.kp_xy);
+    const uint8_t* const mp_desc = uniform_p(h.mp_desc);
     unsigned long long* const claim = uniform_p(h.claim);
     AddRef* const add_list = uniform_p(h.add_list);
     MatchRec* const match_stage = uniform_p(h.match_stage);
@@ -778,7 +872,15 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                 const int64_t o = cb + r * kWave + lane;
                 const bool active = o < se;
                 PairRes res;
-                eval_pair<MODE, STATS>(kd, po.hamming_th, po.nn_ratio, kp_owner, v, T, gate, C, R, p[r], res, st);
+                res.target = -1;
+                res.ku = res.kv = 0.0f;
+                PairScan sq;
+                const bool searching = search_front<MODE, STATS>(kd, v, T, gate, C, R, p[r], sq, st);
+                WaveCand& wc = s_wc[wid];
+                search_scan<MODE, STATS>(v, gate, C, mp_desc, p[r], sq, wc, st);
+                res.best.key = wc.best[lane];
+                res.best.second = (int)wc.second[lane];
+                if (searching) search_back(kd, po.hamming_th, po.nn_ratio, kp_owner, p[r], res);
                 const uint32_t key = res.best.key;
                 const int bidx = key == 0xFFFFFFFFu ? -1 : (int)(key & 0xFFFFu);
                 const int kpg = kd.claim_off + (bidx < 0 ? 0 : bidx);   // claim slot
@@ -812,12 +914,14 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
                     stg_rec(add_list + rg.priv_off + ba + (uint32_t)__popcll(ma & below), e);
                 }
                 if (acc) {
+                    // the matched keypoint's observation
+                    const int64_t kg = (int64_t)kd.kp_off + bidx;
                     MatchRec me;
                     me.x = p[r].x;
                     me.y = p[r].y;
                     me.z = p[r].z;
-                    me.u = res.ku;
-                    me.v = res.kv;
+                    me.u = ldg(kp_xy + 2 * kg);
+                    me.v = ldg(kp_xy + 2 * kg + 1);
                     me.kf = k;
                     me.pad0 = me.pad1 = 0;
                     stg_rec(match_stage + rg.priv_off + bm + (uint32_t)__popcll(mm & below), me);
