@@ -786,6 +786,9 @@ def main():
     ap.add_argument("--only-eager", action="store_true",
                     help="profiling runs: the stream's eager pass alone (no graph or two-stream passes, no "
                          "largest-event or plain runs), so each event's kernels are dispatched W + K times")
+    ap.add_argument("--only-ten-uneven", action="store_true",
+                    help="profiling runs: only the ten uneven 60-keyframe events in one launch, --steps graph "
+                         "launches after 3 untimed ones, its result as the JSON line")
     ap.add_argument("--tuning", type=str, default=None,
                     help="pairs_per_lane,lds_mode,wg_per_cu,xcd_aware instead of the autotuner's choice")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
@@ -843,6 +846,17 @@ def main():
                        note="1 GiB device copy (read + write bytes); eight independent v_xor_b32 + v_bcnt_u32_b32 "
                             "chains per lane on every CU; the rooflines use the published peaks, "
                             "frac_of_measured_peak these")
+    if args.only_ten_uneven:
+        c3s = [synth.gen_c3(seed=303 + i, id_base=1000 + 10 ** 6 * i, fresh_base=10 ** 9 + 10 ** 7 * i)
+               for i in range(10)]
+        B = synth.concat_events(c3s)
+        B.event_S_init = np.stack([e.S_init for e in c3s])
+        if args.tuning:
+            bench.ctx.set_tuning(*[int(x) for x in args.tuning.split(",")])
+        r = bench.batch_graph(B, "ten uneven events", args.steps)
+        bench.ctx.close()
+        print(json.dumps(dict(workload="ten uneven 60-keyframe events in one launch", **r)), flush=True)
+        return
     h = bench.stream_headline()
     evs = h.pop("_evs")
 
