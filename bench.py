@@ -572,7 +572,85 @@ class Bench:
             log(f"essential graph, {name}: {ms:.2f} ms for 10 steps ({res['n_nodes']} keyframes, "
                 f"{res['n_edges']} edges), cost {cost[0]:.3e} -> {cost[-1]:.3e}, CG iterations "
                 f"{res[name]['cg_iterations']}")
+        res["by_size"] = self.pose_graph_by_size(steps)
         return res
+
+    def pose_graph_by_size(self, steps, sizes=(100, 250, 500, 1000, 2000)):
+        """One Levenberg-Marquardt step of the essential graph on the device
+        (edge Jacobians, banded assembly, direct solve, candidate cost) across
+        graph sizes, beside the CPU baseline of the linear solve alone: the
+        same damped system, assembled on the host from the oracle's edge
+        Jacobians (untimed), solved by LAPACK's banded Cholesky under a
+        reverse Cuthill-McKee order and by SuperLU on the sparse matrix."""
+        import synth
+        import scipy.linalg
+        import scipy.sparse
+        import scipy.sparse.linalg
+        from scipy.sparse.csgraph import reverse_cuthill_mckee
+        from oracle import pgo as opgo
+        torch, fl, ctx = self.torch, self.fl, self.ctx
+        out = []
+        for n in sizes:
+            d = synth.gen_pose_graph(n=n, seed=606)
+            S0 = torch.from_numpy(d["S0"]).to(self.dev)
+            S = S0.clone()
+            M = torch.from_numpy(d["M"]).to(self.dev)
+
+            def step():
+                S.copy_(S0)
+                ctx.pose_graph_optimize(S, M, d["edges"], None, iters=1, solver=fl._abi.PGO_SOLVER_DIRECT)
+            gc.collect()
+            gc.disable()
+            dev_ms = self.events_time(step, max(3, steps // 3), 2)
+            gc.enable()
+            # the host system at the start poses, node 0 held
+            rows, cols, vals = [], [], []
+            g = np.zeros(7 * (n - 1))
+            for k, (i, j) in enumerate(d["edges"]):
+                e = opgo.edge_error(d["S0"][i], d["S0"][j], d["M"][k])
+                Ji, Jj = opgo.edge_jacobians(d["S0"][i], d["S0"][j], d["M"][k])
+                for a, Ja in ((int(i), Ji), (int(j), Jj)):
+                    if a == 0:
+                        continue
+                    g[7 * (a - 1):7 * a] += Ja.T @ e
+                    for b, Jb in ((int(i), Ji), (int(j), Jj)):
+                        if b == 0:
+                            continue
+                        blk = Ja.T @ Jb
+                        r, c = np.meshgrid(np.arange(7) + 7 * (a - 1), np.arange(7) + 7 * (b - 1), indexing="ij")
+                        rows.append(r.ravel())
+                        cols.append(c.ravel())
+                        vals.append(blk.ravel())
+            N = 7 * (n - 1)
+            H = scipy.sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                        shape=(N, N))
+            H = H + 1e-4 * scipy.sparse.diags(H.diagonal())
+            perm = reverse_cuthill_mckee(H.tocsr(), symmetric_mode=True)
+            Hp = H.tocsr()[perm][:, perm].tocoo()
+            w = int(np.max(np.abs(Hp.row - Hp.col))) + 1
+            band = np.zeros((w, N))   # lower form: band[i - j, j] = H[i, j], i >= j
+            lo = Hp.row >= Hp.col
+            band[Hp.row[lo] - Hp.col[lo], Hp.col[lo]] = Hp.data[lo]
+            rhs = -g[perm]
+            reps = 20 if n <= 1000 else 10
+
+            def t_ms(f):
+                f()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    f()
+                return (time.perf_counter() - t0) / reps * 1e3
+            chol_ms = t_ms(lambda: scipy.linalg.solveh_banded(band, rhs, lower=True))
+            Hc = H.tocsc()
+            lu_ms = t_ms(lambda: scipy.sparse.linalg.spsolve(Hc, -g))
+            out.append(dict(n_keyframes=n, n_edges=int(d["edges"].shape[0]), unknowns=N, band_width=w,
+                            device_lm_step_ms=dev_ms, cpu_banded_cholesky_solve_ms=chol_ms,
+                            cpu_sparse_lu_solve_ms=lu_ms))
+            log(f"essential graph, {n} keyframes: device LM step {dev_ms:.3f} ms; CPU solve alone: banded "
+                f"Cholesky {chol_ms:.3f} ms, sparse LU {lu_ms:.3f} ms (band {w} of {N} unknowns)")
+        return dict(note="device: one whole Levenberg-Marquardt step (Jacobians, assembly, banded solve, candidate "
+                         "cost); CPU: the linear solve alone in the benchmark process (LAPACK and SuperLU "
+                         "with the process's BLAS threads), assembly excluded", sizes=out)
 
     def residual(self):
         import synth
@@ -667,12 +745,16 @@ class Bench:
         def timed(n_ctx, graph, profile=False):
             """W warmup events, then the K timed events between a device
             synchronisation and HIP events on both sides; returns (wall ms,
-            per-event ms)."""
+            per-event ms).  With profile, HIP events also bracket every event
+            and the library brackets every search and refinement kernel: the
+            per-event latencies and kernel times.  Each event marker holds
+            the queue a few microseconds between kernels, so the throughput
+            is taken from a pass without them."""
             for j in range(W):
                 launch(j % n_events, j % n_ctx, graph)
             reset()
-            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)] if profile else None
+            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)] if profile else None
             t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             if profile:
                 ctx.set_profiling(True)
@@ -682,14 +764,16 @@ class Bench:
                 streams[k].wait_event(t0)
             for j, i in enumerate(seq):
                 k = j % n_ctx
-                e0[j].record(streams[k])
+                if profile:
+                    e0[j].record(streams[k])
                 launch(i, k, graph)
-                e1[j].record(streams[k])
+                if profile:
+                    e1[j].record(streams[k])
             for k in range(1, n_ctx):
                 streams[0].wait_stream(streams[k])
             t1.record(streams[0])
             torch.cuda.synchronize()
-            return t0.elapsed_time(t1), [e0[j].elapsed_time(e1[j]) for j in range(K)]
+            return t0.elapsed_time(t1), ([e0[j].elapsed_time(e1[j]) for j in range(K)] if profile else None)
 
         gc.collect()
         gc.disable()
@@ -700,8 +784,13 @@ class Bench:
                     launch(i, k, graph=True)
                     launch(i, k, graph=False)
             torch.cuda.synchronize()
-        log(f"stream: timing {K} events after {W} warmup events (eager, one stream, kernel events)")
-        wall, per = timed(1, False, profile=True)
+        log(f"stream: timing {K} events after {W} warmup events (eager, one stream)")
+        if not only:
+            wall, _ = timed(1, False)
+        log(f"stream: the same events with HIP events around every event and kernel")
+        wall_p, per = timed(1, False, profile=True)
+        if only:
+            wall = wall_p
         ks_ms, ks_n = ctx.get_profile("search")
         kr_ms, kr_n = ctx.get_profile("refine")
         ctx.set_profiling(False)
@@ -709,8 +798,8 @@ class Bench:
         errs = np.array([sim3_error(S[i].cpu().numpy()[0], evs[i].S_true) for i in range(n_events)])
         init = np.array([sim3_error(ev.S_init, ev.S_true) for ev in evs])
         failed = int((nm < 0).sum().item())
-        wall_g, per_g = timed(1, True) if not only else (float("nan"), [float("nan")])
-        wall_2, per_2 = timed(2, True) if not only else (float("nan"), [float("nan")])
+        wall_g = timed(1, True)[0] if not only else float("nan")
+        wall_2 = timed(2, True)[0] if not only else float("nan")
         gc.enable()
         pairs = int(sum(bs[i].n_pairs for i in seq))
         sb, so = int(sum(nbytes[i] for i in seq)), int(sum(nops[i] for i in seq))
@@ -727,11 +816,10 @@ class Bench:
         res = dict(n_events=n_events, steps=K, warmup=W, pairs=pairs, wall_ms=wall, ms_per_event=wall / K,
                    pairs_per_s=pairs / (wall * 1e-3), events_per_s=K / (wall * 1e-3),
                    p50_ms=float(np.percentile(per, 50)), p99_ms=float(np.percentile(per, 99)),
+                   ms_per_event_instrumented=wall_p / K,
                    search_kernel_ms_total=ks_ms, refine_kernel_ms_total=kr_ms, matched_pairs=n_acc,
                    tuning=tuning, roofline=roof, roofline_other_kernel=other,
-                   graph_one_stream=dict(ms_per_event=wall_g / K, pairs_per_s=pairs / (wall_g * 1e-3),
-                                         p50_ms=float(np.percentile(per_g, 50)),
-                                         p99_ms=float(np.percentile(per_g, 99))),
+                   graph_one_stream=dict(ms_per_event=wall_g / K, pairs_per_s=pairs / (wall_g * 1e-3)),
                    two_contexts_two_streams=dict(ms_per_event=wall_2 / K, pairs_per_s=pairs / (wall_2 * 1e-3),
                                                  events_per_s=K / (wall_2 * 1e-3),
                                                  launch="graph replays, consecutive events alternating between "
@@ -743,7 +831,8 @@ class Bench:
                    init_trans_err_m_median=float(np.median(init[:, 1])),
                    init_scale_err_median=float(np.median(init[:, 2])), failed_events=failed)
         log(f"stream: {wall / K * 1e3:.1f} us per event eager ({pairs / (wall * 1e-3) / 1e9:.2f} G pairs/s), "
-            f"{wall_g / K * 1e3:.1f} graph, {wall_2 / K * 1e3:.1f} on two contexts; p50 {res['p50_ms']:.3f} ms, "
+            f"{wall_g / K * 1e3:.1f} graph, {wall_2 / K * 1e3:.1f} on two contexts, {wall_p / K * 1e3:.1f} with "
+            f"every event and kernel bracketed by HIP events; p50 {res['p50_ms']:.3f} ms, "
             f"p99 {res['p99_ms']:.3f} ms; kernels: search {ks_ms / max(ks_n, 1) * 1e3:.1f} us, "
             f"refine {kr_ms / max(kr_n, 1) * 1e3:.1f} us per event")
         # the stream's largest event on its own: kernel times and search roofline
@@ -784,8 +873,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--only-eager", action="store_true",
-                    help="profiling runs: the stream's eager pass alone (no graph or two-stream passes, no "
-                         "largest-event or plain runs), so each event's kernels are dispatched W + K times")
+                    help="profiling runs: the stream's instrumented eager pass alone (no uninstrumented, graph "
+                         "or two-stream passes, no largest-event or plain runs), so each event's kernels are "
+                         "dispatched W + K times; value is then that pass's")
     ap.add_argument("--only-ten-uneven", action="store_true",
                     help="profiling runs: only the ten uneven 60-keyframe events in one launch, --steps graph "
                          "launches after 3 untimed ones, its result as the JSON line")
@@ -888,6 +978,7 @@ def main():
                     n_kf_range=[min(n_kf), max(n_kf)], n_mp_range=[min(n_mp), max(n_mp)], gn_iters=GN_ITERS,
                     tuning=h["tuning"]),
         ms_per_event_p50=h["p50_ms"], ms_per_event_p99=h["p99_ms"], events_per_s=h["events_per_s"],
+        ms_per_event_instrumented=h["ms_per_event_instrumented"],
         stream_graph_one_stream=h["graph_one_stream"],
         stream_two_contexts_two_streams=h["two_contexts_two_streams"],
         plain=h.get("plain"), batched_vs_plain_same_events=h.get("batched_vs_plain_same_events"),

@@ -157,6 +157,26 @@ typedef struct {
  * together stay within the compute units, which two single-event launches
  * always do.  A wait that does not end within its bound reports the event as
  * failed (event_n_matched = -1); it never blocks the device. */
+/* The other direction of a loop's matches, for two-sided refinement (the
+ * loop's Sim3 is refined on the matches seen from both keyframes of the
+ * loop, Sec. IV-C): points of the current side observed in loop-side
+ * keyframes through S^-1, p = S^-1 X, q = R_m p + t_m, r = pi(q) - uv, with
+ * the Jacobian taken with respect to the same left perturbation of S as the
+ * accepted pairs'.  Pair i of event e is in [event_offset[e],
+ * event_offset[e+1]).  A pair whose kf_idx is outside [0, n_kf) or whose q_z
+ * is not positive adds nothing.  Gauss-Newton only (n_rounds <= 1,
+ * lm_lambda = 0). */
+typedef struct {
+    const int64_t* event_offset;  /* host [n_events+1], event_offset[0] = 0, non-decreasing, total < 2^31 */
+    const float* xyz;             /* device [n][3] point, in the frame S maps into (16-byte aligned base) */
+    const float* uv;              /* device [n][2] observation, pixels */
+    const int32_t* kf_idx;        /* device [n] observing keyframe (index into kf_T and kf_cam) */
+    const float* kf_T;            /* device [n_kf][12] world->camera SE3 of each observing keyframe (R row-major, t) */
+    const float* kf_cam;          /* device [n_kf][4] fx, fy, cx, cy of each observing keyframe */
+    int32_t n_kf;                 /* observing keyframes (> 0 when any pair is given) */
+    int32_t flags;                /* must be 0 */
+} fl_refine_inverse;
+
 typedef struct {
     int32_t n_iters;        /* evaluations per round; 0 = no refinement */
     float huber_delta;      /* pixels */
@@ -176,6 +196,10 @@ typedef struct {
     float outlier_px;       /* > 0 when n_rounds > 1 (may be +inf) */
     float lm_lambda;        /* 0: Gauss-Newton */
     int32_t flags;          /* must be 0 */
+    /* Two-sided refinement: every evaluation also sums the terms of these
+     * pairs at S^-1 (NULL: the accepted pairs only).  event_n_matched then
+     * counts the pairs of both directions. */
+    const fl_refine_inverse* inverse;   /* host, may be NULL */
 } fl_refine;
 
 /* ------------------------------------------------------------------ */

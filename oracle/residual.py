@@ -260,13 +260,15 @@ def grad_hess_inv(S, xyz, uv, kf_idx, kf_T, cam, delta):
     return np.einsum("n,nai,na->i", w, J, r), np.einsum("n,nai,naj->ij", w, J, J), L
 
 
-def gauss_newton_bidir(S0, fwd, bwd, cam, delta, iters=10):
+def gauss_newton_bidir(S0, fwd, bwd, cam, delta, iters=10, cam_bwd=None):
     """Undamped IRLS Gauss-Newton on both directions: g and H are the sums of
     the two sets' (fwd = (xyz, uv, kf_idx, kf_T) observed through S, bwd the
-    same observed through S^-1)."""
+    same observed through S^-1; cam_bwd: the bwd set's camera, default
+    cam)."""
     S = np.asarray(S0, np.float64).copy()
+    cb = cam if cam_bwd is None else cam_bwd
     for _ in range(iters):
         g1, H1, _ = grad_hess(S, *fwd, cam, delta)
-        g2, H2, _ = grad_hess_inv(S, *bwd, cam, delta)
+        g2, H2, _ = grad_hess_inv(S, *bwd, cb, delta)
         S = sim3.compose(sim3.exp(np.linalg.solve(H1 + H2, -(g1 + g2))), S)
     return S

@@ -8,14 +8,14 @@ from ._abi import (ADD, FUSE, INVALID, MAX_KP, NO_DIST, NO_MATCH, NOT_VISIBLE, S
                    LIB_PATH, SIGNATURES, load, last_error)
 
 __all__ = ["load", "last_error", "LIB_PATH", "SIGNATURES", "Context", "DeviceBatch", "FuseOutputs",
-           "Sim3Residual", "FlError", "search_fuse_noalloc"]
+           "Sim3Residual", "FlError", "search_fuse_noalloc", "InversePairs"]
 
 
 def __getattr__(name):
     # the torch-facing binding is imported lazily so that the ABI can be
     # inspected without importing torch
     if name in ("Context", "DeviceBatch", "FuseOutputs", "Sim3Residual", "FlError", "params_struct",
-                "search_fuse_noalloc"):
+                "search_fuse_noalloc", "InversePairs"):
         from . import binding
         return getattr(binding, name)
     raise AttributeError(name)

@@ -77,10 +77,16 @@ PGO_MAX_BAND_NODES = 12   # FL_PGO_MAX_BAND_NODES
 PGO_SOLVER_AUTO, PGO_SOLVER_CG, PGO_SOLVER_DIRECT = 0, 1, 2
 
 
+class RefineInverse(ctypes.Structure):
+    _fields_ = [("event_offset", c_void_p), ("xyz", c_void_p), ("uv", c_void_p), ("kf_idx", c_void_p),
+                ("kf_T", c_void_p), ("kf_cam", c_void_p), ("n_kf", c_int32), ("flags", c_int32)]
+
+
 class Refine(ctypes.Structure):
     _fields_ = [("n_iters", c_int32), ("huber_delta", c_float), ("event_S", c_void_p),
                 ("event_S32", c_void_p), ("event_n_matched", c_void_p), ("n_rounds", c_int32),
-                ("outlier_px", c_float), ("lm_lambda", c_float), ("flags", c_int32)]
+                ("outlier_px", c_float), ("lm_lambda", c_float), ("flags", c_int32),
+                ("inverse", ctypes.POINTER(RefineInverse))]
 
 
 class Tuning(ctypes.Structure):

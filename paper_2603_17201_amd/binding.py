@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import Batch, FuseOut, Keyframe, Params, Pass, PgoParams, Pinhole, PoseGraph, Refine, Sim3, Tuning
+from ._abi import (Batch, FuseOut, Keyframe, Params, Pass, PgoParams, Pinhole, PoseGraph, Refine, RefineInverse,
+                   Sim3, Tuning)
 
 
 class FlError(ValueError):
@@ -200,6 +201,30 @@ class DeviceBatch:
         return b
 
 
+class InversePairs:
+    """The other direction of a loop's matches for two-sided refinement:
+    points of the current side (xyz, float32 [n,3]) observed in loop-side
+    keyframes (uv float32 [n,2], kf_idx int32 [n] into kf_T float32
+    [n_kf,12] and kf_cam float32 [n_kf,4] = fx, fy, cx, cy), all device
+    tensors, with event_offset (host, int64 [n_events+1]) giving each event's
+    pairs."""
+
+    def __init__(self, event_offset, xyz, uv, kf_idx, kf_T, kf_cam):
+        self.event_offset = np.ascontiguousarray(event_offset, dtype=np.int64)
+        self.xyz, self.uv, self.kf_idx, self.kf_T, self.kf_cam = xyz, uv, kf_idx, kf_T, kf_cam
+
+    def struct(self, device) -> RefineInverse:
+        n_kf = int(self.kf_T.shape[0]) if self.kf_T is not None else 0
+        inv = RefineInverse(self.event_offset.ctypes.data_as(ctypes.c_void_p),
+                            _ptr(self.xyz, torch.float32, "inverse.xyz", 16, device),
+                            _ptr(self.uv, torch.float32, "inverse.uv", 8, device),
+                            _ptr(self.kf_idx, torch.int32, "inverse.kf_idx", device=device),
+                            _ptr(self.kf_T, torch.float32, "inverse.kf_T", device=device),
+                            _ptr(self.kf_cam, torch.float32, "inverse.kf_cam", 16, device), n_kf, 0)
+        inv._keep = self.event_offset
+        return inv
+
+
 class Context:
     """An fl_ctx: workspace, pinned staging and captured graphs of one device."""
 
@@ -299,17 +324,24 @@ class Context:
         return outs
 
     def _refine_struct(self, batch, refine):
-        """refine: (n_iters, huber_delta, event_S, event_S32, n_matched) and
-        optionally (n_rounds, outlier_px, lm_lambda) for robust refinement."""
+        """refine: (n_iters, huber_delta, event_S, event_S32, n_matched),
+        optionally (n_rounds, outlier_px, lm_lambda) for robust refinement,
+        and optionally an InversePairs (two-sided refinement) as the ninth
+        element."""
         if refine is None:
             return None, None
         n_iters, delta, event_S, event_S32, n_matched = refine[:5]
         n_rounds, outlier_px, lm_lambda = (tuple(refine[5:8]) + (0, 0.0, 0.0)[len(refine[5:8]):])
+        inverse = refine[8] if len(refine) > 8 else None
         r = Refine(int(n_iters), float(delta),
                    _ptr(event_S, torch.float64, "event_S", 8, self.device),
                    _ptr(event_S32, torch.float32, "event_S32", 16, self.device),
                    _ptr(n_matched, torch.int32, "event_n_matched", device=self.device),
                    int(n_rounds), float(outlier_px), float(lm_lambda), 0)
+        if inverse is not None:
+            inv = inverse.struct(self.device)
+            r.inverse = ctypes.pointer(inv)
+            r._keep = inv
         return r, ctypes.byref(r)
 
     def search_fuse_graph(self, batch: DeviceBatch, params, out: Optional[FuseOutputs] = None, refine=None,

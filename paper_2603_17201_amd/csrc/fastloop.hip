@@ -480,6 +480,9 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         if (c->add_cap_override > 0) cap = std::min<int64_t>(cap, c->add_cap_override);
         ed.list_off = refine ? (int32_t)list_total : 0;
         ed.list_cap = refine ? (int32_t)cap : 0;
+        const fl_refine_inverse* V = refine ? R->inverse : nullptr;
+        ed.inv_off = V ? (int32_t)V->event_offset[e] : 0;
+        ed.inv_n = V ? (int32_t)(V->event_offset[e + 1] - V->event_offset[e]) : 0;
         if (refine) list_total += cap;
         for (int k = kb; k < ke; ++k) {
             // the keyframe's global grid and owner hash set serve every pass
@@ -733,6 +736,14 @@ int prepare_batch(fl_ctx* c, const fl_batch* B, const fl_params* P, const fl_fus
         h.event_S = R->event_S;
         h.event_S32_out = R->event_S32;
         h.event_n_matched = R->event_n_matched;
+        if (const fl_refine_inverse* V = R->inverse) {
+            h.inv_xyz = V->xyz;
+            h.inv_uv = V->uv;
+            h.inv_kf = V->kf_idx;
+            h.inv_T = V->kf_T;
+            h.inv_cam = V->kf_cam;
+            h.inv_n_kf = V->n_kf;
+        }
     }
     return FL_OK;
 }
@@ -893,6 +904,27 @@ int check_refine(const fl_batch* B, const fl_refine* R) {
     if (!(R->lm_lambda >= 0.0f) || !std::isfinite(R->lm_lambda))
         return fail(FL_EINVAL, "refine.lm_lambda must be finite and >= 0");
     if (B->n_events > 0 && !R->event_S) return fail(FL_EINVAL, "refine.event_S must not be NULL");
+    if (const fl_refine_inverse* V = R->inverse) {
+        if (R->n_rounds > 1 || R->lm_lambda > 0.0f)
+            return fail(FL_ENOTSUP, "refine.inverse: two-sided refinement is Gauss-Newton only "
+                                    "(n_rounds <= 1, lm_lambda = 0)");
+        if (V->flags != 0) return fail(FL_EINVAL, "refine.inverse.flags must be 0");
+        if (!V->event_offset) return fail(FL_EINVAL, "refine.inverse.event_offset must not be NULL");
+        if (V->event_offset[0] != 0) return fail(FL_EINVAL, "refine.inverse.event_offset[0] must be 0");
+        for (int e = 0; e < B->n_events; ++e)
+            if (V->event_offset[e + 1] < V->event_offset[e])
+                return fail(FL_EINVAL, "refine.inverse.event_offset must be non-decreasing (event %d)", e);
+        const int64_t n = V->event_offset[B->n_events];
+        if (n > INT32_MAX) return fail(FL_ERANGE, "refine.inverse: %lld pairs, at most 2^31-1", (long long)n);
+        if (n > 0) {
+            if (!V->xyz || !V->uv || !V->kf_idx || !V->kf_T || !V->kf_cam)
+                return fail(FL_EINVAL, "refine.inverse: xyz, uv, kf_idx, kf_T and kf_cam must not be NULL");
+            if (V->n_kf <= 0) return fail(FL_EINVAL, "refine.inverse.n_kf must be > 0");
+            if ((uintptr_t)V->xyz % 16 || (uintptr_t)V->uv % 8 || (uintptr_t)V->kf_idx % 4 ||
+                (uintptr_t)V->kf_T % 4 || (uintptr_t)V->kf_cam % 16)
+                return fail(FL_EINVAL, "refine.inverse: misaligned array (xyz 16, uv 8, kf_cam 16, others 4 bytes)");
+        }
+    }
     return FL_OK;
 }
 

@@ -63,6 +63,8 @@ struct alignas(16) EventDesc {
     int32_t mp_off, n_mp;
     int32_t list_off, list_cap;    // region of the matched-pair list
     int64_t pair_begin, pair_end;  // pair range (pairs of the event are contiguous)
+    int32_t inv_off, inv_n;        // the event's pairs of the other direction (two-sided refinement)
+    int32_t pad0, pad1;
 };
 
 // Offsets in the table blob (which starts at the batch header) of the
@@ -176,6 +178,15 @@ struct alignas(16) BatchHdr {
     fl_sim3* event_S32_out;     // caller's (may be null)
     int32_t* event_n_matched;   // caller's (may be null)
     unsigned long long* refine_rows;   // [2][n_events * refine_blocks][2 * kNAccPad] tagged partial-sum words
+    // two-sided refinement (caller's; null without it): points of the other
+    // side observed through S^-1 in keyframes of their own
+    const float* inv_xyz;       // [n][3]
+    const float* inv_uv;        // [n][2]
+    const int32_t* inv_kf;      // [n] into inv_T / inv_cam
+    const float* inv_T;         // [inv_n_kf][12]
+    const float* inv_cam;       // [inv_n_kf][4] fx, fy, cx, cy
+    int32_t inv_n_kf;
+    int32_t pad_inv[3];
 };
 
 __host__ __device__ constexpr size_t blob_range_offset() { return blob_align(sizeof(BatchHdr)); }

@@ -470,10 +470,13 @@ __device__ __forceinline__ void accumulate_f32(const PairTerm& t, float* acc) {
 // s_out[0..NV) after the call.
 constexpr int kSeg = 8;
 
+static_assert(kSeg == 4 || kSeg == 8, "segments are added as a pairwise tree of 4 or 8");
+
 template <int NV>
 __device__ __forceinline__ double add_segments(const double* s_q, int c) {
-    return ((s_q[c] + s_q[NV + c]) + (s_q[2 * NV + c] + s_q[3 * NV + c])) +
-           ((s_q[4 * NV + c] + s_q[5 * NV + c]) + (s_q[6 * NV + c] + s_q[7 * NV + c]));
+    const double a = (s_q[c] + s_q[NV + c]) + (s_q[2 * NV + c] + s_q[3 * NV + c]);
+    if constexpr (kSeg == 4) return a;
+    else return a + ((s_q[4 * NV + c] + s_q[5 * NV + c]) + (s_q[6 * NV + c] + s_q[7 * NV + c]));
 }
 
 template <int CTRL>
@@ -774,6 +777,38 @@ __device__ __forceinline__ void refine_accumulate_f32(const float* T, float fx, 
     }
 }
 
+// A pair of the other direction (a point of the current side observed in a
+// loop-side keyframe through S^-1, Si = float32 form of S^-1): its terms with
+// respect to the left perturbation of S, added when the point is in front of
+// that keyframe.  The keyframe's pose and intrinsics come from LDS (16 floats
+// per keyframe: T, fx, fy, cx, cy) or from the caller's arrays.
+__device__ __forceinline__ void refine_inverse_f32(const BatchHdr& h, const float* s_ikf, bool lds, int k, float x,
+                                                   float y, float z, float uo, float vo, const fl_sim3& Si,
+                                                   float delta, float* acc) {
+    const float* T;
+    float fx, fy, cx, cy;
+    if (lds) {
+        T = s_ikf + 16 * k;
+        fx = T[12];
+        fy = T[13];
+        cx = T[14];
+        cy = T[15];
+    } else {
+        T = h.inv_T + 12 * (int64_t)k;
+        const float* c = h.inv_cam + 4 * (int64_t)k;
+        fx = c[0];
+        fy = c[1];
+        cx = c[2];
+        cy = c[3];
+    }
+    PairTerm t;
+    pair_term<true>(Si.sR, Si.t, T, fx, fy, cx, cy, x, y, z, uo, vo, delta, true, t);
+    if (t.valid) {
+        accumulate_f32(t, acc);
+        acc[35] += 1.0f;
+    }
+}
+
 // A pair's reprojection error at a float64 Sim3 (13 doubles: R, t, s), in
 // float64 throughout; false when the pair is behind its keyframe.  The
 // quantities that decide something (a Levenberg-Marquardt step's Huber loss,
@@ -817,6 +852,62 @@ __device__ __forceinline__ double block_sum_f64(double v, double* s_w) {
     return sum;
 }
 
+// S <- exp(d) S by the lanes of one wave: every lane holds the same step d
+// and evaluates the exponential's coefficients; lane l < 13 then computes
+// entry l of the product (R row-major, t, s) from the rows of exp(d)
+// (R_d = I + a W + b W^2 and V = c0 I + c1 W + c2 W^2 with W = [omega]x and
+// W^2 = omega omega^T - |omega|^2 I) and from S in LDS, writes it to S64 and
+// its float32 pose to o32; with inv32 the lanes then write the float32 pose
+// of the product's inverse (R^T / s, -R^T t / s).  S64 is read by every lane
+// before any lane writes it (one wave: its LDS accesses are in order).
+__device__ __forceinline__ void compose_exp_lanes(const double* d, double* S64, fl_sim3* o32, fl_sim3* inv32) {
+    const int l = wave_lane();
+    const ExpCoef k = sim3_exp_coef(d[0], d[1], d[2], d[6]);
+    const double w0 = d[0], w1 = d[1], w2 = d[2];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    // this lane's row i of R_d and V: lanes 0-8 entry (i, j) = (l / 3, l % 3)
+    // of the rotation, lanes 9-11 row l - 9 of the translation
+    const int i = l < 9 ? l / 3 : (l < 12 ? l - 9 : 0);
+    const int j = l < 9 ? l % 3 : 0;
+    const double wi = i == 0 ? w0 : (i == 1 ? w1 : w2);
+    // row i of W: (0, -w2, w1), (w2, 0, -w0), (-w1, w0, 0)
+    const double W0 = i == 0 ? 0.0 : (i == 1 ? w2 : -w1);
+    const double W1 = i == 0 ? -w2 : (i == 1 ? 0.0 : w0);
+    const double W2 = i == 0 ? w1 : (i == 1 ? -w0 : 0.0);
+    const double Q0 = wi * w0 - (i == 0 ? th2 : 0.0);   // row i of W^2
+    const double Q1 = wi * w1 - (i == 1 ? th2 : 0.0);
+    const double Q2 = wi * w2 - (i == 2 ? th2 : 0.0);
+    const double R0 = (i == 0 ? 1.0 : 0.0) + k.a * W0 + k.b * Q0;
+    const double R1 = (i == 1 ? 1.0 : 0.0) + k.a * W1 + k.b * Q1;
+    const double R2 = (i == 2 ? 1.0 : 0.0) + k.a * W2 + k.b * Q2;
+    const double s_new = k.es * S64[12];
+    double v;
+    if (l < 9) {
+        v = R0 * S64[j] + R1 * S64[3 + j] + R2 * S64[6 + j];
+    } else if (l < 12) {
+        const double V0 = (i == 0 ? k.c0 : 0.0) + k.c1 * W0 + k.c2 * Q0;
+        const double V1 = (i == 1 ? k.c0 : 0.0) + k.c1 * W1 + k.c2 * Q1;
+        const double V2 = (i == 2 ? k.c0 : 0.0) + k.c1 * W2 + k.c2 * Q2;
+        v = k.es * (R0 * S64[9] + R1 * S64[10] + R2 * S64[11]) + (V0 * d[3] + V1 * d[4] + V2 * d[5]);
+    } else {
+        v = s_new;
+    }
+    if (l < 13) S64[l] = v;
+    if (l < 9) o32->sR[l] = (float)(s_new * v);
+    else if (l < 12) o32->t[l - 9] = (float)v;
+    // the new entries are written before any lane reads them
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (inv32) {
+        const double inv_s = 1.0 / s_new;
+        if (l < 9) {
+            inv32->sR[l] = (float)(inv_s * S64[3 * j + i]);
+        } else if (l < 12) {
+            inv32->t[i] = (float)(-(S64[i] * S64[9] + S64[3 + i] * S64[10] + S64[6 + i] * S64[11]) * inv_s);
+        }
+    }
+}
+
 constexpr int kRefCache = 2;     // accepted pairs a thread keeps in registers across the steps
 constexpr int kRefKfLds = 64;    // keyframes of one event whose pose and intrinsics sit in LDS
 constexpr int kRefMaxB = 64;     // workgroups per event
@@ -850,8 +941,10 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
     __shared__ double s_q[kSeg * NV];
     __shared__ double s_out[NV];
     __shared__ float s_kf[kRefKfLds * 16];   // per keyframe: T (12), fx, fy, cx, cy
+    __shared__ float s_ikf[(LM || ROUNDS) ? 16 : kRefKfLds * 16];   // the same for the other direction's keyframes
     __shared__ double s_S64[13];
     __shared__ fl_sim3 s_S;
+    __shared__ fl_sim3 s_Sinv;               // float32 form of S^-1 (two-sided refinement)
     __shared__ double s_Srs64[13];           // the round's starting Sim3 (inlier tests)
     __shared__ double s_wsum[kRefBlock / kWave];
     __shared__ double s_acc[kNAcc];          // LM: g, H and count at S_acc
@@ -882,14 +975,30 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                 s_kf[i] = f < 12 ? kd.T[f] : f == 12 ? kd.fx : f == 13 ? kd.fy : f == 14 ? kd.cx : kd.cy;
             }
         }
+        // two-sided refinement (Gauss-Newton only): the event's pairs of the
+        // other direction and their keyframes
+        const int n_inv = (LM || ROUNDS) ? 0 : ed.inv_n;
+        const bool ikf_lds = h.inv_n_kf <= kRefKfLds;
+        if (n_inv > 0 && ikf_lds) {
+            for (int i = tid; i < h.inv_n_kf * 16; i += blockDim.x) {
+                const int k = i >> 4, f = i & 15;
+                s_ikf[i] = f < 12 ? h.inv_T[12 * k + f] : h.inv_cam[4 * k + f - 12];
+            }
+        }
         __syncthreads();
-        if (tid == 0) sim3_to_f32(sim3_load(s_S64), &s_S);
+        if (tid == 0) {
+            const Sim3d S0 = sim3_load(s_S64);
+            sim3_to_f32(S0, &s_S);
+            if (n_inv > 0) sim3_to_f32_pose(sim3_inv(S0), &s_Sinv);
+        }
         const uint32_t cnt = h.ev_ctr[ev * kEvCtrs + kEvMatch];
         const bool use_list = !h.refine_scan && cnt <= (uint32_t)ed.list_cap;
         // With the list, the event uses only as many workgroups as give each
-        // thread one pair (every workgroup reads the same count, so all agree
-        // on Be); the others have nothing to add and skip the event.
-        const int Be = use_list ? max(1, min(B, (int)((cnt + blockDim.x - 1) / blockDim.x))) : B;
+        // thread one pair of each direction (every workgroup reads the same
+        // counts, so all agree on Be); the others have nothing to add and
+        // skip the event.
+        const uint32_t per_dir = max(cnt, (uint32_t)n_inv);
+        const int Be = use_list ? max(1, min(B, (int)((per_dir + blockDim.x - 1) / blockDim.x))) : B;
         if (b >= Be) {
             __syncthreads();
             continue;
@@ -914,6 +1023,19 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                 cv_[r] = m.v;
                 ck_[r] = m.kf;
             }
+        }
+        // and its first pair of the other direction
+        float ix_ = 0.0f, iy_ = 0.0f, iz_ = 0.0f, iu_ = 0.0f, iv_ = 0.0f;
+        int ik_ = -1;
+        if (b * (int)blockDim.x + tid < n_inv) {
+            const int64_t g = ed.inv_off + (int64_t)b * blockDim.x + tid;
+            ix_ = h.inv_xyz[3 * g];
+            iy_ = h.inv_xyz[3 * g + 1];
+            iz_ = h.inv_xyz[3 * g + 2];
+            iu_ = h.inv_uv[2 * g];
+            iv_ = h.inv_uv[2 * g + 1];
+            const int k = h.inv_kf[g];
+            ik_ = (k >= 0 && k < h.inv_n_kf) ? k : -1;
         }
         __syncthreads();
         // it: evaluation index (round it / iters); seq: exchanges done, which
@@ -1002,6 +1124,18 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                     }
                 }
             }
+            if (n_inv > 0) {
+                const fl_sim3 Si = s_Sinv;
+                if (ik_ >= 0)
+                    refine_inverse_f32(h, s_ikf, ikf_lds, ik_, ix_, iy_, iz_, iu_, iv_, Si, delta, accf);
+                for (int i = b * blockDim.x + tid + stride; i < n_inv; i += stride) {
+                    const int64_t g = ed.inv_off + (int64_t)i;
+                    const int k = h.inv_kf[g];
+                    if (k < 0 || k >= h.inv_n_kf) continue;
+                    refine_inverse_f32(h, s_ikf, ikf_lds, k, h.inv_xyz[3 * g], h.inv_xyz[3 * g + 1],
+                                       h.inv_xyz[3 * g + 2], h.inv_uv[2 * g], h.inv_uv[2 * g + 1], Si, delta, accf);
+                }
+            }
             // the per-thread float32 sums go through LDS as they are and are
             // widened as the segments are added
             block_reduce_quad<NV, kRefBlock>(accf, s_big, s_q, s_out);
@@ -1076,16 +1210,15 @@ __global__ __launch_bounds__(kRefBlock) void refine_kernel(const BatchHdr* __res
                 if (tid < NV) s_out[tid] = add_segments<NV>(s_q, tid);
                 __syncthreads();
             }
+            if (!LM && tid < kWave) {
+                // Gauss-Newton: every lane of wave 0 solves for the same step,
+                // then the lanes compose it with S together
+                double d[7];
+                if (solve7(s_out, s_out + 7, 0.0, d)) compose_exp_lanes(d, s_S64, &s_S, n_inv > 0 ? &s_Sinv : nullptr);
+            }
             if (tid == 0) {
                 bool round_end = j == iters - 1;
-                if (!LM) {
-                    double d[7];
-                    if (solve7(s_out, s_out + 7, 0.0, d)) {
-                        const Sim3d Sd = sim3_mul(sim3_exp(d), sim3_load(s_S64));
-                        sim3_store(Sd, s_S64);
-                        sim3_to_f32_pose(Sd, &s_S);
-                    }
-                } else {
+                if (LM) {
                     // the evaluation just summed was at s_S64: the round's start
                     // (j = 0) or the last candidate
                     bool take = j == 0;

@@ -7,7 +7,8 @@ matching, Hamming, decision, residual or Gauss-Newton arithmetic.
 """
 from .scenes import (  # noqa: F401
     CAM_752, CAM_512, Event, Batch, LoopParams,
-    gen_c1, gen_c2, gen_c3, gen_c4, gen_c5_event, gen_bidir, gen_pose_graph, gen_event, concat_events,
+    gen_c1, gen_c2, gen_c3, gen_c4, gen_c5_event, gen_bidir, gen_inverse_pairs, gen_pose_graph, gen_event,
+    concat_events,
     gen_tiny, verification_params, search_transforms, perturbed, ps2_passes, gen_c2_misplaced,
     ROBUST_ITERS, ROBUST_ROUNDS, ROBUST_OUTLIER_PX, ROBUST_LM_LAMBDA,
 )

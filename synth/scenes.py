@@ -533,6 +533,46 @@ def gen_c4(seed: int = 404, n: int = 50000, outlier_frac: float = 0.1, outlier_p
                 xi0=xi0, S_eval=S_eval, S_eval_f32=_sim3_f32(S_eval), outlier=out, huber_delta=2.45)
 
 
+def _sim3_inverse(S):
+    R, t, sc = _split(S)
+    return _sim3(R.T, -(R.T @ t) / sc, 1.0 / sc)
+
+
+def _observed_side(rng, n, S_map, n_views, pix_sigma, outlier_frac, outlier_px, cam=CAM_752):
+    """n points seen in n_views keyframes (poses of ~6 deg and ~0.5 m):
+    pixel ~ U(image), depth ~ U[1, 10] m, X back-projected through T_k o S_map,
+    observation = pixel + N(0, pix_sigma), a fraction displaced by outlier_px.
+    Returns ((xyz f32, uv f32, keyframe i32, poses f32 [n_views,12]), outlier mask)."""
+    W, H = cam[4], cam[5]
+    poses = [(_rodrigues(_unit(rng), np.deg2rad(rng.uniform(0.0, 6.0))), _unit(rng) * rng.uniform(0.0, 0.5))
+             for _ in range(n_views)]
+    T = np.stack([np.concatenate([Rk.reshape(9), tk]) for Rk, tk in poses]).astype(np.float32)
+    kf = rng.integers(0, n_views, n).astype(np.int32)
+    u, v, z = rng.uniform(0.0, W, n), rng.uniform(0.0, H, n), rng.uniform(1.0, 10.0, n)
+    X = np.empty((n, 3))
+    for k, (Rk, tk) in enumerate(poses):
+        m = kf == k
+        X[m] = _backproject(cam, u[m], v[m], z[m], _compose_T_S(Rk, tk, S_map))
+    uv = np.stack([u, v], axis=1) + rng.normal(0.0, pix_sigma, (n, 2))
+    out = rng.random(n) < outlier_frac
+    th = rng.uniform(0.0, 2 * np.pi, n)
+    uv[out] += outlier_px * np.stack([np.cos(th[out]), np.sin(th[out])], axis=1)
+    return (X.astype(np.float32), uv.astype(np.float32), kf, T), out
+
+
+def gen_inverse_pairs(S_true, n: int, seed: int, n_views: int = 4, pix_sigma: float = 1.0,
+                      outlier_frac: float = 0.1, outlier_px: float = 20.0):
+    """The other direction of a loop event's matches (two-sided refinement):
+    n points of the current side observed in n_views loop-side keyframes
+    through T_m o S_true^-1, with the noise and outliers of gen_bidir.
+    Returns (xyz f32 [n,3], uv f32 [n,2], keyframe i32 [n], poses f32
+    [n_views,12])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side, _ = _observed_side(rng, n, _sim3_inverse(np.asarray(S_true, np.float64)), n_views, pix_sigma,
+                             outlier_frac, outlier_px)
+    return side
+
+
 def gen_bidir(seed: int = 505, n_fwd: int = 20000, n_bwd: int = 20000, n_views: int = 4,
               pix_sigma: float = 1.0, outlier_frac: float = 0.1, outlier_px: float = 20.0):
     """Matches seen from both sides of a loop (752x480 camera, depth 1-10 m):
@@ -545,28 +585,8 @@ def gen_bidir(seed: int = 505, n_fwd: int = 20000, n_bwd: int = 20000, n_views: 
     [n_views,12])."""
     rng = np.random.Generator(np.random.PCG64(seed))
     S = _random_loop_sim3(rng, 0.95, 1.05, 5.0, 0.1)
-    R, t, sc = _split(S)
-    S_inv = _sim3(R.T, -(R.T @ t) / sc, 1.0 / sc)
-    fx, fy, cx, cy, W, H = CAM_752
-
-    def side(n, S_map):
-        poses = [(_rodrigues(_unit(rng), np.deg2rad(rng.uniform(0.0, 6.0))), _unit(rng) * rng.uniform(0.0, 0.5))
-                 for _ in range(n_views)]
-        T = np.stack([np.concatenate([Rk.reshape(9), tk]) for Rk, tk in poses]).astype(np.float32)
-        kf = rng.integers(0, n_views, n).astype(np.int32)
-        u, v, z = rng.uniform(0.0, W, n), rng.uniform(0.0, H, n), rng.uniform(1.0, 10.0, n)
-        X = np.empty((n, 3))
-        for k, (Rk, tk) in enumerate(poses):
-            m = kf == k
-            X[m] = _backproject(CAM_752, u[m], v[m], z[m], _compose_T_S(Rk, tk, S_map))
-        uv = np.stack([u, v], axis=1) + rng.normal(0.0, pix_sigma, (n, 2))
-        out = rng.random(n) < outlier_frac
-        th = rng.uniform(0.0, 2 * np.pi, n)
-        uv[out] += outlier_px * np.stack([np.cos(th[out]), np.sin(th[out])], axis=1)
-        return (X.astype(np.float32), uv.astype(np.float32), kf, T), out
-
-    fwd, out_f = side(n_fwd, S)
-    bwd, out_b = side(n_bwd, S_inv)
+    fwd, out_f = _observed_side(rng, n_fwd, S, n_views, pix_sigma, outlier_frac, outlier_px)
+    bwd, out_b = _observed_side(rng, n_bwd, _sim3_inverse(S), n_views, pix_sigma, outlier_frac, outlier_px)
     S0 = _perturb(rng, S, 0.5, 0.02, 0.01)
     return dict(S_true=S, S0=S0, cam=_cam_row(CAM_752), fwd=fwd, bwd=bwd, outlier_fwd=out_f, outlier_bwd=out_b,
                 huber_delta=2.45)

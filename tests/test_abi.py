@@ -52,7 +52,8 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_abi.Pinhole) == 32
     assert ctypes.sizeof(_abi.Params) == 32
     assert ctypes.sizeof(_abi.FuseOut) == 40
-    assert ctypes.sizeof(_abi.Refine) == 48
+    assert ctypes.sizeof(_abi.Refine) == 56
+    assert ctypes.sizeof(_abi.RefineInverse) == 56
     assert ctypes.sizeof(_abi.Pass) == 80
     assert ctypes.sizeof(_abi.PoseGraph) == 40
     assert ctypes.sizeof(_abi.PgoParams) == 64

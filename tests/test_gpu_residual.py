@@ -572,3 +572,144 @@ def test_robust_refinement_multi_event_batch(ctx, lm):
             err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
             assert err < 1e-6, (mode, lm, e, err)
         assert n_gpu[3] == 0 and np.array_equal(S_gpu[3], S0[3]), mode
+
+
+def _inverse_set(fl, sets, cams):
+    """InversePairs over the events' sets (xyz, uv, kf, T) (None: no pair);
+    keyframes of every set concatenated, each with its event's camera."""
+    off, xs, us, ks, Ts, Cs = [0], [], [], [], [], []
+    n_kf = 0
+    for st, cam in zip(sets, cams):
+        if st is None:
+            off.append(off[-1])
+            continue
+        x, u, k, T = st
+        xs.append(x)
+        us.append(u)
+        ks.append(k + n_kf)
+        Ts.append(T)
+        Cs.append(np.tile(np.asarray(cam[:4], np.float32), (len(T), 1)))
+        n_kf += len(T)
+        off.append(off[-1] + len(x))
+    cat = lambda a: np.ascontiguousarray(np.concatenate(a))
+    return fl.InversePairs(np.array(off, np.int64), t(cat(xs)), t(cat(us)), t(cat(ks).astype(np.int32)),
+                           t(cat(Ts).astype(np.float32)), t(cat(Cs)))
+
+
+def test_two_sided_refinement_in_the_batched_launch(ctx):
+    """The refinement inside the batched launch on both directions of a loop:
+    the event's accepted pairs observed through S and 8,000 current-side
+    points observed in four loop-side keyframes through S^-1, one system per
+    step; against the float64 two-sided Gauss-Newton, in every launch mode.
+    The other direction moves the result by ~1e-4, far above the bound."""
+    import paper_2603_17201_amd as fl
+    ev = synth.gen_c2()
+    out = oracle.search_fuse(ev, use_grid=True)
+    acc = np.nonzero((out["decision"] == oracle.ADD) | (out["decision"] == oracle.FUSE))[0]
+    kf = (np.searchsorted(ev.pair_offset, acc, side="right") - 1).astype(np.int32)
+    mp = acc - ev.pair_offset[kf]
+    kp = ev.kp_offset[kf] + out["best_idx"][acc]
+    xyz, uv = ev.mp_xyz[mp], ev.kp_xy[kp]
+    T32 = ev.kf_T.astype(np.float32).astype(np.float64)
+    xb, ub, kb, Tb = synth.gen_inverse_pairs(ev.S_true, 8000, seed=707)
+    inv = _inverse_set(fl, [(xb, ub, kb, Tb)], [ev.cams[0]])
+    S_ref = R.gauss_newton_bidir(ev.S_init, (xyz, uv, kf, T32), (xb, ub, kb, Tb.astype(np.float64)), ev.cams[0],
+                                 2.45, iters=10)
+    S_one = R.gauss_newton(ev.S_init, xyz, uv, kf, T32, ev.cams[0], 2.45, iters=10)
+    assert np.linalg.norm(sim3.log(sim3.compose(S_one, sim3.inverse(S_ref)))) > 1e-5
+    b = fl.DeviceBatch(ev, device=dev())
+    res = ctx.search_fuse_graph(b, ev.params)
+    for mode in ("batched", "graph", "scan"):
+        event_S = t(ev.S_init.reshape(1, 13).copy())
+        nm = torch.zeros(1, dtype=torch.int32, device=dev())
+        ref = (10, 2.45, event_S, None, nm, 0, 0.0, 0.0, inv)
+        if mode == "graph":
+            got = ctx.search_fuse_graph(b, ev.params, refine=ref).numpy()
+        elif mode == "batched":
+            got = ctx.search_fuse_batched(b, ev.params, refine=ref).numpy()
+        else:
+            ctx.refine_events(b, res, ref)
+            got = res.numpy()
+        for k in got:
+            assert np.array_equal(got[k], out[k]), (mode, k)
+        assert nm.item() == len(acc) + len(xb), mode   # every point is in front of its keyframe
+        S_gpu = event_S.cpu().numpy()[0]
+        err = np.linalg.norm(sim3.log(sim3.compose(S_gpu, sim3.inverse(S_ref))))
+        assert err < 1e-6, (mode, err)
+
+
+def test_two_sided_refinement_multi_event_batch(ctx):
+    """Four events in one launch with uneven inverse sets: one with none, one
+    whose search accepts no pair (its system comes from the other direction
+    alone), and a keyframe index out of range that must add nothing."""
+    import paper_2603_17201_amd as fl
+    e0 = synth.gen_c3(seed=321, n_kf=10, n_mp=5000, id_base=1000, fresh_base=10 ** 9)
+    e1 = synth.gen_tiny(62, n_kf=3, n_mp=400)
+    e2 = synth.gen_c2(seed=207, n_kf=5, n_mp=3000)
+    e3 = synth.gen_tiny(63, n_kf=2, n_mp=150)
+    e3.kp_desc = e3.kp_desc ^ np.uint8(0xFF)   # every distance far above the threshold
+    B = synth.concat_events([e0, e1, e2, e3])
+    exp = oracle.search_fuse(B, use_grid=True)
+    sets = [synth.gen_inverse_pairs(e0.S_true, 3000, seed=710), None,
+            synth.gen_inverse_pairs(e2.S_true, 5000, seed=712), synth.gen_inverse_pairs(e3.S_true, 2000, seed=713)]
+    cams = [B.cams[int(B.event_kf_offset[e])] for e in range(4)]
+    cam_bwd = np.array(list(synth.CAM_752) + [0.0, 0.0], np.float32)
+    # the inverse sets are seen by 752x480 cameras whatever the event's camera
+    inv = _inverse_set(fl, sets, [cam_bwd] * 4)
+    # one pair of event 2 names a keyframe outside the set: it adds nothing
+    bad = int(inv.event_offset[2]) + 17
+    kfi = inv.kf_idx.cpu().numpy()
+    kfi[bad] = 1000
+    inv.kf_idx = t(kfi)
+    refs = []
+    for e in range(4):
+        fx = _event_pairs(B, exp, e)
+        st = sets[e]
+        if st is not None and e == 2:
+            keep = np.ones(len(st[0]), bool)
+            keep[17] = False
+            st = (st[0][keep], st[1][keep], st[2][keep], st[3])
+        n_f = len(fx[0])
+        if st is None:
+            S_ref = R.gauss_newton(B.events[e].S_init, *fx, cams[e], 2.45, iters=10) if n_f else None
+            refs.append((S_ref, n_f))
+            continue
+        S_ref = R.gauss_newton_bidir(B.events[e].S_init, fx, st[:3] + (st[3].astype(np.float64),), cams[e], 2.45,
+                                     iters=10, cam_bwd=cam_bwd)
+        refs.append((S_ref, n_f + len(st[0])))
+    assert refs[3][1] == 2000   # event 3: the other direction only
+    b = fl.DeviceBatch(B, device=dev())
+    S0 = np.stack([ev.S_init for ev in B.events])
+    for mode in ("batched", "graph"):
+        S = t(S0.copy())
+        nm = torch.zeros(4, dtype=torch.int32, device=dev())
+        ref = (10, 2.45, S, None, nm, 0, 0.0, 0.0, inv)
+        res = (ctx.search_fuse_batched(b, B.params, refine=ref) if mode == "batched"
+               else ctx.search_fuse_graph(b, B.params, refine=ref))
+        got = res.numpy()
+        for k in got:
+            assert np.array_equal(got[k], exp[k]), (mode, k)
+        S_gpu, n_gpu = S.cpu().numpy(), nm.cpu().numpy()
+        for e, (S_ref, n_ref) in enumerate(refs):
+            assert n_gpu[e] == n_ref, (mode, e, n_gpu[e], n_ref)
+            err = np.linalg.norm(sim3.log(sim3.compose(S_gpu[e], sim3.inverse(S_ref))))
+            assert err < 1e-6, (mode, e, err)
+
+
+def test_two_sided_refinement_rejects_bad_arguments(ctx):
+    """Offsets that do not start at 0, and the robust variants (the other
+    direction is Gauss-Newton only), are refused before any launch."""
+    import paper_2603_17201_amd as fl
+    from paper_2603_17201_amd import _abi
+    ev = synth.gen_tiny(64, n_kf=2, n_mp=200)
+    b = fl.DeviceBatch(ev, device=dev())
+    xb, ub, kb, Tb = synth.gen_inverse_pairs(ev.S_true, 100, seed=714)
+    S = t(ev.S_init.reshape(1, 13).copy())
+    cam4 = t(np.tile(np.asarray(ev.cams[0][:4], np.float32), (len(Tb), 1)))
+    for off, rounds, lm, code in (([1, 100], 0, 0.0, _abi.FL_EINVAL), ([0, 100], 0, 0.5, _abi.FL_ENOTSUP),
+                                  ([0, 100], 2, 0.0, _abi.FL_ENOTSUP)):
+        inv = fl.InversePairs(np.asarray(off, np.int64), t(xb), t(ub), t(kb), t(Tb), cam4)
+        ref = (5, 2.45, S, None, None, rounds, 3.0 if rounds else 0.0, lm, inv)
+        with pytest.raises(fl.FlError) as ei:
+            ctx.search_fuse_batched(b, ev.params, refine=ref)
+        assert ei.value.code == code, (off, rounds, lm, ei.value)
