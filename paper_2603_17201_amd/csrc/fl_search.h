@@ -398,6 +398,7 @@ struct KfView {
     const int32_t* own;         // unused: the owner of the best keypoint is read from kp_owner
     const int32_t* hash;
     int32_t hash_mask;
+    int32_t n_rec;              // records (slots) in rec
 };
 
 // Bytes of the 16-bit octave-bucket starts in LDS (a whole number of 16-byte
@@ -523,12 +524,13 @@ struct PairScan {
     int nrows;
 };
 
-// Per wave: the candidate queue, and each lane's best key and second
-// distance.
+// Per wave: the candidate queue, each lane's best key and second distance,
+// and the marks of the scan's item ranges (-1 between uses).
 struct WaveCand {
     uint32_t q[kWave];        // owner lane << 17 | slot
     uint32_t best[kWave];
     uint32_t second[kWave];
+    int32_t mark[kWave];
 };
 constexpr size_t kSearchStaticLds = sizeof(WaveCand) * kWavesPerWG + 1024;   // beside the dynamic LDS
 
@@ -652,7 +654,13 @@ __device__ __forceinline__ void drain_queue(WaveCand& wc, int qn, const KfView& 
 }
 
 // The wave's scan of its lanes' pairs (every lane of the wave calls it; a
-// lane with no pair to search has q.total = 0 and q.nrows = 0).
+// lane with no pair to search has q.total = 0 and q.nrows = 0).  The records
+// of the lanes' runs form one sequence of items, lane after lane (lane l's
+// q.total items from P_l, the exclusive prefix sum of the totals), taken 64
+// at a time, one per lane: a wave makes ceil(N / 64) steps for its N items
+// instead of as many as its busiest lane has records.  Lane l marks where its
+// items start; the owner of an item is the last mark at or before it, and
+// the owner's window and run layout come from the owner lane.
 template <int MODE, bool STATS>
 __device__ __forceinline__ void search_scan(const KfView& v, int gate, int C, const uint8_t* mp_desc,
                                             const PairIn& p, const PairScan& q, WaveCand& wc,
@@ -661,19 +669,41 @@ __device__ __forceinline__ void search_scan(const KfView& v, int gate, int C, co
     wc.best[lane] = 0xFFFFFFFFu;
     wc.second[lane] = FL_NO_DIST;
     int qn = 0;
-    // each record is loaded one step ahead of its test, so the LDS latency
-    // overlaps the previous record's test
-    int i_next = scan_slot(q, 0);
-    KpRec r_next{};
-    if (q.total > 0) r_next = v.rec[i_next];
-    for (int m = 0;; ++m) {
-        const bool act = m < q.total;
-        if (__ballot(act) == 0ull) break;
-        const int i = i_next;
-        const KpRec rc = r_next;
-        i_next = scan_slot(q, m + 1);
-        if (m + 1 < q.total) r_next = v.rec[i_next];
-        const bool cand = act && in_window(q.w, rc.x, rc.y, rc.oct, q.pred, gate);
+    const int L = q.total;
+    const int incl = wave_incl_scan(L);
+    const int P = incl - L;
+    const int N = __builtin_amdgcn_readlane(incl, kWave - 1);
+    // item k of this lane (P <= k < P + L) is record slot
+    // k + B + (d1 if k >= A1) + (d2 if k >= A2) + (d3 if k >= A3)
+    const int B = q.b0 - P, A1 = P + q.c1, A2 = P + q.c2, A3 = P + q.c3;
+    const float lx = q.w.lx, hx = q.w.hx, ly = q.w.ly, hy = q.w.hy;
+    int cur = 0;   // owner of the step's first item when no range starts there
+    for (int base = 0; base < N; base += kWave) {
+        // (one wave's LDS accesses complete in order: the read below sees
+        // the marks, and the reset follows the read)
+        if (L > 0 && P >= base && P < base + kWave) wc.mark[P - base] = lane;
+        int mk = wc.mark[lane];
+        wc.mark[lane] = -1;
+        if (lane == 0 && mk < 0) mk = cur;
+        const unsigned long long starts = __ballot(mk >= 0);   // bit 0 always set
+        const unsigned long long upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+        const int pos = 63 - __builtin_clzll(starts & upto);
+        const int o = __shfl(mk, pos);   // owner lane of item base + lane
+        cur = __builtin_amdgcn_readlane(o, kWave - 1);
+        const int k = base + lane;
+        const bool act = k < N;
+        const int oB = __shfl(B, o), oA1 = __shfl(A1, o), oA2 = __shfl(A2, o), oA3 = __shfl(A3, o);
+        const int od1 = __shfl(q.d1, o), od2 = __shfl(q.d2, o), od3 = __shfl(q.d3, o);
+        Window w;
+        w.lx = __shfl(lx, o);
+        w.hx = __shfl(hx, o);
+        w.ly = __shfl(ly, o);
+        w.hy = __shfl(hy, o);
+        const int opred = __shfl(q.pred, o);
+        const int i = k + oB + (od1 & -(int)(k >= oA1)) + (od2 & -(int)(k >= oA2)) + (od3 & -(int)(k >= oA3));
+        KpRec rc{};
+        if (act) rc = v.rec[min((unsigned)i, (unsigned)(v.n_rec - 1))];   // (in range by construction)
+        const bool cand = act && in_window(w, rc.x, rc.y, rc.oct, opred, gate);
         const unsigned long long cm = __ballot(cand);
         if (cm) {
             const int n = __popcll(cm);
@@ -682,7 +712,7 @@ __device__ __forceinline__ void search_scan(const KfView& v, int gate, int C, co
                 qn = 0;
             }
             if (cand) {
-                wc.q[qn + __popcll(cm & ((1ull << lane) - 1ull))] = ((uint32_t)lane << 17) | (uint32_t)i;
+                wc.q[qn + __popcll(cm & ((1ull << lane) - 1ull))] = ((uint32_t)o << 17) | (uint32_t)i;
                 if (STATS) ++st[3];
             }
             qn += n;
@@ -761,6 +791,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
         s_list[0] = 0;
         s_list[1] = 0;
     }
+    s_wc[tid / kWave].mark[lane] = -1;
 
     // the octave scale table in LDS: the octave search and the window radius
     // index it per lane.  In the LDS modes the barrier that opens the first
@@ -824,6 +855,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             v.cs16 = nullptr;
             v.nb = 1;
             v.rec = h.recs + kd.kp_off;
+            v.n_rec = max(kd.n_kp, 1);
             v.desc = h.desc_sorted + 2 * (int64_t)kd.kp_off;
             v.desc_orig = nullptr;
             v.own = nullptr;
@@ -839,6 +871,7 @@ __global__ __launch_bounds__(kSearchBlock) void search_fused_kernel(const BatchH
             v.cs16 = s_cs;
             v.nb = uniform_i(h.oct_buckets);
             v.rec = s_rec;
+            v.n_rec = search_slots(uniform_i(h.lds_kp_cap), uniform_i(h.oct_buckets));
             v.desc = MODE == kModeLdsDesc ? s_desc : nullptr;
             v.desc_orig = h.kp_desc + 32 * (int64_t)kd.kp_off;
             v.own = nullptr;
