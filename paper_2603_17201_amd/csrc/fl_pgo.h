@@ -21,10 +21,10 @@
 //    so that every edge spans at most b positions (reverse Cuthill-McKee on
 //    the host), H is a band of W = 7 (b + 1) scalars.  pgo_band_assemble_kernel
 //    writes each band row from its node's incident edges;
-//    pgo_band_solve_kernel, one workgroup, factors the band by Cholesky with
-//    the forward substitution folded in, keeping the W rows still being
-//    updated in an LDS window that slides down the matrix, then back-
-//    substitutes;
+//    pgo_band_solve_kernel, one workgroup, factors the band by Cholesky in
+//    block columns of one keyframe (7 columns) with the forward substitution
+//    folded in, keeping the W rows still being updated in an LDS window that
+//    slides down the matrix, then back-substitutes in one wave;
 //  - pgo_solve_kernel, one co-resident workgroup per CU synchronised by a
 //    grid barrier, which gathers g and the diagonal blocks per node over its
 //    incident edges (fixed order, no floating-point atomics) and runs block-
@@ -572,36 +572,57 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Cost, then the banded Cholesky H = L L^T with L y = rhs solved alongside,
-// L^T x = y, and S_n <- exp(x_n) S_n, in one workgroup.
+// Row stride, in doubles, of the band solve's LDS window: even, so that
+// the entries of one band column in consecutive rows (W - 1 apart in the
+// band layout, W + 1 or W apart with the padding) fall in different banks.
+__host__ __device__ constexpr int band_win_stride(int W) { return (W | 1) + 1; }
+
+// A float64 value of lane l (l wave-uniform).
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The banded Cholesky H = L L^T with L y = rhs solved alongside, L^T x = y,
+// and S_n <- exp(x_n) S_n, in one workgroup.
 //
-// Factorisation, column k: rows k .. k + W - 1 sit in the LDS window, row R
-// in slot R mod W (its W band entries).  Phase A scales column k below the
-// pivot (L(i,k) = A(i,k) / sqrt(A(k,k))); phase B subtracts L(i,k) L(j,k)
-// from A(i,j) for k < j <= i <= k + W - 1, takes y_k out of the right-hand
-// side, writes the finished row k of L back and admits row k + W into its
-// slot.  The threads form G = 512 / W admission groups; group k mod G admits
-// at column k the row it loaded into a register G columns earlier, so the
-// loads' latency is spread over G columns.  Back substitution walks the rows
-// of L upwards, staged into the LDS window W rows at a time together with
-// each row's 1 / L(i,i) (a step then multiplies instead of dividing), with a
-// ring of W + 1 right-hand-side entries (the slots read and written in one
-// step are then all different).
+// Factorisation by block columns of 7 (one keyframe): every edge joins
+// keyframes at most b positions apart, so block column K (columns 7K ..
+// 7K + 6) has entries in rows 7K .. 7K + W - 1 only, the W rows the LDS
+// window holds (row R in slot R mod W, its W band entries).  Per block:
+//  1. one wave factors the panel (those W rows by 7 columns) in registers,
+//     lane t holding row t (and t + 64): column by column, the pivot comes
+//     from the diagonal lane, the rows below are scaled and the panel's later
+//     columns and the right-hand sides are updated, with the values of one
+//     lane read by all (readlane) and no barrier;
+//  2. the whole workgroup subtracts the panel's rank-7 product from the
+//     window's remaining triangle, while the finished rows 7K .. 7K + 6 go
+//     back to HBM and the rows of block K + b + 1, loaded two blocks earlier,
+//     take their slots.
+// Every entry sees the same fused multiply-adds, in the same order, as a
+// column-by-column factorisation: two barriers per block instead of two per
+// column.  Back substitution walks the rows of L upwards, staged into the LDS
+// window W rows at a time together with each row's 1 / L(i,i) (a step then
+// multiplies instead of dividing), with a ring of W + 1 right-hand-side
+// entries (the slots read and written in one step are then all different).
 __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     extern __shared__ __align__(16) unsigned char s_mem[];
-    __shared__ double s_w[kBandBlock / kWave];
+    __shared__ int s_fail;
     const int tid = threadIdx.x;
-    const int W = a.band_w, w = W - 1, Vs = a.band_vs, E = a.n_edges;
-    const int G = kBandBlock / W;                  // >= 6
-    const int grp = tid / W, off = tid % W;         // grp < G: an admission thread
-    double* win = (double*)s_mem;      // [W][W]
-    double* sv = win + W * W;          // [W + 1]
+    const int W = a.band_w, w = W - 1, Vs = a.band_vs;
+    const int Ws = band_win_stride(W);
+    double* win = (double*)s_mem;      // [W][Ws]
+    double* sv = win + W * Ws;         // [W + 1]
     double* sr = sv + W + 1;           // [W] right-hand sides of a back-substitution chunk
     double* sd = sr + W;               // [W] 1 / L(i,i) of the chunk's rows
 
-    // this thread's (a, b) pairs of the phase-B triangle, a >= b in [0, w)
+    // this thread's (i, j) pairs, i >= j, of the trailing triangle: local
+    // rows 7 + i and 7 + j of a block's window
     int pk[kBandPairs];
-    const int npair = w * (w + 1) / 2;
+    const int nt = W - 7;
+    const int npair = nt * (nt + 1) / 2;
     for (int q = 0; q < kBandPairs; ++q) {
         const int t = tid + q * kBandBlock;
         pk[q] = -1;
@@ -614,110 +635,216 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     }
     for (int idx = tid; idx < W * W; idx += kBandBlock) {
         const int R = idx / W;
-        win[idx] = R < Vs ? a.band[(int64_t)R * W + idx % W] : 0.0;
+        win[R * Ws + idx % W] = R < Vs ? a.band[(int64_t)R * W + idx % W] : 0.0;
     }
     for (int idx = tid; idx < W; idx += kBandBlock) sv[idx] = idx < Vs ? a.rhs[idx] : 0.0;
-    // group grp first admits row W + grp (at column grp)
-    double pre = 0.0, preb = 0.0;
-    if (grp < G && W + grp < Vs) {
-        pre = a.band[(int64_t)(W + grp) * W + off];
-        if (off == 0) preb = a.rhs[W + grp];
-    }
+    if (tid == 0) s_fail = 0;
+    // admission items of this thread: entry e of row q of a block (7 W <= 2 x 512)
+    const int n_adm = 7 * W;
+    const int q0 = tid / W, e0 = tid % W;
+    const int q1 = (tid + kBandBlock) / W, e1 = (tid + kBandBlock) % W;
+    const bool has0 = tid < n_adm, has1 = tid + kBandBlock < n_adm;
+    // rows of block K + b + 1 (they enter at block K), loaded two blocks ahead
+    double pre[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, preb[2] = {0.0, 0.0};
+    auto prefetch = [&](int K, int set) {
+        const int r = 7 * K + W;
+        pre[set][0] = has0 && r + q0 < Vs ? a.band[(int64_t)(r + q0) * W + e0] : 0.0;
+        pre[set][1] = has1 && r + q1 < Vs ? a.band[(int64_t)(r + q1) * W + e1] : 0.0;
+        if (tid < 7) preb[set] = r + tid < Vs ? a.rhs[r + tid] : 0.0;
+    };
+    prefetch(0, 0);
+    prefetch(1, 1);
     __syncthreads();
 
-    // ring slots advance by one per column (no integer division in the loop)
-    bool ok = true;
-    int sk = 0, kg = 0;   // k mod W, k mod G
-    for (int k = 0; k < Vs; ++k) {
-        const int s1 = sk + 1 == W ? 0 : sk + 1;   // slot of row k + 1
-        const double d = win[sk * W + w];
-        if (!(d > 0.0)) {   // the same value in every thread
-            ok = false;
-            break;
+    const int NB = Vs / 7;
+    int s0 = 0;   // slot of row 7K
+    for (int K = 0; K < NB; ++K) {
+        const int r0 = 7 * K;
+        if (tid < kWave) {
+            // 1. the panel, one wave
+            const int t = tid, t2 = tid + kWave;
+            int sa = s0 + t;   // below 2 W
+            if (sa >= W) sa -= W;
+            int sb = s0 + t2;  // below 3 W when W < 2 x 64
+            if (sb >= W) sb -= W;
+            if (sb >= W) sb -= W;
+            const bool ha = t < W && r0 + t < Vs, hb = t2 < W && r0 + t2 < Vs;
+            double p[7], p2[7];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                p[c] = ha && c <= t ? win[sa * Ws + w + c - t] : 0.0;
+                p2[c] = hb ? win[sb * Ws + w + c - t2] : 0.0;
+            }
+            double b1 = ha ? sv[sa] : 0.0, b2 = hb ? sv[sb] : 0.0;
+            bool okp = true;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                const double d = readlane_f64(p[c], c);
+                okp = okp && d > 0.0;   // the same in every lane; a failed block is discarded whole
+                // 1 / sqrt(d) from the hardware estimate and two Newton steps
+                // (a short dependency chain on this serial path), sqrt(d) =
+                // d / sqrt(d)
+                double ird = __builtin_amdgcn_rsq(d);
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    const double e = fma(-d * ird, ird, 1.0);
+                    ird = fma(0.5 * ird, e, ird);
+                }
+                const double rd = d * ird;
+                const double yc = readlane_f64(b1, c) * ird;
+                if (t == c) {
+                    p[c] = rd;
+                    b1 = yc;
+                } else if (t > c) {
+                    p[c] *= ird;
+                    b1 = fma(-p[c], yc, b1);
+                }
+                p2[c] *= ird;
+                b2 = fma(-p2[c], yc, b2);
+#pragma unroll
+                for (int j = c + 1; j < 7; ++j) {
+                    const double ljc = readlane_f64(p[c], j);   // L(j, c)
+                    if (t >= j) p[j] = fma(-p[c], ljc, p[j]);
+                    p2[j] = fma(-p2[c], ljc, p2[j]);
+                }
+            }
+            if (!okp) {
+                if (t == 0) s_fail = 1;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 7; ++c) {
+                    if (ha && c <= t) win[sa * Ws + w + c - t] = p[c];
+                    if (hb) win[sb * Ws + w + c - t2] = p2[c];
+                }
+                if (ha) sv[sa] = b1;
+                if (hb) sv[sb] = b2;
+            }
         }
-        const double rd = sqrt(d);
-        const double ird = 1.0 / rd;
-        const double yk = sv[sk] * ird;
-        int st = s1 + tid;   // slot of row k + 1 + tid (tid < w)
-        if (st >= W) st -= W;
-        if (tid < w && k + 1 + tid < Vs) win[st * W + w - 1 - tid] *= ird;
         lds_barrier();
-        // every read of this phase (column k) before any write (columns > k):
-        // the reads then issue back to back instead of one round trip per pair
-        double lv[kBandPairs], lw[kBandPairs], av[kBandPairs];
+        if (s_fail) break;   // the same in every thread
+        // 2. the trailing update, with the admission beside it.  Every pair
+        // is read and computed before any is written back (a store could
+        // otherwise be taken to alias the next pair's loads and serialise
+        // them); the panel columns it reads are not written in this phase.
+        double nv[kBandPairs];
         int at[kBandPairs];
 #pragma unroll
         for (int q = 0; q < kBandPairs; ++q) {
-            const int pa = pk[q] >> 8, pb = pk[q] & 255;
             at[q] = -1;
-            if (pk[q] >= 0 && k + 1 + pa < Vs) {
-                int si = s1 + pa, sj = s1 + pb;
-                if (si >= W) si -= W;
-                if (sj >= W) sj -= W;
-                at[q] = si * W + w - pa + pb;
-                lv[q] = win[si * W + w - 1 - pa];
-                lw[q] = win[sj * W + w - 1 - pb];
-                av[q] = win[at[q]];
-            }
+            if (pk[q] < 0) continue;
+            const int i = 7 + (pk[q] >> 8), j = 7 + (pk[q] & 255);
+            if (r0 + i >= Vs) continue;
+            int si = s0 + i, sj = s0 + j;   // both below 2 W
+            if (si >= W) si -= W;
+            if (sj >= W) sj -= W;
+            const double* Li = win + si * Ws + w - i;   // Li[c] = L(7K + i, 7K + c)
+            const double* Lj = win + sj * Ws + w - j;
+            at[q] = si * Ws + w - (i - j);
+            double av = win[at[q]];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) av = fma(-Li[c], Lj[c], av);
+            nv[q] = av;
         }
 #pragma unroll
         for (int q = 0; q < kBandPairs; ++q)
-            if (at[q] >= 0) win[at[q]] = fma(-lv[q], lw[q], av[q]);
-        if (tid < w && k + 1 + tid < Vs) sv[st] = fma(-win[st * W + w - 1 - tid], yk, sv[st]);
-        if (grp == kg) {
-            const double v = off == w ? rd : win[sk * W + off];
-            a.band[(int64_t)k * W + off] = v;
-            win[sk * W + off] = pre;
-            const int nr = k + W + G;
-            pre = nr < Vs ? a.band[(int64_t)nr * W + off] : 0.0;
-            if (off == 0) {
-                a.rhs[k] = yk;
-                sv[sk] = preb;
-                preb = nr < Vs ? a.rhs[nr] : 0.0;
-            }
+            if (at[q] >= 0) win[at[q]] = nv[q];
+        const int set = K & 1;
+        if (has0 && r0 + q0 < Vs) {
+            int sq = s0 + q0;
+            if (sq >= W) sq -= W;
+            a.band[(int64_t)(r0 + q0) * W + e0] = win[sq * Ws + e0];
+            win[sq * Ws + e0] = pre[set][0];
         }
+        if (has1 && r0 + q1 < Vs) {
+            int sq = s0 + q1;
+            if (sq >= W) sq -= W;
+            a.band[(int64_t)(r0 + q1) * W + e1] = win[sq * Ws + e1];
+            win[sq * Ws + e1] = pre[set][1];
+        }
+        if (tid < 7 && r0 + tid < Vs) {
+            int sq = s0 + tid;
+            if (sq >= W) sq -= W;
+            a.rhs[r0 + tid] = sv[sq];
+            sv[sq] = preb[set];
+        }
+        prefetch(K + 2, set);
+        // LDS only: the prefetches stay in flight across the barrier
         lds_barrier();
-        sk = s1;
-        kg = kg + 1 == G ? 0 : kg + 1;
+        s0 += 7;
+        if (s0 >= W) s0 -= W;
     }
-    if (!ok) {   // the same in every thread
+    if (s_fail) {   // the same in every thread
         if (tid == 0) a.lm[kLmFail] = 1.0;
         return;
     }
     if (tid == 0) a.lm[kLmUsed] = 0.0;
     __syncthreads();   // L and y in global memory, visible to every thread
 
-    const int W1 = W + 1;
-    if (tid < W && Vs - W + tid >= 0) sv[(Vs - W + tid) % W1] = a.rhs[Vs - W + tid];
-    int si = (Vs - 1) % W1;   // ring slot of row i, one down per step
+    // Back substitution, L^T x = y, by one wave: x_i = s_i / L(i,i), then
+    // s_j -= L(i,j) x_i for the rows j of row i's band (column-oriented).
+    // The running right-hand sides stay in the wave's registers: lane l
+    // holds the rows j = l (mod 64), one per half of each 128 rows (svA: j =
+    // l, svB: j = l + 64, mod 128), which covers any band of at most 128
+    // rows; when row i is done its lane takes row i - 128 in its place.  The
+    // workgroup stages W rows of L at a time into LDS (with 1 / L(i,i) and the
+    // y entering), and the wave runs through them without a barrier.
+    double svA = 0.0, svB = 0.0;
+    if (tid < kWave) {
+        const int base = Vs - 128;
+        int jA = base + (((tid - base) % 128) + 128) % 128;        // = tid (mod 128)
+        int jB = base + (((tid + 64 - base) % 128) + 128) % 128;   // = tid + 64 (mod 128)
+        svA = jA >= 0 ? a.rhs[jA] : 0.0;
+        svB = jB >= 0 ? a.rhs[jB] : 0.0;
+    }
     for (int top = Vs - 1; top >= 0; top -= W) {
         // rows top - W + 1 .. top of L into the window, row i at (top - i)
         const int lo = top - W + 1 < 0 ? 0 : top - W + 1;
         const int nrow = top - lo + 1;
         for (int idx = tid; idx < nrow * W; idx += kBandBlock) {
             const int ii = idx / W;
-            win[idx] = a.band[(int64_t)(top - ii) * W + idx % W];
+            win[ii * Ws + idx % W] = a.band[(int64_t)(top - ii) * W + idx % W];
         }
         for (int ii = tid; ii < nrow; ii += kBandBlock) {
-            sr[ii] = top - ii - W >= 0 ? a.rhs[top - ii - W] : 0.0;
+            sr[ii] = top - ii - 128 >= 0 ? a.rhs[top - ii - 128] : 0.0;
             sd[ii] = 1.0 / a.band[(int64_t)(top - ii) * W + w];
         }
         __syncthreads();
-        for (int ii = 0; ii < nrow; ++ii) {
-            const int i = top - ii;
-            const double* Li = win + ii * W;
-            const double xi = sv[si] * sd[ii];
-            if (tid < w && i - w + tid >= 0) {
-                int sj = si - w + tid;   // slot of row i - w + tid
-                if (sj < 0) sj += W1;
-                sv[sj] = fma(-Li[tid], xi, sv[sj]);
+        if (tid < kWave) {
+            const int l = tid;
+            // eight rows at a time: their LDS reads (which do not depend on
+            // x) are issued together, ahead of the serial chain
+            constexpr int kU = 8;
+            for (int i0 = 0; i0 < nrow; i0 += kU) {
+                double lA[kU], lB[kU], di[kU], yn[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int ii = i0 + u;
+                    const int i = top - ii;
+                    const int dA = (i - l) & 127, dB = (i - l - 64) & 127;
+                    const bool in = ii < nrow;
+                    const double* Li = win + (in ? ii : 0) * Ws + w;   // Li[-d] = L(i, i - d)
+                    lA[u] = in && dA >= 1 && dA <= w ? Li[-dA] : 0.0;
+                    lB[u] = in && dB >= 1 && dB <= w ? Li[-dB] : 0.0;
+                    di[u] = in ? sd[ii] : 0.0;
+                    yn[u] = in ? sr[ii] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int ii = i0 + u;
+                    if (ii >= nrow) break;   // the same in every lane
+                    const int i = top - ii;
+                    const int li = i & 63;
+                    const bool hi_half = ((i >> 6) & 1) != 0;   // the same in every lane
+                    const double xi = readlane_f64(hi_half ? svB : svA, li) * di[u];
+                    svA = fma(-lA[u], xi, svA);   // lA = 0 outside row i's band
+                    svB = fma(-lB[u], xi, svB);
+                    if (l == li) {
+                        a.xs[i] = xi;
+                        if (hi_half) svB = yn[u];   // row i - 128 in its place
+                        else svA = yn[u];
+                    }
+                }
             }
-            if (tid == w) {
-                a.xs[i] = xi;
-                if (i - W >= 0) sv[si + 1 == W1 ? 0 : si + 1] = sr[ii];   // (i - W) mod (W + 1)
-            }
-            lds_barrier();
-            si = si == 0 ? W1 - 1 : si - 1;
         }
         __syncthreads();   // the window is refilled next
     }
