@@ -982,6 +982,9 @@ int fl_create(fl_ctx** out, int device) {
     allow_lds_all<1>(c->lds_max);
     allow_lds_all<2>(c->lds_max);
     allow_lds_all<4>(c->lds_max);
+    // the band solve's window at the widest band (above 64 KB)
+    (void)hipFuncSetAttribute((const void*)pgo_band_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)band_solve_lds_bytes(kBandMaxW));
     for (auto& f : c->fence) {
         if (hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess) {
             fl_destroy(c);
@@ -1647,7 +1650,7 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
             hipLaunchKernelGGL(pgo_band_assemble_kernel, dim3((unsigned)((band_vs + kBandBlock - 1) / kBandBlock)),
                                dim3(kBandBlock), 0, stream, a);
             hipLaunchKernelGGL(pgo_band_solve_kernel, dim3(1), dim3(kBandBlock),
-                               sizeof(double) * ((size_t)band_w * band_win_stride(band_w) + 3 * band_w + 1), stream, a);
+                               band_solve_lds_bytes(band_w), stream, a);
         } else {
             fill_u32(a.bar, sizeof(uint32_t), 0u, stream);
             hipLaunchKernelGGL(pgo_solve_kernel, dim3(solve_grid), dim3(kPgoBlock), 0, stream, a);

@@ -577,6 +577,13 @@ __device__ __forceinline__ void lds_barrier() {
 // band layout, W + 1 or W apart with the padding) fall in different banks.
 __host__ __device__ constexpr int band_win_stride(int W) { return (W | 1) + 1; }
 
+// Dynamic LDS of the band solve: the window, the right-hand-side ring, a
+// back-substitution chunk's right-hand sides and 1 / L(i,i), and the staged
+// rows of the next block with their right-hand sides.
+__host__ __device__ constexpr size_t band_solve_lds_bytes(int W) {
+    return sizeof(double) * ((size_t)W * band_win_stride(W) + (W + 1) + W + W + 7 * (size_t)W + 7);
+}
+
 // A float64 value of lane l (l wave-uniform).
 __device__ __forceinline__ double readlane_f64(double x, int l) {
     const long long v = __double_as_longlong(x);
@@ -617,6 +624,8 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     double* sv = win + W * Ws;         // [W + 1]
     double* sr = sv + W + 1;           // [W] right-hand sides of a back-substitution chunk
     double* sd = sr + W;               // [W] 1 / L(i,i) of the chunk's rows
+    double* stg = sd + W;              // [7 W] the rows of the block that enters next
+    double* stgb = stg + 7 * W;        // [7] and their right-hand sides
 
     // this thread's (i, j) pairs, i >= j, of the trailing triangle: local
     // rows 7 + i and 7 + j of a block's window
@@ -639,21 +648,6 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     }
     for (int idx = tid; idx < W; idx += kBandBlock) sv[idx] = idx < Vs ? a.rhs[idx] : 0.0;
     if (tid == 0) s_fail = 0;
-    // admission items of this thread: entry e of row q of a block (7 W <= 2 x 512)
-    const int n_adm = 7 * W;
-    const int q0 = tid / W, e0 = tid % W;
-    const int q1 = (tid + kBandBlock) / W, e1 = (tid + kBandBlock) % W;
-    const bool has0 = tid < n_adm, has1 = tid + kBandBlock < n_adm;
-    // rows of block K + b + 1 (they enter at block K), loaded two blocks ahead
-    double pre[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, preb[2] = {0.0, 0.0};
-    auto prefetch = [&](int K, int set) {
-        const int r = 7 * K + W;
-        pre[set][0] = has0 && r + q0 < Vs ? a.band[(int64_t)(r + q0) * W + e0] : 0.0;
-        pre[set][1] = has1 && r + q1 < Vs ? a.band[(int64_t)(r + q1) * W + e1] : 0.0;
-        if (tid < 7) preb[set] = r + tid < Vs ? a.rhs[r + tid] : 0.0;
-    };
-    prefetch(0, 0);
-    prefetch(1, 1);
     __syncthreads();
 
     const int NB = Vs / 7;
@@ -719,6 +713,16 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
                 if (ha) sv[sa] = b1;
                 if (hb) sv[sb] = b2;
             }
+        } else {
+            // meanwhile the other waves stage the rows of block K + b + 1
+            // (they enter at the end of this block), so their loads' latency
+            // is spent beside the panel
+            const int r = r0 + W;
+            for (int idx = tid - kWave; idx < 7 * W; idx += kBandBlock - kWave) {
+                const int q = idx / W, e = idx - q * W;
+                stg[idx] = r + q < Vs ? a.band[(int64_t)(r + q) * W + e] : 0.0;
+            }
+            if (tid - kWave < 7) stgb[tid - kWave] = r + tid - kWave < Vs ? a.rhs[r + tid - kWave] : 0.0;
         }
         lds_barrier();
         if (s_fail) break;   // the same in every thread
@@ -748,27 +752,23 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
 #pragma unroll
         for (int q = 0; q < kBandPairs; ++q)
             if (at[q] >= 0) win[at[q]] = nv[q];
-        const int set = K & 1;
-        if (has0 && r0 + q0 < Vs) {
-            int sq = s0 + q0;
+        // the finished rows 7K .. 7K + 6 go back to HBM and the staged
+        // rows take their slots
+        for (int idx = tid; idx < 7 * W; idx += kBandBlock) {
+            const int q = idx / W, e = idx - q * W;
+            if (r0 + q >= Vs) continue;
+            int sq = s0 + q;
             if (sq >= W) sq -= W;
-            a.band[(int64_t)(r0 + q0) * W + e0] = win[sq * Ws + e0];
-            win[sq * Ws + e0] = pre[set][0];
-        }
-        if (has1 && r0 + q1 < Vs) {
-            int sq = s0 + q1;
-            if (sq >= W) sq -= W;
-            a.band[(int64_t)(r0 + q1) * W + e1] = win[sq * Ws + e1];
-            win[sq * Ws + e1] = pre[set][1];
+            a.band[(int64_t)(r0 + q) * W + e] = win[sq * Ws + e];
+            win[sq * Ws + e] = stg[idx];
         }
         if (tid < 7 && r0 + tid < Vs) {
             int sq = s0 + tid;
             if (sq >= W) sq -= W;
             a.rhs[r0 + tid] = sv[sq];
-            sv[sq] = preb[set];
+            sv[sq] = stgb[tid];
         }
-        prefetch(K + 2, set);
-        // LDS only: the prefetches stay in flight across the barrier
+        // LDS only: the row stores stay in flight across the barrier
         lds_barrier();
         s0 += 7;
         if (s0 >= W) s0 -= W;
