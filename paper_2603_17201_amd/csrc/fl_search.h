@@ -539,27 +539,19 @@ __device__ __forceinline__ bool search_front(const KfDesc& kd, const KfView& v, 
                                              int C, int R, PairIn& p, PairScan& q, unsigned long long* st) {
     q.total = 0;
     q.nrows = 0;
-    // owner probe: a point already observed in this keyframe is skipped
-    if (p.dec == kDecUndecided && p.id >= 0) {
-        uint32_t hh = owner_slot(p.id, v.hash_mask);
-        for (int probe = 0; probe <= v.hash_mask; ++probe) {
-            const int32_t hv = v.hash[hh];
-            if (hv == p.id) {
-                p.dec = FL_SKIP;
-                break;
-            }
-            if (hv < 0) break;
-            hh = (hh + 1) & (uint32_t)v.hash_mask;
-        }
+    // owner probe (a point already observed in this keyframe is skipped):
+    // its first read is issued here and the probe finished after the
+    // window, so its latency overlaps the projection
+    const bool probe = p.dec == kDecUndecided && p.id >= 0;
+    uint32_t hh = 0;
+    int32_t hv = -1;
+    if (probe) {
+        hh = owner_slot(p.id, v.hash_mask);
+        hv = v.hash[hh];
     }
-    if (p.dec != kDecUndecided) return false;
-    Proj pr;
-    if (!project_uv(kd, p.x, p.y, p.z, pr)) {
-        p.dec = FL_NOT_VISIBLE;
-        return false;
-    }
+    Proj pr{};
+    const bool vis = p.dec == kDecUndecided && project_uv(kd, p.x, p.y, p.z, pr);
     q.pred = gate ? predict_octave(T, pr.d, p.dm) : T.N - 1;
-    if (STATS) ++st[0];
     const float rad = window_radius(T, q.pred);
     Window& w = q.w;
     w.lx = pr.u - rad;
@@ -574,17 +566,6 @@ __device__ __forceinline__ bool search_front(const KfDesc& kd, const KfView& v, 
     auto cs_at = [&](int j) -> int { return MODE == kModeGlobal ? v.cs[j] : (int)v.cs16[j]; };
     q.grp = min(q.pred, nb - 1);
     q.nrows = w.r1 - w.r0 + 1;
-    if (STATS) {
-        // cells and keypoints of the window's cells (every octave: the
-        // counting launch stages one group)
-        for (int row = w.r0; row <= w.r1; ++row) {
-            st[1] += (unsigned long long)(w.c1 - w.c0 + 1);
-            for (int g = 0; g < nb; ++g) {
-                const int j = (row * nb + g) * C;
-                st[2] += (unsigned long long)(cs_at(j + w.c1 + 1) - cs_at(j + w.c0));
-            }
-        }
-    }
     // the runs of the first kRowSeg rows (named values, not arrays: an array
     // indexed by a lane-dependent value would be placed in scratch memory)
     auto run = [&](int j, int c_in, int& b_out, int& c_out) {
@@ -602,6 +583,36 @@ __device__ __forceinline__ bool search_front(const KfDesc& kd, const KfView& v, 
     q.d1 = b1 - q.b0;
     q.d2 = b2 - b1;
     q.d3 = b3 - b2;
+    if (probe) {
+        for (int n = 0; n <= v.hash_mask; ++n) {
+            if (hv == p.id) {
+                p.dec = FL_SKIP;
+                break;
+            }
+            if (hv < 0) break;
+            hh = (hh + 1) & (uint32_t)v.hash_mask;
+            hv = v.hash[hh];
+        }
+    }
+    // SKIP before NOT_VISIBLE; neither is searched
+    if (p.dec == kDecUndecided && !vis) p.dec = FL_NOT_VISIBLE;
+    if (p.dec != kDecUndecided) {
+        q.total = 0;
+        q.nrows = 0;
+        return false;
+    }
+    if (STATS) {
+        ++st[0];
+        // cells and keypoints of the window's cells (every octave: the
+        // counting launch stages one group)
+        for (int row = w.r0; row <= w.r1; ++row) {
+            st[1] += (unsigned long long)(w.c1 - w.c0 + 1);
+            for (int g = 0; g < nb; ++g) {
+                const int j = (row * nb + g) * C;
+                st[2] += (unsigned long long)(cs_at(j + w.c1 + 1) - cs_at(j + w.c0));
+            }
+        }
+    }
     return true;
 }
 
