@@ -57,7 +57,8 @@ REFINE_FLOPS_PER_PAIR = 35 * 5 + 1
 REFINE_BYTES_PER_PAIR = 32   # one accepted-pair record read (then kept in registers)
 # HBM bytes per launch measured with rocprofv3 counters, one
 # "traffic: <kernel> <workload> <bytes> <sources hash>" line per kernel and
-# workload
+# workload (the search kernel named with its tuning: pairs per lane, LDS
+# mode, workgroups per CU, XCD ordering)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_counters.md")
 KERNEL_SOURCES = {
     "search_fused_kernel": ("paper_2603_17201_amd/csrc/fl_search.h", "paper_2603_17201_amd/csrc/fl_internal.h"),
@@ -822,7 +823,8 @@ class Bench:
         rs.update(kernel=f"search_fused_kernel<{tv.pairs_per_lane},{tv.lds_mode}>", launches=ks_n,
                   kernel_us=ks_ms / max(ks_n, 1) * 1e3, alg_bytes=sb // max(ks_n, 1), alg_ops=so // max(ks_n, 1),
                   roofline_us=rs["roofline_us"] / max(ks_n, 1))
-        rs["traffic"] = self.traffic(rs["kernel"], "stream")
+        rs["traffic"] = self.traffic(
+            f"{rs['kernel']}/{tv.pairs_per_lane},{tv.lds_mode},{tv.wg_per_cu},{tv.xcd_aware}", "stream")
         rr = refine_roofline(n_acc, kr_ms)
         rr.update(kernel="refine_kernel", launches=kr_n, kernel_us=kr_ms / max(kr_n, 1) * 1e3,
                   alg_flops=rr["alg_flops"] // max(kr_n, 1), alg_bytes=rr["alg_bytes"] // max(kr_n, 1),
