@@ -576,13 +576,16 @@ class Bench:
         res["by_size"] = self.pose_graph_by_size(steps)
         return res
 
-    def pose_graph_by_size(self, steps, sizes=(100, 250, 500, 1000, 2000)):
+    def pose_graph_by_size(self, steps, graphs=((100, 1), (250, 1), (500, 1), (1000, 1), (2000, 1), (1000, 2),
+                                                (1000, 3), (1000, 4))):
         """One Levenberg-Marquardt step of the essential graph on the device
         (edge Jacobians, banded assembly, direct solve, candidate cost) across
-        graph sizes, beside the CPU baseline of the linear solve alone: the
-        same damped system, assembled on the host from the oracle's edge
-        Jacobians (untimed), solved by LAPACK's banded Cholesky under a
-        reverse Cuthill-McKee order and by SuperLU on the sparse matrix."""
+        graph sizes (n keyframes, laps of the trajectory: one loop, or
+        several whose keyframes are joined to the lap before, 3 each), beside
+        the CPU baseline of the linear solve alone: the same damped system,
+        assembled on the host from the oracle's edge Jacobians (untimed),
+        solved by LAPACK's banded Cholesky under a reverse Cuthill-McKee order
+        and by SuperLU on the sparse matrix."""
         import synth
         import scipy.linalg
         import scipy.sparse
@@ -591,8 +594,8 @@ class Bench:
         from oracle import pgo as opgo
         torch, fl, ctx = self.torch, self.fl, self.ctx
         out = []
-        for n in sizes:
-            d = synth.gen_pose_graph(n=n, seed=606)
+        for n, laps in graphs:
+            d = synth.gen_pose_graph(n=n, seed=606, laps=laps, cross=3 if laps > 1 else 0)
             S0 = torch.from_numpy(d["S0"]).to(self.dev)
             S = S0.clone()
             M = torch.from_numpy(d["M"]).to(self.dev)
@@ -644,10 +647,10 @@ class Bench:
             chol_ms = t_ms(lambda: scipy.linalg.solveh_banded(band, rhs, lower=True))
             Hc = H.tocsc()
             lu_ms = t_ms(lambda: scipy.sparse.linalg.spsolve(Hc, -g))
-            out.append(dict(n_keyframes=n, n_edges=int(d["edges"].shape[0]), unknowns=N, band_width=w,
+            out.append(dict(n_keyframes=n, laps=laps, n_edges=int(d["edges"].shape[0]), unknowns=N, band_width=w,
                             device_lm_step_ms=dev_ms, cpu_banded_cholesky_solve_ms=chol_ms,
                             cpu_sparse_lu_solve_ms=lu_ms))
-            log(f"essential graph, {n} keyframes: device LM step {dev_ms:.3f} ms; CPU solve alone: banded "
+            log(f"essential graph, {n} keyframes, {laps} lap(s): device LM step {dev_ms:.3f} ms; CPU solve alone: banded "
                 f"Cholesky {chol_ms:.3f} ms, sparse LU {lu_ms:.3f} ms (band {w} of {N} unknowns)")
         return dict(note="device: one whole Levenberg-Marquardt step (Jacobians, assembly, banded solve, candidate "
                          "cost); CPU: the linear solve alone in the benchmark process (LAPACK and SuperLU "

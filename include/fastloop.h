@@ -405,7 +405,11 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
  *    host; when no edge then spans more than FL_PGO_MAX_BAND_NODES - 1
  *    positions, the banded H is factored by float64 Cholesky in one
  *    workgroup and solved exactly (cg_used = 0; a pivot that is not
- *    positive reports -1 and refuses that iteration's candidate);
+ *    positive reports -1 and refuses that iteration's candidate).  A band
+ *    of at most 12 keyframes is factored through a window of rows in LDS,
+ *    a wider one (several loops, for instance) with the band itself in
+ *    device memory as the window; both take the same floating-point steps
+ *    in the same order and give identical results where both apply;
  *  - block-Jacobi preconditioned conjugate gradients (at most cg_iters,
  *    stopping when |r| <= cg_tol |g|).  This solve runs one workgroup per
  *    compute unit, all resident together and synchronised by a grid
@@ -417,10 +421,12 @@ int fl_gn_step(fl_ctx* ctx, const double* g, const double* H, double lambda, dou
  * every setting.  Deterministic: every sum has a fixed order; the host
  * enqueues the same kernels every iteration and never waits for the
  * device (the damping and the decision stay in device memory). */
-#define FL_PGO_MAX_BAND_NODES 12   /* widest band of the direct solver, in keyframes */
+#define FL_PGO_MAX_BAND_NODES 64   /* widest band of the direct solver, in keyframes */
 #define FL_PGO_SOLVER_AUTO 0       /* direct when the band fits, else conjugate gradients */
 #define FL_PGO_SOLVER_CG 1
 #define FL_PGO_SOLVER_DIRECT 2     /* FL_ERANGE when the band does not fit */
+#define FL_PGO_SOLVER_DIRECT_WIDE 3   /* direct, with the device-memory window at every band width
+                                         (FL_ERANGE when the band does not fit) */
 typedef struct {
     int32_t n_nodes;
     int32_t n_edges;

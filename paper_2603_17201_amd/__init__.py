@@ -5,6 +5,7 @@ The compute lives in ``libfastloop.so`` (HIP, built by ``build.py``) behind
 the C ABI of ``include/fastloop.h``; this package only marshals arguments.
 """
 from ._abi import (ADD, FUSE, INVALID, MAX_KP, NO_DIST, NO_MATCH, NOT_VISIBLE, SKIP,  # noqa: F401
+                   PGO_MAX_BAND_NODES, PGO_SOLVER_AUTO, PGO_SOLVER_CG, PGO_SOLVER_DIRECT, PGO_SOLVER_DIRECT_WIDE,
                    LIB_PATH, SIGNATURES, load, last_error)
 
 __all__ = ["load", "last_error", "LIB_PATH", "SIGNATURES", "Context", "DeviceBatch", "FuseOutputs",

@@ -73,8 +73,8 @@ class PgoParams(ctypes.Structure):
                 ("solver", c_int32), ("reserved", c_int32)]
 
 
-PGO_MAX_BAND_NODES = 12   # FL_PGO_MAX_BAND_NODES
-PGO_SOLVER_AUTO, PGO_SOLVER_CG, PGO_SOLVER_DIRECT = 0, 1, 2
+PGO_MAX_BAND_NODES = 64   # FL_PGO_MAX_BAND_NODES
+PGO_SOLVER_AUTO, PGO_SOLVER_CG, PGO_SOLVER_DIRECT, PGO_SOLVER_DIRECT_WIDE = 0, 1, 2, 3
 
 
 class RefineInverse(ctypes.Structure):

@@ -407,8 +407,9 @@ class Context:
         damping lam; lam = 0: Gauss-Newton): S device float64 [n, 13],
         M device float64 [E, 13], edges host int32 [E, 2], fixed host bool
         [n] or None (node 0 held); solver 0 (direct when the reordered band
-        fits, else conjugate gradients), 1 (conjugate gradients) or 2
-        (direct).  Returns (cost [iters + 1], cg_used [iters], 0 for a
+        fits, else conjugate gradients), 1 (conjugate gradients), 2
+        (direct) or 3 (direct through the device-memory window, which wider
+        bands take anyway).  Returns (cost [iters + 1], cg_used [iters], 0 for a
         direct solve) as device tensors, and with history=True also
         (lambdas [iters], accepted [iters])."""
         n = int(S.shape[0])

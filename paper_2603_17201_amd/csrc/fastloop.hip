@@ -1478,7 +1478,7 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
     if (P->cg_iters < 1 || P->cg_iters > 100000) return fail(FL_ERANGE, "cg_iters %d outside [1, 100000]", P->cg_iters);
     if (!(P->lambda >= 0.0) || !std::isfinite(P->lambda)) return fail(FL_EINVAL, "lambda must be finite and >= 0");
     if (!(P->cg_tol >= 0.0) || !std::isfinite(P->cg_tol)) return fail(FL_EINVAL, "cg_tol must be finite and >= 0");
-    if (P->solver < FL_PGO_SOLVER_AUTO || P->solver > FL_PGO_SOLVER_DIRECT || P->reserved != 0)
+    if (P->solver < FL_PGO_SOLVER_AUTO || P->solver > FL_PGO_SOLVER_DIRECT_WIDE || P->reserved != 0)
         return fail(FL_EINVAL, "solver %d / reserved %d", P->solver, P->reserved);
     // incident edges of every node, in edge order (the gathers' fixed order),
     // then the band position of every node and the node of every position
@@ -1558,9 +1558,12 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
         }
     }
     const bool band_fits = bw + 1 <= FL_PGO_MAX_BAND_NODES;
-    if (P->solver == FL_PGO_SOLVER_DIRECT && !band_fits && E > 0 && nf > 0)
+    if ((P->solver == FL_PGO_SOLVER_DIRECT || P->solver == FL_PGO_SOLVER_DIRECT_WIDE) && !band_fits && E > 0 &&
+        nf > 0)
         return fail(FL_ERANGE, "reordered band spans %d keyframes (at most %d)", bw + 1, FL_PGO_MAX_BAND_NODES);
     const bool direct = E > 0 && nf > 0 && band_fits && P->solver != FL_PGO_SOLVER_CG;
+    // the LDS window up to kBandLdsNodes keyframes, the device-memory one above
+    const bool wide = direct && (bw + 1 > kBandLdsNodes || P->solver == FL_PGO_SOLVER_DIRECT_WIDE);
     const int band_w = 7 * (bw + 1);
     const int64_t band_vs = 7 * (int64_t)nf;
     const size_t tab_bytes = sizeof(int32_t) * tab.size();
@@ -1649,8 +1652,11 @@ int fl_pose_graph_optimize(fl_ctx* c, const fl_pose_graph* G, const fl_pgo_param
         if (direct) {
             hipLaunchKernelGGL(pgo_band_assemble_kernel, dim3((unsigned)((band_vs + kBandBlock - 1) / kBandBlock)),
                                dim3(kBandBlock), 0, stream, a);
-            hipLaunchKernelGGL(pgo_band_solve_kernel, dim3(1), dim3(kBandBlock),
-                               band_solve_lds_bytes(band_w), stream, a);
+            if (wide)
+                hipLaunchKernelGGL(pgo_band_solve_wide_kernel, dim3(1), dim3(kWideBlock), 0, stream, a);
+            else
+                hipLaunchKernelGGL(pgo_band_solve_kernel, dim3(1), dim3(kBandBlock),
+                                   band_solve_lds_bytes(band_w), stream, a);
         } else {
             fill_u32(a.bar, sizeof(uint32_t), 0u, stream);
             hipLaunchKernelGGL(pgo_solve_kernel, dim3(solve_grid), dim3(kPgoBlock), 0, stream, a);

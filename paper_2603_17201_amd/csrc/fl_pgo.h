@@ -43,7 +43,13 @@ namespace fl {
 constexpr int kPgoBlock = 256;      // threads of a solve workgroup (one per CU, all co-resident)
 constexpr int kPgoJacBlock = 256;   // threads of a Jacobian workgroup
 constexpr int kBandBlock = 512;     // threads of the band assembly and of the one band-solve workgroup
-constexpr int kBandMaxW = 7 * FL_PGO_MAX_BAND_NODES;   // widest band row, in scalars
+constexpr int kBandLdsNodes = 12;   // widest band, in keyframes, whose window the LDS holds
+constexpr int kBandMaxW = 7 * kBandLdsNodes;   // widest band row of the LDS-window solve, in scalars
+constexpr int kWideBlock = 1024;    // threads of the device-memory-window band solve
+constexpr int kWideMaxW = 7 * FL_PGO_MAX_BAND_NODES;   // widest band row of any direct solve
+constexpr int kWideRing = 512;      // right-hand-side ring of that solve (a power of two)
+static_assert(kWideMaxW + 14 <= kWideRing && kWideMaxW <= kWideBlock, "one thread per window row");
+static_assert(kBandLdsNodes <= FL_PGO_MAX_BAND_NODES, "the LDS window is the narrow case");
 constexpr int kBandPairs = ((kBandMaxW - 1) * kBandMaxW / 2 + kBandBlock - 1) / kBandBlock;
 static_assert(kBandMaxW <= kBandBlock, "one thread per band offset");
 
@@ -592,6 +598,22 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// The candidate poses of a direct solve: S_n <- exp(x_n) S_n for every free
+// node (x in a.xs, by band position), held nodes copied.
+__device__ inline void band_candidate_poses(const PgoArgs& a) {
+    for (int n = threadIdx.x; n < a.n_nodes; n += blockDim.x) {
+        const int P = a.pos[n];
+        const Sim3d Sn = sim3_load(a.S + 13 * (int64_t)n);
+        if (P < 0) {
+            sim3_store(Sn, a.S_c + 13 * (int64_t)n);
+            continue;
+        }
+        double dn[7];
+        for (int c = 0; c < 7; ++c) dn[c] = a.xs[7 * (int64_t)P + c];
+        sim3_store(sim3_mul(sim3_exp(dn), Sn), a.S_c + 13 * (int64_t)n);
+    }
+}
+
 // The banded Cholesky H = L L^T with L y = rhs solved alongside, L^T x = y,
 // and S_n <- exp(x_n) S_n, in one workgroup.
 //
@@ -849,17 +871,243 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
         __syncthreads();   // the window is refilled next
     }
     __syncthreads();   // every x in global memory
-    for (int n = tid; n < a.n_nodes; n += kBandBlock) {
-        const int P = a.pos[n];
-        const Sim3d Sn = sim3_load(a.S + 13 * (int64_t)n);
-        if (P < 0) {
-            sim3_store(Sn, a.S_c + 13 * (int64_t)n);
-            continue;
+    band_candidate_poses(a);
+}
+
+// The same banded Cholesky for bands too wide for an LDS window (up to
+// FL_PGO_MAX_BAND_NODES keyframes): the band itself, in device memory (the
+// active rows stay in L2), is the window, updated in place, in one workgroup
+// of kWideBlock threads.  Per block column K (rows r0 = 7K ..):
+//  A. thread t holds window row r0 + t's 7 panel entries and right-hand side;
+//     wave 0 factors the 7 x 7 diagonal block exactly as the LDS solve's
+//     panel wave does and publishes 1 / L(c,c), y_c and L(j,c) in LDS, from
+//     which the other rows finish (the same fused multiply-adds in the same
+//     order as in that wave); the finished entries go to device memory and
+//     the panel to LDS;
+//  B. the workgroup subtracts the panel's rank-7 product from the window's
+//     trailing triangle, read and written in device memory with consecutive
+//     threads on consecutive entries of a row; the entries that form the next
+//     panel are also kept in LDS, so the next step A reads its rows from LDS
+//     (only the rows entering the window come from device memory, loaded
+//     during this step).
+// Back substitution by blocks of 7 rows: wave 0 solves the block's 7
+// unknowns (lane l holding row l's running right-hand side), then each
+// thread subtracts the block's 7 products from one earlier row's running
+// right-hand side (a ring in LDS), the loads of the next block issued a
+// block ahead.  Every entry, right-hand side and unknown sees the same fused
+// multiply-adds, in the same order, as in the LDS-window solve, so the two
+// give identical results on any band both take.
+__global__ __launch_bounds__(kWideBlock) void pgo_band_solve_wide_kernel(PgoArgs a) {
+    constexpr int MW = kWideMaxW, RM = kWideRing - 1;
+    constexpr int PW = MW + 8;      // panel column stride: row t at t + 1, so rows 8, 12, .. start 32-byte units
+    __shared__ __align__(16) double sP[7 * PW];   // the panel by column: sP[c PW + t + 1] = L(r0 + t, r0 + c)
+    __shared__ double sN[7 * MW];   // the next panel's entries, as updated by step B
+    __shared__ double sB[kWideRing];   // right-hand sides by row (mod kWideRing)
+    __shared__ double sK[14 + 49];   // 1 / L(c,c), y_c and L(j,c) of a block; x of a block
+    __shared__ int s_fail;
+    const int tid = threadIdx.x;
+    const int W = a.band_w, w = W - 1, Vs = a.band_vs;
+    const int NB = Vs / 7;
+    const int nT = (W - 7 + 3) / 4;   // tile rows of the trailing triangle
+    const int ntile = nT * (nT + 1) / 2;
+    for (int t = tid; t < W; t += kWideBlock) sB[t & RM] = t < Vs ? a.rhs[t] : 0.0;
+    if (tid == 0) s_fail = 0;
+    double pf[7], pfb = 0.0;   // a row entering the window at the next block
+#pragma unroll
+    for (int c = 0; c < 7; ++c) pf[c] = 0.0;
+    __syncthreads();
+
+    for (int K = 0; K < NB; ++K) {
+        const int r0 = 7 * K;
+        const int t = tid, R = r0 + t;
+        const bool hr = t < W && R < Vs;
+        // A. the panel
+        double p[7], b = 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            const bool in = hr && (t >= 7 || c <= t);
+            p[c] = !in ? 0.0 : K == 0 ? a.band[(int64_t)R * W + w + c - t] : t >= W - 7 ? pf[c] : sN[c * MW + t];
         }
-        double dn[7];
-        for (int c = 0; c < 7; ++c) dn[c] = a.xs[7 * (int64_t)P + c];
-        sim3_store(sim3_mul(sim3_exp(dn), Sn), a.S_c + 13 * (int64_t)n);
+        if (hr) b = sB[R & RM];
+        if (tid < kWave) {
+            bool okp = true;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                const double d = readlane_f64(p[c], c);
+                okp = okp && d > 0.0;
+                double ird = __builtin_amdgcn_rsq(d);
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    const double e = fma(-d * ird, ird, 1.0);
+                    ird = fma(0.5 * ird, e, ird);
+                }
+                const double rd = d * ird;
+                const double yc = readlane_f64(b, c) * ird;
+                if (t == c) {
+                    p[c] = rd;
+                    b = yc;
+                } else if (t > c) {
+                    p[c] *= ird;
+                    b = fma(-p[c], yc, b);
+                }
+                if (tid == 0) {
+                    sK[c] = ird;
+                    sK[7 + c] = yc;
+                }
+#pragma unroll
+                for (int j = c + 1; j < 7; ++j) {
+                    const double ljc = readlane_f64(p[c], j);   // L(j, c)
+                    if (t >= j) p[j] = fma(-p[c], ljc, p[j]);
+                    if (tid == 0) sK[14 + 7 * j + c] = ljc;
+                }
+            }
+            if (tid == 0 && !okp) s_fail = 1;
+        }
+        lds_barrier();
+        if (s_fail) break;   // the same in every thread
+        if (tid >= kWave && hr) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                const double ird = sK[c], yc = sK[7 + c];
+                p[c] *= ird;
+                b = fma(-p[c], yc, b);
+#pragma unroll
+                for (int j = c + 1; j < 7; ++j) p[j] = fma(-p[c], sK[14 + 7 * j + c], p[j]);
+            }
+        }
+        if (hr) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c)
+                if (t >= 7 || c <= t) a.band[(int64_t)R * W + w + c - t] = p[c];
+            if (t >= 7) {
+#pragma unroll
+                for (int c = 0; c < 7; ++c) sP[c * PW + t + 1] = p[c];
+            } else {
+                a.rhs[R] = b;   // y of the block's rows, final
+            }
+            sB[R & RM] = b;
+        }
+        lds_barrier();
+        // B. the trailing update.  The rows entering the window at the next
+        // block (rows r0 + W .. r0 + W + 6, untouched so far) are loaded first.
+        const int Rn = r0 + 7 + t;
+        const bool hn = t >= W - 7 && t < W && Rn < Vs;
+        if (hn) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c)
+                pf[c] = t >= 7 || c <= t ? a.band[(int64_t)Rn * W + w + c - t] : 0.0;
+            pfb = a.rhs[Rn];
+        }
+        // The trailing triangle in tiles of 4 x 4 entries (local rows i0 ..
+        // i0 + 3, columns j0 .. j0 + 3), one per thread at a time: a tile
+        // reads 8 panel entries per column for its 16 entries, the columns'
+        // 4 as one 32-byte LDS read, and consecutive threads take
+        // consecutive tiles of a tile row (consecutive device-memory
+        // entries of the same 4 rows).
+        for (int T = tid; T < ntile; T += kWideBlock) {
+            int I = (int)((sqrtf(8.0f * (float)T + 1.0f) - 1.0f) * 0.5f);
+            while (I * (I + 1) / 2 > T) --I;
+            while ((I + 1) * (I + 2) / 2 <= T) ++I;
+            const int J = T - I * (I + 1) / 2;
+            const int i0 = 7 + 4 * I, j0 = 7 + 4 * J;
+            double acc[4][4];
+            // entry (i, j) of the window at band[(r0 + i) W + w - i + j]
+            double* tb = a.band + (int64_t)(r0 + i0) * W + w - i0 + j0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const int i = i0 + x, j = j0 + y;
+                    acc[x][y] = i < W && j <= i && r0 + i < Vs ? tb[x * w + y] : 0.0;
+                }
+#pragma unroll 1
+            for (int c = 0; c < 7; ++c) {
+                const double2 q0 = *(const double2*)&sP[c * PW + j0 + 1];
+                const double2 q1 = *(const double2*)&sP[c * PW + j0 + 3];
+                const double pj[4] = {q0.x, q0.y, q1.x, q1.y};
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const double pi = sP[c * PW + i0 + x + 1];
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = fma(-pi, pj[y], acc[x][y]);
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const int i = i0 + x, j = j0 + y;
+                    if (!(i < W && j <= i && r0 + i < Vs)) continue;
+                    tb[x * w + y] = acc[x][y];
+                    if (j < 14) sN[(j - 7) * MW + (i - 7)] = acc[x][y];
+                }
+        }
+        if (hn) sB[Rn & RM] = pfb;
+        // step B's device-memory entries are read by other threads next block
+        __syncthreads();
     }
+    if (s_fail) {   // the same in every thread
+        if (tid == 0) a.lm[kLmFail] = 1.0;
+        return;
+    }
+    if (tid == 0) a.lm[kLmUsed] = 0.0;
+    __syncthreads();   // L and y in device memory, visible to every thread
+
+    // Back substitution, L^T x = y.  The running right-hand sides s_j of the
+    // rows still open, [r0 - w, r0 + 6] at block K, live in the ring sB.
+    double* sX = sK;
+    {
+        const int lo = 7 * (NB - 1) - w < 0 ? 0 : 7 * (NB - 1) - w;
+        for (int j = lo + tid; j < Vs; j += kWideBlock) sB[j & RM] = a.rhs[j];
+    }
+    // this thread's loads for block K: wave 0 lane l < 7 the block's column l
+    // (Lc[ii] = L(r0 + ii, r0 + l), ii > l) and 1 / L(r0 + l, r0 + l); thread
+    // u < w the block's entries of row j = r0 - w + u (zero outside the band)
+    // and, for u < 7, the y of the row entering the window next
+    double Lc[7], dinv = 0.0, Lr[7], ye = 0.0;
+    auto load_block = [&](int K) {
+        const int r0 = 7 * K;
+#pragma unroll
+        for (int ii = 0; ii < 7; ++ii) {
+            Lc[ii] = tid < 7 && ii > tid ? a.band[(int64_t)(r0 + ii) * W + w - (ii - tid)] : 0.0;
+            const int j = r0 - w + tid;
+            Lr[ii] = tid < w && j >= 0 && ii <= tid ? a.band[(int64_t)(r0 + ii) * W + w - (r0 + ii - j)] : 0.0;
+        }
+        dinv = tid < 7 ? 1.0 / a.band[(int64_t)(r0 + tid) * W + w] : 0.0;
+        const int je = r0 - 7 - w + tid;
+        ye = tid < 7 && je >= 0 ? a.rhs[je] : 0.0;
+    };
+    load_block(NB - 1);
+    __syncthreads();
+    for (int K = NB - 1; K >= 0; --K) {
+        const int r0 = 7 * K;
+        if (tid < kWave) {
+            const int l = tid;
+            double sl = l < 7 ? sB[(r0 + l) & RM] : 0.0;
+#pragma unroll
+            for (int ii = 6; ii >= 0; --ii) {
+                const double xi = readlane_f64(sl, ii) * readlane_f64(dinv, ii);
+                if (l < ii) sl = fma(-Lc[ii], xi, sl);
+                if (l == ii) {
+                    a.xs[r0 + ii] = xi;
+                    sX[ii] = xi;
+                }
+            }
+        }
+        lds_barrier();
+        if (tid < w && r0 - w + tid >= 0) {
+            const int j = r0 - w + tid;
+            double s = sB[j & RM];
+#pragma unroll
+            for (int ii = 6; ii >= 0; --ii) s = fma(-Lr[ii], sX[ii], s);
+            sB[j & RM] = s;
+        }
+        if (tid < 7 && r0 - 7 - w + tid >= 0) sB[(r0 - 7 - w + tid) & RM] = ye;
+        if (K > 0) load_block(K - 1);
+        lds_barrier();
+    }
+    __syncthreads();   // every x in device memory
+    band_candidate_poses(a);
 }
 
 // e^T e of every edge at the poses P (one thread per edge).

@@ -593,23 +593,31 @@ def gen_bidir(seed: int = 505, n_fwd: int = 20000, n_bwd: int = 20000, n_views: 
 
 
 def gen_pose_graph(n: int = 1000, seed: int = 606, covis: int = 3, n_loops: int = 8, noise_deg: float = 0.1,
-                   noise_m: float = 0.01, noise_scale: float = 0.001, drift: bool = True):
+                   noise_m: float = 0.01, noise_scale: float = 0.001, drift: bool = True, laps: int = 1,
+                   cross: int = 0):
     """An essential graph after a loop closure: n keyframes on a closed loop
     of radius 5 m (world -> camera poses, scale 1), edges (i, i + d) for
     d = 1..covis along the trajectory (spanning tree and covisibility), and
     n_loops loop edges joining the trajectory's last keyframes to its first
-    ones.  Each edge measures M_ij = S_j S_i^-1 of the true poses, moved by
-    N(0, noise) in rotation (deg), translation (m) and log scale.  The start
-    chains the odometry edges (i, i + 1) from keyframe 0 with an extra drift
-    of 0.02 deg, 2 mm and 0.2% scale per step (the state before the loop is
-    corrected).  Keyframe 0 is fixed.  Returns dict(S_true [n,13],
-    S0 [n,13], edges int32 [E,2] (host), M [E,13], fixed bool [n])."""
+    ones.  With laps > 1 the trajectory runs round the loop laps times (a
+    spiral whose radius grows by 0.25 m a lap), and every keyframe of a later
+    lap is joined to the `cross` keyframes of the lap before that pass
+    closest to the same place (the covisibility across laps once their map
+    points are fused: several loops in one graph, whose reordered band is
+    then several times wider).  Each edge measures M_ij = S_j S_i^-1 of the
+    true poses, moved by N(0, noise) in rotation (deg), translation (m) and
+    log scale.  The start chains the odometry edges (i, i + 1) from
+    keyframe 0 with an extra drift of 0.02 deg, 2 mm and 0.2% scale per step
+    (the state before the loop is corrected).  Keyframe 0 is fixed.  Returns
+    dict(S_true [n,13], S0 [n,13], edges int32 [E,2] (host), M [E,13],
+    fixed bool [n])."""
     rng = np.random.Generator(np.random.PCG64(seed))
     S_true = []
     for i in range(n):
-        a = 2 * np.pi * i / n
+        a = 2 * np.pi * laps * i / n
+        rad = 5.0 + 0.25 * laps * i / n if laps > 1 else 5.0
         R = _rodrigues(np.array([0.0, 1.0, 0.0]), -a)            # facing along the loop
-        c = np.array([5.0 * np.cos(a), 0.1 * np.sin(3 * a), 5.0 * np.sin(a)])
+        c = np.array([rad * np.cos(a), 0.1 * np.sin(3 * a), rad * np.sin(a)])
         S_true.append(_sim3(R, -R @ c, 1.0))
     S_true = np.stack(S_true)
 
@@ -630,7 +638,12 @@ def gen_pose_graph(n: int = 1000, seed: int = 606, covis: int = 3, n_loops: int 
     edges = [(i, i + d) for d in range(1, covis + 1) for i in range(n - d)]
     for k in range(n_loops):
         edges.append((n - 1 - k, k))
-    edges = np.array(sorted(edges), np.int32)
+    if laps > 1 and cross > 0:
+        period = n / laps
+        for i in range(int(np.ceil(period)), n):
+            j0 = int(round(i - period)) - cross // 2
+            edges.extend((j, i) for j in range(max(j0, 0), min(j0 + cross, i - covis)))
+    edges = np.array(sorted(set(edges)) if laps > 1 else sorted(edges), np.int32)
     M = np.stack([noisy(mul(S_true[j], inv(S_true[i])), noise_deg, noise_m, noise_scale) for i, j in edges])
     # the start: odometry chained from keyframe 0, with drift
     odo = {(int(i), int(j)): M[k] for k, (i, j) in enumerate(edges) if j == i + 1}

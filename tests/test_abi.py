@@ -42,7 +42,8 @@ def test_header_constants_match_binding():
     src = open(HEADER).read()
     for name, val in (("FL_MAX_PASSES", _abi.MAX_PASSES), ("FL_PGO_MAX_BAND_NODES", _abi.PGO_MAX_BAND_NODES),
                       ("FL_PGO_SOLVER_AUTO", _abi.PGO_SOLVER_AUTO), ("FL_PGO_SOLVER_CG", _abi.PGO_SOLVER_CG),
-                      ("FL_PGO_SOLVER_DIRECT", _abi.PGO_SOLVER_DIRECT)):
+                      ("FL_PGO_SOLVER_DIRECT", _abi.PGO_SOLVER_DIRECT),
+                      ("FL_PGO_SOLVER_DIRECT_WIDE", _abi.PGO_SOLVER_DIRECT_WIDE)):
         m = re.search(r"#define\s+%s\s+(\d+)" % name, src)
         assert m and int(m.group(1)) == val, name
 

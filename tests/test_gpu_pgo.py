@@ -42,7 +42,7 @@ def _oracle(d, fixed=None, iters=3, lam=1e-4, S0=None):
     return S, np.array(h), np.array(lams), np.array(acc, np.uint8)
 
 
-CG, DIRECT = 1, 2
+CG, DIRECT, DIRECT_WIDE = 1, 2, 3
 
 
 @pytest.mark.parametrize("solver", [CG, DIRECT])
@@ -116,23 +116,119 @@ def test_direct_solve_matches_oracle(ctx, kw):
     assert np.array_equal(S[0], d["S0"][0])
 
 
+def _rcm_band(d):
+    """The reordered band, in keyframes, that the library computes: reverse
+    Cuthill-McKee over the free nodes (breadth-first from a free node of
+    least degree in each component, neighbours by rising degree, then
+    index), the widest span of an edge between free nodes, plus one."""
+    n, held = len(d["S0"]), np.asarray(d["fixed"], bool)
+    deg, adj = np.zeros(n, int), [[] for _ in range(n)]
+    for i, j in d["edges"]:
+        adj[i].append(j)
+        adj[j].append(i)
+        if not held[i] and not held[j]:
+            deg[i] += 1
+            deg[j] += 1
+    seen, seq = np.zeros(n, bool), []
+    for r in sorted((v for v in range(n) if not held[v]), key=lambda v: deg[v]):
+        if seen[r]:
+            continue
+        seen[r] = True
+        head = len(seq)
+        seq.append(r)
+        while head < len(seq):
+            v = seq[head]
+            head += 1
+            nb = [u for u in adj[v] if not held[u] and not seen[u]]
+            seen[nb] = True
+            seq.extend(sorted(nb, key=lambda u: (deg[u], u)))
+    pos = -np.ones(n, int)
+    pos[np.array(seq[::-1], int)] = np.arange(len(seq))
+    return 1 + max(abs(pos[i] - pos[j]) for i, j in d["edges"] if pos[i] >= 0 and pos[j] >= 0)
+
+
 def test_solver_choice_and_band_limit(ctx):
-    """Automatic choice: direct on a loop (band of 7 keyframes), conjugate
-    gradients where the reordered band spans more keyframes than the direct
-    solver takes; asking for the direct solve there is an error."""
+    """Automatic choice: direct on a loop (band of 7 keyframes) and on a
+    graph of several loops (a band of 22), conjugate gradients where the
+    reordered band spans more keyframes than the direct solver takes; asking
+    for a direct solve there is an error, and so is an unknown solver."""
     import paper_2603_17201_amd as fl
     loop = synth.gen_pose_graph(n=40, seed=31, covis=3, n_loops=3)
     _, _, used, _, _ = _run(ctx, loop, iters=2)
     assert all(u == 0 for u in used)
-    wide = synth.gen_pose_graph(n=40, seed=31, covis=6, n_loops=3)
-    S_ref, _, _, _ = _oracle(wide, iters=2)
-    S, _, used, _, _ = _run(ctx, wide, iters=2, cg_tol=1e-14, cg_iters=2000)
+    laps = synth.gen_pose_graph(n=150, seed=31, laps=3, cross=3)
+    assert _rcm_band(laps) == 22
+    _, _, used, _, _ = _run(ctx, laps, iters=1)
+    assert all(u == 0 for u in used)
+    over = synth.gen_pose_graph(n=70, seed=31, covis=64, n_loops=0)
+    assert _rcm_band(over) == fl.PGO_MAX_BAND_NODES + 1
+    S_ref, _, _, _ = _oracle(over, iters=1)
+    S, _, used, _, _ = _run(ctx, over, iters=1, cg_tol=1e-14, cg_iters=3000)
     assert all(u > 0 for u in used)
     assert _err(S, S_ref) < 1e-8
+    for solver in (DIRECT, DIRECT_WIDE):
+        with pytest.raises(fl.FlError):
+            _run(ctx, over, iters=1, solver=solver)
     with pytest.raises(fl.FlError):
-        _run(ctx, wide, iters=1, solver=DIRECT)
-    with pytest.raises(fl.FlError):
-        _run(ctx, loop, iters=1, solver=3)
+        _run(ctx, loop, iters=1, solver=4)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=2, covis=1, n_loops=0),
+    dict(n=3, covis=2, n_loops=0),
+    dict(n=30, covis=5, n_loops=3),
+    dict(n=60, covis=4, n_loops=6),
+    dict(n=200, covis=3, n_loops=8),
+], ids=["n2", "n3", "widest", "windows", "loop200"])
+def test_device_memory_window_is_identical_to_lds_window(ctx, kw):
+    """Both band factorisations take the same floating-point steps in the
+    same order: on every band the LDS window takes, the device-memory window
+    gives the same poses, costs and decisions bit for bit."""
+    d = synth.gen_pose_graph(seed=29, **kw)
+    a = _run(ctx, d, iters=3, solver=DIRECT)
+    b = _run(ctx, d, iters=3, solver=DIRECT_WIDE)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("kw,band", [
+    (dict(n=150, laps=2, cross=1), 14),
+    (dict(n=150, laps=3, cross=3), 22),
+    (dict(n=150, laps=4, cross=1), 35),
+    (dict(n=120, laps=6, cross=3), 42),
+    (dict(n=70, covis=63, n_loops=0), 64),
+], ids=["laps2", "laps3", "laps4", "laps6", "band64"])
+def test_several_loops_direct_solve_matches_oracle(ctx, kw, band):
+    """Graphs of several loops (a spiral trajectory of 2-6 laps whose
+    keyframes are joined to the lap before; reordered bands of 14-42
+    keyframes) and the widest band the direct solver takes (64 keyframes,
+    448 scalars a row): the Levenberg-Marquardt iterations against the
+    oracle's dense solves."""
+    d = synth.gen_pose_graph(seed=29, **kw)
+    assert _rcm_band(d) == band
+    iters = 1 if band == 64 else 2
+    S_ref, h, lams_ref, acc_ref = _oracle(d, iters=iters)
+    S, cost, used, lams, acc = _run(ctx, d, iters=iters)
+    assert all(u == 0 for u in used)
+    assert np.array_equal(acc, acc_ref)
+    assert np.array_equal(lams, lams_ref)
+    assert _err(S, S_ref) < 1e-9, _err(S, S_ref)
+    assert np.max(np.abs(cost - h) / h) < 1e-9
+
+
+def test_several_loops_of_1000_keyframes_converge_deterministically(ctx):
+    """1,000 keyframes on three laps (a reordered band of 24 keyframes):
+    repeatable to the bit, accepted costs never rise, and the drift is
+    removed."""
+    d = synth.gen_pose_graph(n=1000, seed=606, laps=3, cross=3)
+    assert _rcm_band(d) == 24
+    S1, cost, used, _, acc = _run(ctx, d, iters=10)
+    S2, cost2, _, _, _ = _run(ctx, d, iters=10)
+    assert all(u == 0 for u in used)
+    assert np.array_equal(S1, S2) and np.array_equal(cost, cost2)
+    assert cost[-1] < 1e-3 * cost[0]
+    assert all(b <= a for a, b in zip(cost, cost[1:]))
+    assert _err(S1, d["S_true"]) < 0.1 * _err(d["S0"], d["S_true"])
 
 
 @pytest.mark.parametrize("solver", [CG, DIRECT])
