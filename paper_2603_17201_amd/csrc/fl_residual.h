@@ -258,9 +258,13 @@ __device__ inline void sim3_to_f32_pose(const Sim3d& S, fl_sim3* o) {
 // Solve (H + lambda diag H) d = -g by an LDL^T factorisation (no square
 // roots; one reciprocal per pivot); H given as its 28 upper entries row by
 // row.  Returns false (d = 0) for a pivot that is not clearly positive.
-// In place on the packed lower triangle (a[i(i+1)/2 + j] = H[i][j], then
-// L[i][j] D[j] below the diagonal), with explicit fused multiply-adds: it
-// runs on one lane, so its dependency chains and registers are its cost.
+// Right-looking, on the packed lower triangle (a[i(i+1)/2 + j] = H[i][j]):
+// each pivot's column is scaled and its rank-1 product subtracted from the
+// rest at once, with the forward substitution folded in, and the back
+// substitution likewise updates every open right-hand side once an unknown is
+// known.  It runs on one lane, so its dependency chain is its cost: per pivot
+// one reciprocal, one multiply and one fused multiply-add deep, the updates
+// themselves independent of one another.
 __device__ inline bool solve7(const double* g, const double* Hu, double lambda, double* d) {
     double a[28];
     double dmax = 0.0;
@@ -271,42 +275,40 @@ __device__ inline bool solve7(const double* g, const double* Hu, double lambda, 
         a[i * (i + 1) / 2 + i] *= (1.0 + lambda);
         dmax = fmax(dmax, fabs(a[i * (i + 1) / 2 + i]));
     }
-    double L[21], Dinv[7];   // L[i(i-1)/2 + j] = L[i][j], j < i
+    double y[7], Dinv[7], L[21];   // L[i(i-1)/2 + j] = L[i][j], j < i
+#pragma unroll
+    for (int i = 0; i < 7; ++i) y[i] = -g[i];
+    bool ok = true;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        double dj = a[j * (j + 1) / 2 + j];
-#pragma unroll
-        for (int m = 0; m < j; ++m) dj = fma(-L[j * (j - 1) / 2 + m], a[j * (j + 1) / 2 + m], dj);
-        if (!(dj > 1e-14 * dmax)) {
-            for (int i = 0; i < 7; ++i) d[i] = 0.0;
-            return false;
-        }
+        const double dj = a[j * (j + 1) / 2 + j];
+        ok = ok && dj > 1e-14 * dmax;
         Dinv[j] = recip(dj);
 #pragma unroll
-        for (int i = j + 1; i < 7; ++i) {
-            double v = a[i * (i + 1) / 2 + j];
+        for (int i = j + 1; i < 7; ++i) L[i * (i - 1) / 2 + j] = a[i * (i + 1) / 2 + j] * Dinv[j];
 #pragma unroll
-            for (int m = 0; m < j; ++m) v = fma(-L[i * (i - 1) / 2 + m], a[j * (j + 1) / 2 + m], v);
-            a[i * (i + 1) / 2 + j] = v;   // L[i][j] D[j]
-            L[i * (i - 1) / 2 + j] = v * Dinv[j];
+        for (int i = j + 1; i < 7; ++i) {
+            const double lij = L[i * (i - 1) / 2 + j];
+#pragma unroll
+            for (int k = j + 1; k <= i; ++k)
+                a[i * (i + 1) / 2 + k] = fma(-lij, a[k * (k + 1) / 2 + j], a[i * (i + 1) / 2 + k]);
+            y[i] = fma(-lij, y[j], y[i]);
         }
     }
-    double y[7];
+    // L^T d = D^-1 y
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        double v = -g[i];
-#pragma unroll
-        for (int m = 0; m < i; ++m) v = fma(-L[i * (i - 1) / 2 + m], y[m], v);
-        y[i] = v;
-    }
+    for (int i = 0; i < 7; ++i) y[i] *= Dinv[i];
 #pragma unroll
     for (int i = 6; i >= 0; --i) {
-        double v = y[i] * Dinv[i];
+        d[i] = y[i];
 #pragma unroll
-        for (int m = i + 1; m < 7; ++m) v = fma(-L[m * (m - 1) / 2 + i], d[m], v);
-        d[i] = v;
+        for (int m = 0; m < i; ++m) y[m] = fma(-L[i * (i - 1) / 2 + m], d[i], y[m]);
     }
-    return true;
+    if (!ok) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) d[i] = 0.0;
+    }
+    return ok;
 }
 
 // ---------------------------------------------------------------------------
