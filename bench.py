@@ -57,8 +57,8 @@ REFINE_FLOPS_PER_PAIR = 35 * 5 + 1
 REFINE_BYTES_PER_PAIR = 32   # one accepted-pair record read (then kept in registers)
 # HBM bytes per launch measured with rocprofv3 counters, one
 # "traffic: <kernel> <workload> <bytes> <sources hash>" line per kernel and
-# workload (the search kernel named with its tuning: pairs per lane, LDS
-# mode, workgroups per CU, XCD ordering)
+# workload (each kernel named with the search tuning of the run: pairs per
+# lane, LDS mode, workgroups per CU, XCD ordering)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_counters.md")
 KERNEL_SOURCES = {
     "search_fused_kernel": ("paper_2603_17201_amd/csrc/fl_search.h", "paper_2603_17201_amd/csrc/fl_internal.h"),
@@ -329,7 +329,7 @@ class Bench:
                 lines = [ln.split() for ln in fh if ln.startswith("traffic:")]
         except OSError:
             return None
-        src = "search_fused_kernel" if kernel.startswith("search_fused_kernel") else kernel
+        src = "search_fused_kernel" if kernel.startswith("search_fused_kernel") else kernel.split("/")[0]
         for ln in lines:
             if len(ln) == 5 and ln[1] == kernel and ln[2] == workload and ln[4] == sources_hash(src):
                 return int(float(ln[3]))
@@ -826,12 +826,13 @@ class Bench:
         rs.update(kernel=f"search_fused_kernel<{tv.pairs_per_lane},{tv.lds_mode}>", launches=ks_n,
                   kernel_us=ks_ms / max(ks_n, 1) * 1e3, alg_bytes=sb // max(ks_n, 1), alg_ops=so // max(ks_n, 1),
                   roofline_us=rs["roofline_us"] / max(ks_n, 1))
-        rs["traffic"] = self.traffic(
-            f"{rs['kernel']}/{tv.pairs_per_lane},{tv.lds_mode},{tv.wg_per_cu},{tv.xcd_aware}", "stream")
+        tuning = f"{tv.pairs_per_lane},{tv.lds_mode},{tv.wg_per_cu},{tv.xcd_aware}"
+        rs["traffic"] = self.traffic(f"{rs['kernel']}/{tuning}", "stream")
         rr = refine_roofline(n_acc, kr_ms)
         rr.update(kernel="refine_kernel", launches=kr_n, kernel_us=kr_ms / max(kr_n, 1) * 1e3,
                   alg_flops=rr["alg_flops"] // max(kr_n, 1), alg_bytes=rr["alg_bytes"] // max(kr_n, 1),
-                  roofline_us=rr["roofline_us"] / max(kr_n, 1), traffic=self.traffic("refine_kernel", "stream"))
+                  roofline_us=rr["roofline_us"] / max(kr_n, 1),
+                  traffic=self.traffic(f"refine_kernel/{tuning}", "stream"))
         roof, other = (rs, rr) if ks_ms >= kr_ms else (rr, rs)
         res = dict(n_events=n_events, steps=K, warmup=W, pairs=pairs, wall_ms=wall, ms_per_event=wall / K,
                    pairs_per_s=pairs / (wall * 1e-3), events_per_s=K / (wall * 1e-3),
