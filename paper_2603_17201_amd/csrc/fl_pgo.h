@@ -24,7 +24,9 @@
 //    pgo_band_solve_kernel, one workgroup, factors the band by Cholesky in
 //    block columns of one keyframe (7 columns) with the forward substitution
 //    folded in, keeping the W rows still being updated in an LDS window that
-//    slides down the matrix, then back-substitutes in one wave;
+//    slides down the matrix, then back-substitutes by blocks of 7 rows
+//    (pgo_band_solve_wide_kernel, for bands of more than 12 keyframes, keeps
+//    the window in device memory instead);
 //  - pgo_solve_kernel, one co-resident workgroup per CU synchronised by a
 //    grid barrier, which gathers g and the diagonal blocks per node over its
 //    incident edges (fixed order, no floating-point atomics) and runs block-
@@ -50,7 +52,9 @@ constexpr int kWideMaxW = 7 * FL_PGO_MAX_BAND_NODES;   // widest band row of any
 constexpr int kWideRing = 512;      // right-hand-side ring of that solve (a power of two)
 static_assert(kWideMaxW + 14 <= kWideRing && kWideMaxW <= kWideBlock, "one thread per window row");
 static_assert(kBandLdsNodes <= FL_PGO_MAX_BAND_NODES, "the LDS window is the narrow case");
-constexpr int kBandPairs = ((kBandMaxW - 1) * kBandMaxW / 2 + kBandBlock - 1) / kBandBlock;
+// entries per thread of the two parts of the band solve's trailing update
+constexpr int kBandPart1 = (7 * (kBandMaxW - 7) + kBandBlock - 1) / kBandBlock;
+constexpr int kBandPart2 = ((kBandMaxW - 14) * (kBandMaxW - 13) / 2 + kBandBlock - kWave - 1) / (kBandBlock - kWave);
 static_assert(kBandMaxW <= kBandBlock, "one thread per band offset");
 
 struct PgoArgs {
@@ -583,11 +587,10 @@ __device__ __forceinline__ void lds_barrier() {
 // band layout, W + 1 or W apart with the padding) fall in different banks.
 __host__ __device__ constexpr int band_win_stride(int W) { return (W | 1) + 1; }
 
-// Dynamic LDS of the band solve: the window, the right-hand-side ring, a
-// back-substitution chunk's right-hand sides and 1 / L(i,i), and the staged
-// rows of the next block with their right-hand sides.
+// Dynamic LDS of the band solve: the window, the right-hand-side ring, and
+// the staged rows of the next block with their right-hand sides.
 __host__ __device__ constexpr size_t band_solve_lds_bytes(int W) {
-    return sizeof(double) * ((size_t)W * band_win_stride(W) + (W + 1) + W + W + 7 * (size_t)W + 7);
+    return sizeof(double) * ((size_t)W * band_win_stride(W) + (W + 1) + 7 * (size_t)W + 7);
 }
 
 // A float64 value of lane l (l wave-uniform).
@@ -614,6 +617,74 @@ __device__ inline void band_candidate_poses(const PgoArgs& a) {
     }
 }
 
+// Back substitution L^T x = y (L and y in device memory, visible to the
+// whole workgroup), by blocks of 7 rows from the last: wave 0 solves the
+// block's 7 unknowns, lane l holding row l's running right-hand side
+// (x_i = s_i / L(i,i), then s_l -= L(i,l) x_i for the block's earlier rows),
+// then thread u subtracts the block's 7 products from the running
+// right-hand side of row r0 - w + u.  The running right-hand sides of the
+// rows still open, [r0 - w, r0 + 6] at block K, live in an LDS ring of
+// RM + 1 >= W + 14 entries (RM + 1 a power of two); x goes to a.xs.  Each
+// s_j takes its products in falling row order, one fused multiply-add each,
+// the loads of the next block issued a block ahead.  Needs w < blockDim.x
+// and 7 doubles of LDS at sX.
+__device__ inline void band_back_substitute(const PgoArgs& a, double* sB, int RM, double* sX) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int W = a.band_w, w = W - 1, Vs = a.band_vs;
+    const int NB = Vs / 7;
+    {
+        const int lo = 7 * (NB - 1) - w < 0 ? 0 : 7 * (NB - 1) - w;
+        for (int j = lo + tid; j < Vs; j += nth) sB[j & RM] = a.rhs[j];
+    }
+    // this thread's loads for block K: wave 0 lane l < 7 the block's column l
+    // (Lc[ii] = L(r0 + ii, r0 + l), ii > l) and 1 / L(r0 + l, r0 + l); thread
+    // u < w the block's entries of row j = r0 - w + u (zero outside the band)
+    // and, for u < 7, the y of the row entering the window next
+    double Lc[7], dinv = 0.0, Lr[7], ye = 0.0;
+    auto load_block = [&](int K) {
+        const int r0 = 7 * K;
+#pragma unroll
+        for (int ii = 0; ii < 7; ++ii) {
+            Lc[ii] = tid < 7 && ii > tid ? a.band[(int64_t)(r0 + ii) * W + w - (ii - tid)] : 0.0;
+            const int j = r0 - w + tid;
+            Lr[ii] = tid < w && j >= 0 && ii <= tid ? a.band[(int64_t)(r0 + ii) * W + w - (r0 + ii - j)] : 0.0;
+        }
+        dinv = tid < 7 ? 1.0 / a.band[(int64_t)(r0 + tid) * W + w] : 0.0;
+        const int je = r0 - 7 - w + tid;
+        ye = tid < 7 && je >= 0 ? a.rhs[je] : 0.0;
+    };
+    load_block(NB - 1);
+    __syncthreads();
+    for (int K = NB - 1; K >= 0; --K) {
+        const int r0 = 7 * K;
+        if (tid < kWave) {
+            const int l = tid;
+            double sl = l < 7 ? sB[(r0 + l) & RM] : 0.0;
+#pragma unroll
+            for (int ii = 6; ii >= 0; --ii) {
+                const double xi = readlane_f64(sl, ii) * readlane_f64(dinv, ii);
+                if (l < ii) sl = fma(-Lc[ii], xi, sl);
+                if (l == ii) {
+                    a.xs[r0 + ii] = xi;
+                    sX[ii] = xi;
+                }
+            }
+        }
+        lds_barrier();
+        if (tid < w && r0 - w + tid >= 0) {
+            const int j = r0 - w + tid;
+            double s = sB[j & RM];
+#pragma unroll
+            for (int ii = 6; ii >= 0; --ii) s = fma(-Lr[ii], sX[ii], s);
+            sB[j & RM] = s;
+        }
+        if (tid < 7 && r0 - 7 - w + tid >= 0) sB[(r0 - 7 - w + tid) & RM] = ye;
+        if (K > 0) load_block(K - 1);
+        lds_barrier();
+    }
+    __syncthreads();   // every x in device memory
+}
+
 // The banded Cholesky H = L L^T with L y = rhs solved alongside, L^T x = y,
 // and S_n <- exp(x_n) S_n, in one workgroup.
 //
@@ -632,10 +703,8 @@ __device__ inline void band_candidate_poses(const PgoArgs& a) {
 //     take their slots.
 // Every entry sees the same fused multiply-adds, in the same order, as a
 // column-by-column factorisation: two barriers per block instead of two per
-// column.  Back substitution walks the rows of L upwards, staged into the LDS
-// window W rows at a time together with each row's 1 / L(i,i) (a step then
-// multiplies instead of dividing), with a ring of W + 1 right-hand-side
-// entries (the slots read and written in one step are then all different).
+// column.  Back substitution goes by blocks of 7 rows (band_back_substitute),
+// its running right-hand sides in a ring over the window's LDS.
 __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     extern __shared__ __align__(16) unsigned char s_mem[];
     __shared__ int s_fail;
@@ -644,24 +713,35 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     const int Ws = band_win_stride(W);
     double* win = (double*)s_mem;      // [W][Ws]
     double* sv = win + W * Ws;         // [W + 1]
-    double* sr = sv + W + 1;           // [W] right-hand sides of a back-substitution chunk
-    double* sd = sr + W;               // [W] 1 / L(i,i) of the chunk's rows
-    double* stg = sd + W;              // [7 W] the rows of the block that enters next
+    double* stg = sv + W + 1;          // [7 W] the rows of the block that enters next
     double* stgb = stg + 7 * W;        // [7] and their right-hand sides
 
-    // this thread's (i, j) pairs, i >= j, of the trailing triangle: local
-    // rows 7 + i and 7 + j of a block's window
-    int pk[kBandPairs];
-    const int nt = W - 7;
-    const int npair = nt * (nt + 1) / 2;
-    for (int q = 0; q < kBandPairs; ++q) {
-        const int t = tid + q * kBandBlock;
-        pk[q] = -1;
-        if (t < npair) {
-            int ra = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-            while (ra * (ra + 1) / 2 > t) --ra;
-            while ((ra + 1) * (ra + 2) / 2 <= t) ++ra;
-            pk[q] = (ra << 8) | (t - ra * (ra + 1) / 2);
+    // This thread's entries (i, j), i >= j, of a block's trailing triangle
+    // (local rows of the block's window), in two parts: the 7 columns that
+    // form the next panel (7 <= j <= 13), over the whole workgroup, and the
+    // rest (j >= 14), over waves 1 .. 7 while wave 0 factors that panel.
+    // Packed as i << 8 | j, -1: none.
+    int pk1[kBandPart1], pk2[kBandPart2];
+    {
+        const int n1 = 7 * (W - 7);   // i - 7 in [0, W - 8], j - 7 in [0, 6], j > i skipped
+#pragma unroll
+        for (int q = 0; q < kBandPart1; ++q) {
+            const int t = tid + q * kBandBlock;
+            const int i = 7 + t / 7, j = 7 + t % 7;
+            pk1[q] = t < n1 && j <= i ? (i << 8 | j) : -1;
+        }
+        const int m = W - 14;   // the triangle 14 <= j <= i < W
+        const int n2 = m > 0 ? m * (m + 1) / 2 : 0;
+#pragma unroll
+        for (int q = 0; q < kBandPart2; ++q) {
+            const int t = tid - kWave + q * (kBandBlock - kWave);
+            pk2[q] = -1;
+            if (tid >= kWave && t < n2) {
+                int ra = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+                while (ra * (ra + 1) / 2 > t) --ra;
+                while ((ra + 1) * (ra + 2) / 2 <= t) ++ra;
+                pk2[q] = (14 + ra) << 8 | (14 + t - ra * (ra + 1) / 2);
+            }
         }
     }
     for (int idx = tid; idx < W * W; idx += kBandBlock) {
@@ -672,93 +752,93 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     if (tid == 0) s_fail = 0;
     __syncthreads();
 
-    const int NB = Vs / 7;
-    int s0 = 0;   // slot of row 7K
-    for (int K = 0; K < NB; ++K) {
+    // The panel of block K (window rows from slot s0), by wave 0: lane t
+    // holds row t (and t + 64); column by column, the pivot comes from the
+    // diagonal lane, the rows below are scaled and the panel's later columns
+    // and the right-hand sides are updated, with the values of one lane read
+    // by all (readlane) and no barrier.
+    auto panel = [&](int K, int s0) {
         const int r0 = 7 * K;
-        if (tid < kWave) {
-            // 1. the panel, one wave
-            const int t = tid, t2 = tid + kWave;
-            int sa = s0 + t;   // below 2 W
-            if (sa >= W) sa -= W;
-            int sb = s0 + t2;  // below 3 W when W < 2 x 64
-            if (sb >= W) sb -= W;
-            if (sb >= W) sb -= W;
-            const bool ha = t < W && r0 + t < Vs, hb = t2 < W && r0 + t2 < Vs;
-            double p[7], p2[7];
+        const int t = tid, t2 = tid + kWave;
+        int sa = s0 + t;   // below 2 W
+        if (sa >= W) sa -= W;
+        int sb = s0 + t2;  // below 3 W when W < 2 x 64
+        if (sb >= W) sb -= W;
+        if (sb >= W) sb -= W;
+        const bool ha = t < W && r0 + t < Vs, hb = t2 < W && r0 + t2 < Vs;
+        double p[7], p2[7];
 #pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                p[c] = ha && c <= t ? win[sa * Ws + w + c - t] : 0.0;
-                p2[c] = hb ? win[sb * Ws + w + c - t2] : 0.0;
-            }
-            double b1 = ha ? sv[sa] : 0.0, b2 = hb ? sv[sb] : 0.0;
-            bool okp = true;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                const double d = readlane_f64(p[c], c);
-                okp = okp && d > 0.0;   // the same in every lane; a failed block is discarded whole
-                // 1 / sqrt(d) from the hardware estimate and two Newton steps
-                // (a short dependency chain on this serial path), sqrt(d) =
-                // d / sqrt(d)
-                double ird = __builtin_amdgcn_rsq(d);
-#pragma unroll
-                for (int it = 0; it < 2; ++it) {
-                    const double e = fma(-d * ird, ird, 1.0);
-                    ird = fma(0.5 * ird, e, ird);
-                }
-                const double rd = d * ird;
-                const double yc = readlane_f64(b1, c) * ird;
-                if (t == c) {
-                    p[c] = rd;
-                    b1 = yc;
-                } else if (t > c) {
-                    p[c] *= ird;
-                    b1 = fma(-p[c], yc, b1);
-                }
-                p2[c] *= ird;
-                b2 = fma(-p2[c], yc, b2);
-#pragma unroll
-                for (int j = c + 1; j < 7; ++j) {
-                    const double ljc = readlane_f64(p[c], j);   // L(j, c)
-                    if (t >= j) p[j] = fma(-p[c], ljc, p[j]);
-                    p2[j] = fma(-p2[c], ljc, p2[j]);
-                }
-            }
-            if (!okp) {
-                if (t == 0) s_fail = 1;
-            } else {
-#pragma unroll
-                for (int c = 0; c < 7; ++c) {
-                    if (ha && c <= t) win[sa * Ws + w + c - t] = p[c];
-                    if (hb) win[sb * Ws + w + c - t2] = p2[c];
-                }
-                if (ha) sv[sa] = b1;
-                if (hb) sv[sb] = b2;
-            }
-        } else {
-            // meanwhile the other waves stage the rows of block K + b + 1
-            // (they enter at the end of this block), so their loads' latency
-            // is spent beside the panel
-            const int r = r0 + W;
-            for (int idx = tid - kWave; idx < 7 * W; idx += kBandBlock - kWave) {
-                const int q = idx / W, e = idx - q * W;
-                stg[idx] = r + q < Vs ? a.band[(int64_t)(r + q) * W + e] : 0.0;
-            }
-            if (tid - kWave < 7) stgb[tid - kWave] = r + tid - kWave < Vs ? a.rhs[r + tid - kWave] : 0.0;
+        for (int c = 0; c < 7; ++c) {
+            p[c] = ha && c <= t ? win[sa * Ws + w + c - t] : 0.0;
+            p2[c] = hb ? win[sb * Ws + w + c - t2] : 0.0;
         }
-        lds_barrier();
-        if (s_fail) break;   // the same in every thread
-        // 2. the trailing update, with the admission beside it.  Every pair
-        // is read and computed before any is written back (a store could
-        // otherwise be taken to alias the next pair's loads and serialise
-        // them); the panel columns it reads are not written in this phase.
-        double nv[kBandPairs];
-        int at[kBandPairs];
+        double b1 = ha ? sv[sa] : 0.0, b2 = hb ? sv[sb] : 0.0;
+        bool okp = true;
 #pragma unroll
-        for (int q = 0; q < kBandPairs; ++q) {
+        for (int c = 0; c < 7; ++c) {
+            const double d = readlane_f64(p[c], c);
+            okp = okp && d > 0.0;   // the same in every lane; a failed block is discarded whole
+            // 1 / sqrt(d) from the hardware estimate and two Newton steps
+            // (a short dependency chain on this serial path), sqrt(d) =
+            // d / sqrt(d)
+            double ird = __builtin_amdgcn_rsq(d);
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                const double e = fma(-d * ird, ird, 1.0);
+                ird = fma(0.5 * ird, e, ird);
+            }
+            const double rd = d * ird;
+            const double yc = readlane_f64(b1, c) * ird;
+            if (t == c) {
+                p[c] = rd;
+                b1 = yc;
+            } else if (t > c) {
+                p[c] *= ird;
+                b1 = fma(-p[c], yc, b1);
+            }
+            p2[c] *= ird;
+            b2 = fma(-p2[c], yc, b2);
+#pragma unroll
+            for (int j = c + 1; j < 7; ++j) {
+                const double ljc = readlane_f64(p[c], j);   // L(j, c)
+                if (t >= j) p[j] = fma(-p[c], ljc, p[j]);
+                p2[j] = fma(-p2[c], ljc, p2[j]);
+            }
+        }
+        if (!okp) {
+            if (t == 0) s_fail = 1;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                if (ha && c <= t) win[sa * Ws + w + c - t] = p[c];
+                if (hb) win[sb * Ws + w + c - t2] = p2[c];
+            }
+            if (ha) sv[sa] = b1;
+            if (hb) sv[sb] = b2;
+        }
+    };
+    // Rows 7K + W .. 7K + W + 6 (block K + b + 1, entering the window at the
+    // end of block K) into the staging rows, by waves 1 .. 7.
+    auto stage = [&](int K) {
+        const int r = 7 * K + W;
+        for (int idx = tid - kWave; idx < 7 * W; idx += kBandBlock - kWave) {
+            const int q = idx / W, e = idx - q * W;
+            stg[idx] = r + q < Vs ? a.band[(int64_t)(r + q) * W + e] : 0.0;
+        }
+        if (tid - kWave < 7) stgb[tid - kWave] = r + tid - kWave < Vs ? a.rhs[r + tid - kWave] : 0.0;
+    };
+    // Entries of block K's trailing triangle, all read and computed before
+    // any is written back (a store could otherwise be taken to alias the
+    // next entry's loads and serialise them); the panel columns they read
+    // are not written meanwhile.
+    auto update = [&](const int* pk, auto NP, int r0, int s0) {
+        double nv[decltype(NP)::value];
+        int at[decltype(NP)::value];
+#pragma unroll
+        for (int q = 0; q < decltype(NP)::value; ++q) {
             at[q] = -1;
             if (pk[q] < 0) continue;
-            const int i = 7 + (pk[q] >> 8), j = 7 + (pk[q] & 255);
+            const int i = pk[q] >> 8, j = pk[q] & 255;
             if (r0 + i >= Vs) continue;
             int si = s0 + i, sj = s0 + j;   // both below 2 W
             if (si >= W) si -= W;
@@ -772,10 +852,25 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
             nv[q] = av;
         }
 #pragma unroll
-        for (int q = 0; q < kBandPairs; ++q)
+        for (int q = 0; q < decltype(NP)::value; ++q)
             if (at[q] >= 0) win[at[q]] = nv[q];
-        // the finished rows 7K .. 7K + 6 go back to HBM and the staged
-        // rows take their slots
+    };
+
+    // Per block K, with look-ahead: 1. the whole workgroup updates the
+    // entries of the next panel's columns, writes the finished rows 7K ..
+    // 7K + 6 back to HBM and moves the staged rows into their slots; 2. wave
+    // 0 factors the panel of block K + 1 while waves 1 .. 7 stage the rows
+    // that enter after it and update the rest of block K's triangle (no
+    // entry either side reads is written by the other).  Two LDS-only
+    // barriers per block; the row stores stay in flight across them.
+    const int NB = Vs / 7;
+    if (tid < kWave) panel(0, 0);
+    else stage(0);
+    lds_barrier();
+    int s0 = 0;   // slot of row 7K
+    for (int K = 0; K < NB && !s_fail; ++K) {
+        const int r0 = 7 * K;
+        update(pk1, std::integral_constant<int, kBandPart1>{}, r0, s0);
         for (int idx = tid; idx < 7 * W; idx += kBandBlock) {
             const int q = idx / W, e = idx - q * W;
             if (r0 + q >= Vs) continue;
@@ -790,10 +885,17 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
             a.rhs[r0 + tid] = sv[sq];
             sv[sq] = stgb[tid];
         }
-        // LDS only: the row stores stay in flight across the barrier
         lds_barrier();
-        s0 += 7;
-        if (s0 >= W) s0 -= W;
+        int s1 = s0 + 7;
+        if (s1 >= W) s1 -= W;
+        if (tid < kWave) {
+            if (K + 1 < NB) panel(K + 1, s1);
+        } else {
+            if (K + 1 < NB) stage(K + 1);
+            update(pk2, std::integral_constant<int, kBandPart2>{}, r0, s0);
+        }
+        lds_barrier();   // s_fail is read at the loop's test, the same in every thread
+        s0 = s1;
     }
     if (s_fail) {   // the same in every thread
         if (tid == 0) a.lm[kLmFail] = 1.0;
@@ -802,75 +904,11 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
     if (tid == 0) a.lm[kLmUsed] = 0.0;
     __syncthreads();   // L and y in global memory, visible to every thread
 
-    // Back substitution, L^T x = y, by one wave: x_i = s_i / L(i,i), then
-    // s_j -= L(i,j) x_i for the rows j of row i's band (column-oriented).
-    // The running right-hand sides stay in the wave's registers: lane l
-    // holds the rows j = l (mod 64), one per half of each 128 rows (svA: j =
-    // l, svB: j = l + 64, mod 128), which covers any band of at most 128
-    // rows; when row i is done its lane takes row i - 128 in its place.  The
-    // workgroup stages W rows of L at a time into LDS (with 1 / L(i,i) and the
-    // y entering), and the wave runs through them without a barrier.
-    double svA = 0.0, svB = 0.0;
-    if (tid < kWave) {
-        const int base = Vs - 128;
-        int jA = base + (((tid - base) % 128) + 128) % 128;        // = tid (mod 128)
-        int jB = base + (((tid + 64 - base) % 128) + 128) % 128;   // = tid + 64 (mod 128)
-        svA = jA >= 0 ? a.rhs[jA] : 0.0;
-        svB = jB >= 0 ? a.rhs[jB] : 0.0;
-    }
-    for (int top = Vs - 1; top >= 0; top -= W) {
-        // rows top - W + 1 .. top of L into the window, row i at (top - i)
-        const int lo = top - W + 1 < 0 ? 0 : top - W + 1;
-        const int nrow = top - lo + 1;
-        for (int idx = tid; idx < nrow * W; idx += kBandBlock) {
-            const int ii = idx / W;
-            win[ii * Ws + idx % W] = a.band[(int64_t)(top - ii) * W + idx % W];
-        }
-        for (int ii = tid; ii < nrow; ii += kBandBlock) {
-            sr[ii] = top - ii - 128 >= 0 ? a.rhs[top - ii - 128] : 0.0;
-            sd[ii] = 1.0 / a.band[(int64_t)(top - ii) * W + w];
-        }
-        __syncthreads();
-        if (tid < kWave) {
-            const int l = tid;
-            // eight rows at a time: their LDS reads (which do not depend on
-            // x) are issued together, ahead of the serial chain
-            constexpr int kU = 8;
-            for (int i0 = 0; i0 < nrow; i0 += kU) {
-                double lA[kU], lB[kU], di[kU], yn[kU];
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const int ii = i0 + u;
-                    const int i = top - ii;
-                    const int dA = (i - l) & 127, dB = (i - l - 64) & 127;
-                    const bool in = ii < nrow;
-                    const double* Li = win + (in ? ii : 0) * Ws + w;   // Li[-d] = L(i, i - d)
-                    lA[u] = in && dA >= 1 && dA <= w ? Li[-dA] : 0.0;
-                    lB[u] = in && dB >= 1 && dB <= w ? Li[-dB] : 0.0;
-                    di[u] = in ? sd[ii] : 0.0;
-                    yn[u] = in ? sr[ii] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const int ii = i0 + u;
-                    if (ii >= nrow) break;   // the same in every lane
-                    const int i = top - ii;
-                    const int li = i & 63;
-                    const bool hi_half = ((i >> 6) & 1) != 0;   // the same in every lane
-                    const double xi = readlane_f64(hi_half ? svB : svA, li) * di[u];
-                    svA = fma(-lA[u], xi, svA);   // lA = 0 outside row i's band
-                    svB = fma(-lB[u], xi, svB);
-                    if (l == li) {
-                        a.xs[i] = xi;
-                        if (hi_half) svB = yn[u];   // row i - 128 in its place
-                        else svA = yn[u];
-                    }
-                }
-            }
-        }
-        __syncthreads();   // the window is refilled next
-    }
-    __syncthreads();   // every x in global memory
+    // Back substitution by blocks of 7 rows, the running right-hand sides
+    // in a ring over the window's LDS (W + 14 <= 128 entries)
+    int ring = 16;
+    while (ring < W + 14) ring *= 2;
+    band_back_substitute(a, win, ring - 1, sv);
     band_candidate_poses(a);
 }
 
@@ -885,18 +923,15 @@ __global__ __launch_bounds__(kBandBlock) void pgo_band_solve_kernel(PgoArgs a) {
 //     order as in that wave); the finished entries go to device memory and
 //     the panel to LDS;
 //  B. the workgroup subtracts the panel's rank-7 product from the window's
-//     trailing triangle, read and written in device memory with consecutive
-//     threads on consecutive entries of a row; the entries that form the next
-//     panel are also kept in LDS, so the next step A reads its rows from LDS
-//     (only the rows entering the window come from device memory, loaded
-//     during this step).
-// Back substitution by blocks of 7 rows: wave 0 solves the block's 7
-// unknowns (lane l holding row l's running right-hand side), then each
-// thread subtracts the block's 7 products from one earlier row's running
-// right-hand side (a ring in LDS), the loads of the next block issued a
-// block ahead.  Every entry, right-hand side and unknown sees the same fused
-// multiply-adds, in the same order, as in the LDS-window solve, so the two
-// give identical results on any band both take.
+//     trailing triangle, read and written in device memory in tiles of 4 x 4
+//     entries, consecutive threads on consecutive tiles of a tile row; the
+//     entries that form the next panel are also kept in LDS, so the next
+//     step A reads its rows from LDS (only the rows entering the window come
+//     from device memory, loaded during this step).
+// Back substitution as in the LDS-window solve (band_back_substitute).
+// Every entry, right-hand side and unknown sees the same fused multiply-adds,
+// in the same order, as in the LDS-window solve, so the two give identical
+// results on any band both take.
 __global__ __launch_bounds__(kWideBlock) void pgo_band_solve_wide_kernel(PgoArgs a) {
     constexpr int MW = kWideMaxW, RM = kWideRing - 1;
     constexpr int PW = MW + 8;      // panel column stride: row t at t + 1, so rows 8, 12, .. start 32-byte units
@@ -1053,60 +1088,7 @@ __global__ __launch_bounds__(kWideBlock) void pgo_band_solve_wide_kernel(PgoArgs
     if (tid == 0) a.lm[kLmUsed] = 0.0;
     __syncthreads();   // L and y in device memory, visible to every thread
 
-    // Back substitution, L^T x = y.  The running right-hand sides s_j of the
-    // rows still open, [r0 - w, r0 + 6] at block K, live in the ring sB.
-    double* sX = sK;
-    {
-        const int lo = 7 * (NB - 1) - w < 0 ? 0 : 7 * (NB - 1) - w;
-        for (int j = lo + tid; j < Vs; j += kWideBlock) sB[j & RM] = a.rhs[j];
-    }
-    // this thread's loads for block K: wave 0 lane l < 7 the block's column l
-    // (Lc[ii] = L(r0 + ii, r0 + l), ii > l) and 1 / L(r0 + l, r0 + l); thread
-    // u < w the block's entries of row j = r0 - w + u (zero outside the band)
-    // and, for u < 7, the y of the row entering the window next
-    double Lc[7], dinv = 0.0, Lr[7], ye = 0.0;
-    auto load_block = [&](int K) {
-        const int r0 = 7 * K;
-#pragma unroll
-        for (int ii = 0; ii < 7; ++ii) {
-            Lc[ii] = tid < 7 && ii > tid ? a.band[(int64_t)(r0 + ii) * W + w - (ii - tid)] : 0.0;
-            const int j = r0 - w + tid;
-            Lr[ii] = tid < w && j >= 0 && ii <= tid ? a.band[(int64_t)(r0 + ii) * W + w - (r0 + ii - j)] : 0.0;
-        }
-        dinv = tid < 7 ? 1.0 / a.band[(int64_t)(r0 + tid) * W + w] : 0.0;
-        const int je = r0 - 7 - w + tid;
-        ye = tid < 7 && je >= 0 ? a.rhs[je] : 0.0;
-    };
-    load_block(NB - 1);
-    __syncthreads();
-    for (int K = NB - 1; K >= 0; --K) {
-        const int r0 = 7 * K;
-        if (tid < kWave) {
-            const int l = tid;
-            double sl = l < 7 ? sB[(r0 + l) & RM] : 0.0;
-#pragma unroll
-            for (int ii = 6; ii >= 0; --ii) {
-                const double xi = readlane_f64(sl, ii) * readlane_f64(dinv, ii);
-                if (l < ii) sl = fma(-Lc[ii], xi, sl);
-                if (l == ii) {
-                    a.xs[r0 + ii] = xi;
-                    sX[ii] = xi;
-                }
-            }
-        }
-        lds_barrier();
-        if (tid < w && r0 - w + tid >= 0) {
-            const int j = r0 - w + tid;
-            double s = sB[j & RM];
-#pragma unroll
-            for (int ii = 6; ii >= 0; --ii) s = fma(-Lr[ii], sX[ii], s);
-            sB[j & RM] = s;
-        }
-        if (tid < 7 && r0 - 7 - w + tid >= 0) sB[(r0 - 7 - w + tid) & RM] = ye;
-        if (K > 0) load_block(K - 1);
-        lds_barrier();
-    }
-    __syncthreads();   // every x in device memory
+    band_back_substitute(a, sB, RM, sK);
     band_candidate_poses(a);
 }
 

@@ -1,11 +1,14 @@
 """GPU parity of the essential-graph optimisation (exact Jacobians,
-Levenberg-Marquardt) against the float64 oracle, for both solvers (banded
-Cholesky and conjugate gradients): exact recovery of a consistent graph, the
+Levenberg-Marquardt) against the float64 oracle, for every solver (banded
+Cholesky through an LDS window or through device memory, conjugate
+gradients): exact recovery of a consistent graph, the
 oracle's poses, cost history, damping and accept/refuse sequence on noisy
 graphs (Gauss-Newton, small and large damping, a start that makes the
-undamped step overshoot, several held nodes, the smallest graphs, the widest
-band the direct solver takes, several band windows), the solver choice and
-its limit, and convergence and determinism on a 1,000-keyframe loop."""
+undamped step overshoot, several held nodes, the smallest graphs, several
+band windows, graphs of several loops up to the widest band the direct
+solver takes), the two band windows' identical results, the solver choice
+and its limit, and convergence and determinism on 1,000 keyframes on one and
+on three laps."""
 import numpy as np
 import pytest
 import torch
@@ -45,7 +48,7 @@ def _oracle(d, fixed=None, iters=3, lam=1e-4, S0=None):
 CG, DIRECT, DIRECT_WIDE = 1, 2, 3
 
 
-@pytest.mark.parametrize("solver", [CG, DIRECT])
+@pytest.mark.parametrize("solver", [CG, DIRECT, DIRECT_WIDE])
 def test_consistent_graph_is_recovered_exactly(ctx, solver):
     d = synth.gen_pose_graph(n=12, seed=11, covis=2, n_loops=2, noise_deg=0.0, noise_m=0.0, noise_scale=0.0)
     S, cost, used, lams, acc = _run(ctx, d, iters=6, cg_tol=1e-13, solver=solver)
@@ -54,7 +57,7 @@ def test_consistent_graph_is_recovered_exactly(ctx, solver):
     assert np.array_equal(S[0], d["S0"][0])
 
 
-@pytest.mark.parametrize("solver", [CG, DIRECT])
+@pytest.mark.parametrize("solver", [CG, DIRECT, DIRECT_WIDE])
 @pytest.mark.parametrize("lam", [0.0, 1e-4, 0.1])
 def test_noisy_graph_matches_oracle(ctx, lam, solver):
     # three iterations: every decision has a relative margin above 1e-7
@@ -68,7 +71,7 @@ def test_noisy_graph_matches_oracle(ctx, lam, solver):
     assert all(u > 0 for u in used) if solver == CG else all(u == 0 for u in used)
 
 
-@pytest.mark.parametrize("solver", [CG, DIRECT])
+@pytest.mark.parametrize("solver", [CG, DIRECT, DIRECT_WIDE])
 def test_refused_steps_match_oracle(ctx, solver):
     """Three free keyframes start 2-3 rad off: the undamped steps overshoot,
     the iterations are refused, the damping grows and the poses are kept
@@ -86,7 +89,7 @@ def test_refused_steps_match_oracle(ctx, solver):
     assert cost[k + 1] == cost[k]
 
 
-@pytest.mark.parametrize("solver", [CG, DIRECT])
+@pytest.mark.parametrize("solver", [CG, DIRECT, DIRECT_WIDE])
 def test_several_held_nodes(ctx, solver):
     d = synth.gen_pose_graph(n=12, seed=17, covis=2, n_loops=2)
     fixed = np.zeros(12, bool)
@@ -231,7 +234,7 @@ def test_several_loops_of_1000_keyframes_converge_deterministically(ctx):
     assert _err(S1, d["S_true"]) < 0.1 * _err(d["S0"], d["S_true"])
 
 
-@pytest.mark.parametrize("solver", [CG, DIRECT])
+@pytest.mark.parametrize("solver", [CG, DIRECT, DIRECT_WIDE])
 def test_loop_of_1000_keyframes_converges_deterministically(ctx, solver):
     d = synth.gen_pose_graph(n=1000, seed=606)
     S1, cost, used, _, acc = _run(ctx, d, iters=10, solver=solver)
