@@ -2,7 +2,8 @@
 central differences of the edge error, the adjoint and left-Jacobian
 identities, exact recovery of a consistent graph from a drifted start,
 invariance under a change of world frame, Levenberg-Marquardt reducing to
-Gauss-Newton as the damping vanishes, and a monotone accepted cost."""
+Gauss-Newton as the damping vanishes, a monotone accepted cost, and the
+several-loop workload's structure and exact recovery."""
 import numpy as np
 import pytest
 from scipy.linalg import expm
@@ -146,3 +147,32 @@ def test_large_damping_barely_moves_and_rejects_raise_it():
         assert h[k + 1] == (cand[k] if acc[k] else h[k])
         if k < 7:
             assert lams[k + 1] == pytest.approx(lams[k] / 10 if acc[k] else 10 * lams[k])
+
+
+def test_several_laps_graph_structure_and_exact_recovery():
+    """The several-loop workload: every keyframe of a later lap is joined to
+    keyframes of the lap before that sit at about the same place (the same
+    angle on the spiral, radii 0.25 m apart), the consistent graph is
+    recovered exactly from its drifted start, and one lap gives the
+    single-loop graph edge for edge."""
+    n, laps, cross = 60, 3, 3
+    d = synth.gen_pose_graph(n=n, seed=14, covis=2, n_loops=2, laps=laps, cross=cross, noise_deg=0.0,
+                             noise_m=0.0, noise_scale=0.0)
+    period = n / laps
+    e = {(int(i), int(j)) for i, j in d["edges"]}
+    cross_edges = [(i, j) for i, j in e if j - i > 2 and not (i >= n - 2 and j < 2)]
+    assert cross_edges
+    # camera centres of the world -> camera poses
+    c = np.stack([-np.asarray(S[:9]).reshape(3, 3).T @ S[9:12] for S in d["S_true"]])
+    step = max(np.linalg.norm(c[k + 1] - c[k]) for k in range(n - 1))
+    for i, j in cross_edges:
+        assert abs((j - i) - period) <= cross // 2 + 1
+        # about the same place: within the offset's keyframe spacings plus the radius step of a lap
+        assert np.linalg.norm(c[i] - c[j]) <= (cross // 2 + 1) * step + 0.25 + 1e-9
+    assert all(sum(1 for i, j in e if j == k and j - i > 2) == cross for k in range(int(np.ceil(period)) + 2, n - 2))
+    h = []
+    S = pgo.optimize(d["S0"], d["edges"], d["M"], d["fixed"], iters=6, history=h)
+    assert _err(S, d["S_true"]) < 1e-9 and h[-1] < 1e-18
+    one = synth.gen_pose_graph(n=n, seed=14, covis=2, n_loops=2)
+    same = synth.gen_pose_graph(n=n, seed=14, covis=2, n_loops=2, laps=1, cross=cross)
+    assert np.array_equal(one["edges"], same["edges"]) and np.array_equal(one["M"], same["M"])
