@@ -626,8 +626,8 @@ __device__ inline void band_candidate_poses(const PgoArgs& a) {
 // rows still open, [r0 - w, r0 + 6] at block K, live in an LDS ring of
 // RM + 1 >= W + 14 entries (RM + 1 a power of two); x goes to a.xs.  Each
 // s_j takes its products in falling row order, one fused multiply-add each,
-// the loads of the next block issued a block ahead.  Needs w < blockDim.x
-// and 7 doubles of LDS at sX.
+// each block's loads issued two blocks ahead.  Needs w < blockDim.x and 7
+// doubles of LDS at sX.
 __device__ inline void band_back_substitute(const PgoArgs& a, double* sB, int RM, double* sX) {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int W = a.band_w, w = W - 1, Vs = a.band_vs;
@@ -637,33 +637,37 @@ __device__ inline void band_back_substitute(const PgoArgs& a, double* sB, int RM
         for (int j = lo + tid; j < Vs; j += nth) sB[j & RM] = a.rhs[j];
     }
     // this thread's loads for block K: wave 0 lane l < 7 the block's column l
-    // (Lc[ii] = L(r0 + ii, r0 + l), ii > l) and 1 / L(r0 + l, r0 + l); thread
+    // (Lc[ii] = L(r0 + ii, r0 + l), ii > l) and L(r0 + l, r0 + l); thread
     // u < w the block's entries of row j = r0 - w + u (zero outside the band)
-    // and, for u < 7, the y of the row entering the window next
-    double Lc[7], dinv = 0.0, Lr[7], ye = 0.0;
-    auto load_block = [&](int K) {
+    // and, for u < 7, the y of the row entering the window next.  Two sets,
+    // for the blocks alternately, each loaded two blocks ahead; nothing is
+    // computed from the loaded values until the block is solved, so no load
+    // is waited for early.
+    struct Set {
+        double Lc[7], dg, Lr[7], ye;
+    };
+    auto load_block = [&](int K, Set& st) {
         const int r0 = 7 * K;
 #pragma unroll
         for (int ii = 0; ii < 7; ++ii) {
-            Lc[ii] = tid < 7 && ii > tid ? a.band[(int64_t)(r0 + ii) * W + w - (ii - tid)] : 0.0;
+            st.Lc[ii] = tid < 7 && ii > tid ? a.band[(int64_t)(r0 + ii) * W + w - (ii - tid)] : 0.0;
             const int j = r0 - w + tid;
-            Lr[ii] = tid < w && j >= 0 && ii <= tid ? a.band[(int64_t)(r0 + ii) * W + w - (r0 + ii - j)] : 0.0;
+            st.Lr[ii] = tid < w && j >= 0 && ii <= tid ? a.band[(int64_t)(r0 + ii) * W + w - (r0 + ii - j)] : 0.0;
         }
-        dinv = tid < 7 ? 1.0 / a.band[(int64_t)(r0 + tid) * W + w] : 0.0;
+        st.dg = tid < 7 ? a.band[(int64_t)(r0 + tid) * W + w] : 1.0;
         const int je = r0 - 7 - w + tid;
-        ye = tid < 7 && je >= 0 ? a.rhs[je] : 0.0;
+        st.ye = tid < 7 && je >= 0 ? a.rhs[je] : 0.0;
     };
-    load_block(NB - 1);
-    __syncthreads();
-    for (int K = NB - 1; K >= 0; --K) {
+    auto block = [&](int K, const Set& st) {
         const int r0 = 7 * K;
         if (tid < kWave) {
             const int l = tid;
+            const double dinv = 1.0 / st.dg;   // lanes 0 .. 6: 1 / L(r0 + l, r0 + l)
             double sl = l < 7 ? sB[(r0 + l) & RM] : 0.0;
 #pragma unroll
             for (int ii = 6; ii >= 0; --ii) {
                 const double xi = readlane_f64(sl, ii) * readlane_f64(dinv, ii);
-                if (l < ii) sl = fma(-Lc[ii], xi, sl);
+                if (l < ii) sl = fma(-st.Lc[ii], xi, sl);
                 if (l == ii) {
                     a.xs[r0 + ii] = xi;
                     sX[ii] = xi;
@@ -675,11 +679,22 @@ __device__ inline void band_back_substitute(const PgoArgs& a, double* sB, int RM
             const int j = r0 - w + tid;
             double s = sB[j & RM];
 #pragma unroll
-            for (int ii = 6; ii >= 0; --ii) s = fma(-Lr[ii], sX[ii], s);
+            for (int ii = 6; ii >= 0; --ii) s = fma(-st.Lr[ii], sX[ii], s);
             sB[j & RM] = s;
         }
-        if (tid < 7 && r0 - 7 - w + tid >= 0) sB[(r0 - 7 - w + tid) & RM] = ye;
-        if (K > 0) load_block(K - 1);
+        if (tid < 7 && r0 - 7 - w + tid >= 0) sB[(r0 - 7 - w + tid) & RM] = st.ye;
+    };
+    Set A, B;
+    load_block(NB - 1, A);
+    if (NB >= 2) load_block(NB - 2, B);
+    __syncthreads();
+    for (int K = NB - 1; K >= 0; K -= 2) {
+        block(K, A);
+        if (K >= 2) load_block(K - 2, A);
+        lds_barrier();
+        if (K == 0) break;
+        block(K - 1, B);
+        if (K >= 3) load_block(K - 3, B);
         lds_barrier();
     }
     __syncthreads();   // every x in device memory
