@@ -219,6 +219,30 @@ def test_several_loops_direct_solve_matches_oracle(ctx, kw, band):
     assert np.max(np.abs(cost - h) / h) < 1e-9
 
 
+def test_several_loops_with_held_keyframes_and_an_unconnected_one(ctx):
+    """Three laps with keyframes held along the trajectory (the band is taken
+    over the free ones only) and one keyframe whose every edge was removed
+    (held by the solve: a unit diagonal, no step), through the automatic
+    choice of the device-memory window: the oracle's poses, and the held and
+    unconnected keyframes unmoved."""
+    d = synth.gen_pose_graph(n=150, seed=33, laps=3, cross=3)
+    lone = 77
+    keep = [k for k, (i, j) in enumerate(d["edges"]) if lone not in (i, j)]
+    d = dict(d, edges=d["edges"][keep], M=d["M"][keep])
+    fixed = np.zeros(150, bool)
+    fixed[[0, 40, 90, 140]] = True
+    assert _rcm_band(dict(d, fixed=fixed)) > 12
+    # the oracle's dense solve needs the unconnected keyframe held explicitly
+    S_ref, h, _, acc_ref = _oracle(d, fixed=fixed | (np.arange(150) == lone), iters=2)
+    S, cost, used, _, acc = _run(ctx, d, fixed=fixed, iters=2)
+    assert all(u == 0 for u in used)
+    assert np.array_equal(acc, acc_ref)
+    for n in (0, 40, 90, 140, lone):
+        assert np.array_equal(S[n], d["S0"][n])
+    assert _err(S, S_ref) < 1e-9, _err(S, S_ref)
+    assert np.max(np.abs(cost - h) / h) < 1e-9
+
+
 def test_several_loops_of_1000_keyframes_converge_deterministically(ctx):
     """1,000 keyframes on three laps (a reordered band of 24 keyframes):
     repeatable to the bit, accepted costs never rise, and the drift is
