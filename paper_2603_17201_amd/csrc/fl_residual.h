@@ -80,7 +80,10 @@ struct ExpCoef {
 __device__ inline ExpCoef sim3_exp_coef(double w0, double w1, double w2, double sig) {
     const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
     const bool small = th2 < 1e-4;   // angle below 1e-2: the series need only th^2
-    const double th = small ? 0.0 : sqrt(th2);
+    // th, sin th and cos th only where the series do not serve (taken inside
+    // the branch, so that the common small-angle path does not wait for a
+    // square root whose result it never uses)
+    double th = 0.0, sn = 0.0, cs = 1.0;
     ExpCoef k;
     if (small) {
         // sin(th)/th and (1 - cos(th))/th^2 by their Taylor series: the next
@@ -89,8 +92,11 @@ __device__ inline ExpCoef sim3_exp_coef(double w0, double w1, double w2, double 
         k.a = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t4 * th2 * (1.0 / 5040.0);
         k.b = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t4 * th2 * (1.0 / 40320.0);
     } else {
-        k.a = sin(th) / th;
-        k.b = (1.0 - cos(th)) / th2;
+        th = sqrt(th2);
+        sn = sin(th);
+        cs = cos(th);
+        k.a = sn / th;
+        k.b = (1.0 - cs) / th2;
     }
     // I_n(sigma) for n = 0..6 and e^sigma = sum_k sigma^k / k! share one series
     double I[7];
@@ -125,8 +131,8 @@ __device__ inline ExpCoef sim3_exp_coef(double w0, double w1, double w2, double 
         k.c2 = 0.5 * I[2] - th2 * (1.0 / 24.0) * I[4] + th2 * th2 * (1.0 / 720.0) * I[6];
     } else {
         const double den = sig * sig + th2;
-        k.c1 = (es * (sig * sin(th) - th * cos(th)) + th) / (th * den);
-        k.c2 = (k.c0 - (es * (sig * cos(th) + th * sin(th)) - sig) / den) / th2;
+        k.c1 = (es * (sig * sn - th * cs) + th) / (th * den);
+        k.c2 = (k.c0 - (es * (sig * cs + th * sn) - sig) / den) / th2;
     }
     return k;
 }
