@@ -77,7 +77,7 @@ struct ExpCoef {
     double a, b, c0, c1, c2, es;
 };
 
-__device__ inline ExpCoef sim3_exp_coef(double w0, double w1, double w2, double sig) {
+__device__ __noinline__ ExpCoef sim3_exp_coef_full(double w0, double w1, double w2, double sig) {
     const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
     const bool small = th2 < 1e-4;   // angle below 1e-2: the series need only th^2
     // th, sin th and cos th only where the series do not serve (taken inside
@@ -134,6 +134,31 @@ __device__ inline ExpCoef sim3_exp_coef(double w0, double w1, double w2, double 
         k.c1 = (es * (sig * sn - th * cs) + th) / (th * den);
         k.c2 = (k.c0 - (es * (sig * cs + th * sn) - sig) / den) / th2;
     }
+    return k;
+}
+
+// The same coefficients, with the usual Gauss-Newton step (rotation angle
+// below 1e-2, |sigma| below 1e-2) computed in line by the very same series
+// and every other step by the out-of-line function above: the common case
+// costs no call, and the code placed in line stays small enough not to push
+// a kernel that holds many registers into spilling them.
+__device__ __forceinline__ ExpCoef sim3_exp_coef(double w0, double w1, double w2, double sig) {
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    const double asig = fabs(sig);
+    if (!(th2 < 1e-4 && asig < 0.01)) return sim3_exp_coef_full(w0, w1, w2, sig);
+    ExpCoef k;
+    const double t4 = th2 * th2;
+    k.a = 1.0 - th2 * (1.0 / 6.0) + t4 * (1.0 / 120.0) - t4 * th2 * (1.0 / 5040.0);
+    k.b = 0.5 - th2 * (1.0 / 24.0) + t4 * (1.0 / 720.0) - t4 * th2 * (1.0 / 40320.0);
+    double I[7];
+    double es;
+    if (asig < 2.5e-4) sigma_series<5>(sig, I, es);
+    else if (asig < 4e-3) sigma_series<7>(sig, I, es);
+    else sigma_series<9>(sig, I, es);
+    k.es = es;
+    k.c0 = I[0];
+    k.c1 = I[1] - th2 * (1.0 / 6.0) * I[3] + th2 * th2 * (1.0 / 120.0) * I[5];
+    k.c2 = 0.5 * I[2] - th2 * (1.0 / 24.0) * I[4] + th2 * th2 * (1.0 / 720.0) * I[6];
     return k;
 }
 
