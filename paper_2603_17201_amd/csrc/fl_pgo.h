@@ -712,10 +712,12 @@ __device__ inline void band_back_substitute(const PgoArgs& a, double* sB, int RM
 //     from the diagonal lane, the rows below are scaled and the panel's later
 //     columns and the right-hand sides are updated, with the values of one
 //     lane read by all (readlane) and no barrier;
-//  2. the whole workgroup subtracts the panel's rank-7 product from the
-//     window's remaining triangle, while the finished rows 7K .. 7K + 6 go
-//     back to HBM and the rows of block K + b + 1, loaded two blocks earlier,
-//     take their slots.
+//  2. the workgroup subtracts the panel's rank-7 product from the window's
+//     remaining triangle, while the finished rows 7K .. 7K + 6 go back to
+//     HBM and the rows of block K + b + 1, staged during the previous step,
+//     take their slots.  With look-ahead, the entries of the next panel's
+//     columns are updated first, and the rest of the triangle while wave 0
+//     factors that next panel (step 1 of block K + 1).
 // Every entry sees the same fused multiply-adds, in the same order, as a
 // column-by-column factorisation: two barriers per block instead of two per
 // column.  Back substitution goes by blocks of 7 rows (band_back_substitute),
